@@ -1,0 +1,213 @@
+"""Per-element energies with hand-derived gradients and Hessians (oracle).
+
+TEST INFRASTRUCTURE ONLY.  Arrays are batched over elements: positions x and X
+have shape (E, k, 3); gradients (E, k, 3); Hessians (E, k, 3, k, 3) with index
+order (node a, coord i, node b, coord k).  All functions accept complex x so
+that tests can differentiate them with the complex step; rest data are real.
+
+Energies:
+* Stable Neo-Hookean tet4 -- App. B (Stable Neo-Hookean branch, after Smith et
+  al. 2018 Eq. 14), integrated over a linear tet as E_e = V_e psi(F_e)
+  (Sec. 3.1, element energy by volume integration).  F = Ds Dm^-1.
+* StVK triangle membrane -- App. B (Saint Venant-Kirchhoff branch) applied to
+  the 3x2 deformation gradient of a triangle in its rest frame, times rest area
+  and thickness (Sec. 6.3 uses a 2D FEM integrator for cloth).
+* Quadratic bending hinge -- Eq. 13 (Bergou et al. 2006): E = k_b/2 x^T Q x with
+  the constant Q = 3/(A0+A1) (K K^T) (x) I3 built from the rest cotangents.
+* Inertia -- Eq. 2: m/(2 dt^2) |x - x_tilde|^2 per node.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .rest import snh_reparam
+
+# Levi-Civita symbol eps[i,j,k]
+_EPS = np.zeros((3, 3, 3))
+_EPS[0, 1, 2] = _EPS[1, 2, 0] = _EPS[2, 0, 1] = 1.0
+_EPS[0, 2, 1] = _EPS[2, 1, 0] = _EPS[1, 0, 2] = -1.0
+
+
+def _cols(P):
+    """Stack edge vectors of nodes 1.. relative to node 0 as matrix columns."""
+    return np.stack([P[:, a] - P[:, 0] for a in range(1, P.shape[1])], axis=2)
+
+
+def _shape_gradients(Dinv):
+    """b_a = d F / d x_a contraction vectors: rows of Dm^-1, b_0 = -sum of rows.
+
+    With F = Ds Dm^-1 and Ds columns x_a - x_0, dF_ij/dx_{a,m} = delta_im b_a[j].
+    Returns (E, k, d) for Dinv of shape (E, d, d) with k = d + 1 nodes.
+    """
+    rows = [Dinv[:, r, :] for r in range(Dinv.shape[1])]
+    return np.stack([-sum(rows)] + rows, axis=1)
+
+
+# ----------------------------------------------------------------------------
+# Stable Neo-Hookean tet4
+# ----------------------------------------------------------------------------
+def snh_tet4(x, X, mu, lam, want_hess=True):
+    """Energy, gradient and Hessian of V psi_SNH(F) for linear tets.
+
+    mu, lam are the linear-elasticity Lame parameters per element (E,); the
+    energy applies the Stable Neo-Hookean re-parametrisation itself.
+    psi = mu'/2 (Ic - 3) + lam'/2 (J - alpha)^2 - mu'/2 log(Ic + 1),
+    alpha = 1 + mu'/lam' - mu'/(4 lam').
+    """
+    mu_, lam_ = snh_reparam(np.asarray(mu, dtype=np.float64), np.asarray(lam, dtype=np.float64))
+    Dm = _cols(X)
+    Dinv = np.linalg.inv(Dm)
+    V = np.abs(np.linalg.det(Dm)) / 6.0
+    F = _cols(x) @ Dinv
+    Ic = np.einsum("eij,eij->e", F, F)
+    f0, f1, f2 = F[:, :, 0], F[:, :, 1], F[:, :, 2]
+    J = np.einsum("ei,ei->e", f0, np.cross(f1, f2))
+    cof = np.stack([np.cross(f1, f2), np.cross(f2, f0), np.cross(f0, f1)], axis=2)
+    alpha = 1.0 + mu_ / lam_ - mu_ / (4.0 * lam_)
+    psi = 0.5 * mu_ * (Ic - 3.0) + 0.5 * lam_ * (J - alpha) ** 2 - 0.5 * mu_ * np.log(Ic + 1.0)
+    E = V * psi
+    s1 = mu_ * (1.0 - 1.0 / (Ic + 1.0))                 # coefficient of F in dpsi/dF
+    s2 = lam_ * (J - alpha)                             # coefficient of cof F
+    P = s1[:, None, None] * F + s2[:, None, None] * cof
+    b = _shape_gradients(Dinv)                          # (E,4,3)
+    g = V[:, None, None] * np.einsum("eij,eaj->eai", P, b)
+    if not want_hess:
+        return E, g, None
+    # d2psi/dF_ij dF_kl
+    I3 = np.eye(3)
+    d2 = (s1[:, None, None, None, None] * np.einsum("ik,jl->ijkl", I3, I3)[None]
+          + (2.0 * mu_ / (Ic + 1.0) ** 2)[:, None, None, None, None]
+          * np.einsum("eij,ekl->eijkl", F, F)
+          + lam_[:, None, None, None, None] * np.einsum("eij,ekl->eijkl", cof, cof)
+          + s2[:, None, None, None, None] * np.einsum("ikm,jln,emn->eijkl", _EPS, _EPS, F))
+    H = V[:, None, None, None, None] * np.einsum("eaj,ebl,eijkl->eaibk", b, b, d2)
+    return E, g, H
+
+
+# ----------------------------------------------------------------------------
+# StVK triangle membrane
+# ----------------------------------------------------------------------------
+def tri_rest_frame(X):
+    """2x2 rest matrix Dm of a triangle in the orthonormal frame (e1, e2) of its
+    plane: e1 along X1-X0, e2 = n x e1.  Returns (Dm, area)."""
+    d1 = X[:, 1] - X[:, 0]
+    d2 = X[:, 2] - X[:, 0]
+    e1 = d1 / np.linalg.norm(d1, axis=1, keepdims=True)
+    n = np.cross(d1, d2)
+    n = n / np.linalg.norm(n, axis=1, keepdims=True)
+    e2 = np.cross(n, e1)
+    Dm = np.empty((X.shape[0], 2, 2))
+    Dm[:, 0, 0] = np.einsum("ei,ei->e", d1, e1)
+    Dm[:, 0, 1] = np.einsum("ei,ei->e", d2, e1)
+    Dm[:, 1, 0] = np.einsum("ei,ei->e", d1, e2)
+    Dm[:, 1, 1] = np.einsum("ei,ei->e", d2, e2)
+    area = 0.5 * np.abs(np.linalg.det(Dm))
+    return Dm, area
+
+
+def stvk_tri3(x, X, mu, lam, thickness, want_hess=True):
+    """Energy, gradient and Hessian of h A psi_StVK(F) for a membrane triangle.
+
+    F = [x1-x0, x2-x0] Dm^-1 (3x2), Green strain Eg = (F^T F - I)/2,
+    psi = mu |Eg|_F^2 + lam/2 tr(Eg)^2, first Piola P = F S with
+    S = 2 mu Eg + lam tr(Eg) I.
+    """
+    mu = np.asarray(mu, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    Dm, A = tri_rest_frame(X)
+    Dinv = np.linalg.inv(Dm)
+    F = _cols(x) @ Dinv                                  # (E,3,2)
+    C = np.einsum("eki,ekj->eij", F, F)
+    Eg = 0.5 * (C - np.eye(2)[None])
+    trE = Eg[:, 0, 0] + Eg[:, 1, 1]
+    psi = mu * np.einsum("eij,eij->e", Eg, Eg) + 0.5 * lam * trE ** 2
+    hA = thickness * A
+    E = hA * psi
+    S = 2.0 * mu[:, None, None] * Eg + (lam * trE)[:, None, None] * np.eye(2)[None]
+    P = F @ S
+    b = _shape_gradients(Dinv)                           # (E,3,2)
+    g = hA[:, None, None] * np.einsum("eij,eaj->eai", P, b)
+    if not want_hess:
+        return E, g, None
+    # d(F S)_ij / dF_kl = delta_ik S_lj + mu (F_il F_kj + (F F^T)_ik delta_jl) + lam F_ij F_kl
+    I2 = np.eye(2)
+    I3 = np.eye(3)
+    FFt = np.einsum("eim,ekm->eik", F, F)
+    d2 = (np.einsum("ik,elj->eijkl", I3, S)
+          + mu[:, None, None, None, None] * (np.einsum("eil,ekj->eijkl", F, F)
+                                             + np.einsum("eik,jl->eijkl", FFt, I2))
+          + lam[:, None, None, None, None] * np.einsum("eij,ekl->eijkl", F, F))
+    H = hA[:, None, None, None, None] * np.einsum("eaj,ebl,eijkl->eaibk", b, b, d2)
+    return E, g, H
+
+
+# ----------------------------------------------------------------------------
+# Quadratic bending hinge (Bergou et al. 2006)
+# ----------------------------------------------------------------------------
+def _cot(u, v):
+    return np.einsum("ei,ei->e", u, v) / np.linalg.norm(np.cross(u, v), axis=1)
+
+
+def hinge_rest(X):
+    """Cotangent weights K (E,4) and scale 3/(A0+A1) of rest hinges.
+
+    Nodes 0,1 span the shared edge, 2 and 3 are the wing tips of triangles
+    (0,1,2) and (0,1,3).  a_t, b_t are the interior angles at X0 and X1 of
+    triangle t; K = [cot b0 + cot b1, cot a0 + cot a1, -(cot a0 + cot b0),
+    -(cot a1 + cot b1)].
+    """
+    X0, X1, X2, X3 = X[:, 0], X[:, 1], X[:, 2], X[:, 3]
+    ca0 = _cot(X1 - X0, X2 - X0)
+    cb0 = _cot(X0 - X1, X2 - X1)
+    ca1 = _cot(X1 - X0, X3 - X0)
+    cb1 = _cot(X0 - X1, X3 - X1)
+    K = np.stack([cb0 + cb1, ca0 + ca1, -(ca0 + cb0), -(ca1 + cb1)], axis=1)
+    A0 = 0.5 * np.linalg.norm(np.cross(X1 - X0, X2 - X0), axis=1)
+    A1 = 0.5 * np.linalg.norm(np.cross(X1 - X0, X3 - X0), axis=1)
+    return K, 3.0 / (A0 + A1)
+
+
+def hinge4(x, X, kb, want_hess=True):
+    """E = k_b/2 x^T Q x, g = k_b Q x, H = k_b Q with Q = c (K K^T) (x) I3."""
+    K, c = hinge_rest(X)
+    kb = np.broadcast_to(np.asarray(kb, dtype=np.float64), c.shape)
+    s = np.einsum("ea,eai->ei", K, x)                    # sum_a K_a x_a
+    E = 0.5 * kb * c * np.einsum("ei,ei->e", s, s)
+    g = (kb * c)[:, None, None] * K[:, :, None] * s[:, None, :]
+    if not want_hess:
+        return E, g, None
+    H = (kb * c)[:, None, None, None, None] * np.einsum("ea,eb,ik->eaibk", K, K, np.eye(3))
+    return E, g, H
+
+
+# ----------------------------------------------------------------------------
+# Inertia (per node)
+# ----------------------------------------------------------------------------
+def inertia(x, x_tilde, m, dt):
+    """E_i = m_i/(2 dt^2)|x_i - x~_i|^2, g_i = m_i/dt^2 (x_i - x~_i), H_ii = m_i/dt^2 I."""
+    d = x - x_tilde
+    w = m / dt ** 2
+    E = 0.5 * w * np.einsum("ni,ni->n", d, d)
+    g = w[:, None] * d
+    return E, g, w
+
+
+def x_tilde(x_t, v_t, dt, gravity):
+    """Predicted position x(t) + dt v(t) + dt^2 g (Eq. 2; gravity enters here)."""
+    return x_t + dt * v_t + dt ** 2 * np.asarray(gravity, dtype=np.float64)[None, :]
+
+
+def element_eval(es, x, X, want_hess=True):
+    """Dispatch on the energy kind of an EnergySet (element arrays gathered)."""
+    from .rest import lame, young_array
+    xe = x[es.conn]
+    Xe = X[es.conn]
+    if es.kind == 0:
+        mu, lam = lame(young_array(es), es.poisson)
+        return snh_tet4(xe, Xe, mu, lam, want_hess)
+    if es.kind == 1:
+        mu, lam = lame(young_array(es), es.poisson)
+        return stvk_tri3(xe, Xe, mu, lam, es.thickness, want_hess)
+    if es.kind == 2:
+        return hinge4(xe, Xe, es.bend_kb, want_hess)
+    raise ValueError(f"unknown energy kind {es.kind}")

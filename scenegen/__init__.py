@@ -1,0 +1,290 @@
+"""Seeded synthetic scenes shared by the FP64 oracle and the HIP library.
+
+This module only builds meshes, boundary masks and seeded random state.  It
+holds none of the method's arithmetic: no Lame conversion, no rest-shape
+precomputation, no masses, no energies.  Both sides receive the same arrays
+bit for bit and derive everything else on their own.
+
+The paper measures on its own scenes (stretched cube, twisted beam, cloth);
+their meshes are not public, so procedural grids of the same kind stand in
+(Sec. 7, Tables 2-3).  Grid conventions:
+
+* Tet grids: box of nx*ny*nz cubes of edge h, node id i + (nx+1)(j + (ny+1)k),
+  cube id i + nx(j + ny k), element id 6*cube + p where p indexes the
+  permutations of the axes in lexicographic order (Kuhn/Freudenthal split:
+  the tet follows the path v000 -> +e_p0 -> +e_p1 -> v111).  Tets of odd
+  permutations have vertices 2 and 3 swapped so that every tet is positively
+  oriented; this is decided from the permutation parity, not from geometry.
+* Cloth grids: m*m cells on [0,size]^2 at height z0, node id i + (m+1)j, each
+  cell split along (i,j)->(i+1,j+1) into two counter-clockwise triangles.
+  Hinges are the interior edges shared by two triangles, listed as
+  (edge v0, edge v1, opposite vertex of the first triangle, opposite vertex of
+  the second triangle), ordered by (min, max) edge node ids.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SNH_TET4 = 0
+STVK_TRI3 = 1
+HINGE4 = 2
+
+NODES_PER_ELEM = {SNH_TET4: 4, STVK_TRI3: 3, HINGE4: 4}
+
+_PERMS = list(itertools.permutations(range(3)))          # lexicographic order
+_PERM_ODD = [False, True, True, False, False, True]      # parity of each entry
+
+
+@dataclass
+class EnergySet:
+    """One energy applied to a set of elements (the element set of Eq. 5)."""
+    kind: int
+    conn: np.ndarray                   # (n_elem, k) int32
+    young: float = 1e5                 # Young's modulus when per-element is None
+    young_per_elem: np.ndarray | None = None   # (n_elem,) float64 or None
+    poisson: float = 0.4
+    thickness: float = 1.0             # membrane thickness (tri only)
+    bend_kb: float = 0.0               # bending stiffness (hinge only)
+    density: float = 1000.0            # kg/m^3 (tets and membranes)
+
+
+@dataclass
+class Scene:
+    name: str
+    X: np.ndarray                      # (N,3) float64 rest positions
+    energies: list[EnergySet]
+    fixed: np.ndarray                  # (N,) uint8, 1 = Dirichlet node
+    x0: np.ndarray                     # (N,3) float64 positions x(t)
+    v0: np.ndarray                     # (N,3) float64 velocities v(t)
+    dt: float = 0.01
+    gravity: tuple = (0.0, 0.0, -9.81)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.X.shape[0])
+
+    def n_elements(self) -> int:
+        return int(sum(e.conn.shape[0] for e in self.energies))
+
+
+# ----------------------------------------------------------------------------
+# meshes
+# ----------------------------------------------------------------------------
+def tet_grid(nx: int, ny: int, nz: int, h: float, origin=(0.0, 0.0, 0.0)):
+    """Regular box of nx*ny*nz cubes, each split into 6 positively oriented tets."""
+    ii, jj, kk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1),
+                             indexing="ij")
+    # node id = i + (nx+1)(j + (ny+1)k): order the flattened arrays accordingly
+    X = np.stack([ii.transpose(2, 1, 0).ravel(), jj.transpose(2, 1, 0).ravel(),
+                  kk.transpose(2, 1, 0).ravel()], axis=1).astype(np.float64) * h
+    X += np.asarray(origin, dtype=np.float64)
+
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ci = ci.transpose(2, 1, 0).ravel()
+    cj = cj.transpose(2, 1, 0).ravel()
+    ck = ck.transpose(2, 1, 0).ravel()
+    ncube = ci.size
+    tets = np.empty((ncube, 6, 4), dtype=np.int64)
+    unit = np.eye(3, dtype=np.int64)
+    for p, perm in enumerate(_PERMS):
+        pos = np.zeros(3, dtype=np.int64)
+        path = [pos.copy()]
+        for ax in perm:
+            pos = pos + unit[ax]
+            path.append(pos.copy())
+        verts = [nid(ci + o[0], cj + o[1], ck + o[2]) for o in path]
+        if _PERM_ODD[p]:
+            verts[2], verts[3] = verts[3], verts[2]
+        for a in range(4):
+            tets[:, p, a] = verts[a]
+    return X, tets.reshape(-1, 4).astype(np.int32)
+
+
+def cloth_grid(m: int, size: float = 1.0, z0: float = 0.0, origin_xy=(0.0, 0.0)):
+    """m*m cells on [0,size]^2 at height z0, two counter-clockwise triangles per cell."""
+    jj, ii = np.meshgrid(np.arange(m + 1), np.arange(m + 1), indexing="ij")
+    step = size / m
+    X = np.stack([ii.ravel() * step + origin_xy[0], jj.ravel() * step + origin_xy[1],
+                  np.full(ii.size, z0)], axis=1).astype(np.float64)
+
+    def nid(i, j):
+        return i + (m + 1) * j
+
+    cj, ci = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    ci = ci.ravel()
+    cj = cj.ravel()
+    v00, v10 = nid(ci, cj), nid(ci + 1, cj)
+    v01, v11 = nid(ci, cj + 1), nid(ci + 1, cj + 1)
+    tris = np.empty((ci.size, 2, 3), dtype=np.int64)
+    tris[:, 0] = np.stack([v00, v10, v11], axis=1)
+    tris[:, 1] = np.stack([v00, v11, v01], axis=1)
+    return X, tris.reshape(-1, 3).astype(np.int32)
+
+
+def hinges_from_triangles(tris: np.ndarray) -> np.ndarray:
+    """Interior edges shared by exactly two triangles -> (e0, e1, opp_a, opp_b)."""
+    t = np.asarray(tris, dtype=np.int64)
+    nt = t.shape[0]
+    # each triangle edge (local a,b) with opposite vertex c
+    loc = [(0, 1, 2), (1, 2, 0), (2, 0, 1)]
+    ea = np.concatenate([t[:, a] for a, _, _ in loc])
+    eb = np.concatenate([t[:, b] for _, b, _ in loc])
+    opp = np.concatenate([t[:, c] for _, _, c in loc])
+    tri_id = np.concatenate([np.arange(nt)] * 3)
+    lo = np.minimum(ea, eb)
+    hi = np.maximum(ea, eb)
+    order = np.lexsort((tri_id, hi, lo))
+    lo, hi, opp, tri_id = lo[order], hi[order], opp[order], tri_id[order]
+    same = (lo[:-1] == lo[1:]) & (hi[:-1] == hi[1:])
+    if np.any(same[:-1] & same[1:]):
+        raise ValueError("non-manifold edge (shared by more than two triangles)")
+    first = np.nonzero(same)[0]
+    hinges = np.stack([lo[first], hi[first], opp[first], opp[first + 1]], axis=1)
+    return hinges.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# scenes
+# ----------------------------------------------------------------------------
+def _bottom_fixed(X: np.ndarray, z_min: float | None = None) -> np.ndarray:
+    z = X[:, 2]
+    zmin = z.min() if z_min is None else z_min
+    return (np.abs(z - zmin) <= 1e-12).astype(np.uint8)
+
+
+def tet_cube_scene(n: int, h: float = 0.01, young: float = 1e5, poisson: float = 0.4,
+                   density: float = 1000.0, dt: float = 0.01, seed: int = 1,
+                   perturb: float = 0.01, vel_std: float = 0.0, name: str | None = None,
+                   dims: tuple | None = None) -> Scene:
+    """Cube (or box, via dims) of 6-tet cubes with the bottom face fixed.
+
+    x(t) = X + U(-perturb*h, perturb*h)^3 on free nodes; v(t) ~ N(0, vel_std^2)
+    on free nodes.  Draw order: perturbations (node-major), then velocities.
+    """
+    nx, ny, nz = dims if dims is not None else (n, n, n)
+    X, tets = tet_grid(nx, ny, nz, h)
+    fixed = _bottom_fixed(X)
+    rng = np.random.default_rng(seed)
+    N = X.shape[0]
+    pert = rng.uniform(-perturb * h, perturb * h, size=(N, 3)) if perturb > 0 else np.zeros((N, 3))
+    vel = rng.normal(0.0, vel_std, size=(N, 3)) if vel_std > 0 else np.zeros((N, 3))
+    free = (fixed == 0)[:, None]
+    x0 = X + np.where(free, pert, 0.0)
+    v0 = np.where(free, vel, 0.0)
+    es = EnergySet(SNH_TET4, tets, young=young, poisson=poisson, density=density)
+    return Scene(name or f"tetcube{nx}x{ny}x{nz}", X, [es], fixed, x0, v0, dt=dt,
+                 meta=dict(n=n, h=h, seed=seed))
+
+
+def config_c1() -> Scene:
+    """10^3 cubes, 6,000 tets, SNH E=1e5 nu=0.4, +-1% perturbation (seed 1), v=0."""
+    return tet_cube_scene(10, h=0.01, young=1e5, poisson=0.4, seed=1, perturb=0.01,
+                          vel_std=0.0, name="C1")
+
+
+def config_c2(n: int = 64) -> Scene:
+    """64^3 cubes, 1,572,864 tets, x(t)=X, v ~ N(0, 0.1^2) on free nodes (seed 2)."""
+    return tet_cube_scene(n, h=0.01, young=1e5, poisson=0.4, seed=2, perturb=0.0,
+                          vel_std=0.1, name="C2" if n == 64 else f"C2-n{n}")
+
+
+def config_c4(n: int = 64) -> Scene:
+    """C2 mesh, per-tet E ~ logU(1e4, 1e7) (seed 4), 30% compression, top+bottom fixed."""
+    h = 0.01
+    X, tets = tet_grid(n, n, n, h)
+    rng = np.random.default_rng(4)
+    young = np.exp(rng.uniform(np.log(1e4), np.log(1e7), size=tets.shape[0]))
+    z = X[:, 2]
+    top = np.abs(z - z.max()) <= 1e-12
+    fixed = (_bottom_fixed(X).astype(bool) | top).astype(np.uint8)
+    x0 = X.copy()
+    x0[:, 2] *= 0.7
+    es = EnergySet(SNH_TET4, tets, young_per_elem=young, poisson=0.4, density=1000.0)
+    return Scene("C4" if n == 64 else f"C4-n{n}", X, [es], fixed, x0, np.zeros_like(X),
+                 dt=0.01, meta=dict(n=n, h=h, seed=4))
+
+
+def config_c3(m: int = 512, n_block: int = 32) -> Scene:
+    """Cloth (StVK membrane + Bergou hinges) pinned along y=0, plus an SNH tet block.
+
+    Cloth: [0,1]^2 at z0=1 m, E=1e4, nu=0.3, thickness 1e-3, rho=1000, k_b=1e-3.
+    Block: n_block^3 cubes of 0.01 m at x>=2 m, bottom fixed.  The two are
+    uncoupled; cloth nodes come first in the global numbering.
+    """
+    Xc, tris = cloth_grid(m, 1.0, z0=1.0)
+    hinges = hinges_from_triangles(tris)
+    Xb, tets = tet_grid(n_block, n_block, n_block, 0.01, origin=(2.0, 0.0, 0.0))
+    nc = Xc.shape[0]
+    X = np.concatenate([Xc, Xb])
+    tets = tets + nc
+    fixed = np.zeros(X.shape[0], dtype=np.uint8)
+    fixed[:nc][np.abs(Xc[:, 1]) <= 1e-12] = 1
+    fixed[nc:][np.abs(Xb[:, 2] - Xb[:, 2].min()) <= 1e-12] = 1
+    es = [
+        EnergySet(SNH_TET4, tets, young=1e5, poisson=0.4, density=1000.0),
+        EnergySet(STVK_TRI3, tris, young=1e4, poisson=0.3, thickness=1e-3, density=1000.0),
+        EnergySet(HINGE4, hinges, bend_kb=1e-3),
+    ]
+    return Scene("C3" if m == 512 else f"C3-m{m}", X, es, fixed, X.copy(), np.zeros_like(X),
+                 dt=1.0 / 60.0, meta=dict(m=m, n_block=n_block, seed=3))
+
+
+def cloth_scene(m: int, seed: int = 3, perturb: float = 0.0, kb: float = 1e-3) -> Scene:
+    """Cloth only (membrane + hinges), pinned along y=0, optional seeded perturbation."""
+    Xc, tris = cloth_grid(m, 1.0, z0=1.0)
+    hinges = hinges_from_triangles(tris)
+    fixed = (np.abs(Xc[:, 1]) <= 1e-12).astype(np.uint8)
+    rng = np.random.default_rng(seed)
+    h = 1.0 / m
+    pert = rng.uniform(-perturb * h, perturb * h, size=Xc.shape) if perturb > 0 else 0.0
+    x0 = Xc + np.where((fixed == 0)[:, None], pert, 0.0)
+    es = [EnergySet(STVK_TRI3, tris, young=1e4, poisson=0.3, thickness=1e-3, density=1000.0),
+          EnergySet(HINGE4, hinges, bend_kb=kb)]
+    return Scene(f"cloth{m}", Xc, es, fixed, x0, np.zeros_like(Xc), dt=1.0 / 60.0,
+                 meta=dict(m=m, seed=seed))
+
+
+def config_c5_requests(n_requests: int = 256, rate: float = 200.0, seed: int = 5,
+                       n_min: int = 8, n_max: int = 48):
+    """Serving workload: Poisson arrivals, cube side n ~ round(logU(n_min, n_max)).
+
+    Returns a list of dicts (arrival time [s], n, young, scene seed).  Each
+    request's scene is built with tet_cube_scene(n, young=..., seed=...).
+    """
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    arrivals = np.cumsum(gaps)
+    ns = np.rint(np.exp(rng.uniform(np.log(n_min), np.log(n_max), size=n_requests))).astype(int)
+    young = np.exp(rng.uniform(np.log(1e4), np.log(1e6), size=n_requests))
+    seeds = rng.integers(0, 2**31 - 1, size=n_requests)
+    return [dict(t=float(arrivals[i]), n=int(ns[i]), young=float(young[i]), seed=int(seeds[i]))
+            for i in range(n_requests)]
+
+
+def c5_request_scene(req: dict) -> Scene:
+    return tet_cube_scene(req["n"], h=0.01, young=req["young"], poisson=0.4, seed=req["seed"],
+                          perturb=0.01, vel_std=0.0, name=f"req-n{req['n']}")
+
+
+def random_tets(n_elem: int, seed: int, inverted_frac: float = 0.2):
+    """Stand-alone stressed tets for per-element tests: rest = random well-shaped
+    tet, current = rest under a random affine map (some inverted, some compressed
+    by 30%) plus noise.  Returns (x (E,4,3), X (E,4,3)); conn is implicit."""
+    rng = np.random.default_rng(seed)
+    base = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64) * 0.01
+    X = base[None] + rng.uniform(-0.002, 0.002, size=(n_elem, 4, 3))
+    A = np.eye(3)[None] + rng.uniform(-0.3, 0.3, size=(n_elem, 3, 3))
+    flip = rng.uniform(size=n_elem) < inverted_frac
+    A[flip, :, 2] *= -1.0
+    comp = rng.uniform(size=n_elem) < 0.3
+    A[comp] *= 0.7
+    x = np.einsum("eij,eaj->eai", A, X) + rng.uniform(-1e-4, 1e-4, size=(n_elem, 4, 3))
+    x += rng.uniform(-0.5, 0.5, size=(n_elem, 1, 3))
+    return x, X

@@ -1,0 +1,562 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Every pin is chosen so that a plausible slip (a dropped term, a wrong sign or
+index, a transposed operand) fails one of them:
+* complex-step derivatives of the oracle's own energies (exact to rounding for
+  analytic functions) check the hand-derived gradients and Hessians;
+* textbook linear-elasticity stiffness matrices (Voigt B^T C B) check the rest
+  Hessians and the Stable Neo-Hookean re-parametrisation;
+* closed forms (rest energy, uniaxial stretch, rotating one hinge wing) and
+  invariants (translation, rotation, relabelling, symmetry);
+* brute force for the sparsity pattern and closed-form block counts;
+* matrices with known eigen-decomposition for the PSD projection;
+* a direct sparse solve and exact rigid-motion solutions for the Newton step.
+"""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import assembly, elements, newton, projection, rest
+
+
+def _rot(seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).normal(size=(3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    return q
+
+
+def _cs_grad(f, x, h=1e-30):
+    """Complex-step gradient of a batched scalar function f(x) -> (E,)."""
+    E, k, _ = x.shape
+    g = np.zeros((E, k, 3))
+    for a in range(k):
+        for i in range(3):
+            xc = x.astype(complex)
+            xc[:, a, i] += 1j * h
+            g[:, a, i] = np.imag(f(xc)) / h
+    return g
+
+
+def _cs_jac(gf, x, h=1e-30):
+    """Complex-step Jacobian of a batched gradient function -> (E,k,3,k,3)."""
+    E, k, _ = x.shape
+    H = np.zeros((E, k, 3, k, 3))
+    for b in range(k):
+        for j in range(3):
+            xc = x.astype(complex)
+            xc[:, b, j] += 1j * h
+            H[:, :, :, b, j] = np.imag(gf(xc)) / h
+    return H
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+# ----------------------------------------------------------------------------
+# Stable Neo-Hookean tet4
+# ----------------------------------------------------------------------------
+MU, LAM = rest.lame(1e5, 0.4)
+
+
+def _snh(x, X, **kw):
+    n = x.shape[0]
+    return elements.snh_tet4(x, X, np.full(n, MU), np.full(n, LAM), **kw)
+
+
+def test_lame_c1_values():
+    # E = 1e5, nu = 0.4: mu = E/2.8, lambda = 0.4E/0.28
+    assert MU == pytest.approx(1e5 / 2.8, rel=1e-15)
+    assert LAM == pytest.approx(0.4e5 / 0.28, rel=1e-15)
+    mu_, lam_ = rest.snh_reparam(MU, LAM)
+    assert mu_ == pytest.approx(47619.047619047619, rel=1e-14)
+    assert lam_ == pytest.approx(172619.04761904762, rel=1e-14)
+
+
+def test_snh_gradient_complex_step():
+    x, X = sg.random_tets(40, seed=11)
+    _, g, _ = _snh(x, X, want_hess=False)
+    gc = _cs_grad(lambda xc: _snh(xc, X, want_hess=False)[0], x)
+    assert _rel(g, gc) < 1e-12
+
+
+def test_snh_hessian_complex_step():
+    x, X = sg.random_tets(40, seed=12)
+    _, _, H = _snh(x, X)
+    Hc = _cs_jac(lambda xc: _snh(xc, X, want_hess=False)[1], x)
+    assert _rel(H, Hc) < 1e-12
+
+
+def test_snh_central_differences():
+    x, X = sg.random_tets(5, seed=13)
+    E, g, _ = _snh(x, X, want_hess=False)
+    h = 1e-8
+    for a, i in [(0, 0), (1, 2), (3, 1)]:
+        xp = x.copy(); xp[:, a, i] += h
+        xm = x.copy(); xm[:, a, i] -= h
+        fd = (_snh(xp, X, want_hess=False)[0] - _snh(xm, X, want_hess=False)[0]) / (2 * h)
+        assert np.allclose(fd, g[:, a, i], rtol=1e-5, atol=1e-6 * np.abs(g).max())
+
+
+def _tet_rest():
+    _, X = sg.random_tets(8, seed=14)
+    return X
+
+
+def test_snh_rest_energy_closed_form():
+    # psi(I) = lam'/2 (1-alpha)^2 - mu'/2 log 4 with 1 - alpha = -3 mu'/(4 lam')
+    X = _tet_rest()
+    E, g, _ = _snh(X, X, want_hess=False)
+    mu_ = 4.0 / 3.0 * MU
+    lam_ = LAM + 5.0 / 6.0 * MU
+    psi_I = 9.0 * mu_ ** 2 / (32.0 * lam_) - 0.5 * mu_ * np.log(4.0)
+    assert psi_I == pytest.approx(-29312.4, abs=0.05)            # E=1e5, nu=0.4
+    V = np.abs(np.linalg.det(np.stack([X[:, a] - X[:, 0] for a in (1, 2, 3)], 2))) / 6
+    assert np.allclose(E, V * psi_I, rtol=1e-13)
+    # zero rest gradient (relative to a typical nodal force scale mu*h^2)
+    assert np.max(np.abs(g)) < 1e-9 * MU * 1e-4
+
+
+def _voigt_C3(mu, lam):
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    C[[0, 1, 2], [0, 1, 2]] = lam + 2 * mu
+    C[[3, 4, 5], [3, 4, 5]] = mu
+    return C
+
+
+def _cst_tet_stiffness(X, mu, lam):
+    """Textbook constant-strain tet: K = V B^T C B (Voigt, engineering shear)."""
+    Dm = np.stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]], axis=1)
+    V = abs(np.linalg.det(Dm)) / 6.0
+    # shape-function gradients from the 4x4 system [1 X] c = I
+    M = np.hstack([np.ones((4, 1)), X])
+    grads = np.linalg.inv(M)[1:, :].T          # (4,3): dN_a/dX
+    B = np.zeros((6, 12))
+    for a in range(4):
+        dx, dy, dz = grads[a]
+        B[0, 3 * a + 0] = dx
+        B[1, 3 * a + 1] = dy
+        B[2, 3 * a + 2] = dz
+        B[3, 3 * a + 1] = dz; B[3, 3 * a + 2] = dy      # gamma_yz
+        B[4, 3 * a + 0] = dz; B[4, 3 * a + 2] = dx      # gamma_xz
+        B[5, 3 * a + 0] = dy; B[5, 3 * a + 1] = dx      # gamma_xy
+    return V * B.T @ _voigt_C3(mu, lam) @ B
+
+
+def test_snh_rest_hessian_is_linear_elasticity():
+    X = _tet_rest()
+    _, _, H = _snh(X, X)
+    for e in range(X.shape[0]):
+        K = _cst_tet_stiffness(X[e], MU, LAM)
+        assert _rel(H[e].reshape(12, 12), K) < 1e-12
+        ev = np.linalg.eigvalsh(K)
+        assert np.sum(np.abs(ev) < 1e-9 * ev.max()) == 6        # rigid modes
+
+
+def test_snh_invariances_and_symmetry():
+    x, X = sg.random_tets(20, seed=15)
+    E, g, H = _snh(x, X)
+    Hm = H.reshape(-1, 12, 12)
+    assert _rel(Hm, np.swapaxes(Hm, 1, 2)) < 1e-13
+    # translation: sum of nodal forces = 0, H (1 (x) t) = 0
+    assert np.max(np.abs(g.sum(axis=1))) < 1e-12 * np.abs(g).max()
+    t = np.tile(np.array([0.3, -0.7, 0.2]), 4)
+    assert np.max(np.abs(Hm @ t)) < 1e-11 * np.abs(Hm).max()
+    # rotation
+    R = _rot(3)
+    E2, g2, H2 = _snh(x @ R.T, X)
+    assert np.allclose(E2, E, rtol=1e-12, atol=1e-12 * np.abs(E).max())
+    assert _rel(g2, g @ R.T) < 1e-11
+    RR = np.kron(np.eye(4), R)
+    assert _rel(H2.reshape(-1, 12, 12), RR @ Hm @ RR.T) < 1e-11
+    # relabelling the vertices (same permutation of x and X) leaves E unchanged
+    for perm in ([1, 2, 3, 0], [2, 0, 1, 3], [3, 2, 1, 0]):
+        E3, g3, _ = _snh(x[:, perm], X[:, perm], want_hess=False)
+        assert np.allclose(E3, E, rtol=1e-12, atol=1e-12 * np.abs(E).max())
+        assert _rel(g3, g[:, perm]) < 1e-11
+
+
+# ----------------------------------------------------------------------------
+# StVK membrane
+# ----------------------------------------------------------------------------
+def _random_tris(n, seed, stretch=0.2):
+    rng = np.random.default_rng(seed)
+    base = np.array([[0, 0, 0], [1, 0, 0], [0.2, 0.9, 0]], dtype=np.float64) * 0.01
+    X = base[None] + rng.uniform(-0.002, 0.002, size=(n, 3, 3))
+    X = np.einsum("ij,eaj->eai", _rot(seed), X)
+    A = np.eye(3)[None] + rng.uniform(-stretch, stretch, size=(n, 3, 3))
+    x = np.einsum("eij,eaj->eai", A, X) + rng.uniform(-1, 1, size=(n, 1, 3))
+    return x, X
+
+
+MU2, LAM2 = rest.lame(1e4, 0.3)
+
+
+def _stvk(x, X, **kw):
+    n = x.shape[0]
+    return elements.stvk_tri3(x, X, np.full(n, MU2), np.full(n, LAM2), 1e-3, **kw)
+
+
+def test_stvk_derivatives_complex_step():
+    x, X = _random_tris(30, 21)
+    _, g, H = _stvk(x, X)
+    gc = _cs_grad(lambda xc: _stvk(xc, X, want_hess=False)[0], x)
+    Hc = _cs_jac(lambda xc: _stvk(xc, X, want_hess=False)[1], x)
+    assert _rel(g, gc) < 1e-12
+    assert _rel(H, Hc) < 1e-12
+
+
+def test_stvk_uniaxial_stretch_closed_form():
+    # stretch s along the first rest edge: psi = (mu + lam/2) ((s^2 - 1)/2)^2
+    _, X = _random_tris(6, 22)
+    d1 = X[:, 1] - X[:, 0]
+    e1 = d1 / np.linalg.norm(d1, axis=1, keepdims=True)
+    for s in (1.1, 0.8):
+        x = X + (s - 1.0) * np.einsum("ea,ei->eai", np.einsum("eai,ei->ea", X - X[:, :1], e1), e1)
+        E, _, _ = _stvk(x, X, want_hess=False)
+        A = 0.5 * np.linalg.norm(np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]), axis=1)
+        psi = (MU2 + 0.5 * LAM2) * ((s * s - 1.0) / 2.0) ** 2
+        assert np.allclose(E, 1e-3 * A * psi, rtol=1e-12)
+
+
+def _cst_membrane_stiffness(X, mu, lam, h):
+    """Textbook plane CST in the triangle's own 2D frame, rotated to 3D."""
+    d1 = X[1] - X[0]
+    d2 = X[2] - X[0]
+    n = np.cross(d1, d2); n /= np.linalg.norm(n)
+    t1 = d1 / np.linalg.norm(d1)
+    t2 = np.cross(n, t1)
+    P = np.stack([t1, t2])                     # (2,3) projection to the plane
+    p = (X - X[0]) @ P.T                       # (3,2) local coordinates
+    A = 0.5 * abs(np.linalg.det(np.stack([p[1], p[2]], 1)))
+    M = np.hstack([np.ones((3, 1)), p])
+    grads = np.linalg.inv(M)[1:, :].T          # (3,2)
+    B = np.zeros((3, 6))
+    for a in range(3):
+        dx, dy = grads[a]
+        B[0, 2 * a] = dx
+        B[1, 2 * a + 1] = dy
+        B[2, 2 * a] = dy; B[2, 2 * a + 1] = dx
+    C = np.array([[lam + 2 * mu, lam, 0], [lam, lam + 2 * mu, 0], [0, 0, mu]])
+    K2 = h * A * B.T @ C @ B
+    T = np.kron(np.eye(3), P)                  # (6,9) 3D -> local displacements
+    return T.T @ K2 @ T
+
+
+def test_stvk_rest_is_plane_cst():
+    _, X = _random_tris(6, 23)
+    E, g, H = _stvk(X, X)
+    assert np.max(np.abs(E)) < 1e-20
+    assert np.max(np.abs(g)) < 1e-14
+    for e in range(X.shape[0]):
+        K = _cst_membrane_stiffness(X[e], MU2, LAM2, 1e-3)
+        assert _rel(H[e].reshape(9, 9), K) < 1e-12
+        ev = np.linalg.eigvalsh(K)
+        assert np.sum(ev > 1e-9 * ev.max()) == 3
+
+
+def test_stvk_invariances():
+    x, X = _random_tris(10, 24)
+    E, g, H = _stvk(x, X)
+    R = _rot(5)
+    E2, g2, _ = _stvk(x @ R.T, X)
+    assert np.allclose(E2, E, rtol=1e-12)
+    assert _rel(g2, g @ R.T) < 1e-11
+    # rotating the rest triangle does not change anything (frame choice)
+    E3, g3, H3 = _stvk(x, X @ _rot(6).T)
+    assert np.allclose(E3, E, rtol=1e-11)
+    assert _rel(H3, H) < 1e-10
+    E4, g4, _ = _stvk(x[:, [1, 2, 0]], X[:, [1, 2, 0]], want_hess=False)
+    assert np.allclose(E4, E, rtol=1e-12)
+    assert _rel(g4, g[:, [1, 2, 0]]) < 1e-11
+
+
+# ----------------------------------------------------------------------------
+# Bending hinge
+# ----------------------------------------------------------------------------
+def _flat_hinges(n, seed):
+    rng = np.random.default_rng(seed)
+    X = np.zeros((n, 4, 3))
+    X[:, 1, 0] = rng.uniform(0.5, 1.5, n)
+    X[:, 2, :2] = np.stack([rng.uniform(0.1, 0.9, n), rng.uniform(0.3, 1.0, n)], 1)
+    X[:, 3, :2] = np.stack([rng.uniform(0.1, 0.9, n), -rng.uniform(0.3, 1.0, n)], 1)
+    X = np.einsum("ij,eaj->eai", _rot(seed), X) + rng.normal(size=(n, 1, 3))
+    return X * 0.01
+
+
+def test_hinge_flat_rest_and_translation():
+    X = _flat_hinges(20, 31)
+    K, c = elements.hinge_rest(X)
+    assert np.max(np.abs(K.sum(1))) < 1e-12 * np.abs(K).max()
+    E, g, H = elements.hinge4(X, X, 1e-3)
+    assert np.max(np.abs(E)) < 1e-30 + 1e-24
+    assert np.max(np.abs(g)) < 1e-14
+
+
+def test_hinge_wing_rotation_closed_form():
+    # rotating one wing by theta about the edge: E = k_b/2 * 3|e|^2/(A0+A1) * (2 sin(theta/2))^2
+    X = _flat_hinges(10, 32)
+    kb = 2e-3
+    e = X[:, 1] - X[:, 0]
+    eh = e / np.linalg.norm(e, axis=1, keepdims=True)
+    A0 = 0.5 * np.linalg.norm(np.cross(e, X[:, 2] - X[:, 0]), axis=1)
+    A1 = 0.5 * np.linalg.norm(np.cross(e, X[:, 3] - X[:, 0]), axis=1)
+    for wing in (2, 3):
+        for theta in (0.3, -1.1):
+            x = X.copy()
+            r = X[:, wing] - X[:, 0]
+            par = np.einsum("ei,ei->e", r, eh)[:, None] * eh
+            perp = r - par
+            x[:, wing] = X[:, 0] + par + np.cos(theta) * perp + np.sin(theta) * np.cross(eh, perp)
+            E, _, _ = elements.hinge4(x, X, kb, want_hess=False)
+            ref = 0.5 * kb * 3 * np.sum(e * e, 1) / (A0 + A1) * (2 * np.sin(theta / 2)) ** 2
+            assert np.allclose(E, ref, rtol=1e-11)
+
+
+def test_hinge_derivatives():
+    X = _flat_hinges(10, 33)
+    x = X + np.random.default_rng(1).normal(scale=1e-3, size=X.shape)
+    _, g, H = elements.hinge4(x, X, 1e-3)
+    assert _rel(g, _cs_grad(lambda xc: elements.hinge4(xc, X, 1e-3, want_hess=False)[0], x)) < 1e-12
+    assert _rel(H, _cs_jac(lambda xc: elements.hinge4(xc, X, 1e-3, want_hess=False)[1], x)) < 1e-12
+    _, _, H2 = elements.hinge4(x * 1.7 + 0.2, X, 1e-3)
+    assert _rel(H2, H) < 1e-15                        # constant quadratic form
+    ev = np.linalg.eigvalsh(H.reshape(-1, 12, 12))
+    assert np.all(ev > -1e-12 * ev.max())
+    assert np.all(np.sum(ev > 1e-9 * ev.max(axis=1, keepdims=True), axis=1) == 3)
+
+
+# ----------------------------------------------------------------------------
+# inertia, masses
+# ----------------------------------------------------------------------------
+def test_inertia_and_masses():
+    s = sg.tet_cube_scene(3, h=0.01, seed=1)
+    m = rest.lumped_mass(s)
+    assert np.sum(m) == pytest.approx(1000.0 * (0.03) ** 3, rel=1e-12)
+    assert np.all(m > 0)
+    cs = sg.cloth_scene(4)
+    mc = rest.lumped_mass(cs)
+    assert np.sum(mc) == pytest.approx(1000.0 * 1e-3 * 1.0, rel=1e-12)
+    xt = s.x0 + 0.001
+    E, g, w = elements.inertia(s.x0, xt, m, 0.01)
+    assert np.allclose(E, 0.5 * m / 1e-4 * 3e-6, rtol=1e-12)
+    assert np.allclose(g, -m[:, None] / 1e-4 * 1e-3, rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# projection
+# ----------------------------------------------------------------------------
+def test_projection_known_spectrum():
+    rng = np.random.default_rng(41)
+    for n in (9, 12):
+        Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+        d = rng.normal(size=n)
+        d[:3] = [-2.0, -1e-3, 0.0]
+        H = (Q * d) @ Q.T
+        ref = (Q * np.maximum(d, 0)) @ Q.T
+        P = projection.project_psd(H[None])[0]
+        assert _rel(P, ref) < 1e-13
+        assert _rel(projection.project_psd(P[None])[0], P) < 1e-13        # idempotent
+        S = (Q * np.abs(d)) @ Q.T                                          # PSD input
+        assert _rel(projection.project_psd(S[None])[0], S) < 1e-13
+        # nearest: no random PSD matrix is closer
+        for _ in range(20):
+            B = rng.normal(size=(n, n))
+            T = P + 0.1 * B @ B.T
+            assert np.linalg.norm(H - P) <= np.linalg.norm(H - T) + 1e-14
+
+
+# ----------------------------------------------------------------------------
+# pattern, scatter map, assembly
+# ----------------------------------------------------------------------------
+def _tet_nnzb(n):
+    return (n + 1) ** 3 + 2 * (3 * n * (n + 1) ** 2 + 3 * n * n * (n + 1) + n ** 3)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_tet_pattern_closed_form(n):
+    s = sg.tet_cube_scene(n, seed=1)
+    rp, ci = assembly.pattern(s)
+    assert ci.size == _tet_nnzb(n)
+    upper = np.sum(ci >= np.repeat(np.arange(s.n_nodes), np.diff(rp)))
+    assert upper == (2 * n + 1) ** 3
+    rp2, ci2 = assembly.pattern_fast(s)
+    assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2)
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_cloth_pattern_closed_form(m):
+    s = sg.cloth_scene(m)
+    assert s.energies[1].conn.shape[0] == 3 * m * m - 2 * m
+    rp, ci = assembly.pattern(s)
+    assert ci.size == (m + 1) ** 2 + 12 * m * m
+    rp2, ci2 = assembly.pattern_fast(s)
+    assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2)
+
+
+def test_c1_block_count():
+    s = sg.config_c1()
+    rp, ci = assembly.pattern_fast(s)
+    assert ci.size == 17191 == _tet_nnzb(10)
+    assert np.all(np.diff(rp) <= 15)
+
+
+def test_scatter_map_brute_force():
+    s = sg.tet_cube_scene(2, seed=1)
+    rp, ci = assembly.pattern(s)
+    sm = assembly.scatter_map(s, rp, ci)[0]
+    fast = assembly._block_index(s.energies[0].conn, rp, ci)
+    assert np.array_equal(sm, fast)
+    rows = np.repeat(np.arange(s.n_nodes), np.diff(rp))
+    c = s.energies[0].conn
+    for a in range(4):
+        for b in range(4):
+            assert np.array_equal(rows[sm[:, a, b]], c[:, a])
+            assert np.array_equal(ci[sm[:, a, b]], c[:, b])
+
+
+def _small_mixed_scene():
+    s = sg.tet_cube_scene(2, seed=7, perturb=0.05)
+    c = sg.cloth_scene(2, perturb=0.1)
+    # merge: tets first, cloth nodes after
+    N = s.n_nodes
+    es = [s.energies[0]] + [sg.EnergySet(e.kind, e.conn + N, young=e.young, poisson=e.poisson,
+                                         thickness=e.thickness, bend_kb=e.bend_kb,
+                                         density=e.density) for e in c.energies]
+    X = np.concatenate([s.X, c.X])
+    x0 = np.concatenate([s.x0, c.x0])
+    fixed = np.concatenate([s.fixed, c.fixed])
+    return sg.Scene("mixed", X, es, fixed, x0, np.zeros_like(X))
+
+
+def test_assembly_matches_complex_step_of_total_energy():
+    s = _small_mixed_scene()
+    rng = np.random.default_rng(3)
+    x = s.x0 + rng.uniform(-1e-3, 1e-3, size=s.x0.shape)
+    xt = x + rng.normal(scale=1e-3, size=x.shape)
+    dt = 0.01
+    a = assembly.assemble(s, x, xt, dt, dirichlet=False)
+    N = s.n_nodes
+    A = assembly.to_scipy(a["row_ptr"], a["col_idx"], a["vals"]).toarray()
+    h = 1e-30
+    for k in rng.choice(3 * N, size=12, replace=False):
+        xc = x.astype(complex)
+        xc.reshape(-1)[k] += 1j * h
+        Ec = assembly.energy(s, xc, xt, dt) if False else _energy_complex(s, xc, xt, dt)
+        assert np.imag(Ec) / h == pytest.approx(a["g"].reshape(-1)[k], rel=1e-10,
+                                                abs=1e-12 * np.abs(a["g"]).max())
+        col = _grad_complex(s, xc, xt, dt).reshape(-1)
+        assert np.allclose(np.imag(col) / h, A[:, k], rtol=1e-10, atol=1e-10 * np.abs(A).max())
+    # block symmetry
+    assert np.allclose(A, A.T, rtol=0, atol=1e-12 * np.abs(A).max())
+
+
+def _energy_complex(s, x, xt, dt):
+    E = 0.0
+    for es in s.energies:
+        E = E + np.sum(elements.element_eval(es, x, s.X, want_hess=False)[0])
+    m = rest.lumped_mass(s)
+    return E + np.sum(elements.inertia(x, xt, m, dt)[0])
+
+
+def _grad_complex(s, x, xt, dt):
+    g = np.zeros(x.shape, dtype=complex)
+    for es in s.energies:
+        _, ge, _ = elements.element_eval(es, x, s.X, want_hess=False)
+        np.add.at(g, es.conn.ravel(), ge.reshape(-1, 3))
+    m = rest.lumped_mass(s)
+    return g + elements.inertia(x, xt, m, dt)[1]
+
+
+def test_dirichlet_and_matrix_free_product():
+    s = _small_mixed_scene()
+    x = s.x0
+    a = assembly.assemble(s, x, s.x0, 0.01, dirichlet=True)
+    rp, ci, vals = a["row_ptr"], a["col_idx"], a["vals"]
+    fixed = s.fixed.astype(bool)
+    assert np.all(a["g"][fixed] == 0)
+    rows = np.repeat(np.arange(s.n_nodes), np.diff(rp))
+    for b in range(ci.size):
+        if fixed[rows[b]] or fixed[ci[b]]:
+            ref = np.eye(3) if rows[b] == ci[b] else np.zeros((3, 3))
+            assert np.array_equal(vals[b], ref)
+    # without Dirichlet: BSR p == sum_e R_e^T H_e R_e p + M/dt^2 p
+    a2 = assembly.assemble(s, x, s.x0, 0.01, dirichlet=False)
+    p = np.random.default_rng(5).normal(size=x.shape)
+    y = (assembly.to_scipy(rp, ci, a2["vals"]) @ p.ravel()).reshape(-1, 3)
+    ref = rest.lumped_mass(s)[:, None] / 1e-4 * p
+    for es in s.energies:
+        _, _, He = elements.element_eval(es, x, s.X)
+        k = es.conn.shape[1]
+        ye = np.einsum("emn,en->em", He.reshape(-1, 3 * k, 3 * k), p[es.conn].reshape(-1, 3 * k))
+        np.add.at(ref, es.conn.ravel(), ye.reshape(-1, 3))
+    assert _rel(y, ref) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# solver
+# ----------------------------------------------------------------------------
+def test_pcg_matches_direct_solve():
+    s = sg.config_c1()
+    xt = elements.x_tilde(s.x0, s.v0, 0.01, (0, 0, -9.81))
+    a = assembly.assemble(s, s.x0, xt, 0.01)
+    A = assembly.to_scipy(a["row_ptr"], a["col_idx"], a["vals"])
+    b = -a["g"].ravel()
+    import scipy.sparse.linalg as spla
+    ref = spla.spsolve(A.tocsc(), b)
+    D = newton.diag_inverse(a["row_ptr"], a["col_idx"], a["vals"])
+    x, it, ok = newton.pcg(A, D, b, 1e-13, 2000)
+    assert ok and it > 1
+    assert _rel(x, ref) < 1e-10
+
+
+def test_newton_rigid_translation_is_exact():
+    # no gravity, no fixed nodes, uniform velocity: E_elastic is translation
+    # invariant, so x(t+dt) = x(t) + dt v exactly
+    s = sg.tet_cube_scene(2, seed=2, perturb=0.0)
+    s.fixed[:] = 0
+    v = np.tile(np.array([[0.3, -0.1, 0.2]]), (s.n_nodes, 1))
+    prm = newton.StepParams(dt=0.01, gravity=(0, 0, 0))
+    st = newton.Stepper(s, prm, solver="direct")
+    x1, v1, rep = st.step(s.X.copy(), v)
+    assert rep["status"] == "ok"
+    assert np.allclose(x1, s.X + 0.01 * v, rtol=0, atol=1e-12)
+    assert np.allclose(v1, v, atol=1e-9)
+
+
+def test_newton_quadratic_energy_one_iteration():
+    # inertia + bending only: E_BE is quadratic, so one exact Newton step solves it
+    c = sg.cloth_scene(3, perturb=0.2)
+    c.energies = [c.energies[1]]
+    prm = newton.StepParams(dt=1 / 60)
+    rec = []
+    ok, x, rep = newton.newton_solve(c, c.x0, c.v0, prm.dt, prm, solver="direct", record=rec)
+    assert ok and rep["newton_iters"] == 1
+    assert rep["residual"] <= 1e-9 * rep["residual0"]
+
+
+def test_newton_c1_converges_and_descends():
+    s = sg.config_c1()
+    prm = newton.StepParams(dt=0.01)
+    rec = []
+    ok, x, rep = newton.newton_solve(s, s.x0, s.v0, 0.01, prm, solver="pcg", record=rec)
+    assert ok
+    assert rep["residual"] <= 1e-6 * rep["residual0"]
+    Es = [r["E"] for r in rec] + [rep["energy"]]
+    assert all(b <= a for a, b in zip(Es, Es[1:]))
+
+
+def test_dt_halving_control():
+    s = sg.tet_cube_scene(2, seed=1)
+    prm = newton.StepParams(dt=0.01, max_newton=0, max_halvings=3)
+    st = newton.Stepper(s, prm)
+    x, v, rep = st.step(s.x0, s.v0)
+    assert rep["dt_halvings"] == 3 and rep["status"] == "not_converged"
+    prm2 = newton.StepParams(dt=0.01)
+    st2 = newton.Stepper(s, prm2)
+    st2.dt_cur = 0.0025
+    for k in range(3):
+        st2.step(s.x0, s.v0)
+    assert st2.dt_cur == 0.005
