@@ -1,0 +1,214 @@
+/*
+ * symx.h -- C-ABI of libsymx.so: per-element energy derivatives, assembly into
+ * a 3x3 block-sparse Hessian and implicit-Euler Newton steps on one MI355X.
+ *
+ * Problem statement (the paper's Sec. 3, Eq. 5): the global degrees of freedom
+ * are node positions x (N x 3); every energy set applies one element energy to
+ * a list of fixed-size elements (connectivity + per-element parameters); the
+ * total energy is the sum over sets and elements, plus the inertia term of the
+ * incremental potential (Eq. 2) during time stepping.  The library evaluates
+ * the three levels of Sec. 5.2 (energy; energy and gradient; energy, gradient
+ * and Hessian), assembles the gradient and a 3x3 block compressed-row Hessian
+ * (Sec. 5.3, BCRS), optionally projects every element Hessian to positive
+ * semi-definiteness first (Sec. 5.2, Alg. 1 ProjectToPD), and runs the Newton
+ * loop of Sec. 7 (block-diagonal PCG with a forcing sequence, backtracking line
+ * search, time-step halving on failure).
+ *
+ * Conventions for every function:
+ *   - return value: SYMX_OK or an error status; nothing throws across the ABI.
+ *     symx_last_error() gives a thread-local message for the last failure.
+ *     On error the outputs are unspecified; no caller buffer is freed.
+ *   - "host" pointers are CPU memory; "device" pointers are HIP device memory
+ *     (e.g. torch tensor data pointers) on the mesh's device.
+ *   - position, velocity and gradient arrays are N x 3 row-major float64
+ *     (node-major, x y z), i.e. 3N contiguous doubles.
+ *   - calls enqueue on the mesh's HIP stream; a call that returns a host
+ *     scalar (energy, report) synchronises that stream before returning.
+ *   - one mesh must not be used by two threads at once; different meshes may.
+ */
+#ifndef SYMX_H
+#define SYMX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct symx_mesh_s* symx_mesh;
+
+typedef enum {
+  SYMX_OK = 0,
+  SYMX_ERR_INVALID_ARG = 1,   /* bad pointer, size, index or option */
+  SYMX_ERR_OUT_OF_MEMORY = 2, /* device or pinned host allocation failed */
+  SYMX_ERR_DEVICE = 3,        /* a HIP runtime call or kernel launch failed */
+  SYMX_ERR_NONFINITE = 4,     /* NaN/Inf met in positions, energy or gradient */
+  SYMX_ERR_NOT_CONVERGED = 5, /* Newton did not converge within all halvings */
+  SYMX_ERR_LINE_SEARCH = 6,   /* line search failed within all halvings */
+  SYMX_ERR_BUDGET = 7         /* request exceeds a configured memory budget */
+} symx_status;
+
+/* Arithmetic of the element kernels and of the linear solve. */
+typedef enum {
+  SYMX_F64 = 0,          /* everything in float64 */
+  SYMX_F32 = 1,          /* element kernels, Hessian values and PCG in float32;
+                            gradient and energy sums accumulated in float64 */
+  SYMX_F32_REFINED = 2   /* Newton only: Hessian values, SpMV and PCG in float32;
+                            energies, gradient, residual and the iterative-
+                            refinement correction in float64 */
+} symx_precision;
+
+/* Element energies (the paper's App. B and Eq. 13). */
+typedef enum {
+  SYMX_SNH_TET4 = 0,   /* Stable Neo-Hookean, linear tet: E = V psi(F), 4 nodes  */
+  SYMX_STVK_TRI3 = 1,  /* St. Venant-Kirchhoff membrane triangle, 3 nodes        */
+  SYMX_HINGE4 = 2      /* quadratic bending hinge (edge v0-v1, wings v2, v3)     */
+} symx_energy_kind;
+
+/* Evaluation flags (the three levels of Sec. 5.2, plus options). */
+enum {
+  SYMX_EVAL_E = 1,
+  SYMX_EVAL_GRAD = 2,
+  SYMX_EVAL_HESS = 4,
+  SYMX_PROJECT_PSD = 8,   /* project each element Hessian onto the PSD cone   */
+  SYMX_DIRICHLET = 16     /* zero gradient rows and Hessian rows/columns of
+                             fixed nodes, identity diagonal block            */
+};
+
+/* One energy applied to a set of elements.  Material data are converted by
+ * the library: Lame parameters from (young, poisson) with the 3D formulas. */
+typedef struct {
+  int32_t kind;            /* symx_energy_kind                                 */
+  int64_t n_elem;          /* number of elements, >= 0                         */
+  const int32_t* conn;     /* host, n_elem x (4 | 3 | 4) node ids in [0, N)     */
+  const double* young;     /* host, per-element Young's modulus, or NULL       */
+  double young_const;      /* Young's modulus when young == NULL               */
+  double poisson;          /* Poisson ratio (tets, triangles)                  */
+  double thickness;        /* membrane thickness (triangles)                   */
+  double bend_kb;          /* bending stiffness k_b (hinges)                   */
+  double density;          /* mass density, kg/m^3 (tets, triangles)           */
+} symx_energy_desc;
+
+typedef struct {
+  int64_t n_nodes;                   /* N >= 1                                 */
+  const double* x_rest;              /* host, N x 3 rest positions             */
+  int32_t n_energies;                /* 1..4                                   */
+  const symx_energy_desc* energies;  /* host, n_energies descriptors           */
+  const uint8_t* fixed;              /* host, N flags (1 = Dirichlet) or NULL   */
+  void* hip_stream;                  /* hipStream_t to enqueue on; NULL = null stream */
+} symx_mesh_desc;
+
+/* Read-only view of the mesh-owned assembled Hessian (device pointers).
+ * Values are stored component-major: entry (i, j) of block b is
+ * values[(3*i + j) * nnzb + b], as float or double per `precision`.
+ * Valid until the next call on the mesh or its destruction. */
+typedef struct {
+  int64_t n_block_rows;
+  int64_t nnzb;
+  const int32_t* row_ptr;   /* device, n_block_rows + 1 */
+  const int32_t* col_idx;   /* device, nnzb, ascending within each row */
+  const void* values;       /* device, 9 * nnzb */
+  int32_t precision;        /* SYMX_F64 or SYMX_F32 */
+} symx_bsr_view;
+
+typedef struct {
+  int64_t n_nodes, nnzb, n_incidences, n_batches;
+  int64_t n_elem[4];
+  int32_t n_energies, max_row_blocks;
+  double total_mass;
+} symx_mesh_info;
+
+typedef struct {
+  double dt;                 /* nominal time step (s)                           */
+  double gravity[3];         /* enters through x_tilde = x + dt v + dt^2 g      */
+  double newton_rtol;        /* stop when |g_free| <= rtol * |g_free(x(t))|     */
+  int32_t max_newton;        /* Newton iterations per attempt                   */
+  int32_t max_pcg;           /* PCG iterations per linear solve                 */
+  int32_t project;           /* 1: project element Hessians to PSD              */
+  int32_t precision;         /* symx_precision                                  */
+  int32_t max_halvings;      /* dt halvings before giving up                    */
+  int32_t regrow_after;      /* successful steps before dt is doubled back      */
+  int32_t max_refine;        /* F32_REFINED: refinement passes per solve        */
+} symx_step_params;
+
+typedef struct {
+  int32_t status;            /* symx_status of the step                         */
+  int32_t newton_iters, pcg_iters, ls_backtracks, dt_halvings, refinements;
+  double dt_used;            /* time step actually taken                        */
+  double residual0, residual;/* |g_free| at x(t) and at the result (float64)    */
+  double energy;             /* incremental potential at the result             */
+  double ms_assemble, ms_pcg, ms_linesearch, ms_total;
+} symx_step_report;
+
+/* Defaults for symx_step_params: dt 0.01, gravity (0,0,-9.81), rtol 1e-6,
+ * max_newton 100, max_pcg 500, project 0, precision SYMX_F64, max_halvings 8,
+ * regrow_after 3, max_refine 4. */
+void symx_step_params_default(symx_step_params* p);
+
+/* Build a mesh: copies all host inputs (the caller may free them afterwards),
+ * computes rest data (volumes, areas, hinge weights, lumped masses), the block
+ * sparsity pattern (block (i,j) exists iff i and j share an element; all
+ * diagonal blocks exist), the scatter map and the per-node incidence lists,
+ * and uploads them to the current HIP device.  Errors: INVALID_ARG for node
+ * ids out of range, degenerate rest elements, more than 255 blocks or 256
+ * element incidences on one node; OUT_OF_MEMORY; DEVICE. */
+symx_status symx_mesh_create(const symx_mesh_desc* desc, symx_mesh* out);
+symx_status symx_mesh_destroy(symx_mesh mesh);
+symx_status symx_mesh_get_info(symx_mesh mesh, symx_mesh_info* info);
+
+/* Host copies of the pattern: row_ptr (N+1), col_idx (nnzb) and, if
+ * scatter_map is not NULL, the scatter map of every energy set concatenated:
+ * for set s, element e, local nodes (a, b) in row-major order, the index of
+ * block (conn[e][a], conn[e][b]) in col_idx (n_elem * k * k int32 per set).
+ * Any pointer may be NULL to skip that output. */
+symx_status symx_mesh_get_pattern(symx_mesh mesh, int32_t* row_ptr, int32_t* col_idx,
+                                  int32_t* scatter_map);
+
+/* Lumped node masses (host, N doubles): rho V / 4 per tet, rho h A / 3 per
+ * triangle (the inertia term of Eq. 2). */
+symx_status symx_mesh_get_masses(symx_mesh mesh, double* mass_host);
+
+/* Per-element evaluation of one energy set (the low-level element interface
+ * of Sec. 5.2 and the local-output option of Sec. 5.3).  x_dev: device N x 3
+ * float64 positions.  Outputs are device arrays of the precision's type
+ * (float for SYMX_F32, double for SYMX_F64), any of them NULL to skip:
+ *   elem_E:    n_elem
+ *   elem_grad: n_elem x 3k        (node-major)
+ *   elem_hess: n_elem x 3k x 3k   (row-major; projected if SYMX_PROJECT_PSD)
+ * flags: SYMX_EVAL_* bits select what is computed; SYMX_PROJECT_PSD. */
+symx_status symx_eval_derivatives(symx_mesh mesh, int32_t energy_index, const double* x_dev,
+                                  uint32_t flags, int32_t precision, void* elem_E,
+                                  void* elem_grad, void* elem_hess);
+
+/* Global evaluation and assembly at positions x_dev (device N x 3 float64):
+ *   energy_host: total energy (float64), if flags has SYMX_EVAL_E, else untouched
+ *   grad_dev:    device N x 3 float64 gradient, if flags has SYMX_EVAL_GRAD
+ *   H_out:       view of the mesh-owned BSR Hessian, if flags has SYMX_EVAL_HESS
+ * x_tilde_dev != NULL adds the inertia term m/(2 dt^2)|x - x_tilde|^2 per node
+ * (Eq. 2) with time step dt; NULL assembles the elastic energies only.
+ * Summation order per block and per gradient row is fixed (energy set, then
+ * element id), so results are bitwise reproducible run to run.
+ * precision: SYMX_F64 or SYMX_F32. */
+symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double* x_tilde_dev,
+                              double dt, uint32_t flags, int32_t precision, double* energy_host,
+                              double* grad_dev, symx_bsr_view* H_out);
+
+/* One implicit-Euler time step (Eq. 2-3): x_dev, v_dev (device N x 3 float64)
+ * hold x(t), v(t) on entry and x(t+dt_used), v(t+dt_used) on success; on
+ * failure they are left unchanged.  Newton from x(t); block-Jacobi PCG with
+ * forcing term min(0.5, sqrt(r_k / r_0)); Armijo backtracking (c = 1e-4,
+ * halving, at most 30); on line-search failure or too many Newton iterations
+ * the step restarts with dt/2 (at most max_halvings times); the mesh keeps the
+ * reduced dt and doubles it back after regrow_after successful steps.
+ * report may be NULL. */
+symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
+                             const symx_step_params* params, symx_step_report* report);
+
+const char* symx_status_string(symx_status status);
+const char* symx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYMX_H */

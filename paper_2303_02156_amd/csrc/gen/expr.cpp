@@ -1,0 +1,409 @@
+// Expression graph, hash-consing, differentiation and emitters (see expr.h).
+#include "expr.h"
+
+#include <cmath>
+#include <cstdio>
+#include <functional>
+#include <sstream>
+#include <stdexcept>
+
+namespace symx {
+
+Graph::Graph() { nodes_.reserve(1 << 16); }
+
+int Graph::make(Op op, int a, int b, int n, double c) {
+  char key[96];
+  std::snprintf(key, sizeof key, "%d|%d|%d|%d|%a", (int)op, a, b, n, c);
+  auto it = cse_.find(key);
+  if (it != cse_.end()) return it->second;
+  Node nd;
+  nd.op = op;
+  nd.a = a;
+  nd.b = b;
+  nd.n = n;
+  nd.c = c;
+  nd.dep = 0;
+  if (a >= 0) nd.dep |= nodes_[a].dep;
+  if (b >= 0) nd.dep |= nodes_[b].dep;
+  nodes_.push_back(nd);
+  int id = (int)nodes_.size() - 1;
+  cse_.emplace(key, id);
+  return id;
+}
+
+int Graph::sym(int slot) {
+  auto it = sym_of_slot_.find(slot);
+  if (it != sym_of_slot_.end()) return it->second;
+  int id = make(Op::Sym, -1, -1, slot, 0.0);
+  sym_of_slot_[slot] = id;
+  return id;
+}
+
+int Graph::cst(double v) {
+  if (v == 0.0) v = 0.0;  // fold -0 into +0
+  return make(Op::Const, -1, -1, 0, v);
+}
+
+void Graph::set_dof(int s) {
+  if (nodes_[s].op != Op::Sym) throw std::runtime_error("set_dof on non-symbol");
+  if (dof_bit_.count(s)) return;
+  int bit = (int)dof_bit_.size();
+  if (bit >= 64) throw std::runtime_error("more than 64 differentiation variables");
+  dof_bit_[s] = bit;
+  // only valid before the symbol is used by other nodes
+  nodes_[s].dep |= (uint64_t(1) << bit);
+}
+
+static bool isc(const Node& n) { return n.op == Op::Const; }
+
+int Graph::add(int a, int b) {
+  const Node &A = nodes_[a], &B = nodes_[b];
+  if (isc(A) && isc(B)) return cst(A.c + B.c);
+  if (is_const(a, 0.0)) return b;
+  if (is_const(b, 0.0)) return a;
+  if (B.op == Op::Neg) return sub(a, B.a);
+  if (A.op == Op::Neg) return sub(b, A.a);
+  if (a > b) std::swap(a, b);
+  return make(Op::Add, a, b, 0, 0.0);
+}
+
+int Graph::sub(int a, int b) {
+  const Node &A = nodes_[a], &B = nodes_[b];
+  if (isc(A) && isc(B)) return cst(A.c - B.c);
+  if (is_const(b, 0.0)) return a;
+  if (is_const(a, 0.0)) return neg(b);
+  if (a == b) return cst(0.0);
+  if (B.op == Op::Neg) return add(a, B.a);
+  return make(Op::Sub, a, b, 0, 0.0);
+}
+
+int Graph::mul(int a, int b) {
+  const Node &A = nodes_[a], &B = nodes_[b];
+  if (isc(A) && isc(B)) return cst(A.c * B.c);
+  if (is_const(a, 0.0) || is_const(b, 0.0)) return cst(0.0);
+  if (is_const(a, 1.0)) return b;
+  if (is_const(b, 1.0)) return a;
+  if (is_const(a, -1.0)) return neg(b);
+  if (is_const(b, -1.0)) return neg(a);
+  if (A.op == Op::Neg && B.op == Op::Neg) return mul(A.a, B.a);
+  if (A.op == Op::Neg) return neg(mul(A.a, b));
+  if (B.op == Op::Neg) return neg(mul(a, B.a));
+  if (a > b) std::swap(a, b);
+  return make(Op::Mul, a, b, 0, 0.0);
+}
+
+int Graph::div(int a, int b) {
+  const Node &A = nodes_[a], &B = nodes_[b];
+  if (is_const(b, 0.0)) throw std::runtime_error("symbolic division by zero");
+  if (isc(A) && isc(B)) return cst(A.c / B.c);
+  if (is_const(a, 0.0)) return cst(0.0);
+  if (is_const(b, 1.0)) return a;
+  if (a == b) return cst(1.0);
+  if (A.op == Op::Neg) return neg(div(A.a, b));
+  return make(Op::Div, a, b, 0, 0.0);
+}
+
+int Graph::neg(int a) {
+  const Node& A = nodes_[a];
+  if (isc(A)) return cst(-A.c);
+  if (A.op == Op::Neg) return A.a;
+  return make(Op::Neg, a, -1, 0, 0.0);
+}
+
+int Graph::log(int a) {
+  if (isc(nodes_[a])) return cst(std::log(nodes_[a].c));
+  return make(Op::Log, a, -1, 0, 0.0);
+}
+
+int Graph::sqrt(int a) {
+  if (isc(nodes_[a])) return cst(std::sqrt(nodes_[a].c));
+  return make(Op::Sqrt, a, -1, 0, 0.0);
+}
+
+int Graph::abs(int a) {
+  if (isc(nodes_[a])) return cst(std::fabs(nodes_[a].c));
+  return make(Op::Abs, a, -1, 0, 0.0);
+}
+
+int Graph::pown(int a, int n) {
+  if (n == 0) return cst(1.0);
+  if (n == 1) return a;
+  if (isc(nodes_[a])) return cst(std::pow(nodes_[a].c, n));
+  return make(Op::PowN, a, -1, n, 0.0);
+}
+
+int Graph::diff(int f, int s) {
+  auto bit_it = dof_bit_.find(s);
+  if (bit_it == dof_bit_.end()) throw std::runtime_error("diff w.r.t. a non-dof symbol");
+  uint64_t bit = uint64_t(1) << bit_it->second;
+  if (!(nodes_[f].dep & bit)) return cst(0.0);
+  uint64_t key = (uint64_t(f) << 6) | uint64_t(bit_it->second);
+  auto it = dcache_.find(key);
+  if (it != dcache_.end()) return it->second;
+  const Node nd = nodes_[f];  // copy: nodes_ may grow
+  int r;
+  switch (nd.op) {
+    case Op::Sym: r = cst(f == s ? 1.0 : 0.0); break;
+    case Op::Const: r = cst(0.0); break;
+    case Op::Add: r = add(diff(nd.a, s), diff(nd.b, s)); break;
+    case Op::Sub: r = sub(diff(nd.a, s), diff(nd.b, s)); break;
+    case Op::Mul: r = add(mul(diff(nd.a, s), nd.b), mul(nd.a, diff(nd.b, s))); break;
+    // Quotients are differentiated through the shared reciprocal node 1/b,
+    // so that all gradient and Hessian entries reuse one division.
+    case Op::Div:  // (a/b)' = (a' - (a/b) b') * (1/b)
+      r = mul(sub(diff(nd.a, s), mul(f, diff(nd.b, s))), div(cst(1.0), nd.b));
+      break;
+    case Op::Neg: r = neg(diff(nd.a, s)); break;
+    case Op::Log: r = mul(diff(nd.a, s), div(cst(1.0), nd.a)); break;
+    case Op::Sqrt: r = mul(diff(nd.a, s), mul(cst(0.5), div(cst(1.0), f))); break;
+    case Op::Abs: r = mul(diff(nd.a, s), mul(nd.a, div(cst(1.0), f))); break;
+    case Op::PowN: r = mul(mul(cst((double)nd.n), pown(nd.a, nd.n - 1)), diff(nd.a, s)); break;
+    default: throw std::runtime_error("diff: bad op");
+  }
+  dcache_[key] = r;
+  return r;
+}
+
+std::vector<int> Graph::substitute(const std::vector<int>& roots,
+                                   const std::map<int, double>& slot_values) {
+  std::unordered_map<int, int> memo;
+  std::function<int(int)> go = [&](int id) -> int {
+    auto it = memo.find(id);
+    if (it != memo.end()) return it->second;
+    const Node nd = nodes_[id];
+    int r;
+    switch (nd.op) {
+      case Op::Sym: {
+        auto sv = slot_values.find(nd.n);
+        r = (sv != slot_values.end()) ? cst(sv->second) : id;
+        break;
+      }
+      case Op::Const: r = id; break;
+      case Op::Add: r = add(go(nd.a), go(nd.b)); break;
+      case Op::Sub: r = sub(go(nd.a), go(nd.b)); break;
+      case Op::Mul: r = mul(go(nd.a), go(nd.b)); break;
+      case Op::Div: r = div(go(nd.a), go(nd.b)); break;
+      case Op::Neg: r = neg(go(nd.a)); break;
+      case Op::Log: r = log(go(nd.a)); break;
+      case Op::Sqrt: r = sqrt(go(nd.a)); break;
+      case Op::Abs: r = abs(go(nd.a)); break;
+      case Op::PowN: r = pown(go(nd.a), nd.n); break;
+      default: throw std::runtime_error("substitute: bad op");
+    }
+    memo[id] = r;
+    return r;
+  };
+  std::vector<int> out;
+  out.reserve(roots.size());
+  for (int r : roots) out.push_back(go(r));
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// value-type operators
+// ---------------------------------------------------------------------------
+static Graph* G(S a, S b) { return a.g ? a.g : b.g; }
+S operator+(S a, S b) { return S(G(a, b), G(a, b)->add(a.id, b.id)); }
+S operator-(S a, S b) { return S(G(a, b), G(a, b)->sub(a.id, b.id)); }
+S operator*(S a, S b) { return S(G(a, b), G(a, b)->mul(a.id, b.id)); }
+S operator/(S a, S b) { return S(G(a, b), G(a, b)->div(a.id, b.id)); }
+S operator-(S a) { return S(a.g, a.g->neg(a.id)); }
+S operator+(S a, double b) { return a + S(a.g, a.g->cst(b)); }
+S operator+(double a, S b) { return S(b.g, b.g->cst(a)) + b; }
+S operator-(S a, double b) { return a - S(a.g, a.g->cst(b)); }
+S operator-(double a, S b) { return S(b.g, b.g->cst(a)) - b; }
+S operator*(S a, double b) { return a * S(a.g, a.g->cst(b)); }
+S operator*(double a, S b) { return S(b.g, b.g->cst(a)) * b; }
+S operator/(S a, double b) { return a / S(a.g, a.g->cst(b)); }
+S log(S a) { return S(a.g, a.g->log(a.id)); }
+S sqrt(S a) { return S(a.g, a.g->sqrt(a.id)); }
+S abs(S a) { return S(a.g, a.g->abs(a.id)); }
+S pown(S a, int n) { return S(a.g, a.g->pown(a.id, n)); }
+
+Mat::Mat(int rr, int cc, Graph* g) : r(rr), c(cc), v(rr * cc, S(g, g->cst(0.0))) {}
+
+Mat matmul(const Mat& A, const Mat& B) {
+  Graph* g = A.v[0].g;
+  Mat C(A.r, B.c, g);
+  for (int i = 0; i < A.r; ++i)
+    for (int j = 0; j < B.c; ++j) {
+      S acc(g, g->cst(0.0));
+      for (int k = 0; k < A.c; ++k) acc = acc + A(i, k) * B(k, j);
+      C(i, j) = acc;
+    }
+  return C;
+}
+
+Mat transpose(const Mat& A) {
+  Mat T(A.c, A.r, A.v[0].g);
+  for (int i = 0; i < A.r; ++i)
+    for (int j = 0; j < A.c; ++j) T(j, i) = A(i, j);
+  return T;
+}
+
+S det2(const Mat& A) { return A(0, 0) * A(1, 1) - A(0, 1) * A(1, 0); }
+
+S det3(const Mat& A) {
+  return A(0, 0) * (A(1, 1) * A(2, 2) - A(1, 2) * A(2, 1)) -
+         A(0, 1) * (A(1, 0) * A(2, 2) - A(1, 2) * A(2, 0)) +
+         A(0, 2) * (A(1, 0) * A(2, 1) - A(1, 1) * A(2, 0));
+}
+
+Mat inv3(const Mat& A) {
+  Graph* g = A.v[0].g;
+  S d = det3(A);
+  S inv_d = S(g, g->cst(1.0)) / d;
+  Mat R(3, 3, g);
+  // adjugate: R(j,i) = cofactor(i,j)
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+      S cof = A(i1, j1) * A(i2, j2) - A(i1, j2) * A(i2, j1);
+      R(j, i) = cof * inv_d;
+    }
+  return R;
+}
+
+Mat inv2(const Mat& A) {
+  Graph* g = A.v[0].g;
+  S inv_d = S(g, g->cst(1.0)) / det2(A);
+  Mat R(2, 2, g);
+  R(0, 0) = A(1, 1) * inv_d;
+  R(0, 1) = -A(0, 1) * inv_d;
+  R(1, 0) = -A(1, 0) * inv_d;
+  R(1, 1) = A(0, 0) * inv_d;
+  return R;
+}
+
+S trace(const Mat& A) {
+  S t = A(0, 0);
+  for (int i = 1; i < A.r; ++i) t = t + A(i, i);
+  return t;
+}
+
+S frob2(const Mat& A) {
+  S t = A.v[0] * A.v[0];
+  for (size_t k = 1; k < A.v.size(); ++k) t = t + A.v[k] * A.v[k];
+  return t;
+}
+
+S dot(const Vec& a, const Vec& b) {
+  S t = a[0] * b[0];
+  for (size_t k = 1; k < a.size(); ++k) t = t + a[k] * b[k];
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// emitters
+// ---------------------------------------------------------------------------
+static std::vector<int> topo_order(const Graph& g, const std::vector<int>& roots) {
+  std::vector<int> order;
+  std::vector<char> state(g.size(), 0);
+  std::vector<std::pair<int, int>> stack;
+  for (int r : roots) {
+    if (state[r]) continue;
+    stack.push_back({r, 0});
+    while (!stack.empty()) {
+      auto& top = stack.back();
+      int id = top.first;
+      const Node& nd = g.node(id);
+      if (top.second == 0) {
+        state[id] = 1;
+        top.second = 1;
+        if (nd.a >= 0 && !state[nd.a]) { stack.push_back({nd.a, 0}); continue; }
+      }
+      if (top.second == 1) {
+        top.second = 2;
+        if (nd.b >= 0 && !state[nd.b]) { stack.push_back({nd.b, 0}); continue; }
+      }
+      stack.pop_back();
+      order.push_back(id);
+    }
+  }
+  return order;
+}
+
+static std::string literal(double c, bool hip) {
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "%.17g", c);
+  std::string s(buf);
+  if (s.find_first_of(".eEn") == std::string::npos) s += ".0";
+  return hip ? "T(" + s + ")" : s;
+}
+
+static std::string emit_body(const Graph& g, const Function& f, Census* cen, bool hip) {
+  Census local;
+  Census& C = cen ? *cen : local;
+  C = Census();
+  auto name = [&](int id) -> std::string {
+    const Node& nd = g.node(id);
+    if (nd.op == Op::Sym) return "in[" + std::to_string(nd.n) + "]";
+    if (nd.op == Op::Const) return literal(nd.c, hip);
+    return "v" + std::to_string(id);
+  };
+  const char* ty = hip ? "const T" : "const double";
+  std::ostringstream os;
+  for (int id : topo_order(g, f.outputs)) {
+    const Node& nd = g.node(id);
+    if (nd.op == Op::Sym || nd.op == Op::Const) continue;
+    os << "  " << ty << " v" << id << " = ";
+    switch (nd.op) {
+      case Op::Add: os << name(nd.a) << " + " << name(nd.b); C.add++; break;
+      case Op::Sub: os << name(nd.a) << " - " << name(nd.b); C.sub++; break;
+      case Op::Mul: os << name(nd.a) << " * " << name(nd.b); C.mul++; break;
+      case Op::Div: os << name(nd.a) << " / " << name(nd.b); C.div++; break;
+      case Op::Neg: os << "-" << name(nd.a); C.neg++; break;
+      case Op::Log: os << (hip ? "sx_log(" : "log(") << name(nd.a) << ")"; C.log++; break;
+      case Op::Sqrt: os << (hip ? "sx_sqrt(" : "sqrt(") << name(nd.a) << ")"; C.sqrt++; break;
+      case Op::Abs: os << (hip ? "sx_abs(" : "fabs(") << name(nd.a) << ")"; C.abs++; break;
+      case Op::PowN: {
+        C.pown++;
+        if (nd.n >= 2 && nd.n <= 4) {
+          std::string a = name(nd.a);
+          for (int k = 0; k < nd.n; ++k) os << (k ? " * " : "") << a;
+        } else {
+          os << (hip ? "sx_pown<" : "symx_pown(") << (hip ? std::to_string(nd.n) + ">(" : "")
+             << name(nd.a) << (hip ? ")" : ", " + std::to_string(nd.n) + ")");
+        }
+        break;
+      }
+      default: throw std::runtime_error("emit: bad op");
+    }
+    os << ";\n";
+  }
+  for (size_t k = 0; k < f.outputs.size(); ++k)
+    os << "  out[" << k << "] = " << name(f.outputs[k]) << ";\n";
+  return os.str();
+}
+
+static std::string census_comment(const Census& c, const Function& f) {
+  std::ostringstream os;
+  os << "  // inputs " << f.n_in << ", outputs " << f.outputs.size() << "; ops: add " << c.add
+     << ", sub " << c.sub << ", mul " << c.mul << ", div " << c.div << ", neg " << c.neg
+     << ", log " << c.log << ", sqrt " << c.sqrt << ", abs " << c.abs << ", pown " << c.pown
+     << ", total " << c.total() << "\n";
+  return os.str();
+}
+
+std::string emit_hip(const Graph& g, const Function& f, Census* census) {
+  Census c;
+  std::string body = emit_body(g, f, &c, true);
+  if (census) *census = c;
+  std::ostringstream os;
+  os << "template <typename T>\n__device__ __forceinline__ void " << f.name
+     << "(const T* __restrict__ in, T* __restrict__ out) {\n"
+     << census_comment(c, f) << body << "}\n\n";
+  return os.str();
+}
+
+std::string emit_c(const Graph& g, const Function& f, Census* census) {
+  Census c;
+  std::string body = emit_body(g, f, &c, false);
+  if (census) *census = c;
+  std::ostringstream os;
+  os << "void " << f.name << "(const double* in, double* out) {\n"
+     << census_comment(c, f) << body << "}\n\n";
+  return os.str();
+}
+
+}  // namespace symx

@@ -1,0 +1,227 @@
+// symx_gen: build-time generator of element functions.
+//
+// Each energy is written once for a single representative element with the
+// symbolic scalar type (Sec. 5.1-5.2: energies defined per element on fixed-size
+// local inputs, Eq. 5).  The generator differentiates it symbolically, removes
+// common subexpressions and emits straight-line code, one line per graph node
+// (Sec. 5.2, code generation), as
+//   * HIP device templates (float / double) for the library, and
+//   * plain C (double) for a test-only CPU library that checks the generator
+//     against the hand-derived FP64 oracle.
+//
+// Variants per energy (the paper's three evaluation levels, Sec. 5.2):
+//   NAME_E, NAME_Eg, NAME_EgH      energy / + gradient / + full Hessian, with the
+//                                  paper's input layout (e.g. 26 inputs for tet4)
+//   NAME_s_E, NAME_s_EgH           same with node 0 at the origin (x0 = X0 = 0):
+//                                  the library passes coordinates relative to
+//                                  node 0, so single precision keeps the digits
+//                                  of the element's edge vectors
+//   NAME_row0_g, NAME_row0_gH      gradient of node 0 and Hessian block row 0
+//                                  (node 0 at the origin); node a's row is
+//                                  obtained by relabelling node a as node 0
+//
+// Usage: symx_gen <output directory>
+#include <cstdio>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "expr.h"
+
+using namespace symx;
+
+namespace {
+
+struct EnergySpec {
+  std::string name;
+  int n_nodes;        // element nodes (3 coordinates each are the DoFs)
+  int n_in;           // total inputs
+  int rest_slot;      // first slot of node-0 rest coordinates, or -1
+  std::function<S(Graph&, const std::vector<S>&)> energy;
+};
+
+Mat cols_minus_first(Graph& g, const std::vector<S>& in, int base, int n_nodes) {
+  // columns p_a - p_0 for a = 1..n_nodes-1 of the 3D points in[base + 3a + i]
+  Mat M(3, n_nodes - 1, &g);
+  for (int a = 1; a < n_nodes; ++a)
+    for (int i = 0; i < 3; ++i) M(i, a - 1) = in[base + 3 * a + i] - in[base + i];
+  return M;
+}
+
+// Stable Neo-Hookean tet4 (App. B, Stable Neo-Hookean branch) with the Lame
+// re-parametrisation mu' = 4/3 mu, lambda' = lambda + 5/6 mu; E = V psi(F),
+// F = Ds Dm^-1, V = |det Dm| / 6 (Sec. 3.1).
+S snh_tet4(Graph& g, const std::vector<S>& in) {
+  Mat Ds = cols_minus_first(g, in, 0, 4);
+  Mat Dm = cols_minus_first(g, in, 12, 4);
+  S mu = in[24], lam = in[25];
+  S detDm = det3(Dm);
+  S V = abs(detDm) / 6.0;
+  Mat F = matmul(Ds, inv3(Dm));
+  S mu_ = mu * (4.0 / 3.0);
+  S lam_ = lam + mu * (5.0 / 6.0);
+  S Ic = frob2(F);
+  S J = det3(F);
+  S alpha = 1.0 + mu_ / lam_ - mu_ / (4.0 * lam_);
+  S psi = 0.5 * mu_ * (Ic - 3.0) + 0.5 * lam_ * pown(J - alpha, 2) - 0.5 * mu_ * log(Ic + 1.0);
+  return V * psi;
+}
+
+// StVK membrane triangle (App. B, Saint Venant-Kirchhoff branch, on the 3x2
+// deformation gradient of a triangle).  Written frame-free: with the rest
+// metric G = Dm^T Dm and the current metric C = Ds^T Ds of the two edge
+// vectors, F^T F in any orthonormal rest frame is similar to G^-1 C, so
+// tr(E) = (tr(G^-1 C) - 2)/2 and |E|^2 = tr((G^-1 C - I)^2)/4; the rest area
+// is sqrt(det G)/2 and the energy is thickness * area * psi.
+S stvk_tri3(Graph& g, const std::vector<S>& in) {
+  Mat Ds = cols_minus_first(g, in, 0, 3);
+  Mat Dm = cols_minus_first(g, in, 9, 3);
+  S mu = in[18], lam = in[19], h = in[20];
+  Mat Gm = matmul(transpose(Dm), Dm);
+  Mat Cm = matmul(transpose(Ds), Ds);
+  Mat M = matmul(inv2(Gm), Cm);
+  S trM = trace(M);
+  Mat D(2, 2, &g);
+  D(0, 0) = M(0, 0) - 1.0;
+  D(0, 1) = M(0, 1);
+  D(1, 0) = M(1, 0);
+  D(1, 1) = M(1, 1) - 1.0;
+  S trD2 = D(0, 0) * D(0, 0) + 2.0 * (D(0, 1) * D(1, 0)) + D(1, 1) * D(1, 1);
+  S trE = 0.5 * (trM - 2.0);
+  S psi = mu * (0.25 * trD2) + 0.5 * lam * (trE * trE);
+  S area = 0.5 * sqrt(det2(Gm));
+  return h * area * psi;
+}
+
+// Quadratic bending (Eq. 13, Bergou et al. 2006): E = k_b/2 x^T Q x with the
+// constant Q = c (K K^T) (x) I3; inputs are the per-node weights K_a and the
+// scale c = 3/(A0 + A1), precomputed from the rest hinge.
+S hinge4(Graph& g, const std::vector<S>& in) {
+  (void)g;
+  std::vector<S> s(3);
+  for (int i = 0; i < 3; ++i) {
+    S acc = in[12] * in[i];
+    for (int a = 1; a < 4; ++a) acc = acc + in[12 + a] * in[3 * a + i];
+    s[i] = acc;
+  }
+  S kb = in[17], c = in[16];
+  return 0.5 * kb * c * dot(s, s);
+}
+
+// Inertia of one node (Eq. 2 and the inertia energy of the paper's listing):
+// m / (2 dt^2) |x - x_tilde|^2.
+S inertia(Graph& g, const std::vector<S>& in) {
+  (void)g;
+  std::vector<S> d = {in[0] - in[3], in[1] - in[4], in[2] - in[5]};
+  S m = in[6], dt = in[7];
+  return m / (2.0 * (dt * dt)) * dot(d, d);
+}
+
+struct Generated {
+  std::string hip, c, meta;
+};
+
+void generate(const EnergySpec& spec, Generated& out) {
+  Graph g;
+  std::vector<S> in;
+  for (int k = 0; k < spec.n_in; ++k) in.push_back(S(&g, g.sym(k)));
+  int n_dof = 3 * spec.n_nodes;
+  for (int k = 0; k < n_dof; ++k) g.set_dof(in[k].id);
+  S E = spec.energy(g, in);
+  std::vector<int> grad(n_dof);
+  for (int k = 0; k < n_dof; ++k) grad[k] = g.diff(E.id, in[k].id);
+  std::vector<int> hess(n_dof * n_dof);
+  for (int k = 0; k < n_dof; ++k)
+    for (int l = k; l < n_dof; ++l) hess[k * n_dof + l] = hess[l * n_dof + k] = g.diff(grad[k], in[l].id);
+
+  std::vector<Function> fns;
+  auto add_fn = [&](const std::string& suffix, std::vector<int> outs) {
+    Function f;
+    f.name = spec.name + suffix;
+    f.n_in = spec.n_in;
+    f.outputs = std::move(outs);
+    fns.push_back(f);
+  };
+  std::vector<int> Eg = {E.id};
+  Eg.insert(Eg.end(), grad.begin(), grad.end());
+  std::vector<int> EgH = Eg;
+  EgH.insert(EgH.end(), hess.begin(), hess.end());
+  add_fn("_E", {E.id});
+  add_fn("_Eg", Eg);
+  add_fn("_EgH", EgH);
+
+  // node 0 at the origin
+  std::map<int, double> zero;
+  for (int i = 0; i < 3; ++i) {
+    zero[i] = 0.0;
+    if (spec.rest_slot >= 0) zero[spec.rest_slot + i] = 0.0;
+  }
+  add_fn("_s_E", g.substitute({E.id}, zero));
+  add_fn("_s_EgH", g.substitute(EgH, zero));
+  std::vector<int> row0_g(grad.begin(), grad.begin() + 3);
+  std::vector<int> row0_gH = row0_g;
+  for (int i = 0; i < 3; ++i)
+    for (int l = 0; l < n_dof; ++l) row0_gH.push_back(hess[i * n_dof + l]);
+  add_fn("_row0_g", g.substitute(row0_g, zero));
+  add_fn("_row0_gH", g.substitute(row0_gH, zero));
+
+  for (const Function& f : fns) {
+    Census ch, cc;
+    out.hip += emit_hip(g, f, &ch);
+    out.c += emit_c(g, f, &cc);
+    std::ostringstream m;
+    m << f.name << " " << f.n_in << " " << f.outputs.size() << " " << ch.add << " " << ch.sub << " "
+      << ch.mul << " " << ch.div << " " << ch.neg << " " << ch.log << " " << ch.sqrt << " " << ch.abs
+      << " " << ch.pown << " " << ch.total() << "\n";
+    out.meta += m.str();
+    std::printf("  %-24s in %3d out %4zu ops %6d\n", f.name.c_str(), f.n_in, f.outputs.size(),
+                ch.total());
+  }
+}
+
+bool write_file(const std::string& path, const std::string& text) {
+  std::ofstream f(path);
+  if (!f) return false;
+  f << text;
+  return bool(f);
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc != 2) {
+    std::fprintf(stderr, "usage: %s <output directory>\n", argv[0]);
+    return 2;
+  }
+  std::string dir = argv[1];
+  std::vector<EnergySpec> specs = {
+      {"snh_tet4", 4, 26, 12, snh_tet4},
+      {"stvk_tri3", 3, 21, 9, stvk_tri3},
+      {"hinge4", 4, 18, -1, hinge4},
+      {"inertia", 1, 8, -1, inertia},
+  };
+  Generated all;
+  all.hip =
+      "// Generated by symx_gen from the symbolic energy definitions; do not edit.\n"
+      "#pragma once\n#include \"symx_math.h\"\n\n";
+  all.c =
+      "/* Generated by symx_gen (test-only CPU variant); do not edit. */\n"
+      "#include <math.h>\n"
+      "static double symx_pown(double a, int n) { double r = 1.0; for (int k = 0; k < n; ++k) r *= a; "
+      "return r; }\n\n";
+  all.meta = "# name n_in n_out add sub mul div neg log sqrt abs pown total\n";
+  for (const auto& s : specs) {
+    std::printf("%s\n", s.name.c_str());
+    generate(s, all);
+  }
+  if (!write_file(dir + "/symx_generated.h", all.hip) ||
+      !write_file(dir + "/symx_generated_cpu.c", all.c) ||
+      !write_file(dir + "/symx_generated_meta.txt", all.meta)) {
+    std::fprintf(stderr, "symx_gen: cannot write to %s\n", dir.c_str());
+    return 1;
+  }
+  return 0;
+}

@@ -1,0 +1,259 @@
+// C-ABI of libsymx.so (declared in include/symx.h).  Thin wrappers: argument
+// validation, error reporting and dispatch to the mesh, kernel and Newton
+// code.  No C++ exception crosses the boundary.
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "symx_internal.h"
+
+struct symx_mesh_s {
+  symxi::Mesh* m;
+};
+
+namespace symxi {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+symx_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SYMX_OK;
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? SYMX_ERR_OUT_OF_MEMORY : SYMX_ERR_DEVICE;
+}
+
+symx_status mesh_create(const symx_mesh_desc* d, Mesh** out);
+void free_workspace(Mesh& m);
+symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
+                     bool want_H, bool project, int precision, bool dirichlet, double* g_out);
+symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E);
+symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P,
+                        symx_step_report* out);
+
+void mesh_free(Mesh* m) {
+  if (!m) return;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  else (void)hipDeviceSynchronize();
+  free_workspace(*m);
+  void* dev[] = {m->X, m->mass, m->fixed, m->row_ptr, m->col_idx, m->diag_pos, m->inc_ptr,
+                 m->inc_code, m->inc_slots, m->batch_row, m->vals32, m->vals64, m->elem_H,
+                 m->partials, m->scalars, m->counters, m->nonfinite};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  for (SetHost& s : m->sets) {
+    void* sp[] = {s.d_conn, s.d_prm64, s.d_prm32, s.d_inc_pos};
+    for (void* p : sp)
+      if (p) (void)hipFree(p);
+  }
+  if (m->pinned) (void)hipHostFree(m->pinned);
+  delete m;
+}
+
+}  // namespace symxi
+
+using namespace symxi;
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                   \
+  }                                                 \
+  catch (const std::bad_alloc&) {                   \
+    set_error("host allocation failed");            \
+    return SYMX_ERR_OUT_OF_MEMORY;                  \
+  }                                                 \
+  catch (const std::exception& ex) {                \
+    set_error(ex.what());                           \
+    return SYMX_ERR_DEVICE;                         \
+  }                                                 \
+  catch (...) {                                     \
+    set_error("unknown exception");                 \
+    return SYMX_ERR_DEVICE;                         \
+  }
+
+static bool valid_mesh(symx_mesh h) {
+  if (!h || !h->m) {
+    set_error("null mesh handle");
+    return false;
+  }
+  return true;
+}
+
+extern "C" {
+
+void symx_step_params_default(symx_step_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->dt = 0.01;
+  p->gravity[2] = -9.81;
+  p->newton_rtol = 1e-6;
+  p->max_newton = 100;
+  p->max_pcg = 500;
+  p->project = 0;
+  p->precision = SYMX_F64;
+  p->max_halvings = 8;
+  p->regrow_after = 3;
+  p->max_refine = 4;
+}
+
+symx_status symx_mesh_create(const symx_mesh_desc* desc, symx_mesh* out) {
+  GUARD_BEGIN
+  if (!out) {
+    set_error("null output handle");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  Mesh* m = nullptr;
+  symx_status st = mesh_create(desc, &m);
+  if (st != SYMX_OK) {
+    mesh_free(m);
+    return st;
+  }
+  symx_mesh h = new symx_mesh_s{m};
+  *out = h;
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_mesh_destroy(symx_mesh mesh) {
+  GUARD_BEGIN
+  if (!mesh) return SYMX_OK;
+  mesh_free(mesh->m);
+  delete mesh;
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_mesh_get_info(symx_mesh mesh, symx_mesh_info* info) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh) || !info) return SYMX_ERR_INVALID_ARG;
+  Mesh& m = *mesh->m;
+  std::memset(info, 0, sizeof *info);
+  info->n_nodes = m.N;
+  info->nnzb = m.nnzb;
+  info->n_incidences = m.n_inc;
+  info->n_batches = m.n_batch;
+  info->n_energies = (int32_t)m.sets.size();
+  for (size_t s = 0; s < m.sets.size(); ++s) info->n_elem[s] = m.sets[s].n_elem;
+  info->max_row_blocks = m.max_row_blocks;
+  info->total_mass = m.total_mass;
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_mesh_get_pattern(symx_mesh mesh, int32_t* row_ptr, int32_t* col_idx,
+                                  int32_t* scatter_map) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
+  Mesh& m = *mesh->m;
+  if (row_ptr) std::memcpy(row_ptr, m.h_row_ptr.data(), m.h_row_ptr.size() * sizeof(int32_t));
+  if (col_idx) std::memcpy(col_idx, m.h_col_idx.data(), m.h_col_idx.size() * sizeof(int32_t));
+  if (scatter_map)
+    std::memcpy(scatter_map, m.h_scatter.data(), m.h_scatter.size() * sizeof(int32_t));
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_mesh_get_masses(symx_mesh mesh, double* mass_host) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh) || !mass_host) return SYMX_ERR_INVALID_ARG;
+  Mesh& m = *mesh->m;
+  std::memcpy(mass_host, m.h_mass.data(), m.h_mass.size() * sizeof(double));
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_eval_derivatives(symx_mesh mesh, int32_t energy_index, const double* x_dev,
+                                  uint32_t flags, int32_t precision, void* elem_E,
+                                  void* elem_grad, void* elem_hess) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
+  Mesh& m = *mesh->m;
+  if (energy_index < 0 || energy_index >= (int)m.sets.size() || !x_dev ||
+      (precision != SYMX_F64 && precision != SYMX_F32)) {
+    set_error("invalid energy index, positions or precision");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  void* E = (flags & SYMX_EVAL_E) ? elem_E : nullptr;
+  void* g = (flags & SYMX_EVAL_GRAD) ? elem_grad : nullptr;
+  void* H = (flags & SYMX_EVAL_HESS) ? elem_hess : nullptr;
+  if ((flags & SYMX_PROJECT_PSD) && !H) {
+    set_error("SYMX_PROJECT_PSD needs SYMX_EVAL_HESS and a Hessian buffer");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  symx_status st = launch_elem_eval(m, energy_index, x_dev, (int)flags, precision, E, g, H);
+  if (st != SYMX_OK) return st;
+  if (flags & SYMX_PROJECT_PSD) {
+    const SetHost& s = m.sets[energy_index];
+    st = launch_project(m, precision, H, s.n_elem, 3 * s.k);
+    if (st != SYMX_OK) return st;
+  }
+  return hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize");
+  GUARD_END
+}
+
+symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double* x_tilde_dev,
+                              double dt, uint32_t flags, int32_t precision, double* energy_host,
+                              double* grad_dev, symx_bsr_view* H_out) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
+  Mesh& m = *mesh->m;
+  if (!x_dev || (precision != SYMX_F64 && precision != SYMX_F32) ||
+      (x_tilde_dev && !(dt > 0.0)) || ((flags & SYMX_EVAL_E) && !energy_host) ||
+      ((flags & SYMX_EVAL_GRAD) && !grad_dev) || ((flags & SYMX_EVAL_HESS) && !H_out)) {
+    set_error("invalid arguments to symx_assemble_bsr");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  const bool want_g = (flags & SYMX_EVAL_GRAD) != 0;
+  const bool want_H = (flags & SYMX_EVAL_HESS) != 0;
+  symx_status st = assemble(m, x_dev, x_tilde_dev, dt, want_g, want_H,
+                            (flags & SYMX_PROJECT_PSD) != 0, precision,
+                            (flags & SYMX_DIRICHLET) != 0, grad_dev);
+  if (st != SYMX_OK) return st;
+  if (flags & SYMX_EVAL_E) {
+    st = energy(m, x_dev, x_tilde_dev, dt, precision, energy_host);
+    if (st != SYMX_OK) return st;
+  }
+  if (want_H) {
+    H_out->n_block_rows = m.N;
+    H_out->nnzb = m.nnzb;
+    H_out->row_ptr = m.row_ptr;
+    H_out->col_idx = m.col_idx;
+    H_out->values = precision == SYMX_F64 ? (const void*)m.vals64 : (const void*)m.vals32;
+    H_out->precision = precision;
+  }
+  return hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize");
+  GUARD_END
+}
+
+symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
+                             const symx_step_params* params, symx_step_report* report) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
+  if (!x_dev || !v_dev || !params || !(params->dt > 0.0) || params->max_newton < 0 ||
+      params->max_pcg < 1 || params->precision < SYMX_F64 || params->precision > SYMX_F32_REFINED ||
+      params->max_halvings < 0 || !(params->newton_rtol >= 0.0)) {
+    set_error("invalid arguments to symx_newton_step");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  return newton_step(*mesh->m, x_dev, v_dev, *params, report);
+  GUARD_END
+}
+
+const char* symx_status_string(symx_status s) {
+  switch (s) {
+    case SYMX_OK: return "ok";
+    case SYMX_ERR_INVALID_ARG: return "invalid argument";
+    case SYMX_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SYMX_ERR_DEVICE: return "device error";
+    case SYMX_ERR_NONFINITE: return "non-finite value";
+    case SYMX_ERR_NOT_CONVERGED: return "not converged";
+    case SYMX_ERR_LINE_SEARCH: return "line search failed";
+    case SYMX_ERR_BUDGET: return "memory budget exceeded";
+  }
+  return "unknown status";
+}
+
+const char* symx_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// Internal data structures of libsymx (host side and kernel arguments).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "symx.h"
+
+namespace symxi {
+
+constexpr int kMaxSets = 4;
+constexpr int kRowWG = 256;         // lanes of a row-assembly workgroup
+constexpr int kMaxRowBlocks = 255;  // slots per row are stored as uint8
+constexpr int kRedWG = 256;         // reduction workgroup size
+constexpr int kPrm = 8;             // parameter slots per element (doubles)
+constexpr uint32_t kNoSlot = 0xFFu;
+
+// Parameter layout per element (kPrm doubles):
+//   SNH tet4:  mu, lambda (linear-elasticity Lame pair)
+//   StVK tri3: mu, lambda, thickness
+//   hinge4:    K0, K1, K2, K3, c = 3/(A0+A1), k_b
+struct SetDev {
+  int kind;
+  int k;                 // nodes per element
+  int64_t n_elem;
+  const int4* conn;      // n_elem (unused components = -1)
+  const double* prm64;   // n_elem * kPrm, or kPrm when uniform
+  const float* prm32;
+  int prm_stride;        // kPrm, or 0 when every element has the same parameters
+};
+
+struct SetsDev {
+  SetDev s[kMaxSets];
+  int n;
+};
+
+// Incidence code: element id (bits 0-27), local node a (28-29), set (30-31).
+__host__ __device__ inline uint32_t inc_make(int set, int a, int64_t e) {
+  return (uint32_t(set) << 30) | (uint32_t(a) << 28) | uint32_t(e);
+}
+__host__ __device__ inline int inc_set(uint32_t c) { return int(c >> 30); }
+__host__ __device__ inline int inc_local(uint32_t c) { return int((c >> 28) & 3u); }
+__host__ __device__ inline int inc_elem(uint32_t c) { return int(c & 0x0FFFFFFFu); }
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+struct SetHost {
+  int kind = 0;
+  int k = 0;
+  int64_t n_elem = 0;
+  std::vector<int32_t> conn;        // n_elem * k
+  std::vector<double> prm;          // n_elem * kPrm or kPrm
+  bool uniform = true;
+  // device
+  int4* d_conn = nullptr;
+  double* d_prm64 = nullptr;
+  float* d_prm32 = nullptr;
+  int* d_inc_pos = nullptr;         // n_elem * k: position of incidence (e, a)
+};
+
+struct Workspace;  // Newton / PCG buffers (symx_newton.cpp)
+
+struct Mesh {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t N = 0;
+  int64_t nnzb = 0;
+  int64_t n_inc = 0;
+  int n_batch = 0;
+  int max_row_blocks = 0;
+  double total_mass = 0.0;
+  std::vector<SetHost> sets;
+  std::vector<double> h_X, h_mass;
+  std::vector<uint8_t> h_fixed;
+  std::vector<int32_t> h_row_ptr, h_col_idx;
+  std::vector<int32_t> h_scatter;   // all sets concatenated
+
+  // device data
+  double* X = nullptr;              // N*3
+  double* mass = nullptr;           // N
+  uint8_t* fixed = nullptr;         // N
+  int* row_ptr = nullptr;           // N+1
+  int* col_idx = nullptr;           // nnzb
+  int* diag_pos = nullptr;          // N: index of block (i,i)
+  int* inc_ptr = nullptr;           // N+1
+  uint32_t* inc_code = nullptr;     // n_inc
+  uint32_t* inc_slots = nullptr;    // n_inc: 4 x uint8 slots (relabelled order)
+  int* batch_row = nullptr;         // n_batch+1
+  float* vals32 = nullptr;          // 9*nnzb, component-major
+  double* vals64 = nullptr;
+  // per-element scratch for the projected path (largest set)
+  void* elem_g = nullptr;
+  void* elem_H = nullptr;
+  size_t elem_bytes = 0;
+  // reductions
+  double* partials = nullptr;       // kMaxPartials
+  double* scalars = nullptr;        // small device scalars
+  unsigned* counters = nullptr;
+  double* pinned = nullptr;         // host pinned scalars
+  int* nonfinite = nullptr;         // device flag
+  Workspace* ws = nullptr;
+  // dt control
+  double dt_cur = 0.0, dt_nominal = 0.0;
+  int successes = 0;
+
+  SetsDev sets_dev() const;
+};
+
+constexpr int kMaxPartials = 1 << 16;
+
+// ---------------------------------------------------------------------------
+// kernel launchers (symx_kernels.hip)
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+symx_status hip_check(hipError_t e, const char* what);
+
+// Per-element E/g/H of one set into caller buffers (T = float | double).
+symx_status launch_elem_eval(Mesh& m, int set, const double* x, int want, int precision,
+                             void* E, void* g, void* H);
+// In-place nearest-PSD projection of n element Hessians (dim x dim each).
+symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim);
+// Row assembly: gradient (FP64, may be null) and/or Hessian (precision).
+// from_elem: read projected per-element buffers of each set instead of
+// recomputing (elem_g / elem_H pointers per set).
+struct ElemBuffers {
+  const void* g[kMaxSets];
+  const void* H[kMaxSets];
+};
+symx_status launch_row_assemble(Mesh& m, const double* x, const double* x_tilde, double dt,
+                                bool want_g, bool want_H, int precision, bool dirichlet,
+                                const ElemBuffers* from_elem, double* g_out);
+// Total energy (float64 sum of per-element energies in `precision`).
+symx_status launch_energy(Mesh& m, const double* x, const double* x_tilde, double dt,
+                          int precision, double* E_dev);
+
+// Vector / solver kernels (symx_kernels.hip)
+symx_status launch_x_tilde(Mesh& m, const double* x, const double* v, double dt, const double g[3],
+                           double* xt);
+symx_status launch_dot64(Mesh& m, const double* a, const double* b, int64_t n, double* out_dev);
+symx_status launch_axpy64(Mesh& m, double* y, const double* x, const double* alpha_dev,
+                          double alpha_host, int64_t n);  // y += alpha x
+symx_status launch_lincomb64(Mesh& m, double* out, const double* a, const double* b,
+                             double beta, int64_t n);     // out = a + beta b
+symx_status launch_velocity(Mesh& m, double* v, const double* x_new, const double* x_old,
+                            double inv_dt, int64_t n);
+symx_status launch_check_finite(Mesh& m, const double* a, int64_t n);
+
+// PCG buffers (device): block-Jacobi inverse (9N) and the vectors of the
+// iteration (3N each), float or double per the solve precision.
+struct PcgBuffers {
+  void* Dinv;
+  void* xs;
+  void* r;
+  void* z;
+  void* p;
+  void* q;
+};
+symx_status launch_diag_inverse(Mesh& m, int precision, void* Dinv);
+symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const double* b,
+                            double tol2, int max_iter);
+symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int n_iter);
+symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs);
+symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b, double* r);
+
+}  // namespace symxi

@@ -1,0 +1,1143 @@
+// HIP kernels for gfx950: element evaluation, PSD projection, deterministic
+// row assembly into 3x3 BSR, energies, and the vector kernels of the solver.
+//
+// Element kernels call the generated functions of symx_gen (symbolic
+// derivatives of the energies of App. B and Eq. 13).  Every reduction uses a
+// fixed order (per-workgroup trees plus a final pass by the last workgroup in
+// a fixed order), so all results are bitwise reproducible from run to run; no
+// floating-point atomics are used anywhere.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+#include "symx_generated.h"
+#include "symx_internal.h"
+
+namespace symxi {
+
+// ---------------------------------------------------------------------------
+// common helpers
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
+// XCD i % 8).  Remap so that each XCD processes one contiguous range of work
+// items: neighbouring rows share nodes, which then stay in one L2.
+__device__ __forceinline__ int xcd_remap(int i, int n) {
+  const int q = n >> 3, r = n & 7, x = i & 7, j = i >> 3;
+  return x * q + (x < r ? x : r) + j;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_prm(const T* p, int stride, int64_t e, int k) {
+  return p[(int64_t)stride * e + k];
+}
+
+template <typename T>
+__device__ __forceinline__ const T* prm_ptr(const SetDev& S);
+template <>
+__device__ __forceinline__ const float* prm_ptr<float>(const SetDev& S) { return S.prm32; }
+template <>
+__device__ __forceinline__ const double* prm_ptr<double>(const SetDev& S) { return S.prm64; }
+
+// Deterministic block sum of one double per thread (blockDim = 256).
+__device__ double block_sum_256(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double load_coherent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns true in exactly one workgroup: the last one to finish.  The caller
+// has written its partial result before calling.  The counter is reset by the
+// last workgroup so the next launch can reuse it.
+__device__ bool last_block(unsigned* counter) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == gridDim.x - 1);
+    if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return last != 0;
+}
+
+// Sum partials[0..n) in a fixed order (called by one full workgroup of 256).
+__device__ double sum_partials(const double* partials, int n, double* sh) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += load_coherent(partials + i);
+  return block_sum_256(acc, sh);
+}
+
+// ---------------------------------------------------------------------------
+// element gather: node ids in relabelled order (node a first, then the other
+// nodes in ascending local order), positions relative to node a
+// ---------------------------------------------------------------------------
+struct Relabel {
+  int n[4];    // global node ids
+  int loc[4];  // local indices
+};
+
+__device__ __forceinline__ Relabel relabel(int4 c, int a) {
+  Relabel r;
+  r.n[0] = a == 0 ? c.x : a == 1 ? c.y : a == 2 ? c.z : c.w;
+  r.n[1] = a == 0 ? c.y : c.x;
+  r.n[2] = a <= 1 ? c.z : c.y;
+  r.n[3] = a <= 2 ? c.w : c.z;
+  r.loc[0] = a;
+  r.loc[1] = a == 0 ? 1 : 0;
+  r.loc[2] = a <= 1 ? 2 : 1;
+  r.loc[3] = a <= 2 ? 3 : 2;
+  return r;
+}
+
+__device__ __forceinline__ Relabel identity_order(int4 c) {
+  Relabel r;
+  r.n[0] = c.x; r.n[1] = c.y; r.n[2] = c.z; r.n[3] = c.w;
+  r.loc[0] = 0; r.loc[1] = 1; r.loc[2] = 2; r.loc[3] = 3;
+  return r;
+}
+
+// Fill the generated function's inputs for element `e` of set S with nodes in
+// order R (node R.n[0] moved to the origin; rest positions likewise).  K is the
+// node count of the element, so every index into `in` is a compile-time
+// constant and the array stays in registers.
+template <typename T, int K>
+__device__ __forceinline__ void fill_solid(const SetDev& S, int64_t e, const Relabel& R,
+                                           const double* __restrict__ x,
+                                           const double* __restrict__ X, T* in) {
+  constexpr int rb = 3 * K;  // first rest slot
+  const double* xo = x + 3 * (int64_t)R.n[0];
+  const double* Xo = X + 3 * (int64_t)R.n[0];
+  const double x0 = xo[0], x1 = xo[1], x2 = xo[2];
+  const double X0 = Xo[0], X1 = Xo[1], X2 = Xo[2];
+  in[0] = in[1] = in[2] = T(0);
+  in[rb + 0] = in[rb + 1] = in[rb + 2] = T(0);
+#pragma unroll
+  for (int b = 1; b < K; ++b) {
+    const double* xb = x + 3 * (int64_t)R.n[b];
+    const double* Xb = X + 3 * (int64_t)R.n[b];
+    in[3 * b + 0] = T(xb[0] - x0);
+    in[3 * b + 1] = T(xb[1] - x1);
+    in[3 * b + 2] = T(xb[2] - x2);
+    in[rb + 3 * b + 0] = T(Xb[0] - X0);
+    in[rb + 3 * b + 1] = T(Xb[1] - X1);
+    in[rb + 3 * b + 2] = T(Xb[2] - X2);
+  }
+  const T* P = prm_ptr<T>(S);
+  const int st = S.prm_stride;
+  in[2 * rb + 0] = ld_prm(P, st, e, 0);
+  in[2 * rb + 1] = ld_prm(P, st, e, 1);
+  if (K == 3) in[2 * rb + 2] = ld_prm(P, st, e, 2);
+}
+
+template <typename T>
+__device__ __forceinline__ void fill_hinge(const SetDev& S, int64_t e, const Relabel& R,
+                                           const double* __restrict__ x, T* in) {
+  const double* xo = x + 3 * (int64_t)R.n[0];
+  const double x0 = xo[0], x1 = xo[1], x2 = xo[2];
+  in[0] = in[1] = in[2] = T(0);
+#pragma unroll
+  for (int b = 1; b < 4; ++b) {
+    const double* xb = x + 3 * (int64_t)R.n[b];
+    in[3 * b + 0] = T(xb[0] - x0);
+    in[3 * b + 1] = T(xb[1] - x1);
+    in[3 * b + 2] = T(xb[2] - x2);
+  }
+  const T* P = prm_ptr<T>(S);
+  const int st = S.prm_stride;
+  const T K0 = ld_prm(P, st, e, 0), K1 = ld_prm(P, st, e, 1);
+  const T K2 = ld_prm(P, st, e, 2), K3 = ld_prm(P, st, e, 3);
+  const int a = R.loc[0];
+  // weights follow the relabelled node order
+  in[12] = a == 0 ? K0 : a == 1 ? K1 : a == 2 ? K2 : K3;
+  in[13] = a == 0 ? K1 : K0;
+  in[14] = a <= 1 ? K2 : K1;
+  in[15] = a <= 2 ? K3 : K2;
+  in[16] = ld_prm(P, st, e, 4);
+  in[17] = ld_prm(P, st, e, 5);
+}
+
+// ---------------------------------------------------------------------------
+// element-wise energy (line-search level) -> partial sums
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy_set(SetDev S, const double* __restrict__ x,
+                                                    const double* __restrict__ X,
+                                                    double* __restrict__ partials,
+                                                    int* __restrict__ nonfinite) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < S.n_elem;
+       e += (int64_t)gridDim.x * 256) {
+    const Relabel R = identity_order(S.conn[e]);
+    T in[26];
+    T out[1];
+    if (S.kind == SYMX_SNH_TET4) {
+      fill_solid<T, 4>(S, e, R, x, X, in);
+      snh_tet4_s_E<T>(in, out);
+    } else if (S.kind == SYMX_STVK_TRI3) {
+      fill_solid<T, 3>(S, e, R, x, X, in);
+      stvk_tri3_s_E<T>(in, out);
+    } else {
+      fill_hinge<T>(S, e, R, x, in);
+      hinge4_s_E<T>(in, out);
+    }
+    acc += double(out[0]);
+  }
+  double s = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s;
+    if (!isfinite(s)) *nonfinite = 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_energy_inertia(int64_t N, const double* __restrict__ x,
+                                                        const double* __restrict__ xt,
+                                                        const double* __restrict__ mass, double dt,
+                                                        double* __restrict__ partials,
+                                                        int* __restrict__ nonfinite) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    double in[8] = {x[3 * i], x[3 * i + 1], x[3 * i + 2], xt[3 * i], xt[3 * i + 1], xt[3 * i + 2],
+                    mass[i], dt};
+    double out[1];
+    inertia_E<double>(in, out);
+    acc += out[0];
+  }
+  double s = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s;
+    if (!isfinite(s)) *nonfinite = 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_to_scalar(const double* __restrict__ partials, int n,
+                                                          double* __restrict__ out) {
+  __shared__ double sh[256];
+  double s = sum_partials(partials, n, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// per-element E / gradient / Hessian (low-level element interface)
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+__global__ __launch_bounds__(128) void k_elem_eval(SetDev S, const double* __restrict__ x,
+                                                   const double* __restrict__ X, T* __restrict__ Eo,
+                                                   T* __restrict__ go, T* __restrict__ Ho) {
+  constexpr int K = KIND == SYMX_STVK_TRI3 ? 3 : 4;
+  constexpr int D = 3 * K;
+  for (int64_t e = (int64_t)blockIdx.x * 128 + threadIdx.x; e < S.n_elem;
+       e += (int64_t)gridDim.x * 128) {
+    const Relabel R = identity_order(S.conn[e]);
+    T in[26];
+    T out[1 + D + D * D];
+    if (KIND == SYMX_SNH_TET4) {
+      fill_solid<T, 4>(S, e, R, x, X, in);
+      snh_tet4_s_EgH<T>(in, out);
+    } else if (KIND == SYMX_STVK_TRI3) {
+      fill_solid<T, 3>(S, e, R, x, X, in);
+      stvk_tri3_s_EgH<T>(in, out);
+    } else {
+      fill_hinge<T>(S, e, R, x, in);
+      hinge4_s_EgH<T>(in, out);
+    }
+    if (Eo) Eo[e] = out[0];
+    if (go) {
+#pragma unroll
+      for (int v = 0; v < D; ++v) go[e * D + v] = out[1 + v];
+    }
+    if (Ho) {
+#pragma unroll
+      for (int v = 0; v < D * D; ++v) Ho[e * D * D + v] = out[1 + D + v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// nearest-PSD projection of element Hessians: cyclic Jacobi in round-robin
+// (parallel) order, one 64-lane workgroup per element, then
+// H <- H - sum over negative eigenvalues of lambda v v^T.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_project_psd(T* __restrict__ H, int64_t n, int dim,
+                                                    int max_sweeps, double tol) {
+  __shared__ T A[2][144];
+  __shared__ T V[2][144];
+  __shared__ T H0[144];
+  __shared__ T ca[12], cb[12];
+  __shared__ int partner[12];
+  __shared__ double red[64];
+  __shared__ int any_neg;
+  const int t = threadIdx.x;
+  const int np = dim + (dim & 1);  // even size for the round-robin schedule
+  const int nn = np * np;
+  for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
+    T* He = H + e * dim * dim;
+    for (int idx = t; idx < nn; idx += 64) {
+      int i = idx / np, j = idx % np;
+      T v = (i < dim && j < dim) ? He[i * dim + j] : T(0);
+      A[0][idx] = v;
+      H0[idx] = v;
+      V[0][idx] = (i == j) ? T(1) : T(0);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      // convergence test on the current matrix
+      double off = 0.0, tot = 0.0;
+      for (int idx = t; idx < nn; idx += 64) {
+        double v = double(A[cur][idx]);
+        tot += v * v;
+        if (idx / np != idx % np) off += v * v;
+      }
+      red[t] = off;
+      __syncthreads();
+      for (int s = 32; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+      }
+      double off_sum = red[0];
+      __syncthreads();
+      red[t] = tot;
+      __syncthreads();
+      for (int s = 32; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+      }
+      double tot_sum = red[0];
+      __syncthreads();
+      if (off_sum <= tol * tol * tot_sum) break;
+      for (int round = 0; round < np - 1; ++round) {
+        if (t < np / 2) {
+          int p, q;
+          if (t == 0) {
+            p = np - 1;
+            q = round;
+          } else {
+            p = (round + t) % (np - 1);
+            q = (round - t + (np - 1)) % (np - 1);
+          }
+          if (p > q) { int tmp = p; p = q; q = tmp; }
+          T apq = A[cur][p * np + q];
+          T app = A[cur][p * np + p];
+          T aqq = A[cur][q * np + q];
+          T c = T(1), s = T(0);
+          if (apq != T(0)) {
+            T tau = (aqq - app) / (T(2) * apq);
+            T tt = (tau >= T(0) ? T(1) : T(-1)) / (fabs(tau) + sqrt(T(1) + tau * tau));
+            c = T(1) / sqrt(T(1) + tt * tt);
+            s = tt * c;
+          }
+          ca[p] = c; cb[p] = -s; partner[p] = q;
+          ca[q] = c; cb[q] = s; partner[q] = p;
+        }
+        __syncthreads();
+        const int nx = cur ^ 1;
+        for (int idx = t; idx < nn; idx += 64) {
+          int i = idx / np, j = idx % np;
+          int pi = partner[i], pj = partner[j];
+          T ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
+          A[nx][idx] = ai * aj * A[cur][i * np + j] + ai * bj * A[cur][i * np + pj] +
+                       bi * aj * A[cur][pi * np + j] + bi * bj * A[cur][pi * np + pj];
+          V[nx][idx] = aj * V[cur][i * np + j] + bj * V[cur][i * np + pj];
+        }
+        __syncthreads();
+        cur = nx;
+      }
+    }
+    if (t == 0) {
+      int neg = 0;
+      for (int i = 0; i < dim; ++i) neg |= (A[cur][i * np + i] < T(0));
+      any_neg = neg;
+    }
+    __syncthreads();
+    if (any_neg) {
+      for (int idx = t; idx < dim * dim; idx += 64) {
+        int i = idx / dim, j = idx % dim;
+        T acc = H0[i * np + j];
+        for (int kk = 0; kk < dim; ++kk) {
+          T lam = A[cur][kk * np + kk];
+          if (lam < T(0)) acc -= lam * V[cur][i * np + kk] * V[cur][j * np + kk];
+        }
+        He[idx] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// row assembly: one workgroup per batch of consecutive block rows
+// ---------------------------------------------------------------------------
+template <typename T>
+struct RowArgs {
+  SetsDev sets;
+  const double* x;
+  const double* X;
+  const double* xt;      // x_tilde or null (no inertia)
+  const double* mass;
+  double inv_dt2;
+  const uint8_t* fixed;  // null: no Dirichlet treatment
+  const int* batch_row;
+  const int* row_ptr;
+  const int* col_idx;
+  const int* inc_ptr;
+  const uint32_t* inc_code;
+  const uint32_t* inc_slots;
+  int64_t nnzb;
+  T* vals;               // component-major 9 x nnzb
+  double* g;             // N x 3
+  const void* elem_g[kMaxSets];  // projected path: per-element gradients
+  const void* elem_H[kMaxSets];  // and Hessians
+  int* nonfinite;
+};
+
+// Contribution of one incidence: out[0..2] gradient of node a, out[3 + 12 i +
+// 3 b + k] Hessian entry (a_i, node b of the relabelled order, coord k).
+template <typename T, bool FROM_ELEM, bool WANT_H>
+__device__ __forceinline__ void incidence_row(const RowArgs<T>& A, uint32_t code, T* out) {
+  const int si = inc_set(code);
+  const int a = inc_local(code);
+  const int64_t e = inc_elem(code);
+  const SetDev& S = A.sets.s[si];
+  const Relabel R = relabel(S.conn[e], a);
+  if (FROM_ELEM) {
+    const int D = 3 * S.k;
+    const T* ge = (const T*)A.elem_g[si] + e * D;
+    const T* He = (const T*)A.elem_H[si] + e * D * D;
+    out[0] = ge[3 * a];
+    out[1] = ge[3 * a + 1];
+    out[2] = ge[3 * a + 2];
+    if (WANT_H) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk)
+            out[3 + 12 * i + 3 * b + kk] =
+                b < S.k ? He[(3 * a + i) * D + 3 * R.loc[b] + kk] : T(0);
+    }
+    return;
+  }
+  T in[26];
+  if (S.kind == SYMX_SNH_TET4) {
+    fill_solid<T, 4>(S, e, R, A.x, A.X, in);
+    if (WANT_H)
+      snh_tet4_row0_gH<T>(in, out);
+    else
+      snh_tet4_row0_g<T>(in, out);
+  } else if (S.kind == SYMX_HINGE4) {
+    fill_hinge<T>(S, e, R, A.x, in);
+    if (WANT_H)
+      hinge4_row0_gH<T>(in, out);
+    else
+      hinge4_row0_g<T>(in, out);
+  } else {
+    fill_solid<T, 3>(S, e, R, A.x, A.X, in);
+    if (WANT_H) {
+      T o[30];
+      stvk_tri3_row0_gH<T>(in, o);
+      out[0] = o[0];
+      out[1] = o[1];
+      out[2] = o[2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int v = 0; v < 9; ++v) out[3 + 12 * i + v] = o[3 + 9 * i + v];
+#pragma unroll
+        for (int v = 9; v < 12; ++v) out[3 + 12 * i + v] = T(0);
+      }
+    } else {
+      stvk_tri3_row0_g<T>(in, out);
+    }
+  }
+}
+
+template <typename T, bool FROM_ELEM, bool WANT_G, bool WANT_H>
+__global__ __launch_bounds__(kRowWG) void k_row_assemble(RowArgs<T> A) {
+  constexpr int NV = WANT_H ? 39 : 3;
+  __shared__ T st[NV][kRowWG];
+  __shared__ uint32_t sl[kRowWG];
+  __shared__ int s_blk[kRowWG + 1];
+  __shared__ int s_inc[kRowWG + 1];
+  const int t = threadIdx.x;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int r0 = A.batch_row[b], r1 = A.batch_row[b + 1];
+  const int nrows = r1 - r0;
+  const int q0 = A.inc_ptr[r0];
+  const int p0 = A.row_ptr[r0];
+  for (int r = t; r <= nrows; r += kRowWG) {
+    s_blk[r] = A.row_ptr[r0 + r] - p0;
+    s_inc[r] = A.inc_ptr[r0 + r] - q0;
+  }
+  __syncthreads();
+  const int nq = s_inc[nrows];
+  const int np = s_blk[nrows];
+  if (t < nq) {
+    const uint32_t code = A.inc_code[q0 + t];
+    if (WANT_H) sl[t] = A.inc_slots[q0 + t];
+    T out[39];
+    incidence_row<T, FROM_ELEM, WANT_H>(A, code, out);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) st[v][t] = out[v];
+  }
+  __syncthreads();
+  if (WANT_H && t < np) {
+    int r = 0;
+    while (s_blk[r + 1] <= t) ++r;
+    const int slot = t - s_blk[r];
+    T acc[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] = T(0);
+    for (int q = s_inc[r]; q < s_inc[r + 1]; ++q) {
+      const uint32_t w = sl[q];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        if (((w >> (8 * bb)) & 0xFFu) == (uint32_t)slot) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += st[3 + 12 * i + 3 * bb + kk][q];
+        }
+      }
+    }
+    const int row = r0 + r;
+    const int p = p0 + t;
+    const int col = A.col_idx[p];
+    if (A.xt && col == row) {
+      const T w = T(A.mass[row] * A.inv_dt2);
+      acc[0] += w;
+      acc[4] += w;
+      acc[8] += w;
+    }
+    if (A.fixed && (A.fixed[row] | A.fixed[col])) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] = (col == row && (c % 4) == 0) ? T(1) : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A.vals[(int64_t)c * A.nnzb + p] = acc[c];
+  }
+  if (WANT_G && t < nrows) {
+    const int row = r0 + t;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int q = s_inc[t]; q < s_inc[t + 1]; ++q) {
+      g0 += double(st[0][q]);
+      g1 += double(st[1][q]);
+      g2 += double(st[2][q]);
+    }
+    if (A.xt) {
+      const double w = A.mass[row] * A.inv_dt2;
+      g0 += w * (A.x[3 * row + 0] - A.xt[3 * row + 0]);
+      g1 += w * (A.x[3 * row + 1] - A.xt[3 * row + 1]);
+      g2 += w * (A.x[3 * row + 2] - A.xt[3 * row + 2]);
+    }
+    if (A.fixed && A.fixed[row]) g0 = g1 = g2 = 0.0;
+    if (!(isfinite(g0) && isfinite(g1) && isfinite(g2))) *A.nonfinite = 1;
+    A.g[3 * row + 0] = g0;
+    A.g[3 * row + 1] = g1;
+    A.g[3 * row + 2] = g2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// solver kernels
+// ---------------------------------------------------------------------------
+
+// 3x3 inverse of every diagonal block (block-Jacobi preconditioner).
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_inverse(int64_t N, int64_t nnzb,
+                                                      const int* __restrict__ diag_pos,
+                                                      const T* __restrict__ vals,
+                                                      T* __restrict__ Dinv) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    const int64_t p = diag_pos[i];
+    double a[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) a[c] = double(vals[c * nnzb + p]);
+    double c00 = a[4] * a[8] - a[5] * a[7];
+    double c01 = a[5] * a[6] - a[3] * a[8];
+    double c02 = a[3] * a[7] - a[4] * a[6];
+    double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    double r[9];
+    if (det != 0.0 && isfinite(det)) {
+      double id = 1.0 / det;
+      r[0] = c00 * id;
+      r[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+      r[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+      r[3] = c01 * id;
+      r[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+      r[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+      r[6] = c02 * id;
+      r[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+      r[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) r[c] = (c % 4 == 0) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Dinv[9 * i + c] = T(r[c]);
+  }
+}
+
+// y = A x (BSR, 16 lanes per block row, lane l takes blocks l, l+16, ...)
+template <typename TA, typename TX, typename TY>
+__device__ __forceinline__ void spmv_row(int row, int lane, const int* __restrict__ row_ptr,
+                                         const int* __restrict__ col, const TA* __restrict__ vals,
+                                         int64_t nnzb, const TX* __restrict__ x, TY* acc) {
+  acc[0] = acc[1] = acc[2] = TY(0);
+  const int pe = row_ptr[row + 1];
+  for (int p = row_ptr[row] + lane; p < pe; p += 16) {
+    const int j = col[p];
+    const TY x0 = TY(x[3 * j]), x1 = TY(x[3 * j + 1]), x2 = TY(x[3 * j + 2]);
+    acc[0] += TY(vals[p]) * x0 + TY(vals[nnzb + p]) * x1 + TY(vals[2 * nnzb + p]) * x2;
+    acc[1] += TY(vals[3 * nnzb + p]) * x0 + TY(vals[4 * nnzb + p]) * x1 + TY(vals[5 * nnzb + p]) * x2;
+    acc[2] += TY(vals[6 * nnzb + p]) * x0 + TY(vals[7 * nnzb + p]) * x1 + TY(vals[8 * nnzb + p]) * x2;
+  }
+#pragma unroll
+  for (int m = 8; m > 0; m >>= 1) {
+    acc[0] += __shfl_xor(acc[0], m, 16);
+    acc[1] += __shfl_xor(acc[1], m, 16);
+    acc[2] += __shfl_xor(acc[2], m, 16);
+  }
+}
+
+// r = b - A x  (float64 residual of the Newton system, A promoted)
+template <typename TA>
+__global__ __launch_bounds__(256) void k_residual64(int64_t N, const int* __restrict__ row_ptr,
+                                                    const int* __restrict__ col,
+                                                    const TA* __restrict__ vals, int64_t nnzb,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ r) {
+  const int lane = threadIdx.x & 15;
+  for (int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4; row < N;
+       row += ((int64_t)gridDim.x * 256) >> 4) {
+    double acc[3];
+    spmv_row<TA, double, double>((int)row, lane, row_ptr, col, vals, nnzb, x, acc);
+    if (lane == 0) {
+      r[3 * row + 0] = b[3 * row + 0] - acc[0];
+      r[3 * row + 1] = b[3 * row + 1] - acc[1];
+      r[3 * row + 2] = b[3 * row + 2] - acc[2];
+    }
+  }
+}
+
+// PCG scalars (device array of doubles) and flags
+enum { S_RZ = 0, S_RZ_OLD, S_PQ, S_RR, S_BB, S_ALPHA, S_BETA, S_TOL2, S_DONE, S_ITERS, S_MAXIT,
+       S_NSCALARS };
+// counters: 0 init, 1 spmv, 2 update, 3 dot, 4 energy
+
+// r = b, z = M^-1 r, x = p = q = 0; rz, rr, bb
+template <typename T, typename TB>
+__global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restrict__ b,
+                                                  const T* __restrict__ Dinv, T* __restrict__ xs,
+                                                  T* __restrict__ r, T* __restrict__ z,
+                                                  T* __restrict__ p, T* __restrict__ q,
+                                                  double* __restrict__ partials,
+                                                  double* __restrict__ S, unsigned* counter,
+                                                  double tol2, int max_iter) {
+  __shared__ double sh[256];
+  const int G = gridDim.x;
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)G * 256) {
+    T rv[3], zv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      rv[c] = T(b[3 * i + c]);
+      r[3 * i + c] = rv[c];
+      xs[3 * i + c] = T(0);
+      p[3 * i + c] = T(0);
+      q[3 * i + c] = T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      zv[c] = Dinv[9 * i + 3 * c] * rv[0] + Dinv[9 * i + 3 * c + 1] * rv[1] + Dinv[9 * i + 3 * c + 2] * rv[2];
+      z[3 * i + c] = zv[c];
+      rz += double(rv[c]) * double(zv[c]);
+      rr += double(rv[c]) * double(rv[c]);
+      double bc = double(b[3 * i + c]);
+      bb += bc * bc;
+    }
+  }
+  double s0 = block_sum_256(rz, sh);
+  double s1 = block_sum_256(rr, sh);
+  double s2 = block_sum_256(bb, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s0;
+    partials[G + blockIdx.x] = s1;
+    partials[2 * G + blockIdx.x] = s2;
+  }
+  if (last_block(counter)) {
+    double a0 = sum_partials(partials, G, sh);
+    double a1 = sum_partials(partials + G, G, sh);
+    double a2 = sum_partials(partials + 2 * G, G, sh);
+    if (threadIdx.x == 0) {
+      S[S_RZ] = a0;
+      S[S_RR] = a1;
+      S[S_BB] = a2;
+      S[S_BETA] = 0.0;
+      S[S_TOL2] = tol2;
+      S[S_ITERS] = 0.0;
+      S[S_MAXIT] = double(max_iter);
+      S[S_DONE] = (a2 == 0.0 || a1 <= tol2 * a2) ? 1.0 : 0.0;
+    }
+  }
+}
+
+// w = A z; p = z + beta p; q = w + beta q; partial p.q -> alpha = rz / pq
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_spmv(int64_t N, const int* __restrict__ row_ptr,
+                                                  const int* __restrict__ col,
+                                                  const T* __restrict__ vals, int64_t nnzb,
+                                                  const T* __restrict__ z, T* __restrict__ p,
+                                                  T* __restrict__ q, double* __restrict__ partials,
+                                                  double* __restrict__ S, unsigned* counter) {
+  if (S[S_DONE] != 0.0) return;
+  __shared__ double sh[256];
+  const int G = gridDim.x;
+  const T beta = T(S[S_BETA]);
+  const int lane = threadIdx.x & 15;
+  double pq = 0.0;
+  for (int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4; row < N;
+       row += ((int64_t)G * 256) >> 4) {
+    T acc[3];
+    spmv_row<T, T, T>((int)row, lane, row_ptr, col, vals, nnzb, z, acc);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T pn = z[3 * row + c] + beta * p[3 * row + c];
+        const T qn = acc[c] + beta * q[3 * row + c];
+        p[3 * row + c] = pn;
+        q[3 * row + c] = qn;
+        pq += double(pn) * double(qn);
+      }
+    }
+  }
+  double s = block_sum_256(pq, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (last_block(counter)) {
+    double tot = sum_partials(partials, G, sh);
+    if (threadIdx.x == 0) {
+      S[S_PQ] = tot;
+      if (!(tot > 0.0)) {
+        S[S_ALPHA] = 0.0;
+        S[S_DONE] = 2.0;  // breakdown: direction of non-positive curvature
+      } else {
+        S[S_ALPHA] = S[S_RZ] / tot;
+      }
+    }
+  }
+}
+
+// x += alpha p; r -= alpha q; z = M^-1 r; rz, rr -> beta, convergence
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_update(int64_t N, const T* __restrict__ Dinv,
+                                                    T* __restrict__ xs, T* __restrict__ r,
+                                                    T* __restrict__ z, const T* __restrict__ p,
+                                                    const T* __restrict__ q,
+                                                    double* __restrict__ partials,
+                                                    double* __restrict__ S, unsigned* counter) {
+  if (S[S_DONE] != 0.0) return;
+  __shared__ double sh[256];
+  const int G = gridDim.x;
+  const T alpha = T(S[S_ALPHA]);
+  double rz = 0.0, rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)G * 256) {
+    T rv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xs[3 * i + c] += alpha * p[3 * i + c];
+      rv[c] = r[3 * i + c] - alpha * q[3 * i + c];
+      r[3 * i + c] = rv[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T zc = Dinv[9 * i + 3 * c] * rv[0] + Dinv[9 * i + 3 * c + 1] * rv[1] + Dinv[9 * i + 3 * c + 2] * rv[2];
+      z[3 * i + c] = zc;
+      rz += double(rv[c]) * double(zc);
+      rr += double(rv[c]) * double(rv[c]);
+    }
+  }
+  double s0 = block_sum_256(rz, sh);
+  double s1 = block_sum_256(rr, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s0;
+    partials[G + blockIdx.x] = s1;
+  }
+  if (last_block(counter)) {
+    double a0 = sum_partials(partials, G, sh);
+    double a1 = sum_partials(partials + G, G, sh);
+    if (threadIdx.x == 0) {
+      S[S_RZ_OLD] = S[S_RZ];
+      S[S_RZ] = a0;
+      S[S_RR] = a1;
+      S[S_BETA] = (S[S_RZ_OLD] != 0.0) ? a0 / S[S_RZ_OLD] : 0.0;
+      S[S_ITERS] += 1.0;
+      if (a1 <= S[S_TOL2] * S[S_BB] || S[S_ITERS] >= S[S_MAXIT]) S[S_DONE] = 1.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dot64(int64_t n, const double* __restrict__ a,
+                                               const double* __restrict__ b,
+                                               double* __restrict__ partials,
+                                               double* __restrict__ out, unsigned* counter,
+                                               int* nonfinite) {
+  __shared__ double sh[256];
+  const int G = gridDim.x;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)G * 256)
+    acc += a[i] * b[i];
+  double s = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (last_block(counter)) {
+    double tot = sum_partials(partials, G, sh);
+    if (threadIdx.x == 0) {
+      *out = tot;
+      if (!isfinite(tot)) *nonfinite = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_x_tilde(int64_t n, const double* __restrict__ x,
+                                                 const double* __restrict__ v, double dt, double g0,
+                                                 double g1, double g2, double* __restrict__ xt) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int c = int(i % 3);
+    const double g = c == 0 ? g0 : c == 1 ? g1 : g2;
+    xt[i] = x[i] + dt * v[i] + dt * dt * g;
+  }
+}
+
+// y += alpha x (alpha from a device scalar if given)
+__global__ __launch_bounds__(256) void k_axpy64(int64_t n, double* __restrict__ y,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ alpha_dev,
+                                                double alpha_host) {
+  const double a = alpha_dev ? *alpha_dev : alpha_host;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    y[i] += a * x[i];
+}
+
+// out = a + beta b
+__global__ __launch_bounds__(256) void k_lincomb64(int64_t n, double* __restrict__ out,
+                                                   const double* __restrict__ a,
+                                                   const double* __restrict__ b, double beta) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    out[i] = a[i] + beta * b[i];
+}
+
+__global__ __launch_bounds__(256) void k_velocity(int64_t n, double* __restrict__ v,
+                                                  const double* __restrict__ xn,
+                                                  const double* __restrict__ xo, double inv_dt) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    v[i] = (xn[i] - xo[i]) * inv_dt;
+}
+
+// dx (float64) += x_pcg (T)
+template <typename T>
+__global__ __launch_bounds__(256) void k_accumulate(int64_t n, double* __restrict__ dx,
+                                                    const T* __restrict__ xs) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dx[i] += double(xs[i]);
+}
+
+__global__ __launch_bounds__(256) void k_check_finite(int64_t n, const double* __restrict__ a,
+                                                      int* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    bad |= !isfinite(a[i]);
+  if (bad) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t work, int per_block, int cap = 16384) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+#define LAUNCH_CHECK(what)                                          \
+  do {                                                              \
+    hipError_t e_ = hipGetLastError();                              \
+    if (e_ != hipSuccess) return hip_check(e_, what);              \
+  } while (0)
+
+symx_status launch_energy(Mesh& m, const double* x, const double* xt, double dt, int precision,
+                          double* E_dev) {
+  const SetsDev sd = m.sets_dev();
+  int off = 0;
+  for (int s = 0; s < sd.n; ++s) {
+    const int G = grid_for(sd.s[s].n_elem, 256, 8192);
+    if (precision == SYMX_F32)
+      hipLaunchKernelGGL(k_energy_set<float>, dim3(G), dim3(256), 0, m.stream, sd.s[s], x, m.X,
+                         m.partials + off, m.nonfinite);
+    else
+      hipLaunchKernelGGL(k_energy_set<double>, dim3(G), dim3(256), 0, m.stream, sd.s[s], x, m.X,
+                         m.partials + off, m.nonfinite);
+    LAUNCH_CHECK("k_energy_set");
+    off += G;
+  }
+  if (xt) {
+    const int G = grid_for(m.N, 256, 8192);
+    hipLaunchKernelGGL(k_energy_inertia, dim3(G), dim3(256), 0, m.stream, m.N, x, xt, m.mass, dt,
+                       m.partials + off, m.nonfinite);
+    LAUNCH_CHECK("k_energy_inertia");
+    off += G;
+  }
+  hipLaunchKernelGGL(k_reduce_to_scalar, dim3(1), dim3(256), 0, m.stream, m.partials, off, E_dev);
+  LAUNCH_CHECK("k_reduce_to_scalar");
+  return SYMX_OK;
+}
+
+template <typename T>
+static symx_status elem_eval_t(Mesh& m, int set, const double* x, void* E, void* g, void* H) {
+  const SetsDev sd = m.sets_dev();
+  const SetDev& S = sd.s[set];
+  const int G = grid_for(S.n_elem, 128, 65535);
+  if (S.n_elem == 0) return SYMX_OK;
+  switch (S.kind) {
+    case SYMX_SNH_TET4:
+      hipLaunchKernelGGL((k_elem_eval<T, SYMX_SNH_TET4>), dim3(G), dim3(128), 0, m.stream, S, x,
+                         m.X, (T*)E, (T*)g, (T*)H);
+      break;
+    case SYMX_STVK_TRI3:
+      hipLaunchKernelGGL((k_elem_eval<T, SYMX_STVK_TRI3>), dim3(G), dim3(128), 0, m.stream, S, x,
+                         m.X, (T*)E, (T*)g, (T*)H);
+      break;
+    default:
+      hipLaunchKernelGGL((k_elem_eval<T, SYMX_HINGE4>), dim3(G), dim3(128), 0, m.stream, S, x,
+                         m.X, (T*)E, (T*)g, (T*)H);
+  }
+  LAUNCH_CHECK("k_elem_eval");
+  return SYMX_OK;
+}
+
+symx_status launch_elem_eval(Mesh& m, int set, const double* x, int want, int precision, void* E,
+                             void* g, void* H) {
+  (void)want;
+  if (precision == SYMX_F32) return elem_eval_t<float>(m, set, x, E, g, H);
+  return elem_eval_t<double>(m, set, x, E, g, H);
+}
+
+symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim) {
+  if (n == 0) return SYMX_OK;
+  const int G = grid_for(n, 1, 65535);
+  if (precision == SYMX_F32)
+    hipLaunchKernelGGL(k_project_psd<float>, dim3(G), dim3(64), 0, m.stream, (float*)H, n, dim, 30,
+                       1e-7);
+  else
+    hipLaunchKernelGGL(k_project_psd<double>, dim3(G), dim3(64), 0, m.stream, (double*)H, n, dim,
+                       30, 1e-15);
+  LAUNCH_CHECK("k_project_psd");
+  return SYMX_OK;
+}
+
+template <typename T>
+static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, double dt,
+                                  bool want_g, bool want_H, bool dirichlet,
+                                  const ElemBuffers* eb, double* g_out) {
+  RowArgs<T> A;
+  A.sets = m.sets_dev();
+  A.x = x;
+  A.X = m.X;
+  A.xt = xt;
+  A.mass = m.mass;
+  A.inv_dt2 = xt ? 1.0 / (dt * dt) : 0.0;
+  A.fixed = dirichlet ? m.fixed : nullptr;
+  A.batch_row = m.batch_row;
+  A.row_ptr = m.row_ptr;
+  A.col_idx = m.col_idx;
+  A.inc_ptr = m.inc_ptr;
+  A.inc_code = m.inc_code;
+  A.inc_slots = m.inc_slots;
+  A.nnzb = m.nnzb;
+  A.vals = nullptr;
+  if (want_H) A.vals = (T*)(sizeof(T) == 4 ? (void*)m.vals32 : (void*)m.vals64);
+  A.g = g_out;
+  A.nonfinite = m.nonfinite;
+  for (int s = 0; s < kMaxSets; ++s) {
+    A.elem_g[s] = eb ? eb->g[s] : nullptr;
+    A.elem_H[s] = eb ? eb->H[s] : nullptr;
+  }
+  if ((want_g && !g_out) || (!want_g && !want_H)) {
+    set_error("row assembly without an output");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  const dim3 grid(m.n_batch), block(kRowWG);
+  if (eb) {
+    if (want_H && want_g)
+      hipLaunchKernelGGL((k_row_assemble<T, true, true, true>), grid, block, 0, m.stream, A);
+    else if (want_H)
+      hipLaunchKernelGGL((k_row_assemble<T, true, false, true>), grid, block, 0, m.stream, A);
+    else
+      hipLaunchKernelGGL((k_row_assemble<T, true, true, false>), grid, block, 0, m.stream, A);
+  } else if (want_H && want_g) {
+    hipLaunchKernelGGL((k_row_assemble<T, false, true, true>), grid, block, 0, m.stream, A);
+  } else if (want_H) {
+    hipLaunchKernelGGL((k_row_assemble<T, false, false, true>), grid, block, 0, m.stream, A);
+  } else {
+    hipLaunchKernelGGL((k_row_assemble<T, false, true, false>), grid, block, 0, m.stream, A);
+  }
+  LAUNCH_CHECK("k_row_assemble");
+  return SYMX_OK;
+}
+
+symx_status launch_row_assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
+                                bool want_H, int precision, bool dirichlet,
+                                const ElemBuffers* from_elem, double* g_out) {
+  if (precision == SYMX_F32)
+    return row_assemble_t<float>(m, x, xt, dt, want_g, want_H, dirichlet, from_elem, g_out);
+  return row_assemble_t<double>(m, x, xt, dt, want_g, want_H, dirichlet, from_elem, g_out);
+}
+
+symx_status launch_x_tilde(Mesh& m, const double* x, const double* v, double dt, const double g[3],
+                           double* xt) {
+  const int64_t n = 3 * m.N;
+  hipLaunchKernelGGL(k_x_tilde, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, x, v, dt, g[0],
+                     g[1], g[2], xt);
+  LAUNCH_CHECK("k_x_tilde");
+  return SYMX_OK;
+}
+
+symx_status launch_dot64(Mesh& m, const double* a, const double* b, int64_t n, double* out_dev) {
+  hipLaunchKernelGGL(k_dot64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, m.stream, n, a, b,
+                     m.partials, out_dev, m.counters + 3, m.nonfinite);
+  LAUNCH_CHECK("k_dot64");
+  return SYMX_OK;
+}
+
+symx_status launch_axpy64(Mesh& m, double* y, const double* x, const double* alpha_dev,
+                          double alpha_host, int64_t n) {
+  hipLaunchKernelGGL(k_axpy64, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, y, x, alpha_dev,
+                     alpha_host);
+  LAUNCH_CHECK("k_axpy64");
+  return SYMX_OK;
+}
+
+symx_status launch_lincomb64(Mesh& m, double* out, const double* a, const double* b, double beta,
+                             int64_t n) {
+  hipLaunchKernelGGL(k_lincomb64, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, out, a, b,
+                     beta);
+  LAUNCH_CHECK("k_lincomb64");
+  return SYMX_OK;
+}
+
+symx_status launch_velocity(Mesh& m, double* v, const double* xn, const double* xo, double inv_dt,
+                            int64_t n) {
+  hipLaunchKernelGGL(k_velocity, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, v, xn, xo,
+                     inv_dt);
+  LAUNCH_CHECK("k_velocity");
+  return SYMX_OK;
+}
+
+symx_status launch_check_finite(Mesh& m, const double* a, int64_t n) {
+  hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, 256, 4096)), dim3(256), 0, m.stream, n, a,
+                     m.nonfinite);
+  LAUNCH_CHECK("k_check_finite");
+  return SYMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PCG driver pieces (called from symx_newton.cpp)
+// ---------------------------------------------------------------------------
+symx_status launch_diag_inverse(Mesh& m, int precision, void* Dinv) {
+  const int G = grid_for(m.N, 256);
+  if (precision == SYMX_F64)
+    hipLaunchKernelGGL(k_diag_inverse<double>, dim3(G), dim3(256), 0, m.stream, m.N, m.nnzb,
+                       m.diag_pos, m.vals64, (double*)Dinv);
+  else
+    hipLaunchKernelGGL(k_diag_inverse<float>, dim3(G), dim3(256), 0, m.stream, m.N, m.nnzb,
+                       m.diag_pos, m.vals32, (float*)Dinv);
+  LAUNCH_CHECK("k_diag_inverse");
+  return SYMX_OK;
+}
+
+symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const double* b,
+                            double tol2, int max_iter) {
+  const int G = grid_for(m.N, 256, 8192);
+  if (precision == SYMX_F64)
+    hipLaunchKernelGGL((k_pcg_init<double, double>), dim3(G), dim3(256), 0, m.stream, m.N, b,
+                       (const double*)B.Dinv, (double*)B.xs, (double*)B.r, (double*)B.z,
+                       (double*)B.p, (double*)B.q, m.partials, m.scalars, m.counters + 0, tol2,
+                       max_iter);
+  else
+    hipLaunchKernelGGL((k_pcg_init<float, double>), dim3(G), dim3(256), 0, m.stream, m.N, b,
+                       (const float*)B.Dinv, (float*)B.xs, (float*)B.r, (float*)B.z, (float*)B.p,
+                       (float*)B.q, m.partials, m.scalars, m.counters + 0, tol2, max_iter);
+  LAUNCH_CHECK("k_pcg_init");
+  return SYMX_OK;
+}
+
+symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int n_iter) {
+  const int Gs = grid_for(m.N * 16, 256, 16384);
+  const int Gu = grid_for(m.N, 256, 8192);
+  for (int it = 0; it < n_iter; ++it) {
+    if (precision == SYMX_F64) {
+      hipLaunchKernelGGL(k_pcg_spmv<double>, dim3(Gs), dim3(256), 0, m.stream, m.N, m.row_ptr,
+                         m.col_idx, m.vals64, m.nnzb, (const double*)B.z, (double*)B.p,
+                         (double*)B.q, m.partials, m.scalars, m.counters + 1);
+      hipLaunchKernelGGL(k_pcg_update<double>, dim3(Gu), dim3(256), 0, m.stream, m.N,
+                         (const double*)B.Dinv, (double*)B.xs, (double*)B.r, (double*)B.z,
+                         (const double*)B.p, (const double*)B.q, m.partials + 32768, m.scalars,
+                         m.counters + 2);
+    } else {
+      hipLaunchKernelGGL(k_pcg_spmv<float>, dim3(Gs), dim3(256), 0, m.stream, m.N, m.row_ptr,
+                         m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p, (float*)B.q,
+                         m.partials, m.scalars, m.counters + 1);
+      hipLaunchKernelGGL(k_pcg_update<float>, dim3(Gu), dim3(256), 0, m.stream, m.N,
+                         (const float*)B.Dinv, (float*)B.xs, (float*)B.r, (float*)B.z,
+                         (const float*)B.p, (const float*)B.q, m.partials + 32768, m.scalars,
+                         m.counters + 2);
+    }
+  }
+  LAUNCH_CHECK("k_pcg");
+  return SYMX_OK;
+}
+
+symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs) {
+  const int64_t n = 3 * m.N;
+  if (precision == SYMX_F64)
+    hipLaunchKernelGGL(k_accumulate<double>, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, dx,
+                       (const double*)xs);
+  else
+    hipLaunchKernelGGL(k_accumulate<float>, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, dx,
+                       (const float*)xs);
+  LAUNCH_CHECK("k_accumulate");
+  return SYMX_OK;
+}
+
+symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b,
+                              double* r) {
+  const int G = grid_for(m.N * 16, 256, 16384);
+  if (precision == SYMX_F64)
+    hipLaunchKernelGGL(k_residual64<double>, dim3(G), dim3(256), 0, m.stream, m.N, m.row_ptr,
+                       m.col_idx, m.vals64, m.nnzb, x, b, r);
+  else
+    hipLaunchKernelGGL(k_residual64<float>, dim3(G), dim3(256), 0, m.stream, m.N, m.row_ptr,
+                       m.col_idx, m.vals32, m.nnzb, x, b, r);
+  LAUNCH_CHECK("k_residual64");
+  return SYMX_OK;
+}
+
+}  // namespace symxi

@@ -1,0 +1,367 @@
+// Assembly entry points and the Newton driver on the mesh's stream.
+//
+// Newton step (Eq. 2-3, Sec. 7): minimise the incremental potential from
+// x(t); per iteration assemble the gradient and Hessian, stop when
+// |g_free| <= rtol |g_free(x(t))|, solve H dx = -g with block-Jacobi PCG to the
+// forcing tolerance min(0.5, sqrt(r_k / r_0)), backtrack along dx with the
+// Armijo test E(x + a dx) <= E(x) + 1e-4 a g.dx (a halves, at most 30 times),
+// and restart the whole step with dt/2 when the line search fails or Newton
+// exceeds its iteration limit (the paper's benchmark protocol, Sec. 7).
+//
+// Precision modes: SYMX_F64 runs everything in float64.  SYMX_F32_REFINED
+// assembles the Hessian and runs SpMV/PCG in float32, while energies, the
+// gradient (hence the residual) and the solution update stay float64; the
+// linear solve is refined in float64 (residual b - H dx with the float32 H
+// promoted, then another float32 PCG solve for the correction).  SYMX_F32
+// evaluates all element quantities in float32 (sums in float64).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "symx_internal.h"
+
+namespace symxi {
+
+
+enum { S_RZ = 0, S_RZ_OLD, S_PQ, S_RR, S_BB, S_ALPHA, S_BETA, S_TOL2, S_DONE, S_ITERS, S_MAXIT };
+// device scalar slots used by the driver (after the PCG scalars)
+enum { D_ENERGY = 16, D_DOT = 17, D_DOT2 = 18 };
+
+#define TRY(expr)                 \
+  do {                            \
+    symx_status s_ = (expr);      \
+    if (s_ != SYMX_OK) return s_; \
+  } while (0)
+
+struct Workspace {
+  int64_t N = 0;
+  double *x_t = nullptr, *v_t = nullptr, *xt = nullptr, *xk = nullptr, *xtrial = nullptr;
+  double *g = nullptr, *dx = nullptr, *b = nullptr, *res = nullptr;
+  void* pcg[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // Dinv xs r z p q (max size)
+};
+
+static symx_status dalloc(void** p, size_t bytes) {
+  if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) {
+    *p = nullptr;
+    set_error("device allocation failed");
+    return SYMX_ERR_OUT_OF_MEMORY;
+  }
+  return SYMX_OK;
+}
+
+static symx_status ensure_values(Mesh& m, int precision) {
+  if (precision == SYMX_F64 && !m.vals64) return dalloc((void**)&m.vals64, 9 * m.nnzb * sizeof(double));
+  if (precision != SYMX_F64 && !m.vals32) return dalloc((void**)&m.vals32, 9 * m.nnzb * sizeof(float));
+  return SYMX_OK;
+}
+
+static symx_status ensure_workspace(Mesh& m) {
+  if (m.ws) return SYMX_OK;
+  Workspace* w = new Workspace();
+  m.ws = w;
+  w->N = m.N;
+  const size_t v64 = 3 * m.N * sizeof(double);
+  double** vecs[] = {&w->x_t, &w->v_t, &w->xt, &w->xk, &w->xtrial, &w->g, &w->dx, &w->b, &w->res};
+  for (double** p : vecs) TRY(dalloc((void**)p, v64));
+  TRY(dalloc(&w->pcg[0], 9 * m.N * sizeof(double)));
+  for (int i = 1; i < 6; ++i) TRY(dalloc(&w->pcg[i], v64));
+  return SYMX_OK;
+}
+
+void free_workspace(Mesh& m) {
+  if (!m.ws) return;
+  Workspace* w = m.ws;
+  double* vecs[] = {w->x_t, w->v_t, w->xt, w->xk, w->xtrial, w->g, w->dx, w->b, w->res};
+  for (double* p : vecs)
+    if (p) (void)hipFree(p);
+  for (void* p : w->pcg)
+    if (p) (void)hipFree(p);
+  delete w;
+  m.ws = nullptr;
+}
+
+static symx_status sync_read(Mesh& m, const double* dev, int n, double* host) {
+  TRY(hip_check(hipMemcpyAsync(m.pinned, dev, n * sizeof(double), hipMemcpyDeviceToHost, m.stream),
+                "hipMemcpyAsync"));
+  TRY(hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize"));
+  std::memcpy(host, m.pinned, n * sizeof(double));
+  return SYMX_OK;
+}
+
+static symx_status check_nonfinite(Mesh& m) {
+  int flag = 0;
+  TRY(hip_check(hipMemcpyAsync(&flag, m.nonfinite, sizeof(int), hipMemcpyDeviceToHost, m.stream),
+                "hipMemcpyAsync"));
+  TRY(hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize"));
+  if (flag) {
+    TRY(hip_check(hipMemsetAsync(m.nonfinite, 0, sizeof(int), m.stream), "hipMemsetAsync"));
+    set_error("non-finite value in positions, energy or gradient");
+    return SYMX_ERR_NONFINITE;
+  }
+  return SYMX_OK;
+}
+
+// Per-element buffers for the projected path (allocated on first use).
+static symx_status project_elements(Mesh& m, const double* x, int precision, bool want_g,
+                                    ElemBuffers* eb) {
+  const size_t es = precision == SYMX_F64 ? 8 : 4;
+  size_t need = 0;
+  std::vector<size_t> offg(m.sets.size()), offH(m.sets.size());
+  for (size_t s = 0; s < m.sets.size(); ++s) {
+    const size_t D = 3 * m.sets[s].k;
+    offg[s] = need;
+    need += m.sets[s].n_elem * D * es;
+    need = (need + 255) & ~size_t(255);
+    offH[s] = need;
+    need += m.sets[s].n_elem * D * D * es;
+    need = (need + 255) & ~size_t(255);
+  }
+  if (need > m.elem_bytes) {
+    if (m.elem_H) (void)hipFree(m.elem_H);
+    m.elem_H = nullptr;
+    m.elem_bytes = 0;
+    TRY(dalloc(&m.elem_H, need));
+    m.elem_bytes = need;
+  }
+  (void)want_g;
+  for (int s = 0; s < kMaxSets; ++s) eb->g[s] = eb->H[s] = nullptr;
+  for (size_t s = 0; s < m.sets.size(); ++s) {
+    char* base = (char*)m.elem_H;
+    void* g = base + offg[s];
+    void* H = base + offH[s];
+    const int D = 3 * m.sets[s].k;
+    TRY(launch_elem_eval(m, (int)s, x, 7, precision, nullptr, g, H));
+    TRY(launch_project(m, precision, H, m.sets[s].n_elem, D));
+    eb->g[s] = g;
+    eb->H[s] = H;
+  }
+  return SYMX_OK;
+}
+
+// Assemble gradient (float64) and/or Hessian values (precision) at x.
+symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g, bool want_H,
+                     bool project, int precision, bool dirichlet, double* g_out) {
+  if (want_H) TRY(ensure_values(m, precision));
+  if (project && want_H) {
+    ElemBuffers eb;
+    TRY(project_elements(m, x, precision, want_g, &eb));
+    return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, &eb, g_out);
+  }
+  if (!want_g && !want_H) return SYMX_OK;
+  return launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, g_out);
+}
+
+symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E) {
+  TRY(launch_energy(m, x, xt, dt, precision, m.scalars + D_ENERGY));
+  TRY(sync_read(m, m.scalars + D_ENERGY, 1, E));
+  TRY(check_nonfinite(m));
+  return SYMX_OK;
+}
+
+static symx_status dot(Mesh& m, const double* a, const double* b, double* out) {
+  TRY(launch_dot64(m, a, b, 3 * m.N, m.scalars + D_DOT));
+  return sync_read(m, m.scalars + D_DOT, 1, out);
+}
+
+// PCG on H y = b (b float64), y accumulated into dx (float64).  Returns
+// iterations through *iters.
+static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rtol, int max_iter,
+                             double* dx, int* iters, bool* breakdown) {
+  Workspace* w = m.ws;
+  PcgBuffers B{w->pcg[0], w->pcg[1], w->pcg[2], w->pcg[3], w->pcg[4], w->pcg[5]};
+  const int pp = precision == SYMX_F64 ? SYMX_F64 : SYMX_F32;
+  TRY(launch_pcg_init(m, pp, B, b, rtol * rtol, max_iter));
+  double S[11];
+  int done_iters = 0;
+  int chunk = 8;
+  *breakdown = false;
+  while (true) {
+    TRY(launch_pcg_iters(m, pp, B, chunk));
+    TRY(sync_read(m, m.scalars, 11, S));
+    if (S[S_DONE] != 0.0) {
+      done_iters = (int)S[S_ITERS];
+      *breakdown = S[S_DONE] == 2.0;
+      break;
+    }
+    if (chunk < 32) chunk *= 2;
+  }
+  *iters = done_iters;
+  return launch_accumulate(m, pp, dx, B.xs);
+}
+
+// Linear solve with optional float64 refinement (F32_REFINED).
+static symx_status linear_solve(Mesh& m, const symx_step_params& P, const double* g, double eta,
+                                double gnorm, int* pcg_iters, int* refinements) {
+  Workspace* w = m.ws;
+  const int n = (int)(3 * m.N);
+  // b = -g ; dx = 0
+  TRY(hip_check(hipMemsetAsync(w->dx, 0, n * sizeof(double), m.stream), "hipMemsetAsync"));
+  TRY(launch_lincomb64(m, w->b, w->dx, g, -1.0, n));
+  const int prec_h = P.precision == SYMX_F64 ? SYMX_F64 : SYMX_F32;
+  TRY(launch_diag_inverse(m, prec_h, w->pcg[0]));
+  int it = 0;
+  bool bd = false;
+  TRY(pcg_solve(m, P.precision, w->b, eta, P.max_pcg, w->dx, &it, &bd));
+  *pcg_iters += it;
+  if (P.precision != SYMX_F32_REFINED) return SYMX_OK;
+  // float64 refinement: r = b - H dx (H float32 promoted); solve H c = r; dx += c
+  for (int k = 0; k < P.max_refine; ++k) {
+    TRY(launch_residual64(m, SYMX_F32, w->dx, w->b, w->res));
+    double rr = 0.0;
+    TRY(dot(m, w->res, w->res, &rr));
+    if (std::sqrt(rr) <= eta * gnorm) break;
+    int it2 = 0;
+    double tol = std::max(eta * gnorm / std::sqrt(rr), 1e-6);
+    TRY(pcg_solve(m, P.precision, w->res, std::min(tol, 0.5), P.max_pcg, w->dx, &it2, &bd));
+    *pcg_iters += it2;
+    *refinements += 1;
+  }
+  return SYMX_OK;
+}
+
+using clk = std::chrono::steady_clock;
+static double ms_since(clk::time_point t0) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+// One attempt at fixed dt from (x_t, v_t) in the workspace; result in w->xk.
+static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, symx_step_report* R) {
+  Workspace* w = m.ws;
+  const int64_t n = 3 * m.N;
+  const int pe = P.precision == SYMX_F64 ? SYMX_F64 : (P.precision == SYMX_F32 ? SYMX_F32 : SYMX_F64);
+  const int ph = P.precision == SYMX_F64 ? SYMX_F64 : SYMX_F32;
+  TRY(launch_x_tilde(m, w->x_t, w->v_t, dt, P.gravity, w->xt));
+  TRY(hip_check(hipMemcpyAsync(w->xk, w->x_t, n * sizeof(double), hipMemcpyDeviceToDevice, m.stream),
+                "hipMemcpyAsync"));
+  double r0 = -1.0, E0 = 0.0;
+  bool have_E0 = false;
+  for (int it = 0;; ++it) {
+    auto t0 = clk::now();
+    if (pe == ph) {
+      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project != 0, ph, true, w->g));
+    } else {
+      TRY(assemble(m, w->xk, w->xt, dt, true, false, false, pe, true, w->g));
+      TRY(assemble(m, w->xk, w->xt, dt, false, true, P.project != 0, ph, true, nullptr));
+    }
+    double gg = 0.0;
+    TRY(dot(m, w->g, w->g, &gg));
+    TRY(check_nonfinite(m));
+    R->ms_assemble += ms_since(t0);
+    const double r = std::sqrt(gg);
+    if (r0 < 0.0) {
+      r0 = r;
+      R->residual0 = r0;
+    }
+    R->residual = r;
+    if (r <= P.newton_rtol * r0) {
+      if (!have_E0) TRY(energy(m, w->xk, w->xt, dt, pe, &E0));
+      R->energy = E0;
+      return SYMX_OK;
+    }
+    if (it >= P.max_newton) {
+      set_error("Newton did not converge within max_newton iterations");
+      return SYMX_ERR_NOT_CONVERGED;
+    }
+    auto t1 = clk::now();
+    const double eta = std::min(0.5, std::sqrt(r / r0));
+    TRY(linear_solve(m, P, w->g, eta, r, &R->pcg_iters, &R->refinements));
+    R->ms_pcg += ms_since(t1);
+    auto t2 = clk::now();
+    double gd = 0.0;
+    TRY(dot(m, w->g, w->dx, &gd));
+    if (!(gd < 0.0)) {
+      set_error("Newton direction is not a descent direction");
+      return SYMX_ERR_LINE_SEARCH;
+    }
+    if (!have_E0) TRY(energy(m, w->xk, w->xt, dt, pe, &E0));
+    double alpha = 1.0;
+    bool ok = false;
+    double Et = 0.0;
+    for (int ls = 0; ls <= 30; ++ls) {
+      TRY(launch_lincomb64(m, w->xtrial, w->xk, w->dx, alpha, n));
+      symx_status st = energy(m, w->xtrial, w->xt, dt, pe, &Et);
+      if (st == SYMX_OK && Et <= E0 + 1e-4 * alpha * gd) {
+        ok = true;
+        break;
+      }
+      if (st != SYMX_OK && st != SYMX_ERR_NONFINITE) return st;
+      alpha *= 0.5;
+      R->ls_backtracks++;
+    }
+    R->ms_linesearch += ms_since(t2);
+    if (!ok) {
+      set_error("line search failed");
+      return SYMX_ERR_LINE_SEARCH;
+    }
+    std::swap(w->xk, w->xtrial);
+    E0 = Et;
+    have_E0 = true;
+    R->newton_iters++;
+  }
+}
+
+symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P,
+                        symx_step_report* out) {
+  TRY(ensure_workspace(m));
+  Workspace* w = m.ws;
+  const int64_t n = 3 * m.N;
+  symx_step_report R;
+  std::memset(&R, 0, sizeof R);
+  auto t0 = clk::now();
+  TRY(launch_check_finite(m, x, n));
+  TRY(launch_check_finite(m, v, n));
+  TRY(check_nonfinite(m));
+  TRY(hip_check(hipMemcpyAsync(w->x_t, x, n * sizeof(double), hipMemcpyDeviceToDevice, m.stream),
+                "hipMemcpyAsync"));
+  TRY(hip_check(hipMemcpyAsync(w->v_t, v, n * sizeof(double), hipMemcpyDeviceToDevice, m.stream),
+                "hipMemcpyAsync"));
+  if (m.dt_nominal != P.dt) {
+    m.dt_nominal = P.dt;
+    m.dt_cur = P.dt;
+    m.successes = 0;
+  }
+  double dt = m.dt_cur;
+  int halvings = 0;
+  symx_status st;
+  while (true) {
+    symx_step_report attempt;
+    std::memset(&attempt, 0, sizeof attempt);
+    st = solve_step(m, P, dt, &attempt);
+    R.newton_iters += attempt.newton_iters;
+    R.pcg_iters += attempt.pcg_iters;
+    R.ls_backtracks += attempt.ls_backtracks;
+    R.refinements += attempt.refinements;
+    R.ms_assemble += attempt.ms_assemble;
+    R.ms_pcg += attempt.ms_pcg;
+    R.ms_linesearch += attempt.ms_linesearch;
+    R.residual0 = attempt.residual0;
+    R.residual = attempt.residual;
+    R.energy = attempt.energy;
+    if (st == SYMX_OK) break;
+    if (st != SYMX_ERR_LINE_SEARCH && st != SYMX_ERR_NOT_CONVERGED) break;
+    if (halvings >= P.max_halvings) break;
+    dt *= 0.5;
+    ++halvings;
+  }
+  R.dt_halvings = halvings;
+  R.dt_used = dt;
+  R.status = st;
+  if (st == SYMX_OK) {
+    TRY(launch_velocity(m, v, w->xk, w->x_t, 1.0 / dt, n));
+    TRY(hip_check(hipMemcpyAsync(x, w->xk, n * sizeof(double), hipMemcpyDeviceToDevice, m.stream),
+                  "hipMemcpyAsync"));
+    TRY(hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize"));
+    if (halvings) {
+      m.dt_cur = dt;
+      m.successes = 0;
+    } else if (++m.successes >= P.regrow_after && m.dt_cur < m.dt_nominal) {
+      m.dt_cur = std::min(2.0 * m.dt_cur, m.dt_nominal);
+      m.successes = 0;
+    }
+  }
+  R.ms_total = ms_since(t0);
+  if (out) *out = R;
+  return st;
+}
+
+}  // namespace symxi

@@ -1,0 +1,159 @@
+"""The symbolic generator (symx_gen) against the hand-derived FP64 oracle, on CPU.
+
+symx_gen emits the same element functions twice: as HIP device templates for
+the library and as plain C for this test.  Both come from one expression graph,
+so checking the C variant in FP64 checks the symbolic energy definitions, the
+differentiation and the code emission independently of any GPU.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import elements, rest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIBPATH = os.path.join(ROOT, "_build", "libsymx_gen_cpu.so")
+META = os.path.join(ROOT, "paper_2303_02156_amd", "csrc", "generated", "symx_generated_meta.txt")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not (os.path.exists(LIBPATH) and os.path.exists(META)):
+        from paper_2303_02156_amd import build
+        build.build_generator()
+        build.build_cpu_testlib()
+    return ctypes.CDLL(LIBPATH)
+
+
+def _call(lib, name, inp, n_out):
+    fn = getattr(lib, name)
+    fn.restype = None
+    out = np.zeros((inp.shape[0], n_out))
+    buf_in = np.ascontiguousarray(inp, dtype=np.float64)
+    o = np.zeros(n_out)
+    for e in range(inp.shape[0]):
+        fn(buf_in[e].ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+           o.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        out[e] = o
+    return out
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def _meta():
+    rows = {}
+    for line in open(META):
+        if line.startswith("#"):
+            continue
+        f = line.split()
+        rows[f[0]] = [int(v) for v in f[1:]]
+    return rows
+
+
+def test_io_counts_match_paper(lib):
+    meta = _meta()
+    gold = os.path.join(ROOT, "tests", "golden", "tet4_function_io.txt")
+    for line in open(gold):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, nin, nout = line.split()
+        assert meta[name][0] == int(nin) and meta[name][1] == int(nout)
+
+
+MU, LAM = rest.lame(1e5, 0.4)
+
+
+def test_snh_generated_vs_oracle(lib):
+    x, X = sg.random_tets(60, seed=101)
+    n = x.shape[0]
+    E, g, H = elements.snh_tet4(x, X, np.full(n, MU), np.full(n, LAM))
+    inp = np.concatenate([x.reshape(n, 12), X.reshape(n, 12), np.full((n, 1), MU),
+                          np.full((n, 1), LAM)], axis=1)
+    out = _call(lib, "snh_tet4_EgH", inp, 157)
+    assert _rel(out[:, 0], E) < 1e-11
+    assert _rel(out[:, 1:13], g.reshape(n, 12)) < 1e-11
+    assert _rel(out[:, 13:], H.reshape(n, 144)) < 1e-11
+    assert _rel(_call(lib, "snh_tet4_E", inp, 1)[:, 0], E) < 1e-11
+    # node 0 at the origin
+    xs = x - x[:, :1]
+    Xs = X - X[:, :1]
+    inp_s = np.concatenate([xs.reshape(n, 12), Xs.reshape(n, 12), inp[:, 24:]], axis=1)
+    out_s = _call(lib, "snh_tet4_s_EgH", inp_s, 157)
+    assert _rel(out_s, out) < 1e-10
+    # block rows by relabelling node a as node 0
+    for a in range(4):
+        perm = [a] + [b for b in range(4) if b != a]
+        xp = x[:, perm] - x[:, a:a + 1]
+        Xp = X[:, perm] - X[:, a:a + 1]
+        inp_r = np.concatenate([xp.reshape(n, 12), Xp.reshape(n, 12), inp[:, 24:]], axis=1)
+        r = _call(lib, "snh_tet4_row0_gH", inp_r, 39)
+        assert _rel(r[:, :3], g[:, a]) < 1e-10
+        Hrow = H[:, a][:, :, perm, :].reshape(n, 3, 12)     # (e, i, b', k)
+        assert _rel(r[:, 3:].reshape(n, 3, 12), Hrow) < 1e-10
+        rg = _call(lib, "snh_tet4_row0_g", inp_r, 3)
+        assert _rel(rg, g[:, a]) < 1e-10
+
+
+def _random_tris(n, seed):
+    rng = np.random.default_rng(seed)
+    base = np.array([[0, 0, 0], [1, 0, 0], [0.2, 0.9, 0]], dtype=np.float64) * 0.01
+    X = base[None] + rng.uniform(-0.002, 0.002, size=(n, 3, 3))
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    X = X @ q.T
+    A = np.eye(3)[None] + rng.uniform(-0.2, 0.2, size=(n, 3, 3))
+    x = np.einsum("eij,eaj->eai", A, X) + rng.uniform(-1, 1, size=(n, 1, 3))
+    return x, X
+
+
+def test_stvk_generated_vs_oracle(lib):
+    mu, lam = rest.lame(1e4, 0.3)
+    x, X = _random_tris(60, 102)
+    n = x.shape[0]
+    E, g, H = elements.stvk_tri3(x, X, np.full(n, mu), np.full(n, lam), 1e-3)
+    prm = np.tile([mu, lam, 1e-3], (n, 1))
+    inp = np.concatenate([x.reshape(n, 9), X.reshape(n, 9), prm], axis=1)
+    out = _call(lib, "stvk_tri3_EgH", inp, 91)
+    assert _rel(out[:, 0], E) < 1e-10
+    assert _rel(out[:, 1:10], g.reshape(n, 9)) < 1e-10
+    assert _rel(out[:, 10:], H.reshape(n, 81)) < 1e-10
+    for a in range(3):
+        perm = [a] + [b for b in range(3) if b != a]
+        xp = x[:, perm] - x[:, a:a + 1]
+        Xp = X[:, perm] - X[:, a:a + 1]
+        r = _call(lib, "stvk_tri3_row0_gH",
+                  np.concatenate([xp.reshape(n, 9), Xp.reshape(n, 9), prm], axis=1), 30)
+        assert _rel(r[:, :3], g[:, a]) < 1e-10
+        assert _rel(r[:, 3:].reshape(n, 3, 9), H[:, a][:, :, perm, :].reshape(n, 3, 9)) < 1e-10
+
+
+def test_hinge_and_inertia_generated_vs_oracle(lib):
+    rng = np.random.default_rng(103)
+    n = 40
+    X = np.zeros((n, 4, 3))
+    X[:, 1, 0] = 1.0
+    X[:, 2, :2] = rng.uniform(0.2, 0.8, (n, 2))
+    X[:, 3, 0] = rng.uniform(0.2, 0.8, n)
+    X[:, 3, 1] = -rng.uniform(0.2, 0.8, n)
+    X *= 0.01
+    x = X + rng.normal(scale=2e-3, size=X.shape)
+    E, g, H = elements.hinge4(x, X, 1e-3)
+    K, c = elements.hinge_rest(X)
+    inp = np.concatenate([x.reshape(n, 12), K, c[:, None], np.full((n, 1), 1e-3)], axis=1)
+    out = _call(lib, "hinge4_EgH", inp, 157)
+    assert _rel(out[:, 0], E) < 1e-11
+    assert _rel(out[:, 1:13], g.reshape(n, 12)) < 1e-11
+    assert _rel(out[:, 13:], H.reshape(n, 144)) < 1e-11
+    # inertia
+    xi = rng.normal(size=(n, 3))
+    xt = rng.normal(size=(n, 3))
+    m = rng.uniform(0.1, 1.0, n)
+    Ei, gi, w = elements.inertia(xi, xt, m, 0.01)
+    out = _call(lib, "inertia_EgH", np.concatenate([xi, xt, m[:, None], np.full((n, 1), 0.01)], 1), 13)
+    assert _rel(out[:, 0], Ei) < 1e-13
+    assert _rel(out[:, 1:4], gi) < 1e-13
+    assert _rel(out[:, 4:], (w[:, None, None] * np.eye(3)).reshape(n, 9)) < 1e-13

@@ -1,0 +1,309 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances (normwise, max|a-b| / max|b| per output array): 1e-10 in float64,
+1e-4 in float32 (the element kernels, Hessian values and PCG in single
+precision).  Integer outputs (pattern, scatter map) are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import assembly, elements, newton, projection, rest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-10
+F32_TOL = 1e-4
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def symx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_02156_amd import symx as s
+    s.load()
+    return s
+
+
+def loose_tet_scene(n_elem, seed):
+    """Disjoint stressed tets (inverted / compressed / stretched): one scene."""
+    x, X = sg.random_tets(n_elem, seed)
+    conn = np.arange(4 * n_elem, dtype=np.int32).reshape(n_elem, 4)
+    es = sg.EnergySet(sg.SNH_TET4, conn, young_per_elem=np.exp(
+        np.random.default_rng(seed).uniform(np.log(1e4), np.log(1e7), n_elem)), poisson=0.4)
+    Xf = X.reshape(-1, 3)
+    return sg.Scene("loose", Xf, [es], np.zeros(Xf.shape[0], np.uint8), x.reshape(-1, 3),
+                    np.zeros_like(Xf)), x.reshape(-1, 3)
+
+
+def mixed_scene():
+    """Tet block + cloth (membrane + hinges) in one global system, perturbed."""
+    s = sg.tet_cube_scene(3, seed=7, perturb=0.05)
+    c = sg.cloth_scene(5, perturb=0.2)
+    N = s.n_nodes
+    es = [s.energies[0]] + [sg.EnergySet(e.kind, e.conn + N, young=e.young, poisson=e.poisson,
+                                         thickness=e.thickness, bend_kb=e.bend_kb,
+                                         density=e.density) for e in c.energies]
+    X = np.concatenate([s.X, c.X])
+    return sg.Scene("mixed", X, es, np.concatenate([s.fixed, c.fixed]),
+                    np.concatenate([s.x0, c.x0]), np.zeros_like(X), dt=0.01)
+
+
+# ---------------------------------------------------------------------------
+# pattern, scatter map, masses
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["c1", "mixed"])
+def test_pattern_and_scatter_map_bit_exact(symx, which):
+    scene = sg.config_c1() if which == "c1" else mixed_scene()
+    mesh = symx.Mesh(scene)
+    rp, ci, maps = mesh.pattern()
+    rp_o, ci_o = assembly.pattern_fast(scene)
+    assert np.array_equal(rp, rp_o)
+    assert np.array_equal(ci, ci_o)
+    for es, m in zip(scene.energies, maps):
+        assert np.array_equal(m, assembly._block_index(es.conn, rp_o, ci_o))
+    assert mesh.info.nnzb == ci_o.size
+    assert rel(mesh.masses(), rest.lumped_mass(scene)) < 1e-14
+    mesh.close()
+
+
+# ---------------------------------------------------------------------------
+# per-element derivatives
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_elem_derivatives_stressed_tets(symx, precision):
+    scene, x = loose_tet_scene(3000, 5)
+    mesh = symx.Mesh(scene)
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32
+    E, g, H = mesh.eval_derivatives(0, x, precision=p)
+    Eo, go, Ho = elements.element_eval(scene.energies[0], x, scene.X)
+    tol = F64_TOL if precision == "f64" else F32_TOL
+    n = Eo.shape[0]
+    # energies: per element (SNH has a large rest offset, so compare per element)
+    assert rel(E.cpu().numpy(), Eo) < tol
+    assert rel(g.cpu().numpy().reshape(n, 4, 3), go) < tol
+    Hd = H.cpu().numpy().reshape(n, 12, 12)
+    Hr = Ho.reshape(n, 12, 12)
+    worst = max(rel(Hd[e], Hr[e]) for e in range(0, n, 7))
+    assert worst < tol
+    mesh.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_elem_derivatives_cloth(symx, precision):
+    scene = sg.cloth_scene(6, perturb=0.3)
+    mesh = symx.Mesh(scene)
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32
+    tol = F64_TOL if precision == "f64" else F32_TOL
+    x = scene.x0 + np.random.default_rng(2).normal(scale=0.01, size=scene.x0.shape)
+    for si, es in enumerate(scene.energies):
+        E, g, H = mesh.eval_derivatives(si, x, precision=p)
+        Eo, go, Ho = elements.element_eval(es, x, scene.X)
+        k = es.conn.shape[1]
+        n = es.conn.shape[0]
+        assert rel(E.cpu().numpy(), Eo) < tol, si
+        assert rel(g.cpu().numpy().reshape(n, k, 3), go) < tol, si
+        assert rel(H.cpu().numpy().reshape(n, 3 * k, 3 * k), Ho.reshape(n, 3 * k, 3 * k)) < tol, si
+    mesh.close()
+
+
+def test_elem_projection_matches_eigh(symx):
+    scene, x = loose_tet_scene(600, 9)
+    mesh = symx.Mesh(scene)
+    flags = symx.SYMX_EVAL_HESS | symx.SYMX_PROJECT_PSD
+    _, _, H = mesh.eval_derivatives(0, x, flags=flags, precision=symx.SYMX_F64)
+    _, _, Ho = elements.element_eval(scene.energies[0], x, scene.X)
+    Po = projection.project_psd(Ho.reshape(-1, 12, 12))
+    Hd = H.cpu().numpy()
+    n_neg = np.sum(np.linalg.eigvalsh(Ho.reshape(-1, 12, 12)).min(axis=1) < 0)
+    assert n_neg > 50  # the stressed set really exercises the projection
+    for e in range(Hd.shape[0]):
+        assert rel(Hd[e], Po[e]) < F64_TOL, e
+    _, _, H32 = mesh.eval_derivatives(0, x, flags=flags, precision=symx.SYMX_F32)
+    H32 = H32.cpu().numpy()
+    worst = max(rel(H32[e], Po[e]) for e in range(H32.shape[0]))
+    assert worst < F32_TOL
+    mesh.close()
+
+
+# ---------------------------------------------------------------------------
+# global assembly
+# ---------------------------------------------------------------------------
+def _bsr(vals):
+    return vals.cpu().numpy().astype(np.float64).T.reshape(-1, 3, 3)
+
+
+@pytest.mark.parametrize("which", ["c1", "mixed"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_assembly_matches_oracle(symx, which, precision):
+    scene = sg.config_c1() if which == "c1" else mixed_scene()
+    mesh = symx.Mesh(scene)
+    dt = scene.dt
+    xt = elements.x_tilde(scene.x0, scene.x0 * 0 + 0.05, dt, scene.gravity)
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32
+    tol = F64_TOL if precision == "f64" else F32_TOL
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    E, g, vals = mesh.assemble(scene.x0, xt, dt, flags, p)
+    ref = assembly.assemble(scene, scene.x0, xt, dt)
+    assert abs(E - ref["E"]) <= tol * abs(ref["E"])
+    assert rel(g.cpu().numpy(), ref["g"]) < tol
+    assert rel(_bsr(vals), ref["vals"]) < tol
+    # elastic only, no Dirichlet
+    flags2 = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS
+    E2, g2, v2 = mesh.assemble(scene.x0, None, 0.0, flags2, p)
+    ref2 = assembly.assemble(scene, scene.x0, dirichlet=False)
+    assert abs(E2 - ref2["E"]) <= tol * abs(ref2["E"])
+    assert rel(g2.cpu().numpy(), ref2["g"]) < tol
+    assert rel(_bsr(v2), ref2["vals"]) < tol
+    mesh.close()
+
+
+def test_projected_assembly_c1(symx):
+    scene = sg.config_c1()
+    x = scene.x0 + np.random.default_rng(4).uniform(-2e-3, 2e-3, size=scene.x0.shape)
+    x[scene.fixed.astype(bool)] = scene.X[scene.fixed.astype(bool)]
+    mesh = symx.Mesh(scene)
+    xt = elements.x_tilde(scene.x0, scene.v0, 0.01, scene.gravity)
+    flags = (symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+             | symx.SYMX_PROJECT_PSD)
+    E, g, vals = mesh.assemble(x, xt, 0.01, flags, symx.SYMX_F64)
+    ref = assembly.assemble(scene, x, xt, 0.01, project=True)
+    raw = assembly.assemble(scene, x, xt, 0.01, project=False)
+    assert rel(raw["vals"], ref["vals"]) > 1e-6  # projection is not a no-op here
+    assert rel(_bsr(vals), ref["vals"]) < F64_TOL
+    assert rel(g.cpu().numpy(), ref["g"]) < F64_TOL
+    E32, g32, v32 = mesh.assemble(x, xt, 0.01, flags, symx.SYMX_F32)
+    assert rel(_bsr(v32), ref["vals"]) < F32_TOL
+    mesh.close()
+
+
+def test_assembly_bitwise_reproducible(symx):
+    scene = mixed_scene()
+    mesh = symx.Mesh(scene)
+    xt = elements.x_tilde(scene.x0, scene.v0, 0.01, scene.gravity)
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    for p in (symx.SYMX_F64, symx.SYMX_F32):
+        outs = [mesh.assemble(scene.x0, xt, 0.01, flags, p) for _ in range(3)]
+        for E, g, v in outs[1:]:
+            assert E == outs[0][0]
+            assert torch.equal(g, outs[0][1])
+            assert torch.equal(v, outs[0][2])
+    mesh.close()
+
+
+def test_bsr_symmetry_and_matvec(symx):
+    scene = sg.config_c1()
+    mesh = symx.Mesh(scene)
+    xt = elements.x_tilde(scene.x0, scene.v0, 0.01, scene.gravity)
+    flags = symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS
+    _, _, vals = mesh.assemble(scene.x0, xt, 0.01, flags, symx.SYMX_F64)
+    rp, ci, _ = mesh.pattern()
+    A = assembly.to_scipy(rp, ci, _bsr(vals))
+    assert abs(A - A.T).max() <= 1e-12 * abs(A).max()
+    p = np.random.default_rng(1).normal(size=3 * scene.n_nodes)
+    y = A @ p
+    ref = rest.lumped_mass(scene).repeat(3) / 1e-4 * p
+    _, _, He = elements.element_eval(scene.energies[0], scene.x0, scene.X)
+    c = scene.energies[0].conn
+    ye = np.einsum("emn,en->em", He.reshape(-1, 12, 12), p.reshape(-1, 3)[c].reshape(-1, 12))
+    refv = ref.reshape(-1, 3)
+    np.add.at(refv, c.ravel(), ye.reshape(-1, 3))
+    assert rel(y, refv.ravel()) < F64_TOL
+    mesh.close()
+
+
+# ---------------------------------------------------------------------------
+# Newton step
+# ---------------------------------------------------------------------------
+def _newton(symx, scene, precision, **kw):
+    mesh = symx.Mesh(scene)
+    x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    prm = symx.step_params(dt=scene.dt, precision=precision, **kw)
+    st, rep = mesh.newton_step(x, v, prm)
+    mesh.close()
+    return st, rep, x.cpu().numpy(), v.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32r"])
+def test_newton_step_c1(symx, precision):
+    scene = sg.config_c1()
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32_REFINED
+    st, rep, x, v = _newton(symx, scene, p)
+    assert st == 0, (symx.STATUS[st], rep.as_dict())
+    dt = scene.dt
+    xt = elements.x_tilde(scene.x0, scene.v0, dt, scene.gravity)
+    # the oracle's float64 gradient at the device's answer meets the tolerance
+    g = assembly.assemble(scene, x, xt, dt, want_hess=False)["g"]
+    r0 = np.linalg.norm(assembly.assemble(scene, scene.x0, xt, dt, want_hess=False)["g"])
+    assert rep.residual0 == pytest.approx(r0, rel=1e-10)
+    assert np.linalg.norm(g) <= 1.01e-6 * r0
+    assert np.allclose(v, (x - scene.x0) / dt)
+    # same minimiser as the oracle's own Newton step (agreement within the
+    # solver tolerance: |dx| <= |H^-1| |g| with |H^-1| <= dt^2 / m_min)
+    ok, xo, repo = newton.newton_solve(scene, scene.x0, scene.v0, dt, newton.StepParams(dt=dt))
+    assert ok
+    m_min = rest.lumped_mass(scene).min()
+    bound = 2.0e-6 * r0 * dt * dt / m_min
+    assert np.max(np.abs(x - xo)) <= bound
+    assert rep.energy == pytest.approx(repo["energy"], rel=1e-9)
+
+
+def test_newton_step_mixed_f32_refined(symx):
+    scene = mixed_scene()
+    st, rep, x, _ = _newton(symx, scene, symx.SYMX_F32_REFINED)
+    assert st == 0, (symx.STATUS[st], rep.as_dict())
+    xt = elements.x_tilde(scene.x0, scene.v0, scene.dt, scene.gravity)
+    g = assembly.assemble(scene, x, xt, scene.dt, want_hess=False)["g"]
+    assert np.linalg.norm(g) <= 1.01e-6 * rep.residual0
+
+
+def test_newton_rigid_translation_exact(symx):
+    s = sg.tet_cube_scene(3, seed=2, perturb=0.0)
+    s.fixed[:] = 0
+    s.v0 = np.tile(np.array([[0.3, -0.1, 0.2]]), (s.n_nodes, 1))
+    st, rep, x, v = _newton(symx, s, symx.SYMX_F64, gravity=(0.0, 0.0, 0.0))
+    assert st == 0
+    # exact answer X + dt v; Newton stops at |g| <= 1e-6 r0 and H >= M/dt^2 at
+    # rest, so the error is at most dt^2/m_min * 1e-6 r0
+    bound = s.dt ** 2 / rest.lumped_mass(s).min() * 1.01e-6 * rep.residual0
+    assert np.max(np.abs(x - (s.X + s.dt * s.v0))) <= bound
+
+
+def test_nonfinite_input_is_reported(symx):
+    scene = sg.tet_cube_scene(2, seed=1)
+    mesh = symx.Mesh(scene)
+    x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    x[3, 1] = float("nan")
+    v = torch.zeros_like(x)
+    st, rep = mesh.newton_step(x, v, symx.step_params(dt=0.01))
+    assert symx.STATUS[st] == "NONFINITE"
+    # the mesh stays usable afterwards
+    x[3, 1] = float(scene.x0[3, 1])
+    st, rep = mesh.newton_step(x, v, symx.step_params(dt=0.01))
+    assert st == 0
+    mesh.close()
+
+
+def test_forced_failures_halve_dt(symx):
+    scene = sg.tet_cube_scene(2, seed=1)
+    st, rep, x, _ = _newton(symx, scene, symx.SYMX_F64, max_newton=0, max_halvings=3)
+    assert symx.STATUS[st] == "NOT_CONVERGED"
+    assert rep.dt_halvings == 3 and rep.dt_used == pytest.approx(0.01 / 8)
+    assert np.array_equal(x, scene.x0)  # unchanged on failure
+
+
+def test_invalid_mesh_rejected(symx):
+    s = sg.tet_cube_scene(1, seed=1)
+    s.energies[0].conn = s.energies[0].conn.copy()
+    s.energies[0].conn[0, 0] = 999
+    with pytest.raises(symx.SymxError, match="INVALID_ARG"):
+        symx.Mesh(s)
