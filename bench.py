@@ -1,0 +1,294 @@
+#!/usr/bin/env python3
+"""Benchmark of the element-derivative / BSR-assembly / Newton hot path on one GPU.
+
+Workload (default): a 64^3 grid of cubes, 6 Stable Neo-Hookean tets each
+(1,572,864 tets, 274,625 nodes, 4,018,753 3x3 blocks), E = 1e5 Pa, nu = 0.4,
+rho = 1000, bottom face fixed, x(t) = rest, v(t) ~ N(0, 0.1^2) m/s per
+component (seed 2), dt = 0.01 s, gravity -9.81 z; Newton to 1e-6 relative
+residual, block-Jacobi PCG at most 500 iterations.  All inputs are synthetic
+and resident on the GPU before timing starts.
+
+One step = one implicit-Euler time step through the whole path (assembly of
+energy, gradient and BSR Hessian; PCG; float64 refinement; line search;
+update) in the FP32-with-refinement mode.  The JSON line reports
+  value        element evaluation + assembly throughput (Melem/s, FP32, no
+               projection): device time of one full E + gradient + BSR Hessian
+               evaluation, median over repetitions
+  ms_per_step  FP32-refined Newton time step (K timed steps)
+and, beside them, FP64 figures, projection-on figures, the roofline of the
+dominant kernel (live HIP-event timing inside the timed steps) and the FP64
+CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+IDLE_MS = 0.004  # PCG launches shorter than this found the solve converged
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel, N, nnzb, n_elem, t_bytes):
+    """Bytes the method itself must move per launch of a kernel (no staging,
+    no index metadata beyond the matrix structure, gathers counted once)."""
+    if kernel == "pcg_spmv":
+        # values + column index + row pointer; z read; p, q read and written
+        return (9 * t_bytes + 4) * nnzb + 4 * (N + 1) + 5 * 3 * t_bytes * N
+    if kernel == "pcg_update":
+        # Dinv (9), x rw, r rw, z w, p r, q r (3 each)
+        return (9 + 6 + 6 + 3 + 3 + 3) * t_bytes * N
+    if kernel in ("row_assemble_gH", "row_assemble_H"):
+        out = 9 * t_bytes * nnzb + (24 * N if kernel == "row_assemble_gH" else 0)
+        # connectivity, positions and rest positions (float64), masses, x_tilde, flags
+        return 16 * n_elem + 24 * N + 24 * N + 8 * N + 24 * N + N + out
+    if kernel == "row_assemble_g":
+        return 16 * n_elem + 24 * N + 24 * N + 8 * N + 24 * N + N + 24 * N
+    if kernel == "energy":
+        return 16 * n_elem + 24 * N + 24 * N + 8 * N + 24 * N
+    return None
+
+
+def cpu_baseline(seconds_target=10.0):
+    """FP64 numpy oracle: eval + assembly (E, g, BSR) of a 24^3 cube of the same
+    workload recipe, repeated until ~seconds_target of CPU work."""
+    import numpy as np
+
+    import scenegen as sg
+    from oracle import assembly, elements
+    n = 24
+    s = sg.tet_cube_scene(n, h=0.01, seed=2, perturb=0.0, vel_std=0.1)
+    rp, ci = assembly.pattern_fast(s)
+    xt = elements.x_tilde(s.x0, s.v0, 0.01, s.gravity)
+    ne = s.energies[0].conn.shape[0]
+    times = []
+    cpu0 = time.process_time()
+    w0 = time.perf_counter()
+    while sum(times) < seconds_target and len(times) < 8:
+        t = time.perf_counter()
+        assembly.assemble(s, xt, xt, 0.01, row_ptr=rp, col_idx=ci)
+        times.append(time.perf_counter() - t)
+    wall = time.perf_counter() - w0
+    cores = max(1, round((time.process_time() - cpu0) / wall))
+    med = statistics.median(times)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(ne / med / 1e6, 5), "unit": "Melem/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"FP64 numpy oracle, E+g+BSR assembly of a 24^3-cube grid ({ne} tets, "
+                      f"same material/state recipe), median of {len(times)} passes "
+                      f"({sum(times):.1f} s); host {model or platform.processor()}, "
+                      f"{os.cpu_count()} logical CPUs visible"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=64, help="cubes per side")
+    ap.add_argument("--asm-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64-newton", action="store_true")
+    ap.add_argument("--no-projection", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} / WORLD_SIZE {world} "
+              "is not supported (the multi-GPU sharding is a design note, not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenegen as sg
+    from paper_2303_02156_amd import symx
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    symx.load()
+    scene = sg.config_c2(args.n)
+    n_elem = scene.n_elements()
+    log(f"scene {scene.name}: {scene.n_nodes} nodes, {n_elem} tets")
+    t = time.perf_counter()
+    mesh = symx.Mesh(scene)
+    setup_s = time.perf_counter() - t
+    N, nnzb = mesh.info.n_nodes, mesh.info.nnzb
+    log(f"mesh setup {setup_s:.2f} s, nnzb {nnzb}, batches {mesh.info.n_batches}")
+    dt = scene.dt
+    xt_np = scene.x0 + dt * scene.v0 + dt * dt * np.asarray(scene.gravity)[None, :]
+    x0 = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v0 = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    xt = torch.tensor(xt_np, dtype=torch.float64, device="cuda")
+    g = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+
+    # ---- element evaluation + assembly throughput --------------------------
+    def time_assembly(precision, fl, reps):
+        for _ in range(3):
+            mesh.assemble(x0, xt, dt, fl, precision, grad_out=g)
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            symx.symx_assemble_bsr(mesh.handle, x0.data_ptr(), xt.data_ptr(), dt, fl, precision,
+                                   g.data_ptr())
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        return statistics.median(ms)
+
+    melem = {}
+    asm_ms = {}
+    for name, prec in (("f32", symx.SYMX_F32), ("f64", symx.SYMX_F64)):
+        m = time_assembly(prec, flags, args.asm_reps)
+        asm_ms[name] = m
+        melem[name] = n_elem / (m * 1e-3) / 1e6
+        log(f"eval+assembly {name}: {m:.3f} ms -> {melem[name]:.1f} Melem/s")
+    if not args.no_projection:
+        for name, prec in (("f32_project", symx.SYMX_F32), ("f64_project", symx.SYMX_F64)):
+            m = time_assembly(prec, flags | symx.SYMX_PROJECT_PSD, 3)
+            asm_ms[name] = m
+            melem[name] = n_elem / (m * 1e-3) / 1e6
+            log(f"eval+assembly {name}: {m:.3f} ms -> {melem[name]:.2f} Melem/s")
+    # per-kernel split of one FP32 assembly
+    mesh.profile(True)
+    mesh.assemble(x0, xt, dt, flags, symx.SYMX_F32, grad_out=g)
+    asm_kernels = mesh.kernel_times()
+    mesh.profile(False)
+
+    # ---- Newton time steps -----------------------------------------------------
+    def run_steps(precision, K, W, profile):
+        x = x0.clone()
+        v = v0.clone()
+        prm = symx.step_params(dt=dt, precision=precision, max_pcg=500)
+        for k in range(W):
+            st, rep = mesh.newton_step(x, v, prm)
+            log(f"warmup step {k}: status {symx.STATUS[st]} newton {rep.newton_iters} "
+                f"pcg {rep.pcg_iters} {rep.ms_total:.1f} ms")
+        if profile:
+            mesh.profile(True)
+        reps = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            st, rep = mesh.newton_step(x, v, prm)
+            reps.append(rep.as_dict())
+            log(f"step {k}: status {symx.STATUS[st]} newton {rep.newton_iters} pcg "
+                f"{rep.pcg_iters} refine {rep.refinements} halvings {rep.dt_halvings} "
+                f"res {rep.residual:.3e}/{rep.residual0:.3e} {rep.ms_total:.1f} ms")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kt = None
+        if profile:
+            # launches enqueued past PCG convergence only test a flag (< 4 us)
+            kt = {"busy": mesh.kernel_times(min_ms=IDLE_MS), "all": mesh.kernel_times()}
+            mesh.profile(False)
+        return wall * 1e3 / K, reps, kt
+
+    ms_f32r, reps_f32r, ktimes = run_steps(symx.SYMX_F32_REFINED, args.steps, args.warmup, True)
+    log(f"newton f32_refined: {ms_f32r:.2f} ms/step")
+    ms_f64, reps_f64 = None, None
+    if not args.no_f64_newton:
+        ms_f64, reps_f64, _ = run_steps(symx.SYMX_F64, args.steps, args.warmup, False)
+        log(f"newton f64: {ms_f64:.2f} ms/step")
+
+    # ---- roofline of the dominant kernel (live HIP-event timing) --------------
+    busy, allk = ktimes["busy"], ktimes["all"]
+    kname, (launches, total_ms) = max(busy.items(), key=lambda kv: kv[1][1])
+    avg_ms = total_ms / max(launches, 1)
+    t_bytes = 4
+    nbytes = algorithmic_bytes(kname, N, nnzb, n_elem, t_bytes)
+    roofline = {"kernel": kname, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None, "traffic": None, "launches": launches,
+                "avg_ms": round(avg_ms, 5), "algorithmic_bytes": nbytes,
+                "idle_launches": allk[kname][0] - launches,
+                "idle_ms": round(allk[kname][1] - total_ms, 3),
+                "share_of_step_time": round(allk[kname][1] / (ms_f32r * args.steps), 4)}
+    if nbytes:
+        ach = nbytes / (avg_ms * 1e-3) / 1e9
+        roofline["achieved"] = round(ach, 1)
+        roofline["frac"] = round(ach / HBM_PEAK_GBS, 4)
+    kernels = {}
+    for k, (n, ms) in sorted(allk.items(), key=lambda kv: -kv[1][1]):
+        nb_, msb = busy.get(k, (0, 0.0))
+        d = {"launches": n, "total_ms": round(ms, 3), "busy_launches": nb_,
+             "busy_avg_ms": round(msb / max(nb_, 1), 5)}
+        b_ = algorithmic_bytes(k, N, nnzb, n_elem, t_bytes)
+        if b_ and nb_:
+            d["busy_gbs"] = round(b_ / (msb / nb_ * 1e-3) / 1e9, 1)
+        kernels[k] = d
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle)...")
+        cpu = cpu_baseline()
+        log(f"cpu baseline {cpu['value']} Melem/s")
+
+    def summary(reps):
+        if not reps:
+            return None
+        return {"newton_iters": sum(r["newton_iters"] for r in reps),
+                "pcg_iters": sum(r["pcg_iters"] for r in reps),
+                "refinements": sum(r["refinements"] for r in reps),
+                "dt_halvings": sum(r["dt_halvings"] for r in reps),
+                "all_converged": all(r["status"] == 0 for r in reps),
+                "max_rel_residual": max(r["residual"] / max(r["residual0"], 1e-300) for r in reps)}
+
+    out = {
+        "metric": "elem eval+assembly Melem/s, Newton step ms FP32-refined vs FP64; p99 latency",
+        "value": round(melem["f32"], 2),
+        "unit": "Melem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_f32r, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"C2: {args.n}^3-cube grid x 6 Stable Neo-Hookean tets "
+                               f"({n_elem} tets, {N} nodes, {nnzb} 3x3 blocks), E=1e5 nu=0.4, "
+                               "v~N(0,0.1) seed 2, dt=0.01, Newton rtol 1e-6, PCG<=500",
+                   "precision": "FP32 element kernels/SpMV/PCG, FP64 energies, gradient, "
+                                "residual and refinement"},
+        "melem_per_s": {k: round(v, 3) for k, v in melem.items()},
+        "assembly_ms": {k: round(v, 4) for k, v in asm_ms.items()},
+        "assembly_kernels_f32": {k: {"launches": n, "ms": round(ms, 4)}
+                                 for k, (n, ms) in asm_kernels.items()},
+        "newton_step_ms": {"f32_refined": round(ms_f32r, 3),
+                           "f64": None if ms_f64 is None else round(ms_f64, 3)},
+        "newton_f32_refined": summary(reps_f32r),
+        "newton_f64": summary(reps_f64),
+        "p99_latency_ms": None,
+        "mesh_setup_s": round(setup_s, 3),
+        "kernels_f32_refined_steps": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    mesh.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -204,6 +204,22 @@ symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double*
 symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
                              const symx_step_params* params, symx_step_report* report);
 
+/* Kernel timing for measurement: with profiling on, every kernel launch of
+ * the mesh carries start/stop HIP events on the mesh's stream
+ * (hipExtLaunchKernelGGL), which time the kernel itself.  set_profiling
+ * resets all counters.  get_kernel_time returns the number of launches of one
+ * kernel whose device time was at least min_ms, and their summed time (PCG
+ * kernels enqueued past convergence only check a flag and return; a small
+ * min_ms separates them).  kernel_names writes the known names, comma
+ * separated, into buf (host, buf_len bytes).  Names: row_assemble_gH,
+ * row_assemble_H, row_assemble_g, energy, reduce, elem_eval, project_psd,
+ * diag_inverse, pcg_init, pcg_spmv, pcg_update, residual64, dot64, x_tilde,
+ * axpy64, lincomb64, velocity, check_finite, accumulate. */
+symx_status symx_mesh_set_profiling(symx_mesh mesh, int32_t enable);
+symx_status symx_mesh_get_kernel_time(symx_mesh mesh, const char* name, double min_ms,
+                                      int64_t* launches, double* total_ms);
+symx_status symx_mesh_kernel_names(symx_mesh mesh, char* buf, int64_t buf_len);
+
 const char* symx_status_string(symx_status status);
 const char* symx_last_error(void);
 

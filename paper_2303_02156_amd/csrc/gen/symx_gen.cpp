@@ -167,6 +167,13 @@ void generate(const EnergySpec& spec, Generated& out) {
     for (int l = 0; l < n_dof; ++l) row0_gH.push_back(hess[i * n_dof + l]);
   add_fn("_row0_g", g.substitute(row0_g, zero));
   add_fn("_row0_gH", g.substitute(row0_gH, zero));
+  // gradient of node 0 and the off-diagonal blocks of its Hessian row; the
+  // diagonal block follows from translation invariance (each Hessian row sums
+  // to zero over the nodes), so the kernel forms it as minus their sum
+  std::vector<int> row0_gHoff = row0_g;
+  for (int i = 0; i < 3; ++i)
+    for (int l = 3; l < n_dof; ++l) row0_gHoff.push_back(hess[i * n_dof + l]);
+  add_fn("_row0_gHoff", g.substitute(row0_gHoff, zero));
 
   for (const Function& f : fns) {
     Census ch, cc;

@@ -37,9 +37,10 @@ void mesh_free(Mesh* m) {
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   else (void)hipDeviceSynchronize();
   free_workspace(*m);
+  m->prof.destroy();
   void* dev[] = {m->X, m->mass, m->fixed, m->row_ptr, m->col_idx, m->diag_pos, m->inc_ptr,
-                 m->inc_code, m->inc_slots, m->batch_row, m->vals32, m->vals64, m->elem_H,
-                 m->partials, m->scalars, m->counters, m->nonfinite};
+                 m->inc_code, m->inc_slots, m->batch_row, m->blk_info, m->centry, m->batch_entry, m->vals32, m->vals64, m->elem_H,
+                 m->partials, m->scalars};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   for (SetHost& s : m->sets) {
@@ -237,6 +238,53 @@ symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
     return SYMX_ERR_INVALID_ARG;
   }
   return newton_step(*mesh->m, x_dev, v_dev, *params, report);
+  GUARD_END
+}
+
+symx_status symx_mesh_set_profiling(symx_mesh mesh, int32_t enable) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
+  Mesh& m = *mesh->m;
+  m.prof.reset();
+  m.prof.on = enable != 0;
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_mesh_get_kernel_time(symx_mesh mesh, const char* name, double min_ms,
+                                      int64_t* launches, double* total_ms) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh) || !name || !launches || !total_ms) return SYMX_ERR_INVALID_ARG;
+  Mesh& m = *mesh->m;
+  m.prof.resolve();
+  *launches = 0;
+  *total_ms = 0.0;
+  for (size_t i = 0; i < m.prof.names.size(); ++i)
+    if (m.prof.names[i] == name)
+      for (float t : m.prof.dur[i])
+        if (t >= min_ms) {
+          *launches += 1;
+          *total_ms += t;
+        }
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_mesh_kernel_names(symx_mesh mesh, char* buf, int64_t buf_len) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh) || !buf || buf_len < 1) return SYMX_ERR_INVALID_ARG;
+  Mesh& m = *mesh->m;
+  std::string all;
+  for (size_t i = 0; i < m.prof.names.size(); ++i) {
+    if (i) all += ",";
+    all += m.prof.names[i];
+  }
+  if ((int64_t)all.size() + 1 > buf_len) {
+    set_error("buffer too small for kernel names");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  std::memcpy(buf, all.c_str(), all.size() + 1);
+  return SYMX_OK;
   GUARD_END
 }
 

@@ -67,6 +67,25 @@ struct SetHost {
 
 struct Workspace;  // Newton / PCG buffers (symx_newton.cpp)
 
+// Optional per-kernel timing: HIP events recorded around every launch on the
+// mesh's stream, resolved lazily.
+struct Profiler {
+  bool on = false;
+  std::vector<std::string> names;
+  std::vector<std::vector<float>> dur;  // per name: device time of each launch (ms)
+  struct Pending {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int id_of(const char* name);
+  hipEvent_t take();
+  void resolve();
+  void reset();
+  void destroy();
+};
+
 struct Mesh {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -93,6 +112,9 @@ struct Mesh {
   uint32_t* inc_code = nullptr;     // n_inc
   uint32_t* inc_slots = nullptr;    // n_inc: 4 x uint8 slots (relabelled order)
   int* batch_row = nullptr;         // n_batch+1
+  uint32_t* blk_info = nullptr;     // nnzb: off-diagonal contribution list (start << 8 | count)
+  uint16_t* centry = nullptr;       // contribution entries (incidence << 2 | node)
+  int* batch_entry = nullptr;       // n_batch+1: first entry of each batch
   float* vals32 = nullptr;          // 9*nnzb, component-major
   double* vals64 = nullptr;
   // per-element scratch for the projected path (largest set)
@@ -102,18 +124,27 @@ struct Mesh {
   // reductions
   double* partials = nullptr;       // kMaxPartials
   double* scalars = nullptr;        // small device scalars
-  unsigned* counters = nullptr;
   double* pinned = nullptr;         // host pinned scalars
-  int* nonfinite = nullptr;         // device flag
+  int* nonfinite = nullptr;         // device flag (inside `scalars`)
   Workspace* ws = nullptr;
   // dt control
   double dt_cur = 0.0, dt_nominal = 0.0;
   int successes = 0;
+  int last_pcg_iters = 0;
+  Profiler prof;
 
   SetsDev sets_dev() const;
 };
 
 constexpr int kMaxPartials = 1 << 16;
+
+// Event pair for one profiled launch (null events when profiling is off).
+struct ProfPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  int id = -1;
+};
+ProfPair prof_begin(Mesh& m, const char* name);
+void prof_end(Mesh& m, const ProfPair& p);
 
 // ---------------------------------------------------------------------------
 // kernel launchers (symx_kernels.hip)
@@ -165,7 +196,7 @@ struct PcgBuffers {
 symx_status launch_diag_inverse(Mesh& m, int precision, void* Dinv);
 symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const double* b,
                             double tol2, int max_iter);
-symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int n_iter);
+symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0, int n_iter);
 symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs);
 symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b, double* r);
 

@@ -6,6 +6,7 @@
 // fixed order (per-workgroup trees plus a final pass by the last workgroup in
 // a fixed order), so all results are bitwise reproducible from run to run; no
 // floating-point atomics are used anywhere.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -15,6 +16,19 @@
 #include "symx_internal.h"
 
 namespace symxi {
+
+// Launch on the mesh's stream; with profiling on, the launch carries start
+// and stop events (hipExtLaunchKernelGGL), which time the kernel itself.
+#define SYMX_LAUNCH(m, name, kernel, grid, block, shmem, ...)                                 \
+  do {                                                                                        \
+    const ProfPair pp_ = prof_begin((m), (name));                                             \
+    if (pp_.a)                                                                                \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, (m).stream, pp_.a, pp_.b, 0,          \
+                            __VA_ARGS__);                                                     \
+    else                                                                                      \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, (m).stream, __VA_ARGS__);                \
+    prof_end((m), pp_);                                                                       \
+  } while (0)
 
 // ---------------------------------------------------------------------------
 // common helpers
@@ -40,45 +54,24 @@ __device__ __forceinline__ const float* prm_ptr<float>(const SetDev& S) { return
 template <>
 __device__ __forceinline__ const double* prm_ptr<double>(const SetDev& S) { return S.prm64; }
 
-// Deterministic block sum of one double per thread (blockDim = 256).
+// Deterministic block sum of one double per thread (blockDim = 256): a fixed
+// butterfly inside each 64-lane wave, then the four wave sums in order.
 __device__ double block_sum_256(double v, double* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
 #pragma unroll
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) sh[t] += sh[t + s];
-    __syncthreads();
-  }
-  double r = sh[0];
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  const int w = threadIdx.x >> 6;
   __syncthreads();
-  return r;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
-__device__ __forceinline__ double load_coherent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Returns true in exactly one workgroup: the last one to finish.  The caller
-// has written its partial result before calling.  The counter is reset by the
-// last workgroup so the next launch can reuse it.
-__device__ bool last_block(unsigned* counter) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == gridDim.x - 1);
-    if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  return last != 0;
-}
-
-// Sum partials[0..n) in a fixed order (called by one full workgroup of 256).
-__device__ double sum_partials(const double* partials, int n, double* sh) {
+// Sum partials[0..n) written by an earlier kernel, in a fixed order; every
+// workgroup that calls it gets the same value.  Visibility comes from the
+// kernel boundary, so no fences or atomics are needed.
+__device__ double sum_partials(const double* __restrict__ partials, int n, double* sh) {
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += load_coherent(partials + i);
+  for (int i = threadIdx.x; i < n; i += 256) acc += partials[i];
   return block_sum_256(acc, sh);
 }
 
@@ -226,12 +219,6 @@ __global__ __launch_bounds__(256) void k_energy_inertia(int64_t N, const double*
   }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_to_scalar(const double* __restrict__ partials, int n,
-                                                          double* __restrict__ out) {
-  __shared__ double sh[256];
-  double s = sum_partials(partials, n, sh);
-  if (threadIdx.x == 0) *out = s;
-}
 
 // ---------------------------------------------------------------------------
 // per-element E / gradient / Hessian (low-level element interface)
@@ -400,6 +387,9 @@ struct RowArgs {
   const int* inc_ptr;
   const uint32_t* inc_code;
   const uint32_t* inc_slots;
+  const uint32_t* blk_info;
+  const uint16_t* centry;
+  const int* batch_entry;
   int64_t nnzb;
   T* vals;               // component-major 9 x nnzb
   double* g;             // N x 3
@@ -556,6 +546,150 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble(RowArgs<T> A) {
   }
 }
 
+// Off-diagonal part of one incidence's Hessian block row (recompute path):
+// out[0..2] gradient of node a, out[3 + 9 i + 3 (b-1) + k] entry (a_i, node b
+// of the relabelled order, coord k) for b = 1, 2, 3.
+template <typename T>
+__device__ __forceinline__ void incidence_row_off(const RowArgs<T>& A, uint32_t code, T* out) {
+  const int si = inc_set(code);
+  const int a = inc_local(code);
+  const int64_t e = inc_elem(code);
+  const SetDev& S = A.sets.s[si];
+  const Relabel R = relabel(S.conn[e], a);
+  T in[26];
+  if (S.kind == SYMX_SNH_TET4) {
+    fill_solid<T, 4>(S, e, R, A.x, A.X, in);
+    snh_tet4_row0_gHoff<T>(in, out);
+  } else if (S.kind == SYMX_HINGE4) {
+    fill_hinge<T>(S, e, R, A.x, in);
+    hinge4_row0_gHoff<T>(in, out);
+  } else {
+    fill_solid<T, 3>(S, e, R, A.x, A.X, in);
+    T o[21];
+    stvk_tri3_row0_gHoff<T>(in, o);
+    out[0] = o[0];
+    out[1] = o[1];
+    out[2] = o[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) out[3 + 9 * i + v] = o[3 + 6 * i + v];
+#pragma unroll
+      for (int v = 6; v < 9; ++v) out[3 + 9 * i + v] = T(0);
+    }
+  }
+}
+
+// Row assembly for translation-invariant element energies (all three kinds:
+// each element Hessian row sums to zero over the nodes).  Phase 1: one lane
+// per incidence evaluates the gradient and the off-diagonal blocks of its
+// Hessian row into LDS.  Phase 2: one lane per off-diagonal block sums its
+// precomputed contribution list in incidence order; one lane per row sums the
+// gradient.  Phase 3: the elastic diagonal block is minus the sum of the row's
+// off-diagonal blocks (taken in slot order); inertia and Dirichlet are
+// applied and every block is written once.
+template <typename T, bool WANT_G>
+__global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
+  constexpr int NV = 30;
+  __shared__ T st[NV][kRowWG];
+  __shared__ int s_blk[kRowWG + 1];
+  __shared__ int s_inc[kRowWG + 1];
+  const int t = threadIdx.x;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int r0 = A.batch_row[b], r1 = A.batch_row[b + 1];
+  const int nrows = r1 - r0;
+  const int q0 = A.inc_ptr[r0];
+  const int p0 = A.row_ptr[r0];
+  for (int r = t; r <= nrows; r += kRowWG) {
+    s_blk[r] = A.row_ptr[r0 + r] - p0;
+    s_inc[r] = A.inc_ptr[r0 + r] - q0;
+  }
+  __syncthreads();
+  const int nq = s_inc[nrows];
+  const int np = s_blk[nrows];
+  if (t < nq) {
+    T out[NV];
+    incidence_row_off<T>(A, A.inc_code[q0 + t], out);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) st[v][t] = out[v];
+  }
+  __syncthreads();
+  // phase 2: off-diagonal blocks from their contribution lists
+  int r = 0, col = 0;
+  bool diag = false;
+  T acc[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = T(0);
+  if (t < np) {
+    while (s_blk[r + 1] <= t) ++r;
+    col = A.col_idx[p0 + t];
+    diag = (col == r0 + r);
+    const uint32_t info = A.blk_info[p0 + t];
+    const uint16_t* ce = A.centry + A.batch_entry[b] + (info >> 8);
+    const int cnt = int(info & 0xFFu);
+    for (int j = 0; j < cnt; ++j) {
+      const uint32_t w = ce[j];
+      const int q = int(w >> 2);
+      const int bb = int(w & 3u) - 1;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += st[3 + 9 * i + 3 * bb + kk][q];
+    }
+  }
+  if (WANT_G && t < nrows) {
+    const int row = r0 + t;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int q = s_inc[t]; q < s_inc[t + 1]; ++q) {
+      g0 += double(st[0][q]);
+      g1 += double(st[1][q]);
+      g2 += double(st[2][q]);
+    }
+    if (A.xt) {
+      const double w = A.mass[row] * A.inv_dt2;
+      g0 += w * (A.x[3 * row + 0] - A.xt[3 * row + 0]);
+      g1 += w * (A.x[3 * row + 1] - A.xt[3 * row + 1]);
+      g2 += w * (A.x[3 * row + 2] - A.xt[3 * row + 2]);
+    }
+    if (A.fixed && A.fixed[row]) g0 = g1 = g2 = 0.0;
+    if (!(isfinite(g0) && isfinite(g1) && isfinite(g2))) *A.nonfinite = 1;
+    A.g[3 * row + 0] = g0;
+    A.g[3 * row + 1] = g1;
+    A.g[3 * row + 2] = g2;
+  }
+  __syncthreads();
+  // phase 3: publish the off-diagonal blocks, then form the diagonal ones
+  if (t < np) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) st[c][t] = acc[c];
+  }
+  __syncthreads();
+  if (t < np) {
+    const int row = r0 + r;
+    if (diag) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] = T(0);
+      for (int s = s_blk[r]; s < s_blk[r + 1]; ++s) {
+        if (s == t) continue;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c] -= st[c][s];
+      }
+      if (A.xt) {
+        const T w = T(A.mass[row] * A.inv_dt2);
+        acc[0] += w;
+        acc[4] += w;
+        acc[8] += w;
+      }
+    }
+    if (A.fixed && (A.fixed[row] | A.fixed[col])) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] = (diag && (c % 4) == 0) ? T(1) : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A.vals[(int64_t)c * A.nnzb + p0 + t] = acc[c];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // solver kernels
 // ---------------------------------------------------------------------------
@@ -639,25 +773,27 @@ __global__ __launch_bounds__(256) void k_residual64(int64_t N, const int* __rest
   }
 }
 
-// PCG scalars (device array of doubles) and flags
-enum { S_RZ = 0, S_RZ_OLD, S_PQ, S_RR, S_BB, S_ALPHA, S_BETA, S_TOL2, S_DONE, S_ITERS, S_MAXIT,
-       S_NSCALARS };
-// counters: 0 init, 1 spmv, 2 update, 3 dot, 4 energy
+// PCG state.  Partial sums (one per workgroup, kPcgG workgroups) are written
+// by one kernel and reduced, redundantly and in the same order, by every
+// workgroup of the next kernel.  Scalars live in a small device array; rz of
+// iteration k is kept in slot S_RZ + (k & 1) so that readers of the previous
+// value never race with the writer of the new one.
+constexpr int kPcgG = 1024;
+enum { S_DONE = 0, S_ITERS, S_TOL2, S_BB, S_RZ, S_RZ1, S_MAXIT, S_NSCALARS };
+enum { P_RZ = 0, P_RR = 1, P_BB = 2, P_PQ = 3 };  // partial arrays, kPcgG each
 
-// r = b, z = M^-1 r, x = p = q = 0; rz, rr, bb
+// r = b, z = M^-1 r, x = p = q = 0; partials of rz, rr, bb
 template <typename T, typename TB>
 __global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restrict__ b,
                                                   const T* __restrict__ Dinv, T* __restrict__ xs,
                                                   T* __restrict__ r, T* __restrict__ z,
                                                   T* __restrict__ p, T* __restrict__ q,
-                                                  double* __restrict__ partials,
-                                                  double* __restrict__ S, unsigned* counter,
+                                                  double* __restrict__ P, double* __restrict__ S,
                                                   double tol2, int max_iter) {
-  __shared__ double sh[256];
-  const int G = gridDim.x;
+  __shared__ double sh[4];
   double rz = 0.0, rr = 0.0, bb = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)G * 256) {
-    T rv[3], zv[3];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    T rv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       rv[c] = T(b[3 * i + c]);
@@ -665,58 +801,66 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restric
       xs[3 * i + c] = T(0);
       p[3 * i + c] = T(0);
       q[3 * i + c] = T(0);
+      const double bc = double(b[3 * i + c]);
+      bb += bc * bc;
+      rr += double(rv[c]) * double(rv[c]);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      zv[c] = Dinv[9 * i + 3 * c] * rv[0] + Dinv[9 * i + 3 * c + 1] * rv[1] + Dinv[9 * i + 3 * c + 2] * rv[2];
-      z[3 * i + c] = zv[c];
-      rz += double(rv[c]) * double(zv[c]);
-      rr += double(rv[c]) * double(rv[c]);
-      double bc = double(b[3 * i + c]);
-      bb += bc * bc;
+      const T zc = Dinv[9 * i + 3 * c] * rv[0] + Dinv[9 * i + 3 * c + 1] * rv[1] +
+                   Dinv[9 * i + 3 * c + 2] * rv[2];
+      z[3 * i + c] = zc;
+      rz += double(rv[c]) * double(zc);
     }
   }
-  double s0 = block_sum_256(rz, sh);
-  double s1 = block_sum_256(rr, sh);
-  double s2 = block_sum_256(bb, sh);
+  const double s0 = block_sum_256(rz, sh);
+  const double s1 = block_sum_256(rr, sh);
+  const double s2 = block_sum_256(bb, sh);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = s0;
-    partials[G + blockIdx.x] = s1;
-    partials[2 * G + blockIdx.x] = s2;
-  }
-  if (last_block(counter)) {
-    double a0 = sum_partials(partials, G, sh);
-    double a1 = sum_partials(partials + G, G, sh);
-    double a2 = sum_partials(partials + 2 * G, G, sh);
-    if (threadIdx.x == 0) {
-      S[S_RZ] = a0;
-      S[S_RR] = a1;
-      S[S_BB] = a2;
-      S[S_BETA] = 0.0;
-      S[S_TOL2] = tol2;
+    P[P_RZ * kPcgG + blockIdx.x] = s0;
+    P[P_RR * kPcgG + blockIdx.x] = s1;
+    P[P_BB * kPcgG + blockIdx.x] = s2;
+    if (blockIdx.x == 0) {
+      S[S_DONE] = 0.0;
       S[S_ITERS] = 0.0;
+      S[S_TOL2] = tol2;
       S[S_MAXIT] = double(max_iter);
-      S[S_DONE] = (a2 == 0.0 || a1 <= tol2 * a2) ? 1.0 : 0.0;
     }
   }
 }
 
-// w = A z; p = z + beta p; q = w + beta q; partial p.q -> alpha = rz / pq
+// Iteration k: reduce rz, rr of the previous update; stop on convergence or
+// at the iteration limit; beta = rz_k / rz_(k-1); w = A z; p = z + beta p;
+// q = w + beta q; partials of p.q.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pcg_spmv(int64_t N, const int* __restrict__ row_ptr,
+__global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* __restrict__ row_ptr,
                                                   const int* __restrict__ col,
                                                   const T* __restrict__ vals, int64_t nnzb,
                                                   const T* __restrict__ z, T* __restrict__ p,
-                                                  T* __restrict__ q, double* __restrict__ partials,
-                                                  double* __restrict__ S, unsigned* counter) {
+                                                  T* __restrict__ q, double* __restrict__ P,
+                                                  double* __restrict__ S) {
   if (S[S_DONE] != 0.0) return;
-  __shared__ double sh[256];
-  const int G = gridDim.x;
-  const T beta = T(S[S_BETA]);
+  __shared__ double sh[4];
+  const double rz = sum_partials(P + P_RZ * kPcgG, kPcgG, sh);
+  const double rr = sum_partials(P + P_RR * kPcgG, kPcgG, sh);
+  const double bb = k == 0 ? sum_partials(P + P_BB * kPcgG, kPcgG, sh) : S[S_BB];
+  const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+  if (bb == 0.0 || rr <= S[S_TOL2] * bb || k >= int(S[S_MAXIT]) || !isfinite(rr)) {
+    if (first) {
+      S[S_DONE] = isfinite(rr) ? 1.0 : 3.0;
+      S[S_ITERS] = double(k);
+    }
+    return;
+  }
+  const T beta = k == 0 ? T(0) : T(rz / S[S_RZ + ((k - 1) & 1)]);
+  if (first) {
+    S[S_RZ + (k & 1)] = rz;
+    if (k == 0) S[S_BB] = bb;
+  }
   const int lane = threadIdx.x & 15;
   double pq = 0.0;
   for (int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4; row < N;
-       row += ((int64_t)G * 256) >> 4) {
+       row += ((int64_t)gridDim.x * 256) >> 4) {
     T acc[3];
     spmv_row<T, T, T>((int)row, lane, row_ptr, col, vals, nnzb, z, acc);
     if (lane == 0) {
@@ -730,89 +874,75 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int64_t N, const int* __restri
       }
     }
   }
-  double s = block_sum_256(pq, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (last_block(counter)) {
-    double tot = sum_partials(partials, G, sh);
-    if (threadIdx.x == 0) {
-      S[S_PQ] = tot;
-      if (!(tot > 0.0)) {
-        S[S_ALPHA] = 0.0;
-        S[S_DONE] = 2.0;  // breakdown: direction of non-positive curvature
-      } else {
-        S[S_ALPHA] = S[S_RZ] / tot;
-      }
-    }
-  }
+  const double s = block_sum_256(pq, sh);
+  if (threadIdx.x == 0) P[P_PQ * kPcgG + blockIdx.x] = s;
 }
 
-// x += alpha p; r -= alpha q; z = M^-1 r; rz, rr -> beta, convergence
+// Iteration k: alpha = rz_k / p.q; x += alpha p; r -= alpha q; z = M^-1 r;
+// partials of rz, rr.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pcg_update(int64_t N, const T* __restrict__ Dinv,
+__global__ __launch_bounds__(256) void k_pcg_update(int k, int64_t N, const T* __restrict__ Dinv,
                                                     T* __restrict__ xs, T* __restrict__ r,
                                                     T* __restrict__ z, const T* __restrict__ p,
                                                     const T* __restrict__ q,
-                                                    double* __restrict__ partials,
-                                                    double* __restrict__ S, unsigned* counter) {
+                                                    double* __restrict__ P,
+                                                    double* __restrict__ S) {
   if (S[S_DONE] != 0.0) return;
-  __shared__ double sh[256];
-  const int G = gridDim.x;
-  const T alpha = T(S[S_ALPHA]);
+  __shared__ double sh[4];
+  const double pq = sum_partials(P + P_PQ * kPcgG, kPcgG, sh);
+  if (!(pq > 0.0)) {  // direction of non-positive curvature: stop
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      S[S_DONE] = 2.0;
+      S[S_ITERS] = double(k);
+    }
+    return;
+  }
+  const T alpha = T(S[S_RZ + (k & 1)] / pq);
   double rz = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)G * 256) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
     T rv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       xs[3 * i + c] += alpha * p[3 * i + c];
       rv[c] = r[3 * i + c] - alpha * q[3 * i + c];
       r[3 * i + c] = rv[c];
+      rr += double(rv[c]) * double(rv[c]);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T zc = Dinv[9 * i + 3 * c] * rv[0] + Dinv[9 * i + 3 * c + 1] * rv[1] + Dinv[9 * i + 3 * c + 2] * rv[2];
+      const T zc = Dinv[9 * i + 3 * c] * rv[0] + Dinv[9 * i + 3 * c + 1] * rv[1] +
+                   Dinv[9 * i + 3 * c + 2] * rv[2];
       z[3 * i + c] = zc;
       rz += double(rv[c]) * double(zc);
-      rr += double(rv[c]) * double(rv[c]);
     }
   }
-  double s0 = block_sum_256(rz, sh);
-  double s1 = block_sum_256(rr, sh);
+  const double s0 = block_sum_256(rz, sh);
+  const double s1 = block_sum_256(rr, sh);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = s0;
-    partials[G + blockIdx.x] = s1;
-  }
-  if (last_block(counter)) {
-    double a0 = sum_partials(partials, G, sh);
-    double a1 = sum_partials(partials + G, G, sh);
-    if (threadIdx.x == 0) {
-      S[S_RZ_OLD] = S[S_RZ];
-      S[S_RZ] = a0;
-      S[S_RR] = a1;
-      S[S_BETA] = (S[S_RZ_OLD] != 0.0) ? a0 / S[S_RZ_OLD] : 0.0;
-      S[S_ITERS] += 1.0;
-      if (a1 <= S[S_TOL2] * S[S_BB] || S[S_ITERS] >= S[S_MAXIT]) S[S_DONE] = 1.0;
-    }
+    P[P_RZ * kPcgG + blockIdx.x] = s0;
+    P[P_RR * kPcgG + blockIdx.x] = s1;
   }
 }
 
 __global__ __launch_bounds__(256) void k_dot64(int64_t n, const double* __restrict__ a,
                                                const double* __restrict__ b,
-                                               double* __restrict__ partials,
-                                               double* __restrict__ out, unsigned* counter,
-                                               int* nonfinite) {
-  __shared__ double sh[256];
-  const int G = gridDim.x;
+                                               double* __restrict__ partials) {
+  __shared__ double sh[4];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)G * 256)
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     acc += a[i] * b[i];
-  double s = block_sum_256(acc, sh);
+  const double s = block_sum_256(acc, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (last_block(counter)) {
-    double tot = sum_partials(partials, G, sh);
-    if (threadIdx.x == 0) {
-      *out = tot;
-      if (!isfinite(tot)) *nonfinite = 1;
-    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_checked(const double* __restrict__ partials, int n,
+                                                        double* __restrict__ out,
+                                                        int* __restrict__ nonfinite) {
+  __shared__ double sh[4];
+  const double s = sum_partials(partials, n, sh);
+  if (threadIdx.x == 0) {
+    *out = s;
+    if (!isfinite(s)) *nonfinite = 1;
   }
 }
 
@@ -885,48 +1015,51 @@ static int grid_for(int64_t work, int per_block, int cap = 16384) {
 
 symx_status launch_energy(Mesh& m, const double* x, const double* xt, double dt, int precision,
                           double* E_dev) {
+  const char* PNAME = "energy";
   const SetsDev sd = m.sets_dev();
   int off = 0;
   for (int s = 0; s < sd.n; ++s) {
     const int G = grid_for(sd.s[s].n_elem, 256, 8192);
     if (precision == SYMX_F32)
-      hipLaunchKernelGGL(k_energy_set<float>, dim3(G), dim3(256), 0, m.stream, sd.s[s], x, m.X,
+      SYMX_LAUNCH(m, PNAME, k_energy_set<float>, dim3(G), dim3(256), 0, sd.s[s], x, m.X,
                          m.partials + off, m.nonfinite);
     else
-      hipLaunchKernelGGL(k_energy_set<double>, dim3(G), dim3(256), 0, m.stream, sd.s[s], x, m.X,
+      SYMX_LAUNCH(m, PNAME, k_energy_set<double>, dim3(G), dim3(256), 0, sd.s[s], x, m.X,
                          m.partials + off, m.nonfinite);
     LAUNCH_CHECK("k_energy_set");
     off += G;
   }
   if (xt) {
     const int G = grid_for(m.N, 256, 8192);
-    hipLaunchKernelGGL(k_energy_inertia, dim3(G), dim3(256), 0, m.stream, m.N, x, xt, m.mass, dt,
+    SYMX_LAUNCH(m, PNAME, k_energy_inertia, dim3(G), dim3(256), 0, m.N, x, xt, m.mass, dt,
                        m.partials + off, m.nonfinite);
     LAUNCH_CHECK("k_energy_inertia");
     off += G;
   }
-  hipLaunchKernelGGL(k_reduce_to_scalar, dim3(1), dim3(256), 0, m.stream, m.partials, off, E_dev);
-  LAUNCH_CHECK("k_reduce_to_scalar");
+  SYMX_LAUNCH(m, "reduce", k_reduce_checked, dim3(1), dim3(256), 0, m.partials, off, E_dev,
+                     m.nonfinite);
+  LAUNCH_CHECK("k_reduce_checked");
   return SYMX_OK;
 }
 
 template <typename T>
 static symx_status elem_eval_t(Mesh& m, int set, const double* x, void* E, void* g, void* H) {
+  const char* PNAME = "elem_eval";
   const SetsDev sd = m.sets_dev();
   const SetDev& S = sd.s[set];
   const int G = grid_for(S.n_elem, 128, 65535);
   if (S.n_elem == 0) return SYMX_OK;
   switch (S.kind) {
     case SYMX_SNH_TET4:
-      hipLaunchKernelGGL((k_elem_eval<T, SYMX_SNH_TET4>), dim3(G), dim3(128), 0, m.stream, S, x,
+      SYMX_LAUNCH(m, PNAME, (k_elem_eval<T, SYMX_SNH_TET4>), dim3(G), dim3(128), 0, S, x,
                          m.X, (T*)E, (T*)g, (T*)H);
       break;
     case SYMX_STVK_TRI3:
-      hipLaunchKernelGGL((k_elem_eval<T, SYMX_STVK_TRI3>), dim3(G), dim3(128), 0, m.stream, S, x,
+      SYMX_LAUNCH(m, PNAME, (k_elem_eval<T, SYMX_STVK_TRI3>), dim3(G), dim3(128), 0, S, x,
                          m.X, (T*)E, (T*)g, (T*)H);
       break;
     default:
-      hipLaunchKernelGGL((k_elem_eval<T, SYMX_HINGE4>), dim3(G), dim3(128), 0, m.stream, S, x,
+      SYMX_LAUNCH(m, PNAME, (k_elem_eval<T, SYMX_HINGE4>), dim3(G), dim3(128), 0, S, x,
                          m.X, (T*)E, (T*)g, (T*)H);
   }
   LAUNCH_CHECK("k_elem_eval");
@@ -941,13 +1074,14 @@ symx_status launch_elem_eval(Mesh& m, int set, const double* x, int want, int pr
 }
 
 symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim) {
+  const char* PNAME = "project_psd";
   if (n == 0) return SYMX_OK;
   const int G = grid_for(n, 1, 65535);
   if (precision == SYMX_F32)
-    hipLaunchKernelGGL(k_project_psd<float>, dim3(G), dim3(64), 0, m.stream, (float*)H, n, dim, 30,
+    SYMX_LAUNCH(m, PNAME, k_project_psd<float>, dim3(G), dim3(64), 0, (float*)H, n, dim, 30,
                        1e-7);
   else
-    hipLaunchKernelGGL(k_project_psd<double>, dim3(G), dim3(64), 0, m.stream, (double*)H, n, dim,
+    SYMX_LAUNCH(m, PNAME, k_project_psd<double>, dim3(G), dim3(64), 0, (double*)H, n, dim,
                        30, 1e-15);
   LAUNCH_CHECK("k_project_psd");
   return SYMX_OK;
@@ -971,6 +1105,9 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   A.inc_ptr = m.inc_ptr;
   A.inc_code = m.inc_code;
   A.inc_slots = m.inc_slots;
+  A.blk_info = m.blk_info;
+  A.centry = m.centry;
+  A.batch_entry = m.batch_entry;
   A.nnzb = m.nnzb;
   A.vals = nullptr;
   if (want_H) A.vals = (T*)(sizeof(T) == 4 ? (void*)m.vals32 : (void*)m.vals64);
@@ -985,19 +1122,20 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
     return SYMX_ERR_INVALID_ARG;
   }
   const dim3 grid(m.n_batch), block(kRowWG);
+  const char* PNAME = want_H ? (want_g ? "row_assemble_gH" : "row_assemble_H") : "row_assemble_g";
   if (eb) {
     if (want_H && want_g)
-      hipLaunchKernelGGL((k_row_assemble<T, true, true, true>), grid, block, 0, m.stream, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble<T, true, true, true>), grid, block, 0, A);
     else if (want_H)
-      hipLaunchKernelGGL((k_row_assemble<T, true, false, true>), grid, block, 0, m.stream, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble<T, true, false, true>), grid, block, 0, A);
     else
-      hipLaunchKernelGGL((k_row_assemble<T, true, true, false>), grid, block, 0, m.stream, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble<T, true, true, false>), grid, block, 0, A);
   } else if (want_H && want_g) {
-    hipLaunchKernelGGL((k_row_assemble<T, false, true, true>), grid, block, 0, m.stream, A);
+    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true>), grid, block, 0, A);
   } else if (want_H) {
-    hipLaunchKernelGGL((k_row_assemble<T, false, false, true>), grid, block, 0, m.stream, A);
+    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false>), grid, block, 0, A);
   } else {
-    hipLaunchKernelGGL((k_row_assemble<T, false, true, false>), grid, block, 0, m.stream, A);
+    SYMX_LAUNCH(m, PNAME, (k_row_assemble<T, false, true, false>), grid, block, 0, A);
   }
   LAUNCH_CHECK("k_row_assemble");
   return SYMX_OK;
@@ -1013,23 +1151,28 @@ symx_status launch_row_assemble(Mesh& m, const double* x, const double* xt, doub
 
 symx_status launch_x_tilde(Mesh& m, const double* x, const double* v, double dt, const double g[3],
                            double* xt) {
+  const char* PNAME = "x_tilde";
   const int64_t n = 3 * m.N;
-  hipLaunchKernelGGL(k_x_tilde, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, x, v, dt, g[0],
+  SYMX_LAUNCH(m, PNAME, k_x_tilde, dim3(grid_for(n, 256)), dim3(256), 0, n, x, v, dt, g[0],
                      g[1], g[2], xt);
   LAUNCH_CHECK("k_x_tilde");
   return SYMX_OK;
 }
 
 symx_status launch_dot64(Mesh& m, const double* a, const double* b, int64_t n, double* out_dev) {
-  hipLaunchKernelGGL(k_dot64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, m.stream, n, a, b,
-                     m.partials, out_dev, m.counters + 3, m.nonfinite);
+  const char* PNAME = "dot64";
+  const int G = grid_for(n, 256, 1024);
+  SYMX_LAUNCH(m, PNAME, k_dot64, dim3(G), dim3(256), 0, n, a, b, m.partials);
+  SYMX_LAUNCH(m, "reduce", k_reduce_checked, dim3(1), dim3(256), 0, m.partials, G, out_dev,
+                     m.nonfinite);
   LAUNCH_CHECK("k_dot64");
   return SYMX_OK;
 }
 
 symx_status launch_axpy64(Mesh& m, double* y, const double* x, const double* alpha_dev,
                           double alpha_host, int64_t n) {
-  hipLaunchKernelGGL(k_axpy64, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, y, x, alpha_dev,
+  const char* PNAME = "axpy64";
+  SYMX_LAUNCH(m, PNAME, k_axpy64, dim3(grid_for(n, 256)), dim3(256), 0, n, y, x, alpha_dev,
                      alpha_host);
   LAUNCH_CHECK("k_axpy64");
   return SYMX_OK;
@@ -1037,7 +1180,8 @@ symx_status launch_axpy64(Mesh& m, double* y, const double* x, const double* alp
 
 symx_status launch_lincomb64(Mesh& m, double* out, const double* a, const double* b, double beta,
                              int64_t n) {
-  hipLaunchKernelGGL(k_lincomb64, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, out, a, b,
+  const char* PNAME = "lincomb64";
+  SYMX_LAUNCH(m, PNAME, k_lincomb64, dim3(grid_for(n, 256)), dim3(256), 0, n, out, a, b,
                      beta);
   LAUNCH_CHECK("k_lincomb64");
   return SYMX_OK;
@@ -1045,14 +1189,16 @@ symx_status launch_lincomb64(Mesh& m, double* out, const double* a, const double
 
 symx_status launch_velocity(Mesh& m, double* v, const double* xn, const double* xo, double inv_dt,
                             int64_t n) {
-  hipLaunchKernelGGL(k_velocity, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, v, xn, xo,
+  const char* PNAME = "velocity";
+  SYMX_LAUNCH(m, PNAME, k_velocity, dim3(grid_for(n, 256)), dim3(256), 0, n, v, xn, xo,
                      inv_dt);
   LAUNCH_CHECK("k_velocity");
   return SYMX_OK;
 }
 
 symx_status launch_check_finite(Mesh& m, const double* a, int64_t n) {
-  hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, 256, 4096)), dim3(256), 0, m.stream, n, a,
+  const char* PNAME = "check_finite";
+  SYMX_LAUNCH(m, PNAME, k_check_finite, dim3(grid_for(n, 256, 4096)), dim3(256), 0, n, a,
                      m.nonfinite);
   LAUNCH_CHECK("k_check_finite");
   return SYMX_OK;
@@ -1062,12 +1208,13 @@ symx_status launch_check_finite(Mesh& m, const double* a, int64_t n) {
 // PCG driver pieces (called from symx_newton.cpp)
 // ---------------------------------------------------------------------------
 symx_status launch_diag_inverse(Mesh& m, int precision, void* Dinv) {
+  const char* PNAME = "diag_inverse";
   const int G = grid_for(m.N, 256);
   if (precision == SYMX_F64)
-    hipLaunchKernelGGL(k_diag_inverse<double>, dim3(G), dim3(256), 0, m.stream, m.N, m.nnzb,
+    SYMX_LAUNCH(m, PNAME, k_diag_inverse<double>, dim3(G), dim3(256), 0, m.N, m.nnzb,
                        m.diag_pos, m.vals64, (double*)Dinv);
   else
-    hipLaunchKernelGGL(k_diag_inverse<float>, dim3(G), dim3(256), 0, m.stream, m.N, m.nnzb,
+    SYMX_LAUNCH(m, PNAME, k_diag_inverse<float>, dim3(G), dim3(256), 0, m.N, m.nnzb,
                        m.diag_pos, m.vals32, (float*)Dinv);
   LAUNCH_CHECK("k_diag_inverse");
   return SYMX_OK;
@@ -1075,40 +1222,43 @@ symx_status launch_diag_inverse(Mesh& m, int precision, void* Dinv) {
 
 symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const double* b,
                             double tol2, int max_iter) {
-  const int G = grid_for(m.N, 256, 8192);
+  const char* PNAME = "pcg_init";
   if (precision == SYMX_F64)
-    hipLaunchKernelGGL((k_pcg_init<double, double>), dim3(G), dim3(256), 0, m.stream, m.N, b,
+    SYMX_LAUNCH(m, PNAME, (k_pcg_init<double, double>), dim3(kPcgG), dim3(256), 0, m.N, b,
                        (const double*)B.Dinv, (double*)B.xs, (double*)B.r, (double*)B.z,
-                       (double*)B.p, (double*)B.q, m.partials, m.scalars, m.counters + 0, tol2,
-                       max_iter);
+                       (double*)B.p, (double*)B.q, m.partials, m.scalars, tol2, max_iter);
   else
-    hipLaunchKernelGGL((k_pcg_init<float, double>), dim3(G), dim3(256), 0, m.stream, m.N, b,
+    SYMX_LAUNCH(m, PNAME, (k_pcg_init<float, double>), dim3(kPcgG), dim3(256), 0, m.N, b,
                        (const float*)B.Dinv, (float*)B.xs, (float*)B.r, (float*)B.z, (float*)B.p,
-                       (float*)B.q, m.partials, m.scalars, m.counters + 0, tol2, max_iter);
+                       (float*)B.q, m.partials, m.scalars, tol2, max_iter);
   LAUNCH_CHECK("k_pcg_init");
   return SYMX_OK;
 }
 
-symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int n_iter) {
-  const int Gs = grid_for(m.N * 16, 256, 16384);
-  const int Gu = grid_for(m.N, 256, 8192);
-  for (int it = 0; it < n_iter; ++it) {
-    if (precision == SYMX_F64) {
-      hipLaunchKernelGGL(k_pcg_spmv<double>, dim3(Gs), dim3(256), 0, m.stream, m.N, m.row_ptr,
-                         m.col_idx, m.vals64, m.nnzb, (const double*)B.z, (double*)B.p,
-                         (double*)B.q, m.partials, m.scalars, m.counters + 1);
-      hipLaunchKernelGGL(k_pcg_update<double>, dim3(Gu), dim3(256), 0, m.stream, m.N,
-                         (const double*)B.Dinv, (double*)B.xs, (double*)B.r, (double*)B.z,
-                         (const double*)B.p, (const double*)B.q, m.partials + 32768, m.scalars,
-                         m.counters + 2);
-    } else {
-      hipLaunchKernelGGL(k_pcg_spmv<float>, dim3(Gs), dim3(256), 0, m.stream, m.N, m.row_ptr,
-                         m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p, (float*)B.q,
-                         m.partials, m.scalars, m.counters + 1);
-      hipLaunchKernelGGL(k_pcg_update<float>, dim3(Gu), dim3(256), 0, m.stream, m.N,
-                         (const float*)B.Dinv, (float*)B.xs, (float*)B.r, (float*)B.z,
-                         (const float*)B.p, (const float*)B.q, m.partials + 32768, m.scalars,
-                         m.counters + 2);
+// Enqueue iterations k0 .. k0+n_iter-1 (each: SpMV kernel, update kernel).
+symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0, int n_iter) {
+  for (int it = k0; it < k0 + n_iter; ++it) {
+    {
+      const char* PNAME = "pcg_spmv";
+      if (precision == SYMX_F64)
+        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<double>, dim3(kPcgG), dim3(256), 0, it, m.N,
+                           m.row_ptr, m.col_idx, m.vals64, m.nnzb, (const double*)B.z,
+                           (double*)B.p, (double*)B.q, m.partials, m.scalars);
+      else
+        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<float>, dim3(kPcgG), dim3(256), 0, it, m.N,
+                           m.row_ptr, m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p,
+                           (float*)B.q, m.partials, m.scalars);
+    }
+    {
+      const char* PNAME = "pcg_update";
+      if (precision == SYMX_F64)
+        SYMX_LAUNCH(m, PNAME, k_pcg_update<double>, dim3(kPcgG), dim3(256), 0, it, m.N,
+                           (const double*)B.Dinv, (double*)B.xs, (double*)B.r, (double*)B.z,
+                           (const double*)B.p, (const double*)B.q, m.partials, m.scalars);
+      else
+        SYMX_LAUNCH(m, PNAME, k_pcg_update<float>, dim3(kPcgG), dim3(256), 0, it, m.N,
+                           (const float*)B.Dinv, (float*)B.xs, (float*)B.r, (float*)B.z,
+                           (const float*)B.p, (const float*)B.q, m.partials, m.scalars);
     }
   }
   LAUNCH_CHECK("k_pcg");
@@ -1116,12 +1266,13 @@ symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int n_
 }
 
 symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs) {
+  const char* PNAME = "accumulate";
   const int64_t n = 3 * m.N;
   if (precision == SYMX_F64)
-    hipLaunchKernelGGL(k_accumulate<double>, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, dx,
+    SYMX_LAUNCH(m, PNAME, k_accumulate<double>, dim3(grid_for(n, 256)), dim3(256), 0, n, dx,
                        (const double*)xs);
   else
-    hipLaunchKernelGGL(k_accumulate<float>, dim3(grid_for(n, 256)), dim3(256), 0, m.stream, n, dx,
+    SYMX_LAUNCH(m, PNAME, k_accumulate<float>, dim3(grid_for(n, 256)), dim3(256), 0, n, dx,
                        (const float*)xs);
   LAUNCH_CHECK("k_accumulate");
   return SYMX_OK;
@@ -1129,12 +1280,13 @@ symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs
 
 symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b,
                               double* r) {
+  const char* PNAME = "residual64";
   const int G = grid_for(m.N * 16, 256, 16384);
   if (precision == SYMX_F64)
-    hipLaunchKernelGGL(k_residual64<double>, dim3(G), dim3(256), 0, m.stream, m.N, m.row_ptr,
+    SYMX_LAUNCH(m, PNAME, k_residual64<double>, dim3(G), dim3(256), 0, m.N, m.row_ptr,
                        m.col_idx, m.vals64, m.nnzb, x, b, r);
   else
-    hipLaunchKernelGGL(k_residual64<float>, dim3(G), dim3(256), 0, m.stream, m.N, m.row_ptr,
+    SYMX_LAUNCH(m, PNAME, k_residual64<float>, dim3(G), dim3(256), 0, m.N, m.row_ptr,
                        m.col_idx, m.vals32, m.nnzb, x, b, r);
   LAUNCH_CHECK("k_residual64");
   return SYMX_OK;

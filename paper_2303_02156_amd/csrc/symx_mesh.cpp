@@ -283,6 +283,54 @@ static symx_status build_pattern(Mesh& m) {
   }
   batch.push_back((int32_t)N);
   m.n_batch = (int)batch.size() - 1;
+  // Off-diagonal contribution lists.  For every off-diagonal block of a batch,
+  // the (incidence, relabelled node b >= 1) pairs that add to it, in incidence
+  // order; entries are u16 = (incidence index within the batch << 2) | b.
+  // blk_info[p] = (first entry relative to the batch's base << 8) | count.
+  std::vector<uint32_t> blk_info(m.nnzb, 0);
+  std::vector<uint16_t> centry;
+  centry.reserve(m.n_inc * 3);
+  std::vector<int32_t> batch_entry(m.n_batch + 1, 0);
+  std::vector<int32_t> cnt_blk, fillp;
+  for (int b = 0; b < m.n_batch; ++b) {
+    const int64_t r0 = batch[b], r1 = batch[b + 1];
+    const int64_t q0 = cnt[r0], p0 = m.h_row_ptr[r0];
+    const int64_t np = m.h_row_ptr[r1] - p0;
+    batch_entry[b] = (int32_t)centry.size();
+    cnt_blk.assign(np + 1, 0);
+    for (int64_t r = r0; r < r1; ++r)
+      for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
+        const int k = m.sets[inc_set(code[q])].k;
+        for (int bp = 1; bp < k; ++bp) {
+          const int64_t pl = m.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0;
+          cnt_blk[pl + 1]++;
+        }
+      }
+    for (int64_t i = 0; i < np; ++i) {
+      if (cnt_blk[i + 1] > 255) {
+        set_error("more than 255 elements share one node pair");
+        return SYMX_ERR_INVALID_ARG;
+      }
+      blk_info[p0 + i] = (uint32_t(cnt_blk[i]) << 8) | uint32_t(cnt_blk[i + 1]);
+      cnt_blk[i + 1] += cnt_blk[i];
+    }
+    if (cnt_blk[np] >= (1 << 24)) {
+      set_error("batch contribution list too long");
+      return SYMX_ERR_INVALID_ARG;
+    }
+    const size_t base = centry.size();
+    centry.resize(base + cnt_blk[np]);
+    fillp.assign(cnt_blk.begin(), cnt_blk.end() - 1);
+    for (int64_t r = r0; r < r1; ++r)
+      for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
+        const int k = m.sets[inc_set(code[q])].k;
+        for (int bp = 1; bp < k; ++bp) {
+          const int64_t pl = m.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0;
+          centry[base + fillp[pl]++] = (uint16_t)(((q - q0) << 2) | bp);
+        }
+      }
+  }
+  batch_entry[m.n_batch] = (int32_t)centry.size();
   // device upload
   std::vector<int32_t> inc_ptr32(N + 1);
   for (int64_t i = 0; i <= N; ++i) inc_ptr32[i] = (int32_t)cnt[i];
@@ -295,6 +343,9 @@ static symx_status build_pattern(Mesh& m) {
   TRY(upload(&m.inc_code, code.data(), m.n_inc));
   TRY(upload(&m.inc_slots, slots.data(), m.n_inc));
   TRY(upload(&m.batch_row, batch.data(), batch.size()));
+  TRY(upload(&m.blk_info, blk_info.data(), blk_info.size()));
+  TRY(upload(&m.centry, centry.data(), centry.size()));
+  TRY(upload(&m.batch_entry, batch_entry.data(), batch_entry.size()));
   for (size_t si = 0; si < m.sets.size(); ++si)
     TRY(upload(&m.sets[si].d_inc_pos, inc_pos[si].data(), inc_pos[si].size()));
   return SYMX_OK;
@@ -318,10 +369,10 @@ static symx_status upload_mesh(Mesh& m) {
   }
   TRY(upload<double>(&m.partials, nullptr, kMaxPartials));
   TRY(upload<double>(&m.scalars, nullptr, 64));
-  TRY(upload<unsigned>(&m.counters, nullptr, 16));
-  TRY(upload<int>(&m.nonfinite, nullptr, 1));
-  TRY(hip_check(hipMemset(m.counters, 0, 16 * sizeof(unsigned)), "hipMemset"));
-  TRY(hip_check(hipMemset(m.nonfinite, 0, sizeof(int)), "hipMemset"));
+  TRY(hip_check(hipMemset(m.scalars, 0, 64 * sizeof(double)), "hipMemset"));
+  // the non-finite flag shares the scalar array (slot 24) so the Newton driver
+  // reads results and flag with one copy
+  m.nonfinite = reinterpret_cast<int*>(m.scalars + 24);
   if (hipHostMalloc((void**)&m.pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     m.pinned = nullptr;
     set_error("pinned host allocation failed");

@@ -14,6 +14,7 @@
 // linear solve is refined in float64 (residual b - H dx with the float32 H
 // promoted, then another float32 PCG solve for the correction).  SYMX_F32
 // evaluates all element quantities in float32 (sums in float64).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -23,9 +24,11 @@
 namespace symxi {
 
 
-enum { S_RZ = 0, S_RZ_OLD, S_PQ, S_RR, S_BB, S_ALPHA, S_BETA, S_TOL2, S_DONE, S_ITERS, S_MAXIT };
+enum { S_DONE = 0, S_ITERS };  // PCG flags (see the PCG kernels)
 // device scalar slots used by the driver (after the PCG scalars)
-enum { D_ENERGY = 16, D_DOT = 17, D_DOT2 = 18 };
+enum { D_ENERGY = 16, D_DOT = 17, D_GG = 18, D_GD = 19, D_E0 = 20, D_ET = 21, D_FLAG = 24 };
+// the device non-finite flag is the int stored at scalars[D_FLAG], so one copy
+// of scalars[D_ENERGY .. D_FLAG] returns results and the flag together
 
 #define TRY(expr)                 \
   do {                            \
@@ -101,6 +104,18 @@ static symx_status check_nonfinite(Mesh& m) {
   return SYMX_OK;
 }
 
+// Copy scalars[D_ENERGY .. D_FLAG] to the host; returns true in *bad (and
+// clears the device flag) if a kernel met a non-finite value since the last read.
+static symx_status read_window(Mesh& m, double* win, bool* bad) {
+  const int n = D_FLAG - D_ENERGY + 1;
+  TRY(sync_read(m, m.scalars + D_ENERGY, n, win));
+  int flag = 0;
+  std::memcpy(&flag, &win[D_FLAG - D_ENERGY], sizeof(int));
+  *bad = flag != 0;
+  if (*bad) TRY(hip_check(hipMemsetAsync(m.nonfinite, 0, sizeof(int), m.stream), "hipMemsetAsync"));
+  return SYMX_OK;
+}
+
 // Per-element buffers for the projected path (allocated on first use).
 static symx_status project_elements(Mesh& m, const double* x, int precision, bool want_g,
                                     ElemBuffers* eb) {
@@ -171,20 +186,31 @@ static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rto
   PcgBuffers B{w->pcg[0], w->pcg[1], w->pcg[2], w->pcg[3], w->pcg[4], w->pcg[5]};
   const int pp = precision == SYMX_F64 ? SYMX_F64 : SYMX_F32;
   TRY(launch_pcg_init(m, pp, B, b, rtol * rtol, max_iter));
-  double S[11];
+  double S[2];
   int done_iters = 0;
-  int chunk = 8;
+  // first chunk sized from the previous solve, so that few launches run past
+  // convergence and few host synchronisations are needed
+  int chunk = std::max(8, (3 * m.last_pcg_iters) / 4);
+  int k = 0;
   *breakdown = false;
   while (true) {
-    TRY(launch_pcg_iters(m, pp, B, chunk));
-    TRY(sync_read(m, m.scalars, 11, S));
+    // the SpMV kernel of iteration max_iter only records the stop
+    const int n = std::min(chunk, max_iter + 1 - k);
+    TRY(launch_pcg_iters(m, pp, B, k, n));
+    k += n;
+    TRY(sync_read(m, m.scalars, 2, S));
     if (S[S_DONE] != 0.0) {
       done_iters = (int)S[S_ITERS];
       *breakdown = S[S_DONE] == 2.0;
       break;
     }
-    if (chunk < 32) chunk *= 2;
+    if (k > max_iter) {  // cannot happen: the last SpMV sets the flag
+      set_error("PCG did not stop");
+      return SYMX_ERR_DEVICE;
+    }
+    chunk = 8;
   }
+  m.last_pcg_iters = done_iters;
   *iters = done_iters;
   return launch_accumulate(m, pp, dx, B.xs);
 }
@@ -225,11 +251,16 @@ static double ms_since(clk::time_point t0) {
 }
 
 // One attempt at fixed dt from (x_t, v_t) in the workspace; result in w->xk.
+// Host synchronisations per Newton iteration: one after assembly (residual),
+// the PCG chunk checks, and one per line-search trial.
 static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, symx_step_report* R) {
   Workspace* w = m.ws;
   const int64_t n = 3 * m.N;
-  const int pe = P.precision == SYMX_F64 ? SYMX_F64 : (P.precision == SYMX_F32 ? SYMX_F32 : SYMX_F64);
-  const int ph = P.precision == SYMX_F64 ? SYMX_F64 : SYMX_F32;
+  const int pe = P.precision == SYMX_F32 ? SYMX_F32 : SYMX_F64;  // energies and gradient
+  const int ph = P.precision == SYMX_F64 ? SYMX_F64 : SYMX_F32;  // Hessian and PCG
+  double win[D_FLAG - D_ENERGY + 1];
+  auto at = [&](int slot) { return win[slot - D_ENERGY]; };
+  bool bad = false;
   TRY(launch_x_tilde(m, w->x_t, w->v_t, dt, P.gravity, w->xt));
   TRY(hip_check(hipMemcpyAsync(w->xk, w->x_t, n * sizeof(double), hipMemcpyDeviceToDevice, m.stream),
                 "hipMemcpyAsync"));
@@ -243,21 +274,26 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
       TRY(assemble(m, w->xk, w->xt, dt, true, false, false, pe, true, w->g));
       TRY(assemble(m, w->xk, w->xt, dt, false, true, P.project != 0, ph, true, nullptr));
     }
-    double gg = 0.0;
-    TRY(dot(m, w->g, w->g, &gg));
-    TRY(check_nonfinite(m));
+    TRY(launch_dot64(m, w->g, w->g, n, m.scalars + D_GG));
+    if (!have_E0) TRY(launch_energy(m, w->xk, w->xt, dt, pe, m.scalars + D_E0));
+    TRY(read_window(m, win, &bad));
     R->ms_assemble += ms_since(t0);
-    const double r = std::sqrt(gg);
+    if (bad) {
+      set_error("non-finite value in energy or gradient");
+      return SYMX_ERR_NONFINITE;
+    }
+    if (!have_E0) {
+      E0 = at(D_E0);
+      have_E0 = true;
+    }
+    const double r = std::sqrt(at(D_GG));
     if (r0 < 0.0) {
       r0 = r;
       R->residual0 = r0;
     }
     R->residual = r;
-    if (r <= P.newton_rtol * r0) {
-      if (!have_E0) TRY(energy(m, w->xk, w->xt, dt, pe, &E0));
-      R->energy = E0;
-      return SYMX_OK;
-    }
+    R->energy = E0;
+    if (r <= P.newton_rtol * r0) return SYMX_OK;
     if (it >= P.max_newton) {
       set_error("Newton did not converge within max_newton iterations");
       return SYMX_ERR_NOT_CONVERGED;
@@ -267,26 +303,31 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
     TRY(linear_solve(m, P, w->g, eta, r, &R->pcg_iters, &R->refinements));
     R->ms_pcg += ms_since(t1);
     auto t2 = clk::now();
-    double gd = 0.0;
-    TRY(dot(m, w->g, w->dx, &gd));
+    // slope and the full step's energy in one round trip
+    TRY(launch_dot64(m, w->g, w->dx, n, m.scalars + D_GD));
+    double alpha = 1.0;
+    TRY(launch_lincomb64(m, w->xtrial, w->xk, w->dx, alpha, n));
+    TRY(launch_energy(m, w->xtrial, w->xt, dt, pe, m.scalars + D_ET));
+    TRY(read_window(m, win, &bad));
+    const double gd = at(D_GD);
     if (!(gd < 0.0)) {
       set_error("Newton direction is not a descent direction");
       return SYMX_ERR_LINE_SEARCH;
     }
-    if (!have_E0) TRY(energy(m, w->xk, w->xt, dt, pe, &E0));
-    double alpha = 1.0;
     bool ok = false;
-    double Et = 0.0;
-    for (int ls = 0; ls <= 30; ++ls) {
-      TRY(launch_lincomb64(m, w->xtrial, w->xk, w->dx, alpha, n));
-      symx_status st = energy(m, w->xtrial, w->xt, dt, pe, &Et);
-      if (st == SYMX_OK && Et <= E0 + 1e-4 * alpha * gd) {
+    double Et = at(D_ET);
+    for (int ls = 0;; ++ls) {
+      if (!bad && Et <= E0 + 1e-4 * alpha * gd) {
         ok = true;
         break;
       }
-      if (st != SYMX_OK && st != SYMX_ERR_NONFINITE) return st;
+      if (ls == 30) break;
       alpha *= 0.5;
       R->ls_backtracks++;
+      TRY(launch_lincomb64(m, w->xtrial, w->xk, w->dx, alpha, n));
+      TRY(launch_energy(m, w->xtrial, w->xt, dt, pe, m.scalars + D_ET));
+      TRY(read_window(m, win, &bad));
+      Et = at(D_ET);
     }
     R->ms_linesearch += ms_since(t2);
     if (!ok) {
@@ -295,7 +336,6 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
     }
     std::swap(w->xk, w->xtrial);
     E0 = Et;
-    have_E0 = true;
     R->newton_iters++;
   }
 }

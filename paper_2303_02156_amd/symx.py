@@ -79,6 +79,10 @@ EXPORTS = {
                                     C.POINTER(BsrView)]),
     "symx_newton_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(StepParams),
                                    C.POINTER(StepReport)]),
+    "symx_mesh_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
+    "symx_mesh_get_kernel_time": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double,
+                                            C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "symx_mesh_kernel_names": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
     "symx_status_string": (C.c_char_p, [C.c_int]),
     "symx_last_error": (C.c_char_p, []),
 }
@@ -155,6 +159,25 @@ def symx_newton_step(h, x_dev, v_dev, params):
     rep = StepReport()
     st = load().symx_newton_step(h, x_dev, v_dev, C.byref(params), C.byref(rep))
     return st, rep
+
+
+def symx_mesh_set_profiling(h, enable):
+    _check(load().symx_mesh_set_profiling(h, int(enable)), "symx_mesh_set_profiling")
+
+
+def symx_mesh_get_kernel_time(h, name, min_ms=0.0):
+    n = C.c_int64(0)
+    ms = C.c_double(0.0)
+    _check(load().symx_mesh_get_kernel_time(h, name.encode(), min_ms, C.byref(n), C.byref(ms)),
+           "symx_mesh_get_kernel_time")
+    return n.value, ms.value
+
+
+def symx_mesh_kernel_names(h):
+    buf = C.create_string_buffer(4096)
+    _check(load().symx_mesh_kernel_names(h, buf, 4096), "symx_mesh_kernel_names")
+    v = buf.value.decode()
+    return v.split(",") if v else []
 
 
 def symx_step_params_default():
@@ -265,6 +288,15 @@ class Mesh:
             vals = t.empty((9, self.info.nnzb), dtype=dtype, device="cuda")
             _device_copy(vals.data_ptr(), view.values, vals.numel() * vals.element_size())
         return E, g, vals
+
+    def profile(self, enable=True):
+        symx_mesh_set_profiling(self.handle, enable)
+
+    def kernel_times(self, min_ms=0.0):
+        """{kernel name: (launches, total device ms)} since profiling was enabled,
+        counting launches of at least min_ms."""
+        return {n: symx_mesh_get_kernel_time(self.handle, n, min_ms)
+                for n in symx_mesh_kernel_names(self.handle)}
 
     def newton_step(self, x, v, params):
         st, rep = symx_newton_step(self.handle, x.data_ptr(), v.data_ptr(), params)

@@ -157,3 +157,45 @@ def test_hinge_and_inertia_generated_vs_oracle(lib):
     assert _rel(out[:, 0], Ei) < 1e-13
     assert _rel(out[:, 1:4], gi) < 1e-13
     assert _rel(out[:, 4:], (w[:, None, None] * np.eye(3)).reshape(n, 9)) < 1e-13
+
+
+def test_hessian_rows_sum_to_zero_and_offdiagonal_rows(lib):
+    """The row assembly forms each diagonal block as minus the sum of the
+    off-diagonal blocks of its row; that needs every element Hessian row to sum
+    to zero over the nodes (translation invariance).  Pin it on the generated
+    code for all three energies, and pin the off-diagonal row function."""
+    x, X = sg.random_tets(30, seed=104)
+    n = x.shape[0]
+    inp = np.concatenate([x.reshape(n, 12), X.reshape(n, 12), np.full((n, 1), MU),
+                          np.full((n, 1), LAM)], axis=1)
+    H = _call(lib, "snh_tet4_EgH", inp, 157)[:, 13:].reshape(n, 4, 3, 4, 3)
+    assert np.max(np.abs(H.sum(axis=3))) < 1e-9 * np.abs(H).max()
+    _, g, Ho = elements.snh_tet4(x, X, np.full(n, MU), np.full(n, LAM))
+    for a in range(4):
+        perm = [a] + [b for b in range(4) if b != a]
+        xp = x[:, perm] - x[:, a:a + 1]
+        Xp = X[:, perm] - X[:, a:a + 1]
+        r = _call(lib, "snh_tet4_row0_gHoff",
+                  np.concatenate([xp.reshape(n, 12), Xp.reshape(n, 12), inp[:, 24:]], 1), 30)
+        assert _rel(r[:, :3], g[:, a]) < 1e-10
+        ref = Ho[:, a][:, :, perm[1:], :].reshape(n, 3, 9)
+        assert _rel(r[:, 3:].reshape(n, 3, 9), ref) < 1e-10
+    mu, lam = rest.lame(1e4, 0.3)
+    xt, Xt = _random_tris(20, 105)
+    m = xt.shape[0]
+    prm = np.tile([mu, lam, 1e-3], (m, 1))
+    Ht = _call(lib, "stvk_tri3_EgH", np.concatenate([xt.reshape(m, 9), Xt.reshape(m, 9), prm], 1),
+               91)[:, 10:].reshape(m, 3, 3, 3, 3)
+    assert np.max(np.abs(Ht.sum(axis=3))) < 1e-9 * np.abs(Ht).max()
+    rng = np.random.default_rng(106)
+    Xh = np.zeros((20, 4, 3))
+    Xh[:, 1, 0] = 1.0
+    Xh[:, 2, :2] = rng.uniform(0.2, 0.8, (20, 2))
+    Xh[:, 3, 0] = rng.uniform(0.2, 0.8, 20)
+    Xh[:, 3, 1] = -rng.uniform(0.2, 0.8, 20)
+    K, c = elements.hinge_rest(Xh)
+    xh = Xh + rng.normal(scale=0.05, size=Xh.shape)
+    Hh = _call(lib, "hinge4_EgH", np.concatenate([xh.reshape(20, 12), K, c[:, None],
+                                                  np.full((20, 1), 1e-3)], 1), 157)
+    Hh = Hh[:, 13:].reshape(20, 4, 3, 4, 3)
+    assert np.max(np.abs(Hh.sum(axis=3))) < 1e-12 * np.abs(Hh).max()
