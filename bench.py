@@ -58,6 +58,24 @@ def algorithmic_bytes(kernel, N, nnzb, n_elem, t_bytes):
     return None
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2303_02156_amd", "csrc", "symx_kernels.hip")).read()
+    a = src.find(f"// [traffic-hash-begin {kernel}]")
+    e = src.find(f"// [traffic-hash-end {kernel}]")
+    if a < 0 or e < 0:
+        return None
+    if hashlib.sha256(src[a:e].encode()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(seconds_target=10.0):
     """FP64 numpy oracle: eval + assembly (E, g, BSR) of a 24^3 cube of the same
     workload recipe, repeated until ~seconds_target of CPU work."""
@@ -106,6 +124,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64-newton", action="store_true")
     ap.add_argument("--no-projection", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run plain 512 MiB device copies first (byte-counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -125,6 +145,15 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     symx.load()
+    if args.calib_copy:
+        # a plain copy kernel of known size: 512 MiB read + 512 MiB written per launch
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copies done (4 x 512 MiB)")
     scene = sg.config_c2(args.n)
     n_elem = scene.n_elements()
     log(f"scene {scene.name}: {scene.n_nodes} nodes, {n_elem} tets")
@@ -205,8 +234,15 @@ def main():
             mesh.profile(False)
         return wall * 1e3 / K, reps, kt
 
-    ms_f32r, reps_f32r, ktimes = run_steps(symx.SYMX_F32_REFINED, args.steps, args.warmup, True)
+    # timed run without per-kernel events (they add host work to every launch)
+    ms_f32r, reps_f32r, _ = run_steps(symx.SYMX_F32_REFINED, args.steps, args.warmup, False)
     log(f"newton f32_refined: {ms_f32r:.2f} ms/step")
+    # replay of the identical (deterministic) step sequence with per-kernel
+    # start/stop events; kernel device times feed the roofline
+    ms_prof, reps_prof, ktimes = run_steps(symx.SYMX_F32_REFINED, args.steps, args.warmup, True)
+    log(f"newton f32_refined with kernel events: {ms_prof:.2f} ms/step")
+    same = [(a["newton_iters"], a["pcg_iters"]) for a in reps_f32r] == \
+        [(a["newton_iters"], a["pcg_iters"]) for a in reps_prof]
     ms_f64, reps_f64 = None, None
     if not args.no_f64_newton:
         ms_f64, reps_f64, _ = run_steps(symx.SYMX_F64, args.steps, args.warmup, False)
@@ -223,11 +259,15 @@ def main():
                 "avg_ms": round(avg_ms, 5), "algorithmic_bytes": nbytes,
                 "idle_launches": allk[kname][0] - launches,
                 "idle_ms": round(allk[kname][1] - total_ms, 3),
-                "share_of_step_time": round(allk[kname][1] / (ms_f32r * args.steps), 4)}
+                "share_of_step_time": round(allk[kname][1] / (ms_f32r * args.steps), 4),
+                "timing": "hipExtLaunchKernelGGL start/stop events in a replay of the timed "
+                          "steps (identical iteration counts: %s)" % same}
     if nbytes:
         ach = nbytes / (avg_ms * 1e-3) / 1e9
         roofline["achieved"] = round(ach, 1)
         roofline["frac"] = round(ach / HBM_PEAK_GBS, 4)
+    if args.n == 64:
+        roofline["traffic"] = measured_traffic(kname)
     kernels = {}
     for k, (n, ms) in sorted(allk.items(), key=lambda kv: -kv[1][1]):
         nb_, msb = busy.get(k, (0, 0.0))
@@ -276,6 +316,7 @@ def main():
         "assembly_ms": {k: round(v, 4) for k, v in asm_ms.items()},
         "assembly_kernels_f32": {k: {"launches": n, "ms": round(ms, 4)}
                                  for k, (n, ms) in asm_kernels.items()},
+        "newton_step_ms_with_kernel_events": round(ms_prof, 3),
         "newton_step_ms": {"f32_refined": round(ms_f32r, 3),
                            "f64": None if ms_f64 is None else round(ms_f64, 3)},
         "newton_f32_refined": summary(reps_f32r),

@@ -27,7 +27,8 @@ symx_status hip_check(hipError_t e, const char* what) {
 symx_status mesh_create(const symx_mesh_desc* d, Mesh** out);
 void free_workspace(Mesh& m);
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
-                     bool want_H, bool project, int precision, bool dirichlet, double* g_out);
+                     bool want_H, bool project, int precision, bool dirichlet, double* g_out,
+                     void* dinv);
 symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E);
 symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P,
                         symx_step_report* out);
@@ -209,7 +210,7 @@ symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double*
   const bool want_H = (flags & SYMX_EVAL_HESS) != 0;
   symx_status st = assemble(m, x_dev, x_tilde_dev, dt, want_g, want_H,
                             (flags & SYMX_PROJECT_PSD) != 0, precision,
-                            (flags & SYMX_DIRICHLET) != 0, grad_dev);
+                            (flags & SYMX_DIRICHLET) != 0, grad_dev, nullptr);
   if (st != SYMX_OK) return st;
   if (flags & SYMX_EVAL_E) {
     st = energy(m, x_dev, x_tilde_dev, dt, precision, energy_host);
@@ -247,6 +248,7 @@ symx_status symx_mesh_set_profiling(symx_mesh mesh, int32_t enable) {
   Mesh& m = *mesh->m;
   m.prof.reset();
   m.prof.on = enable != 0;
+  if (m.prof.on) m.prof.reserve(1 << 15);  // events for 16k launches, created up front
   return SYMX_OK;
   GUARD_END
 }

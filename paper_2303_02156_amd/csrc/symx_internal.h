@@ -17,6 +17,7 @@ constexpr int kMaxRowBlocks = 255;  // slots per row are stored as uint8
 constexpr int kRedWG = 256;         // reduction workgroup size
 constexpr int kPrm = 8;             // parameter slots per element (doubles)
 constexpr uint32_t kNoSlot = 0xFFu;
+constexpr int kPcgHistory = 64;    // remembered PCG iteration counts
 
 // Parameter layout per element (kPrm doubles):
 //   SNH tet4:  mu, lambda (linear-elasticity Lame pair)
@@ -83,6 +84,7 @@ struct Profiler {
   hipEvent_t take();
   void resolve();
   void reset();
+  void reserve(size_t n);
   void destroy();
 };
 
@@ -130,7 +132,7 @@ struct Mesh {
   // dt control
   double dt_cur = 0.0, dt_nominal = 0.0;
   int successes = 0;
-  int last_pcg_iters = 0;
+  int last_pcg_iters[kPcgHistory] = {};  // per Newton iteration index
   Profiler prof;
 
   SetsDev sets_dev() const;
@@ -164,9 +166,11 @@ struct ElemBuffers {
   const void* g[kMaxSets];
   const void* H[kMaxSets];
 };
+// dinv (optional, recompute path only): the kernel also writes the inverses
+// of the final diagonal blocks (N x 9, precision's type).
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* x_tilde, double dt,
                                 bool want_g, bool want_H, int precision, bool dirichlet,
-                                const ElemBuffers* from_elem, double* g_out);
+                                const ElemBuffers* from_elem, double* g_out, void* dinv);
 // Total energy (float64 sum of per-element energies in `precision`).
 symx_status launch_energy(Mesh& m, const double* x, const double* x_tilde, double dt,
                           int precision, double* E_dev);

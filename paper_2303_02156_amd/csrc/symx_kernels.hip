@@ -392,6 +392,7 @@ struct RowArgs {
   const int* batch_entry;
   int64_t nnzb;
   T* vals;               // component-major 9 x nnzb
+  T* dinv;               // N x 9 inverses of the diagonal blocks, or null
   double* g;             // N x 3
   const void* elem_g[kMaxSets];  // projected path: per-element gradients
   const void* elem_H[kMaxSets];  // and Hessians
@@ -546,6 +547,30 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble(RowArgs<T> A) {
   }
 }
 
+// Inverse of a 3x3 block in float64 (identity for a singular block); the
+// block-Jacobi preconditioner of the PCG.
+__device__ __forceinline__ void inverse3(const double a[9], double r[9]) {
+  const double c00 = a[4] * a[8] - a[5] * a[7];
+  const double c01 = a[5] * a[6] - a[3] * a[8];
+  const double c02 = a[3] * a[7] - a[4] * a[6];
+  const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+  if (det != 0.0 && isfinite(det)) {
+    const double id = 1.0 / det;
+    r[0] = c00 * id;
+    r[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+    r[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+    r[3] = c01 * id;
+    r[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+    r[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+    r[6] = c02 * id;
+    r[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+    r[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) r[c] = (c % 4 == 0) ? 1.0 : 0.0;
+  }
+}
+
 // Off-diagonal part of one incidence's Hessian block row (recompute path):
 // out[0..2] gradient of node a, out[3 + 9 i + 3 (b-1) + k] entry (a_i, node b
 // of the relabelled order, coord k) for b = 1, 2, 3.
@@ -687,6 +712,14 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) A.vals[(int64_t)c * A.nnzb + p0 + t] = acc[c];
+    if (diag && A.dinv) {
+      double a[9], ri[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) a[c] = double(acc[c]);
+      inverse3(a, ri);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) A.dinv[9 * (int64_t)row + c] = T(ri[c]);
+    }
   }
 }
 
@@ -702,34 +735,16 @@ __global__ __launch_bounds__(256) void k_diag_inverse(int64_t N, int64_t nnzb,
                                                       T* __restrict__ Dinv) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
     const int64_t p = diag_pos[i];
-    double a[9];
+    double a[9], r[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) a[c] = double(vals[c * nnzb + p]);
-    double c00 = a[4] * a[8] - a[5] * a[7];
-    double c01 = a[5] * a[6] - a[3] * a[8];
-    double c02 = a[3] * a[7] - a[4] * a[6];
-    double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
-    double r[9];
-    if (det != 0.0 && isfinite(det)) {
-      double id = 1.0 / det;
-      r[0] = c00 * id;
-      r[1] = (a[2] * a[7] - a[1] * a[8]) * id;
-      r[2] = (a[1] * a[5] - a[2] * a[4]) * id;
-      r[3] = c01 * id;
-      r[4] = (a[0] * a[8] - a[2] * a[6]) * id;
-      r[5] = (a[2] * a[3] - a[0] * a[5]) * id;
-      r[6] = c02 * id;
-      r[7] = (a[1] * a[6] - a[0] * a[7]) * id;
-      r[8] = (a[0] * a[4] - a[1] * a[3]) * id;
-    } else {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) r[c] = (c % 4 == 0) ? 1.0 : 0.0;
-    }
+    inverse3(a, r);
 #pragma unroll
     for (int c = 0; c < 9; ++c) Dinv[9 * i + c] = T(r[c]);
   }
 }
 
+// [traffic-hash-begin pcg_spmv]
 // y = A x (BSR, 16 lanes per block row, lane l takes blocks l, l+16, ...)
 template <typename TA, typename TX, typename TY>
 __device__ __forceinline__ void spmv_row(int row, int lane, const int* __restrict__ row_ptr,
@@ -773,14 +788,17 @@ __global__ __launch_bounds__(256) void k_residual64(int64_t N, const int* __rest
   }
 }
 
-// PCG state.  Partial sums (one per workgroup, kPcgG workgroups) are written
+// PCG state.  Partial sums (one per workgroup) are written
 // by one kernel and reduced, redundantly and in the same order, by every
 // workgroup of the next kernel.  Scalars live in a small device array; rz of
 // iteration k is kept in slot S_RZ + (k & 1) so that readers of the previous
 // value never race with the writer of the new one.
-constexpr int kPcgG = 1024;
+// Grid sizes: the SpMV kernel streams the matrix and runs best with 2048
+// workgroups; the node-wise kernels use 1024.  Each partial array holds up to
+// kPcgP entries.
+constexpr int kPcgGs = 2048, kPcgGu = 1024, kPcgP = 4096;
 enum { S_DONE = 0, S_ITERS, S_TOL2, S_BB, S_RZ, S_RZ1, S_MAXIT, S_NSCALARS };
-enum { P_RZ = 0, P_RR = 1, P_BB = 2, P_PQ = 3 };  // partial arrays, kPcgG each
+enum { P_RZ = 0, P_RR = 1, P_BB = 2, P_PQ = 3 };  // partial arrays, kPcgP each
 
 // r = b, z = M^-1 r, x = p = q = 0; partials of rz, rr, bb
 template <typename T, typename TB>
@@ -817,9 +835,9 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restric
   const double s1 = block_sum_256(rr, sh);
   const double s2 = block_sum_256(bb, sh);
   if (threadIdx.x == 0) {
-    P[P_RZ * kPcgG + blockIdx.x] = s0;
-    P[P_RR * kPcgG + blockIdx.x] = s1;
-    P[P_BB * kPcgG + blockIdx.x] = s2;
+    P[P_RZ * kPcgP + blockIdx.x] = s0;
+    P[P_RR * kPcgP + blockIdx.x] = s1;
+    P[P_BB * kPcgP + blockIdx.x] = s2;
     if (blockIdx.x == 0) {
       S[S_DONE] = 0.0;
       S[S_ITERS] = 0.0;
@@ -841,9 +859,9 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* _
                                                   double* __restrict__ S) {
   if (S[S_DONE] != 0.0) return;
   __shared__ double sh[4];
-  const double rz = sum_partials(P + P_RZ * kPcgG, kPcgG, sh);
-  const double rr = sum_partials(P + P_RR * kPcgG, kPcgG, sh);
-  const double bb = k == 0 ? sum_partials(P + P_BB * kPcgG, kPcgG, sh) : S[S_BB];
+  const double rz = sum_partials(P + P_RZ * kPcgP, kPcgGu, sh);
+  const double rr = sum_partials(P + P_RR * kPcgP, kPcgGu, sh);
+  const double bb = k == 0 ? sum_partials(P + P_BB * kPcgP, kPcgGu, sh) : S[S_BB];
   const bool first = blockIdx.x == 0 && threadIdx.x == 0;
   if (bb == 0.0 || rr <= S[S_TOL2] * bb || k >= int(S[S_MAXIT]) || !isfinite(rr)) {
     if (first) {
@@ -875,8 +893,10 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* _
     }
   }
   const double s = block_sum_256(pq, sh);
-  if (threadIdx.x == 0) P[P_PQ * kPcgG + blockIdx.x] = s;
+  if (threadIdx.x == 0) P[P_PQ * kPcgP + blockIdx.x] = s;
 }
+
+// [traffic-hash-end pcg_spmv]
 
 // Iteration k: alpha = rz_k / p.q; x += alpha p; r -= alpha q; z = M^-1 r;
 // partials of rz, rr.
@@ -889,7 +909,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(int k, int64_t N, const T* _
                                                     double* __restrict__ S) {
   if (S[S_DONE] != 0.0) return;
   __shared__ double sh[4];
-  const double pq = sum_partials(P + P_PQ * kPcgG, kPcgG, sh);
+  const double pq = sum_partials(P + P_PQ * kPcgP, kPcgGs, sh);
   if (!(pq > 0.0)) {  // direction of non-positive curvature: stop
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       S[S_DONE] = 2.0;
@@ -919,8 +939,8 @@ __global__ __launch_bounds__(256) void k_pcg_update(int k, int64_t N, const T* _
   const double s0 = block_sum_256(rz, sh);
   const double s1 = block_sum_256(rr, sh);
   if (threadIdx.x == 0) {
-    P[P_RZ * kPcgG + blockIdx.x] = s0;
-    P[P_RR * kPcgG + blockIdx.x] = s1;
+    P[P_RZ * kPcgP + blockIdx.x] = s0;
+    P[P_RR * kPcgP + blockIdx.x] = s1;
   }
 }
 
@@ -1090,7 +1110,7 @@ symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim) 
 template <typename T>
 static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, double dt,
                                   bool want_g, bool want_H, bool dirichlet,
-                                  const ElemBuffers* eb, double* g_out) {
+                                  const ElemBuffers* eb, double* g_out, void* dinv) {
   RowArgs<T> A;
   A.sets = m.sets_dev();
   A.x = x;
@@ -1112,6 +1132,7 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   A.vals = nullptr;
   if (want_H) A.vals = (T*)(sizeof(T) == 4 ? (void*)m.vals32 : (void*)m.vals64);
   A.g = g_out;
+  A.dinv = (T*)dinv;
   A.nonfinite = m.nonfinite;
   for (int s = 0; s < kMaxSets; ++s) {
     A.elem_g[s] = eb ? eb->g[s] : nullptr;
@@ -1143,10 +1164,10 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
 
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
                                 bool want_H, int precision, bool dirichlet,
-                                const ElemBuffers* from_elem, double* g_out) {
+                                const ElemBuffers* from_elem, double* g_out, void* dinv) {
   if (precision == SYMX_F32)
-    return row_assemble_t<float>(m, x, xt, dt, want_g, want_H, dirichlet, from_elem, g_out);
-  return row_assemble_t<double>(m, x, xt, dt, want_g, want_H, dirichlet, from_elem, g_out);
+    return row_assemble_t<float>(m, x, xt, dt, want_g, want_H, dirichlet, from_elem, g_out, dinv);
+  return row_assemble_t<double>(m, x, xt, dt, want_g, want_H, dirichlet, from_elem, g_out, dinv);
 }
 
 symx_status launch_x_tilde(Mesh& m, const double* x, const double* v, double dt, const double g[3],
@@ -1224,11 +1245,11 @@ symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const d
                             double tol2, int max_iter) {
   const char* PNAME = "pcg_init";
   if (precision == SYMX_F64)
-    SYMX_LAUNCH(m, PNAME, (k_pcg_init<double, double>), dim3(kPcgG), dim3(256), 0, m.N, b,
+    SYMX_LAUNCH(m, PNAME, (k_pcg_init<double, double>), dim3(kPcgGu), dim3(256), 0, m.N, b,
                        (const double*)B.Dinv, (double*)B.xs, (double*)B.r, (double*)B.z,
                        (double*)B.p, (double*)B.q, m.partials, m.scalars, tol2, max_iter);
   else
-    SYMX_LAUNCH(m, PNAME, (k_pcg_init<float, double>), dim3(kPcgG), dim3(256), 0, m.N, b,
+    SYMX_LAUNCH(m, PNAME, (k_pcg_init<float, double>), dim3(kPcgGu), dim3(256), 0, m.N, b,
                        (const float*)B.Dinv, (float*)B.xs, (float*)B.r, (float*)B.z, (float*)B.p,
                        (float*)B.q, m.partials, m.scalars, tol2, max_iter);
   LAUNCH_CHECK("k_pcg_init");
@@ -1241,22 +1262,22 @@ symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0
     {
       const char* PNAME = "pcg_spmv";
       if (precision == SYMX_F64)
-        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<double>, dim3(kPcgG), dim3(256), 0, it, m.N,
+        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<double>, dim3(kPcgGs), dim3(256), 0, it, m.N,
                            m.row_ptr, m.col_idx, m.vals64, m.nnzb, (const double*)B.z,
                            (double*)B.p, (double*)B.q, m.partials, m.scalars);
       else
-        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<float>, dim3(kPcgG), dim3(256), 0, it, m.N,
+        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<float>, dim3(kPcgGs), dim3(256), 0, it, m.N,
                            m.row_ptr, m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p,
                            (float*)B.q, m.partials, m.scalars);
     }
     {
       const char* PNAME = "pcg_update";
       if (precision == SYMX_F64)
-        SYMX_LAUNCH(m, PNAME, k_pcg_update<double>, dim3(kPcgG), dim3(256), 0, it, m.N,
+        SYMX_LAUNCH(m, PNAME, k_pcg_update<double>, dim3(kPcgGu), dim3(256), 0, it, m.N,
                            (const double*)B.Dinv, (double*)B.xs, (double*)B.r, (double*)B.z,
                            (const double*)B.p, (const double*)B.q, m.partials, m.scalars);
       else
-        SYMX_LAUNCH(m, PNAME, k_pcg_update<float>, dim3(kPcgG), dim3(256), 0, it, m.N,
+        SYMX_LAUNCH(m, PNAME, k_pcg_update<float>, dim3(kPcgGu), dim3(256), 0, it, m.N,
                            (const float*)B.Dinv, (float*)B.xs, (float*)B.r, (float*)B.z,
                            (const float*)B.p, (const float*)B.q, m.partials, m.scalars);
     }

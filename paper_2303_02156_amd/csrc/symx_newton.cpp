@@ -153,17 +153,21 @@ static symx_status project_elements(Mesh& m, const double* x, int precision, boo
   return SYMX_OK;
 }
 
-// Assemble gradient (float64) and/or Hessian values (precision) at x.
+// Assemble gradient (float64) and/or Hessian values (precision) at x.  With
+// dinv, the block-Jacobi inverses (N x 9, precision's type) are produced too.
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g, bool want_H,
-                     bool project, int precision, bool dirichlet, double* g_out) {
+                     bool project, int precision, bool dirichlet, double* g_out,
+                     void* dinv = nullptr) {
   if (want_H) TRY(ensure_values(m, precision));
   if (project && want_H) {
     ElemBuffers eb;
     TRY(project_elements(m, x, precision, want_g, &eb));
-    return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, &eb, g_out);
+    TRY(launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, &eb, g_out, nullptr));
+    return dinv ? launch_diag_inverse(m, precision, dinv) : SYMX_OK;
   }
   if (!want_g && !want_H) return SYMX_OK;
-  return launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, g_out);
+  return launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, g_out,
+                             want_H ? dinv : nullptr);
 }
 
 symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E) {
@@ -181,7 +185,7 @@ static symx_status dot(Mesh& m, const double* a, const double* b, double* out) {
 // PCG on H y = b (b float64), y accumulated into dx (float64).  Returns
 // iterations through *iters.
 static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rtol, int max_iter,
-                             double* dx, int* iters, bool* breakdown) {
+                             double* dx, int* iters, bool* breakdown, int slot) {
   Workspace* w = m.ws;
   PcgBuffers B{w->pcg[0], w->pcg[1], w->pcg[2], w->pcg[3], w->pcg[4], w->pcg[5]};
   const int pp = precision == SYMX_F64 ? SYMX_F64 : SYMX_F32;
@@ -190,7 +194,7 @@ static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rto
   int done_iters = 0;
   // first chunk sized from the previous solve, so that few launches run past
   // convergence and few host synchronisations are needed
-  int chunk = std::max(8, (3 * m.last_pcg_iters) / 4);
+  int chunk = std::max(8, (7 * m.last_pcg_iters[slot]) / 8);
   int k = 0;
   *breakdown = false;
   while (true) {
@@ -210,24 +214,24 @@ static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rto
     }
     chunk = 8;
   }
-  m.last_pcg_iters = done_iters;
+  m.last_pcg_iters[slot] = done_iters;
   *iters = done_iters;
   return launch_accumulate(m, pp, dx, B.xs);
 }
 
 // Linear solve with optional float64 refinement (F32_REFINED).
+// `slot` indexes the solve within a step (its Newton iteration); the iteration
+// count of the same solve in the previous step sizes the first PCG chunk.
 static symx_status linear_solve(Mesh& m, const symx_step_params& P, const double* g, double eta,
-                                double gnorm, int* pcg_iters, int* refinements) {
+                                double gnorm, int* pcg_iters, int* refinements, int slot) {
   Workspace* w = m.ws;
   const int n = (int)(3 * m.N);
   // b = -g ; dx = 0
   TRY(hip_check(hipMemsetAsync(w->dx, 0, n * sizeof(double), m.stream), "hipMemsetAsync"));
   TRY(launch_lincomb64(m, w->b, w->dx, g, -1.0, n));
-  const int prec_h = P.precision == SYMX_F64 ? SYMX_F64 : SYMX_F32;
-  TRY(launch_diag_inverse(m, prec_h, w->pcg[0]));
   int it = 0;
   bool bd = false;
-  TRY(pcg_solve(m, P.precision, w->b, eta, P.max_pcg, w->dx, &it, &bd));
+  TRY(pcg_solve(m, P.precision, w->b, eta, P.max_pcg, w->dx, &it, &bd, slot));
   *pcg_iters += it;
   if (P.precision != SYMX_F32_REFINED) return SYMX_OK;
   // float64 refinement: r = b - H dx (H float32 promoted); solve H c = r; dx += c
@@ -238,7 +242,8 @@ static symx_status linear_solve(Mesh& m, const symx_step_params& P, const double
     if (std::sqrt(rr) <= eta * gnorm) break;
     int it2 = 0;
     double tol = std::max(eta * gnorm / std::sqrt(rr), 1e-6);
-    TRY(pcg_solve(m, P.precision, w->res, std::min(tol, 0.5), P.max_pcg, w->dx, &it2, &bd));
+    TRY(pcg_solve(m, P.precision, w->res, std::min(tol, 0.5), P.max_pcg, w->dx, &it2, &bd,
+                  kPcgHistory - 1));
     *pcg_iters += it2;
     *refinements += 1;
   }
@@ -268,11 +273,13 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
   bool have_E0 = false;
   for (int it = 0;; ++it) {
     auto t0 = clk::now();
+    // gradient, Hessian and the block-Jacobi inverses (workspace pcg[0])
     if (pe == ph) {
-      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project != 0, ph, true, w->g));
+      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project != 0, ph, true, w->g, w->pcg[0]));
     } else {
       TRY(assemble(m, w->xk, w->xt, dt, true, false, false, pe, true, w->g));
-      TRY(assemble(m, w->xk, w->xt, dt, false, true, P.project != 0, ph, true, nullptr));
+      TRY(assemble(m, w->xk, w->xt, dt, false, true, P.project != 0, ph, true, nullptr,
+                   w->pcg[0]));
     }
     TRY(launch_dot64(m, w->g, w->g, n, m.scalars + D_GG));
     if (!have_E0) TRY(launch_energy(m, w->xk, w->xt, dt, pe, m.scalars + D_E0));
@@ -300,7 +307,8 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
     }
     auto t1 = clk::now();
     const double eta = std::min(0.5, std::sqrt(r / r0));
-    TRY(linear_solve(m, P, w->g, eta, r, &R->pcg_iters, &R->refinements));
+    TRY(linear_solve(m, P, w->g, eta, r, &R->pcg_iters, &R->refinements,
+                     std::min(it, kPcgHistory - 2)));
     R->ms_pcg += ms_since(t1);
     auto t2 = clk::now();
     // slope and the full step's energy in one round trip

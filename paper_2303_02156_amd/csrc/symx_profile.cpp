@@ -35,6 +35,15 @@ void Profiler::resolve() {
   pending.clear();
 }
 
+// Create events ahead of time so that profiled launches do not create them.
+void Profiler::reserve(size_t n) {
+  while (pool.size() < n) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    pool.push_back(e);
+  }
+}
+
 void Profiler::reset() {
   resolve();
   for (auto& d : dur) d.clear();
@@ -63,7 +72,6 @@ ProfPair prof_begin(Mesh& m, const char* name) {
 void prof_end(Mesh& m, const ProfPair& p) {
   if (p.id < 0) return;
   m.prof.pending.push_back({p.id, p.a, p.b});
-  if (m.prof.pending.size() > 8192) m.prof.resolve();
 }
 
 }  // namespace symxi
