@@ -76,6 +76,67 @@ def measured_traffic(kernel):
     return rec["bytes_per_launch"]
 
 
+def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
+    """C5: Poisson arrivals of time-step requests; p50/p99 latency, throughput."""
+    import numpy as np
+
+    import scenegen as sg
+    reqs = sg.config_c5_requests(n_requests, rate)
+    scenes = [sg.c5_request_scene(r) for r in reqs]
+    descs = [symx.scene_desc(sc) for sc in scenes]
+    prm = symx.step_params(dt=0.01, precision=symx.SYMX_F32_REFINED)
+    est = [symx.symx_server_estimate_bytes(d, symx.SYMX_F32_REFINED) for d, _ in descs]
+    n_tets = sum(sc.n_elements() for sc in scenes)
+    free, _ = torch.cuda.mem_get_info()
+
+    def run(budget, n_slots, paced):
+        srv = symx.symx_server_create(budget, n_slots)
+        t0 = time.perf_counter()
+        tickets = []
+        for r, (desc, _), sc in zip(reqs, descs, scenes):
+            if paced:
+                delay = t0 + r["t"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(symx.symx_server_submit(srv, desc, np.ascontiguousarray(sc.x0),
+                                                   np.ascontiguousarray(sc.v0), prm))
+        lat, ends, ok, statuses, failed = [], [], 0, {}, []
+        for i, tk in enumerate(tickets):
+            st, rep, times = symx.symx_server_poll(srv, tk, 1)
+            ok += int(st == 0)
+            name = symx.STATUS.get(st, str(st))
+            statuses[name] = statuses.get(name, 0) + 1
+            if st != 0:
+                failed.append({"request": i, "n": reqs[i]["n"], "status": name,
+                               "error": symx.load().symx_last_error().decode(),
+                               "report": {k: rep.as_dict()[k] for k in
+                                          ("newton_iters", "pcg_iters", "dt_halvings")}})
+            lat.append(times[2] - times[0])
+            ends.append(times[2])
+        stats = symx.symx_server_get_stats(srv)
+        symx.symx_server_destroy(srv)
+        span_s = max(ends) / 1e3  # server creation to last completion
+        return {"budget_gb": round(budget / 1e9, 3), "slots": n_slots,
+                "arrivals": "poisson 200/s" if paced else "all at t=0",
+                "completed_ok": ok, "statuses": statuses, "failed": failed[:8],
+                "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "requests_per_s": round(float(len(reqs) / span_s), 2),
+                "melem_steps_per_s": round(float(n_tets / span_s / 1e6), 3),
+                "peak_active": stats.peak_active, "peak_gb": round(stats.peak_bytes / 1e9, 3)}
+
+    out = {"requests": n_requests, "tets_total": n_tets,
+           "n_range": [min(r["n"] for r in reqs), max(r["n"] for r in reqs)]}
+    out["full_budget"] = run(int(0.8 * free), slots, True)
+    log(f"serving full budget: {out['full_budget']}")
+    binding = sum(sorted(est)[-3:])
+    out["binding_budget"] = run(binding, slots, True)
+    log(f"serving binding budget: {out['binding_budget']}")
+    out["sequential"] = run(int(0.8 * free), 1, False)
+    log(f"serving sequential: {out['sequential']}")
+    return out
+
+
 def cpu_baseline(seconds_target=10.0):
     """FP64 numpy oracle: eval + assembly (E, g, BSR) of a 24^3 cube of the same
     workload recipe, repeated until ~seconds_target of CPU work."""
@@ -124,6 +185,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64-newton", action="store_true")
     ap.add_argument("--no-projection", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run plain 512 MiB device copies first (byte-counter calibration)")
     args = ap.parse_args()
@@ -145,6 +208,9 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     symx.load()
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(symx, torch)}), flush=True)
+        return
     if args.calib_copy:
         # a plain copy kernel of known size: 512 MiB read + 512 MiB written per launch
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -278,6 +344,11 @@ def main():
             d["busy_gbs"] = round(b_ / (msb / nb_ * 1e-3) / 1e9, 1)
         kernels[k] = d
 
+    serving = None
+    if not args.no_serving:
+        log("serving (256 requests, Poisson 200/s)...")
+        serving = serving_bench(symx, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)...")
@@ -321,7 +392,8 @@ def main():
                            "f64": None if ms_f64 is None else round(ms_f64, 3)},
         "newton_f32_refined": summary(reps_f32r),
         "newton_f64": summary(reps_f64),
-        "p99_latency_ms": None,
+        "p99_latency_ms": None if serving is None else serving["full_budget"]["p99_ms"],
+        "serving": serving,
         "mesh_setup_s": round(setup_s, 3),
         "kernels_f32_refined_steps": kernels,
         "roofline": roofline,

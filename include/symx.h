@@ -45,7 +45,8 @@ typedef enum {
   SYMX_ERR_NONFINITE = 4,     /* NaN/Inf met in positions, energy or gradient */
   SYMX_ERR_NOT_CONVERGED = 5, /* Newton did not converge within all halvings */
   SYMX_ERR_LINE_SEARCH = 6,   /* line search failed within all halvings */
-  SYMX_ERR_BUDGET = 7         /* request exceeds a configured memory budget */
+  SYMX_ERR_BUDGET = 7,        /* request exceeds a configured memory budget */
+  SYMX_PENDING = 8            /* serving: the request has not finished yet */
 } symx_status;
 
 /* Arithmetic of the element kernels and of the linear solve. */
@@ -219,6 +220,42 @@ symx_status symx_mesh_set_profiling(symx_mesh mesh, int32_t enable);
 symx_status symx_mesh_get_kernel_time(symx_mesh mesh, const char* name, double min_ms,
                                       int64_t* launches, double* total_ms);
 symx_status symx_mesh_kernel_names(symx_mesh mesh, char* buf, int64_t buf_len);
+
+/* ---- serving: time-step requests of many scenes on one GPU -------------------
+ * Requests wait in a FIFO queue and are admitted when one of max_slots slots
+ * is free and the request's estimated device footprint fits in what is left
+ * of hbm_budget_bytes.  Each slot has its own worker thread and HIP stream;
+ * admitted requests run concurrently (their kernels overlap on the device).
+ * A request is one implicit-Euler time step (as symx_newton_step) of its own
+ * scene; the result does not depend on the other requests in flight. */
+typedef struct symx_server_s* symx_server;
+typedef struct {
+  uint64_t budget_bytes, in_use_bytes, peak_bytes;
+  int64_t queued, completed;
+  int32_t active, peak_active, max_slots;
+} symx_server_stats;
+
+/* Create a server on the current HIP device; max_slots in 1..64. */
+symx_status symx_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, symx_server* out);
+/* Queue a request.  All host inputs are copied; x_host, v_host are N x 3
+ * float64.  Returns SYMX_ERR_BUDGET if the scene can never fit the budget.
+ * *ticket identifies the request. */
+symx_status symx_server_submit(symx_server server, const symx_mesh_desc* scene,
+                               const double* x_host, const double* v_host,
+                               const symx_step_params* params, int64_t* ticket);
+/* Result of a request: SYMX_PENDING while it runs (wait = 0), otherwise the
+ * step's status, with x_out, v_out (host N x 3, may be NULL), the report and
+ * times_ms[3] = {submitted, started, finished} in ms since server creation
+ * (may be NULL).  A finished ticket is released by this call. */
+symx_status symx_server_poll(symx_server server, int64_t ticket, int32_t wait, double* x_out,
+                             double* v_out, symx_step_report* report, double* times_ms);
+symx_status symx_server_get_stats(symx_server server, symx_server_stats* stats);
+/* Device footprint the server charges against its budget for a scene solved
+ * at `precision` (an upper bound of the mesh and Newton workspace). */
+symx_status symx_server_estimate_bytes(const symx_mesh_desc* scene, int32_t precision,
+                                       uint64_t* bytes);
+/* Waits for running requests, abandons queued ones, frees the server. */
+symx_status symx_server_destroy(symx_server server);
 
 const char* symx_status_string(symx_status status);
 const char* symx_last_error(void);

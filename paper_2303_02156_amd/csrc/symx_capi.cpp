@@ -13,6 +13,22 @@ struct symx_mesh_s {
 };
 
 namespace symxi {
+struct Server;
+symx_status server_create(uint64_t budget, int32_t max_slots, Server** out);
+void server_destroy(Server* s);
+symx_status server_submit(Server* s, const symx_mesh_desc* d, const double* x, const double* v,
+                          const symx_step_params* P, int64_t* ticket);
+symx_status server_poll(Server* s, int64_t ticket, int32_t wait, double* x_out, double* v_out,
+                        symx_step_report* rep, double* times_ms);
+void server_stats(Server* s, symx_server_stats* out);
+size_t estimate_request_bytes(const symx_mesh_desc& d, int precision);
+}  // namespace symxi
+
+struct symx_server_s {
+  symxi::Server* s;
+};
+
+namespace symxi {
 
 static thread_local std::string g_last_error;
 
@@ -25,6 +41,7 @@ symx_status hip_check(hipError_t e, const char* what) {
 }
 
 symx_status mesh_create(const symx_mesh_desc* d, Mesh** out);
+void build_scatter(Mesh& m);
 void free_workspace(Mesh& m);
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
                      bool want_H, bool project, int precision, bool dirichlet, double* g_out,
@@ -150,8 +167,10 @@ symx_status symx_mesh_get_pattern(symx_mesh mesh, int32_t* row_ptr, int32_t* col
   Mesh& m = *mesh->m;
   if (row_ptr) std::memcpy(row_ptr, m.h_row_ptr.data(), m.h_row_ptr.size() * sizeof(int32_t));
   if (col_idx) std::memcpy(col_idx, m.h_col_idx.data(), m.h_col_idx.size() * sizeof(int32_t));
-  if (scatter_map)
+  if (scatter_map) {
+    build_scatter(m);
     std::memcpy(scatter_map, m.h_scatter.data(), m.h_scatter.size() * sizeof(int32_t));
+  }
   return SYMX_OK;
   GUARD_END
 }
@@ -290,6 +309,77 @@ symx_status symx_mesh_kernel_names(symx_mesh mesh, char* buf, int64_t buf_len) {
   GUARD_END
 }
 
+symx_status symx_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, symx_server* out) {
+  GUARD_BEGIN
+  if (!out || max_slots < 1 || max_slots > 64 || hbm_budget_bytes == 0) {
+    set_error("invalid server arguments");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  Server* s = nullptr;
+  symx_status st = server_create(hbm_budget_bytes, max_slots, &s);
+  if (st != SYMX_OK) return st;
+  *out = new symx_server_s{s};
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_server_submit(symx_server server, const symx_mesh_desc* scene,
+                               const double* x_host, const double* v_host,
+                               const symx_step_params* params, int64_t* ticket) {
+  GUARD_BEGIN
+  if (!server || !server->s) {
+    set_error("null server handle");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  return server_submit(server->s, scene, x_host, v_host, params, ticket);
+  GUARD_END
+}
+
+symx_status symx_server_poll(symx_server server, int64_t ticket, int32_t wait, double* x_out,
+                             double* v_out, symx_step_report* report, double* times_ms) {
+  GUARD_BEGIN
+  if (!server || !server->s) {
+    set_error("null server handle");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  return server_poll(server->s, ticket, wait, x_out, v_out, report, times_ms);
+  GUARD_END
+}
+
+symx_status symx_server_get_stats(symx_server server, symx_server_stats* stats) {
+  GUARD_BEGIN
+  if (!server || !server->s || !stats) {
+    set_error("null server handle or stats");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  server_stats(server->s, stats);
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_server_estimate_bytes(const symx_mesh_desc* scene, int32_t precision,
+                                       uint64_t* bytes) {
+  GUARD_BEGIN
+  if (!scene || !bytes || scene->n_energies < 1 || scene->n_energies > kMaxSets ||
+      !scene->energies) {
+    set_error("invalid scene descriptor");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  *bytes = estimate_request_bytes(*scene, precision);
+  return SYMX_OK;
+  GUARD_END
+}
+
+symx_status symx_server_destroy(symx_server server) {
+  GUARD_BEGIN
+  if (!server) return SYMX_OK;
+  server_destroy(server->s);
+  delete server;
+  return SYMX_OK;
+  GUARD_END
+}
+
 const char* symx_status_string(symx_status s) {
   switch (s) {
     case SYMX_OK: return "ok";
@@ -300,6 +390,7 @@ const char* symx_status_string(symx_status s) {
     case SYMX_ERR_NOT_CONVERGED: return "not converged";
     case SYMX_ERR_LINE_SEARCH: return "line search failed";
     case SYMX_ERR_BUDGET: return "memory budget exceeded";
+    case SYMX_PENDING: return "pending";
   }
   return "unknown status";
 }

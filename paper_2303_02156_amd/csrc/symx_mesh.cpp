@@ -13,9 +13,11 @@
 // also stores the row-local slots of the blocks it touches, in the relabelled
 // node order (a first, then the others ascending) that the row kernels use.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
 
 #include "symx_internal.h"
 
@@ -69,6 +71,20 @@ SetsDev Mesh::sets_dev() const {
   return d;
 }
 
+// Run f(lo, hi) over [0, n) split into contiguous chunks on host threads.
+template <typename F>
+static void parallel_chunks(int64_t n, int64_t min_chunk, F f) {
+  int T = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
+  T = (int)std::max<int64_t>(1, std::min<int64_t>(T, n / std::max<int64_t>(min_chunk, 1)));
+  if (T <= 1) {
+    f((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) th.emplace_back(f, n * t / T, n * (t + 1) / T);
+  for (auto& x : th) x.join();
+}
+
 static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s) {
   s.kind = d.kind;
   if (d.kind == SYMX_SNH_TET4 || d.kind == SYMX_HINGE4)
@@ -85,19 +101,26 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s) {
   }
   s.n_elem = d.n_elem;
   s.conn.assign(d.conn, d.conn + d.n_elem * s.k);
-  for (int64_t e = 0; e < s.n_elem; ++e)
-    for (int a = 0; a < s.k; ++a) {
-      int32_t v = s.conn[e * s.k + a];
-      if (v < 0 || v >= m.N) {
-        set_error("node id out of range in element " + std::to_string(e));
-        return SYMX_ERR_INVALID_ARG;
-      }
-      for (int b = 0; b < a; ++b)
-        if (s.conn[e * s.k + b] == v) {
-          set_error("repeated node in element " + std::to_string(e));
-          return SYMX_ERR_INVALID_ARG;
+  {
+    std::atomic<int64_t> bad_range{-1}, bad_repeat{-1};
+    parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
+      for (int64_t e = e0; e < e1; ++e)
+        for (int a = 0; a < s.k; ++a) {
+          const int32_t v = s.conn[e * s.k + a];
+          if (v < 0 || v >= m.N) bad_range = e;
+          for (int b = 0; b < a; ++b)
+            if (s.conn[e * s.k + b] == v) bad_repeat = e;
         }
+    });
+    if (bad_range >= 0) {
+      set_error("node id out of range in element " + std::to_string(bad_range.load()));
+      return SYMX_ERR_INVALID_ARG;
     }
+    if (bad_repeat >= 0) {
+      set_error("repeated node in element " + std::to_string(bad_repeat.load()));
+      return SYMX_ERR_INVALID_ARG;
+    }
+  }
   const double* X = m.h_X.data();
   auto P = [&](int64_t e, int a) {
     int64_t n = s.conn[e * s.k + a];
@@ -124,15 +147,20 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s) {
   }
   // rest measures, masses, hinge weights
   if (d.kind == SYMX_SNH_TET4) {
+    std::vector<double> vol(s.n_elem);
+    parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
+      for (int64_t e = e0; e < e1; ++e) {
+        V3 x0 = P(e, 0);
+        V3 d1 = sub(P(e, 1), x0), d2 = sub(P(e, 2), x0), d3 = sub(P(e, 3), x0);
+        vol[e] = std::fabs(dot(d1, cross(d2, d3))) / 6.0;
+      }
+    });
     for (int64_t e = 0; e < s.n_elem; ++e) {
-      V3 x0 = P(e, 0);
-      V3 d1 = sub(P(e, 1), x0), d2 = sub(P(e, 2), x0), d3 = sub(P(e, 3), x0);
-      double vol = std::fabs(dot(d1, cross(d2, d3))) / 6.0;
-      if (!(vol > 0.0)) {
+      if (!(vol[e] > 0.0)) {
         set_error("degenerate rest tet " + std::to_string(e));
         return SYMX_ERR_INVALID_ARG;
       }
-      for (int a = 0; a < 4; ++a) m.h_mass[s.conn[e * 4 + a]] += d.density * vol / 4.0;
+      for (int a = 0; a < 4; ++a) m.h_mass[s.conn[e * 4 + a]] += d.density * vol[e] / 4.0;
     }
   } else if (d.kind == SYMX_STVK_TRI3) {
     for (int64_t e = 0; e < s.n_elem; ++e) {
@@ -185,95 +213,103 @@ static symx_status build_pattern(Mesh& m) {
     set_error("too many incidences");
     return SYMX_ERR_INVALID_ARG;
   }
-  std::vector<uint32_t> code(m.n_inc);
-  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-  for (int si = 0; si < (int)m.sets.size(); ++si) {
-    const SetHost& s = m.sets[si];
-    for (int64_t e = 0; e < s.n_elem; ++e)
-      for (int a = 0; a < s.k; ++a) code[fill[s.conn[e * s.k + a]]++] = inc_make(si, a, e);
-  }
-  // rows: sorted unique neighbour sets
-  m.h_row_ptr.assign(N + 1, 0);
-  std::vector<int32_t> cols;
-  cols.reserve(m.n_inc * 3 + N);
-  std::vector<int32_t> nb;
-  m.max_row_blocks = 0;
-  for (int64_t i = 0; i < N; ++i) {
-    nb.clear();
-    nb.push_back((int32_t)i);
-    for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
-      const SetHost& s = m.sets[inc_set(code[q])];
-      int64_t e = inc_elem(code[q]);
-      for (int b = 0; b < s.k; ++b) nb.push_back(s.conn[e * s.k + b]);
-    }
-    std::sort(nb.begin(), nb.end());
-    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
-    if ((int)nb.size() > kMaxRowBlocks) {
-      set_error("node " + std::to_string(i) + " couples to more than 255 nodes");
-      return SYMX_ERR_INVALID_ARG;
-    }
+  for (int64_t i = 0; i < N; ++i)
     if (cnt[i + 1] - cnt[i] > kRowWG) {
       set_error("node " + std::to_string(i) + " belongs to more than 256 elements");
       return SYMX_ERR_INVALID_ARG;
     }
-    m.max_row_blocks = std::max(m.max_row_blocks, (int)nb.size());
-    cols.insert(cols.end(), nb.begin(), nb.end());
-    m.h_row_ptr[i + 1] = (int32_t)cols.size();
+  std::vector<uint32_t> code(m.n_inc);
+  {
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int si = 0; si < (int)m.sets.size(); ++si) {
+      const SetHost& s = m.sets[si];
+      for (int64_t e = 0; e < s.n_elem; ++e)
+        for (int a = 0; a < s.k; ++a) code[fill[s.conn[e * s.k + a]]++] = inc_make(si, a, e);
+    }
   }
-  if (cols.size() >= (size_t(1) << 31)) {
-    set_error("too many blocks");
-    return SYMX_ERR_INVALID_ARG;
-  }
-  m.h_col_idx.swap(cols);
-  m.nnzb = (int64_t)m.h_col_idx.size();
-  auto slot_of = [&](int32_t i, int32_t j) -> int {
-    const int32_t* b = m.h_col_idx.data() + m.h_row_ptr[i];
-    const int32_t* e = m.h_col_idx.data() + m.h_row_ptr[i + 1];
-    const int32_t* p = std::lower_bound(b, e, j);
-    return int(p - b);
-  };
-  // scatter map (all sets concatenated)
-  size_t total = 0;
-  for (const SetHost& s : m.sets) total += size_t(s.n_elem) * s.k * s.k;
-  m.h_scatter.resize(total);
-  size_t off = 0;
-  for (const SetHost& s : m.sets) {
-    for (int64_t e = 0; e < s.n_elem; ++e)
-      for (int a = 0; a < s.k; ++a) {
-        int32_t i = s.conn[e * s.k + a];
-        for (int b = 0; b < s.k; ++b)
-          m.h_scatter[off++] = m.h_row_ptr[i] + slot_of(i, s.conn[e * s.k + b]);
-      }
-  }
-  // incidence slots in the relabelled order (a first, then the others)
+  // Rows in parallel chunks: sorted unique neighbour list of each node, and
+  // for each incidence the row-local slots of its blocks in the relabelled
+  // node order (a first, then the others ascending).
   std::vector<uint32_t> slots(m.n_inc);
   std::vector<std::vector<int32_t>> inc_pos(m.sets.size());
   for (size_t si = 0; si < m.sets.size(); ++si) inc_pos[si].assign(m.sets[si].n_elem * m.sets[si].k, -1);
-  for (int64_t i = 0; i < N; ++i)
-    for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
-      int si = inc_set(code[q]);
-      const SetHost& s = m.sets[si];
-      int a = inc_local(code[q]);
-      int64_t e = inc_elem(code[q]);
-      uint32_t w = 0;
-      int bp = 0;
-      int order[4] = {a, -1, -1, -1};
-      for (int b = 0, t = 1; b < s.k; ++b)
-        if (b != a) order[t++] = b;
-      for (bp = 0; bp < 4; ++bp) {
-        uint32_t sl = kNoSlot;
-        if (bp < s.k) sl = (uint32_t)slot_of((int32_t)i, s.conn[e * s.k + order[bp]]);
-        w |= sl << (8 * bp);
+  std::vector<int32_t> row_len(N);
+  const int64_t n_chunks = std::min<int64_t>(64, std::max<int64_t>(1, N / 2048));
+  std::vector<std::vector<int32_t>> chunk_cols(n_chunks);
+  std::vector<int> chunk_bad(n_chunks, 0);
+  parallel_chunks(n_chunks, 1, [&](int64_t c0, int64_t c1) {
+    std::vector<int32_t> nb;
+    for (int64_t c = c0; c < c1; ++c) {
+      const int64_t r0 = N * c / n_chunks, r1 = N * (c + 1) / n_chunks;
+      std::vector<int32_t>& cols = chunk_cols[c];
+      for (int64_t i = r0; i < r1; ++i) {
+        nb.clear();
+        nb.push_back((int32_t)i);
+        for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
+          const SetHost& s = m.sets[inc_set(code[q])];
+          const int64_t e = inc_elem(code[q]);
+          for (int b = 0; b < s.k; ++b) nb.push_back(s.conn[e * s.k + b]);
+        }
+        std::sort(nb.begin(), nb.end());
+        nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+        if ((int)nb.size() > kMaxRowBlocks) chunk_bad[c] = 1;
+        row_len[i] = (int32_t)nb.size();
+        for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
+          const int si = inc_set(code[q]);
+          const SetHost& s = m.sets[si];
+          const int a = inc_local(code[q]);
+          const int64_t e = inc_elem(code[q]);
+          int order[4] = {a, -1, -1, -1};
+          for (int b = 0, t = 1; b < s.k; ++b)
+            if (b != a) order[t++] = b;
+          uint32_t w = 0;
+          for (int bp = 0; bp < 4; ++bp) {
+            uint32_t sl = kNoSlot;
+            if (bp < s.k) {
+              const int32_t j = s.conn[e * s.k + order[bp]];
+              sl = (uint32_t)(std::lower_bound(nb.begin(), nb.end(), j) - nb.begin());
+            }
+            w |= sl << (8 * bp);
+          }
+          slots[q] = w;
+          inc_pos[si][e * s.k + a] = (int32_t)q;
+        }
+        cols.insert(cols.end(), nb.begin(), nb.end());
       }
-      slots[q] = w;
-      inc_pos[si][e * s.k + a] = (int32_t)q;
     }
+  });
+  for (int64_t c = 0; c < n_chunks; ++c)
+    if (chunk_bad[c]) {
+      set_error("a node couples to more than 255 nodes");
+      return SYMX_ERR_INVALID_ARG;
+    }
+  m.h_row_ptr.assign(N + 1, 0);
+  m.max_row_blocks = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    m.h_row_ptr[i + 1] = m.h_row_ptr[i] + row_len[i];
+    m.max_row_blocks = std::max(m.max_row_blocks, (int)row_len[i]);
+  }
+  if ((int64_t)m.h_row_ptr[N] >= (int64_t(1) << 31) - 1) {
+    set_error("too many blocks");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  m.nnzb = m.h_row_ptr[N];
+  m.h_col_idx.resize(m.nnzb);
+  {
+    std::vector<int64_t> off(n_chunks + 1, 0);
+    for (int64_t c = 0; c < n_chunks; ++c) off[c + 1] = off[c] + (int64_t)chunk_cols[c].size();
+    parallel_chunks(n_chunks, 1, [&](int64_t c0, int64_t c1) {
+      for (int64_t c = c0; c < c1; ++c)
+        std::copy(chunk_cols[c].begin(), chunk_cols[c].end(), m.h_col_idx.begin() + off[c]);
+    });
+  }
+  chunk_cols.clear();
   // row batches: consecutive rows with <= kRowWG incidences and <= kRowWG blocks
   std::vector<int32_t> batch{0};
   int64_t bi = 0, bb = 0;
   for (int64_t i = 0; i < N; ++i) {
-    int64_t ni = cnt[i + 1] - cnt[i];
-    int64_t nbk = m.h_row_ptr[i + 1] - m.h_row_ptr[i];
+    const int64_t ni = cnt[i + 1] - cnt[i];
+    const int64_t nbk = row_len[i];
     if (i > batch.back() && (bi + ni > kRowWG || bb + nbk > kRowWG)) {
       batch.push_back((int32_t)i);
       bi = bb = 0;
@@ -287,55 +323,59 @@ static symx_status build_pattern(Mesh& m) {
   // the (incidence, relabelled node b >= 1) pairs that add to it, in incidence
   // order; entries are u16 = (incidence index within the batch << 2) | b.
   // blk_info[p] = (first entry relative to the batch's base << 8) | count.
-  std::vector<uint32_t> blk_info(m.nnzb, 0);
-  std::vector<uint16_t> centry;
-  centry.reserve(m.n_inc * 3);
   std::vector<int32_t> batch_entry(m.n_batch + 1, 0);
-  std::vector<int32_t> cnt_blk, fillp;
   for (int b = 0; b < m.n_batch; ++b) {
-    const int64_t r0 = batch[b], r1 = batch[b + 1];
-    const int64_t q0 = cnt[r0], p0 = m.h_row_ptr[r0];
-    const int64_t np = m.h_row_ptr[r1] - p0;
-    batch_entry[b] = (int32_t)centry.size();
-    cnt_blk.assign(np + 1, 0);
-    for (int64_t r = r0; r < r1; ++r)
-      for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
-        const int k = m.sets[inc_set(code[q])].k;
-        for (int bp = 1; bp < k; ++bp) {
-          const int64_t pl = m.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0;
-          cnt_blk[pl + 1]++;
+    int64_t ne = 0;
+    for (int64_t q = cnt[batch[b]]; q < cnt[batch[b + 1]]; ++q) ne += m.sets[inc_set(code[q])].k - 1;
+    batch_entry[b + 1] = batch_entry[b] + (int32_t)ne;
+  }
+  std::vector<uint32_t> blk_info(m.nnzb, 0);
+  std::vector<uint16_t> centry(batch_entry[m.n_batch]);
+  std::vector<int> batch_bad(m.n_batch, 0);
+  parallel_chunks(m.n_batch, 256, [&](int64_t b0, int64_t b1) {
+    std::vector<int32_t> cnt_blk, fillp;
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t r0 = batch[b], r1 = batch[b + 1];
+      const int64_t q0 = cnt[r0], p0 = m.h_row_ptr[r0];
+      const int64_t np = m.h_row_ptr[r1] - p0;
+      cnt_blk.assign(np + 1, 0);
+      for (int64_t r = r0; r < r1; ++r)
+        for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
+          const int k = m.sets[inc_set(code[q])].k;
+          for (int bp = 1; bp < k; ++bp)
+            cnt_blk[m.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0 + 1]++;
         }
+      for (int64_t i = 0; i < np; ++i) {
+        if (cnt_blk[i + 1] > 255) batch_bad[b] = 1;
+        blk_info[p0 + i] = (uint32_t(cnt_blk[i]) << 8) | uint32_t(cnt_blk[i + 1]);
+        cnt_blk[i + 1] += cnt_blk[i];
       }
-    for (int64_t i = 0; i < np; ++i) {
-      if (cnt_blk[i + 1] > 255) {
-        set_error("more than 255 elements share one node pair");
-        return SYMX_ERR_INVALID_ARG;
-      }
-      blk_info[p0 + i] = (uint32_t(cnt_blk[i]) << 8) | uint32_t(cnt_blk[i + 1]);
-      cnt_blk[i + 1] += cnt_blk[i];
+      if (cnt_blk[np] >= (1 << 24)) batch_bad[b] = 1;
+      uint16_t* base = centry.data() + batch_entry[b];
+      fillp.assign(cnt_blk.begin(), cnt_blk.end() - 1);
+      for (int64_t r = r0; r < r1; ++r)
+        for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
+          const int k = m.sets[inc_set(code[q])].k;
+          for (int bp = 1; bp < k; ++bp) {
+            const int64_t pl = m.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0;
+            base[fillp[pl]++] = (uint16_t)(((q - q0) << 2) | bp);
+          }
+        }
     }
-    if (cnt_blk[np] >= (1 << 24)) {
-      set_error("batch contribution list too long");
+  });
+  for (int b = 0; b < m.n_batch; ++b)
+    if (batch_bad[b]) {
+      set_error("more than 255 elements share one node pair");
       return SYMX_ERR_INVALID_ARG;
     }
-    const size_t base = centry.size();
-    centry.resize(base + cnt_blk[np]);
-    fillp.assign(cnt_blk.begin(), cnt_blk.end() - 1);
-    for (int64_t r = r0; r < r1; ++r)
-      for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
-        const int k = m.sets[inc_set(code[q])].k;
-        for (int bp = 1; bp < k; ++bp) {
-          const int64_t pl = m.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0;
-          centry[base + fillp[pl]++] = (uint16_t)(((q - q0) << 2) | bp);
-        }
-      }
-  }
-  batch_entry[m.n_batch] = (int32_t)centry.size();
   // device upload
   std::vector<int32_t> inc_ptr32(N + 1);
   for (int64_t i = 0; i <= N; ++i) inc_ptr32[i] = (int32_t)cnt[i];
   std::vector<int32_t> diag(N);
-  for (int64_t i = 0; i < N; ++i) diag[i] = m.h_row_ptr[i] + slot_of((int32_t)i, (int32_t)i);
+  for (int64_t i = 0; i < N; ++i) {
+    const int32_t* b = m.h_col_idx.data() + m.h_row_ptr[i];
+    diag[i] = m.h_row_ptr[i] + (int32_t)(std::lower_bound(b, b + row_len[i], (int32_t)i) - b);
+  }
   TRY(upload(&m.row_ptr, m.h_row_ptr.data(), N + 1));
   TRY(upload(&m.col_idx, m.h_col_idx.data(), m.nnzb));
   TRY(upload(&m.diag_pos, diag.data(), N));
@@ -349,6 +389,27 @@ static symx_status build_pattern(Mesh& m) {
   for (size_t si = 0; si < m.sets.size(); ++si)
     TRY(upload(&m.sets[si].d_inc_pos, inc_pos[si].data(), inc_pos[si].size()));
   return SYMX_OK;
+}
+
+// Scatter map of every set (element e, local a, b -> block position), built
+// on demand for symx_mesh_get_pattern.
+void build_scatter(Mesh& m) {
+  if (!m.h_scatter.empty()) return;
+  size_t total = 0;
+  for (const SetHost& s : m.sets) total += size_t(s.n_elem) * s.k * s.k;
+  m.h_scatter.resize(total);
+  size_t off = 0;
+  for (const SetHost& s : m.sets) {
+    for (int64_t e = 0; e < s.n_elem; ++e)
+      for (int a = 0; a < s.k; ++a) {
+        const int32_t i = s.conn[e * s.k + a];
+        const int32_t* b = m.h_col_idx.data() + m.h_row_ptr[i];
+        const int32_t* en = m.h_col_idx.data() + m.h_row_ptr[i + 1];
+        for (int c = 0; c < s.k; ++c)
+          m.h_scatter[off++] =
+              m.h_row_ptr[i] + (int32_t)(std::lower_bound(b, en, s.conn[e * s.k + c]) - b);
+      }
+  }
 }
 
 static symx_status upload_mesh(Mesh& m) {
@@ -369,7 +430,10 @@ static symx_status upload_mesh(Mesh& m) {
   }
   TRY(upload<double>(&m.partials, nullptr, kMaxPartials));
   TRY(upload<double>(&m.scalars, nullptr, 64));
-  TRY(hip_check(hipMemset(m.scalars, 0, 64 * sizeof(double)), "hipMemset"));
+  // on the mesh's stream: a null-stream memset is not ordered with work on a
+  // non-blocking stream, so the first flag read could see stale memory
+  TRY(hip_check(hipMemsetAsync(m.scalars, 0, 64 * sizeof(double), m.stream), "hipMemsetAsync"));
+  TRY(hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize"));
   // the non-finite flag shares the scalar array (slot 24) so the Newton driver
   // reads results and flag with one copy
   m.nonfinite = reinterpret_cast<int*>(m.scalars + 24);

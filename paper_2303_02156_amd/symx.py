@@ -18,7 +18,8 @@ LIBPATH = os.path.join(_PKG, "libsymx.so")
 
 SYMX_OK = 0
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NONFINITE",
-          5: "NOT_CONVERGED", 6: "LINE_SEARCH", 7: "BUDGET"}
+          5: "NOT_CONVERGED", 6: "LINE_SEARCH", 7: "BUDGET", 8: "PENDING"}
+SYMX_PENDING = 8
 SYMX_F64, SYMX_F32, SYMX_F32_REFINED = 0, 1, 2
 SYMX_SNH_TET4, SYMX_STVK_TRI3, SYMX_HINGE4 = 0, 1, 2
 SYMX_EVAL_E, SYMX_EVAL_GRAD, SYMX_EVAL_HESS, SYMX_PROJECT_PSD, SYMX_DIRICHLET = 1, 2, 4, 8, 16
@@ -65,6 +66,12 @@ class StepReport(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("in_use_bytes", C.c_uint64),
+                ("peak_bytes", C.c_uint64), ("queued", C.c_int64), ("completed", C.c_int64),
+                ("active", C.c_int32), ("peak_active", C.c_int32), ("max_slots", C.c_int32)]
+
+
 EXPORTS = {
     "symx_step_params_default": (None, [C.POINTER(StepParams)]),
     "symx_mesh_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(C.c_void_p)]),
@@ -83,6 +90,15 @@ EXPORTS = {
     "symx_mesh_get_kernel_time": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double,
                                             C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "symx_mesh_kernel_names": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
+    "symx_server_create": (C.c_int, [C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "symx_server_submit": (C.c_int, [C.c_void_p, C.POINTER(MeshDesc), C.c_void_p, C.c_void_p,
+                                     C.POINTER(StepParams), C.POINTER(C.c_int64)]),
+    "symx_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.POINTER(StepReport), C.c_void_p]),
+    "symx_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "symx_server_destroy": (C.c_int, [C.c_void_p]),
+    "symx_server_estimate_bytes": (C.c_int, [C.POINTER(MeshDesc), C.c_int32,
+                                             C.POINTER(C.c_uint64)]),
     "symx_status_string": (C.c_char_p, [C.c_int]),
     "symx_last_error": (C.c_char_p, []),
 }
@@ -186,9 +202,72 @@ def symx_step_params_default():
     return p
 
 
+def symx_server_create(budget_bytes, max_slots):
+    h = C.c_void_p()
+    _check(load().symx_server_create(int(budget_bytes), int(max_slots), C.byref(h)),
+           "symx_server_create")
+    return h
+
+
+def symx_server_submit(h, desc, x_host, v_host, params):
+    t = C.c_int64(0)
+    _check(load().symx_server_submit(h, C.byref(desc), x_host.ctypes.data, v_host.ctypes.data,
+                                     C.byref(params), C.byref(t)), "symx_server_submit")
+    return t.value
+
+
+def symx_server_poll(h, ticket, wait, x_out=None, v_out=None):
+    rep = StepReport()
+    times = np.zeros(3)
+    st = load().symx_server_poll(h, ticket, int(wait),
+                                 None if x_out is None else x_out.ctypes.data,
+                                 None if v_out is None else v_out.ctypes.data,
+                                 C.byref(rep), times.ctypes.data)
+    return st, rep, times
+
+
+def symx_server_get_stats(h):
+    s = ServerStats()
+    _check(load().symx_server_get_stats(h, C.byref(s)), "symx_server_get_stats")
+    return s
+
+
+def symx_server_estimate_bytes(desc, precision):
+    b = C.c_uint64(0)
+    _check(load().symx_server_estimate_bytes(C.byref(desc), int(precision), C.byref(b)),
+           "symx_server_estimate_bytes")
+    return b.value
+
+
+def symx_server_destroy(h):
+    _check(load().symx_server_destroy(h), "symx_server_destroy")
+
+
 # --- convenience wrapper around a scene (marshalling only) -------------------
 def _ptr(a):
     return None if a is None else a.ctypes.data
+
+
+def scene_desc(scene, stream_handle=None):
+    """Build a MeshDesc for a scenegen.Scene-like object.  Returns (desc, keep):
+    `keep` holds the arrays the descriptor points to and must outlive its use."""
+    keep = []
+    descs = (EnergyDesc * len(scene.energies))()
+    for i, es in enumerate(scene.energies):
+        conn = np.ascontiguousarray(es.conn, dtype=np.int32)
+        young = None
+        if es.young_per_elem is not None:
+            young = np.ascontiguousarray(es.young_per_elem, dtype=np.float64)
+        keep += [conn, young]
+        descs[i] = EnergyDesc(es.kind, conn.shape[0], _ptr(conn), _ptr(young), float(es.young),
+                              float(es.poisson), float(es.thickness), float(es.bend_kb),
+                              float(es.density))
+    X = np.ascontiguousarray(scene.X, dtype=np.float64)
+    fixed = np.ascontiguousarray(scene.fixed, dtype=np.uint8)
+    keep += [descs, X, fixed]
+    desc = MeshDesc(scene.n_nodes, _ptr(X), len(scene.energies), descs, _ptr(fixed),
+                    C.c_void_p(stream_handle or 0))
+    return desc, keep
 
 
 class Mesh:
@@ -198,24 +277,10 @@ class Mesh:
         import torch
         self.torch = torch
         self.N = scene.n_nodes
-        keep = []
-        descs = (EnergyDesc * len(scene.energies))()
-        for i, es in enumerate(scene.energies):
-            conn = np.ascontiguousarray(es.conn, dtype=np.int32)
-            young = None
-            if es.young_per_elem is not None:
-                young = np.ascontiguousarray(es.young_per_elem, dtype=np.float64)
-            keep += [conn, young]
-            descs[i] = EnergyDesc(es.kind, conn.shape[0], _ptr(conn), _ptr(young), float(es.young),
-                                  float(es.poisson), float(es.thickness), float(es.bend_kb),
-                                  float(es.density))
-        X = np.ascontiguousarray(scene.X, dtype=np.float64)
-        fixed = np.ascontiguousarray(scene.fixed, dtype=np.uint8)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
-        desc = MeshDesc(self.N, _ptr(X), len(scene.energies), descs, _ptr(fixed),
-                        C.c_void_p(stream.cuda_stream))
+        desc, keep = scene_desc(scene, stream.cuda_stream)
         self.handle = symx_mesh_create(desc)
         self.info = symx_mesh_get_info(self.handle)
         self.kinds = [es.kind for es in scene.energies]

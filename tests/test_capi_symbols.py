@@ -48,7 +48,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_status_strings(lib):
-    for s in range(8):
+    for s in range(9):
         assert lib.symx_status_string(s)
     assert lib.symx_status_string(99) == b"unknown status"
 
@@ -62,6 +62,7 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(symx.BsrView) == 8 * 5 + 8
     assert C.sizeof(symx.StepParams) == 8 * 5 + 4 * 7 + 4
     assert C.sizeof(symx.StepReport) == 4 * 6 + 8 * 8
+    assert C.sizeof(symx.ServerStats) == 8 * 5 + 4 * 3 + 4
 
 
 def test_null_arguments_rejected_without_gpu(lib):
@@ -71,5 +72,8 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.symx_mesh_create(None, C.byref(h)) == 1
     assert lib.symx_mesh_get_info(None, None) == 1
     assert lib.symx_newton_step(None, None, None, None, None) == 1
+    assert lib.symx_server_create(0, 4, C.byref(h)) == 1
+    assert lib.symx_server_create(1 << 30, 0, C.byref(h)) == 1
+    assert lib.symx_server_poll(None, 1, 0, None, None, None, None) == 1
     assert b"null" in lib.symx_last_error() or lib.symx_last_error()
     assert symx.STATUS[1] == "INVALID_ARG"
