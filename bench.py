@@ -137,6 +137,154 @@ def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
     return out
 
 
+def trajectory(symx, torch, scene, precision, steps, dt):
+    """Run `steps` implicit-Euler steps; returns (x, v, reports, ms per step)."""
+    mesh = symx.Mesh(scene)
+    x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    prm = symx.step_params(dt=dt, precision=precision, max_pcg=500)
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        st, rep = mesh.newton_step(x, v, prm)
+        reps.append(rep.as_dict())
+        log(f"  {scene.name} {symx.STATUS[st]} step {k}: newton {rep.newton_iters} pcg "
+            f"{rep.pcg_iters} halvings {rep.dt_halvings} {rep.ms_total:.1f} ms")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = (x.cpu().numpy(), v.cpu().numpy(), reps, ms)
+    mesh.close()
+    return out
+
+
+def precision_c4(symx, torch, n=64, steps=10):
+    """C4: stiff heterogeneous compressed grid, FP32-refined against all-FP64.
+
+    The FP64 run chooses the time steps (with dt halving); the FP32-refined
+    runs reuse that exact dt sequence with halving off, so both reach the same
+    simulated times:
+      per step   from each FP64 state, one FP32-refined step, compared with the
+                 next FP64 state (relative to that step's displacement)
+      trajectory FP32-refined from the start along the same dt sequence,
+                 compared after all steps (relative to the total displacement)
+    """
+    import numpy as np
+
+    import scenegen as sg
+    scene = sg.config_c4(n)
+    mesh = symx.Mesh(scene)
+    x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    states, dts, E64, ms64 = [(scene.x0.copy(), scene.v0.copy())], [], [], []
+    p64 = symx.step_params(dt=scene.dt, precision=symx.SYMX_F64, max_pcg=500)
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rep = mesh.newton_step(x, v, p64)
+        torch.cuda.synchronize()
+        ms64.append((time.perf_counter() - t0) * 1e3)
+        if st != 0:
+            mesh.close()
+            return {"error": f"FP64 step {k} failed: {symx.STATUS[st]}"}
+        dts.append(rep.dt_used)
+        E64.append(rep.energy)
+        states.append((x.cpu().numpy(), v.cpu().numpy()))
+        log(f"  C4 f64 step {k}: dt {rep.dt_used:.3g} newton {rep.newton_iters} "
+            f"pcg {rep.pcg_iters} halvings {rep.dt_halvings}")
+
+    def step32(xs, vs, dt):
+        xd = torch.tensor(xs, dtype=torch.float64, device="cuda")
+        vd = torch.tensor(vs, dtype=torch.float64, device="cuda")
+        prm = symx.step_params(dt=dt, precision=symx.SYMX_F32_REFINED, max_pcg=500,
+                               max_halvings=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rep = mesh.newton_step(xd, vd, prm)
+        torch.cuda.synchronize()
+        return st, rep, xd.cpu().numpy(), vd.cpu().numpy(), (time.perf_counter() - t0) * 1e3
+
+    local_pos, local_E, ms32 = [], [], []
+    for k in range(steps):
+        st, rep, x32, _, ms = step32(states[k][0], states[k][1], dts[k])
+        ms32.append(ms)
+        if st != 0:
+            local_pos.append(float("inf"))
+            continue
+        local_pos.append(float(np.max(np.linalg.norm(x32 - states[k + 1][0], axis=1))))
+        local_E.append((rep.energy - E64[k]) / abs(E64[k]))
+    xs, vs = states[0]
+    traj_ok, fail_at = True, None
+    for k in range(steps):
+        st, rep, xs, vs, _ = step32(xs, vs, dts[k])
+        if st != 0:
+            traj_ok, fail_at = False, k
+            break
+    out = {"workload": f"C4: {n}^3 cubes x 6 SNH tets, E ~ logU(1e4, 1e7) seed 4, 30% "
+                       "compression, top and bottom fixed, dt 0.01 with halving",
+           "steps": steps, "dt_sequence": dts,
+           "ms_per_step": {"f32_refined_same_dt": round(float(np.mean(ms32)), 3),
+                           "f64": round(float(np.mean(ms64)), 3)},
+           "per_step_max_abs_position_error_m": max(local_pos),
+           "per_step_max_rel_position_error": max(local_pos) / float(
+               max(np.max(np.linalg.norm(s[0] - scene.x0, axis=1)) for s in states[1:])),
+           "per_step_max_rel_energy_error": max(abs(e) for e in local_E) if local_E else None,
+           "per_step_abs_position_error_m": [float("%.3g" % e) for e in local_pos],
+           "per_step_signed_rel_energy_diff_f32r_minus_f64": [float("%.3g" % e) for e in local_E],
+           "per_step_note": "steps whose energies differ reached different local minima of the "
+                            "non-convex incremental potential (both meet the 1e-6 residual test)",
+           "trajectory_converged": traj_ok, "trajectory_failed_at_step": fail_at}
+    if traj_ok:
+        xT = states[-1][0]
+        disp = np.max(np.linalg.norm(xT - scene.x0, axis=1))
+        out["trajectory_max_rel_position_error"] = float(
+            np.max(np.linalg.norm(xs - xT, axis=1)) / disp)
+        out["trajectory_max_abs_position_error_m"] = float(np.max(np.linalg.norm(xs - xT, axis=1)))
+        out["trajectory_rel_energy_error"] = float(abs(rep.energy - E64[-1]) / abs(E64[-1]))
+    mesh.close()
+    return out
+
+
+def mixed_c3(symx, torch, steps=20):
+    """C3: 512^2 cloth (membrane + hinges) beside a 32^3 tet block, FP32-refined."""
+    import scenegen as sg
+    scene = sg.config_c3()
+    mesh = symx.Mesh(scene)
+    info = mesh.info
+    dt = scene.dt
+    import numpy as np
+    xt = torch.tensor(scene.x0 + dt * scene.v0 + dt * dt * np.asarray(scene.gravity)[None, :],
+                      dtype=torch.float64, device="cuda")
+    x0 = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(x0)
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    ms = []
+    for r in range(13):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        symx.symx_assemble_bsr(mesh.handle, x0.data_ptr(), xt.data_ptr(), dt, flags,
+                               symx.SYMX_F32, g.data_ptr())
+        b.record()
+        b.synchronize()
+        if r >= 3:
+            ms.append(a.elapsed_time(b))
+    asm_ms = statistics.median(ms)
+    mesh.close()
+    n_elem = scene.n_elements()
+    _, _, reps, ms_step = trajectory(symx, torch, scene, symx.SYMX_F32_REFINED, steps, dt)
+    return {"workload": "C3: 512^2 cloth (524,288 StVK triangles, 785,408 hinges, pinned edge) "
+                        "+ 32^3-cube SNH block (196,608 tets), dt 1/60",
+            "elements": n_elem, "nnzb": int(info.nnzb),
+            "assembly_ms_f32": round(asm_ms, 4),
+            "melem_per_s_f32": round(n_elem / (asm_ms * 1e-3) / 1e6, 2),
+            "steps": steps, "ms_per_step_f32_refined": round(ms_step, 3),
+            "newton_iters": sum(r["newton_iters"] for r in reps),
+            "pcg_iters": sum(r["pcg_iters"] for r in reps),
+            "all_converged": all(r["status"] == 0 for r in reps),
+            "dt_halvings": sum(r["dt_halvings"] for r in reps)}
+
+
 def cpu_baseline(seconds_target=10.0):
     """FP64 numpy oracle: eval + assembly (E, g, BSR) of a 24^3 cube of the same
     workload recipe, repeated until ~seconds_target of CPU work."""
@@ -187,6 +335,9 @@ def main():
     ap.add_argument("--no-projection", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--only", choices=["c3", "c4"], help="run only this extra workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run plain 512 MiB device copies first (byte-counter calibration)")
     args = ap.parse_args()
@@ -210,6 +361,12 @@ def main():
     symx.load()
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(symx, torch)}), flush=True)
+        return
+    if args.only == "c3":
+        print(json.dumps({"c3": mixed_c3(symx, torch)}), flush=True)
+        return
+    if args.only == "c4":
+        print(json.dumps({"c4": precision_c4(symx, torch)}), flush=True)
         return
     if args.calib_copy:
         # a plain copy kernel of known size: 512 MiB read + 512 MiB written per launch
@@ -344,6 +501,13 @@ def main():
             d["busy_gbs"] = round(b_ / (msb / nb_ * 1e-3) / 1e9, 1)
         kernels[k] = d
 
+    c4 = None if args.no_c4 else precision_c4(symx, torch)
+    if c4:
+        log(f"c4: {c4}")
+    c3 = None if args.no_c3 else mixed_c3(symx, torch)
+    if c3:
+        log(f"c3: {c3}")
+
     serving = None
     if not args.no_serving:
         log("serving (256 requests, Poisson 200/s)...")
@@ -394,6 +558,8 @@ def main():
         "newton_f64": summary(reps_f64),
         "p99_latency_ms": None if serving is None else serving["full_budget"]["p99_ms"],
         "serving": serving,
+        "c4_precision": c4,
+        "c3_mixed": c3,
         "mesh_setup_s": round(setup_s, 3),
         "kernels_f32_refined_steps": kernels,
         "roofline": roofline,

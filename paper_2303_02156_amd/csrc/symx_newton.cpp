@@ -234,6 +234,9 @@ static symx_status linear_solve(Mesh& m, const symx_step_params& P, const double
   TRY(pcg_solve(m, P.precision, w->b, eta, P.max_pcg, w->dx, &it, &bd, slot));
   *pcg_iters += it;
   if (P.precision != SYMX_F32_REFINED) return SYMX_OK;
+  // Refinement corrects what single precision loses; a solve that stopped at
+  // its iteration limit (or on breakdown) is used as is, as in float64 mode.
+  if (bd || it >= P.max_pcg) return SYMX_OK;
   // float64 refinement: r = b - H dx (H float32 promoted); solve H c = r; dx += c
   for (int k = 0; k < P.max_refine; ++k) {
     TRY(launch_residual64(m, SYMX_F32, w->dx, w->b, w->res));
@@ -246,6 +249,7 @@ static symx_status linear_solve(Mesh& m, const symx_step_params& P, const double
                   kPcgHistory - 1));
     *pcg_iters += it2;
     *refinements += 1;
+    if (bd || it2 >= P.max_pcg) break;
   }
   return SYMX_OK;
 }

@@ -307,3 +307,31 @@ def test_invalid_mesh_rejected(symx):
     s.energies[0].conn[0, 0] = 999
     with pytest.raises(symx.SymxError, match="INVALID_ARG"):
         symx.Mesh(s)
+
+
+def test_f32_refined_tracks_f64_trajectory(symx):
+    """Stiff heterogeneous compressed block (the C4 recipe at n=6): the FP32-
+    refined steps, taken with the FP64 run's time steps, stay within the Newton
+    tolerance of the FP64 trajectory."""
+    scene = sg.config_c4(6)
+    mesh = symx.Mesh(scene)
+    x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    dts, E64 = [], []
+    for _ in range(4):
+        st, rep = mesh.newton_step(x, v, symx.step_params(dt=0.01, precision=symx.SYMX_F64))
+        assert st == 0
+        dts.append(rep.dt_used)
+        E64.append(rep.energy)
+    x64 = x.cpu().numpy()
+    x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    for dt in dts:
+        st, rep = mesh.newton_step(x, v, symx.step_params(dt=dt, precision=symx.SYMX_F32_REFINED,
+                                                          max_halvings=0))
+        assert st == 0
+    x32 = x.cpu().numpy()
+    mesh.close()
+    disp = np.max(np.linalg.norm(x64 - scene.x0, axis=1))
+    assert np.max(np.linalg.norm(x32 - x64, axis=1)) <= 1e-3 * disp
+    assert abs(rep.energy - E64[-1]) <= 1e-6 * abs(E64[-1])
