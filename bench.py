@@ -100,7 +100,7 @@ def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
                     time.sleep(delay)
             tickets.append(symx.symx_server_submit(srv, desc, np.ascontiguousarray(sc.x0),
                                                    np.ascontiguousarray(sc.v0), prm))
-        lat, ends, ok, statuses, failed = [], [], 0, {}, []
+        lat, ends, ok, statuses, failed, phases = [], [], 0, {}, [], []
         for i, tk in enumerate(tickets):
             st, rep, times = symx.symx_server_poll(srv, tk, 1)
             ok += int(st == 0)
@@ -111,8 +111,9 @@ def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
                                "error": symx.load().symx_last_error().decode(),
                                "report": {k: rep.as_dict()[k] for k in
                                           ("newton_iters", "pcg_iters", "dt_halvings")}})
-            lat.append(times[2] - times[0])
-            ends.append(times[2])
+            lat.append(times[4] - times[0])
+            ends.append(times[4])
+            phases.append(np.diff(times))
         stats = symx.symx_server_get_stats(srv)
         symx.symx_server_destroy(srv)
         span_s = max(ends) / 1e3  # server creation to last completion
@@ -123,7 +124,10 @@ def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
                 "p99_ms": round(float(np.percentile(lat, 99)), 2),
                 "requests_per_s": round(float(len(reqs) / span_s), 2),
                 "melem_steps_per_s": round(float(n_tets / span_s / 1e6), 3),
-                "peak_active": stats.peak_active, "peak_gb": round(stats.peak_bytes / 1e9, 3)}
+                "peak_active": stats.peak_active, "peak_gb": round(stats.peak_bytes / 1e9, 3),
+                "pattern_cache": {"hits": stats.pattern_hits, "misses": stats.pattern_misses},
+                "mean_phase_ms": dict(zip(("queued", "setup", "step", "teardown"),
+                                          [round(float(v), 2) for v in np.mean(phases, axis=0)]))}
 
     out = {"requests": n_requests, "tets_total": n_tets,
            "n_range": [min(r["n"] for r in reqs), max(r["n"] for r in reqs)]}

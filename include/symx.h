@@ -227,11 +227,18 @@ symx_status symx_mesh_kernel_names(symx_mesh mesh, char* buf, int64_t buf_len);
  * of hbm_budget_bytes.  Each slot has its own worker thread and HIP stream;
  * admitted requests run concurrently (their kernels overlap on the device).
  * A request is one implicit-Euler time step (as symx_newton_step) of its own
- * scene; the result does not depend on the other requests in flight. */
+ * scene; the result does not depend on the other requests in flight.
+ * Device memory comes from a pool owned by the server, and the block pattern
+ * of a scene stays on the device after its request: a later request with the
+ * same node count, energy kinds and connectivity reuses it (only positions,
+ * materials and masses are rebuilt).  Idle patterns count against the budget
+ * and are evicted, least recently used first, when a request needs room. */
 typedef struct symx_server_s* symx_server;
 typedef struct {
   uint64_t budget_bytes, in_use_bytes, peak_bytes;
+  uint64_t pattern_cache_bytes;      /* idle cached patterns                    */
   int64_t queued, completed;
+  int64_t pattern_hits, pattern_misses;
   int32_t active, peak_active, max_slots;
 } symx_server_stats;
 
@@ -245,8 +252,9 @@ symx_status symx_server_submit(symx_server server, const symx_mesh_desc* scene,
                                const symx_step_params* params, int64_t* ticket);
 /* Result of a request: SYMX_PENDING while it runs (wait = 0), otherwise the
  * step's status, with x_out, v_out (host N x 3, may be NULL), the report and
- * times_ms[3] = {submitted, started, finished} in ms since server creation
- * (may be NULL).  A finished ticket is released by this call. */
+ * times_ms[5] = {submitted, started, mesh ready on the device, step done and
+ * result on the host, finished (device memory released)} in ms since server
+ * creation (may be NULL).  A finished ticket is released by this call. */
 symx_status symx_server_poll(symx_server server, int64_t ticket, int32_t wait, double* x_out,
                              double* v_out, symx_step_report* report, double* times_ms);
 symx_status symx_server_get_stats(symx_server server, symx_server_stats* stats);

@@ -40,7 +40,8 @@ symx_status hip_check(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? SYMX_ERR_OUT_OF_MEMORY : SYMX_ERR_DEVICE;
 }
 
-symx_status mesh_create(const symx_mesh_desc* d, Mesh** out);
+symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool = nullptr,
+                        TopologyCache* cache = nullptr);
 void build_scatter(Mesh& m);
 void free_workspace(Mesh& m);
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
@@ -56,17 +57,14 @@ void mesh_free(Mesh* m) {
   else (void)hipDeviceSynchronize();
   free_workspace(*m);
   m->prof.destroy();
-  void* dev[] = {m->X, m->mass, m->fixed, m->row_ptr, m->col_idx, m->diag_pos, m->inc_ptr,
-                 m->inc_code, m->inc_slots, m->batch_row, m->blk_info, m->centry, m->batch_entry, m->vals32, m->vals64, m->elem_H,
-                 m->partials, m->scalars};
-  for (void* p : dev)
-    if (p) (void)hipFree(p);
+  void* dev[] = {m->X, m->mass, m->fixed, m->vals32, m->vals64, m->elem_H, m->partials, m->scalars};
+  for (void* p : dev) dev_free(m->pool, p);
   for (SetHost& s : m->sets) {
-    void* sp[] = {s.d_conn, s.d_prm64, s.d_prm32, s.d_inc_pos};
-    for (void* p : sp)
-      if (p) (void)hipFree(p);
+    dev_free(m->pool, s.d_prm64);
+    dev_free(m->pool, s.d_prm32);
   }
-  if (m->pinned) (void)hipHostFree(m->pinned);
+  pinned_free(m->pool, m->pinned);
+  m->topo.reset();  // frees the pattern unless a cache or another mesh holds it
   delete m;
 }
 
@@ -165,8 +163,9 @@ symx_status symx_mesh_get_pattern(symx_mesh mesh, int32_t* row_ptr, int32_t* col
   GUARD_BEGIN
   if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
   Mesh& m = *mesh->m;
-  if (row_ptr) std::memcpy(row_ptr, m.h_row_ptr.data(), m.h_row_ptr.size() * sizeof(int32_t));
-  if (col_idx) std::memcpy(col_idx, m.h_col_idx.data(), m.h_col_idx.size() * sizeof(int32_t));
+  const Topology& t = *m.topo;
+  if (row_ptr) std::memcpy(row_ptr, t.h_row_ptr.data(), t.h_row_ptr.size() * sizeof(int32_t));
+  if (col_idx) std::memcpy(col_idx, t.h_col_idx.data(), t.h_col_idx.size() * sizeof(int32_t));
   if (scatter_map) {
     build_scatter(m);
     std::memcpy(scatter_map, m.h_scatter.data(), m.h_scatter.size() * sizeof(int32_t));

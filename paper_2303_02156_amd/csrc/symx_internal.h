@@ -3,8 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "symx.h"
@@ -52,18 +58,104 @@ struct DevBuf {
   size_t n = 0;
 };
 
-struct SetHost {
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+
+// Caching allocator for the meshes of one server.  Freed blocks are kept in
+// size-keyed free lists and handed out again, so a stream of requests does
+// not call hipMalloc / hipFree (hipFree can wait for work on other streams).
+// Blocks are returned to the device only by trim() or the destructor.
+class DevicePool {
+ public:
+  explicit DevicePool(int device) : device_(device) {}
+  ~DevicePool();
+  DevicePool(const DevicePool&) = delete;
+  DevicePool& operator=(const DevicePool&) = delete;
+  void* alloc(size_t bytes);  // null on failure
+  void release(void* p);
+  void* alloc_pinned(size_t bytes);
+  void release_pinned(void* p);
+  void trim();                // hipFree every cached free block
+  size_t cached_bytes();      // free bytes held by the pool
+ private:
+  static size_t round_size(size_t bytes);
+  int device_;
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_, pinned_free_;
+  std::unordered_map<void*, size_t> live_, pinned_live_;
+  size_t cached_ = 0;
+};
+
+// Through the pool when there is one, else hipMalloc / hipFree.
+symx_status dev_alloc(DevicePool* pool, void** p, size_t bytes);
+void dev_free(DevicePool* pool, void* p);
+symx_status pinned_alloc(DevicePool* pool, void** p, size_t bytes);
+void pinned_free(DevicePool* pool, void* p);
+
+// Everything derived from the connectivity alone: block pattern, incidence
+// lists, row batches and contribution lists (host and device copies).  Meshes
+// with the same node count, energy kinds and connectivity can share one.
+struct TopoSet {
   int kind = 0;
   int k = 0;
   int64_t n_elem = 0;
   std::vector<int32_t> conn;        // n_elem * k
+  int4* d_conn = nullptr;           // n_elem (unused components = -1)
+};
+
+struct Topology {
+  DevicePool* pool = nullptr;
+  uint64_t hash = 0;
+  size_t device_bytes = 0;
+  int64_t N = 0, n_inc = 0, nnzb = 0;
+  int n_batch = 0, max_row_blocks = 0;
+  std::vector<TopoSet> sets;
+  std::vector<int32_t> h_row_ptr, h_col_idx;
+  int* row_ptr = nullptr;           // N+1
+  int* col_idx = nullptr;           // nnzb
+  int* diag_pos = nullptr;          // N: index of block (i,i)
+  int* inc_ptr = nullptr;           // N+1
+  uint32_t* inc_code = nullptr;     // n_inc
+  uint32_t* inc_slots = nullptr;    // n_inc: 4 x uint8 slots (relabelled order)
+  int* batch_row = nullptr;         // n_batch+1
+  uint32_t* blk_info = nullptr;     // nnzb: off-diagonal contribution list (start << 8 | count)
+  uint16_t* centry = nullptr;       // contribution entries (incidence << 2 | node)
+  int* batch_entry = nullptr;       // n_batch+1: first entry of each batch
+  ~Topology();
+  bool matches(const symx_mesh_desc& d) const;  // same N, kinds and connectivity
+};
+
+// Hash of node count, energy kinds and a sample of the connectivity.
+uint64_t topology_hash(const symx_mesh_desc& d);
+
+// Topologies kept on the device between requests of a server, least recently
+// used first out.  Entries not used by any mesh are "idle" and may be evicted.
+class TopologyCache {
+ public:
+  explicit TopologyCache(size_t max_entries) : max_entries_(max_entries) {}
+  std::shared_ptr<Topology> find(const symx_mesh_desc& d, uint64_t hash);
+  void insert(const std::shared_ptr<Topology>& t);
+  size_t idle_bytes();
+  size_t evict_idle(size_t need);  // evict idle entries until `need` bytes are freed
+  std::atomic<int64_t> hits{0}, misses{0};
+ private:
+  std::mutex mu_;
+  std::list<std::shared_ptr<Topology>> lru_;  // front: most recently used
+  size_t max_entries_;
+};
+
+struct SetHost {
+  int kind = 0;
+  int k = 0;
+  int64_t n_elem = 0;
+  const int32_t* conn = nullptr;    // n_elem * k (the topology's host copy)
   std::vector<double> prm;          // n_elem * kPrm or kPrm
   bool uniform = true;
   // device
-  int4* d_conn = nullptr;
+  const int4* d_conn = nullptr;     // the topology's
   double* d_prm64 = nullptr;
   float* d_prm32 = nullptr;
-  int* d_inc_pos = nullptr;         // n_elem * k: position of incidence (e, a)
 };
 
 struct Workspace;  // Newton / PCG buffers (symx_newton.cpp)
@@ -91,6 +183,8 @@ struct Profiler {
 struct Mesh {
   int device = 0;
   hipStream_t stream = nullptr;
+  DevicePool* pool = nullptr;       // null: plain hipMalloc / hipFree
+  std::shared_ptr<Topology> topo;   // owns the pattern arrays below
   int64_t N = 0;
   int64_t nnzb = 0;
   int64_t n_inc = 0;
@@ -100,23 +194,23 @@ struct Mesh {
   std::vector<SetHost> sets;
   std::vector<double> h_X, h_mass;
   std::vector<uint8_t> h_fixed;
-  std::vector<int32_t> h_row_ptr, h_col_idx;
   std::vector<int32_t> h_scatter;   // all sets concatenated
 
   // device data
   double* X = nullptr;              // N*3
   double* mass = nullptr;           // N
   uint8_t* fixed = nullptr;         // N
-  int* row_ptr = nullptr;           // N+1
-  int* col_idx = nullptr;           // nnzb
-  int* diag_pos = nullptr;          // N: index of block (i,i)
-  int* inc_ptr = nullptr;           // N+1
-  uint32_t* inc_code = nullptr;     // n_inc
-  uint32_t* inc_slots = nullptr;    // n_inc: 4 x uint8 slots (relabelled order)
-  int* batch_row = nullptr;         // n_batch+1
-  uint32_t* blk_info = nullptr;     // nnzb: off-diagonal contribution list (start << 8 | count)
-  uint16_t* centry = nullptr;       // contribution entries (incidence << 2 | node)
-  int* batch_entry = nullptr;       // n_batch+1: first entry of each batch
+  // pattern arrays, borrowed from `topo`
+  const int* row_ptr = nullptr;
+  const int* col_idx = nullptr;
+  const int* diag_pos = nullptr;
+  const int* inc_ptr = nullptr;
+  const uint32_t* inc_code = nullptr;
+  const uint32_t* inc_slots = nullptr;
+  const int* batch_row = nullptr;
+  const uint32_t* blk_info = nullptr;
+  const uint16_t* centry = nullptr;
+  const int* batch_entry = nullptr;
   float* vals32 = nullptr;          // 9*nnzb, component-major
   double* vals64 = nullptr;
   // per-element scratch for the projected path (largest set)

@@ -35,16 +35,23 @@ inline V3 cross(V3 a, V3 b) {
 }
 inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
 
+// Allocate n elements (through the pool, if any) and copy src to them on
+// `stream`; returns when the copy is done, so src may be freed at once.
+// *bytes accumulates the allocation size.
 template <typename T>
-symx_status upload(T** dst, const T* src, size_t n) {
+symx_status upload(DevicePool* pool, hipStream_t stream, T** dst, const T* src, size_t n,
+                   size_t* bytes = nullptr) {
   if (n == 0) n = 1;
-  if (hipMalloc((void**)dst, n * sizeof(T)) != hipSuccess) {
-    *dst = nullptr;
-    set_error("device allocation failed");
-    return SYMX_ERR_OUT_OF_MEMORY;
-  }
-  if (src) return hip_check(hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
-  return SYMX_OK;
+  void* p = nullptr;
+  symx_status st = dev_alloc(pool, &p, n * sizeof(T));
+  *dst = static_cast<T*>(p);
+  if (st != SYMX_OK) return st;
+  if (bytes) *bytes += n * sizeof(T);
+  if (!src) return SYMX_OK;
+  st = hip_check(hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, stream),
+                 "hipMemcpyAsync");
+  if (st == SYMX_OK) st = hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  return st;
 }
 
 #define TRY(expr)                         \
@@ -85,7 +92,10 @@ static void parallel_chunks(int64_t n, int64_t min_chunk, F f) {
   for (auto& x : th) x.join();
 }
 
-static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s) {
+// Per-mesh data of one energy set: parameters, rest measures, lumped masses
+// (added to m.h_mass).  validate_conn: check node ids (skipped when the
+// connectivity equals that of a cached, already validated topology).
+static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s, bool validate_conn) {
   s.kind = d.kind;
   if (d.kind == SYMX_SNH_TET4 || d.kind == SYMX_HINGE4)
     s.k = 4;
@@ -100,16 +110,16 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s) {
     return SYMX_ERR_INVALID_ARG;
   }
   s.n_elem = d.n_elem;
-  s.conn.assign(d.conn, d.conn + d.n_elem * s.k);
-  {
+  const int32_t* conn = d.conn;
+  if (validate_conn) {
     std::atomic<int64_t> bad_range{-1}, bad_repeat{-1};
     parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
       for (int64_t e = e0; e < e1; ++e)
         for (int a = 0; a < s.k; ++a) {
-          const int32_t v = s.conn[e * s.k + a];
+          const int32_t v = conn[e * s.k + a];
           if (v < 0 || v >= m.N) bad_range = e;
           for (int b = 0; b < a; ++b)
-            if (s.conn[e * s.k + b] == v) bad_repeat = e;
+            if (conn[e * s.k + b] == v) bad_repeat = e;
         }
     });
     if (bad_range >= 0) {
@@ -123,7 +133,7 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s) {
   }
   const double* X = m.h_X.data();
   auto P = [&](int64_t e, int a) {
-    int64_t n = s.conn[e * s.k + a];
+    int64_t n = conn[e * s.k + a];
     return V3{X[3 * n], X[3 * n + 1], X[3 * n + 2]};
   };
   bool per_elem = (d.young != nullptr) && d.kind != SYMX_HINGE4;
@@ -160,7 +170,7 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s) {
         set_error("degenerate rest tet " + std::to_string(e));
         return SYMX_ERR_INVALID_ARG;
       }
-      for (int a = 0; a < 4; ++a) m.h_mass[s.conn[e * 4 + a]] += d.density * vol[e] / 4.0;
+      for (int a = 0; a < 4; ++a) m.h_mass[conn[e * 4 + a]] += d.density * vol[e] / 4.0;
     }
   } else if (d.kind == SYMX_STVK_TRI3) {
     for (int64_t e = 0; e < s.n_elem; ++e) {
@@ -171,7 +181,7 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s) {
         return SYMX_ERR_INVALID_ARG;
       }
       for (int a = 0; a < 3; ++a)
-        m.h_mass[s.conn[e * 3 + a]] += d.density * d.thickness * area / 3.0;
+        m.h_mass[conn[e * 3 + a]] += d.density * d.thickness * area / 3.0;
     }
   } else {  // hinge: per-element K and c (Eq. 13, Bergou et al. 2006)
     s.uniform = false;
@@ -201,15 +211,31 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s) {
   return SYMX_OK;
 }
 
-static symx_status build_pattern(Mesh& m) {
-  const int64_t N = m.N;
+// Pattern, incidence lists, row batches and contribution lists of the
+// connectivity in `d` (already validated), uploaded on `stream`.
+static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hipStream_t stream,
+                                  std::shared_ptr<Topology>* out) {
+  auto tp = std::make_shared<Topology>();
+  Topology& t = *tp;
+  t.pool = pool;
+  t.hash = topology_hash(d);
+  t.N = d.n_nodes;
+  t.sets.resize(d.n_energies);
+  for (int si = 0; si < d.n_energies; ++si) {
+    TopoSet& ts = t.sets[si];
+    ts.kind = d.energies[si].kind;
+    ts.k = ts.kind == SYMX_STVK_TRI3 ? 3 : 4;
+    ts.n_elem = d.energies[si].n_elem;
+    ts.conn.assign(d.energies[si].conn, d.energies[si].conn + ts.n_elem * ts.k);
+  }
+  const int64_t N = t.N;
   // node -> incidences (set, element, local node), in (set, element) order
   std::vector<int64_t> cnt(N + 1, 0);
-  for (const SetHost& s : m.sets)
+  for (const TopoSet& s : t.sets)
     for (int32_t v : s.conn) cnt[v + 1]++;
   for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
-  m.n_inc = cnt[N];
-  if (m.n_inc >= (int64_t(1) << 31)) {
+  t.n_inc = cnt[N];
+  if (t.n_inc >= (int64_t(1) << 31)) {
     set_error("too many incidences");
     return SYMX_ERR_INVALID_ARG;
   }
@@ -218,11 +244,11 @@ static symx_status build_pattern(Mesh& m) {
       set_error("node " + std::to_string(i) + " belongs to more than 256 elements");
       return SYMX_ERR_INVALID_ARG;
     }
-  std::vector<uint32_t> code(m.n_inc);
+  std::vector<uint32_t> code(t.n_inc);
   {
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int si = 0; si < (int)m.sets.size(); ++si) {
-      const SetHost& s = m.sets[si];
+    for (int si = 0; si < (int)t.sets.size(); ++si) {
+      const TopoSet& s = t.sets[si];
       for (int64_t e = 0; e < s.n_elem; ++e)
         for (int a = 0; a < s.k; ++a) code[fill[s.conn[e * s.k + a]]++] = inc_make(si, a, e);
     }
@@ -230,9 +256,7 @@ static symx_status build_pattern(Mesh& m) {
   // Rows in parallel chunks: sorted unique neighbour list of each node, and
   // for each incidence the row-local slots of its blocks in the relabelled
   // node order (a first, then the others ascending).
-  std::vector<uint32_t> slots(m.n_inc);
-  std::vector<std::vector<int32_t>> inc_pos(m.sets.size());
-  for (size_t si = 0; si < m.sets.size(); ++si) inc_pos[si].assign(m.sets[si].n_elem * m.sets[si].k, -1);
+  std::vector<uint32_t> slots(t.n_inc);
   std::vector<int32_t> row_len(N);
   const int64_t n_chunks = std::min<int64_t>(64, std::max<int64_t>(1, N / 2048));
   std::vector<std::vector<int32_t>> chunk_cols(n_chunks);
@@ -246,7 +270,7 @@ static symx_status build_pattern(Mesh& m) {
         nb.clear();
         nb.push_back((int32_t)i);
         for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
-          const SetHost& s = m.sets[inc_set(code[q])];
+          const TopoSet& s = t.sets[inc_set(code[q])];
           const int64_t e = inc_elem(code[q]);
           for (int b = 0; b < s.k; ++b) nb.push_back(s.conn[e * s.k + b]);
         }
@@ -256,7 +280,7 @@ static symx_status build_pattern(Mesh& m) {
         row_len[i] = (int32_t)nb.size();
         for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
           const int si = inc_set(code[q]);
-          const SetHost& s = m.sets[si];
+          const TopoSet& s = t.sets[si];
           const int a = inc_local(code[q]);
           const int64_t e = inc_elem(code[q]);
           int order[4] = {a, -1, -1, -1};
@@ -272,7 +296,6 @@ static symx_status build_pattern(Mesh& m) {
             w |= sl << (8 * bp);
           }
           slots[q] = w;
-          inc_pos[si][e * s.k + a] = (int32_t)q;
         }
         cols.insert(cols.end(), nb.begin(), nb.end());
       }
@@ -283,24 +306,24 @@ static symx_status build_pattern(Mesh& m) {
       set_error("a node couples to more than 255 nodes");
       return SYMX_ERR_INVALID_ARG;
     }
-  m.h_row_ptr.assign(N + 1, 0);
-  m.max_row_blocks = 0;
+  t.h_row_ptr.assign(N + 1, 0);
+  t.max_row_blocks = 0;
   for (int64_t i = 0; i < N; ++i) {
-    m.h_row_ptr[i + 1] = m.h_row_ptr[i] + row_len[i];
-    m.max_row_blocks = std::max(m.max_row_blocks, (int)row_len[i]);
+    t.h_row_ptr[i + 1] = t.h_row_ptr[i] + row_len[i];
+    t.max_row_blocks = std::max(t.max_row_blocks, (int)row_len[i]);
   }
-  if ((int64_t)m.h_row_ptr[N] >= (int64_t(1) << 31) - 1) {
+  if ((int64_t)t.h_row_ptr[N] >= (int64_t(1) << 31) - 1) {
     set_error("too many blocks");
     return SYMX_ERR_INVALID_ARG;
   }
-  m.nnzb = m.h_row_ptr[N];
-  m.h_col_idx.resize(m.nnzb);
+  t.nnzb = t.h_row_ptr[N];
+  t.h_col_idx.resize(t.nnzb);
   {
     std::vector<int64_t> off(n_chunks + 1, 0);
     for (int64_t c = 0; c < n_chunks; ++c) off[c + 1] = off[c] + (int64_t)chunk_cols[c].size();
     parallel_chunks(n_chunks, 1, [&](int64_t c0, int64_t c1) {
       for (int64_t c = c0; c < c1; ++c)
-        std::copy(chunk_cols[c].begin(), chunk_cols[c].end(), m.h_col_idx.begin() + off[c]);
+        std::copy(chunk_cols[c].begin(), chunk_cols[c].end(), t.h_col_idx.begin() + off[c]);
     });
   }
   chunk_cols.clear();
@@ -318,32 +341,32 @@ static symx_status build_pattern(Mesh& m) {
     bb += nbk;
   }
   batch.push_back((int32_t)N);
-  m.n_batch = (int)batch.size() - 1;
+  t.n_batch = (int)batch.size() - 1;
   // Off-diagonal contribution lists.  For every off-diagonal block of a batch,
   // the (incidence, relabelled node b >= 1) pairs that add to it, in incidence
   // order; entries are u16 = (incidence index within the batch << 2) | b.
   // blk_info[p] = (first entry relative to the batch's base << 8) | count.
-  std::vector<int32_t> batch_entry(m.n_batch + 1, 0);
-  for (int b = 0; b < m.n_batch; ++b) {
+  std::vector<int32_t> batch_entry(t.n_batch + 1, 0);
+  for (int b = 0; b < t.n_batch; ++b) {
     int64_t ne = 0;
-    for (int64_t q = cnt[batch[b]]; q < cnt[batch[b + 1]]; ++q) ne += m.sets[inc_set(code[q])].k - 1;
+    for (int64_t q = cnt[batch[b]]; q < cnt[batch[b + 1]]; ++q) ne += t.sets[inc_set(code[q])].k - 1;
     batch_entry[b + 1] = batch_entry[b] + (int32_t)ne;
   }
-  std::vector<uint32_t> blk_info(m.nnzb, 0);
-  std::vector<uint16_t> centry(batch_entry[m.n_batch]);
-  std::vector<int> batch_bad(m.n_batch, 0);
-  parallel_chunks(m.n_batch, 256, [&](int64_t b0, int64_t b1) {
+  std::vector<uint32_t> blk_info(t.nnzb, 0);
+  std::vector<uint16_t> centry(batch_entry[t.n_batch]);
+  std::vector<int> batch_bad(t.n_batch, 0);
+  parallel_chunks(t.n_batch, 256, [&](int64_t b0, int64_t b1) {
     std::vector<int32_t> cnt_blk, fillp;
     for (int64_t b = b0; b < b1; ++b) {
       const int64_t r0 = batch[b], r1 = batch[b + 1];
-      const int64_t q0 = cnt[r0], p0 = m.h_row_ptr[r0];
-      const int64_t np = m.h_row_ptr[r1] - p0;
+      const int64_t q0 = cnt[r0], p0 = t.h_row_ptr[r0];
+      const int64_t np = t.h_row_ptr[r1] - p0;
       cnt_blk.assign(np + 1, 0);
       for (int64_t r = r0; r < r1; ++r)
         for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
-          const int k = m.sets[inc_set(code[q])].k;
+          const int k = t.sets[inc_set(code[q])].k;
           for (int bp = 1; bp < k; ++bp)
-            cnt_blk[m.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0 + 1]++;
+            cnt_blk[t.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0 + 1]++;
         }
       for (int64_t i = 0; i < np; ++i) {
         if (cnt_blk[i + 1] > 255) batch_bad[b] = 1;
@@ -355,15 +378,15 @@ static symx_status build_pattern(Mesh& m) {
       fillp.assign(cnt_blk.begin(), cnt_blk.end() - 1);
       for (int64_t r = r0; r < r1; ++r)
         for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
-          const int k = m.sets[inc_set(code[q])].k;
+          const int k = t.sets[inc_set(code[q])].k;
           for (int bp = 1; bp < k; ++bp) {
-            const int64_t pl = m.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0;
+            const int64_t pl = t.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0;
             base[fillp[pl]++] = (uint16_t)(((q - q0) << 2) | bp);
           }
         }
     }
   });
-  for (int b = 0; b < m.n_batch; ++b)
+  for (int b = 0; b < t.n_batch; ++b)
     if (batch_bad[b]) {
       set_error("more than 255 elements share one node pair");
       return SYMX_ERR_INVALID_ARG;
@@ -373,21 +396,30 @@ static symx_status build_pattern(Mesh& m) {
   for (int64_t i = 0; i <= N; ++i) inc_ptr32[i] = (int32_t)cnt[i];
   std::vector<int32_t> diag(N);
   for (int64_t i = 0; i < N; ++i) {
-    const int32_t* b = m.h_col_idx.data() + m.h_row_ptr[i];
-    diag[i] = m.h_row_ptr[i] + (int32_t)(std::lower_bound(b, b + row_len[i], (int32_t)i) - b);
+    const int32_t* b = t.h_col_idx.data() + t.h_row_ptr[i];
+    diag[i] = t.h_row_ptr[i] + (int32_t)(std::lower_bound(b, b + row_len[i], (int32_t)i) - b);
   }
-  TRY(upload(&m.row_ptr, m.h_row_ptr.data(), N + 1));
-  TRY(upload(&m.col_idx, m.h_col_idx.data(), m.nnzb));
-  TRY(upload(&m.diag_pos, diag.data(), N));
-  TRY(upload(&m.inc_ptr, inc_ptr32.data(), N + 1));
-  TRY(upload(&m.inc_code, code.data(), m.n_inc));
-  TRY(upload(&m.inc_slots, slots.data(), m.n_inc));
-  TRY(upload(&m.batch_row, batch.data(), batch.size()));
-  TRY(upload(&m.blk_info, blk_info.data(), blk_info.size()));
-  TRY(upload(&m.centry, centry.data(), centry.size()));
-  TRY(upload(&m.batch_entry, batch_entry.data(), batch_entry.size()));
-  for (size_t si = 0; si < m.sets.size(); ++si)
-    TRY(upload(&m.sets[si].d_inc_pos, inc_pos[si].data(), inc_pos[si].size()));
+  size_t& nb = t.device_bytes;
+  TRY(upload(pool, stream, &t.row_ptr, t.h_row_ptr.data(), N + 1, &nb));
+  TRY(upload(pool, stream, &t.col_idx, t.h_col_idx.data(), t.nnzb, &nb));
+  TRY(upload(pool, stream, &t.diag_pos, diag.data(), N, &nb));
+  TRY(upload(pool, stream, &t.inc_ptr, inc_ptr32.data(), N + 1, &nb));
+  TRY(upload(pool, stream, &t.inc_code, code.data(), t.n_inc, &nb));
+  TRY(upload(pool, stream, &t.inc_slots, slots.data(), t.n_inc, &nb));
+  TRY(upload(pool, stream, &t.batch_row, batch.data(), batch.size(), &nb));
+  TRY(upload(pool, stream, &t.blk_info, blk_info.data(), blk_info.size(), &nb));
+  TRY(upload(pool, stream, &t.centry, centry.data(), centry.size(), &nb));
+  TRY(upload(pool, stream, &t.batch_entry, batch_entry.data(), batch_entry.size(), &nb));
+  for (TopoSet& ts : t.sets) {
+    std::vector<int4> c4(std::max<int64_t>(ts.n_elem, 1));
+    for (int64_t e = 0; e < ts.n_elem; ++e) {
+      int v[4] = {-1, -1, -1, -1};
+      for (int a = 0; a < ts.k; ++a) v[a] = ts.conn[e * ts.k + a];
+      c4[e] = make_int4(v[0], v[1], v[2], v[3]);
+    }
+    TRY(upload(pool, stream, &ts.d_conn, c4.data(), c4.size(), &nb));
+  }
+  *out = std::move(tp);
   return SYMX_OK;
 }
 
@@ -395,41 +427,64 @@ static symx_status build_pattern(Mesh& m) {
 // on demand for symx_mesh_get_pattern.
 void build_scatter(Mesh& m) {
   if (!m.h_scatter.empty()) return;
+  const Topology& t = *m.topo;
   size_t total = 0;
-  for (const SetHost& s : m.sets) total += size_t(s.n_elem) * s.k * s.k;
+  for (const TopoSet& s : t.sets) total += size_t(s.n_elem) * s.k * s.k;
   m.h_scatter.resize(total);
   size_t off = 0;
-  for (const SetHost& s : m.sets) {
+  for (const TopoSet& s : t.sets) {
     for (int64_t e = 0; e < s.n_elem; ++e)
       for (int a = 0; a < s.k; ++a) {
         const int32_t i = s.conn[e * s.k + a];
-        const int32_t* b = m.h_col_idx.data() + m.h_row_ptr[i];
-        const int32_t* en = m.h_col_idx.data() + m.h_row_ptr[i + 1];
+        const int32_t* b = t.h_col_idx.data() + t.h_row_ptr[i];
+        const int32_t* en = t.h_col_idx.data() + t.h_row_ptr[i + 1];
         for (int c = 0; c < s.k; ++c)
           m.h_scatter[off++] =
-              m.h_row_ptr[i] + (int32_t)(std::lower_bound(b, en, s.conn[e * s.k + c]) - b);
+              t.h_row_ptr[i] + (int32_t)(std::lower_bound(b, en, s.conn[e * s.k + c]) - b);
       }
   }
 }
 
-static symx_status upload_mesh(Mesh& m) {
-  TRY(upload(&m.X, m.h_X.data(), m.h_X.size()));
-  TRY(upload(&m.mass, m.h_mass.data(), m.h_mass.size()));
-  TRY(upload(&m.fixed, m.h_fixed.data(), m.h_fixed.size()));
-  for (SetHost& s : m.sets) {
-    std::vector<int4> c4(std::max<int64_t>(s.n_elem, 1));
-    for (int64_t e = 0; e < s.n_elem; ++e) {
-      int v[4] = {-1, -1, -1, -1};
-      for (int a = 0; a < s.k; ++a) v[a] = s.conn[e * s.k + a];
-      c4[e] = make_int4(v[0], v[1], v[2], v[3]);
-    }
-    TRY(upload(&s.d_conn, c4.data(), c4.size()));
-    std::vector<float> p32(s.prm.begin(), s.prm.end());
-    TRY(upload(&s.d_prm64, s.prm.data(), s.prm.size()));
-    TRY(upload(&s.d_prm32, p32.data(), p32.size()));
+// Point the mesh at its topology's arrays.
+static void attach_topology(Mesh& m, std::shared_ptr<Topology> tp) {
+  const Topology& t = *tp;
+  m.nnzb = t.nnzb;
+  m.n_inc = t.n_inc;
+  m.n_batch = t.n_batch;
+  m.max_row_blocks = t.max_row_blocks;
+  m.row_ptr = t.row_ptr;
+  m.col_idx = t.col_idx;
+  m.diag_pos = t.diag_pos;
+  m.inc_ptr = t.inc_ptr;
+  m.inc_code = t.inc_code;
+  m.inc_slots = t.inc_slots;
+  m.batch_row = t.batch_row;
+  m.blk_info = t.blk_info;
+  m.centry = t.centry;
+  m.batch_entry = t.batch_entry;
+  for (size_t s = 0; s < m.sets.size(); ++s) {
+    m.sets[s].conn = t.sets[s].conn.data();
+    m.sets[s].d_conn = t.sets[s].d_conn;
   }
-  TRY(upload<double>(&m.partials, nullptr, kMaxPartials));
-  TRY(upload<double>(&m.scalars, nullptr, 64));
+  m.topo = std::move(tp);
+}
+
+// Per-mesh device data: rest positions, masses, Dirichlet flags, element
+// parameters, reduction scratch.
+static symx_status upload_instance(Mesh& m) {
+  DevicePool* pool = m.pool;
+  TRY(upload(pool, m.stream, &m.X, m.h_X.data(), m.h_X.size()));
+  TRY(upload(pool, m.stream, &m.mass, m.h_mass.data(), m.h_mass.size()));
+  TRY(upload(pool, m.stream, &m.fixed, m.h_fixed.data(), m.h_fixed.size()));
+  std::vector<std::vector<float>> p32(m.sets.size());
+  for (size_t i = 0; i < m.sets.size(); ++i) {
+    SetHost& s = m.sets[i];
+    p32[i].assign(s.prm.begin(), s.prm.end());
+    TRY(upload(pool, m.stream, &s.d_prm64, s.prm.data(), s.prm.size()));
+    TRY(upload(pool, m.stream, &s.d_prm32, p32[i].data(), p32[i].size()));
+  }
+  TRY(upload<double>(pool, m.stream, &m.partials, nullptr, kMaxPartials));
+  TRY(upload<double>(pool, m.stream, &m.scalars, nullptr, 64));
   // on the mesh's stream: a null-stream memset is not ordered with work on a
   // non-blocking stream, so the first flag read could see stale memory
   TRY(hip_check(hipMemsetAsync(m.scalars, 0, 64 * sizeof(double), m.stream), "hipMemsetAsync"));
@@ -437,15 +492,14 @@ static symx_status upload_mesh(Mesh& m) {
   // the non-finite flag shares the scalar array (slot 24) so the Newton driver
   // reads results and flag with one copy
   m.nonfinite = reinterpret_cast<int*>(m.scalars + 24);
-  if (hipHostMalloc((void**)&m.pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    m.pinned = nullptr;
-    set_error("pinned host allocation failed");
-    return SYMX_ERR_OUT_OF_MEMORY;
-  }
+  void* pin = nullptr;
+  TRY(pinned_alloc(pool, &pin, 64 * sizeof(double)));
+  m.pinned = static_cast<double*>(pin);
   return SYMX_OK;
 }
 
-symx_status mesh_create(const symx_mesh_desc* d, Mesh** out) {
+symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool,
+                        TopologyCache* cache) {
   if (!d || !out || d->n_nodes < 1 || !d->x_rest || d->n_energies < 1 ||
       d->n_energies > kMaxSets || !d->energies) {
     set_error("invalid mesh descriptor");
@@ -460,6 +514,7 @@ symx_status mesh_create(const symx_mesh_desc* d, Mesh** out) {
   *out = m;  // the caller destroys on error
   TRY(hip_check(hipGetDevice(&m->device), "hipGetDevice"));
   m->stream = (hipStream_t)d->hip_stream;
+  m->pool = pool;
   m->N = d->n_nodes;
   m->h_X.assign(d->x_rest, d->x_rest + 3 * m->N);
   for (double v : m->h_X)
@@ -470,13 +525,24 @@ symx_status mesh_create(const symx_mesh_desc* d, Mesh** out) {
   m->h_fixed.assign(m->N, 0);
   if (d->fixed)
     for (int64_t i = 0; i < m->N; ++i) m->h_fixed[i] = d->fixed[i] ? 1 : 0;
+  std::shared_ptr<Topology> topo;
+  uint64_t hash = 0;
+  if (cache) {
+    hash = topology_hash(*d);
+    topo = cache->find(*d, hash);
+  }
   m->h_mass.assign(m->N, 0.0);
   m->sets.resize(d->n_energies);
-  for (int s = 0; s < d->n_energies; ++s) TRY(build_set(*m, d->energies[s], m->sets[s]));
+  for (int s = 0; s < d->n_energies; ++s)
+    TRY(build_set(*m, d->energies[s], m->sets[s], /*validate_conn=*/!topo));
   m->total_mass = 0.0;
   for (double v : m->h_mass) m->total_mass += v;
-  TRY(build_pattern(*m));
-  TRY(upload_mesh(*m));
+  if (!topo) {
+    TRY(build_topology(*d, pool, m->stream, &topo));
+    if (cache) cache->insert(topo);
+  }
+  attach_topology(*m, std::move(topo));
+  TRY(upload_instance(*m));
   return SYMX_OK;
 }
 

@@ -43,18 +43,10 @@ struct Workspace {
   void* pcg[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // Dinv xs r z p q (max size)
 };
 
-static symx_status dalloc(void** p, size_t bytes) {
-  if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) {
-    *p = nullptr;
-    set_error("device allocation failed");
-    return SYMX_ERR_OUT_OF_MEMORY;
-  }
-  return SYMX_OK;
-}
 
 static symx_status ensure_values(Mesh& m, int precision) {
-  if (precision == SYMX_F64 && !m.vals64) return dalloc((void**)&m.vals64, 9 * m.nnzb * sizeof(double));
-  if (precision != SYMX_F64 && !m.vals32) return dalloc((void**)&m.vals32, 9 * m.nnzb * sizeof(float));
+  if (precision == SYMX_F64 && !m.vals64) return dev_alloc(m.pool, (void**)&m.vals64, 9 * m.nnzb * sizeof(double));
+  if (precision != SYMX_F64 && !m.vals32) return dev_alloc(m.pool, (void**)&m.vals32, 9 * m.nnzb * sizeof(float));
   return SYMX_OK;
 }
 
@@ -65,9 +57,9 @@ static symx_status ensure_workspace(Mesh& m) {
   w->N = m.N;
   const size_t v64 = 3 * m.N * sizeof(double);
   double** vecs[] = {&w->x_t, &w->v_t, &w->xt, &w->xk, &w->xtrial, &w->g, &w->dx, &w->b, &w->res};
-  for (double** p : vecs) TRY(dalloc((void**)p, v64));
-  TRY(dalloc(&w->pcg[0], 9 * m.N * sizeof(double)));
-  for (int i = 1; i < 6; ++i) TRY(dalloc(&w->pcg[i], v64));
+  for (double** p : vecs) TRY(dev_alloc(m.pool, (void**)p, v64));
+  TRY(dev_alloc(m.pool, &w->pcg[0], 9 * m.N * sizeof(double)));
+  for (int i = 1; i < 6; ++i) TRY(dev_alloc(m.pool, &w->pcg[i], v64));
   return SYMX_OK;
 }
 
@@ -75,10 +67,8 @@ void free_workspace(Mesh& m) {
   if (!m.ws) return;
   Workspace* w = m.ws;
   double* vecs[] = {w->x_t, w->v_t, w->xt, w->xk, w->xtrial, w->g, w->dx, w->b, w->res};
-  for (double* p : vecs)
-    if (p) (void)hipFree(p);
-  for (void* p : w->pcg)
-    if (p) (void)hipFree(p);
+  for (double* p : vecs) dev_free(m.pool, p);
+  for (void* p : w->pcg) dev_free(m.pool, p);
   delete w;
   m.ws = nullptr;
 }
@@ -132,10 +122,10 @@ static symx_status project_elements(Mesh& m, const double* x, int precision, boo
     need = (need + 255) & ~size_t(255);
   }
   if (need > m.elem_bytes) {
-    if (m.elem_H) (void)hipFree(m.elem_H);
+    dev_free(m.pool, m.elem_H);
     m.elem_H = nullptr;
     m.elem_bytes = 0;
-    TRY(dalloc(&m.elem_H, need));
+    TRY(dev_alloc(m.pool, &m.elem_H, need));
     m.elem_bytes = need;
   }
   (void)want_g;

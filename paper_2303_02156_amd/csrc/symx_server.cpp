@@ -10,6 +10,14 @@
 // back and frees the mesh.  Kernels of different slots run concurrently on the
 // device.  Every request's kernels touch only its own buffers and use fixed
 // reduction orders, so a result does not depend on what else is running.
+//
+// Device memory comes from the server's pool (no hipMalloc / hipFree per
+// request), and block patterns stay resident in a topology cache: a request
+// whose connectivity was seen before skips the pattern build and upload.
+// Budget accounting: running requests are charged their estimate; idle cached
+// patterns are charged their size and evicted when a request needs the room;
+// the pool's free blocks are returned to the device when, together with the
+// two, they would exceed the budget.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -24,7 +32,8 @@
 
 namespace symxi {
 
-symx_status mesh_create(const symx_mesh_desc* d, Mesh** out);
+symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool,
+                        TopologyCache* cache);
 void mesh_free(Mesh* m);
 symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P,
                         symx_step_report* out);
@@ -48,7 +57,7 @@ struct Request {
   std::vector<double> x, v;
   symx_step_params params{};
   size_t bytes = 0;
-  clk::time_point t_submit, t_start, t_end;
+  clk::time_point t_submit, t_start, t_setup, t_step, t_end;
   bool done = false;
   symx_status status = SYMX_OK;
   symx_step_report report{};
@@ -93,18 +102,30 @@ struct Server {
   clk::time_point t0 = clk::now();
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
+  std::unique_ptr<DevicePool> pool;
+  std::unique_ptr<TopologyCache> cache;
 
   void worker(int slot);
+  bool fits(size_t bytes);  // with mu held
 };
+
+// Room for a request of `bytes` next to the running requests, evicting idle
+// cached patterns if that makes it fit.
+bool Server::fits(size_t bytes) {
+  const size_t room = budget - in_use;  // in_use <= budget always
+  if (bytes > room) return false;
+  const size_t idle = cache->idle_bytes();
+  if (bytes + idle <= room) return true;
+  cache->evict_idle(bytes + idle - room);
+  return bytes + cache->idle_bytes() <= room;
+}
 
 void Server::worker(int slot) {
   (void)hipSetDevice(device);
   hipStream_t stream = streams[slot];
   std::unique_lock<std::mutex> lk(mu);
   while (true) {
-    cv_work.wait(lk, [&] {
-      return stop || (!queue.empty() && queue.front()->bytes <= budget - in_use);
-    });
+    cv_work.wait(lk, [&] { return stop || (!queue.empty() && fits(queue.front()->bytes)); });
     if (stop) return;
     Request* r = queue.front();
     queue.pop_front();
@@ -120,15 +141,17 @@ void Server::worker(int slot) {
     double *dx = nullptr, *dv = nullptr;
     const size_t nb = r->x.size() * sizeof(double);
     r->scene.desc.hip_stream = stream;
-    st = mesh_create(&r->scene.desc, &m);
+    st = mesh_create(&r->scene.desc, &m, pool.get(), cache.get());
     if (st == SYMX_OK) {
-      st = hip_check(hipMalloc((void**)&dx, nb), "hipMalloc");
-      if (st == SYMX_OK) st = hip_check(hipMalloc((void**)&dv, nb), "hipMalloc");
+      st = dev_alloc(pool.get(), (void**)&dx, nb);
+      if (st == SYMX_OK) st = dev_alloc(pool.get(), (void**)&dv, nb);
     }
     if (st == SYMX_OK)
       st = hip_check(hipMemcpyAsync(dx, r->x.data(), nb, hipMemcpyHostToDevice, stream), "copy");
     if (st == SYMX_OK)
       st = hip_check(hipMemcpyAsync(dv, r->v.data(), nb, hipMemcpyHostToDevice, stream), "copy");
+    if (st == SYMX_OK) st = hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    r->t_setup = clk::now();
     if (st == SYMX_OK) st = newton_step(*m, dx, dv, r->params, &r->report);
     if (st == SYMX_OK) {
       symx_status s2 = hip_check(hipMemcpyAsync(r->x.data(), dx, nb, hipMemcpyDeviceToHost, stream), "copy");
@@ -138,9 +161,16 @@ void Server::worker(int slot) {
       st = s2;
     }
     (void)hipStreamSynchronize(stream);
-    if (dx) (void)hipFree(dx);
-    if (dv) (void)hipFree(dv);
+    r->t_step = clk::now();
+    dev_free(pool.get(), dx);
+    dev_free(pool.get(), dv);
     if (m) mesh_free(m);
+    // the pool's free blocks count against the budget too
+    {
+      std::lock_guard<std::mutex> g(mu);
+      const size_t held = in_use - r->bytes + cache->idle_bytes() + pool->cached_bytes();
+      if (held > budget) pool->trim();
+    }
 
     lk.lock();
     r->status = st;
@@ -168,6 +198,8 @@ symx_status server_create(uint64_t budget, int32_t max_slots, Server** out) {
     delete s;
     return st;
   }
+  s->pool = std::make_unique<DevicePool>(s->device);
+  s->cache = std::make_unique<TopologyCache>(256);
   for (int i = 0; i < max_slots; ++i) {
     hipStream_t h = nullptr;
     st = hip_check(hipStreamCreateWithFlags(&h, hipStreamNonBlocking), "hipStreamCreate");
@@ -192,6 +224,8 @@ void server_destroy(Server* s) {
   s->cv_work.notify_all();
   for (std::thread& t : s->workers) t.join();
   for (hipStream_t h : s->streams) (void)hipStreamDestroy(h);
+  s->cache.reset();  // cached patterns go back to the pool first
+  s->pool.reset();
   delete s;
 }
 
@@ -263,7 +297,9 @@ symx_status server_poll(Server* s, int64_t ticket, int32_t wait, double* x_out, 
   if (times_ms) {
     times_ms[0] = ms_between(s->t0, r->t_submit);
     times_ms[1] = ms_between(s->t0, r->t_start);
-    times_ms[2] = ms_between(s->t0, r->t_end);
+    times_ms[2] = ms_between(s->t0, r->t_setup);
+    times_ms[3] = ms_between(s->t0, r->t_step);
+    times_ms[4] = ms_between(s->t0, r->t_end);
   }
   const symx_status st = r->status;
   s->requests.erase(it);
@@ -276,6 +312,9 @@ void server_stats(Server* s, symx_server_stats* out) {
   out->budget_bytes = s->budget;
   out->in_use_bytes = s->in_use;
   out->peak_bytes = s->peak;
+  out->pattern_cache_bytes = s->cache->idle_bytes();
+  out->pattern_hits = s->cache->hits;
+  out->pattern_misses = s->cache->misses;
   out->queued = (int64_t)s->queue.size();
   out->active = s->active;
   out->peak_active = s->peak_active;

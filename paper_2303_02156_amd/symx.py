@@ -68,8 +68,10 @@ class StepReport(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("in_use_bytes", C.c_uint64),
-                ("peak_bytes", C.c_uint64), ("queued", C.c_int64), ("completed", C.c_int64),
-                ("active", C.c_int32), ("peak_active", C.c_int32), ("max_slots", C.c_int32)]
+                ("peak_bytes", C.c_uint64), ("pattern_cache_bytes", C.c_uint64),
+                ("queued", C.c_int64), ("completed", C.c_int64), ("pattern_hits", C.c_int64),
+                ("pattern_misses", C.c_int64), ("active", C.c_int32), ("peak_active", C.c_int32),
+                ("max_slots", C.c_int32)]
 
 
 EXPORTS = {
@@ -218,7 +220,7 @@ def symx_server_submit(h, desc, x_host, v_host, params):
 
 def symx_server_poll(h, ticket, wait, x_out=None, v_out=None):
     rep = StepReport()
-    times = np.zeros(3)
+    times = np.zeros(5)
     st = load().symx_server_poll(h, ticket, int(wait),
                                  None if x_out is None else x_out.ctypes.data,
                                  None if v_out is None else v_out.ctypes.data,

@@ -62,7 +62,7 @@ def test_struct_sizes_match_c_layout():
     assert C.sizeof(symx.BsrView) == 8 * 5 + 8
     assert C.sizeof(symx.StepParams) == 8 * 5 + 4 * 7 + 4
     assert C.sizeof(symx.StepReport) == 4 * 6 + 8 * 8
-    assert C.sizeof(symx.ServerStats) == 8 * 5 + 4 * 3 + 4
+    assert C.sizeof(symx.ServerStats) == 8 * 8 + 4 * 3 + 4
 
 
 def test_null_arguments_rejected_without_gpu(lib):

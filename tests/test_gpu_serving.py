@@ -70,7 +70,7 @@ def test_served_step_equals_direct_step_and_converges(symx):
     (req, sc), = _requests()[1:2]
     res, _ = _run(symx, [(req, sc)], 2)
     st, rep, x, v, times = res[0]
-    assert st == 0 and times[0] <= times[1] <= times[2]
+    assert st == 0 and all(times[i] <= times[i + 1] for i in range(4))
     mesh = symx.Mesh(sc)
     xd = torch.tensor(sc.x0, dtype=torch.float64, device="cuda")
     vd = torch.tensor(sc.v0, dtype=torch.float64, device="cuda")
@@ -117,3 +117,37 @@ def test_many_concurrent_requests_all_succeed(symx):
     res, stats = _run(symx, [(None, sc) for sc in scenes], 8, precision=2)
     assert [r[0] for r in res] == [0] * len(scenes)
     assert stats.completed == len(scenes) and stats.peak_active >= 2
+
+
+def test_resident_patterns_are_reused_and_give_identical_results(symx):
+    """Requests that repeat a connectivity (same n, other material and
+    perturbation) reuse the device-resident pattern; each result must equal
+    the one of a fresh, uncached mesh bit for bit."""
+    rng = np.random.default_rng(22)
+    reqs = [dict(n=int(n), young=float(y), seed=int(s)) for n, y, s in
+            zip([5, 6, 5, 5, 6, 4, 5, 6], rng.uniform(2e4, 5e5, 8), rng.integers(0, 1 << 30, 8))]
+    scenes = [(r, sg.c5_request_scene(r)) for r in reqs]
+    res, stats = _run(symx, scenes, 3, precision=2)
+    assert stats.pattern_misses >= 3 and stats.pattern_hits >= 1
+    assert stats.pattern_hits + stats.pattern_misses == len(scenes)
+    prm = symx.step_params(dt=0.01, precision=2)
+    for (st, rep, x, v, _), (_, sc) in zip(res, scenes):
+        mesh = symx.Mesh(sc)
+        xd = torch.tensor(sc.x0, dtype=torch.float64, device="cuda")
+        vd = torch.tensor(sc.v0, dtype=torch.float64, device="cuda")
+        st2, rep2 = mesh.newton_step(xd, vd, prm)
+        mesh.close()
+        assert st == 0 and st2 == 0
+        assert np.array_equal(xd.cpu().numpy(), x) and np.array_equal(vd.cpu().numpy(), v)
+
+
+def test_idle_patterns_are_evicted_under_a_tight_budget(symx):
+    """With a budget that fits one request, cached patterns of other sizes must
+    make room: every request still runs and the charge stays in the budget."""
+    reqs = [dict(n=n, young=1e5, seed=30 + i) for i, n in enumerate([6, 4, 6, 5, 4, 6])]
+    scenes = [(r, sg.c5_request_scene(r)) for r in reqs]
+    budget = int(1.05 * max(_estimate(symx, sc, 2) for _, sc in scenes))
+    res, stats = _run(symx, scenes, 2, budget=budget, precision=2)
+    assert [r[0] for r in res] == [0] * len(scenes)
+    assert stats.peak_bytes <= stats.budget_bytes
+    assert stats.pattern_cache_bytes <= stats.budget_bytes
