@@ -62,29 +62,44 @@ struct DevBuf {
 // device memory
 // ---------------------------------------------------------------------------
 
-// Caching allocator for the meshes of one server.  Freed blocks are kept in
-// size-keyed free lists and handed out again, so a stream of requests does
+// Device memory of one server: large chunks from hipMalloc, carved into
+// blocks by best fit and coalesced on release, so a stream of requests does
 // not call hipMalloc / hipFree (hipFree can wait for work on other streams).
-// Blocks are returned to the device only by trim() or the destructor.
+// Chunks are added while the total stays within `capacity` (0: no limit; a
+// request that still does not fit gets a chunk of its own) and are returned
+// to the device only by the destructor.  Pinned host blocks are kept in
+// size-keyed free lists.
 class DevicePool {
  public:
-  explicit DevicePool(int device) : device_(device) {}
+  DevicePool(int device, size_t capacity) : device_(device), capacity_(capacity) {}
   ~DevicePool();
   DevicePool(const DevicePool&) = delete;
   DevicePool& operator=(const DevicePool&) = delete;
-  void* alloc(size_t bytes);  // null on failure
+  void* alloc(size_t bytes);  // 256-byte aligned; null on failure
   void release(void* p);
   void* alloc_pinned(size_t bytes);
   void release_pinned(void* p);
-  void trim();                // hipFree every cached free block
-  size_t cached_bytes();      // free bytes held by the pool
+  size_t chunk_bytes();       // device bytes held
+  size_t live_bytes();        // device bytes handed out
  private:
-  static size_t round_size(size_t bytes);
+  struct Chunk {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_at;  // offset -> length of each free range
+  };
+  using FreeKey = std::pair<Chunk*, size_t>;
+  void add_free(Chunk* c, size_t off, size_t len);
+  void remove_free(Chunk* c, size_t off, size_t len);
+  bool add_chunk(size_t min_bytes);
   int device_;
+  size_t capacity_;
   std::mutex mu_;
-  std::multimap<size_t, void*> free_, pinned_free_;
-  std::unordered_map<void*, size_t> live_, pinned_live_;
-  size_t cached_ = 0;
+  std::vector<std::unique_ptr<Chunk>> chunks_;
+  std::multimap<size_t, FreeKey> free_by_len_;                   // length -> (chunk, offset)
+  std::unordered_map<void*, std::pair<Chunk*, size_t>> live_;  // block -> (chunk, length)
+  size_t held_ = 0, live_bytes_ = 0;
+  std::multimap<size_t, void*> pinned_free_;
+  std::unordered_map<void*, size_t> pinned_live_;
 };
 
 // Through the pool when there is one, else hipMalloc / hipFree.

@@ -4,7 +4,7 @@
 // A request of the serving loop builds a mesh, runs one time step and frees
 // the mesh.  Without a pool every request would call hipMalloc / hipFree some
 // forty times, and hipFree may wait for kernels of other requests.  The pool
-// keeps freed blocks for reuse instead.  Requests whose scenes have the same
+// carves blocks out of a few large chunks instead (best fit, coalescing).  Requests whose scenes have the same
 // connectivity (same node count, energy kinds and element lists) also share
 // one Topology: the block pattern, incidence lists and contribution lists stay
 // on the device, and only the per-request rest data (positions, materials,
@@ -20,42 +20,61 @@ namespace symxi {
 // DevicePool
 // ---------------------------------------------------------------------------
 
-// Size classes: 4 KiB granules up to 64 KiB, then 1/8 of the next power of
-// two (at most 12.5% slack), so repeated requests of one scene size reuse
-// exactly the blocks they freed.
-size_t DevicePool::round_size(size_t bytes) {
-  if (bytes <= (size_t(64) << 10)) return std::max<size_t>(4096, (bytes + 4095) & ~size_t(4095));
-  size_t p2 = 1;
-  while (p2 < bytes) p2 <<= 1;
-  const size_t g = p2 >> 3;
-  return (bytes + g - 1) / g * g;
+namespace {
+constexpr size_t kAlign = 256;
+constexpr size_t kChunk = size_t(256) << 20;  // 256 MiB
+size_t align_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
+}  // namespace
+
+void DevicePool::add_free(Chunk* c, size_t off, size_t len) {
+  c->free_at[off] = len;
+  free_by_len_.emplace(len, FreeKey(c, off));
+}
+
+void DevicePool::remove_free(Chunk* c, size_t off, size_t len) {
+  c->free_at.erase(off);
+  auto r = free_by_len_.equal_range(len);
+  for (auto it = r.first; it != r.second; ++it)
+    if (it->second.first == c && it->second.second == off) {
+      free_by_len_.erase(it);
+      return;
+    }
+}
+
+bool DevicePool::add_chunk(size_t min_bytes) {
+  size_t size = std::max(kChunk, align_up(min_bytes, size_t(2) << 20));
+  if (capacity_ && held_ + size > capacity_ && held_ + min_bytes <= capacity_)
+    size = align_up(capacity_ - held_, kAlign);  // last chunk: what the capacity leaves
+  void* p = nullptr;
+  if (hipMalloc(&p, size) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  auto c = std::make_unique<Chunk>();
+  c->base = static_cast<char*>(p);
+  c->size = size;
+  add_free(c.get(), 0, size);
+  held_ += size;
+  chunks_.push_back(std::move(c));
+  return true;
 }
 
 void* DevicePool::alloc(size_t bytes) {
-  const size_t cls = round_size(bytes ? bytes : 1);
-  {
-    std::lock_guard<std::mutex> lk(mu_);
-    // smallest cached block of at least cls bytes, if not much larger
-    auto it = free_.lower_bound(cls);
-    if (it != free_.end() && it->first <= cls + cls / 2) {
-      void* p = it->second;
-      live_[p] = it->first;
-      cached_ -= it->first;
-      free_.erase(it);
-      return p;
-    }
-  }
-  void* p = nullptr;
-  if (hipMalloc(&p, cls) != hipSuccess) {
-    (void)hipGetLastError();
-    trim();
-    if (hipMalloc(&p, cls) != hipSuccess) {
-      (void)hipGetLastError();
-      return nullptr;
-    }
-  }
+  const size_t n = align_up(bytes ? bytes : 1, kAlign);
   std::lock_guard<std::mutex> lk(mu_);
-  live_[p] = cls;
+  auto it = free_by_len_.lower_bound(n);  // best fit
+  if (it == free_by_len_.end()) {
+    if (!add_chunk(n)) return nullptr;
+    it = free_by_len_.lower_bound(n);
+    if (it == free_by_len_.end()) return nullptr;
+  }
+  Chunk* c = it->second.first;
+  const size_t off = it->second.second, len = it->first;
+  remove_free(c, off, len);
+  if (len > n) add_free(c, off + n, len - n);
+  void* p = c->base + off;
+  live_[p] = {c, n};
+  live_bytes_ += n;
   return p;
 }
 
@@ -64,13 +83,32 @@ void DevicePool::release(void* p) {
   std::lock_guard<std::mutex> lk(mu_);
   auto it = live_.find(p);
   if (it == live_.end()) return;  // not ours: leave it alone
-  free_.emplace(it->second, p);
-  cached_ += it->second;
+  Chunk* c = it->second.first;
+  size_t off = size_t(static_cast<char*>(p) - c->base), len = it->second.second;
+  live_bytes_ -= len;
   live_.erase(it);
+  // coalesce with the free neighbours
+  auto next = c->free_at.find(off + len);
+  if (next != c->free_at.end()) {
+    const size_t nl = next->second;
+    remove_free(c, off + len, nl);
+    len += nl;
+  }
+  auto prev = c->free_at.lower_bound(off);
+  if (prev != c->free_at.begin()) {
+    --prev;
+    if (prev->first + prev->second == off) {
+      const size_t po = prev->first, pl = prev->second;
+      remove_free(c, po, pl);
+      off = po;
+      len += pl;
+    }
+  }
+  add_free(c, off, len);
 }
 
 void* DevicePool::alloc_pinned(size_t bytes) {
-  const size_t cls = round_size(bytes ? bytes : 1);
+  const size_t cls = align_up(bytes ? bytes : 1, 4096);
   {
     std::lock_guard<std::mutex> lk(mu_);
     auto it = pinned_free_.find(cls);
@@ -100,25 +138,19 @@ void DevicePool::release_pinned(void* p) {
   pinned_live_.erase(it);
 }
 
-void DevicePool::trim() {
-  std::multimap<size_t, void*> blocks;
-  {
-    std::lock_guard<std::mutex> lk(mu_);
-    blocks.swap(free_);
-    cached_ = 0;
-  }
-  for (auto& b : blocks) (void)hipFree(b.second);
+size_t DevicePool::chunk_bytes() {
+  std::lock_guard<std::mutex> lk(mu_);
+  return held_;
 }
 
-size_t DevicePool::cached_bytes() {
+size_t DevicePool::live_bytes() {
   std::lock_guard<std::mutex> lk(mu_);
-  return cached_;
+  return live_bytes_;
 }
 
 DevicePool::~DevicePool() {
-  // Called once no mesh of the pool is alive: every block is idle.
-  for (auto& b : free_) (void)hipFree(b.second);
-  for (auto& b : live_) (void)hipFree(b.first);
+  // Called once no mesh of the pool is alive.
+  for (auto& c : chunks_) (void)hipFree(c->base);
   for (auto& b : pinned_free_) (void)hipHostFree(b.second);
   for (auto& b : pinned_live_) (void)hipHostFree(b.first);
 }

@@ -15,9 +15,9 @@
 // request), and block patterns stay resident in a topology cache: a request
 // whose connectivity was seen before skips the pattern build and upload.
 // Budget accounting: running requests are charged their estimate; idle cached
-// patterns are charged their size and evicted when a request needs the room;
-// the pool's free blocks are returned to the device when, together with the
-// two, they would exceed the budget.
+// patterns are charged their size and evicted when a request needs the room.
+// The pool itself holds at most the budget in chunks (a request that does not
+// fit because of fragmentation gets a chunk beyond it).
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -165,12 +165,6 @@ void Server::worker(int slot) {
     dev_free(pool.get(), dx);
     dev_free(pool.get(), dv);
     if (m) mesh_free(m);
-    // the pool's free blocks count against the budget too
-    {
-      std::lock_guard<std::mutex> g(mu);
-      const size_t held = in_use - r->bytes + cache->idle_bytes() + pool->cached_bytes();
-      if (held > budget) pool->trim();
-    }
 
     lk.lock();
     r->status = st;
@@ -198,7 +192,7 @@ symx_status server_create(uint64_t budget, int32_t max_slots, Server** out) {
     delete s;
     return st;
   }
-  s->pool = std::make_unique<DevicePool>(s->device);
+  s->pool = std::make_unique<DevicePool>(s->device, budget);
   s->cache = std::make_unique<TopologyCache>(256);
   for (int i = 0; i < max_slots; ++i) {
     hipStream_t h = nullptr;
