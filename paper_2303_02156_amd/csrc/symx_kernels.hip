@@ -793,10 +793,19 @@ __global__ __launch_bounds__(256) void k_residual64(int64_t N, const int* __rest
 // workgroup of the next kernel.  Scalars live in a small device array; rz of
 // iteration k is kept in slot S_RZ + (k & 1) so that readers of the previous
 // value never race with the writer of the new one.
-// Grid sizes: the SpMV kernel streams the matrix and runs best with 2048
-// workgroups; the node-wise kernels use 1024.  Each partial array holds up to
-// kPcgP entries.
+// Grid sizes: the SpMV kernel streams the matrix and runs best with up to
+// 2048 workgroups; the node-wise kernels use up to 1024.  Small meshes get
+// grids sized to their rows (gs a multiple of 8), so that no launch is made
+// of workgroups with nothing to do.  Each partial array holds up to kPcgP
+// entries.
 constexpr int kPcgGs = 2048, kPcgGu = 1024, kPcgP = 4096;
+static int pcg_gs(int64_t N) {
+  const int64_t g = (N * 16 + 255) / 256;
+  return (int)std::min<int64_t>(kPcgGs, std::max<int64_t>(8, (g + 7) / 8 * 8));
+}
+static int pcg_gu(int64_t N) {
+  return (int)std::min<int64_t>(kPcgGu, std::max<int64_t>(1, (N + 255) / 256));
+}
 enum { S_DONE = 0, S_ITERS, S_TOL2, S_BB, S_RZ, S_RZ1, S_MAXIT, S_NSCALARS };
 enum { P_RZ = 0, P_RR = 1, P_BB = 2, P_PQ = 3 };  // partial arrays, kPcgP each
 
@@ -850,18 +859,21 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restric
 // Iteration k: reduce rz, rr of the previous update; stop on convergence or
 // at the iteration limit; beta = rz_k / rz_(k-1); w = A z; p = z + beta p;
 // q = w + beta q; partials of p.q.
+// Rows: workgroup b runs on XCD b % 8 and takes, in steps of 16 rows, the
+// rows of the XCD's contiguous eighth of the matrix, so that the gathered
+// entries of z stay in that XCD's L2 (gridDim.x is a multiple of 8).
 template <typename T>
 __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* __restrict__ row_ptr,
                                                   const int* __restrict__ col,
                                                   const T* __restrict__ vals, int64_t nnzb,
                                                   const T* __restrict__ z, T* __restrict__ p,
                                                   T* __restrict__ q, double* __restrict__ P,
-                                                  double* __restrict__ S) {
+                                                  double* __restrict__ S, int gu) {
   if (S[S_DONE] != 0.0) return;
   __shared__ double sh[4];
-  const double rz = sum_partials(P + P_RZ * kPcgP, kPcgGu, sh);
-  const double rr = sum_partials(P + P_RR * kPcgP, kPcgGu, sh);
-  const double bb = k == 0 ? sum_partials(P + P_BB * kPcgP, kPcgGu, sh) : S[S_BB];
+  const double rz = sum_partials(P + P_RZ * kPcgP, gu, sh);
+  const double rr = sum_partials(P + P_RR * kPcgP, gu, sh);
+  const double bb = k == 0 ? sum_partials(P + P_BB * kPcgP, gu, sh) : S[S_BB];
   const bool first = blockIdx.x == 0 && threadIdx.x == 0;
   if (bb == 0.0 || rr <= S[S_TOL2] * bb || k >= int(S[S_MAXIT]) || !isfinite(rr)) {
     if (first) {
@@ -876,9 +888,12 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* _
     if (k == 0) S[S_BB] = bb;
   }
   const int lane = threadIdx.x & 15;
+  const int xcd = blockIdx.x & 7;
+  const int64_t lo = N * xcd / 8, hi = N * (xcd + 1) / 8;
+  const int64_t stride = (int64_t)(gridDim.x >> 3) * 16;
   double pq = 0.0;
-  for (int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4; row < N;
-       row += ((int64_t)gridDim.x * 256) >> 4) {
+  for (int64_t row = lo + (int64_t)(blockIdx.x >> 3) * 16 + (threadIdx.x >> 4); row < hi;
+       row += stride) {
     T acc[3];
     spmv_row<T, T, T>((int)row, lane, row_ptr, col, vals, nnzb, z, acc);
     if (lane == 0) {
@@ -906,10 +921,10 @@ __global__ __launch_bounds__(256) void k_pcg_update(int k, int64_t N, const T* _
                                                     T* __restrict__ z, const T* __restrict__ p,
                                                     const T* __restrict__ q,
                                                     double* __restrict__ P,
-                                                    double* __restrict__ S) {
+                                                    double* __restrict__ S, int gs) {
   if (S[S_DONE] != 0.0) return;
   __shared__ double sh[4];
-  const double pq = sum_partials(P + P_PQ * kPcgP, kPcgGs, sh);
+  const double pq = sum_partials(P + P_PQ * kPcgP, gs, sh);
   if (!(pq > 0.0)) {  // direction of non-positive curvature: stop
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       S[S_DONE] = 2.0;
@@ -1244,12 +1259,13 @@ symx_status launch_diag_inverse(Mesh& m, int precision, void* Dinv) {
 symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const double* b,
                             double tol2, int max_iter) {
   const char* PNAME = "pcg_init";
+  const int gu = pcg_gu(m.N);
   if (precision == SYMX_F64)
-    SYMX_LAUNCH(m, PNAME, (k_pcg_init<double, double>), dim3(kPcgGu), dim3(256), 0, m.N, b,
+    SYMX_LAUNCH(m, PNAME, (k_pcg_init<double, double>), dim3(gu), dim3(256), 0, m.N, b,
                        (const double*)B.Dinv, (double*)B.xs, (double*)B.r, (double*)B.z,
                        (double*)B.p, (double*)B.q, m.partials, m.scalars, tol2, max_iter);
   else
-    SYMX_LAUNCH(m, PNAME, (k_pcg_init<float, double>), dim3(kPcgGu), dim3(256), 0, m.N, b,
+    SYMX_LAUNCH(m, PNAME, (k_pcg_init<float, double>), dim3(gu), dim3(256), 0, m.N, b,
                        (const float*)B.Dinv, (float*)B.xs, (float*)B.r, (float*)B.z, (float*)B.p,
                        (float*)B.q, m.partials, m.scalars, tol2, max_iter);
   LAUNCH_CHECK("k_pcg_init");
@@ -1258,28 +1274,29 @@ symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const d
 
 // Enqueue iterations k0 .. k0+n_iter-1 (each: SpMV kernel, update kernel).
 symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0, int n_iter) {
+  const int gs = pcg_gs(m.N), gu = pcg_gu(m.N);
   for (int it = k0; it < k0 + n_iter; ++it) {
     {
       const char* PNAME = "pcg_spmv";
       if (precision == SYMX_F64)
-        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<double>, dim3(kPcgGs), dim3(256), 0, it, m.N,
+        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<double>, dim3(gs), dim3(256), 0, it, m.N,
                            m.row_ptr, m.col_idx, m.vals64, m.nnzb, (const double*)B.z,
-                           (double*)B.p, (double*)B.q, m.partials, m.scalars);
+                           (double*)B.p, (double*)B.q, m.partials, m.scalars, gu);
       else
-        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<float>, dim3(kPcgGs), dim3(256), 0, it, m.N,
+        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<float>, dim3(gs), dim3(256), 0, it, m.N,
                            m.row_ptr, m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p,
-                           (float*)B.q, m.partials, m.scalars);
+                           (float*)B.q, m.partials, m.scalars, gu);
     }
     {
       const char* PNAME = "pcg_update";
       if (precision == SYMX_F64)
-        SYMX_LAUNCH(m, PNAME, k_pcg_update<double>, dim3(kPcgGu), dim3(256), 0, it, m.N,
+        SYMX_LAUNCH(m, PNAME, k_pcg_update<double>, dim3(gu), dim3(256), 0, it, m.N,
                            (const double*)B.Dinv, (double*)B.xs, (double*)B.r, (double*)B.z,
-                           (const double*)B.p, (const double*)B.q, m.partials, m.scalars);
+                           (const double*)B.p, (const double*)B.q, m.partials, m.scalars, gs);
       else
-        SYMX_LAUNCH(m, PNAME, k_pcg_update<float>, dim3(kPcgGu), dim3(256), 0, it, m.N,
+        SYMX_LAUNCH(m, PNAME, k_pcg_update<float>, dim3(gu), dim3(256), 0, it, m.N,
                            (const float*)B.Dinv, (float*)B.xs, (float*)B.r, (float*)B.z,
-                           (const float*)B.p, (const float*)B.q, m.partials, m.scalars);
+                           (const float*)B.p, (const float*)B.q, m.partials, m.scalars, gs);
     }
   }
   LAUNCH_CHECK("k_pcg");

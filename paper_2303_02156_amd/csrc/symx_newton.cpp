@@ -202,7 +202,10 @@ static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rto
       set_error("PCG did not stop");
       return SYMX_ERR_DEVICE;
     }
-    chunk = 8;
+    // past the prediction: short chunks; with no prediction (a fresh mesh),
+    // chunks that double, so both the launches that run past convergence and
+    // the host synchronisations stay few
+    chunk = m.last_pcg_iters[slot] > 0 ? 8 : std::min(64, std::max(8, k));
   }
   m.last_pcg_iters[slot] = done_iters;
   *iters = done_iters;
