@@ -257,116 +257,161 @@ __global__ __launch_bounds__(128) void k_elem_eval(SetDev S, const double* __res
 }
 
 // ---------------------------------------------------------------------------
-// nearest-PSD projection of element Hessians: cyclic Jacobi in round-robin
-// (parallel) order, one 64-lane workgroup per element, then
-// H <- H - sum over negative eigenvalues of lambda v v^T.
+// nearest-PSD projection of element Hessians (Sec. 5.2, projection to a
+// positive semi-definite matrix): H <- H - sum over negative eigenvalues of
+// lambda u u^T.  One element per lane, everything in registers.
+//
+// Every element energy here is translation invariant, so H (1 (x) t) = 0 for
+// every t and H = Q M Q^T exactly, where the columns of Q = [h_i (x) I_3] are
+// an orthonormal basis of the node-space vectors orthogonal to (1, ..., 1)
+// (Helmert basis: h_i = (1, ..., 1, -(i+1), 0, ...) / sqrt((i+1)(i+2)),
+// i = 0..K-2) and M = Q^T H Q is (3K-3) x (3K-3).  The spectrum of H is that
+// of M plus three zeros (translations), with eigenvectors u = Q w, so
+// projecting M projects H.  M's upper triangle is diagonalised by cyclic
+// Jacobi rotations (Golub & Van Loan, Alg. 8.4.3: one sweep visits every pair
+// p < q in row order), accumulated in V.  Indices are compile-time constants
+// once a sweep is unrolled.
 // ---------------------------------------------------------------------------
+template <int R>
+__device__ constexpr int up_idx(int i, int j) {
+  return i <= j ? i * R - i * (i - 1) / 2 + (j - i) : j * R - j * (j - 1) / 2 + (i - j);
+}
+
+// Helmert basis vector i (i = 0..K-2) at node a.
 template <typename T>
-__global__ __launch_bounds__(64) void k_project_psd(T* __restrict__ H, int64_t n, int dim,
-                                                    int max_sweeps, double tol) {
-  __shared__ T A[2][144];
-  __shared__ T V[2][144];
-  __shared__ T H0[144];
-  __shared__ T ca[12], cb[12];
-  __shared__ int partner[12];
-  __shared__ double red[64];
-  __shared__ int any_neg;
-  const int t = threadIdx.x;
-  const int np = dim + (dim & 1);  // even size for the round-robin schedule
-  const int nn = np * np;
-  for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
-    T* He = H + e * dim * dim;
-    for (int idx = t; idx < nn; idx += 64) {
-      int i = idx / np, j = idx % np;
-      T v = (i < dim && j < dim) ? He[i * dim + j] : T(0);
-      A[0][idx] = v;
-      H0[idx] = v;
-      V[0][idx] = (i == j) ? T(1) : T(0);
-    }
-    __syncthreads();
-    int cur = 0;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-      // convergence test on the current matrix
-      double off = 0.0, tot = 0.0;
-      for (int idx = t; idx < nn; idx += 64) {
-        double v = double(A[cur][idx]);
-        tot += v * v;
-        if (idx / np != idx % np) off += v * v;
-      }
-      red[t] = off;
-      __syncthreads();
-      for (int s = 32; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-      }
-      double off_sum = red[0];
-      __syncthreads();
-      red[t] = tot;
-      __syncthreads();
-      for (int s = 32; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-      }
-      double tot_sum = red[0];
-      __syncthreads();
-      if (off_sum <= tol * tol * tot_sum) break;
-      for (int round = 0; round < np - 1; ++round) {
-        if (t < np / 2) {
-          int p, q;
-          if (t == 0) {
-            p = np - 1;
-            q = round;
-          } else {
-            p = (round + t) % (np - 1);
-            q = (round - t + (np - 1)) % (np - 1);
-          }
-          if (p > q) { int tmp = p; p = q; q = tmp; }
-          T apq = A[cur][p * np + q];
-          T app = A[cur][p * np + p];
-          T aqq = A[cur][q * np + q];
-          T c = T(1), s = T(0);
-          if (apq != T(0)) {
-            T tau = (aqq - app) / (T(2) * apq);
-            T tt = (tau >= T(0) ? T(1) : T(-1)) / (fabs(tau) + sqrt(T(1) + tau * tau));
-            c = T(1) / sqrt(T(1) + tt * tt);
-            s = tt * c;
-          }
-          ca[p] = c; cb[p] = -s; partner[p] = q;
-          ca[q] = c; cb[q] = s; partner[q] = p;
-        }
-        __syncthreads();
-        const int nx = cur ^ 1;
-        for (int idx = t; idx < nn; idx += 64) {
-          int i = idx / np, j = idx % np;
-          int pi = partner[i], pj = partner[j];
-          T ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
-          A[nx][idx] = ai * aj * A[cur][i * np + j] + ai * bj * A[cur][i * np + pj] +
-                       bi * aj * A[cur][pi * np + j] + bi * bj * A[cur][pi * np + pj];
-          V[nx][idx] = aj * V[cur][i * np + j] + bj * V[cur][i * np + pj];
-        }
-        __syncthreads();
-        cur = nx;
-      }
-    }
-    if (t == 0) {
-      int neg = 0;
-      for (int i = 0; i < dim; ++i) neg |= (A[cur][i * np + i] < T(0));
-      any_neg = neg;
-    }
-    __syncthreads();
-    if (any_neg) {
-      for (int idx = t; idx < dim * dim; idx += 64) {
-        int i = idx / dim, j = idx % dim;
-        T acc = H0[i * np + j];
-        for (int kk = 0; kk < dim; ++kk) {
-          T lam = A[cur][kk * np + kk];
-          if (lam < T(0)) acc -= lam * V[cur][i * np + kk] * V[cur][j * np + kk];
-        }
-        He[idx] = acc;
-      }
-    }
-    __syncthreads();
+__device__ constexpr T helmert(int i, int a) {
+  return a <= i ? T(1) / sqrt(T((i + 1) * (i + 2)))
+                : (a == i + 1 ? -T(i + 1) / sqrt(T((i + 1) * (i + 2))) : T(0));
+}
+
+// One Jacobi rotation zeroing a(p,q) (Golub & Van Loan, Alg. 8.4.1): with
+// tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+// c = 1 / sqrt(1 + t^2), s = t c:  A <- J^T A J, V <- V J.
+template <typename T, int R, int P, int Q>
+__device__ __forceinline__ void jacobi_rotate(T* a, T* v) {
+  const T apq = a[up_idx<R>(P, Q)];
+  const T app = a[up_idx<R>(P, P)], aqq = a[up_idx<R>(Q, Q)];
+  const bool nz = apq != T(0);
+  const T tau = (aqq - app) / (T(2) * (nz ? apq : T(1)));
+  T t = T(1) / (fabs(tau) + sqrt(T(1) + tau * tau));
+  t = nz ? (tau < T(0) ? -t : t) : T(0);
+  const T c = T(1) / sqrt(T(1) + t * t);
+  const T sn = t * c;
+  a[up_idx<R>(P, P)] = app - t * apq;
+  a[up_idx<R>(Q, Q)] = aqq + t * apq;
+  a[up_idx<R>(P, Q)] = T(0);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k == P || k == Q) continue;
+    const T akp = a[up_idx<R>(k, P)], akq = a[up_idx<R>(k, Q)];
+    a[up_idx<R>(k, P)] = c * akp - sn * akq;
+    a[up_idx<R>(k, Q)] = sn * akp + c * akq;
   }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const T vkp = v[k * R + P], vkq = v[k * R + Q];
+    v[k * R + P] = c * vkp - sn * vkq;
+    v[k * R + Q] = sn * vkp + c * vkq;
+  }
+}
+
+template <typename T, int R, int P, int Q>
+__device__ __forceinline__ void jacobi_sweep_from(T* a, T* v) {
+  if constexpr (P < R - 1) {
+    jacobi_rotate<T, R, P, Q>(a, v);
+    if constexpr (Q + 1 < R)
+      jacobi_sweep_from<T, R, P, Q + 1>(a, v);
+    else
+      jacobi_sweep_from<T, R, P + 1, P + 2>(a, v);
+  }
+}
+
+// K nodes per element: H is D x D with D = 3K, M is R x R with R = 3K - 3.
+template <typename T, int K>
+__device__ __forceinline__ void project_psd_lane(T* __restrict__ H, int64_t n, int max_sweeps,
+                                                 T tol) {
+  constexpr int D = 3 * K, R = 3 * (K - 1), NU = R * (R + 1) / 2;
+  for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 64) {
+    T* He = H + e * D * D;
+    T a[NU], v[R * R];
+    // M = Q^T H Q, upper triangle; reduced index 3i + c (basis vector i, coord c)
+#pragma unroll
+    for (int k = 0; k < NU; ++k) a[k] = T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        T hb[K][K];  // node block (a, b) of H for coordinates (c, d)
+#pragma unroll
+        for (int na = 0; na < K; ++na)
+#pragma unroll
+          for (int nb = 0; nb < K; ++nb) hb[na][nb] = He[(3 * na + c) * D + 3 * nb + d];
+#pragma unroll
+        for (int i = 0; i < K - 1; ++i)
+#pragma unroll
+          for (int j = 0; j < K - 1; ++j) {
+            if (3 * i + c > 3 * j + d) continue;
+            T m = T(0);
+#pragma unroll
+            for (int na = 0; na <= i + 1; ++na)
+#pragma unroll
+              for (int nb = 0; nb <= j + 1; ++nb)
+                m += helmert<T>(i, na) * helmert<T>(j, nb) * hb[na][nb];
+            a[up_idx<R>(3 * i + c, 3 * j + d)] = m;
+          }
+      }
+#pragma unroll
+    for (int k = 0; k < R * R; ++k) v[k] = (k % (R + 1) == 0) ? T(1) : T(0);
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      T off = T(0), dia = T(0);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        dia += a[up_idx<R>(i, i)] * a[up_idx<R>(i, i)];
+#pragma unroll
+        for (int j = i + 1; j < R; ++j) off += a[up_idx<R>(i, j)] * a[up_idx<R>(i, j)];
+      }
+      if (off <= tol * tol * (dia + T(2) * off)) break;
+      jacobi_sweep_from<T, R, 0, 1>(a, v);
+    }
+    bool neg = false;
+#pragma unroll
+    for (int k = 0; k < R; ++k) neg |= a[up_idx<R>(k, k)] < T(0);
+    if (!neg) continue;  // already PSD: H stays as it is
+    // H <- H - sum_k min(lambda_k, 0) u_k u_k^T with u_k = Q w_k, done one
+    // eigenpair at a time (lanes skip the non-negative ones)
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const T lam = a[up_idx<R>(k, k)];
+      if (!(lam < T(0))) continue;
+      T u[D];
+#pragma unroll
+      for (int na = 0; na < K; ++na)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T s = T(0);
+#pragma unroll
+          for (int i = 0; i < K - 1; ++i) s += helmert<T>(i, na) * v[(3 * i + c) * R + k];
+          u[3 * na + c] = s;
+        }
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+#pragma unroll
+        for (int q = 0; q < D; ++q) He[p * D + q] -= lam * u[p] * u[q];
+    }
+  }
+}
+
+// Single precision fits A and V in 256 registers: two waves per SIMD.  Double
+// precision needs more and runs one wave per SIMD.
+template <int K>
+__global__ __launch_bounds__(64, 2) void k_project_psd32(float* __restrict__ H, int64_t n,
+                                                         int max_sweeps, float tol) {
+  project_psd_lane<float, K>(H, n, max_sweeps, tol);
+}
+template <int K>
+__global__ __launch_bounds__(64) void k_project_psd64(double* __restrict__ H, int64_t n,
+                                                      int max_sweeps, double tol) {
+  project_psd_lane<double, K>(H, n, max_sweeps, tol);
 }
 
 // ---------------------------------------------------------------------------
@@ -1111,13 +1156,27 @@ symx_status launch_elem_eval(Mesh& m, int set, const double* x, int want, int pr
 symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim) {
   const char* PNAME = "project_psd";
   if (n == 0) return SYMX_OK;
-  const int G = grid_for(n, 1, 65535);
-  if (precision == SYMX_F32)
-    SYMX_LAUNCH(m, PNAME, k_project_psd<float>, dim3(G), dim3(64), 0, (float*)H, n, dim, 30,
-                       1e-7);
-  else
-    SYMX_LAUNCH(m, PNAME, k_project_psd<double>, dim3(G), dim3(64), 0, (double*)H, n, dim,
-                       30, 1e-15);
+  if (dim != 9 && dim != 12) {
+    set_error("projection supports 9x9 and 12x12 element Hessians");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  // stop when the off-diagonal norm is below tol times the matrix norm
+  const int G = grid_for(n, 64, 65535);
+  if (precision == SYMX_F32) {
+    if (dim == 12)
+      SYMX_LAUNCH(m, PNAME, k_project_psd32<4>, dim3(G), dim3(64), 0, (float*)H, n, 30,
+                  2e-7f);
+    else
+      SYMX_LAUNCH(m, PNAME, k_project_psd32<3>, dim3(G), dim3(64), 0, (float*)H, n, 30,
+                  2e-7f);
+  } else {
+    if (dim == 12)
+      SYMX_LAUNCH(m, PNAME, k_project_psd64<4>, dim3(G), dim3(64), 0, (double*)H, n, 30,
+                  1e-15);
+    else
+      SYMX_LAUNCH(m, PNAME, k_project_psd64<3>, dim3(G), dim3(64), 0, (double*)H, n, 30,
+                  1e-15);
+  }
   LAUNCH_CHECK("k_project_psd");
   return SYMX_OK;
 }

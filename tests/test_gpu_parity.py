@@ -134,6 +134,34 @@ def test_elem_projection_matches_eigh(symx):
     mesh.close()
 
 
+def test_elem_projection_membrane_and_hinge_match_eigh(symx):
+    """9x9 membrane and 12x12 hinge Hessians of a strongly perturbed cloth: the
+    projection of each element equals the eigendecomposition-based oracle.
+    Errors are measured against the element's unprojected Hessian: the nearest
+    PSD map is 1-Lipschitz, and a fully compressed membrane projects to zero,
+    where an error relative to the result itself has no scale."""
+    scene = sg.cloth_scene(6, perturb=0.3)
+    x = scene.x0 + np.random.default_rng(12).normal(scale=0.03, size=scene.x0.shape)
+    mesh = symx.Mesh(scene)
+    flags = symx.SYMX_EVAL_HESS | symx.SYMX_PROJECT_PSD
+    for si, es in enumerate(scene.energies):
+        D = 3 * es.conn.shape[1]
+        _, _, Ho = elements.element_eval(es, x, scene.X)
+        Ho = Ho.reshape(-1, D, D)
+        Po = projection.project_psd(Ho)
+        for p, tol in ((symx.SYMX_F64, F64_TOL), (symx.SYMX_F32, F32_TOL)):
+            _, _, H = mesh.eval_derivatives(si, x, flags=flags, precision=p)
+            Hd = H.cpu().numpy().astype(np.float64).reshape(-1, D, D)
+            worst = max(np.max(np.abs(Hd[e] - Po[e])) / np.max(np.abs(Ho[e]))
+                        for e in range(Hd.shape[0]))
+            assert worst < tol, (si, p, worst)
+    n_neg = np.sum(np.linalg.eigvalsh(
+        elements.element_eval(scene.energies[0], x, scene.X)[2].reshape(-1, 9, 9)).min(axis=1)
+        < -1e-9)
+    assert n_neg > 10  # the membrane set really exercises the projection
+    mesh.close()
+
+
 # ---------------------------------------------------------------------------
 # global assembly
 # ---------------------------------------------------------------------------
@@ -182,6 +210,24 @@ def test_projected_assembly_c1(symx):
     assert rel(g.cpu().numpy(), ref["g"]) < F64_TOL
     E32, g32, v32 = mesh.assemble(x, xt, 0.01, flags, symx.SYMX_F32)
     assert rel(_bsr(v32), ref["vals"]) < F32_TOL
+    mesh.close()
+
+
+def test_projected_assembly_mixed(symx):
+    scene = mixed_scene()
+    x = scene.x0 + np.random.default_rng(5).normal(scale=0.02, size=scene.x0.shape)
+    x[scene.fixed.astype(bool)] = scene.X[scene.fixed.astype(bool)]
+    mesh = symx.Mesh(scene)
+    xt = elements.x_tilde(scene.x0, scene.v0, 0.01, scene.gravity)
+    flags = (symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+             | symx.SYMX_PROJECT_PSD)
+    ref = assembly.assemble(scene, x, xt, 0.01, project=True)
+    raw = assembly.assemble(scene, x, xt, 0.01, project=False)
+    assert rel(raw["vals"], ref["vals"]) > 1e-6
+    for p, tol in ((symx.SYMX_F64, F64_TOL), (symx.SYMX_F32, F32_TOL)):
+        E, g, vals = mesh.assemble(x, xt, 0.01, flags, p)
+        assert rel(_bsr(vals), ref["vals"]) < tol
+        assert rel(g.cpu().numpy(), ref["g"]) < tol
     mesh.close()
 
 
