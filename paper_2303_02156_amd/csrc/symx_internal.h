@@ -132,7 +132,6 @@ struct Topology {
   int* diag_pos = nullptr;          // N: index of block (i,i)
   int* inc_ptr = nullptr;           // N+1
   uint32_t* inc_code = nullptr;     // n_inc
-  uint32_t* inc_slots = nullptr;    // n_inc: 4 x uint8 slots (relabelled order)
   int* batch_row = nullptr;         // n_batch+1
   uint32_t* blk_info = nullptr;     // nnzb: off-diagonal contribution list (start << 8 | count)
   uint16_t* centry = nullptr;       // contribution entries (incidence << 2 | node)
@@ -221,7 +220,6 @@ struct Mesh {
   const int* diag_pos = nullptr;
   const int* inc_ptr = nullptr;
   const uint32_t* inc_code = nullptr;
-  const uint32_t* inc_slots = nullptr;
   const int* batch_row = nullptr;
   const uint32_t* blk_info = nullptr;
   const uint16_t* centry = nullptr;

@@ -284,18 +284,38 @@ __device__ constexpr T helmert(int i, int a) {
                 : (a == i + 1 ? -T(i + 1) / sqrt(T((i + 1) * (i + 2))) : T(0));
 }
 
-// One Jacobi rotation zeroing a(p,q) (Golub & Van Loan, Alg. 8.4.1): with
-// tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
-// c = 1 / sqrt(1 + t^2), s = t c:  A <- J^T A J, V <- V J.
-template <typename T, int R, int P, int Q>
-__device__ __forceinline__ void jacobi_rotate(T* a, T* v) {
+// Reciprocal, reciprocal square root and square root for the rotation
+// parameters: the hardware approximations (about 1 ulp) in single precision,
+// correctly rounded operations in double precision.
+__device__ __forceinline__ float rot_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rot_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float rot_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double rot_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ double rot_rsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ double rot_sqrt(double x) { return sqrt(x); }
+
+// Eigenvector matrix V (R x R, row-major) of one lane: in registers, or in
+// LDS with the lanes of the workgroup interleaved (entry i at i * 64 + lane).
+template <typename T, int STRIDE>
+struct LaneMat {
+  T* p;
+  __device__ __forceinline__ T& operator[](int i) const { return p[i * STRIDE]; }
+};
+
+// One Jacobi rotation zeroing a(p,q) (Golub & Van Loan, Alg. 8.4.1): the
+// smaller root t of t^2 + 2 tau t - 1 = 0 with tau = (a_qq - a_pp) / (2 a_pq),
+// written as t = sign(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp
+// (no division by a_pq, no overflow of tau^2); c = 1 / sqrt(1 + t^2), s = t c;
+// A <- J^T A J, V <- V J.
+template <typename T, int R, int P, int Q, typename VM>
+__device__ __forceinline__ void jacobi_rotate(T* a, VM v) {
   const T apq = a[up_idx<R>(P, Q)];
   const T app = a[up_idx<R>(P, P)], aqq = a[up_idx<R>(Q, Q)];
-  const bool nz = apq != T(0);
-  const T tau = (aqq - app) / (T(2) * (nz ? apq : T(1)));
-  T t = T(1) / (fabs(tau) + sqrt(T(1) + tau * tau));
-  t = nz ? (tau < T(0) ? -t : t) : T(0);
-  const T c = T(1) / sqrt(T(1) + t * t);
+  const T d = aqq - app;
+  const T den = fabs(d) + rot_sqrt(d * d + T(4) * apq * apq);
+  const T num = d < T(0) ? T(-2) * apq : T(2) * apq;
+  const T t = (apq != T(0) && den > T(0)) ? num * rot_rcp(den) : T(0);
+  const T c = rot_rsq(T(1) + t * t);
   const T sn = t * c;
   a[up_idx<R>(P, P)] = app - t * apq;
   a[up_idx<R>(Q, Q)] = aqq + t * apq;
@@ -315,8 +335,8 @@ __device__ __forceinline__ void jacobi_rotate(T* a, T* v) {
   }
 }
 
-template <typename T, int R, int P, int Q>
-__device__ __forceinline__ void jacobi_sweep_from(T* a, T* v) {
+template <typename T, int R, int P, int Q, typename VM>
+__device__ __forceinline__ void jacobi_sweep_from(T* a, VM v) {
   if constexpr (P < R - 1) {
     jacobi_rotate<T, R, P, Q>(a, v);
     if constexpr (Q + 1 < R)
@@ -327,13 +347,16 @@ __device__ __forceinline__ void jacobi_sweep_from(T* a, T* v) {
 }
 
 // K nodes per element: H is D x D with D = 3K, M is R x R with R = 3K - 3.
-template <typename T, int K>
+// vstore: null keeps V in registers, else the workgroup's LDS array of R*R*64.
+template <typename T, int K, int VSTRIDE>
 __device__ __forceinline__ void project_psd_lane(T* __restrict__ H, int64_t n, int max_sweeps,
-                                                 T tol) {
+                                                 T tol, T* vstore) {
   constexpr int D = 3 * K, R = 3 * (K - 1), NU = R * (R + 1) / 2;
+  T vreg[VSTRIDE == 1 ? R * R : 1];
+  const LaneMat<T, VSTRIDE> v{VSTRIDE == 1 ? vreg : vstore + threadIdx.x};
   for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 64) {
     T* He = H + e * D * D;
-    T a[NU], v[R * R];
+    T a[NU];
     // M = Q^T H Q, upper triangle; reduced index 3i + c (basis vector i, coord c)
 #pragma unroll
     for (int k = 0; k < NU; ++k) a[k] = T(0);
@@ -406,12 +429,19 @@ __device__ __forceinline__ void project_psd_lane(T* __restrict__ H, int64_t n, i
 template <int K>
 __global__ __launch_bounds__(64, 2) void k_project_psd32(float* __restrict__ H, int64_t n,
                                                          int max_sweeps, float tol) {
-  project_psd_lane<float, K>(H, n, max_sweeps, tol);
+  project_psd_lane<float, K, 1>(H, n, max_sweeps, tol, nullptr);
 }
+// Double precision: the 9 x 9 V of four-node elements lives in LDS (41 KiB per
+// 64-lane workgroup); registers alone would spill to scratch.
 template <int K>
 __global__ __launch_bounds__(64) void k_project_psd64(double* __restrict__ H, int64_t n,
                                                       int max_sweeps, double tol) {
-  project_psd_lane<double, K>(H, n, max_sweeps, tol);
+  if constexpr (K == 4) {
+    __shared__ double vs[9 * 9 * 64];
+    project_psd_lane<double, K, 64>(H, n, max_sweeps, tol, vs);
+  } else {
+    project_psd_lane<double, K, 1>(H, n, max_sweeps, tol, nullptr);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -429,9 +459,9 @@ struct RowArgs {
   const int* batch_row;
   const int* row_ptr;
   const int* col_idx;
+  const int* diag_pos;
   const int* inc_ptr;
   const uint32_t* inc_code;
-  const uint32_t* inc_slots;
   const uint32_t* blk_info;
   const uint16_t* centry;
   const int* batch_entry;
@@ -444,133 +474,57 @@ struct RowArgs {
   int* nonfinite;
 };
 
-// Contribution of one incidence: out[0..2] gradient of node a, out[3 + 12 i +
-// 3 b + k] Hessian entry (a_i, node b of the relabelled order, coord k).
-template <typename T, bool FROM_ELEM, bool WANT_H>
-__device__ __forceinline__ void incidence_row(const RowArgs<T>& A, uint32_t code, T* out) {
+// Gradient row of one incidence (element e seen from its local node a).
+template <typename T, bool FROM_ELEM>
+__device__ __forceinline__ void incidence_grad(const RowArgs<T>& A, uint32_t code, T* out) {
   const int si = inc_set(code);
   const int a = inc_local(code);
   const int64_t e = inc_elem(code);
   const SetDev& S = A.sets.s[si];
-  const Relabel R = relabel(S.conn[e], a);
   if (FROM_ELEM) {
-    const int D = 3 * S.k;
-    const T* ge = (const T*)A.elem_g[si] + e * D;
-    const T* He = (const T*)A.elem_H[si] + e * D * D;
+    const T* ge = (const T*)A.elem_g[si] + e * 3 * S.k;
     out[0] = ge[3 * a];
     out[1] = ge[3 * a + 1];
     out[2] = ge[3 * a + 2];
-    if (WANT_H) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk)
-            out[3 + 12 * i + 3 * b + kk] =
-                b < S.k ? He[(3 * a + i) * D + 3 * R.loc[b] + kk] : T(0);
-    }
     return;
   }
+  const Relabel R = relabel(S.conn[e], a);
   T in[26];
   if (S.kind == SYMX_SNH_TET4) {
     fill_solid<T, 4>(S, e, R, A.x, A.X, in);
-    if (WANT_H)
-      snh_tet4_row0_gH<T>(in, out);
-    else
-      snh_tet4_row0_g<T>(in, out);
+    snh_tet4_row0_g<T>(in, out);
   } else if (S.kind == SYMX_HINGE4) {
     fill_hinge<T>(S, e, R, A.x, in);
-    if (WANT_H)
-      hinge4_row0_gH<T>(in, out);
-    else
-      hinge4_row0_g<T>(in, out);
+    hinge4_row0_g<T>(in, out);
   } else {
     fill_solid<T, 3>(S, e, R, A.x, A.X, in);
-    if (WANT_H) {
-      T o[30];
-      stvk_tri3_row0_gH<T>(in, o);
-      out[0] = o[0];
-      out[1] = o[1];
-      out[2] = o[2];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-#pragma unroll
-        for (int v = 0; v < 9; ++v) out[3 + 12 * i + v] = o[3 + 9 * i + v];
-#pragma unroll
-        for (int v = 9; v < 12; ++v) out[3 + 12 * i + v] = T(0);
-      }
-    } else {
-      stvk_tri3_row0_g<T>(in, out);
-    }
+    stvk_tri3_row0_g<T>(in, out);
   }
 }
 
-template <typename T, bool FROM_ELEM, bool WANT_G, bool WANT_H>
-__global__ __launch_bounds__(kRowWG) void k_row_assemble(RowArgs<T> A) {
-  constexpr int NV = WANT_H ? 39 : 3;
-  __shared__ T st[NV][kRowWG];
-  __shared__ uint32_t sl[kRowWG];
-  __shared__ int s_blk[kRowWG + 1];
+// Gradient-only row assembly: one lane per incidence of the batch's rows, then
+// one lane per row sums its incidences in (set, element id) order and adds
+// inertia and Dirichlet.
+template <typename T, bool FROM_ELEM>
+__global__ __launch_bounds__(kRowWG) void k_row_gradient(RowArgs<T> A) {
+  __shared__ T st[3][kRowWG];
   __shared__ int s_inc[kRowWG + 1];
   const int t = threadIdx.x;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int r0 = A.batch_row[b], r1 = A.batch_row[b + 1];
   const int nrows = r1 - r0;
   const int q0 = A.inc_ptr[r0];
-  const int p0 = A.row_ptr[r0];
-  for (int r = t; r <= nrows; r += kRowWG) {
-    s_blk[r] = A.row_ptr[r0 + r] - p0;
-    s_inc[r] = A.inc_ptr[r0 + r] - q0;
-  }
+  for (int r = t; r <= nrows; r += kRowWG) s_inc[r] = A.inc_ptr[r0 + r] - q0;
   __syncthreads();
   const int nq = s_inc[nrows];
-  const int np = s_blk[nrows];
   if (t < nq) {
-    const uint32_t code = A.inc_code[q0 + t];
-    if (WANT_H) sl[t] = A.inc_slots[q0 + t];
-    T out[39];
-    incidence_row<T, FROM_ELEM, WANT_H>(A, code, out);
+    T out[3];
+    incidence_grad<T, FROM_ELEM>(A, A.inc_code[q0 + t], out);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) st[v][t] = out[v];
+    for (int v = 0; v < 3; ++v) st[v][t] = out[v];
   }
   __syncthreads();
-  if (WANT_H && t < np) {
-    int r = 0;
-    while (s_blk[r + 1] <= t) ++r;
-    const int slot = t - s_blk[r];
-    T acc[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] = T(0);
-    for (int q = s_inc[r]; q < s_inc[r + 1]; ++q) {
-      const uint32_t w = sl[q];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        if (((w >> (8 * bb)) & 0xFFu) == (uint32_t)slot) {
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += st[3 + 12 * i + 3 * bb + kk][q];
-        }
-      }
-    }
-    const int row = r0 + r;
-    const int p = p0 + t;
-    const int col = A.col_idx[p];
-    if (A.xt && col == row) {
-      const T w = T(A.mass[row] * A.inv_dt2);
-      acc[0] += w;
-      acc[4] += w;
-      acc[8] += w;
-    }
-    if (A.fixed && (A.fixed[row] | A.fixed[col])) {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) acc[c] = (col == row && (c % 4) == 0) ? T(1) : T(0);
-    }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) A.vals[(int64_t)c * A.nnzb + p] = acc[c];
-  }
-  if (WANT_G && t < nrows) {
+  if (t < nrows) {
     const int row = r0 + t;
     double g0 = 0.0, g1 = 0.0, g2 = 0.0;
     for (int q = s_inc[t]; q < s_inc[t + 1]; ++q) {
@@ -650,20 +604,54 @@ __device__ __forceinline__ void incidence_row_off(const RowArgs<T>& A, uint32_t 
   }
 }
 
+// Same contribution, read from per-element gradients and (projected) Hessians.
+template <typename T>
+__device__ __forceinline__ void incidence_row_off_elem(const RowArgs<T>& A, uint32_t code, T* out) {
+  const int si = inc_set(code);
+  const int a = inc_local(code);
+  const int64_t e = inc_elem(code);
+  const SetDev& S = A.sets.s[si];
+  const Relabel R = relabel(S.conn[e], a);
+  const int D = 3 * S.k;
+  const T* ge = (const T*)A.elem_g[si] + e * D;
+  const T* He = (const T*)A.elem_H[si] + e * D * D;
+  out[0] = ge[3 * a];
+  out[1] = ge[3 * a + 1];
+  out[2] = ge[3 * a + 2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int b = 1; b < 4; ++b)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+        out[3 + 9 * i + 3 * (b - 1) + kk] =
+            b < S.k ? He[(3 * a + i) * D + 3 * R.loc[b] + kk] : T(0);
+}
+
 // Row assembly for translation-invariant element energies (all three kinds:
-// each element Hessian row sums to zero over the nodes).  Phase 1: one lane
-// per incidence evaluates the gradient and the off-diagonal blocks of its
-// Hessian row into LDS.  Phase 2: one lane per off-diagonal block sums its
-// precomputed contribution list in incidence order; one lane per row sums the
-// gradient.  Phase 3: the elastic diagonal block is minus the sum of the row's
-// off-diagonal blocks (taken in slot order); inertia and Dirichlet are
-// applied and every block is written once.
-template <typename T, bool WANT_G>
+// each element Hessian row sums to zero over the nodes, and so does its
+// nearest-PSD projection, which only removes directions orthogonal to the
+// translations).
+//  1. one lane per incidence evaluates the gradient and the off-diagonal
+//     blocks of its Hessian row into LDS;
+//  2. one lane per off-diagonal block sums its precomputed contribution list
+//     in incidence order;
+//  3. the off-diagonal blocks are published to LDS;
+//  4. one lane per (row, component): the elastic diagonal block is minus the
+//     sum of the row's off-diagonal blocks (slot order), plus inertia; and
+//     the gradient sums the row's incidences (float64, incidence order);
+//  5. Dirichlet is applied and every block is written once, with the inverse
+//     of each diagonal block when requested.
+// FROM_ELEM: step 1 reads each incidence's row from the per-element buffers
+// (projected path) instead of evaluating it.
+template <typename T, bool WANT_G, bool FROM_ELEM>
 __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   constexpr int NV = 30;
   __shared__ T st[NV][kRowWG];
-  __shared__ int s_blk[kRowWG + 1];
-  __shared__ int s_inc[kRowWG + 1];
+  // batch-relative offsets (at most kRowWG) in 16 bits keep the workgroup's
+  // LDS within 32 KiB: five workgroups (20 waves) per CU in single precision
+  __shared__ uint16_t s_blk[kRowWG + 1];
+  __shared__ uint16_t s_inc[kRowWG + 1];
   const int t = threadIdx.x;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int r0 = A.batch_row[b], r1 = A.batch_row[b + 1];
@@ -671,15 +659,18 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   const int q0 = A.inc_ptr[r0];
   const int p0 = A.row_ptr[r0];
   for (int r = t; r <= nrows; r += kRowWG) {
-    s_blk[r] = A.row_ptr[r0 + r] - p0;
-    s_inc[r] = A.inc_ptr[r0 + r] - q0;
+    s_blk[r] = (uint16_t)(A.row_ptr[r0 + r] - p0);
+    s_inc[r] = (uint16_t)(A.inc_ptr[r0 + r] - q0);
   }
   __syncthreads();
   const int nq = s_inc[nrows];
   const int np = s_blk[nrows];
   if (t < nq) {
     T out[NV];
-    incidence_row_off<T>(A, A.inc_code[q0 + t], out);
+    if (FROM_ELEM)
+      incidence_row_off_elem<T>(A, A.inc_code[q0 + t], out);
+    else
+      incidence_row_off<T>(A, A.inc_code[q0 + t], out);
 #pragma unroll
     for (int v = 0; v < NV; ++v) st[v][t] = out[v];
   }
@@ -707,49 +698,45 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
         for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += st[3 + 9 * i + 3 * bb + kk][q];
     }
   }
-  if (WANT_G && t < nrows) {
-    const int row = r0 + t;
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-    for (int q = s_inc[t]; q < s_inc[t + 1]; ++q) {
-      g0 += double(st[0][q]);
-      g1 += double(st[1][q]);
-      g2 += double(st[2][q]);
-    }
-    if (A.xt) {
-      const double w = A.mass[row] * A.inv_dt2;
-      g0 += w * (A.x[3 * row + 0] - A.xt[3 * row + 0]);
-      g1 += w * (A.x[3 * row + 1] - A.xt[3 * row + 1]);
-      g2 += w * (A.x[3 * row + 2] - A.xt[3 * row + 2]);
-    }
-    if (A.fixed && A.fixed[row]) g0 = g1 = g2 = 0.0;
-    if (!(isfinite(g0) && isfinite(g1) && isfinite(g2))) *A.nonfinite = 1;
-    A.g[3 * row + 0] = g0;
-    A.g[3 * row + 1] = g1;
-    A.g[3 * row + 2] = g2;
-  }
   __syncthreads();
-  // phase 3: publish the off-diagonal blocks, then form the diagonal ones
+  // phase 3: publish the off-diagonal blocks (over the off-diagonal rows of
+  // the incidence table; the gradients in st[0..2] stay)
   if (t < np) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) st[c][t] = acc[c];
+    for (int c = 0; c < 9; ++c) st[3 + c][t] = acc[c];
   }
   __syncthreads();
+  // phase 4: one lane per (row, component) of the elastic diagonal blocks
+  // (minus the sum of the row's off-diagonal blocks, in slot order; the
+  // diagonal slot still holds zero) and per (row, component) of the
+  // gradient (incidences in order, float64)
+  for (int j = t; j < (WANT_G ? 12 : 9) * nrows; j += kRowWG) {
+    if (j < 9 * nrows) {
+      const int rr = j / 9, c = j - 9 * rr;
+      T sum = T(0);
+      for (int sl = s_blk[rr]; sl < s_blk[rr + 1]; ++sl) sum += st[3 + c][sl];
+      T dv = -sum;
+      if (A.xt && (c % 4) == 0) dv += T(A.mass[r0 + rr] * A.inv_dt2);
+      st[3 + c][A.diag_pos[r0 + rr] - p0] = dv;
+    } else {
+      const int jj = j - 9 * nrows;
+      const int rr = jj / 3, c = jj - 3 * rr;
+      const int row = r0 + rr;
+      double g = 0.0;
+      for (int q = s_inc[rr]; q < s_inc[rr + 1]; ++q) g += double(st[c][q]);
+      if (A.xt) g += A.mass[row] * A.inv_dt2 * (A.x[3 * row + c] - A.xt[3 * row + c]);
+      if (A.fixed && A.fixed[row]) g = 0.0;
+      if (!isfinite(g)) *A.nonfinite = 1;
+      A.g[3 * row + c] = g;
+    }
+  }
+  __syncthreads();
+  // phase 5: Dirichlet, write every block once, block-Jacobi inverses
   if (t < np) {
     const int row = r0 + r;
     if (diag) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc[c] = T(0);
-      for (int s = s_blk[r]; s < s_blk[r + 1]; ++s) {
-        if (s == t) continue;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) acc[c] -= st[c][s];
-      }
-      if (A.xt) {
-        const T w = T(A.mass[row] * A.inv_dt2);
-        acc[0] += w;
-        acc[4] += w;
-        acc[8] += w;
-      }
+      for (int c = 0; c < 9; ++c) acc[c] = st[3 + c][t];
     }
     if (A.fixed && (A.fixed[row] | A.fixed[col])) {
 #pragma unroll
@@ -1196,9 +1183,9 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   A.batch_row = m.batch_row;
   A.row_ptr = m.row_ptr;
   A.col_idx = m.col_idx;
+  A.diag_pos = m.diag_pos;
   A.inc_ptr = m.inc_ptr;
   A.inc_code = m.inc_code;
-  A.inc_slots = m.inc_slots;
   A.blk_info = m.blk_info;
   A.centry = m.centry;
   A.batch_entry = m.batch_entry;
@@ -1220,17 +1207,17 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   const char* PNAME = want_H ? (want_g ? "row_assemble_gH" : "row_assemble_H") : "row_assemble_g";
   if (eb) {
     if (want_H && want_g)
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble<T, true, true, true>), grid, block, 0, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, true>), grid, block, 0, A);
     else if (want_H)
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble<T, true, false, true>), grid, block, 0, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, true>), grid, block, 0, A);
     else
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble<T, true, true, false>), grid, block, 0, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_gradient<T, true>), grid, block, 0, A);
   } else if (want_H && want_g) {
-    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true>), grid, block, 0, A);
+    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, false>), grid, block, 0, A);
   } else if (want_H) {
-    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false>), grid, block, 0, A);
+    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, false>), grid, block, 0, A);
   } else {
-    SYMX_LAUNCH(m, PNAME, (k_row_assemble<T, false, true, false>), grid, block, 0, A);
+    SYMX_LAUNCH(m, PNAME, (k_row_gradient<T, false>), grid, block, 0, A);
   }
   LAUNCH_CHECK("k_row_assemble");
   return SYMX_OK;

@@ -9,9 +9,10 @@
 //
 // The device assembles row by row.  For every node i the incidence list holds
 // its (set, element, local node a) entries in (set, element id) order, which
-// fixes the summation order of every block and gradient row.  Each incidence
-// also stores the row-local slots of the blocks it touches, in the relabelled
-// node order (a first, then the others ascending) that the row kernels use.
+// fixes the summation order of every block and gradient row.  The row-local
+// slots of the blocks an incidence touches (relabelled node order: a first,
+// then the others ascending) define each block's contribution list: the
+// (incidence, node) pairs that add to it, in incidence order.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -405,7 +406,6 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   TRY(upload(pool, stream, &t.diag_pos, diag.data(), N, &nb));
   TRY(upload(pool, stream, &t.inc_ptr, inc_ptr32.data(), N + 1, &nb));
   TRY(upload(pool, stream, &t.inc_code, code.data(), t.n_inc, &nb));
-  TRY(upload(pool, stream, &t.inc_slots, slots.data(), t.n_inc, &nb));
   TRY(upload(pool, stream, &t.batch_row, batch.data(), batch.size(), &nb));
   TRY(upload(pool, stream, &t.blk_info, blk_info.data(), blk_info.size(), &nb));
   TRY(upload(pool, stream, &t.centry, centry.data(), centry.size(), &nb));
@@ -457,7 +457,6 @@ static void attach_topology(Mesh& m, std::shared_ptr<Topology> tp) {
   m.diag_pos = t.diag_pos;
   m.inc_ptr = t.inc_ptr;
   m.inc_code = t.inc_code;
-  m.inc_slots = t.inc_slots;
   m.batch_row = t.batch_row;
   m.blk_info = t.blk_info;
   m.centry = t.centry;

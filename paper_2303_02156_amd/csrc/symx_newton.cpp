@@ -152,8 +152,7 @@ symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool
   if (project && want_H) {
     ElemBuffers eb;
     TRY(project_elements(m, x, precision, want_g, &eb));
-    TRY(launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, &eb, g_out, nullptr));
-    return dinv ? launch_diag_inverse(m, precision, dinv) : SYMX_OK;
+    return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, &eb, g_out, dinv);
   }
   if (!want_g && !want_H) return SYMX_OK;
   return launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, g_out,

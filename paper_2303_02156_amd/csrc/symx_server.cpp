@@ -78,7 +78,7 @@ size_t estimate_request_bytes(const symx_mesh_desc& d, int precision) {
   const size_t vbytes = precision == SYMX_F64 ? 8 : 4;
   size_t b = 0;
   b += pairs * (9 * vbytes + 4 + 4 + 2 * 3);   // values, col_idx, contribution info/entries
-  b += inc * (4 + 4) + elems * (16 + 2 * 8 * kPrm + 4 * 4);  // incidences, conn, params
+  b += inc * 4 + elems * (16 + 2 * 8 * kPrm + 4 * 4);  // incidence codes, conn, params
   b += N * (3 * 8 + 8 + 1 + 4 * 4);            // X, mass, fixed, row/inc pointers
   b += N * 3 * 8 * 9 + N * 9 * 8;              // Newton workspace, Dinv
   b += N * 3 * 8 * 5;                          // PCG vectors (double worst case)
