@@ -273,8 +273,8 @@ struct ElemBuffers {
   const void* g[kMaxSets];
   const void* H[kMaxSets];
 };
-// dinv (optional, recompute path only): the kernel also writes the inverses
-// of the final diagonal blocks (N x 9, precision's type).
+// dinv (optional): the kernel also writes the inverses of the final diagonal
+// blocks (N x 9, precision's type).
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* x_tilde, double dt,
                                 bool want_g, bool want_H, int precision, bool dirichlet,
                                 const ElemBuffers* from_elem, double* g_out, void* dinv);
@@ -304,7 +304,6 @@ struct PcgBuffers {
   void* p;
   void* q;
 };
-symx_status launch_diag_inverse(Mesh& m, int precision, void* Dinv);
 symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const double* b,
                             double tol2, int max_iter);
 symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0, int n_iter);

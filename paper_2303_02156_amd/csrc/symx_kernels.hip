@@ -759,23 +759,6 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
 // solver kernels
 // ---------------------------------------------------------------------------
 
-// 3x3 inverse of every diagonal block (block-Jacobi preconditioner).
-template <typename T>
-__global__ __launch_bounds__(256) void k_diag_inverse(int64_t N, int64_t nnzb,
-                                                      const int* __restrict__ diag_pos,
-                                                      const T* __restrict__ vals,
-                                                      T* __restrict__ Dinv) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
-    const int64_t p = diag_pos[i];
-    double a[9], r[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) a[c] = double(vals[c * nnzb + p]);
-    inverse3(a, r);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) Dinv[9 * i + c] = T(r[c]);
-  }
-}
-
 // [traffic-hash-begin pcg_spmv]
 // y = A x (BSR, 16 lanes per block row, lane l takes blocks l, l+16, ...)
 template <typename TA, typename TX, typename TY>
@@ -1289,19 +1272,6 @@ symx_status launch_check_finite(Mesh& m, const double* a, int64_t n) {
 // ---------------------------------------------------------------------------
 // PCG driver pieces (called from symx_newton.cpp)
 // ---------------------------------------------------------------------------
-symx_status launch_diag_inverse(Mesh& m, int precision, void* Dinv) {
-  const char* PNAME = "diag_inverse";
-  const int G = grid_for(m.N, 256);
-  if (precision == SYMX_F64)
-    SYMX_LAUNCH(m, PNAME, k_diag_inverse<double>, dim3(G), dim3(256), 0, m.N, m.nnzb,
-                       m.diag_pos, m.vals64, (double*)Dinv);
-  else
-    SYMX_LAUNCH(m, PNAME, k_diag_inverse<float>, dim3(G), dim3(256), 0, m.N, m.nnzb,
-                       m.diag_pos, m.vals32, (float*)Dinv);
-  LAUNCH_CHECK("k_diag_inverse");
-  return SYMX_OK;
-}
-
 symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const double* b,
                             double tol2, int max_iter) {
   const char* PNAME = "pcg_init";
