@@ -214,8 +214,8 @@ symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
  * min_ms separates them).  kernel_names writes the known names, comma
  * separated, into buf (host, buf_len bytes).  Names: row_assemble_gH,
  * row_assemble_H, row_assemble_g, energy, reduce, elem_eval, project_psd,
- * pcg_init, pcg_spmv, pcg_update, residual64, dot64, x_tilde, axpy64,
- * lincomb64, velocity, check_finite, accumulate. */
+ * pcg_init, pcg_spmv, pcg_update, residual64, dot64, x_tilde, lincomb64,
+ * velocity, check_finite, accumulate. */
 symx_status symx_mesh_set_profiling(symx_mesh mesh, int32_t enable);
 symx_status symx_mesh_get_kernel_time(symx_mesh mesh, const char* name, double min_ms,
                                       int64_t* launches, double* total_ms);

@@ -286,8 +286,6 @@ symx_status launch_energy(Mesh& m, const double* x, const double* x_tilde, doubl
 symx_status launch_x_tilde(Mesh& m, const double* x, const double* v, double dt, const double g[3],
                            double* xt);
 symx_status launch_dot64(Mesh& m, const double* a, const double* b, int64_t n, double* out_dev);
-symx_status launch_axpy64(Mesh& m, double* y, const double* x, const double* alpha_dev,
-                          double alpha_host, int64_t n);  // y += alpha x
 symx_status launch_lincomb64(Mesh& m, double* out, const double* a, const double* b,
                              double beta, int64_t n);     // out = a + beta b
 symx_status launch_velocity(Mesh& m, double* v, const double* x_new, const double* x_old,

@@ -1007,15 +1007,6 @@ __global__ __launch_bounds__(256) void k_x_tilde(int64_t n, const double* __rest
 }
 
 // y += alpha x (alpha from a device scalar if given)
-__global__ __launch_bounds__(256) void k_axpy64(int64_t n, double* __restrict__ y,
-                                                const double* __restrict__ x,
-                                                const double* __restrict__ alpha_dev,
-                                                double alpha_host) {
-  const double a = alpha_dev ? *alpha_dev : alpha_host;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    y[i] += a * x[i];
-}
-
 // out = a + beta b
 __global__ __launch_bounds__(256) void k_lincomb64(int64_t n, double* __restrict__ out,
                                                    const double* __restrict__ a,
@@ -1231,15 +1222,6 @@ symx_status launch_dot64(Mesh& m, const double* a, const double* b, int64_t n, d
   SYMX_LAUNCH(m, "reduce", k_reduce_checked, dim3(1), dim3(256), 0, m.partials, G, out_dev,
                      m.nonfinite);
   LAUNCH_CHECK("k_dot64");
-  return SYMX_OK;
-}
-
-symx_status launch_axpy64(Mesh& m, double* y, const double* x, const double* alpha_dev,
-                          double alpha_host, int64_t n) {
-  const char* PNAME = "axpy64";
-  SYMX_LAUNCH(m, PNAME, k_axpy64, dim3(grid_for(n, 256)), dim3(256), 0, n, y, x, alpha_dev,
-                     alpha_host);
-  LAUNCH_CHECK("k_axpy64");
   return SYMX_OK;
 }
 
