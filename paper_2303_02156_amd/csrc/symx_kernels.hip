@@ -1006,7 +1006,6 @@ __global__ __launch_bounds__(256) void k_x_tilde(int64_t n, const double* __rest
   }
 }
 
-// y += alpha x (alpha from a device scalar if given)
 // out = a + beta b
 __global__ __launch_bounds__(256) void k_lincomb64(int64_t n, double* __restrict__ out,
                                                    const double* __restrict__ a,
