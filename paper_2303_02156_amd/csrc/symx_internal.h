@@ -108,6 +108,29 @@ void dev_free(DevicePool* pool, void* p);
 symx_status pinned_alloc(DevicePool* pool, void** p, size_t bytes);
 void pinned_free(DevicePool* pool, void* p);
 
+// std::vector whose resize leaves new elements uninitialised (for large
+// arrays that are written in full right after, often by several threads).
+template <typename T>
+struct UninitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = UninitAlloc<U>;
+  };
+  UninitAlloc() = default;
+  template <typename U>
+  UninitAlloc(const UninitAlloc<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+template <typename T>
+using uvector = std::vector<T, UninitAlloc<T>>;
+
 // Everything derived from the connectivity alone: block pattern, incidence
 // lists, row batches and contribution lists (host and device copies).  Meshes
 // with the same node count, energy kinds and connectivity can share one.
@@ -126,7 +149,10 @@ struct Topology {
   int64_t N = 0, n_inc = 0, nnzb = 0;
   int n_batch = 0, max_row_blocks = 0;
   std::vector<TopoSet> sets;
-  std::vector<int32_t> h_row_ptr, h_col_idx;
+  std::vector<int32_t> h_row_ptr;
+  uvector<int32_t> h_col_idx;
+  std::vector<int64_t> h_inc_ptr;   // N+1: incidences of each node
+  uvector<uint32_t> h_inc_code;     // n_inc, in (set, element) order per node
   int* row_ptr = nullptr;           // N+1
   int* col_idx = nullptr;           // nnzb
   int* diag_pos = nullptr;          // N: index of block (i,i)

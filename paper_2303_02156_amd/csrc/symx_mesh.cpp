@@ -79,10 +79,27 @@ SetsDev Mesh::sets_dev() const {
   return d;
 }
 
+static int host_threads() {
+  return (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+}
+
+// Run f(th) for th = 0..T-1 on T host threads.
+template <typename F>
+static void parallel_for_threads(int T, F f) {
+  if (T <= 1) {
+    f(0);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int i = 1; i < T; ++i) th.emplace_back(f, i);
+  f(0);
+  for (auto& x : th) x.join();
+}
+
 // Run f(lo, hi) over [0, n) split into contiguous chunks on host threads.
 template <typename F>
 static void parallel_chunks(int64_t n, int64_t min_chunk, F f) {
-  int T = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
+  int T = host_threads();
   T = (int)std::max<int64_t>(1, std::min<int64_t>(T, n / std::max<int64_t>(min_chunk, 1)));
   if (T <= 1) {
     f((int64_t)0, n);
@@ -93,16 +110,16 @@ static void parallel_chunks(int64_t n, int64_t min_chunk, F f) {
   for (auto& x : th) x.join();
 }
 
-// Per-mesh data of one energy set: parameters, rest measures, lumped masses
-// (added to m.h_mass).  validate_conn: check node ids (skipped when the
+static int kind_nodes(int kind) {
+  return kind == SYMX_SNH_TET4 || kind == SYMX_HINGE4 ? 4 : kind == SYMX_STVK_TRI3 ? 3 : 0;
+}
+
+// Element kind, count and connectivity of one energy set.  check_nodes: node
+// ids in range and distinct within each element (skipped when the
 // connectivity equals that of a cached, already validated topology).
-static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s, bool validate_conn) {
-  s.kind = d.kind;
-  if (d.kind == SYMX_SNH_TET4 || d.kind == SYMX_HINGE4)
-    s.k = 4;
-  else if (d.kind == SYMX_STVK_TRI3)
-    s.k = 3;
-  else {
+static symx_status validate_set(const symx_energy_desc& d, int64_t N, bool check_nodes) {
+  const int k = kind_nodes(d.kind);
+  if (k == 0) {
     set_error("unknown energy kind " + std::to_string(d.kind));
     return SYMX_ERR_INVALID_ARG;
   }
@@ -110,28 +127,45 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s, boo
     set_error("invalid element count or connectivity pointer");
     return SYMX_ERR_INVALID_ARG;
   }
+  if (!check_nodes) return SYMX_OK;
+  std::atomic<int64_t> bad_range{-1}, bad_repeat{-1};
+  const int32_t* conn = d.conn;
+  parallel_chunks(d.n_elem, 16384, [&](int64_t e0, int64_t e1) {
+    for (int64_t e = e0; e < e1; ++e)
+      for (int a = 0; a < k; ++a) {
+        const int32_t v = conn[e * k + a];
+        if (v < 0 || v >= N) bad_range = e;
+        for (int b = 0; b < a; ++b)
+          if (conn[e * k + b] == v) bad_repeat = e;
+      }
+  });
+  if (bad_range >= 0) {
+    set_error("node id out of range in element " + std::to_string(bad_range.load()));
+    return SYMX_ERR_INVALID_ARG;
+  }
+  if (bad_repeat >= 0) {
+    set_error("repeated node in element " + std::to_string(bad_repeat.load()));
+    return SYMX_ERR_INVALID_ARG;
+  }
+  return SYMX_OK;
+}
+
+// Keep the smallest element id that failed a check.
+static void note_first(std::atomic<int64_t>& first, int64_t e) {
+  int64_t cur = first.load();
+  while ((cur < 0 || e < cur) && !first.compare_exchange_weak(cur, e)) {
+  }
+}
+
+// Per-mesh data of one energy set: parameters and rest measures.  elem_mass
+// receives each element's lumped mass per node (rho V / 4 per tet, rho h A / 3
+// per triangle; hinges carry none).
+static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s,
+                             std::vector<double>& elem_mass) {
+  s.kind = d.kind;
+  s.k = kind_nodes(d.kind);
   s.n_elem = d.n_elem;
   const int32_t* conn = d.conn;
-  if (validate_conn) {
-    std::atomic<int64_t> bad_range{-1}, bad_repeat{-1};
-    parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
-      for (int64_t e = e0; e < e1; ++e)
-        for (int a = 0; a < s.k; ++a) {
-          const int32_t v = conn[e * s.k + a];
-          if (v < 0 || v >= m.N) bad_range = e;
-          for (int b = 0; b < a; ++b)
-            if (conn[e * s.k + b] == v) bad_repeat = e;
-        }
-    });
-    if (bad_range >= 0) {
-      set_error("node id out of range in element " + std::to_string(bad_range.load()));
-      return SYMX_ERR_INVALID_ARG;
-    }
-    if (bad_repeat >= 0) {
-      set_error("repeated node in element " + std::to_string(bad_repeat.load()));
-      return SYMX_ERR_INVALID_ARG;
-    }
-  }
   const double* X = m.h_X.data();
   auto P = [&](int64_t e, int a) {
     int64_t n = conn[e * s.k + a];
@@ -156,57 +190,67 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s, boo
       p[2] = d.thickness;
     }
   }
-  // rest measures, masses, hinge weights
+  // rest measures, element masses, hinge weights
+  std::atomic<int64_t> bad{-1};
   if (d.kind == SYMX_SNH_TET4) {
-    std::vector<double> vol(s.n_elem);
+    elem_mass.resize(s.n_elem);
     parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
       for (int64_t e = e0; e < e1; ++e) {
         V3 x0 = P(e, 0);
         V3 d1 = sub(P(e, 1), x0), d2 = sub(P(e, 2), x0), d3 = sub(P(e, 3), x0);
-        vol[e] = std::fabs(dot(d1, cross(d2, d3))) / 6.0;
+        const double vol = std::fabs(dot(d1, cross(d2, d3))) / 6.0;
+        if (!(vol > 0.0)) note_first(bad, e);
+        elem_mass[e] = d.density * vol / 4.0;
       }
     });
-    for (int64_t e = 0; e < s.n_elem; ++e) {
-      if (!(vol[e] > 0.0)) {
-        set_error("degenerate rest tet " + std::to_string(e));
-        return SYMX_ERR_INVALID_ARG;
-      }
-      for (int a = 0; a < 4; ++a) m.h_mass[conn[e * 4 + a]] += d.density * vol[e] / 4.0;
+    if (bad >= 0) {
+      set_error("degenerate rest tet " + std::to_string(bad.load()));
+      return SYMX_ERR_INVALID_ARG;
     }
   } else if (d.kind == SYMX_STVK_TRI3) {
-    for (int64_t e = 0; e < s.n_elem; ++e) {
-      V3 x0 = P(e, 0);
-      double area = 0.5 * norm(cross(sub(P(e, 1), x0), sub(P(e, 2), x0)));
-      if (!(area > 0.0)) {
-        set_error("degenerate rest triangle " + std::to_string(e));
-        return SYMX_ERR_INVALID_ARG;
+    elem_mass.resize(s.n_elem);
+    parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
+      for (int64_t e = e0; e < e1; ++e) {
+        V3 x0 = P(e, 0);
+        const double area = 0.5 * norm(cross(sub(P(e, 1), x0), sub(P(e, 2), x0)));
+        if (!(area > 0.0)) note_first(bad, e);
+        elem_mass[e] = d.density * d.thickness * area / 3.0;
       }
-      for (int a = 0; a < 3; ++a)
-        m.h_mass[conn[e * 3 + a]] += d.density * d.thickness * area / 3.0;
+    });
+    if (bad >= 0) {
+      set_error("degenerate rest triangle " + std::to_string(bad.load()));
+      return SYMX_ERR_INVALID_ARG;
     }
   } else {  // hinge: per-element K and c (Eq. 13, Bergou et al. 2006)
+    elem_mass.clear();
     s.uniform = false;
     s.prm.assign(s.n_elem * kPrm, 0.0);
     auto cot = [](V3 u, V3 v) { return dot(u, v) / norm(cross(u, v)); };
-    for (int64_t e = 0; e < s.n_elem; ++e) {
-      V3 X0 = P(e, 0), X1 = P(e, 1), X2 = P(e, 2), X3 = P(e, 3);
-      V3 e01 = sub(X1, X0);
-      double A0 = 0.5 * norm(cross(e01, sub(X2, X0)));
-      double A1 = 0.5 * norm(cross(e01, sub(X3, X0)));
-      if (!(A0 > 0.0) || !(A1 > 0.0)) {
-        set_error("degenerate rest hinge " + std::to_string(e));
-        return SYMX_ERR_INVALID_ARG;
+    parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
+      for (int64_t e = e0; e < e1; ++e) {
+        V3 X0 = P(e, 0), X1 = P(e, 1), X2 = P(e, 2), X3 = P(e, 3);
+        V3 e01 = sub(X1, X0);
+        double A0 = 0.5 * norm(cross(e01, sub(X2, X0)));
+        double A1 = 0.5 * norm(cross(e01, sub(X3, X0)));
+        if (!(A0 > 0.0) || !(A1 > 0.0)) {
+          note_first(bad, e);
+          continue;
+        }
+        // interior angles at X0 (a_t) and X1 (b_t) of wing triangles t = 0, 1
+        double ca0 = cot(sub(X1, X0), sub(X2, X0)), cb0 = cot(sub(X0, X1), sub(X2, X1));
+        double ca1 = cot(sub(X1, X0), sub(X3, X0)), cb1 = cot(sub(X0, X1), sub(X3, X1));
+        double* p = &s.prm[e * kPrm];
+        p[0] = cb0 + cb1;
+        p[1] = ca0 + ca1;
+        p[2] = -(ca0 + cb0);
+        p[3] = -(ca1 + cb1);
+        p[4] = 3.0 / (A0 + A1);
+        p[5] = d.bend_kb;
       }
-      // interior angles at X0 (a_t) and X1 (b_t) of wing triangles t = 0, 1
-      double ca0 = cot(sub(X1, X0), sub(X2, X0)), cb0 = cot(sub(X0, X1), sub(X2, X1));
-      double ca1 = cot(sub(X1, X0), sub(X3, X0)), cb1 = cot(sub(X0, X1), sub(X3, X1));
-      double* p = &s.prm[e * kPrm];
-      p[0] = cb0 + cb1;
-      p[1] = ca0 + ca1;
-      p[2] = -(ca0 + cb0);
-      p[3] = -(ca1 + cb1);
-      p[4] = 3.0 / (A0 + A1);
-      p[5] = d.bend_kb;
+    });
+    if (bad >= 0) {
+      set_error("degenerate rest hinge " + std::to_string(bad.load()));
+      return SYMX_ERR_INVALID_ARG;
     }
   }
   return SYMX_OK;
@@ -230,71 +274,115 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
     ts.conn.assign(d.energies[si].conn, d.energies[si].conn + ts.n_elem * ts.k);
   }
   const int64_t N = t.N;
-  // node -> incidences (set, element, local node), in (set, element) order
+  // Node -> incidences (set, element, local node), in (set, element) order:
+  // a counting sort over the concatenated element list, split into
+  // contiguous ranges, one per host thread.  Thread ranges are taken in
+  // order for every node, so each node's list keeps (set, element) order.
+  int64_t n_all = 0;
+  std::vector<int64_t> set_first(t.sets.size() + 1, 0);
+  for (size_t si = 0; si < t.sets.size(); ++si) set_first[si + 1] = set_first[si] + t.sets[si].n_elem;
+  n_all = set_first.back();
+  const int T = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n_all / 16384));
+  std::vector<uvector<int32_t>> local(T);
+  auto for_range = [&](int th, auto&& f) {  // f(set, element) over thread th's range
+    const int64_t g0 = n_all * th / T, g1 = n_all * (th + 1) / T;
+    for (size_t si = 0; si < t.sets.size(); ++si) {
+      const int64_t lo = std::max(g0, set_first[si]), hi = std::min(g1, set_first[si + 1]);
+      for (int64_t g = lo; g < hi; ++g) f((int)si, g - set_first[si]);
+    }
+  };
+  parallel_for_threads(T, [&](int th) {
+    local[th].assign(N, 0);
+    for_range(th, [&](int si, int64_t e) {
+      const TopoSet& s = t.sets[si];
+      for (int a = 0; a < s.k; ++a) local[th][s.conn[e * s.k + a]]++;
+    });
+  });
   std::vector<int64_t> cnt(N + 1, 0);
-  for (const TopoSet& s : t.sets)
-    for (int32_t v : s.conn) cnt[v + 1]++;
+  std::atomic<int64_t> crowded{-1};
+  parallel_chunks(N, 16384, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int32_t c = 0;
+      for (int th = 0; th < T; ++th) {
+        const int32_t n = local[th][i];
+        local[th][i] = c;  // becomes the thread's offset within node i's list
+        c += n;
+      }
+      cnt[i + 1] = c;
+      if (c > kRowWG) crowded = i;
+    }
+  });
+  if (crowded >= 0) {
+    set_error("node " + std::to_string(crowded.load()) + " belongs to more than 256 elements");
+    return SYMX_ERR_INVALID_ARG;
+  }
   for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
   t.n_inc = cnt[N];
   if (t.n_inc >= (int64_t(1) << 31)) {
     set_error("too many incidences");
     return SYMX_ERR_INVALID_ARG;
   }
-  for (int64_t i = 0; i < N; ++i)
-    if (cnt[i + 1] - cnt[i] > kRowWG) {
-      set_error("node " + std::to_string(i) + " belongs to more than 256 elements");
-      return SYMX_ERR_INVALID_ARG;
-    }
-  std::vector<uint32_t> code(t.n_inc);
-  {
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int si = 0; si < (int)t.sets.size(); ++si) {
+  uvector<uint32_t> code(t.n_inc);
+  parallel_for_threads(T, [&](int th) {
+    for_range(th, [&](int si, int64_t e) {
       const TopoSet& s = t.sets[si];
-      for (int64_t e = 0; e < s.n_elem; ++e)
-        for (int a = 0; a < s.k; ++a) code[fill[s.conn[e * s.k + a]]++] = inc_make(si, a, e);
-    }
-  }
+      for (int a = 0; a < s.k; ++a) {
+        const int32_t v = s.conn[e * s.k + a];
+        code[cnt[v] + local[th][v]++] = inc_make(si, a, e);
+      }
+    });
+  });
+  local.clear();
+  t.h_inc_ptr = cnt;
   // Rows in parallel chunks: sorted unique neighbour list of each node, and
   // for each incidence the row-local slots of its blocks in the relabelled
-  // node order (a first, then the others ascending).
-  std::vector<uint32_t> slots(t.n_inc);
+  // node order (a first, then the others ascending).  Each thread marks the
+  // nodes already in the current row (mark[j] == row) and maps node -> slot
+  // (pos[j]), so a row costs O(incidences) plus a sort of its few columns.
+  uvector<uint32_t> slots(t.n_inc);
   std::vector<int32_t> row_len(N);
   const int64_t n_chunks = std::min<int64_t>(64, std::max<int64_t>(1, N / 2048));
   std::vector<std::vector<int32_t>> chunk_cols(n_chunks);
   std::vector<int> chunk_bad(n_chunks, 0);
   parallel_chunks(n_chunks, 1, [&](int64_t c0, int64_t c1) {
     std::vector<int32_t> nb;
+    uvector<int32_t> mark(N), pos(N);
+    for (int64_t i = 0; i < N; ++i) mark[i] = -1;
     for (int64_t c = c0; c < c1; ++c) {
       const int64_t r0 = N * c / n_chunks, r1 = N * (c + 1) / n_chunks;
       std::vector<int32_t>& cols = chunk_cols[c];
       for (int64_t i = r0; i < r1; ++i) {
         nb.clear();
         nb.push_back((int32_t)i);
+        mark[i] = (int32_t)i;
         for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
           const TopoSet& s = t.sets[inc_set(code[q])];
           const int64_t e = inc_elem(code[q]);
-          for (int b = 0; b < s.k; ++b) nb.push_back(s.conn[e * s.k + b]);
+          for (int b = 0; b < s.k; ++b) {
+            const int32_t j = s.conn[e * s.k + b];
+            if (mark[j] != (int32_t)i) {
+              mark[j] = (int32_t)i;
+              nb.push_back(j);
+            }
+          }
         }
         std::sort(nb.begin(), nb.end());
-        nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
         if ((int)nb.size() > kMaxRowBlocks) chunk_bad[c] = 1;
         row_len[i] = (int32_t)nb.size();
+        for (size_t sl = 0; sl < nb.size(); ++sl) pos[nb[sl]] = (int32_t)sl;
         for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
           const int si = inc_set(code[q]);
           const TopoSet& s = t.sets[si];
           const int a = inc_local(code[q]);
           const int64_t e = inc_elem(code[q]);
           int order[4] = {a, -1, -1, -1};
-          for (int b = 0, t = 1; b < s.k; ++b)
-            if (b != a) order[t++] = b;
+          for (int b = 0, o = 1; b < s.k; ++b)
+            if (b != a) order[o++] = b;
           uint32_t w = 0;
           for (int bp = 0; bp < 4; ++bp) {
-            uint32_t sl = kNoSlot;
-            if (bp < s.k) {
-              const int32_t j = s.conn[e * s.k + order[bp]];
-              sl = (uint32_t)(std::lower_bound(nb.begin(), nb.end(), j) - nb.begin());
-            }
-            w |= sl << (8 * bp);
+            const uint32_t sl =
+                bp < s.k ? (uint32_t)pos[s.conn[e * s.k + order[bp]]] : kNoSlot;
+            w |= (sl & 0xFFu) << (8 * bp);
           }
           slots[q] = w;
         }
@@ -353,8 +441,8 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
     for (int64_t q = cnt[batch[b]]; q < cnt[batch[b + 1]]; ++q) ne += t.sets[inc_set(code[q])].k - 1;
     batch_entry[b + 1] = batch_entry[b] + (int32_t)ne;
   }
-  std::vector<uint32_t> blk_info(t.nnzb, 0);
-  std::vector<uint16_t> centry(batch_entry[t.n_batch]);
+  uvector<uint32_t> blk_info(t.nnzb);
+  uvector<uint16_t> centry(batch_entry[t.n_batch]);
   std::vector<int> batch_bad(t.n_batch, 0);
   parallel_chunks(t.n_batch, 256, [&](int64_t b0, int64_t b1) {
     std::vector<int32_t> cnt_blk, fillp;
@@ -406,17 +494,20 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   TRY(upload(pool, stream, &t.diag_pos, diag.data(), N, &nb));
   TRY(upload(pool, stream, &t.inc_ptr, inc_ptr32.data(), N + 1, &nb));
   TRY(upload(pool, stream, &t.inc_code, code.data(), t.n_inc, &nb));
+  t.h_inc_code = std::move(code);
   TRY(upload(pool, stream, &t.batch_row, batch.data(), batch.size(), &nb));
   TRY(upload(pool, stream, &t.blk_info, blk_info.data(), blk_info.size(), &nb));
   TRY(upload(pool, stream, &t.centry, centry.data(), centry.size(), &nb));
   TRY(upload(pool, stream, &t.batch_entry, batch_entry.data(), batch_entry.size(), &nb));
   for (TopoSet& ts : t.sets) {
-    std::vector<int4> c4(std::max<int64_t>(ts.n_elem, 1));
-    for (int64_t e = 0; e < ts.n_elem; ++e) {
-      int v[4] = {-1, -1, -1, -1};
-      for (int a = 0; a < ts.k; ++a) v[a] = ts.conn[e * ts.k + a];
-      c4[e] = make_int4(v[0], v[1], v[2], v[3]);
-    }
+    uvector<int4> c4(std::max<int64_t>(ts.n_elem, 1));
+    parallel_chunks(ts.n_elem, 65536, [&](int64_t e0, int64_t e1) {
+      for (int64_t e = e0; e < e1; ++e) {
+        int v[4] = {-1, -1, -1, -1};
+        for (int a = 0; a < ts.k; ++a) v[a] = ts.conn[e * ts.k + a];
+        c4[e] = make_int4(v[0], v[1], v[2], v[3]);
+      }
+    });
     TRY(upload(pool, stream, &ts.d_conn, c4.data(), c4.size(), &nb));
   }
   *out = std::move(tp);
@@ -524,22 +615,33 @@ symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool,
   m->h_fixed.assign(m->N, 0);
   if (d->fixed)
     for (int64_t i = 0; i < m->N; ++i) m->h_fixed[i] = d->fixed[i] ? 1 : 0;
+  for (int s = 0; s < d->n_energies; ++s) TRY(validate_set(d->energies[s], m->N, false));
   std::shared_ptr<Topology> topo;
-  uint64_t hash = 0;
-  if (cache) {
-    hash = topology_hash(*d);
-    topo = cache->find(*d, hash);
-  }
-  m->h_mass.assign(m->N, 0.0);
-  m->sets.resize(d->n_energies);
-  for (int s = 0; s < d->n_energies; ++s)
-    TRY(build_set(*m, d->energies[s], m->sets[s], /*validate_conn=*/!topo));
-  m->total_mass = 0.0;
-  for (double v : m->h_mass) m->total_mass += v;
+  if (cache) topo = cache->find(*d, topology_hash(*d));
   if (!topo) {
+    for (int s = 0; s < d->n_energies; ++s) TRY(validate_set(d->energies[s], m->N, true));
     TRY(build_topology(*d, pool, m->stream, &topo));
     if (cache) cache->insert(topo);
   }
+  m->sets.resize(d->n_energies);
+  std::vector<std::vector<double>> elem_mass(d->n_energies);
+  for (int s = 0; s < d->n_energies; ++s)
+    TRY(build_set(*m, d->energies[s], m->sets[s], elem_mass[s]));
+  // lumped masses: each node sums its incidences in (set, element) order
+  const Topology& t = *topo;
+  m->h_mass.assign(m->N, 0.0);
+  parallel_chunks(m->N, 16384, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      double mi = 0.0;
+      for (int64_t q = t.h_inc_ptr[i]; q < t.h_inc_ptr[i + 1]; ++q) {
+        const std::vector<double>& em = elem_mass[inc_set(t.h_inc_code[q])];
+        if (!em.empty()) mi += em[inc_elem(t.h_inc_code[q])];
+      }
+      m->h_mass[i] = mi;
+    }
+  });
+  m->total_mass = 0.0;
+  for (double v : m->h_mass) m->total_mass += v;
   attach_topology(*m, std::move(topo));
   TRY(upload_instance(*m));
   return SYMX_OK;
