@@ -76,6 +76,49 @@ def measured_traffic(kernel):
     return rec["bytes_per_launch"]
 
 
+GEN_SOURCES = ("expr.h", "expr.cpp", "symx_gen.cpp")
+
+
+def row_kernel_hash():
+    """Hash of the row-assembly kernel source and of the generator that emits
+    its element functions (the committed VALU record is tied to both)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2303_02156_amd", "csrc")
+    src = open(os.path.join(csrc, "symx_kernels.hip")).read()
+    a = src.find("// [valu-hash-begin row_assemble]")
+    e = src.find("// [valu-hash-end row_assemble]")
+    if a < 0 or e < 0:
+        return None
+    h = hashlib.sha256(src[a:e].encode())
+    for f in GEN_SOURCES:
+        h.update(open(os.path.join(csrc, "gen", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_valu():
+    """Wave-level VALU instructions per FP32 g+H row-assembly launch from the
+    committed rocprofv3 counter run, or None when the source changed since."""
+    path = os.path.join(ROOT, "profiles", "row_assemble_c2_valu.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != row_kernel_hash():
+        return None
+    return rec["sq_insts_valu_per_launch"]
+
+
+def census_ops(name):
+    """Operation count of a generated element function (the generator's census)."""
+    path = os.path.join(ROOT, "paper_2303_02156_amd", "csrc", "generated", "symx_generated_meta.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = line.split()
+        if f and f[0] == name:
+            return int(f[-1])
+    return None
+
+
 def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
     """C5: Poisson arrivals of time-step requests; p50/p99 latency, throughput."""
     import numpy as np
@@ -426,11 +469,37 @@ def main():
             asm_ms[name] = m
             melem[name] = n_elem / (m * 1e-3) / 1e6
             log(f"eval+assembly {name}: {m:.3f} ms -> {melem[name]:.2f} Melem/s")
-    # per-kernel split of one FP32 assembly
+    # per-kernel split of FP32 assemblies (device time per launch)
     mesh.profile(True)
-    mesh.assemble(x0, xt, dt, flags, symx.SYMX_F32, grad_out=g)
+    n_prof = 5
+    for _ in range(n_prof):
+        mesh.assemble(x0, xt, dt, flags, symx.SYMX_F32, grad_out=g)
     asm_kernels = mesh.kernel_times()
     mesh.profile(False)
+    roofline_asm = None
+    kt_gh = asm_kernels.get("row_assemble_gH")
+    kt_e = asm_kernels.get("energy")
+    ops_elem = census_ops("snh_tet4_EgH")
+    if kt_gh and kt_gh[0] and kt_e and ops_elem:
+        t_gh = kt_gh[1] / kt_gh[0]
+        t_e = kt_e[1] / n_prof
+        achieved = ops_elem * n_elem / ((t_gh + t_e) * 1e-3) / 1e12
+        peak = 78.6
+        valu = measured_valu()
+        executed = [census_ops("snh_tet4_row0_gHoff"), census_ops("snh_tet4_s_E")]
+        roofline_asm = {
+            "kernel": "row_assemble_gH + energy (FP32 E, g, H)", "bound": "alu",
+            "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "peak_note": "FP32 vector without packed math (packed FP32 is disabled): "
+                         "256 CU x 64 lanes x 2.4 GHz x 2 (FMA)",
+            "algorithmic_ops_per_elem": ops_elem,
+            "executed_ops_per_elem": (4 * executed[0] + executed[1]) if all(executed) else None,
+            "avg_ms": round(t_gh + t_e, 5),
+            "valu_issue_frac": (round(valu / (t_gh * 1e-3 * 256 * 2.4e9), 3)
+                                if valu else None),
+        }
+        log(f"assembly ALU roofline: {roofline_asm}")
 
     # ---- Newton time steps -----------------------------------------------------
     def run_steps(precision, K, W, profile):
@@ -567,6 +636,7 @@ def main():
         "mesh_setup_s": round(setup_s, 3),
         "kernels_f32_refined_steps": kernels,
         "roofline": roofline,
+        "roofline_assembly": roofline_asm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

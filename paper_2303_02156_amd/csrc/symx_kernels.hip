@@ -546,6 +546,7 @@ __global__ __launch_bounds__(kRowWG) void k_row_gradient(RowArgs<T> A) {
   }
 }
 
+// [valu-hash-begin row_assemble]
 // Inverse of a 3x3 block in float64 (identity for a singular block); the
 // block-Jacobi preconditioner of the PCG.
 __device__ __forceinline__ void inverse3(const double a[9], double r[9]) {
@@ -754,6 +755,8 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
     }
   }
 }
+
+// [valu-hash-end row_assemble]
 
 // ---------------------------------------------------------------------------
 // solver kernels
