@@ -24,6 +24,7 @@ constexpr int kRedWG = 256;         // reduction workgroup size
 constexpr int kPrm = 8;             // parameter slots per element (doubles)
 constexpr uint32_t kNoSlot = 0xFFu;
 constexpr int kPcgHistory = 64;    // remembered PCG iteration counts
+constexpr int kIncRec = 32;        // values per incidence record (projected path)
 
 // Parameter layout per element (kPrm doubles):
 //   SNH tet4:  mu, lambda (linear-elasticity Lame pair)
@@ -252,10 +253,10 @@ struct Mesh {
   const int* batch_entry = nullptr;
   float* vals32 = nullptr;          // 9*nnzb, component-major
   double* vals64 = nullptr;
-  // per-element scratch for the projected path (largest set)
-  void* elem_g = nullptr;
-  void* elem_H = nullptr;
-  size_t elem_bytes = 0;
+  // projected path: incidence positions (n_inc) and records (n_inc x 32)
+  int* inc_pos = nullptr;
+  void* inc_rows = nullptr;
+  size_t inc_rows_bytes = 0;
   // reductions
   double* partials = nullptr;       // kMaxPartials
   double* scalars = nullptr;        // small device scalars
@@ -293,17 +294,18 @@ symx_status launch_elem_eval(Mesh& m, int set, const double* x, int want, int pr
 // In-place nearest-PSD projection of n element Hessians (dim x dim each).
 symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim);
 // Row assembly: gradient (FP64, may be null) and/or Hessian (precision).
-// from_elem: read projected per-element buffers of each set instead of
-// recomputing (elem_g / elem_H pointers per set).
-struct ElemBuffers {
-  const void* g[kMaxSets];
-  const void* H[kMaxSets];
-};
+// inc_rows: projected path, read each incidence's row from the incidence
+// records (kIncRec values each) instead of evaluating it.
 // dinv (optional): the kernel also writes the inverses of the final diagonal
 // blocks (N x 9, precision's type).
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* x_tilde, double dt,
                                 bool want_g, bool want_H, int precision, bool dirichlet,
-                                const ElemBuffers* from_elem, double* g_out, void* dinv);
+                                const void* inc_rows, double* g_out, void* dinv);
+// Incidence positions (inverse of the incidence codes), n_inc ints.
+symx_status launch_incidence_positions(Mesh& m, int* inc_pos);
+// Projected element rows into the incidence records (n_inc x 32, precision).
+symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precision,
+                                            const int* inc_pos, void* rows);
 // Total energy (float64 sum of per-element energies in `precision`).
 symx_status launch_energy(Mesh& m, const double* x, const double* x_tilde, double dt,
                           int precision, double* E_dev);

@@ -346,6 +346,91 @@ __device__ __forceinline__ void jacobi_sweep_from(T* a, VM v) {
   }
 }
 
+// M = Q^T H Q, upper triangle, reduced index 3i + c (basis vector i, coord
+// c), of a K-node element Hessian given entry by entry by h(p, q).
+template <typename T, int K, typename HF>
+__device__ __forceinline__ void reduce_hessian(HF h, T* a) {
+  constexpr int R = 3 * (K - 1);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      T hb[K][K];  // node block (a, b) of H for coordinates (c, d)
+#pragma unroll
+      for (int na = 0; na < K; ++na)
+#pragma unroll
+        for (int nb = 0; nb < K; ++nb) hb[na][nb] = h(3 * na + c, 3 * nb + d);
+#pragma unroll
+      for (int i = 0; i < K - 1; ++i)
+#pragma unroll
+        for (int j = 0; j < K - 1; ++j) {
+          if (3 * i + c > 3 * j + d) continue;
+          T m = T(0);
+#pragma unroll
+          for (int na = 0; na <= i + 1; ++na)
+#pragma unroll
+            for (int nb = 0; nb <= j + 1; ++nb)
+              m += helmert<T>(i, na) * helmert<T>(j, nb) * hb[na][nb];
+          a[up_idx<R>(3 * i + c, 3 * j + d)] = m;
+        }
+    }
+}
+
+// Cyclic Jacobi on the packed upper triangle a (R x R) with V accumulated;
+// stops when the off-diagonal norm is below tol times the matrix norm.
+// Returns whether an eigenvalue (diagonal of a) is negative.
+template <typename T, int R, typename VM>
+__device__ __forceinline__ bool jacobi_eigen(T* a, VM v, int max_sweeps, T tol) {
+#pragma unroll
+  for (int k = 0; k < R * R; ++k) v[k] = (k % (R + 1) == 0) ? T(1) : T(0);
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    T off = T(0), dia = T(0);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      dia += a[up_idx<R>(i, i)] * a[up_idx<R>(i, i)];
+#pragma unroll
+      for (int j = i + 1; j < R; ++j) off += a[up_idx<R>(i, j)] * a[up_idx<R>(i, j)];
+    }
+    if (off <= tol * tol * (dia + T(2) * off)) break;
+    jacobi_sweep_from<T, R, 0, 1>(a, v);
+  }
+  bool neg = false;
+#pragma unroll
+  for (int k = 0; k < R; ++k) neg |= a[up_idx<R>(k, k)] < T(0);
+  return neg;
+}
+
+// u = Q w_k, the full-space eigenvector of eigenpair k of M.
+template <typename T, int K, int KV, typename VM>
+__device__ __forceinline__ void lift_eigenvector(VM v, T* u) {
+  constexpr int R = 3 * (K - 1);
+#pragma unroll
+  for (int na = 0; na < K; ++na)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T s = T(0);
+#pragma unroll
+      for (int i = 0; i < K - 1; ++i) s += helmert<T>(i, na) * v[(3 * i + c) * R + KV];
+      u[3 * na + c] = s;
+    }
+}
+
+// For each negative eigenvalue lambda_k (k = KV ... R-1): f(lambda_k, u_k).
+template <typename T, int K, int KV, typename VM, typename F>
+__device__ __forceinline__ void for_negative_pairs(const T* a, VM v, F f) {
+  constexpr int R = 3 * (K - 1);
+  if constexpr (KV < R) {
+    const T lam = a[up_idx<R>(KV, KV)];
+    if (lam < T(0)) {
+      T u[3 * K];
+      lift_eigenvector<T, K, KV>(v, u);
+      f(lam, u);
+    }
+    for_negative_pairs<T, K, KV + 1>(a, v, f);
+  }
+}
+
+// In-place projection of n element Hessians (D x D, row-major, one per lane).
 // K nodes per element: H is D x D with D = 3K, M is R x R with R = 3K - 3.
 // vstore: null keeps V in registers, else the workgroup's LDS array of R*R*64.
 template <typename T, int K, int VSTRIDE>
@@ -357,70 +442,129 @@ __device__ __forceinline__ void project_psd_lane(T* __restrict__ H, int64_t n, i
   for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 64) {
     T* He = H + e * D * D;
     T a[NU];
-    // M = Q^T H Q, upper triangle; reduced index 3i + c (basis vector i, coord c)
-#pragma unroll
-    for (int k = 0; k < NU; ++k) a[k] = T(0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        T hb[K][K];  // node block (a, b) of H for coordinates (c, d)
-#pragma unroll
-        for (int na = 0; na < K; ++na)
-#pragma unroll
-          for (int nb = 0; nb < K; ++nb) hb[na][nb] = He[(3 * na + c) * D + 3 * nb + d];
-#pragma unroll
-        for (int i = 0; i < K - 1; ++i)
-#pragma unroll
-          for (int j = 0; j < K - 1; ++j) {
-            if (3 * i + c > 3 * j + d) continue;
-            T m = T(0);
-#pragma unroll
-            for (int na = 0; na <= i + 1; ++na)
-#pragma unroll
-              for (int nb = 0; nb <= j + 1; ++nb)
-                m += helmert<T>(i, na) * helmert<T>(j, nb) * hb[na][nb];
-            a[up_idx<R>(3 * i + c, 3 * j + d)] = m;
-          }
-      }
-#pragma unroll
-    for (int k = 0; k < R * R; ++k) v[k] = (k % (R + 1) == 0) ? T(1) : T(0);
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-      T off = T(0), dia = T(0);
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        dia += a[up_idx<R>(i, i)] * a[up_idx<R>(i, i)];
-#pragma unroll
-        for (int j = i + 1; j < R; ++j) off += a[up_idx<R>(i, j)] * a[up_idx<R>(i, j)];
-      }
-      if (off <= tol * tol * (dia + T(2) * off)) break;
-      jacobi_sweep_from<T, R, 0, 1>(a, v);
-    }
-    bool neg = false;
-#pragma unroll
-    for (int k = 0; k < R; ++k) neg |= a[up_idx<R>(k, k)] < T(0);
-    if (!neg) continue;  // already PSD: H stays as it is
-    // H <- H - sum_k min(lambda_k, 0) u_k u_k^T with u_k = Q w_k, done one
-    // eigenpair at a time (lanes skip the non-negative ones)
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const T lam = a[up_idx<R>(k, k)];
-      if (!(lam < T(0))) continue;
-      T u[D];
-#pragma unroll
-      for (int na = 0; na < K; ++na)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          T s = T(0);
-#pragma unroll
-          for (int i = 0; i < K - 1; ++i) s += helmert<T>(i, na) * v[(3 * i + c) * R + k];
-          u[3 * na + c] = s;
-        }
+    reduce_hessian<T, K>([&](int p, int q) { return He[p * D + q]; }, a);
+    if (!jacobi_eigen<T, R>(a, v, max_sweeps, tol)) continue;  // PSD: H stays as it is
+    // H <- H - sum_k min(lambda_k, 0) u_k u_k^T, one eigenpair at a time
+    for_negative_pairs<T, K, 0>(a, v, [&](T lam, const T* u) {
 #pragma unroll
       for (int p = 0; p < D; ++p)
 #pragma unroll
         for (int q = 0; q < D; ++q) He[p * D + q] -= lam * u[p] * u[q];
+    });
+  }
+}
+
+// Projected path of the global assembly: one lane per element evaluates E's
+// gradient and Hessian, writes each node's row (gradient and the three
+// off-diagonal blocks, in the relabelled order that the row kernel uses) to
+// that incidence's record of the incidence-ordered buffer (kIncRec values per
+// record, so an element's records are whole cache lines and the row kernel
+// reads them contiguously), then projects the Hessian as above and subtracts
+// the negative eigenpairs from the records it wrote.  The diagonal blocks are
+// not stored: the row kernel forms them from the off-diagonal ones.
+
+template <typename T, int KIND, int VSTRIDE>
+__device__ __forceinline__ void elem_rows_projected(SetDev S, const double* __restrict__ x,
+                                                    const double* __restrict__ X,
+                                                    const int* __restrict__ inc_pos,
+                                                    T* __restrict__ rows, int max_sweeps, T tol,
+                                                    T* vstore) {
+  constexpr int K = KIND == SYMX_STVK_TRI3 ? 3 : 4;
+  constexpr int D = 3 * K, R = 3 * (K - 1), NU = R * (R + 1) / 2;
+  T vreg[VSTRIDE == 1 ? R * R : 1];
+  const LaneMat<T, VSTRIDE> v{VSTRIDE == 1 ? vreg : vstore + threadIdx.x};
+  for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < S.n_elem;
+       e += (int64_t)gridDim.x * 64) {
+    const Relabel R0 = identity_order(S.conn[e]);
+    T in[26];
+    T out[1 + D + D * D];
+    if (KIND == SYMX_SNH_TET4) {
+      fill_solid<T, 4>(S, e, R0, x, X, in);
+      snh_tet4_s_EgH<T>(in, out);
+    } else if (KIND == SYMX_STVK_TRI3) {
+      fill_solid<T, 3>(S, e, R0, x, X, in);
+      stvk_tri3_s_EgH<T>(in, out);
+    } else {
+      fill_hinge<T>(S, e, R0, x, in);
+      hinge4_s_EgH<T>(in, out);
     }
+    const T* g = out + 1;
+    const T* h = out + 1 + D;
+    // record of incidence (e, a): g_a, then H(a_i, b_k) for b = the other
+    // nodes in ascending local order (zeros for a triangle's missing node)
+    T* rec[K];
+#pragma unroll
+    for (int na = 0; na < K; ++na) {
+      rec[na] = rows + (int64_t)inc_pos[e * K + na] * kIncRec;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rec[na][i] = g[3 * na + i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int bp = 1; bp < 4; ++bp) {
+          const int nb = bp <= na ? bp - 1 : bp;  // bp-th node other than na
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk)
+            rec[na][3 + 9 * i + 3 * (bp - 1) + kk] =
+                nb < K ? h[(3 * na + i) * D + 3 * nb + kk] : T(0);
+        }
+    }
+    // A hinge Hessian k_b c (K K^T) (x) I_3 (c > 0) is positive semi-definite
+    // by construction: the projection leaves it as it is.
+    if (KIND == SYMX_HINGE4) continue;
+    T a[NU];
+    reduce_hessian<T, K>([&](int p, int q) { return h[p * D + q]; }, a);
+    if (!jacobi_eigen<T, R>(a, v, max_sweeps, tol)) continue;
+    for_negative_pairs<T, K, 0>(a, v, [&](T lam, const T* u) {
+#pragma unroll
+      for (int na = 0; na < K; ++na)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int bp = 1; bp < K; ++bp) {
+            const int nb = bp <= na ? bp - 1 : bp;
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk)
+              rec[na][3 + 9 * i + 3 * (bp - 1) + kk] -= lam * u[3 * na + i] * u[3 * nb + kk];
+          }
+    });
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(64, 2) void k_elem_rows_projected32(SetDev S, const double* x,
+                                                                 const double* X,
+                                                                 const int* inc_pos, float* rows,
+                                                                 int max_sweeps, float tol) {
+  elem_rows_projected<float, KIND, 1>(S, x, X, inc_pos, rows, max_sweeps, tol, nullptr);
+}
+template <int KIND>
+__global__ __launch_bounds__(64) void k_elem_rows_projected64(SetDev S, const double* x,
+                                                              const double* X,
+                                                              const int* inc_pos, double* rows,
+                                                              int max_sweeps, double tol) {
+  if constexpr (KIND == SYMX_STVK_TRI3) {
+    elem_rows_projected<double, KIND, 1>(S, x, X, inc_pos, rows, max_sweeps, tol, nullptr);
+  } else {
+    __shared__ double vs[9 * 9 * 64];
+    elem_rows_projected<double, KIND, 64>(S, x, X, inc_pos, rows, max_sweeps, tol, vs);
+  }
+}
+
+// inc_pos[set_first[s] + e k + a] = position of incidence (s, e, a) in the
+// incidence lists (inverse of the incidence codes).
+struct SetOffsets {
+  int64_t first[kMaxSets];
+};
+__global__ __launch_bounds__(256) void k_incidence_positions(int64_t n_inc,
+                                                             const uint32_t* __restrict__ code,
+                                                             SetsDev sets, SetOffsets off,
+                                                             int* __restrict__ inc_pos) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n_inc;
+       q += (int64_t)gridDim.x * 256) {
+    const uint32_t c = code[q];
+    const int si = inc_set(c);
+    inc_pos[off.first[si] + (int64_t)inc_elem(c) * sets.s[si].k + inc_local(c)] = (int)q;
   }
 }
 
@@ -469,25 +613,17 @@ struct RowArgs {
   T* vals;               // component-major 9 x nnzb
   T* dinv;               // N x 9 inverses of the diagonal blocks, or null
   double* g;             // N x 3
-  const void* elem_g[kMaxSets];  // projected path: per-element gradients
-  const void* elem_H[kMaxSets];  // and Hessians
+  const T* inc_rows;     // projected path: incidence records (kIncRec per incidence)
   int* nonfinite;
 };
 
 // Gradient row of one incidence (element e seen from its local node a).
-template <typename T, bool FROM_ELEM>
+template <typename T>
 __device__ __forceinline__ void incidence_grad(const RowArgs<T>& A, uint32_t code, T* out) {
   const int si = inc_set(code);
   const int a = inc_local(code);
   const int64_t e = inc_elem(code);
   const SetDev& S = A.sets.s[si];
-  if (FROM_ELEM) {
-    const T* ge = (const T*)A.elem_g[si] + e * 3 * S.k;
-    out[0] = ge[3 * a];
-    out[1] = ge[3 * a + 1];
-    out[2] = ge[3 * a + 2];
-    return;
-  }
   const Relabel R = relabel(S.conn[e], a);
   T in[26];
   if (S.kind == SYMX_SNH_TET4) {
@@ -505,7 +641,7 @@ __device__ __forceinline__ void incidence_grad(const RowArgs<T>& A, uint32_t cod
 // Gradient-only row assembly: one lane per incidence of the batch's rows, then
 // one lane per row sums its incidences in (set, element id) order and adds
 // inertia and Dirichlet.
-template <typename T, bool FROM_ELEM>
+template <typename T>
 __global__ __launch_bounds__(kRowWG) void k_row_gradient(RowArgs<T> A) {
   __shared__ T st[3][kRowWG];
   __shared__ int s_inc[kRowWG + 1];
@@ -519,7 +655,7 @@ __global__ __launch_bounds__(kRowWG) void k_row_gradient(RowArgs<T> A) {
   const int nq = s_inc[nrows];
   if (t < nq) {
     T out[3];
-    incidence_grad<T, FROM_ELEM>(A, A.inc_code[q0 + t], out);
+    incidence_grad<T>(A, A.inc_code[q0 + t], out);
 #pragma unroll
     for (int v = 0; v < 3; ++v) st[v][t] = out[v];
   }
@@ -605,30 +741,6 @@ __device__ __forceinline__ void incidence_row_off(const RowArgs<T>& A, uint32_t 
   }
 }
 
-// Same contribution, read from per-element gradients and (projected) Hessians.
-template <typename T>
-__device__ __forceinline__ void incidence_row_off_elem(const RowArgs<T>& A, uint32_t code, T* out) {
-  const int si = inc_set(code);
-  const int a = inc_local(code);
-  const int64_t e = inc_elem(code);
-  const SetDev& S = A.sets.s[si];
-  const Relabel R = relabel(S.conn[e], a);
-  const int D = 3 * S.k;
-  const T* ge = (const T*)A.elem_g[si] + e * D;
-  const T* He = (const T*)A.elem_H[si] + e * D * D;
-  out[0] = ge[3 * a];
-  out[1] = ge[3 * a + 1];
-  out[2] = ge[3 * a + 2];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int b = 1; b < 4; ++b)
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk)
-        out[3 + 9 * i + 3 * (b - 1) + kk] =
-            b < S.k ? He[(3 * a + i) * D + 3 * R.loc[b] + kk] : T(0);
-}
-
 // Row assembly for translation-invariant element energies (all three kinds:
 // each element Hessian row sums to zero over the nodes, and so does its
 // nearest-PSD projection, which only removes directions orthogonal to the
@@ -643,9 +755,9 @@ __device__ __forceinline__ void incidence_row_off_elem(const RowArgs<T>& A, uint
 //     the gradient sums the row's incidences (float64, incidence order);
 //  5. Dirichlet is applied and every block is written once, with the inverse
 //     of each diagonal block when requested.
-// FROM_ELEM: step 1 reads each incidence's row from the per-element buffers
-// (projected path) instead of evaluating it.
-template <typename T, bool WANT_G, bool FROM_ELEM>
+// FROM_REC: step 1 reads each incidence's row from its record in the
+// incidence-ordered buffer (projected path) instead of evaluating it.
+template <typename T, bool WANT_G, bool FROM_REC>
 __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   constexpr int NV = 30;
   __shared__ T st[NV][kRowWG];
@@ -668,10 +780,13 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   const int np = s_blk[nrows];
   if (t < nq) {
     T out[NV];
-    if (FROM_ELEM)
-      incidence_row_off_elem<T>(A, A.inc_code[q0 + t], out);
-    else
+    if (FROM_REC) {
+      const T* rec = A.inc_rows + (int64_t)(q0 + t) * kIncRec;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] = rec[v];
+    } else {
       incidence_row_off<T>(A, A.inc_code[q0 + t], out);
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) st[v][t] = out[v];
   }
@@ -1116,6 +1231,59 @@ symx_status launch_elem_eval(Mesh& m, int set, const double* x, int want, int pr
   return elem_eval_t<double>(m, set, x, E, g, H);
 }
 
+symx_status launch_incidence_positions(Mesh& m, int* inc_pos) {
+  const char* PNAME = "incidence_positions";
+  SetOffsets off{};
+  int64_t acc = 0;
+  for (size_t s = 0; s < m.sets.size(); ++s) {
+    off.first[s] = acc;
+    acc += m.sets[s].n_elem * m.sets[s].k;
+  }
+  SYMX_LAUNCH(m, PNAME, k_incidence_positions, dim3(grid_for(m.n_inc, 256)), dim3(256), 0,
+              m.n_inc, m.inc_code, m.sets_dev(), off, inc_pos);
+  LAUNCH_CHECK("k_incidence_positions");
+  return SYMX_OK;
+}
+
+symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precision,
+                                            const int* inc_pos, void* rows) {
+  const char* PNAME = "elem_rows_projected";
+  const SetsDev sd = m.sets_dev();
+  int64_t first = 0;
+  for (int s = 0; s < sd.n; ++s) {
+    const SetDev& S = sd.s[s];
+    const int* ip = inc_pos + first;
+    first += S.n_elem * S.k;
+    if (S.n_elem == 0) continue;
+    const int G = grid_for(S.n_elem, 64, 65535);
+    if (precision == SYMX_F32) {
+      float* r = (float*)rows;
+      if (S.kind == SYMX_SNH_TET4)
+        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected32<SYMX_SNH_TET4>, dim3(G), dim3(64), 0, S, x,
+                    m.X, ip, r, 30, 2e-7f);
+      else if (S.kind == SYMX_STVK_TRI3)
+        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected32<SYMX_STVK_TRI3>, dim3(G), dim3(64), 0, S, x,
+                    m.X, ip, r, 30, 2e-7f);
+      else
+        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected32<SYMX_HINGE4>, dim3(G), dim3(64), 0, S, x,
+                    m.X, ip, r, 30, 2e-7f);
+    } else {
+      double* r = (double*)rows;
+      if (S.kind == SYMX_SNH_TET4)
+        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected64<SYMX_SNH_TET4>, dim3(G), dim3(64), 0, S, x,
+                    m.X, ip, r, 30, 1e-15);
+      else if (S.kind == SYMX_STVK_TRI3)
+        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected64<SYMX_STVK_TRI3>, dim3(G), dim3(64), 0, S,
+                    x, m.X, ip, r, 30, 1e-15);
+      else
+        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected64<SYMX_HINGE4>, dim3(G), dim3(64), 0, S, x,
+                    m.X, ip, r, 30, 1e-15);
+    }
+    LAUNCH_CHECK("k_elem_rows_projected");
+  }
+  return SYMX_OK;
+}
+
 symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim) {
   const char* PNAME = "project_psd";
   if (n == 0) return SYMX_OK;
@@ -1147,7 +1315,7 @@ symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim) 
 template <typename T>
 static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, double dt,
                                   bool want_g, bool want_H, bool dirichlet,
-                                  const ElemBuffers* eb, double* g_out, void* dinv) {
+                                  const void* inc_rows, double* g_out, void* dinv) {
   RowArgs<T> A;
   A.sets = m.sets_dev();
   A.x = x;
@@ -1171,29 +1339,24 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   A.g = g_out;
   A.dinv = (T*)dinv;
   A.nonfinite = m.nonfinite;
-  for (int s = 0; s < kMaxSets; ++s) {
-    A.elem_g[s] = eb ? eb->g[s] : nullptr;
-    A.elem_H[s] = eb ? eb->H[s] : nullptr;
-  }
+  A.inc_rows = (const T*)inc_rows;
   if ((want_g && !g_out) || (!want_g && !want_H)) {
     set_error("row assembly without an output");
     return SYMX_ERR_INVALID_ARG;
   }
   const dim3 grid(m.n_batch), block(kRowWG);
   const char* PNAME = want_H ? (want_g ? "row_assemble_gH" : "row_assemble_H") : "row_assemble_g";
-  if (eb) {
-    if (want_H && want_g)
+  if (inc_rows && want_H) {
+    if (want_g)
       SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, true>), grid, block, 0, A);
-    else if (want_H)
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, true>), grid, block, 0, A);
     else
-      SYMX_LAUNCH(m, PNAME, (k_row_gradient<T, true>), grid, block, 0, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, true>), grid, block, 0, A);
   } else if (want_H && want_g) {
     SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, false>), grid, block, 0, A);
   } else if (want_H) {
     SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, false>), grid, block, 0, A);
   } else {
-    SYMX_LAUNCH(m, PNAME, (k_row_gradient<T, false>), grid, block, 0, A);
+    SYMX_LAUNCH(m, PNAME, (k_row_gradient<T>), grid, block, 0, A);
   }
   LAUNCH_CHECK("k_row_assemble");
   return SYMX_OK;
@@ -1201,10 +1364,10 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
 
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
                                 bool want_H, int precision, bool dirichlet,
-                                const ElemBuffers* from_elem, double* g_out, void* dinv) {
+                                const void* inc_rows, double* g_out, void* dinv) {
   if (precision == SYMX_F32)
-    return row_assemble_t<float>(m, x, xt, dt, want_g, want_H, dirichlet, from_elem, g_out, dinv);
-  return row_assemble_t<double>(m, x, xt, dt, want_g, want_H, dirichlet, from_elem, g_out, dinv);
+    return row_assemble_t<float>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, g_out, dinv);
+  return row_assemble_t<double>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, g_out, dinv);
 }
 
 symx_status launch_x_tilde(Mesh& m, const double* x, const double* v, double dt, const double g[3],

@@ -106,41 +106,22 @@ static symx_status read_window(Mesh& m, double* win, bool* bad) {
   return SYMX_OK;
 }
 
-// Per-element buffers for the projected path (allocated on first use).
-static symx_status project_elements(Mesh& m, const double* x, int precision, bool want_g,
-                                    ElemBuffers* eb) {
-  const size_t es = precision == SYMX_F64 ? 8 : 4;
-  size_t need = 0;
-  std::vector<size_t> offg(m.sets.size()), offH(m.sets.size());
-  for (size_t s = 0; s < m.sets.size(); ++s) {
-    const size_t D = 3 * m.sets[s].k;
-    offg[s] = need;
-    need += m.sets[s].n_elem * D * es;
-    need = (need + 255) & ~size_t(255);
-    offH[s] = need;
-    need += m.sets[s].n_elem * D * D * es;
-    need = (need + 255) & ~size_t(255);
+// Projected path: incidence positions and records (allocated on first use),
+// then the fused evaluation + projection of every element into the records.
+static symx_status project_into_records(Mesh& m, const double* x, int precision) {
+  if (!m.inc_pos) {
+    TRY(dev_alloc(m.pool, (void**)&m.inc_pos, m.n_inc * sizeof(int)));
+    TRY(launch_incidence_positions(m, m.inc_pos));
   }
-  if (need > m.elem_bytes) {
-    dev_free(m.pool, m.elem_H);
-    m.elem_H = nullptr;
-    m.elem_bytes = 0;
-    TRY(dev_alloc(m.pool, &m.elem_H, need));
-    m.elem_bytes = need;
+  const size_t need = m.n_inc * kIncRec * (precision == SYMX_F64 ? 8 : 4);
+  if (need > m.inc_rows_bytes) {
+    dev_free(m.pool, m.inc_rows);
+    m.inc_rows = nullptr;
+    m.inc_rows_bytes = 0;
+    TRY(dev_alloc(m.pool, &m.inc_rows, need));
+    m.inc_rows_bytes = need;
   }
-  (void)want_g;
-  for (int s = 0; s < kMaxSets; ++s) eb->g[s] = eb->H[s] = nullptr;
-  for (size_t s = 0; s < m.sets.size(); ++s) {
-    char* base = (char*)m.elem_H;
-    void* g = base + offg[s];
-    void* H = base + offH[s];
-    const int D = 3 * m.sets[s].k;
-    TRY(launch_elem_eval(m, (int)s, x, 7, precision, nullptr, g, H));
-    TRY(launch_project(m, precision, H, m.sets[s].n_elem, D));
-    eb->g[s] = g;
-    eb->H[s] = H;
-  }
-  return SYMX_OK;
+  return launch_incidence_rows_projected(m, x, precision, m.inc_pos, m.inc_rows);
 }
 
 // Assemble gradient (float64) and/or Hessian values (precision) at x.  With
@@ -150,9 +131,9 @@ symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool
                      void* dinv = nullptr) {
   if (want_H) TRY(ensure_values(m, precision));
   if (project && want_H) {
-    ElemBuffers eb;
-    TRY(project_elements(m, x, precision, want_g, &eb));
-    return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, &eb, g_out, dinv);
+    TRY(project_into_records(m, x, precision));
+    return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, m.inc_rows, g_out,
+                               dinv);
   }
   if (!want_g && !want_H) return SYMX_OK;
   return launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, g_out,
