@@ -303,6 +303,27 @@ def test_newton_step_c1(symx, precision):
     assert rep.energy == pytest.approx(repo["energy"], rel=1e-9)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32r"])
+def test_newton_step_projected_c1(symx, precision):
+    """Newton with per-element PSD projection (the fused evaluation +
+    projection path) converges and reaches the oracle's projected step."""
+    scene = sg.config_c1()
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32_REFINED
+    st, rep, x, v = _newton(symx, scene, p, project=1)
+    assert st == 0, (symx.STATUS[st], rep.as_dict())
+    dt = scene.dt
+    xt = elements.x_tilde(scene.x0, scene.v0, dt, scene.gravity)
+    r0 = np.linalg.norm(assembly.assemble(scene, scene.x0, xt, dt, want_hess=False)["g"])
+    g = assembly.assemble(scene, x, xt, dt, want_hess=False)["g"]
+    assert np.linalg.norm(g) <= 1.01e-6 * r0
+    ok, xo, repo = newton.newton_solve(scene, scene.x0, scene.v0, dt,
+                                       newton.StepParams(dt=dt, project=True))
+    assert ok
+    m_min = rest.lumped_mass(scene).min()
+    assert np.max(np.abs(x - xo)) <= 2.0e-6 * r0 * dt * dt / m_min
+    assert rep.energy == pytest.approx(repo["energy"], rel=1e-9)
+
+
 def test_newton_step_mixed_f32_refined(symx):
     scene = mixed_scene()
     st, rep, x, _ = _newton(symx, scene, symx.SYMX_F32_REFINED)
