@@ -1,0 +1,135 @@
+"""Parity at the full 64^3-cube size (1,572,864 tets), in the launch
+configuration that bench.py times.
+
+The oracle cannot assemble the whole Hessian at this size in a test, so it
+checks sampled block rows: for each sampled node, the oracle's element
+derivatives of the node's incident elements are summed in element order into
+the node's gradient row and Hessian block row, with inertia and Dirichlet, and
+compared with the device's row.  The Newton step is checked through properties
+that hold at any size, with the oracle's full float64 gradient and energy.
+"""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import assembly, elements, rest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-10
+F32_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def symx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_02156_amd import symx as s
+    s.load()
+    return s
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return sg.config_c2()
+
+
+def _sample_nodes(scene, n, seed):
+    """Interior, surface and fixed nodes, seeded."""
+    rng = np.random.default_rng(seed)
+    fixed = np.nonzero(scene.fixed)[0]
+    free = np.nonzero(scene.fixed == 0)[0]
+    return np.unique(np.concatenate([rng.choice(free, n - 16, replace=False),
+                                     rng.choice(fixed, 16, replace=False),
+                                     [0, scene.n_nodes - 1]]))
+
+
+def _oracle_rows(scene, x, xt, dt, nodes):
+    """Gradient rows and Hessian block rows {(i, j): 3x3} of the sampled nodes,
+    from the oracle's element functions on the incident elements."""
+    es = scene.energies[0]
+    conn = es.conn
+    sel = np.nonzero(np.isin(conn, nodes).any(axis=1))[0]        # ascending element ids
+    sub = sg.EnergySet(es.kind, conn[sel], young=es.young,
+                       young_per_elem=None if es.young_per_elem is None else es.young_per_elem[sel],
+                       poisson=es.poisson, density=es.density)
+    _, ge, He = elements.element_eval(sub, x, scene.X)
+    ge = ge.reshape(-1, 4, 3)
+    He = He.reshape(-1, 4, 3, 4, 3)
+    mass = rest.lumped_mass(scene)
+    w = mass / dt ** 2
+    fixed = scene.fixed.astype(bool)
+    csel = conn[sel]
+    rows = {}
+    for i in nodes:
+        g = np.zeros(3)
+        blocks = {}
+        for k, a in np.argwhere(csel == i):          # ascending element id
+            g += ge[k, a]
+            for b in range(4):
+                j = int(csel[k, b])
+                blocks[j] = blocks.get(j, np.zeros((3, 3))) + He[k, a, :, b, :]
+        g += w[i] * (x[i] - xt[i])
+        blocks[int(i)] = blocks.get(int(i), np.zeros((3, 3))) + w[i] * np.eye(3)
+        if fixed[i]:
+            g[:] = 0.0
+        for j in blocks:
+            if fixed[i] or fixed[j]:
+                blocks[j] = np.eye(3) if j == i else np.zeros((3, 3))
+        rows[int(i)] = (g, blocks)
+    return rows
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_c2_sampled_rows_match_oracle(symx, c2, precision):
+    scene = c2
+    mesh = symx.Mesh(scene)
+    dt = scene.dt
+    xt = elements.x_tilde(scene.x0, scene.v0, dt, scene.gravity)
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32
+    tol = F64_TOL if precision == "f64" else F32_TOL
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    E, g, vals = mesh.assemble(scene.x0, xt, dt, flags, p)
+    rp, ci, _ = mesh.pattern()
+    V = vals.cpu().numpy().astype(np.float64).T.reshape(-1, 3, 3)
+    gd = g.cpu().numpy()
+    nodes = _sample_nodes(scene, 200, seed=41)
+    ref = _oracle_rows(scene, scene.x0, xt, dt, nodes)
+    gerr = gmax = herr = hmax = 0.0
+    for i, (go, blocks) in ref.items():
+        cols = ci[rp[i]:rp[i + 1]]
+        assert sorted(blocks) == list(cols)                        # row pattern
+        gerr = max(gerr, np.abs(gd[i] - go).max())
+        gmax = max(gmax, np.abs(go).max())
+        for s_, j in enumerate(cols):
+            herr = max(herr, np.abs(V[rp[i] + s_] - blocks[int(j)]).max())
+            hmax = max(hmax, np.abs(blocks[int(j)]).max())
+    assert herr <= tol * hmax
+    assert gerr <= tol * max(gmax, 1e-300)
+    E_ref = assembly.energy(scene, scene.x0, xt, dt)
+    assert abs(E - E_ref) <= tol * abs(E_ref)
+    mesh.close()
+
+
+def test_c2_newton_step_f32_refined(symx, c2):
+    """One FP32-refined step at full size: the oracle's float64 gradient at the
+    result meets the Newton tolerance, and the reported energy is the oracle's."""
+    scene = c2
+    mesh = symx.Mesh(scene)
+    x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    st, rep = mesh.newton_step(x, v, symx.step_params(dt=scene.dt,
+                                                      precision=symx.SYMX_F32_REFINED))
+    mesh.close()
+    assert st == 0, (symx.STATUS[st], rep.as_dict())
+    xh = x.cpu().numpy()
+    xt = elements.x_tilde(scene.x0, scene.v0, scene.dt, scene.gravity)
+    r0 = np.linalg.norm(assembly.assemble(scene, scene.x0, xt, scene.dt, want_hess=False)["g"])
+    assert rep.residual0 == pytest.approx(r0, rel=1e-10)
+    r = np.linalg.norm(assembly.assemble(scene, xh, xt, scene.dt, want_hess=False)["g"])
+    assert r <= 1.01e-6 * r0
+    E_ref = assembly.energy(scene, xh, xt, scene.dt)
+    assert rep.energy == pytest.approx(E_ref, rel=1e-10)
+    assert np.allclose(v.cpu().numpy(), (xh - scene.x0) / scene.dt)

@@ -376,6 +376,85 @@ def test_invalid_mesh_rejected(symx):
         symx.Mesh(s)
 
 
+def _edge_scene():
+    """Tet block, an empty membrane set and three isolated nodes (rows with
+    only a diagonal block), one fixed isolated node."""
+    s = sg.tet_cube_scene(3, seed=7, perturb=0.05)
+    iso = np.array([[1.0, 1.0, 1.0], [1.1, 1.0, 1.0], [1.0, 1.2, 1.0]])
+    X = np.concatenate([s.X, iso])
+    x0 = np.concatenate([s.x0, iso + 0.001])
+    es = [s.energies[0], sg.EnergySet(sg.STVK_TRI3, np.zeros((0, 3), np.int32), young=1e4,
+                                      poisson=0.3, thickness=1e-3)]
+    fixed = np.concatenate([s.fixed, np.array([0, 0, 1], np.uint8)])
+    return sg.Scene("edge", X, es, fixed, x0, np.zeros_like(X), dt=0.01)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_empty_set_and_isolated_nodes(symx, precision):
+    scene = _edge_scene()
+    mesh = symx.Mesh(scene)
+    rp, ci, _ = mesh.pattern()
+    rp_o, ci_o = assembly.pattern_fast(scene)
+    assert np.array_equal(rp, rp_o) and np.array_equal(ci, ci_o)
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32
+    tol = F64_TOL if precision == "f64" else F32_TOL
+    xt = elements.x_tilde(scene.x0, scene.v0, scene.dt, scene.gravity)
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    for extra in (0, symx.SYMX_PROJECT_PSD):
+        E, g, vals = mesh.assemble(scene.x0, xt, scene.dt, flags | extra, p)
+        ref = assembly.assemble(scene, scene.x0, xt, scene.dt, project=bool(extra))
+        assert abs(E - ref["E"]) <= tol * abs(ref["E"])
+        assert rel(g.cpu().numpy(), ref["g"]) < tol
+        assert rel(_bsr(vals), ref["vals"]) < tol
+    E1, g1, H1 = mesh.eval_derivatives(1, scene.x0, precision=p)  # the empty set
+    assert E1.numel() == 0
+    st, rep, x, v = _newton(symx, scene, p if p == symx.SYMX_F64 else symx.SYMX_F32_REFINED)
+    assert st == 0
+    mesh.close()
+
+
+def test_single_element(symx):
+    x, X = sg.random_tets(1, seed=3)
+    conn = np.arange(4, dtype=np.int32).reshape(1, 4)
+    es = sg.EnergySet(sg.SNH_TET4, conn, young=1e5, poisson=0.4)
+    scene = sg.Scene("one", X.reshape(4, 3), [es], np.zeros(4, np.uint8), x.reshape(4, 3),
+                     np.zeros((4, 3)))
+    mesh = symx.Mesh(scene)
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS
+    E, g, vals = mesh.assemble(scene.x0, None, 0.0, flags, symx.SYMX_F64)
+    ref = assembly.assemble(scene, scene.x0, dirichlet=False)
+    assert abs(E - ref["E"]) <= F64_TOL * abs(ref["E"])
+    assert rel(g.cpu().numpy(), ref["g"]) < F64_TOL
+    assert rel(_bsr(vals), ref["vals"]) < F64_TOL
+    mesh.close()
+
+
+def test_invalid_elements_rejected(symx):
+    """Degenerate rest tet, repeated node, a node in more than 256 elements."""
+    s = sg.tet_cube_scene(1, seed=1)
+    flat = s.energies[0].conn.copy()
+    X = s.X.copy()
+    X[flat[0]] = X[flat[0, 0]] + np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [3, 0, 0]]) * 1e-3
+    bad = sg.Scene("degenerate", X, [s.energies[0]], s.fixed, X.copy(), np.zeros_like(X))
+    with pytest.raises(symx.SymxError, match="INVALID_ARG"):
+        symx.Mesh(bad)
+    rep = s.energies[0].conn.copy()
+    rep[0, 1] = rep[0, 0]
+    s2 = sg.Scene("repeat", s.X, [sg.EnergySet(sg.SNH_TET4, rep)], s.fixed, s.x0, s.v0)
+    with pytest.raises(symx.SymxError, match="INVALID_ARG"):
+        symx.Mesh(s2)
+    # 257 tets sharing node 0 (a fan of thin tets around the z axis)
+    n = 257
+    ang = 2 * np.pi * np.arange(n + 1) / n
+    ring = np.stack([np.cos(ang), np.sin(ang), np.zeros(n + 1)], axis=1) * 0.01
+    Xf = np.concatenate([np.zeros((1, 3)), np.array([[0, 0, 0.01]]), ring[:n]])
+    conn = np.array([[0, 2 + i, 2 + (i + 1) % n, 1] for i in range(n)], np.int32)
+    fan = sg.Scene("fan", Xf, [sg.EnergySet(sg.SNH_TET4, conn)], np.zeros(len(Xf), np.uint8),
+                   Xf.copy(), np.zeros_like(Xf))
+    with pytest.raises(symx.SymxError, match="INVALID_ARG"):
+        symx.Mesh(fan)
+
+
 def test_f32_refined_tracks_f64_trajectory(symx):
     """Stiff heterogeneous compressed block (the C4 recipe at n=6): the FP32-
     refined steps, taken with the FP64 run's time steps, stay within the Newton
