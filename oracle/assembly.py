@@ -92,12 +92,13 @@ def scatter_map(scene, row_ptr, col_idx):
 
 
 def assemble(scene, x, x_tilde=None, dt=None, project=False, dirichlet=True,
-             want_hess=True, row_ptr=None, col_idx=None):
+             want_hess=True, row_ptr=None, col_idx=None, x_lag=None):
     """Assemble E (float), g (N,3) and BSR values (nnzb,3,3) at positions x.
 
     Returns dict(E, g, row_ptr, col_idx, vals, E_parts).  With x_tilde/dt the
     inertia term of the incremental potential is included.  project=True
     replaces each element Hessian by its PSD projection before assembly.
+    x_lag: positions of the lagged rotations (default: rest).
     """
     N = scene.n_nodes
     if row_ptr is None:
@@ -109,7 +110,7 @@ def assemble(scene, x, x_tilde=None, dt=None, project=False, dirichlet=True,
     E_total = 0.0
     parts = []
     for es in scene.energies:
-        Ee, ge, He = elements.element_eval(es, x, scene.X, want_hess)
+        Ee, ge, He = elements.element_eval(es, x, scene.X, want_hess, x_lag)
         parts.append(float(np.sum(Ee)))
         E_total += float(np.sum(Ee))
         c = es.conn
@@ -167,11 +168,11 @@ def _diag_index(row_ptr, col_idx):
     return d
 
 
-def energy(scene, x, x_tilde=None, dt=None):
+def energy(scene, x, x_tilde=None, dt=None, x_lag=None):
     """Total energy only (the line-search evaluation level)."""
     E = 0.0
     for es in scene.energies:
-        Ee, _, _ = elements.element_eval(es, x, scene.X, want_hess=False)
+        Ee, _, _ = elements.element_eval(es, x, scene.X, want_hess=False, x_lag=x_lag)
         E += float(np.sum(Ee))
     if x_tilde is not None:
         m = lumped_mass(scene)

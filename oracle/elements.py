@@ -15,6 +15,11 @@ Energies:
 * Quadratic bending hinge -- Eq. 13 (Bergou et al. 2006): E = k_b/2 x^T Q x with
   the constant Q = 3/(A0+A1) (K K^T) (x) I3 built from the rest cotangents.
 * Inertia -- Eq. 2: m/(2 dt^2) |x - x_tilde|^2 per node.
+* The other App. B constitutive models on linear tets, E_e = V_e psi(F_e):
+  classic Neo-Hookean (Eq. 6 with the rest-stable sign of the log term),
+  Saint Venant-Kirchhoff, fixed co-rotational and as-rigid-as-possible with a
+  volume term, the last two with the rotation R held constant over a time step
+  (lagged, Sec. 6.1); R is the rotation closest to F at the lag positions.
 """
 from __future__ import annotations
 
@@ -82,6 +87,130 @@ def snh_tet4(x, X, mu, lam, want_hess=True):
           + s2[:, None, None, None, None] * np.einsum("ikm,jln,emn->eijkl", _EPS, _EPS, F))
     H = V[:, None, None, None, None] * np.einsum("eaj,ebl,eijkl->eaibk", b, b, d2)
     return E, g, H
+
+
+# ----------------------------------------------------------------------------
+# Other App. B materials on linear tets
+# ----------------------------------------------------------------------------
+def _tet_kinematics(x, X):
+    Dm = _cols(X)
+    Dinv = np.linalg.inv(Dm)
+    V = np.abs(np.linalg.det(Dm)) / 6.0
+    F = _cols(x) @ Dinv
+    f0, f1, f2 = F[:, :, 0], F[:, :, 1], F[:, :, 2]
+    J = np.einsum("ei,ei->e", f0, np.cross(f1, f2))
+    cof = np.stack([np.cross(f1, f2), np.cross(f2, f0), np.cross(f0, f1)], axis=2)
+    return V, F, J, cof, _shape_gradients(Dinv)
+
+
+def _tet_element(V, psi, P, d2, b, want_hess):
+    """E = V psi, g_a = V P b_a, H_ab = V sum b_aj b_bl d2_ijkl."""
+    E = V * psi
+    g = V[:, None, None] * np.einsum("eij,eaj->eai", P, b)
+    if not want_hess:
+        return E, g, None
+    return E, g, V[:, None, None, None, None] * np.einsum("eaj,ebl,eijkl->eaibk", b, b, d2())
+
+
+def _hess_J(F):
+    """d2 J / dF_ij dF_kl = eps_ikm eps_jln F_mn."""
+    return np.einsum("ikm,jln,emn->eijkl", _EPS, _EPS, F)
+
+
+def _I4(n):
+    I3 = np.eye(3)
+    return np.broadcast_to(np.einsum("ik,jl->ijkl", I3, I3)[None], (n, 3, 3, 3, 3))
+
+
+def nh_tet4(x, X, mu, lam, want_hess=True):
+    """Classic Neo-Hookean: psi = mu/2 (Ic - 3) - mu log J + lam/2 log^2 J.
+    P = mu F + (lam log J - mu) F^-T; with Fi = F^-T,
+    d2psi_ijkl = mu d_ik d_jl + lam Fi_ij Fi_kl - (lam log J - mu) Fi_il Fi_kj."""
+    mu = np.asarray(mu, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    V, F, J, cof, b = _tet_kinematics(x, X)
+    Ic = np.einsum("eij,eij->e", F, F)
+    logJ = np.log(J)
+    psi = 0.5 * mu * (Ic - 3.0) - mu * logJ + 0.5 * lam * logJ ** 2
+    Fi = cof / J[:, None, None]
+    c = lam * logJ - mu
+    P = mu[:, None, None] * F + c[:, None, None] * Fi
+    return _tet_element(V, psi, P, lambda: (
+        mu[:, None, None, None, None] * _I4(len(V))
+        + lam[:, None, None, None, None] * np.einsum("eij,ekl->eijkl", Fi, Fi)
+        - c[:, None, None, None, None] * np.einsum("eil,ekj->eijkl", Fi, Fi)), b, want_hess)
+
+
+def stvk_tet4(x, X, mu, lam, want_hess=True):
+    """Saint Venant-Kirchhoff: psi = mu |E|^2 + lam/2 tr(E)^2, E = (F^T F - I)/2.
+    P = F S, S = 2 mu E + lam tr(E) I;
+    d2psi_ijkl = d_ik S_lj + mu (F_il F_kj + (F F^T)_ik d_jl) + lam F_ij F_kl."""
+    mu = np.asarray(mu, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    V, F, J, cof, b = _tet_kinematics(x, X)
+    Eg = 0.5 * (np.einsum("eki,ekj->eij", F, F) - np.eye(3)[None])
+    trE = np.einsum("eii->e", Eg)
+    psi = mu * np.einsum("eij,eij->e", Eg, Eg) + 0.5 * lam * trE ** 2
+    S = 2.0 * mu[:, None, None] * Eg + (lam * trE)[:, None, None] * np.eye(3)[None]
+    P = F @ S
+    I3 = np.eye(3)
+
+    def d2():
+        FFt = np.einsum("eim,ekm->eik", F, F)
+        return (np.einsum("ik,elj->eijkl", I3, S)
+                + mu[:, None, None, None, None] * (np.einsum("eil,ekj->eijkl", F, F)
+                                                   + np.einsum("eik,jl->eijkl", FFt, I3))
+                + lam[:, None, None, None, None] * np.einsum("eij,ekl->eijkl", F, F))
+    return _tet_element(V, psi, P, d2, b, want_hess)
+
+
+def fcr_tet4(x, X, mu, lam, R, want_hess=True):
+    """Fixed co-rotational with lagged R: psi = mu |F - R|^2 + lam/2 (J - 1)^2.
+    P = 2 mu (F - R) + lam (J - 1) cof F;
+    d2psi = 2 mu d_ik d_jl + lam cof_ij cof_kl + lam (J - 1) d2J."""
+    mu = np.asarray(mu, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    V, F, J, cof, b = _tet_kinematics(x, X)
+    D = F - R
+    psi = mu * np.einsum("eij,eij->e", D, D) + 0.5 * lam * (J - 1.0) ** 2
+    P = 2.0 * mu[:, None, None] * D + (lam * (J - 1.0))[:, None, None] * cof
+    return _tet_element(V, psi, P, lambda: (
+        2.0 * mu[:, None, None, None, None] * _I4(len(V))
+        + lam[:, None, None, None, None] * np.einsum("eij,ekl->eijkl", cof, cof)
+        + (lam * (J - 1.0))[:, None, None, None, None] * _hess_J(F)), b, want_hess)
+
+
+def arap_tet4(x, X, mu, lam, R, want_hess=True):
+    """As-rigid-as-possible with a volume term, lagged R:
+    psi = mu/2 (Ic - 2 tr(F^T R) + 3) + lam/2 (J - 1)^2 = mu/2 |F - R|^2 + ...
+    P = mu (F - R) + lam (J - 1) cof F;
+    d2psi = mu d_ik d_jl + lam cof_ij cof_kl + lam (J - 1) d2J."""
+    mu = np.asarray(mu, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    V, F, J, cof, b = _tet_kinematics(x, X)
+    Ic = np.einsum("eij,eij->e", F, F)
+    trFR = np.einsum("eij,eij->e", F, R)
+    psi = 0.5 * mu * (Ic - 2.0 * trFR + 3.0) + 0.5 * lam * (J - 1.0) ** 2
+    P = mu[:, None, None] * (F - R) + (lam * (J - 1.0))[:, None, None] * cof
+    return _tet_element(V, psi, P, lambda: (
+        mu[:, None, None, None, None] * _I4(len(V))
+        + lam[:, None, None, None, None] * np.einsum("eij,ekl->eijkl", cof, cof)
+        + (lam * (J - 1.0))[:, None, None, None, None] * _hess_J(F)), b, want_hess)
+
+
+def closest_rotation(F):
+    """The rotation R maximising tr(R^T F) (orthogonal Procrustes on SO(3)):
+    with F = U S V^T, R = U diag(1, 1, det(U V^T)) V^T."""
+    U, _, Vt = np.linalg.svd(F)
+    d = np.sign(np.linalg.det(U @ Vt))
+    D = np.ones((F.shape[0], 3))
+    D[:, 2] = d
+    return np.einsum("eij,ej,ejk->eik", U, D, Vt)
+
+
+def lagged_rotations(x_lag, X):
+    """Rotations of the deformation gradients at the lag positions (E,k,3)."""
+    return closest_rotation(_cols(x_lag) @ np.linalg.inv(_cols(X)))
 
 
 # ----------------------------------------------------------------------------
@@ -197,17 +326,26 @@ def x_tilde(x_t, v_t, dt, gravity):
     return x_t + dt * v_t + dt ** 2 * np.asarray(gravity, dtype=np.float64)[None, :]
 
 
-def element_eval(es, x, X, want_hess=True):
-    """Dispatch on the energy kind of an EnergySet (element arrays gathered)."""
+def element_eval(es, x, X, want_hess=True, x_lag=None):
+    """Dispatch on the energy kind of an EnergySet (element arrays gathered).
+    x_lag: positions the lagged rotations are taken at (default: rest)."""
     from .rest import lame, young_array
     xe = x[es.conn]
     Xe = X[es.conn]
-    if es.kind == 0:
-        mu, lam = lame(young_array(es), es.poisson)
-        return snh_tet4(xe, Xe, mu, lam, want_hess)
     if es.kind == 1:
         mu, lam = lame(young_array(es), es.poisson)
         return stvk_tri3(xe, Xe, mu, lam, es.thickness, want_hess)
     if es.kind == 2:
         return hinge4(xe, Xe, es.bend_kb, want_hess)
+    mu, lam = lame(young_array(es), es.poisson)
+    if es.kind == 0:
+        return snh_tet4(xe, Xe, mu, lam, want_hess)
+    if es.kind == 3:
+        return nh_tet4(xe, Xe, mu, lam, want_hess)
+    if es.kind == 4:
+        return stvk_tet4(xe, Xe, mu, lam, want_hess)
+    if es.kind in (5, 6):
+        R = lagged_rotations(Xe if x_lag is None else x_lag[es.conn], Xe)
+        f = fcr_tet4 if es.kind == 5 else arap_tet4
+        return f(xe, Xe, mu, lam, R, want_hess)
     raise ValueError(f"unknown energy kind {es.kind}")

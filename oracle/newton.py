@@ -83,7 +83,8 @@ def pcg(A, Dinv, b, rtol, max_iter):
 
 
 def newton_solve(scene, x_t, v_t, dt, prm: StepParams, solver="pcg", record=None):
-    """One implicit-Euler step at fixed dt.  Returns (ok, x, report dict)."""
+    """One implicit-Euler step at fixed dt.  Returns (ok, x, report dict).
+    Lagged rotations (fixed co-rotational, ARAP) are taken at x(t)."""
     xt = predict(x_t, v_t, dt, prm.gravity)
     x = x_t.copy()
     rp, ci = assembly.pattern_fast(scene)
@@ -91,7 +92,8 @@ def newton_solve(scene, x_t, v_t, dt, prm: StepParams, solver="pcg", record=None
                energy=0.0, status="ok")
     r0 = None
     for it in range(prm.max_newton + 1):
-        asm = assembly.assemble(scene, x, xt, dt, project=prm.project, row_ptr=rp, col_idx=ci)
+        asm = assembly.assemble(scene, x, xt, dt, project=prm.project, row_ptr=rp, col_idx=ci,
+                                x_lag=x_t)
         g = asm["g"]
         r = float(np.linalg.norm(g))
         if r0 is None:
@@ -125,7 +127,7 @@ def newton_solve(scene, x_t, v_t, dt, prm: StepParams, solver="pcg", record=None
         alpha = 1.0
         ok = False
         for _ in range(prm.ls_max + 1):
-            Et = assembly.energy(scene, x + alpha * dx, xt, dt)
+            Et = assembly.energy(scene, x + alpha * dx, xt, dt, x_lag=x_t)
             if Et <= E0 + prm.armijo_c * alpha * gd:
                 ok = True
                 break

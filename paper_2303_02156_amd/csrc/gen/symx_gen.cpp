@@ -70,6 +70,75 @@ S snh_tet4(Graph& g, const std::vector<S>& in) {
   return V * psi;
 }
 
+// Deformation gradient and rest volume of a tet4 with inputs x (0..11), X
+// (12..23): F = Ds Dm^-1, V = |det Dm| / 6 (Sec. 3.1).
+struct TetKinematics {
+  Mat F;
+  S V;
+};
+TetKinematics tet_kinematics(Graph& g, const std::vector<S>& in) {
+  Mat Ds = cols_minus_first(g, in, 0, 4);
+  Mat Dm = cols_minus_first(g, in, 12, 4);
+  return {matmul(Ds, inv3(Dm)), abs(det3(Dm)) / 6.0};
+}
+
+// Rotation R (row-major, inputs 26..34) of the lagged-rotation materials.
+Mat lagged_rotation(Graph& g, const std::vector<S>& in) {
+  Mat R(3, 3, &g);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) R(i, j) = in[26 + 3 * i + j];
+  return R;
+}
+
+// Classic Neo-Hookean tet4 (App. B, Neo-Hookean branch; Eq. 6 with the sign
+// of the log term that makes the rest state stress free):
+// psi = mu/2 (Ic - 3) - mu log J + lambda/2 log^2 J.
+S nh_tet4(Graph& g, const std::vector<S>& in) {
+  TetKinematics k = tet_kinematics(g, in);
+  S mu = in[24], lam = in[25];
+  S logJ = log(det3(k.F));
+  S psi = 0.5 * mu * (frob2(k.F) - 3.0) - mu * logJ + 0.5 * lam * pown(logJ, 2);
+  return k.V * psi;
+}
+
+// Saint Venant-Kirchhoff tet4 (App. B, Saint Venant branch):
+// psi = mu |E|^2 + lambda/2 tr(E)^2, E = (F^T F - I) / 2.
+S stvk_tet4(Graph& g, const std::vector<S>& in) {
+  TetKinematics k = tet_kinematics(g, in);
+  S mu = in[24], lam = in[25];
+  Mat C = matmul(transpose(k.F), k.F);
+  Mat E(3, 3, &g);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) E(i, j) = i == j ? 0.5 * (C(i, j) - 1.0) : 0.5 * C(i, j);
+  S psi = mu * frob2(E) + 0.5 * lam * pown(trace(E), 2);
+  return k.V * psi;
+}
+
+// Fixed co-rotational tet4 (App. B, fixed co-rotational branch) with the
+// rotation R held constant over a time step (lagged):
+// psi = mu |F - R|^2 + lambda/2 (J - 1)^2.
+S fcr_tet4(Graph& g, const std::vector<S>& in) {
+  TetKinematics k = tet_kinematics(g, in);
+  Mat R = lagged_rotation(g, in);
+  S mu = in[24], lam = in[25];
+  Mat D(3, 3, &g);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) D(i, j) = k.F(i, j) - R(i, j);
+  S psi = mu * frob2(D) + 0.5 * lam * pown(det3(k.F) - 1.0, 2);
+  return k.V * psi;
+}
+
+// As-rigid-as-possible tet4 with a volume term (App. B, ARAP branch), R
+// lagged: psi = mu/2 (Ic - 2 tr(F^T R) + 3) + lambda/2 (J - 1)^2.
+S arap_tet4(Graph& g, const std::vector<S>& in) {
+  TetKinematics k = tet_kinematics(g, in);
+  Mat R = lagged_rotation(g, in);
+  S mu = in[24], lam = in[25];
+  S trFR = trace(matmul(transpose(k.F), R));
+  S psi = 0.5 * mu * (frob2(k.F) - 2.0 * trFR + 3.0) + 0.5 * lam * pown(det3(k.F) - 1.0, 2);
+  return k.V * psi;
+}
+
 // StVK membrane triangle (App. B, Saint Venant-Kirchhoff branch, on the 3x2
 // deformation gradient of a triangle).  Written frame-free: with the rest
 // metric G = Dm^T Dm and the current metric C = Ds^T Ds of the two edge
@@ -209,6 +278,10 @@ int main(int argc, char** argv) {
       {"stvk_tri3", 3, 21, 9, stvk_tri3},
       {"hinge4", 4, 18, -1, hinge4},
       {"inertia", 1, 8, -1, inertia},
+      {"nh_tet4", 4, 26, 12, nh_tet4},
+      {"stvk_tet4", 4, 26, 12, stvk_tet4},
+      {"fcr_tet4", 4, 35, 12, fcr_tet4},
+      {"arap_tet4", 4, 35, 12, arap_tet4},
   };
   Generated all;
   all.hip =

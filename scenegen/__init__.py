@@ -31,8 +31,13 @@ import numpy as np
 SNH_TET4 = 0
 STVK_TRI3 = 1
 HINGE4 = 2
+NH_TET4 = 3
+STVK_TET4 = 4
+FCR_TET4 = 5
+ARAP_TET4 = 6
 
-NODES_PER_ELEM = {SNH_TET4: 4, STVK_TRI3: 3, HINGE4: 4}
+NODES_PER_ELEM = {SNH_TET4: 4, STVK_TRI3: 3, HINGE4: 4, NH_TET4: 4, STVK_TET4: 4, FCR_TET4: 4,
+                  ARAP_TET4: 4}
 
 _PERMS = list(itertools.permutations(range(3)))          # lexicographic order
 _PERM_ODD = [False, True, True, False, False, True]      # parity of each entry
@@ -162,11 +167,12 @@ def _bottom_fixed(X: np.ndarray, z_min: float | None = None) -> np.ndarray:
 def tet_cube_scene(n: int, h: float = 0.01, young: float = 1e5, poisson: float = 0.4,
                    density: float = 1000.0, dt: float = 0.01, seed: int = 1,
                    perturb: float = 0.01, vel_std: float = 0.0, name: str | None = None,
-                   dims: tuple | None = None) -> Scene:
+                   dims: tuple | None = None, kind: int = SNH_TET4) -> Scene:
     """Cube (or box, via dims) of 6-tet cubes with the bottom face fixed.
 
     x(t) = X + U(-perturb*h, perturb*h)^3 on free nodes; v(t) ~ N(0, vel_std^2)
     on free nodes.  Draw order: perturbations (node-major), then velocities.
+    kind: the tet material (SNH_TET4, NH_TET4, STVK_TET4, FCR_TET4, ARAP_TET4).
     """
     nx, ny, nz = dims if dims is not None else (n, n, n)
     X, tets = tet_grid(nx, ny, nz, h)
@@ -178,9 +184,31 @@ def tet_cube_scene(n: int, h: float = 0.01, young: float = 1e5, poisson: float =
     free = (fixed == 0)[:, None]
     x0 = X + np.where(free, pert, 0.0)
     v0 = np.where(free, vel, 0.0)
-    es = EnergySet(SNH_TET4, tets, young=young, poisson=poisson, density=density)
+    es = EnergySet(kind, tets, young=young, poisson=poisson, density=density)
     return Scene(name or f"tetcube{nx}x{ny}x{nz}", X, [es], fixed, x0, v0, dt=dt,
                  meta=dict(n=n, h=h, seed=seed))
+
+
+def stretched_box_scene(kind: int, dims: tuple = (40, 40, 60), h: float = 0.01,
+                        young: float = 1e4, poisson: float = 0.3, stretch: float = 0.2,
+                        seed: int = 6) -> Scene:
+    """The material comparison workload (Sec. 6.1, Table 3): a box of 6-tet
+    cubes (40 x 40 x 60 cubes: 41*41*61 nodes = 307,623 DoF), E=1e4 Pa,
+    nu=0.3, bottom face fixed, top face fixed at (1 + stretch) of the height,
+    interior stretched affinely in z plus +-1% noise (seed)."""
+    nx, ny, nz = dims
+    X, tets = tet_grid(nx, ny, nz, h)
+    z = X[:, 2]
+    top = z >= z.max() - 1e-12
+    fixed = (_bottom_fixed(X).astype(bool) | top).astype(np.uint8)
+    rng = np.random.default_rng(seed)
+    pert = rng.uniform(-0.01 * h, 0.01 * h, size=X.shape)
+    x0 = X.copy()
+    x0[:, 2] *= 1.0 + stretch
+    x0 = np.where(fixed[:, None] == 1, x0, x0 + pert)
+    es = EnergySet(kind, tets, young=young, poisson=poisson, density=1000.0)
+    return Scene(f"stretched-box-k{kind}", X, [es], fixed, x0, np.zeros_like(X), dt=0.01,
+                 meta=dict(dims=dims, h=h, stretch=stretch, seed=seed))
 
 
 def config_c1() -> Scene:

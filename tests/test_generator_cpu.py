@@ -99,6 +99,43 @@ def test_snh_generated_vs_oracle(lib):
         assert _rel(rg, g[:, a]) < 1e-10
 
 
+@pytest.mark.parametrize("name", ["nh_tet4", "stvk_tet4", "fcr_tet4", "arap_tet4"])
+def test_other_materials_generated_vs_oracle(lib, name):
+    """The remaining App. B materials: full E/g/H, node 0 at the origin, and the
+    off-diagonal row function of every relabelled node."""
+    x, X = sg.random_tets(40, seed=107, inverted_frac=0.0)
+    n = x.shape[0]
+    rng = np.random.default_rng(108)
+    q, _ = np.linalg.qr(rng.normal(size=(n, 3, 3)))
+    R = elements.closest_rotation(q)
+    mu, lam = np.full(n, MU), np.full(n, LAM)
+    oracle_fn = {"nh_tet4": lambda xx: elements.nh_tet4(xx, X, mu, lam),
+                 "stvk_tet4": lambda xx: elements.stvk_tet4(xx, X, mu, lam),
+                 "fcr_tet4": lambda xx: elements.fcr_tet4(xx, X, mu, lam, R),
+                 "arap_tet4": lambda xx: elements.arap_tet4(xx, X, mu, lam, R)}[name]
+    E, g, H = oracle_fn(x)
+    extra = [R.reshape(n, 9)] if name in ("fcr_tet4", "arap_tet4") else []
+    n_in = 26 + 9 * len(extra)
+
+    def inputs(xx, XX):
+        return np.concatenate([xx.reshape(n, 12), XX.reshape(n, 12), mu[:, None], lam[:, None]]
+                              + extra, axis=1)
+    inp = inputs(x, X)
+    assert inp.shape[1] == n_in
+    out = _call(lib, name + "_EgH", inp, 157)
+    assert _rel(out[:, 0], E) < 1e-10
+    assert _rel(out[:, 1:13], g.reshape(n, 12)) < 1e-10
+    assert _rel(out[:, 13:], H.reshape(n, 144)) < 1e-10
+    out_s = _call(lib, name + "_s_EgH", inputs(x - x[:, :1], X - X[:, :1]), 157)
+    assert _rel(out_s, out) < 1e-9
+    for a in range(4):
+        perm = [a] + [b for b in range(4) if b != a]
+        r = _call(lib, name + "_row0_gHoff",
+                  inputs(x[:, perm] - x[:, a:a + 1], X[:, perm] - X[:, a:a + 1]), 30)
+        assert _rel(r[:, :3], g[:, a]) < 1e-9
+        assert _rel(r[:, 3:].reshape(n, 3, 9), H[:, a][:, :, perm[1:], :].reshape(n, 3, 9)) < 1e-9
+
+
 def _random_tris(n, seed):
     rng = np.random.default_rng(seed)
     base = np.array([[0, 0, 0], [1, 0, 0], [0.2, 0.9, 0]], dtype=np.float64) * 0.01

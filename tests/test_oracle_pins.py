@@ -181,6 +181,98 @@ def test_snh_invariances_and_symmetry():
 # ----------------------------------------------------------------------------
 # StVK membrane
 # ----------------------------------------------------------------------------
+# ----------------------------------------------------------------------------
+# Other App. B materials on tets (classic NH, StVK, fixed co-rotational, ARAP)
+# ----------------------------------------------------------------------------
+def _mat(kind, x, X, R=None, **kw):
+    n = x.shape[0]
+    mu, lam = np.full(n, MU), np.full(n, LAM)
+    if kind == "nh":
+        return elements.nh_tet4(x, X, mu, lam, **kw)
+    if kind == "stvk":
+        return elements.stvk_tet4(x, X, mu, lam, **kw)
+    if kind == "fcr":
+        return elements.fcr_tet4(x, X, mu, lam, R, **kw)
+    return elements.arap_tet4(x, X, mu, lam, R, **kw)
+
+
+@pytest.mark.parametrize("kind", ["nh", "stvk", "fcr", "arap"])
+def test_material_derivatives_complex_step(kind):
+    x, X = sg.random_tets(25, seed=31, inverted_frac=0.0)    # log J needs J > 0
+    R = np.stack([_rot(s) for s in range(25)])
+    E, g, H = _mat(kind, x, X, R)
+    gc = _cs_grad(lambda xc: _mat(kind, xc, X, R, want_hess=False)[0], x)
+    Hc = _cs_jac(lambda xc: _mat(kind, xc, X, R, want_hess=False)[1], x)
+    assert _rel(g, gc) < 1e-12
+    assert _rel(H, Hc) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["nh", "stvk"])
+def test_nh_and_stvk_rest_is_linear_elasticity(kind):
+    X = _tet_rest()
+    E, g, H = _mat(kind, X, X)
+    assert np.max(np.abs(E)) < 1e-12 * MU * 1e-6
+    assert np.max(np.abs(g)) < 1e-9 * MU * 1e-4
+    for e in range(X.shape[0]):
+        assert _rel(H[e].reshape(12, 12), _cst_tet_stiffness(X[e], MU, LAM)) < 1e-12
+
+
+@pytest.mark.parametrize("kind,c", [("fcr", 2.0), ("arap", 1.0)])
+def test_lagged_rotation_rest_hessian_closed_form(kind, c):
+    """With R = I at rest: E = 0, g = 0 and d2psi = c mu d_ik d_jl + lam d_ij d_kl,
+    so block (a,b) = V (c mu (b_a . b_b) I + lam b_a b_b^T), b_a the shape
+    gradients (rows of Dm^-1 and minus their sum)."""
+    X = _tet_rest()
+    R = np.broadcast_to(np.eye(3), (X.shape[0], 3, 3))
+    E, g, H = _mat(kind, X, X, R)
+    assert np.max(np.abs(E)) < 1e-12 * MU * 1e-6
+    assert np.max(np.abs(g)) < 1e-9 * MU * 1e-4
+    for e in range(X.shape[0]):
+        M = np.hstack([np.ones((4, 1)), X[e]])
+        bg = np.linalg.inv(M)[1:, :].T                       # dN_a/dX, (4,3)
+        V = abs(np.linalg.det(np.stack([X[e][a] - X[e][0] for a in (1, 2, 3)], 1))) / 6
+        K = np.zeros((4, 3, 4, 3))
+        for a in range(4):
+            for b in range(4):
+                K[a, :, b, :] = V * (c * MU * (bg[a] @ bg[b]) * np.eye(3)
+                                     + LAM * np.outer(bg[a], bg[b]))
+        assert _rel(H[e], K) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["fcr", "arap"])
+def test_lagged_rotation_energies_rotate_with_r(kind):
+    """Rotating positions and the lagged rotation together leaves E unchanged
+    and rotates g and H; translation leaves everything unchanged."""
+    x, X = sg.random_tets(20, seed=32, inverted_frac=0.2)
+    R = np.stack([_rot(s + 40) for s in range(20)])
+    E, g, H = _mat(kind, x, X, R)
+    Q = _rot(5)
+    E2, g2, H2 = _mat(kind, x @ Q.T, X, Q[None] @ R)
+    assert np.allclose(E2, E, rtol=1e-12, atol=1e-12 * np.abs(E).max())
+    assert _rel(g2, g @ Q.T) < 1e-11
+    QQ = np.kron(np.eye(4), Q)
+    assert _rel(H2.reshape(-1, 12, 12), QQ @ H.reshape(-1, 12, 12) @ QQ.T) < 1e-11
+    E3, g3, _ = _mat(kind, x + np.array([0.2, -0.1, 0.3]), X, R)
+    assert np.allclose(E3, E, rtol=1e-12) and _rel(g3, g) < 1e-12
+
+
+def test_closest_rotation():
+    rng = np.random.default_rng(33)
+    Q = np.stack([_rot(s + 60) for s in range(30)])
+    A = rng.normal(size=(30, 3, 3))
+    S = A @ np.swapaxes(A, 1, 2) + 0.5 * np.eye(3)
+    R = elements.closest_rotation(Q @ S)                    # polar factor of Q S is Q
+    assert _rel(R, Q) < 1e-12
+    F = rng.normal(size=(30, 3, 3))                        # some with det F < 0
+    R = elements.closest_rotation(F)
+    assert np.max(np.abs(R @ np.swapaxes(R, 1, 2) - np.eye(3))) < 1e-13
+    assert np.allclose(np.linalg.det(R), 1.0, atol=1e-13)
+    best = np.einsum("eij,eij->e", R, F)
+    for s in range(300):                                  # no rotation does better
+        T = _rot(s + 100)
+        assert np.all(np.einsum("ij,eij->e", T, F) <= best + 1e-12)
+
+
 def _random_tris(n, seed, stretch=0.2):
     rng = np.random.default_rng(seed)
     base = np.array([[0, 0, 0], [1, 0, 0], [0.2, 0.9, 0]], dtype=np.float64) * 0.01
