@@ -15,6 +15,11 @@ from __future__ import annotations
 import numpy as np
 
 
+# Every tetrahedral element kind: Stable Neo-Hookean, classic Neo-Hookean,
+# Saint Venant-Kirchhoff, fixed co-rotational, ARAP (scenegen numbering).
+TET_KINDS = (0, 3, 4, 5, 6)
+
+
 def lame(young, poisson):
     """(mu, lambda) of isotropic linear elasticity."""
     young = np.asarray(young, dtype=np.float64)
@@ -43,7 +48,7 @@ def lumped_mass(scene):
     """Per-node mass: sum over tets of rho V/4 and over triangles of rho h A/3."""
     m = np.zeros(scene.n_nodes)
     for es in scene.energies:
-        if es.kind == 0:
+        if es.kind in TET_KINDS:
             V = tet_volume(scene.X[es.conn])
             np.add.at(m, es.conn.ravel(), np.repeat(es.density * V / 4.0, 4))
         elif es.kind == 1:

@@ -423,6 +423,20 @@ def test_hinge_derivatives():
 # ----------------------------------------------------------------------------
 # inertia, masses
 # ----------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", [sg.SNH_TET4, sg.NH_TET4, sg.STVK_TET4, sg.FCR_TET4,
+                                  sg.ARAP_TET4])
+def test_tet_masses_every_material(kind):
+    """Mass does not depend on the material: every tet kind lumps rho V / 4,
+    so a box of side L carries rho L^3, split equally among a tet's nodes."""
+    s = sg.tet_cube_scene(3, h=0.01, seed=1, kind=kind)
+    m = rest.lumped_mass(s)
+    assert np.sum(m) == pytest.approx(1000.0 * (0.03) ** 3, rel=1e-12)
+    assert np.all(m > 0)
+    # and node by node the same as the Stable Neo-Hookean box
+    ref = rest.lumped_mass(sg.tet_cube_scene(3, h=0.01, seed=1))
+    assert np.array_equal(m, ref)
+
+
 def test_inertia_and_masses():
     s = sg.tet_cube_scene(3, h=0.01, seed=1)
     m = rest.lumped_mass(s)
