@@ -59,11 +59,16 @@ typedef enum {
                             refinement correction in float64 */
 } symx_precision;
 
-/* Element energies (the paper's App. B and Eq. 13). */
+/* Element energies (the paper's App. B and Eq. 13).  Tets use E = V psi(F)
+ * with F = Ds Dm^-1 and Lame parameters from (young, poisson). */
 typedef enum {
-  SYMX_SNH_TET4 = 0,   /* Stable Neo-Hookean, linear tet: E = V psi(F), 4 nodes  */
+  SYMX_SNH_TET4 = 0,   /* Stable Neo-Hookean, linear tet, 4 nodes                */
   SYMX_STVK_TRI3 = 1,  /* St. Venant-Kirchhoff membrane triangle, 3 nodes        */
-  SYMX_HINGE4 = 2      /* quadratic bending hinge (edge v0-v1, wings v2, v3)     */
+  SYMX_HINGE4 = 2,     /* quadratic bending hinge (edge v0-v1, wings v2, v3)     */
+  SYMX_NH_TET4 = 3,    /* classic Neo-Hookean (needs det F > 0)                  */
+  SYMX_STVK_TET4 = 4,  /* St. Venant-Kirchhoff tet                               */
+  SYMX_FCR_TET4 = 5,   /* fixed co-rotational, rotation R lagged per time step   */
+  SYMX_ARAP_TET4 = 6   /* as-rigid-as-possible + volume term, R lagged           */
 } symx_energy_kind;
 
 /* Evaluation flags (the three levels of Sec. 5.2, plus options). */
@@ -205,6 +210,17 @@ symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double*
 symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
                              const symx_step_params* params, symx_step_report* report);
 
+/* Lagged rotations of the fixed co-rotational and ARAP sets (Sec. 6.1: the
+ * rotation is held constant over a time step): for every such element, R is
+ * the rotation closest to its deformation gradient at positions x_dev (device
+ * N x 3 float64), i.e. the maximiser of tr(R^T F) over rotations (from the
+ * SVD of F, with the sign of the smallest singular value's direction chosen
+ * so that det R = 1).  A new mesh starts from the rotations at rest (R = I);
+ * symx_newton_step takes them at x(t) itself; symx_assemble_bsr and
+ * symx_eval_derivatives use the current ones.  No-op for meshes without such
+ * sets. */
+symx_status symx_mesh_update_rotations(symx_mesh mesh, const double* x_dev);
+
 /* Kernel timing for measurement: with profiling on, every kernel launch of
  * the mesh carries start/stop HIP events on the mesh's stream
  * (hipExtLaunchKernelGGL), which time the kernel itself.  set_profiling
@@ -259,7 +275,9 @@ symx_status symx_server_poll(symx_server server, int64_t ticket, int32_t wait, d
                              double* v_out, symx_step_report* report, double* times_ms);
 symx_status symx_server_get_stats(symx_server server, symx_server_stats* stats);
 /* Device footprint the server charges against its budget for a scene solved
- * at `precision` (an upper bound of the mesh and Newton workspace). */
+ * at `precision` (an upper bound of the mesh and Newton workspace, with the
+ * records of per-element projection; a request without projection is charged
+ * that much less). */
 symx_status symx_server_estimate_bytes(const symx_mesh_desc* scene, int32_t precision,
                                        uint64_t* bytes);
 /* Waits for running requests, abandons queued ones, frees the server. */

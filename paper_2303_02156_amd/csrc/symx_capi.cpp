@@ -21,7 +21,7 @@ symx_status server_submit(Server* s, const symx_mesh_desc* d, const double* x, c
 symx_status server_poll(Server* s, int64_t ticket, int32_t wait, double* x_out, double* v_out,
                         symx_step_report* rep, double* times_ms);
 void server_stats(Server* s, symx_server_stats* out);
-size_t estimate_request_bytes(const symx_mesh_desc& d, int precision);
+size_t estimate_request_bytes(const symx_mesh_desc& d, int precision, bool project);
 }  // namespace symxi
 
 struct symx_server_s {
@@ -63,6 +63,8 @@ void mesh_free(Mesh* m) {
   for (SetHost& s : m->sets) {
     dev_free(m->pool, s.d_prm64);
     dev_free(m->pool, s.d_prm32);
+    dev_free(m->pool, s.d_rot64);
+    dev_free(m->pool, s.d_rot32);
   }
   pinned_free(m->pool, m->pinned);
   m->topo.reset();  // frees the pattern unless a cache or another mesh holds it
@@ -261,6 +263,16 @@ symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
   GUARD_END
 }
 
+symx_status symx_mesh_update_rotations(symx_mesh mesh, const double* x_dev) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh) || !x_dev) return SYMX_ERR_INVALID_ARG;
+  Mesh& m = *mesh->m;
+  symx_status st = launch_lagged_rotations(m, x_dev);
+  if (st != SYMX_OK) return st;
+  return hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize");
+  GUARD_END
+}
+
 symx_status symx_mesh_set_profiling(symx_mesh mesh, int32_t enable) {
   GUARD_BEGIN
   if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
@@ -366,7 +378,7 @@ symx_status symx_server_estimate_bytes(const symx_mesh_desc* scene, int32_t prec
     set_error("invalid scene descriptor");
     return SYMX_ERR_INVALID_ARG;
   }
-  *bytes = estimate_request_bytes(*scene, precision);
+  *bytes = estimate_request_bytes(*scene, precision, true);
   return SYMX_OK;
   GUARD_END
 }

@@ -38,7 +38,14 @@ struct SetDev {
   const double* prm64;   // n_elem * kPrm, or kPrm when uniform
   const float* prm32;
   int prm_stride;        // kPrm, or 0 when every element has the same parameters
+  const double* rot64;   // lagged-rotation materials: n_elem x 9 (row-major R), else null
+  const float* rot32;
 };
+
+// Fixed co-rotational and ARAP tets carry a lagged rotation per element.
+inline bool kind_has_rotation(int kind) {
+  return kind == SYMX_FCR_TET4 || kind == SYMX_ARAP_TET4;
+}
 
 struct SetsDev {
   SetDev s[kMaxSets];
@@ -197,6 +204,8 @@ struct SetHost {
   const int4* d_conn = nullptr;     // the topology's
   double* d_prm64 = nullptr;
   float* d_prm32 = nullptr;
+  double* d_rot64 = nullptr;        // lagged rotations (FCR / ARAP sets)
+  float* d_rot32 = nullptr;
 };
 
 struct Workspace;  // Newton / PCG buffers (symx_newton.cpp)
@@ -306,6 +315,9 @@ symx_status launch_incidence_positions(Mesh& m, int* inc_pos);
 // Projected element rows into the incidence records (n_inc x 32, precision).
 symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precision,
                                             const int* inc_pos, void* rows);
+// Lagged rotations of every fixed co-rotational / ARAP set: the rotation
+// closest to each element's deformation gradient at positions x.
+symx_status launch_lagged_rotations(Mesh& m, const double* x);
 // Total energy (float64 sum of per-element energies in `precision`).
 symx_status launch_energy(Mesh& m, const double* x, const double* x_tilde, double dt,
                           int precision, double* E_dev);

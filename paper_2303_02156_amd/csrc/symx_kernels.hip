@@ -164,10 +164,241 @@ __device__ __forceinline__ void fill_hinge(const SetDev& S, int64_t e, const Rel
   in[17] = ld_prm(P, st, e, 5);
 }
 
+// Lagged rotation of element e (row-major) into the 9 inputs after the
+// 26-input tet layout.  Relabelling the nodes does not change F, so R is the
+// same for every node order.
+template <typename T>
+__device__ __forceinline__ const T* rot_ptr(const SetDev& S);
+template <>
+__device__ __forceinline__ const float* rot_ptr<float>(const SetDev& S) { return S.rot32; }
+template <>
+__device__ __forceinline__ const double* rot_ptr<double>(const SetDev& S) { return S.rot64; }
+
+// Inputs of the generated functions of kind KIND for element e, nodes in
+// order R (largest layout: 35 inputs).
+constexpr int kMaxIn = 35;
+template <typename T, int KIND>
+__device__ __forceinline__ void elem_inputs(const SetDev& S, int64_t e, const Relabel& R,
+                                            const double* __restrict__ x,
+                                            const double* __restrict__ X, T* in) {
+  if constexpr (KIND == SYMX_STVK_TRI3) {
+    fill_solid<T, 3>(S, e, R, x, X, in);
+  } else if constexpr (KIND == SYMX_HINGE4) {
+    fill_hinge<T>(S, e, R, x, in);
+  } else {
+    fill_solid<T, 4>(S, e, R, x, X, in);
+    if constexpr (KIND == SYMX_FCR_TET4 || KIND == SYMX_ARAP_TET4) {
+      const T* r = rot_ptr<T>(S) + 9 * e;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) in[26 + c] = r[c];
+    }
+  }
+}
+
+// The generated functions of kind KIND, by evaluation level.
+#define SYMX_GEN_DISPATCH(LEVEL)                                                   \
+  template <typename T, int KIND>                                                 \
+  __device__ __forceinline__ void gen_##LEVEL(const T* in, T* out) {              \
+    if constexpr (KIND == SYMX_SNH_TET4) snh_tet4_##LEVEL<T>(in, out);            \
+    else if constexpr (KIND == SYMX_STVK_TRI3) stvk_tri3_##LEVEL<T>(in, out);     \
+    else if constexpr (KIND == SYMX_HINGE4) hinge4_##LEVEL<T>(in, out);           \
+    else if constexpr (KIND == SYMX_NH_TET4) nh_tet4_##LEVEL<T>(in, out);         \
+    else if constexpr (KIND == SYMX_STVK_TET4) stvk_tet4_##LEVEL<T>(in, out);     \
+    else if constexpr (KIND == SYMX_FCR_TET4) fcr_tet4_##LEVEL<T>(in, out);       \
+    else arap_tet4_##LEVEL<T>(in, out);                                           \
+  }
+SYMX_GEN_DISPATCH(s_E)
+SYMX_GEN_DISPATCH(s_EgH)
+SYMX_GEN_DISPATCH(row0_g)
+SYMX_GEN_DISPATCH(row0_gHoff)
+#undef SYMX_GEN_DISPATCH
+
+// Kinds compiled into a kernel that meets elements of several sets: bit k
+// set for kind k.  f(std::integral_constant<int, KIND>) runs for the
+// element's kind.
+constexpr uint32_t kKindsAll = 0x7Fu;
+constexpr uint32_t kKindsSnh = 1u << SYMX_SNH_TET4;
+constexpr uint32_t kKindsShell = (1u << SYMX_SNH_TET4) | (1u << SYMX_STVK_TRI3) | (1u << SYMX_HINGE4);
+template <uint32_t KMASK, int KIND = 0, typename F>
+__device__ __forceinline__ void with_kind(int kind, F&& f) {
+  if constexpr (KIND < 7) {
+    if constexpr ((KMASK >> KIND) & 1u) {
+      if (kind == KIND) {
+        f(std::integral_constant<int, KIND>{});
+        return;
+      }
+    }
+    with_kind<KMASK, KIND + 1>(kind, f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// lagged rotations (fixed co-rotational and ARAP tets)
+// ---------------------------------------------------------------------------
+
+// One Jacobi rotation of the symmetric 3x3 matrix a in the (P, Q) plane,
+// accumulated into the columns of v: tan(phi) = t is the root of smaller
+// magnitude of t^2 + 2 t cot(2 phi) - 1 = 0, cot(2 phi) = (a_QQ - a_PP) / 2a_PQ.
+template <int P, int Q>
+__device__ __forceinline__ void jacobi3_rotate(double (&a)[3][3], double (&v)[3][3]) {
+  constexpr int Rr = 3 - P - Q;  // the third index
+  const double apq = a[P][Q];
+  if (apq == 0.0) return;
+  const double d = a[Q][Q] - a[P][P];
+  const double t = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
+  const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+  a[P][P] -= t * apq;
+  a[Q][Q] += t * apq;
+  a[P][Q] = a[Q][P] = 0.0;
+  const double arp = a[Rr][P], arq = a[Rr][Q];
+  a[Rr][P] = a[P][Rr] = c * arp - s * arq;
+  a[Rr][Q] = a[Q][Rr] = s * arp + c * arq;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double vp = v[r][P], vq = v[r][Q];
+    v[r][P] = c * vp - s * vq;
+    v[r][Q] = s * vp + c * vq;
+  }
+}
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// R = argmax tr(R^T F) over rotations (the rotation factor of the polar
+// decomposition, with the sign of det F put on the smallest singular value).
+// F^T F = V diag(s^2) V^T by cyclic Jacobi, columns sorted by decreasing s;
+// u1 = F v1 / |F v1|, u2 = F v2 made orthogonal to u1 and normalised,
+// u3 = u1 x u2, v3 = v1 x v2, so U and V are proper rotations and R = U V^T.
+// Rank-deficient F (non-unique maximiser) takes any completion; F = 0
+// gives R = I.
+__device__ void closest_rotation3(const double (&F)[3][3], double (&R)[3][3]) {
+  double a[3][3], v[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      a[i][j] = F[0][i] * F[0][j] + F[1][i] * F[1][j] + F[2][i] * F[2][j];
+      v[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (!(off > 1e-34 * dia)) break;
+    jacobi3_rotate<0, 1>(a, v);
+    jacobi3_rotate<0, 2>(a, v);
+    jacobi3_rotate<1, 2>(a, v);
+  }
+  // the two largest eigenvalues' columns
+  int i1 = 0, i2 = 1, i3 = 2;
+  auto swap_if = [&](int& p, int& q) {
+    const double lp = p == 0 ? a[0][0] : p == 1 ? a[1][1] : a[2][2];
+    const double lq = q == 0 ? a[0][0] : q == 1 ? a[1][1] : a[2][2];
+    if (lq > lp) {
+      const int t = p;
+      p = q;
+      q = t;
+    }
+  };
+  swap_if(i1, i2);
+  swap_if(i1, i3);
+  swap_if(i2, i3);
+  double v1[3], v2[3], v3[3], u1[3], u2[3], u3[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    v1[r] = i1 == 0 ? v[r][0] : i1 == 1 ? v[r][1] : v[r][2];
+    v2[r] = i2 == 0 ? v[r][0] : i2 == 1 ? v[r][1] : v[r][2];
+  }
+  cross3(v1, v2, v3);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    u1[r] = F[r][0] * v1[0] + F[r][1] * v1[1] + F[r][2] * v1[2];
+    u2[r] = F[r][0] * v2[0] + F[r][1] * v2[1] + F[r][2] * v2[2];
+  }
+  const double n1 = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+  if (!(n1 > 0.0)) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) R[i][j] = i == j ? 1.0 : 0.0;
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) u1[r] /= n1;
+  const double p = u1[0] * u2[0] + u1[1] * u2[1] + u1[2] * u2[2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) u2[r] -= p * u1[r];
+  double n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  if (!(n2 > 1e-300)) {
+    // rank one: any unit vector orthogonal to u1
+    const double ax = fabs(u1[0]), ay = fabs(u1[1]), az = fabs(u1[2]);
+    const double e[3] = {ax <= ay && ax <= az ? 1.0 : 0.0, ay < ax && ay <= az ? 1.0 : 0.0,
+                         az < ax && az < ay ? 1.0 : 0.0};
+    cross3(u1, e, u2);
+    n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) u2[r] /= n2;
+  cross3(u1, u2, u3);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) R[i][j] = u1[i] * v1[j] + u2[i] * v2[j] + u3[i] * v3[j];
+}
+
+// One lane per element: F = Ds Dm^-1 at positions x (node order of the
+// connectivity), R of F row-major into rot64 and its float copy into rot32.
+__global__ __launch_bounds__(256) void k_lagged_rotations(int64_t n, const int4* __restrict__ conn,
+                                                          const double* __restrict__ x,
+                                                          const double* __restrict__ X,
+                                                          double* __restrict__ rot64,
+                                                          float* __restrict__ rot32) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const int4 c = conn[e];
+    const int nd[4] = {c.x, c.y, c.z, c.w};
+    double Ds[3][3], Dm[3][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        Ds[r][b] = x[3 * (int64_t)nd[b + 1] + r] - x[3 * (int64_t)nd[0] + r];
+        Dm[r][b] = X[3 * (int64_t)nd[b + 1] + r] - X[3 * (int64_t)nd[0] + r];
+      }
+    // Dm^-1 = adj(Dm) / det(Dm)
+    double Mi[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3, i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+        Mi[i][j] = Dm[j1][i1] * Dm[j2][i2] - Dm[j1][i2] * Dm[j2][i1];
+      }
+    const double det = Dm[0][0] * Mi[0][0] + Dm[0][1] * Mi[1][0] + Dm[0][2] * Mi[2][0];
+    double F[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        F[i][j] = (Ds[i][0] * Mi[0][j] + Ds[i][1] * Mi[1][j] + Ds[i][2] * Mi[2][j]) / det;
+    double R[3][3];
+    closest_rotation3(F, R);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        rot64[9 * e + 3 * i + j] = R[i][j];
+        rot32[9 * e + 3 * i + j] = float(R[i][j]);
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // element-wise energy (line-search level) -> partial sums
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int KIND>
 __global__ __launch_bounds__(256) void k_energy_set(SetDev S, const double* __restrict__ x,
                                                     const double* __restrict__ X,
                                                     double* __restrict__ partials,
@@ -177,18 +408,10 @@ __global__ __launch_bounds__(256) void k_energy_set(SetDev S, const double* __re
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < S.n_elem;
        e += (int64_t)gridDim.x * 256) {
     const Relabel R = identity_order(S.conn[e]);
-    T in[26];
+    T in[kMaxIn];
     T out[1];
-    if (S.kind == SYMX_SNH_TET4) {
-      fill_solid<T, 4>(S, e, R, x, X, in);
-      snh_tet4_s_E<T>(in, out);
-    } else if (S.kind == SYMX_STVK_TRI3) {
-      fill_solid<T, 3>(S, e, R, x, X, in);
-      stvk_tri3_s_E<T>(in, out);
-    } else {
-      fill_hinge<T>(S, e, R, x, in);
-      hinge4_s_E<T>(in, out);
-    }
+    elem_inputs<T, KIND>(S, e, R, x, X, in);
+    gen_s_E<T, KIND>(in, out);
     acc += double(out[0]);
   }
   double s = block_sum_256(acc, sh);
@@ -232,18 +455,10 @@ __global__ __launch_bounds__(128) void k_elem_eval(SetDev S, const double* __res
   for (int64_t e = (int64_t)blockIdx.x * 128 + threadIdx.x; e < S.n_elem;
        e += (int64_t)gridDim.x * 128) {
     const Relabel R = identity_order(S.conn[e]);
-    T in[26];
+    T in[kMaxIn];
     T out[1 + D + D * D];
-    if (KIND == SYMX_SNH_TET4) {
-      fill_solid<T, 4>(S, e, R, x, X, in);
-      snh_tet4_s_EgH<T>(in, out);
-    } else if (KIND == SYMX_STVK_TRI3) {
-      fill_solid<T, 3>(S, e, R, x, X, in);
-      stvk_tri3_s_EgH<T>(in, out);
-    } else {
-      fill_hinge<T>(S, e, R, x, in);
-      hinge4_s_EgH<T>(in, out);
-    }
+    elem_inputs<T, KIND>(S, e, R, x, X, in);
+    gen_s_EgH<T, KIND>(in, out);
     if (Eo) Eo[e] = out[0];
     if (go) {
 #pragma unroll
@@ -476,18 +691,10 @@ __device__ __forceinline__ void elem_rows_projected(SetDev S, const double* __re
   for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < S.n_elem;
        e += (int64_t)gridDim.x * 64) {
     const Relabel R0 = identity_order(S.conn[e]);
-    T in[26];
+    T in[kMaxIn];
     T out[1 + D + D * D];
-    if (KIND == SYMX_SNH_TET4) {
-      fill_solid<T, 4>(S, e, R0, x, X, in);
-      snh_tet4_s_EgH<T>(in, out);
-    } else if (KIND == SYMX_STVK_TRI3) {
-      fill_solid<T, 3>(S, e, R0, x, X, in);
-      stvk_tri3_s_EgH<T>(in, out);
-    } else {
-      fill_hinge<T>(S, e, R0, x, in);
-      hinge4_s_EgH<T>(in, out);
-    }
+    elem_inputs<T, KIND>(S, e, R0, x, X, in);
+    gen_s_EgH<T, KIND>(in, out);
     const T* g = out + 1;
     const T* h = out + 1 + D;
     // record of incidence (e, a): g_a, then H(a_i, b_k) for b = the other
@@ -618,30 +825,25 @@ struct RowArgs {
 };
 
 // Gradient row of one incidence (element e seen from its local node a).
-template <typename T>
+template <typename T, uint32_t KMASK>
 __device__ __forceinline__ void incidence_grad(const RowArgs<T>& A, uint32_t code, T* out) {
   const int si = inc_set(code);
   const int a = inc_local(code);
   const int64_t e = inc_elem(code);
   const SetDev& S = A.sets.s[si];
   const Relabel R = relabel(S.conn[e], a);
-  T in[26];
-  if (S.kind == SYMX_SNH_TET4) {
-    fill_solid<T, 4>(S, e, R, A.x, A.X, in);
-    snh_tet4_row0_g<T>(in, out);
-  } else if (S.kind == SYMX_HINGE4) {
-    fill_hinge<T>(S, e, R, A.x, in);
-    hinge4_row0_g<T>(in, out);
-  } else {
-    fill_solid<T, 3>(S, e, R, A.x, A.X, in);
-    stvk_tri3_row0_g<T>(in, out);
-  }
+  with_kind<KMASK>(S.kind, [&](auto kc) {
+    constexpr int KIND = decltype(kc)::value;
+    T in[kMaxIn];
+    elem_inputs<T, KIND>(S, e, R, A.x, A.X, in);
+    gen_row0_g<T, KIND>(in, out);
+  });
 }
 
 // Gradient-only row assembly: one lane per incidence of the batch's rows, then
 // one lane per row sums its incidences in (set, element id) order and adds
 // inertia and Dirichlet.
-template <typename T>
+template <typename T, uint32_t KMASK>
 __global__ __launch_bounds__(kRowWG) void k_row_gradient(RowArgs<T> A) {
   __shared__ T st[3][kRowWG];
   __shared__ int s_inc[kRowWG + 1];
@@ -655,7 +857,7 @@ __global__ __launch_bounds__(kRowWG) void k_row_gradient(RowArgs<T> A) {
   const int nq = s_inc[nrows];
   if (t < nq) {
     T out[3];
-    incidence_grad<T>(A, A.inc_code[q0 + t], out);
+    incidence_grad<T, KMASK>(A, A.inc_code[q0 + t], out);
 #pragma unroll
     for (int v = 0; v < 3; ++v) st[v][t] = out[v];
   }
@@ -709,36 +911,36 @@ __device__ __forceinline__ void inverse3(const double a[9], double r[9]) {
 
 // Off-diagonal part of one incidence's Hessian block row (recompute path):
 // out[0..2] gradient of node a, out[3 + 9 i + 3 (b-1) + k] entry (a_i, node b
-// of the relabelled order, coord k) for b = 1, 2, 3.
-template <typename T>
+// of the relabelled order, coord k) for b = 1, 2, 3 (zero for a triangle's
+// missing node).
+template <typename T, uint32_t KMASK>
 __device__ __forceinline__ void incidence_row_off(const RowArgs<T>& A, uint32_t code, T* out) {
   const int si = inc_set(code);
   const int a = inc_local(code);
   const int64_t e = inc_elem(code);
   const SetDev& S = A.sets.s[si];
   const Relabel R = relabel(S.conn[e], a);
-  T in[26];
-  if (S.kind == SYMX_SNH_TET4) {
-    fill_solid<T, 4>(S, e, R, A.x, A.X, in);
-    snh_tet4_row0_gHoff<T>(in, out);
-  } else if (S.kind == SYMX_HINGE4) {
-    fill_hinge<T>(S, e, R, A.x, in);
-    hinge4_row0_gHoff<T>(in, out);
-  } else {
-    fill_solid<T, 3>(S, e, R, A.x, A.X, in);
-    T o[21];
-    stvk_tri3_row0_gHoff<T>(in, o);
-    out[0] = o[0];
-    out[1] = o[1];
-    out[2] = o[2];
+  with_kind<KMASK>(S.kind, [&](auto kc) {
+    constexpr int KIND = decltype(kc)::value;
+    T in[kMaxIn];
+    elem_inputs<T, KIND>(S, e, R, A.x, A.X, in);
+    if constexpr (KIND == SYMX_STVK_TRI3) {
+      T o[21];
+      gen_row0_gHoff<T, KIND>(in, o);
+      out[0] = o[0];
+      out[1] = o[1];
+      out[2] = o[2];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+      for (int i = 0; i < 3; ++i) {
 #pragma unroll
-      for (int v = 0; v < 6; ++v) out[3 + 9 * i + v] = o[3 + 6 * i + v];
+        for (int v = 0; v < 6; ++v) out[3 + 9 * i + v] = o[3 + 6 * i + v];
 #pragma unroll
-      for (int v = 6; v < 9; ++v) out[3 + 9 * i + v] = T(0);
+        for (int v = 6; v < 9; ++v) out[3 + 9 * i + v] = T(0);
+      }
+    } else {
+      gen_row0_gHoff<T, KIND>(in, out);
     }
-  }
+  });
 }
 
 // Row assembly for translation-invariant element energies (all three kinds:
@@ -757,7 +959,9 @@ __device__ __forceinline__ void incidence_row_off(const RowArgs<T>& A, uint32_t 
 //     of each diagonal block when requested.
 // FROM_REC: step 1 reads each incidence's row from its record in the
 // incidence-ordered buffer (projected path) instead of evaluating it.
-template <typename T, bool WANT_G, bool FROM_REC>
+// KMASK: the element kinds compiled in (kKindsSnh for the common single-
+// material mesh keeps the kernel small).
+template <typename T, bool WANT_G, bool FROM_REC, uint32_t KMASK>
 __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   constexpr int NV = 30;
   __shared__ T st[NV][kRowWG];
@@ -785,7 +989,7 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) out[v] = rec[v];
     } else {
-      incidence_row_off<T>(A, A.inc_code[q0 + t], out);
+      incidence_row_off<T, KMASK>(A, A.inc_code[q0 + t], out);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) st[v][t] = out[v];
@@ -1158,6 +1362,21 @@ __global__ __launch_bounds__(256) void k_check_finite(int64_t n, const double* _
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+// Host side of the kind dispatch: f(std::integral_constant<int, KIND>) for a
+// set of kind `kind` (validated at mesh creation).
+template <typename F>
+static void host_with_kind(int kind, F&& f) {
+  switch (kind) {
+    case SYMX_SNH_TET4: f(std::integral_constant<int, SYMX_SNH_TET4>{}); break;
+    case SYMX_STVK_TRI3: f(std::integral_constant<int, SYMX_STVK_TRI3>{}); break;
+    case SYMX_HINGE4: f(std::integral_constant<int, SYMX_HINGE4>{}); break;
+    case SYMX_NH_TET4: f(std::integral_constant<int, SYMX_NH_TET4>{}); break;
+    case SYMX_STVK_TET4: f(std::integral_constant<int, SYMX_STVK_TET4>{}); break;
+    case SYMX_FCR_TET4: f(std::integral_constant<int, SYMX_FCR_TET4>{}); break;
+    default: f(std::integral_constant<int, SYMX_ARAP_TET4>{}); break;
+  }
+}
+
 static int grid_for(int64_t work, int per_block, int cap = 16384) {
   int64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -1178,12 +1397,15 @@ symx_status launch_energy(Mesh& m, const double* x, const double* xt, double dt,
   int off = 0;
   for (int s = 0; s < sd.n; ++s) {
     const int G = grid_for(sd.s[s].n_elem, 256, 8192);
-    if (precision == SYMX_F32)
-      SYMX_LAUNCH(m, PNAME, k_energy_set<float>, dim3(G), dim3(256), 0, sd.s[s], x, m.X,
-                         m.partials + off, m.nonfinite);
-    else
-      SYMX_LAUNCH(m, PNAME, k_energy_set<double>, dim3(G), dim3(256), 0, sd.s[s], x, m.X,
-                         m.partials + off, m.nonfinite);
+    host_with_kind(sd.s[s].kind, [&](auto kc) {
+      constexpr int KIND = decltype(kc)::value;
+      if (precision == SYMX_F32)
+        SYMX_LAUNCH(m, PNAME, (k_energy_set<float, KIND>), dim3(G), dim3(256), 0, sd.s[s], x,
+                    m.X, m.partials + off, m.nonfinite);
+      else
+        SYMX_LAUNCH(m, PNAME, (k_energy_set<double, KIND>), dim3(G), dim3(256), 0, sd.s[s], x,
+                    m.X, m.partials + off, m.nonfinite);
+    });
     LAUNCH_CHECK("k_energy_set");
     off += G;
   }
@@ -1207,19 +1429,11 @@ static symx_status elem_eval_t(Mesh& m, int set, const double* x, void* E, void*
   const SetDev& S = sd.s[set];
   const int G = grid_for(S.n_elem, 128, 65535);
   if (S.n_elem == 0) return SYMX_OK;
-  switch (S.kind) {
-    case SYMX_SNH_TET4:
-      SYMX_LAUNCH(m, PNAME, (k_elem_eval<T, SYMX_SNH_TET4>), dim3(G), dim3(128), 0, S, x,
-                         m.X, (T*)E, (T*)g, (T*)H);
-      break;
-    case SYMX_STVK_TRI3:
-      SYMX_LAUNCH(m, PNAME, (k_elem_eval<T, SYMX_STVK_TRI3>), dim3(G), dim3(128), 0, S, x,
-                         m.X, (T*)E, (T*)g, (T*)H);
-      break;
-    default:
-      SYMX_LAUNCH(m, PNAME, (k_elem_eval<T, SYMX_HINGE4>), dim3(G), dim3(128), 0, S, x,
-                         m.X, (T*)E, (T*)g, (T*)H);
-  }
+  host_with_kind(S.kind, [&](auto kc) {
+    constexpr int KIND = decltype(kc)::value;
+    SYMX_LAUNCH(m, PNAME, (k_elem_eval<T, KIND>), dim3(G), dim3(128), 0, S, x, m.X, (T*)E,
+                (T*)g, (T*)H);
+  });
   LAUNCH_CHECK("k_elem_eval");
   return SYMX_OK;
 }
@@ -1229,6 +1443,19 @@ symx_status launch_elem_eval(Mesh& m, int set, const double* x, int want, int pr
   (void)want;
   if (precision == SYMX_F32) return elem_eval_t<float>(m, set, x, E, g, H);
   return elem_eval_t<double>(m, set, x, E, g, H);
+}
+
+symx_status launch_lagged_rotations(Mesh& m, const double* x) {
+  const char* PNAME = "lagged_rotations";
+  const SetsDev sd = m.sets_dev();
+  for (int s = 0; s < sd.n; ++s) {
+    const SetDev& S = sd.s[s];
+    if (!kind_has_rotation(S.kind) || S.n_elem == 0) continue;
+    SYMX_LAUNCH(m, PNAME, k_lagged_rotations, dim3(grid_for(S.n_elem, 256)), dim3(256), 0,
+                S.n_elem, S.conn, x, m.X, m.sets[s].d_rot64, m.sets[s].d_rot32);
+    LAUNCH_CHECK("k_lagged_rotations");
+  }
+  return SYMX_OK;
 }
 
 symx_status launch_incidence_positions(Mesh& m, int* inc_pos) {
@@ -1256,29 +1483,15 @@ symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precis
     first += S.n_elem * S.k;
     if (S.n_elem == 0) continue;
     const int G = grid_for(S.n_elem, 64, 65535);
-    if (precision == SYMX_F32) {
-      float* r = (float*)rows;
-      if (S.kind == SYMX_SNH_TET4)
-        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected32<SYMX_SNH_TET4>, dim3(G), dim3(64), 0, S, x,
-                    m.X, ip, r, 30, 2e-7f);
-      else if (S.kind == SYMX_STVK_TRI3)
-        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected32<SYMX_STVK_TRI3>, dim3(G), dim3(64), 0, S, x,
-                    m.X, ip, r, 30, 2e-7f);
+    host_with_kind(S.kind, [&](auto kc) {
+      constexpr int KIND = decltype(kc)::value;
+      if (precision == SYMX_F32)
+        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected32<KIND>, dim3(G), dim3(64), 0, S, x, m.X, ip,
+                    (float*)rows, 30, 2e-7f);
       else
-        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected32<SYMX_HINGE4>, dim3(G), dim3(64), 0, S, x,
-                    m.X, ip, r, 30, 2e-7f);
-    } else {
-      double* r = (double*)rows;
-      if (S.kind == SYMX_SNH_TET4)
-        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected64<SYMX_SNH_TET4>, dim3(G), dim3(64), 0, S, x,
-                    m.X, ip, r, 30, 1e-15);
-      else if (S.kind == SYMX_STVK_TRI3)
-        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected64<SYMX_STVK_TRI3>, dim3(G), dim3(64), 0, S,
-                    x, m.X, ip, r, 30, 1e-15);
-      else
-        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected64<SYMX_HINGE4>, dim3(G), dim3(64), 0, S, x,
-                    m.X, ip, r, 30, 1e-15);
-    }
+        SYMX_LAUNCH(m, PNAME, k_elem_rows_projected64<KIND>, dim3(G), dim3(64), 0, S, x, m.X, ip,
+                    (double*)rows, 30, 1e-15);
+    });
     LAUNCH_CHECK("k_elem_rows_projected");
   }
   return SYMX_OK;
@@ -1310,6 +1523,18 @@ symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim) 
   }
   LAUNCH_CHECK("k_project_psd");
   return SYMX_OK;
+}
+
+template <typename T, uint32_t KMASK>
+static void row_assemble_launch(Mesh& m, const char* PNAME, dim3 grid, dim3 block,
+                                const RowArgs<T>& A, bool want_g, bool want_H) {
+  if (want_H && want_g) {
+    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, false, KMASK>), grid, block, 0, A);
+  } else if (want_H) {
+    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, false, KMASK>), grid, block, 0, A);
+  } else {
+    SYMX_LAUNCH(m, PNAME, (k_row_gradient<T, KMASK>), grid, block, 0, A);
+  }
 }
 
 template <typename T>
@@ -1346,18 +1571,31 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   }
   const dim3 grid(m.n_batch), block(kRowWG);
   const char* PNAME = want_H ? (want_g ? "row_assemble_gH" : "row_assemble_H") : "row_assemble_g";
+  // Kernels compiled for the kinds the mesh holds keep their register count
+  // (and occupancy) at that of the heaviest kind present: one kind alone, the
+  // solid + shell kinds, or all kinds for any other mix.  The projected path
+  // reads records and evaluates no element.
+  uint32_t kinds = 0;
+  for (const SetHost& s : m.sets) kinds |= 1u << s.kind;
   if (inc_rows && want_H) {
     if (want_g)
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, true>), grid, block, 0, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, true, 0u>), grid, block, 0, A);
     else
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, true>), grid, block, 0, A);
-  } else if (want_H && want_g) {
-    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, false>), grid, block, 0, A);
-  } else if (want_H) {
-    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, false>), grid, block, 0, A);
-  } else {
-    SYMX_LAUNCH(m, PNAME, (k_row_gradient<T>), grid, block, 0, A);
-  }
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, true, 0u>), grid, block, 0, A);
+  } else if (kinds == kKindsSnh)
+    row_assemble_launch<T, kKindsSnh>(m, PNAME, grid, block, A, want_g, want_H);
+  else if ((kinds & ~kKindsShell) == 0)
+    row_assemble_launch<T, kKindsShell>(m, PNAME, grid, block, A, want_g, want_H);
+  else if (kinds == 1u << SYMX_NH_TET4)
+    row_assemble_launch<T, 1u << SYMX_NH_TET4>(m, PNAME, grid, block, A, want_g, want_H);
+  else if (kinds == 1u << SYMX_STVK_TET4)
+    row_assemble_launch<T, 1u << SYMX_STVK_TET4>(m, PNAME, grid, block, A, want_g, want_H);
+  else if (kinds == 1u << SYMX_FCR_TET4)
+    row_assemble_launch<T, 1u << SYMX_FCR_TET4>(m, PNAME, grid, block, A, want_g, want_H);
+  else if (kinds == 1u << SYMX_ARAP_TET4)
+    row_assemble_launch<T, 1u << SYMX_ARAP_TET4>(m, PNAME, grid, block, A, want_g, want_H);
+  else
+    row_assemble_launch<T, kKindsAll>(m, PNAME, grid, block, A, want_g, want_H);
   LAUNCH_CHECK("k_row_assemble");
   return SYMX_OK;
 }

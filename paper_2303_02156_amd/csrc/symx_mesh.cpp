@@ -75,6 +75,8 @@ SetsDev Mesh::sets_dev() const {
     d.s[s].prm64 = h.d_prm64;
     d.s[s].prm32 = h.d_prm32;
     d.s[s].prm_stride = h.uniform ? 0 : kPrm;
+    d.s[s].rot64 = h.d_rot64;
+    d.s[s].rot32 = h.d_rot32;
   }
   return d;
 }
@@ -111,7 +113,8 @@ static void parallel_chunks(int64_t n, int64_t min_chunk, F f) {
 }
 
 static int kind_nodes(int kind) {
-  return kind == SYMX_SNH_TET4 || kind == SYMX_HINGE4 ? 4 : kind == SYMX_STVK_TRI3 ? 3 : 0;
+  if (kind == SYMX_STVK_TRI3) return 3;
+  return kind >= SYMX_SNH_TET4 && kind <= SYMX_ARAP_TET4 ? 4 : 0;
 }
 
 // Element kind, count and connectivity of one energy set.  check_nodes: node
@@ -178,7 +181,7 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s,
     *mu = E / (2.0 * (1.0 + nu));
     *lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
   };
-  if (d.kind == SYMX_SNH_TET4 || d.kind == SYMX_STVK_TRI3) {
+  if (d.kind != SYMX_HINGE4) {
     if (!(d.poisson > -1.0 && d.poisson < 0.5)) {
       set_error("Poisson ratio must lie in (-1, 0.5)");
       return SYMX_ERR_INVALID_ARG;
@@ -192,7 +195,7 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s,
   }
   // rest measures, element masses, hinge weights
   std::atomic<int64_t> bad{-1};
-  if (d.kind == SYMX_SNH_TET4) {
+  if (s.k == 4 && d.kind != SYMX_HINGE4) {
     elem_mass.resize(s.n_elem);
     parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
       for (int64_t e = e0; e < e1; ++e) {
@@ -572,6 +575,14 @@ static symx_status upload_instance(Mesh& m) {
     p32[i].assign(s.prm.begin(), s.prm.end());
     TRY(upload(pool, m.stream, &s.d_prm64, s.prm.data(), s.prm.size()));
     TRY(upload(pool, m.stream, &s.d_prm32, p32[i].data(), p32[i].size()));
+    if (kind_has_rotation(s.kind)) {
+      // lagged rotations start at the identity (the rest state's rotation)
+      std::vector<double> r64(size_t(s.n_elem) * 9, 0.0);
+      for (int64_t e = 0; e < s.n_elem; ++e) r64[9 * e] = r64[9 * e + 4] = r64[9 * e + 8] = 1.0;
+      std::vector<float> r32(r64.begin(), r64.end());
+      TRY(upload(pool, m.stream, &s.d_rot64, r64.data(), r64.size()));
+      TRY(upload(pool, m.stream, &s.d_rot32, r32.data(), r32.size()));
+    }
   }
   TRY(upload<double>(pool, m.stream, &m.partials, nullptr, kMaxPartials));
   TRY(upload<double>(pool, m.stream, &m.scalars, nullptr, 64));

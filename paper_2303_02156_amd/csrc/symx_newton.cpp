@@ -244,6 +244,9 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
   auto at = [&](int slot) { return win[slot - D_ENERGY]; };
   bool bad = false;
   TRY(launch_x_tilde(m, w->x_t, w->v_t, dt, P.gravity, w->xt));
+  // lagged rotations (co-rotational and ARAP sets) are those of x(t) for the
+  // whole step
+  TRY(launch_lagged_rotations(m, w->x_t));
   TRY(hip_check(hipMemcpyAsync(w->xk, w->x_t, n * sizeof(double), hipMemcpyDeviceToDevice, m.stream),
                 "hipMemcpyAsync"));
   double r0 = -1.0, E0 = 0.0;

@@ -66,19 +66,23 @@ struct Request {
 }  // namespace
 
 // Device bytes a mesh and its Newton workspace need (upper bound from sizes).
-size_t estimate_request_bytes(const symx_mesh_desc& d, int precision) {
+// project: include the incidence-ordered records of per-element projection.
+size_t estimate_request_bytes(const symx_mesh_desc& d, int precision, bool project) {
   const size_t N = (size_t)d.n_nodes;
-  size_t pairs = N, inc = 0, elems = 0;
+  size_t pairs = N, inc = 0, elems = 0, rot_elems = 0;
   for (int s = 0; s < d.n_energies; ++s) {
     const int k = d.energies[s].kind == SYMX_STVK_TRI3 ? 3 : 4;
     pairs += (size_t)d.energies[s].n_elem * k * (k - 1);
     inc += (size_t)d.energies[s].n_elem * k;
     elems += (size_t)d.energies[s].n_elem;
+    if (kind_has_rotation(d.energies[s].kind)) rot_elems += (size_t)d.energies[s].n_elem;
   }
   const size_t vbytes = precision == SYMX_F64 ? 8 : 4;
   size_t b = 0;
   b += pairs * (9 * vbytes + 4 + 4 + 2 * 3);   // values, col_idx, contribution info/entries
   b += inc * 4 + elems * (16 + 2 * 8 * kPrm + 4 * 4);  // incidence codes, conn, params
+  b += rot_elems * 9 * (8 + 4);                // lagged rotations
+  if (project) b += inc * (kIncRec * vbytes + 4);  // projected records, their positions
   b += N * (3 * 8 + 8 + 1 + 4 * 4);            // X, mass, fixed, row/inc pointers
   b += N * 3 * 8 * 9 + N * 9 * 8;              // Newton workspace, Dinv
   b += N * 3 * 8 * 5;                          // PCG vectors (double worst case)
@@ -259,7 +263,7 @@ symx_status server_submit(Server* s, const symx_mesh_desc* d, const double* x, c
   r->x.assign(x, x + 3 * N);
   r->v.assign(v, v + 3 * N);
   r->params = *P;
-  r->bytes = estimate_request_bytes(*d, P->precision);
+  r->bytes = estimate_request_bytes(*d, P->precision, P->project != 0);
   if (r->bytes > s->budget) {
     set_error("request footprint exceeds the server's memory budget");
     return SYMX_ERR_BUDGET;

@@ -22,6 +22,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NONFIN
 SYMX_PENDING = 8
 SYMX_F64, SYMX_F32, SYMX_F32_REFINED = 0, 1, 2
 SYMX_SNH_TET4, SYMX_STVK_TRI3, SYMX_HINGE4 = 0, 1, 2
+SYMX_NH_TET4, SYMX_STVK_TET4, SYMX_FCR_TET4, SYMX_ARAP_TET4 = 3, 4, 5, 6
 SYMX_EVAL_E, SYMX_EVAL_GRAD, SYMX_EVAL_HESS, SYMX_PROJECT_PSD, SYMX_DIRICHLET = 1, 2, 4, 8, 16
 
 
@@ -88,6 +89,7 @@ EXPORTS = {
                                     C.POINTER(BsrView)]),
     "symx_newton_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(StepParams),
                                    C.POINTER(StepReport)]),
+    "symx_mesh_update_rotations": (C.c_int, [C.c_void_p, C.c_void_p]),
     "symx_mesh_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "symx_mesh_get_kernel_time": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double,
                                             C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -177,6 +179,10 @@ def symx_newton_step(h, x_dev, v_dev, params):
     rep = StepReport()
     st = load().symx_newton_step(h, x_dev, v_dev, C.byref(params), C.byref(rep))
     return st, rep
+
+
+def symx_mesh_update_rotations(h, x_dev):
+    _check(load().symx_mesh_update_rotations(h, x_dev), "symx_mesh_update_rotations")
 
 
 def symx_mesh_set_profiling(h, enable):
@@ -355,6 +361,10 @@ class Mesh:
             vals = t.empty((9, self.info.nnzb), dtype=dtype, device="cuda")
             _device_copy(vals.data_ptr(), view.values, vals.numel() * vals.element_size())
         return E, g, vals
+
+    def update_rotations(self, x):
+        """Lagged rotations of the co-rotational and ARAP sets taken at x."""
+        symx_mesh_update_rotations(self.handle, self._dev(x).data_ptr())
 
     def profile(self, enable=True):
         symx_mesh_set_profiling(self.handle, enable)
