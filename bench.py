@@ -332,6 +332,71 @@ def mixed_c3(symx, torch, steps=20):
             "dt_halvings": sum(r["dt_halvings"] for r in reps)}
 
 
+# Evaluation + assembly per Newton iteration on the material-comparison box
+# (Sec. 6.1: 307,623 DoF), in ms on the reference CPU (application timings
+# table); context only, another machine.
+PAPER_MATERIAL_MS = {"arap": 38.79, "fcr": 35.40, "stvk": 37.85, "nh": 35.83, "snh": 35.10}
+
+
+def materials_bench(symx, torch, reps=10):
+    """The five tet materials on the stretched box (40 x 40 x 60 cubes, 576,000
+    tets, 102,541 nodes): one E+g+H assembly in FP32 and FP64 (device events,
+    median of reps), and one FP32-refined Newton step from the stretched state
+    with lagged rotations taken at x(t)."""
+    import numpy as np
+    import scenegen as sg
+    kinds = {"snh": sg.SNH_TET4, "nh": sg.NH_TET4, "stvk": sg.STVK_TET4, "fcr": sg.FCR_TET4,
+             "arap": sg.ARAP_TET4}
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    out = {}
+    for name, kind in kinds.items():
+        scene = sg.stretched_box_scene(kind)
+        mesh = symx.Mesh(scene)
+        n_elem = scene.n_elements()
+        dt = scene.dt
+        x0 = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+        v0 = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+        xt = torch.tensor(scene.x0 + dt * scene.v0 + dt * dt * np.asarray(scene.gravity)[None, :],
+                          dtype=torch.float64, device="cuda")
+        g = torch.empty_like(x0)
+        mesh.update_rotations(x0)
+        row = {"elements": n_elem, "dof": 3 * scene.n_nodes}
+        for pname, prec in (("f32", symx.SYMX_F32), ("f64", symx.SYMX_F64)):
+            ms = []
+            for r in range(reps + 3):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                symx.symx_assemble_bsr(mesh.handle, x0.data_ptr(), xt.data_ptr(), dt, flags, prec,
+                                       g.data_ptr())
+                b.record()
+                b.synchronize()
+                if r >= 3:
+                    ms.append(a.elapsed_time(b))
+            m = statistics.median(ms)
+            row[f"assembly_ms_{pname}"] = round(m, 4)
+            row[f"melem_per_s_{pname}"] = round(n_elem / (m * 1e-3) / 1e6, 2)
+        x = x0.clone()
+        v = v0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rep = mesh.newton_step(x, v, symx.step_params(dt=dt, precision=symx.SYMX_F32_REFINED,
+                                                          max_pcg=500))
+        torch.cuda.synchronize()
+        row.update({"newton_ms_f32_refined": round((time.perf_counter() - t0) * 1e3, 2),
+                    "status": symx.STATUS[st], "newton_iters": rep.newton_iters,
+                    "pcg_iters": rep.pcg_iters,
+                    "rel_residual": rep.residual / max(rep.residual0, 1e-300),
+                    "paper_cpu_ms_per_newton_iter": PAPER_MATERIAL_MS[name]})
+        mesh.close()
+        log(f"material {name}: {row}")
+        out[name] = row
+    return {"workload": "stretched box: 40x40x60 cubes x 6 tets (576,000 tets, 307,623 DoF), "
+                        "E=1e4 nu=0.3, top face held at 1.2x height, +-1% noise (seed 6), "
+                        "dt=0.01",
+            "materials": out}
+
+
 def cpu_baseline(seconds_target=10.0):
     """FP64 numpy oracle: eval + assembly (E, g, BSR) of a 24^3 cube of the same
     workload recipe, repeated until ~seconds_target of CPU work."""
@@ -384,7 +449,9 @@ def main():
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-c4", action="store_true")
-    ap.add_argument("--only", choices=["c3", "c4"], help="run only this extra workload")
+    ap.add_argument("--no-materials", action="store_true")
+    ap.add_argument("--only", choices=["c3", "c4", "materials"],
+                    help="run only this extra workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run plain 512 MiB device copies first (byte-counter calibration)")
     args = ap.parse_args()
@@ -414,6 +481,9 @@ def main():
         return
     if args.only == "c4":
         print(json.dumps({"c4": precision_c4(symx, torch)}), flush=True)
+        return
+    if args.only == "materials":
+        print(json.dumps({"materials": materials_bench(symx, torch)}), flush=True)
         return
     if args.calib_copy:
         # a plain copy kernel of known size: 512 MiB read + 512 MiB written per launch
@@ -580,6 +650,7 @@ def main():
     c3 = None if args.no_c3 else mixed_c3(symx, torch)
     if c3:
         log(f"c3: {c3}")
+    materials = None if args.no_materials else materials_bench(symx, torch)
 
     serving = None
     if not args.no_serving:
@@ -633,6 +704,7 @@ def main():
         "serving": serving,
         "c4_precision": c4,
         "c3_mixed": c3,
+        "materials": materials,
         "mesh_setup_s": round(setup_s, 3),
         "kernels_f32_refined_steps": kernels,
         "roofline": roofline,
