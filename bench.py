@@ -76,22 +76,31 @@ def measured_traffic(kernel):
     return rec["bytes_per_launch"]
 
 
-GEN_SOURCES = ("expr.h", "expr.cpp", "symx_gen.cpp")
+# Generated functions the Stable Neo-Hookean row assembly and energy kernels run.
+ROW_GEN_FUNCS = ("snh_tet4_row0_gHoff", "snh_tet4_row0_g", "snh_tet4_s_E")
 
 
 def row_kernel_hash():
-    """Hash of the row-assembly kernel source and of the generator that emits
-    its element functions (the committed VALU record is tied to both)."""
+    """Hash of the row-assembly kernel source (its inputs gather and kind
+    dispatch, and the kernels) and of the generated element functions it runs;
+    the committed VALU record is tied to it."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2303_02156_amd", "csrc")
     src = open(os.path.join(csrc, "symx_kernels.hip")).read()
-    a = src.find("// [valu-hash-begin row_assemble]")
-    e = src.find("// [valu-hash-end row_assemble]")
-    if a < 0 or e < 0:
-        return None
-    h = hashlib.sha256(src[a:e].encode())
-    for f in GEN_SOURCES:
-        h.update(open(os.path.join(csrc, "gen", f), "rb").read())
+    h = hashlib.sha256()
+    for region in ("row_inputs", "row_assemble"):
+        a = src.find(f"// [valu-hash-begin {region}]")
+        e = src.find(f"// [valu-hash-end {region}]")
+        if a < 0 or e < 0:
+            return None
+        h.update(src[a:e].encode())
+    gen = open(os.path.join(csrc, "generated", "symx_generated.h")).read()
+    for fn in ROW_GEN_FUNCS:
+        a = gen.find(f"void {fn}(")
+        e = gen.find("\n}\n", a)
+        if a < 0 or e < 0:
+            return None
+        h.update(gen[a:e].encode())
     return h.hexdigest()
 
 
