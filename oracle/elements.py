@@ -20,6 +20,10 @@ Energies:
   Saint Venant-Kirchhoff, fixed co-rotational and as-rigid-as-possible with a
   volume term, the last two with the rotation R held constant over a time step
   (lagged, Sec. 6.1); R is the rotation closest to F at the lag positions.
+* Stable Neo-Hookean quadratic tet (tet10) -- Eq. 12: E_e = sum over the
+  quadrature points xi_q of w_q |det J_X(xi_q)| psi(F(xi_q)), F = J_x J_X^-1,
+  with the tet10 interpolation of App. A and a symmetric 4-point rule of
+  degree 2 (Sec. 5.2 fixed value summation: the same density at each point).
 """
 from __future__ import annotations
 
@@ -214,6 +218,80 @@ def lagged_rotations(x_lag, X):
 
 
 # ----------------------------------------------------------------------------
+# Stable Neo-Hookean quadratic tet (tet10)
+# ----------------------------------------------------------------------------
+# Symmetric 4-point rule of degree 2 on the reference tet {xi >= 0, sum <= 1}
+# (Hammer, Marlowe and Stroud 1956): barycentric points (a, b, b, b) and their
+# permutations, a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20, weights 1/24 (the
+# reference volume 1/6 split evenly).  xi = (L1, L2, L3).
+_Q4_A = (5.0 + 3.0 * np.sqrt(5.0)) / 20.0
+_Q4_B = (5.0 - np.sqrt(5.0)) / 20.0
+TET10_RULE = [(1.0 / 24.0, np.array([_Q4_B if j != i else _Q4_A for j in range(4)])[1:])
+              for i in range(4)]
+
+
+def tet10_shape_derivatives(xi):
+    """dN_a/dxi_k (10, 3) of the App. A quadratic interpolation at xi:
+    corners N_c = L_c (2 L_c - 1), edge (i, j) N = 4 L_i L_j, L0 = 1 - sum xi."""
+    L = np.array([1.0 - xi.sum(), xi[0], xi[1], xi[2]])
+    dL = np.array([[-1.0, -1.0, -1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    dN = np.empty((10, 3))
+    for c in range(4):
+        dN[c] = (4.0 * L[c] - 1.0) * dL[c]
+    edges = ((0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3))
+    for k, (i, j) in enumerate(edges):
+        dN[4 + k] = 4.0 * (L[i] * dL[j] + L[j] * dL[i])
+    return dN
+
+
+def _snh_density(F, mu_, lam_):
+    """psi, dpsi/dF and (lazily) d2psi/dF2 of Stable Neo-Hookean (App. B)."""
+    Ic = np.einsum("eij,eij->e", F, F)
+    f0, f1, f2 = F[:, :, 0], F[:, :, 1], F[:, :, 2]
+    J = np.einsum("ei,ei->e", f0, np.cross(f1, f2))
+    cof = np.stack([np.cross(f1, f2), np.cross(f2, f0), np.cross(f0, f1)], axis=2)
+    alpha = 1.0 + mu_ / lam_ - mu_ / (4.0 * lam_)
+    psi = 0.5 * mu_ * (Ic - 3.0) + 0.5 * lam_ * (J - alpha) ** 2 - 0.5 * mu_ * np.log(Ic + 1.0)
+    s1 = mu_ * (1.0 - 1.0 / (Ic + 1.0))
+    s2 = lam_ * (J - alpha)
+    P = s1[:, None, None] * F + s2[:, None, None] * cof
+
+    def d2():
+        return (s1[:, None, None, None, None] * _I4(F.shape[0])
+                + (2.0 * mu_ / (Ic + 1.0) ** 2)[:, None, None, None, None]
+                * np.einsum("eij,ekl->eijkl", F, F)
+                + lam_[:, None, None, None, None] * np.einsum("eij,ekl->eijkl", cof, cof)
+                + s2[:, None, None, None, None] * _hess_J(F))
+    return psi, P, d2
+
+
+def snh_tet10(x, X, mu, lam, want_hess=True, rule=None):
+    """Energy, gradient (E,10,3) and Hessian (E,10,3,10,3) of a quadratic tet:
+    at each quadrature point the shape gradients b_a = J_X^-T dN_a/dxi give
+    dF_ij/dx_{a,m} = delta_im b_a[j], and the point adds w |det J_X| times
+    psi, P b_a and b_a d2psi b_b to E, g_a and H_ab."""
+    mu_, lam_ = snh_reparam(np.asarray(mu, dtype=np.float64), np.asarray(lam, dtype=np.float64))
+    n = x.shape[0]
+    E = np.zeros(n, dtype=x.dtype)
+    g = np.zeros((n, 10, 3), dtype=x.dtype)
+    H = np.zeros((n, 10, 3, 10, 3), dtype=x.dtype) if want_hess else None
+    for w, xi in (TET10_RULE if rule is None else rule):
+        dN = tet10_shape_derivatives(xi)
+        JX = np.einsum("eai,ak->eik", X, dN)
+        Jx = np.einsum("eai,ak->eik", x, dN)
+        JXinv = np.linalg.inv(JX)
+        wdet = w * np.abs(np.linalg.det(JX))
+        F = Jx @ JXinv
+        b = np.einsum("ak,ekj->eaj", dN, JXinv)
+        psi, P, d2 = _snh_density(F, mu_, lam_)
+        E = E + wdet * psi
+        g = g + wdet[:, None, None] * np.einsum("eij,eaj->eai", P, b)
+        if want_hess:
+            H = H + wdet[:, None, None, None, None] * np.einsum("eaj,ebl,eijkl->eaibk", b, b, d2())
+    return E, g, H
+
+
+# ----------------------------------------------------------------------------
 # StVK triangle membrane
 # ----------------------------------------------------------------------------
 def tri_rest_frame(X):
@@ -348,4 +426,6 @@ def element_eval(es, x, X, want_hess=True, x_lag=None):
         R = lagged_rotations(Xe if x_lag is None else x_lag[es.conn], Xe)
         f = fcr_tet4 if es.kind == 5 else arap_tet4
         return f(xe, Xe, mu, lam, R, want_hess)
+    if es.kind == 7:
+        return snh_tet10(xe, Xe, mu, lam, want_hess)
     raise ValueError(f"unknown energy kind {es.kind}")

@@ -9,6 +9,12 @@
   which tests/test_oracle_pins.py checks against the textbook stiffness.
 * Lumped masses for the inertia term of the incremental potential (Eq. 2):
   each tet gives rho*V/4 to its nodes, each membrane triangle rho*h*A/3.
+  Quadratic tets (the paper does not say how their mass is lumped): HRZ
+  lumping, the consistent mass diagonal rho int N_a^2 dV scaled to the total
+  rho V.  With int L0^p L1^q L2^r L3^s dV = 6V p!q!r!s!/(p+q+r+s+3)! the
+  diagonal is V/70 at a corner and 8V/105 at an edge node (sum 18V/35), so a
+  corner gets rho V/36 and an edge node 4 rho V/27 (V of the straight-sided
+  element, i.e. of its corner tet).
 """
 from __future__ import annotations
 
@@ -18,6 +24,7 @@ import numpy as np
 # Every tetrahedral element kind: Stable Neo-Hookean, classic Neo-Hookean,
 # Saint Venant-Kirchhoff, fixed co-rotational, ARAP (scenegen numbering).
 TET_KINDS = (0, 3, 4, 5, 6)
+TET10_KIND = 7                     # quadratic Stable Neo-Hookean tet
 
 
 def lame(young, poisson):
@@ -51,6 +58,10 @@ def lumped_mass(scene):
         if es.kind in TET_KINDS:
             V = tet_volume(scene.X[es.conn])
             np.add.at(m, es.conn.ravel(), np.repeat(es.density * V / 4.0, 4))
+        elif es.kind == TET10_KIND:
+            V = tet_volume(scene.X[es.conn[:, :4]])
+            share = np.array([1.0 / 36.0] * 4 + [4.0 / 27.0] * 6)
+            np.add.at(m, es.conn.ravel(), (es.density * V[:, None] * share[None, :]).ravel())
         elif es.kind == 1:
             A = tri_area(scene.X[es.conn])
             np.add.at(m, es.conn.ravel(), np.repeat(es.density * es.thickness * A / 3.0, 3))

@@ -15,6 +15,10 @@ their meshes are not public, so procedural grids of the same kind stand in
   the tet follows the path v000 -> +e_p0 -> +e_p1 -> v111).  Tets of odd
   permutations have vertices 2 and 3 swapped so that every tet is positively
   oriented; this is decided from the permutation parity, not from geometry.
+* Quadratic tet grids: the tet grid's nodes keep their ids; every distinct
+  tet edge (i, j), i < j, gets a mid-edge node at the midpoint of its rest
+  endpoints, numbered after the vertices in ascending (i, j) order.  Element
+  connectivity is (4 corners, 6 edge nodes) in the App. A order above.
 * Cloth grids: m*m cells on [0,size]^2 at height z0, node id i + (m+1)j, each
   cell split along (i,j)->(i+1,j+1) into two counter-clockwise triangles.
   Hinges are the interior edges shared by two triangles, listed as
@@ -35,9 +39,14 @@ NH_TET4 = 3
 STVK_TET4 = 4
 FCR_TET4 = 5
 ARAP_TET4 = 6
+SNH_TET10 = 7
 
 NODES_PER_ELEM = {SNH_TET4: 4, STVK_TRI3: 3, HINGE4: 4, NH_TET4: 4, STVK_TET4: 4, FCR_TET4: 4,
-                  ARAP_TET4: 4}
+                  ARAP_TET4: 4, SNH_TET10: 10}
+
+# Quadratic tet node order (App. A, tet10 interpolation): corners 0-3, then the
+# mid-edge nodes of edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3).
+TET10_EDGES = ((0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3))
 
 _PERMS = list(itertools.permutations(range(3)))          # lexicographic order
 _PERM_ODD = [False, True, True, False, False, True]      # parity of each entry
@@ -112,6 +121,22 @@ def tet_grid(nx: int, ny: int, nz: int, h: float, origin=(0.0, 0.0, 0.0)):
     return X, tets.reshape(-1, 4).astype(np.int32)
 
 
+def tet10_grid(nx: int, ny: int, nz: int, h: float, origin=(0.0, 0.0, 0.0)):
+    """The tet grid with a mid-edge node on every tet edge (quadratic tets)."""
+    X, tets = tet_grid(nx, ny, nz, h, origin)
+    nv = X.shape[0]
+    t = tets.astype(np.int64)
+    ends = np.stack([np.stack([t[:, i], t[:, j]], axis=1) for i, j in TET10_EDGES], axis=1)
+    lo = ends.min(axis=2)
+    hi = ends.max(axis=2)
+    key = lo * nv + hi                                    # (n_tet, 6)
+    uniq, inv = np.unique(key.ravel(), return_inverse=True)
+    ulo, uhi = uniq // nv, uniq % nv
+    Xe = 0.5 * (X[ulo] + X[uhi])
+    conn = np.concatenate([t, nv + inv.reshape(-1, 6)], axis=1)
+    return np.concatenate([X, Xe]), conn.astype(np.int32)
+
+
 def cloth_grid(m: int, size: float = 1.0, z0: float = 0.0, origin_xy=(0.0, 0.0)):
     """m*m cells on [0,size]^2 at height z0, two counter-clockwise triangles per cell."""
     jj, ii = np.meshgrid(np.arange(m + 1), np.arange(m + 1), indexing="ij")
@@ -172,10 +197,11 @@ def tet_cube_scene(n: int, h: float = 0.01, young: float = 1e5, poisson: float =
 
     x(t) = X + U(-perturb*h, perturb*h)^3 on free nodes; v(t) ~ N(0, vel_std^2)
     on free nodes.  Draw order: perturbations (node-major), then velocities.
-    kind: the tet material (SNH_TET4, NH_TET4, STVK_TET4, FCR_TET4, ARAP_TET4).
+    kind: the tet material (SNH_TET4, NH_TET4, STVK_TET4, FCR_TET4, ARAP_TET4),
+    or SNH_TET10 for quadratic Stable Neo-Hookean tets on the same cubes.
     """
     nx, ny, nz = dims if dims is not None else (n, n, n)
-    X, tets = tet_grid(nx, ny, nz, h)
+    X, tets = tet10_grid(nx, ny, nz, h) if kind == SNH_TET10 else tet_grid(nx, ny, nz, h)
     fixed = _bottom_fixed(X)
     rng = np.random.default_rng(seed)
     N = X.shape[0]
@@ -195,9 +221,10 @@ def stretched_box_scene(kind: int, dims: tuple = (40, 40, 60), h: float = 0.01,
     """The material comparison workload (Sec. 6.1, Table 3): a box of 6-tet
     cubes (40 x 40 x 60 cubes: 41*41*61 nodes = 307,623 DoF), E=1e4 Pa,
     nu=0.3, bottom face fixed, top face fixed at (1 + stretch) of the height,
-    interior stretched affinely in z plus +-1% noise (seed)."""
+    interior stretched affinely in z plus +-1% noise (seed).  SNH_TET10
+    builds the same box from quadratic tets."""
     nx, ny, nz = dims
-    X, tets = tet_grid(nx, ny, nz, h)
+    X, tets = tet10_grid(nx, ny, nz, h) if kind == SNH_TET10 else tet_grid(nx, ny, nz, h)
     z = X[:, 2]
     top = z >= z.max() - 1e-12
     fixed = (_bottom_fixed(X).astype(bool) | top).astype(np.uint8)

@@ -12,6 +12,8 @@ index, a transposed operand) fails one of them:
 * matrices with known eigen-decomposition for the PSD projection;
 * a direct sparse solve and exact rigid-motion solutions for the Newton step.
 """
+import itertools
+
 import numpy as np
 import pytest
 
@@ -271,6 +273,138 @@ def test_closest_rotation():
     for s in range(300):                                  # no rotation does better
         T = _rot(s + 100)
         assert np.all(np.einsum("ij,eij->e", T, F) <= best + 1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Quadratic tet (tet10), Eq. 12 with the App. A interpolation
+# ----------------------------------------------------------------------------
+def _tet10_random(n, seed, curved=0.1):
+    """Straight-sided rest tet10s (edge nodes at midpoints), and current
+    states: an affine map plus node noise (curved = noise / edge length)."""
+    x4, X4 = sg.random_tets(n, seed, inverted_frac=0.0)
+    E = [(0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3)]
+    X = np.concatenate([X4, np.stack([0.5 * (X4[:, i] + X4[:, j]) for i, j in E], 1)], 1)
+    x = np.concatenate([x4, np.stack([0.5 * (x4[:, i] + x4[:, j]) for i, j in E], 1)], 1)
+    x = x + np.random.default_rng(seed + 1).uniform(-curved, curved, x.shape) * 0.01
+    return x, X
+
+
+def _snh10(x, X, **kw):
+    n = x.shape[0]
+    return elements.snh_tet10(x, X, np.full(n, MU), np.full(n, LAM), **kw)
+
+
+def test_tet10_rule_is_degree_two():
+    """The 4-point rule integrates every monomial of degree <= 2 over the
+    reference tet exactly (int xi^a = a!b!c!/(a+b+c+3)!), and not degree 3."""
+    from math import factorial
+    rule = elements.TET10_RULE
+
+    def exact(p):
+        return factorial(p[0]) * factorial(p[1]) * factorial(p[2]) / factorial(sum(p) + 3)
+    for p in itertools.product(range(4), repeat=3):
+        q = sum(w * xi[0] ** p[0] * xi[1] ** p[1] * xi[2] ** p[2] for w, xi in rule)
+        if sum(p) <= 2:
+            assert q == pytest.approx(exact(p), rel=1e-14)
+    cubic = sum(w * xi[0] ** 3 for w, xi in rule)
+    assert abs(cubic - exact((3, 0, 0))) > 1e-6
+
+
+def test_tet10_shape_derivatives():
+    """dN/dxi matches the complex-step derivative of the App. A interpolation
+    written out here, the functions are a partition of unity (derivatives sum
+    to zero) and interpolate: N_a(node b) = delta_ab."""
+    nodes = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [.5, 0, 0], [.5, .5, 0],
+                      [0, .5, 0], [0, 0, .5], [.5, 0, .5], [0, .5, .5]])
+
+    def N(xi):
+        L0, L1, L2, L3 = 1 - xi[0] - xi[1] - xi[2], xi[0], xi[1], xi[2]
+        return np.array([L0 * (2 * L0 - 1), L1 * (2 * L1 - 1), L2 * (2 * L2 - 1), L3 * (2 * L3 - 1),
+                         4 * L0 * L1, 4 * L1 * L2, 4 * L2 * L0, 4 * L0 * L3, 4 * L1 * L3,
+                         4 * L2 * L3])
+    assert np.allclose(np.stack([N(p) for p in nodes]), np.eye(10), atol=1e-15)
+    rng = np.random.default_rng(50)
+    for _ in range(10):
+        xi = rng.dirichlet(np.ones(4))[1:]
+        dN = elements.tet10_shape_derivatives(xi)
+        cs = np.stack([np.imag(N(xi + 1e-30j * np.eye(3)[k])) / 1e-30 for k in range(3)], 1)
+        assert np.allclose(dN, cs, rtol=0, atol=1e-13)
+        assert np.allclose(dN.sum(axis=0), 0.0, atol=1e-14)
+
+
+def test_tet10_affine_patch_equals_tet4():
+    """Under an affine map every quadrature point sees the same F, so the
+    quadratic element's energy is V psi(F) of its corner tet (the linear
+    element, pinned separately), and its gradient sums to zero."""
+    _, X = _tet10_random(12, 51)
+    A = np.eye(3)[None] + np.random.default_rng(52).uniform(-0.3, 0.3, (12, 3, 3))
+    x = np.einsum("eij,eaj->eai", A, X) + 0.3
+    E10, g10, _ = _snh10(x, X, want_hess=False)
+    E4, _, _ = _snh(x[:, :4], X[:, :4], want_hess=False)
+    assert _rel(E10, E4) < 1e-12
+    assert np.max(np.abs(g10.sum(axis=1))) < 1e-9 * np.max(np.abs(g10))
+
+
+def test_tet10_derivatives_complex_step():
+    x, X = _tet10_random(6, 53)
+    E, g, H = _snh10(x, X)
+    gc = _cs_grad(lambda xc: _snh10(xc, X, want_hess=False)[0], x)
+    Hc = _cs_jac(lambda xc: _snh10(xc, X, want_hess=False)[1], x)
+    assert _rel(g, gc) < 1e-12
+    assert _rel(H, Hc) < 1e-11
+    Hm = H.reshape(6, 30, 30)
+    assert _rel(Hm, np.swapaxes(Hm, 1, 2)) < 1e-13
+
+
+def test_tet10_invariances():
+    """Translation leaves E and g unchanged, rotation rotates g, and relabelling
+    the corners (edge nodes following their edges) permutes g: the symmetric
+    rule maps onto itself, so E is unchanged."""
+    x, X = _tet10_random(10, 54)
+    E, g, H = _snh10(x, X)
+    E2, g2, _ = _snh10(x + np.array([0.3, -0.2, 0.1]), X, want_hess=False)
+    assert np.allclose(E2, E, rtol=1e-12) and _rel(g2, g) < 1e-12
+    Q = _rot(55)
+    E3, g3, _ = _snh10(x @ Q.T, X, want_hess=False)
+    assert np.allclose(E3, E, rtol=1e-12) and _rel(g3, g @ Q.T) < 1e-11
+    edges = [(0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3)]
+    for sigma in itertools.permutations(range(4)):
+        perm = list(sigma)
+        for i, j in edges:
+            a, b = sigma[i], sigma[j]
+            perm.append(4 + next(k for k, e in enumerate(edges) if set(e) == {a, b}))
+        E4, g4, H4 = _snh10(x[:, perm], X[:, perm])
+        assert np.allclose(E4, E, rtol=1e-12)
+        assert _rel(g4, g[:, perm]) < 1e-11
+        assert _rel(H4, H[:, perm][:, :, :, perm]) < 1e-11
+
+
+def test_tet10_hrz_masses():
+    """HRZ lumping: int N_a^2 over a straight-sided tet by a brute-force
+    tensor Gauss rule on the collapsed cube, scaled to rho V, gives rho V/36
+    per corner and 4 rho V/27 per edge node."""
+    t, w = np.polynomial.legendre.leggauss(8)
+    t, w = 0.5 * (t + 1.0), 0.5 * w
+    total = np.zeros(10)
+    for u, wu in zip(t, w):
+        for v, wv in zip(t, w):
+            for r, wr in zip(t, w):
+                xi = np.array([u, v * (1 - u), r * (1 - u) * (1 - v)])   # Duffy map
+                jac = (1 - u) ** 2 * (1 - v)
+                L = np.array([1 - xi.sum(), *xi])
+                N = [L[c] * (2 * L[c] - 1) for c in range(4)]
+                N += [4 * L[i] * L[j] for i, j in [(0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3)]]
+                total += wu * wv * wr * jac * np.array(N) ** 2
+    frac = total / total.sum()
+    assert np.allclose(frac[:4], 1 / 36, rtol=1e-12) and np.allclose(frac[4:], 4 / 27, rtol=1e-12)
+    s = sg.tet_cube_scene(2, h=0.01, kind=sg.SNH_TET10)
+    m = rest.lumped_mass(s)
+    assert np.sum(m) == pytest.approx(1000.0 * 0.02 ** 3, rel=1e-12)
+    V = 0.01 ** 3 / 6
+    e = s.energies[0].conn[0]
+    own = np.zeros(s.n_nodes)
+    np.add.at(own, e, 1000.0 * V * np.array([1 / 36] * 4 + [4 / 27] * 6))
+    assert np.all(m[e] >= own[e] - 1e-18)
 
 
 def _random_tris(n, seed, stretch=0.2):
