@@ -19,6 +19,9 @@
 //   NAME_row0_g, NAME_row0_gH      gradient of node 0 and Hessian block row 0
 //                                  (node 0 at the origin); node a's row is
 //                                  obtained by relabelling node a as node 0
+//   NAME_rowR_g, NAME_rowR_gHoff   the same for node R (R = 0, and 4 for the
+//                                  quadratic tet, whose edge nodes cannot be
+//                                  relabelled into a corner)
 //
 // Usage: symx_gen <output directory>
 #include <cstdio>
@@ -41,6 +44,7 @@ struct EnergySpec {
   int n_in;           // total inputs
   int rest_slot;      // first slot of node-0 rest coordinates, or -1
   std::function<S(Graph&, const std::vector<S>&)> energy;
+  std::vector<int> row_nodes = {0};  // nodes with row functions (see header)
 };
 
 Mat cols_minus_first(Graph& g, const std::vector<S>& in, int base, int n_nodes) {
@@ -165,6 +169,51 @@ S stvk_tri3(Graph& g, const std::vector<S>& in) {
   return h * area * psi;
 }
 
+// Stable Neo-Hookean density (App. B, Stable Neo-Hookean branch) with the Lame
+// re-parametrisation mu' = 4/3 mu, lambda' = lambda + 5/6 mu.
+S snh_density(const Mat& F, S mu, S lam) {
+  S mu_ = mu * (4.0 / 3.0);
+  S lam_ = lam + mu * (5.0 / 6.0);
+  S Ic = frob2(F);
+  S J = det3(F);
+  S alpha = 1.0 + mu_ / lam_ - mu_ / (4.0 * lam_);
+  return 0.5 * mu_ * (Ic - 3.0) + 0.5 * lam_ * pown(J - alpha, 2) - 0.5 * mu_ * log(Ic + 1.0);
+}
+
+// Jacobian d p / d xi of the quadratic tet interpolation p(xi) = sum_a N_a(xi)
+// p_a (App. A: the interpolation is written out and differentiated
+// symbolically with respect to the reference coordinates xi).  Node order:
+// corners 0-3, then edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3).
+Mat tet10_jacobian(Graph& g, const std::vector<S>& in, int base, const std::vector<S>& xi) {
+  S L0 = 1.0 - xi[0] - xi[1] - xi[2];
+  std::vector<S> L = {L0, xi[0], xi[1], xi[2]};
+  const int edge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+  std::vector<S> N;
+  for (int c = 0; c < 4; ++c) N.push_back(L[c] * (2.0 * L[c] - 1.0));
+  for (const auto& e : edge) N.push_back(4.0 * L[e[0]] * L[e[1]]);
+  Mat Jm(3, 3, &g);
+  for (int i = 0; i < 3; ++i) {
+    S p = N[0] * in[base + i];
+    for (int a = 1; a < 10; ++a) p = p + N[a] * in[base + 3 * a + i];
+    for (int k = 0; k < 3; ++k) Jm(i, k) = S(&g, g.diff(p.id, xi[k].id));
+  }
+  return Jm;
+}
+
+// One quadrature point of the quadratic Stable Neo-Hookean tet (Eq. 12):
+// w |det J_X| psi(F), F = J_x J_X^-1.  Inputs: x (0..29), X (30..59), mu (60),
+// lambda (61), weight w (62), point xi (63..65).  The element energy is the
+// sum over the rule's points of this one function (Sec. 5.2, fixed value
+// summation), so only it is differentiated and compiled.
+S snh_tet10_qp(Graph& g, const std::vector<S>& in) {
+  std::vector<S> xi = {in[63], in[64], in[65]};
+  for (const S& v : xi) g.set_dof(v.id);  // differentiation symbols for the Jacobians
+  Mat Jx = tet10_jacobian(g, in, 0, xi);
+  Mat JX = tet10_jacobian(g, in, 30, xi);
+  Mat F = matmul(Jx, inv3(JX));
+  return in[62] * abs(det3(JX)) * snh_density(F, in[60], in[61]);
+}
+
 // Quadratic bending (Eq. 13, Bergou et al. 2006): E = k_b/2 x^T Q x with the
 // constant Q = c (K K^T) (x) I3; inputs are the per-node weights K_a and the
 // scale c = 3/(A0 + A1), precomputed from the rest hinge.
@@ -230,19 +279,26 @@ void generate(const EnergySpec& spec, Generated& out) {
   }
   add_fn("_s_E", g.substitute({E.id}, zero));
   add_fn("_s_EgH", g.substitute(EgH, zero));
-  std::vector<int> row0_g(grad.begin(), grad.begin() + 3);
-  std::vector<int> row0_gH = row0_g;
-  for (int i = 0; i < 3; ++i)
-    for (int l = 0; l < n_dof; ++l) row0_gH.push_back(hess[i * n_dof + l]);
-  add_fn("_row0_g", g.substitute(row0_g, zero));
-  add_fn("_row0_gH", g.substitute(row0_gH, zero));
-  // gradient of node 0 and the off-diagonal blocks of its Hessian row; the
-  // diagonal block follows from translation invariance (each Hessian row sums
-  // to zero over the nodes), so the kernel forms it as minus their sum
-  std::vector<int> row0_gHoff = row0_g;
-  for (int i = 0; i < 3; ++i)
-    for (int l = 3; l < n_dof; ++l) row0_gHoff.push_back(hess[i * n_dof + l]);
-  add_fn("_row0_gHoff", g.substitute(row0_gHoff, zero));
+  for (int r : spec.row_nodes) {
+    const std::string R = "_row" + std::to_string(r);
+    std::vector<int> row_g(grad.begin() + 3 * r, grad.begin() + 3 * r + 3);
+    add_fn(R + "_g", g.substitute(row_g, zero));
+    if (r == 0) {
+      std::vector<int> row_gH = row_g;
+      for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < n_dof; ++l) row_gH.push_back(hess[i * n_dof + l]);
+      add_fn(R + "_gH", g.substitute(row_gH, zero));
+    }
+    // gradient of node r and the off-diagonal blocks of its Hessian row (the
+    // other nodes in ascending order); the diagonal block follows from
+    // translation invariance (each Hessian row sums to zero over the nodes),
+    // so the kernel forms it as minus their sum
+    std::vector<int> row_gHoff = row_g;
+    for (int i = 0; i < 3; ++i)
+      for (int l = 0; l < n_dof; ++l)
+        if (l / 3 != r) row_gHoff.push_back(hess[(3 * r + i) * n_dof + l]);
+    add_fn(R + "_gHoff", g.substitute(row_gHoff, zero));
+  }
 
   for (const Function& f : fns) {
     Census ch, cc;
@@ -282,6 +338,7 @@ int main(int argc, char** argv) {
       {"stvk_tet4", 4, 26, 12, stvk_tet4},
       {"fcr_tet4", 4, 35, 12, fcr_tet4},
       {"arap_tet4", 4, 35, 12, arap_tet4},
+      {"snh_tet10", 10, 66, 30, snh_tet10_qp, {0, 4}},
   };
   Generated all;
   all.hip =

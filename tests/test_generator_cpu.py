@@ -236,3 +236,70 @@ def test_hessian_rows_sum_to_zero_and_offdiagonal_rows(lib):
                                                   np.full((20, 1), 1e-3)], 1), 157)
     Hh = Hh[:, 13:].reshape(20, 4, 3, 4, 3)
     assert np.max(np.abs(Hh.sum(axis=3))) < 1e-12 * np.abs(Hh).max()
+
+
+# ---------------------------------------------------------------------------
+# quadratic tet: one generated function per quadrature point, summed
+# ---------------------------------------------------------------------------
+TET10_EDGES = ((0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3))
+
+
+def _tet10_states(n, seed):
+    x4, X4 = sg.random_tets(n, seed, inverted_frac=0.0)
+    X = np.concatenate([X4, np.stack([0.5 * (X4[:, i] + X4[:, j]) for i, j in TET10_EDGES], 1)], 1)
+    x = np.concatenate([x4, np.stack([0.5 * (x4[:, i] + x4[:, j]) for i, j in TET10_EDGES], 1)], 1)
+    return x + np.random.default_rng(seed + 1).uniform(-1e-3, 1e-3, x.shape), X
+
+
+def _tet10_inputs(x, X, mu, lam, w, xi):
+    n = x.shape[0]
+    return np.concatenate([x.reshape(n, 30), X.reshape(n, 30), mu[:, None], lam[:, None],
+                           np.full((n, 1), w), np.broadcast_to(xi, (n, 3))], axis=1)
+
+
+def _tet10_sum(lib, name, x, X, mu, lam, n_out):
+    return sum(_call(lib, name, _tet10_inputs(x, X, mu, lam, w, xi), n_out)
+               for w, xi in elements.TET10_RULE)
+
+
+def tet10_relabel(a):
+    """Node order putting local node a first (corner a) or at position 4 (edge
+    node a = edge (i, j): corners i, j first); corners permuted, edge nodes
+    following their edges."""
+    if a < 4:
+        sigma = [a] + [c for c in range(4) if c != a]
+    else:
+        i, j = TET10_EDGES[a - 4]
+        sigma = [i, j] + [c for c in range(4) if c not in (i, j)]
+    perm = list(sigma)
+    for i, j in TET10_EDGES:
+        e = {sigma[i], sigma[j]}
+        perm.append(4 + next(k for k, ed in enumerate(TET10_EDGES) if set(ed) == e))
+    return perm
+
+
+def test_tet10_generated_vs_oracle(lib):
+    """Sum over the rule's points of the generated per-point function = the
+    oracle's quadratic element (E, g, H); and every node's row from the corner
+    (row 0) or edge (row 4) row function of the relabelled element."""
+    x, X = _tet10_states(12, 61)
+    n = x.shape[0]
+    mu, lam = np.full(n, MU), np.full(n, LAM)
+    E, g, H = elements.snh_tet10(x, X, mu, lam)
+    out = _tet10_sum(lib, "snh_tet10_EgH", x, X, mu, lam, 931)
+    assert _rel(out[:, 0], E) < 1e-10
+    assert _rel(out[:, 1:31], g.reshape(n, 30)) < 1e-10
+    assert _rel(out[:, 31:], H.reshape(n, 900)) < 1e-10
+    out_s = _tet10_sum(lib, "snh_tet10_s_EgH", x - x[:, :1], X - X[:, :1], mu, lam, 931)
+    assert _rel(out_s, out) < 1e-9
+    for a in range(10):
+        perm = tet10_relabel(a)
+        r = 0 if a < 4 else 4
+        assert perm[r] == a
+        xs, Xs = x[:, perm] - x[:, perm[:1]], X[:, perm] - X[:, perm[:1]]
+        row = _tet10_sum(lib, f"snh_tet10_row{r}_gHoff", xs, Xs, mu, lam, 84)
+        others = [perm[b] for b in range(10) if b != r]
+        assert _rel(row[:, :3], g[:, a]) < 1e-9
+        assert _rel(row[:, 3:].reshape(n, 3, 9, 3), H[:, a][:, :, others, :]) < 1e-9
+        rg = _tet10_sum(lib, f"snh_tet10_row{r}_g", xs, Xs, mu, lam, 3)
+        assert _rel(rg, g[:, a]) < 1e-9
