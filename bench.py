@@ -406,6 +406,74 @@ def materials_bench(symx, torch, reps=10):
             "materials": out}
 
 
+# Quadratic tets on the stretched box: the paper's per-Newton-iteration
+# evaluation + assembly time of its 137K-DoF stretched cube with quadratic
+# elements (simulation benchmark table, SymX column) and its single-element
+# E+g+H time of a quadratic tet (single element benchmark table), CPU, ms and
+# us; context only, another machine.
+PAPER_TET10_MS_PER_ITER = 24.3
+PAPER_TET10_US_PER_ELEM = 5.91
+
+
+def quadratic_bench(symx, torch, reps=10):
+    """Quadratic SNH tets (Eq. 12, 4-point rule) on a stretched box of
+    17 x 17 x 18 cubes (31,212 tets, 45,325 nodes = 135,975 DoF): one E+g+H
+    assembly in FP32 and FP64 (device events, median of reps) and one
+    FP32-refined Newton step."""
+    import numpy as np
+    import scenegen as sg
+    scene = sg.stretched_box_scene(sg.SNH_TET10, dims=(17, 17, 18))
+    mesh = symx.Mesh(scene)
+    n_elem = scene.n_elements()
+    dt = scene.dt
+    x0 = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v0 = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    xt = torch.tensor(scene.x0 + dt * scene.v0 + dt * dt * np.asarray(scene.gravity)[None, :],
+                      dtype=torch.float64, device="cuda")
+    g = torch.empty_like(x0)
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    out = {"workload": "stretched box of quadratic SNH tets: 17x17x18 cubes x 6 tet10 "
+                       f"({n_elem} elements, {3 * scene.n_nodes} DoF), E=1e4 nu=0.3, top face "
+                       "held at 1.2x height, +-1% noise (seed 6), dt=0.01, 4-point rule",
+           "elements": n_elem, "dof": 3 * scene.n_nodes, "nnzb": int(mesh.info.nnzb)}
+    for pname, prec in (("f32", symx.SYMX_F32), ("f64", symx.SYMX_F64)):
+        ms = []
+        for r in range(reps + 3):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            symx.symx_assemble_bsr(mesh.handle, x0.data_ptr(), xt.data_ptr(), dt, flags, prec,
+                                   g.data_ptr())
+            b.record()
+            b.synchronize()
+            if r >= 3:
+                ms.append(a.elapsed_time(b))
+        m = statistics.median(ms)
+        out[f"assembly_ms_{pname}"] = round(m, 4)
+        out[f"ns_per_elem_{pname}"] = round(m * 1e6 / n_elem, 2)
+    ops = census_ops("snh_tet10_EgH")
+    if ops:
+        out["algorithmic_ops_per_elem"] = 4 * ops
+        out["achieved_tflops_f32"] = round(4 * ops * n_elem / (out["assembly_ms_f32"] * 1e-3) / 1e12,
+                                           2)
+    x = x0.clone()
+    v = v0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rep = mesh.newton_step(x, v, symx.step_params(dt=dt, precision=symx.SYMX_F32_REFINED,
+                                                      max_pcg=500))
+    torch.cuda.synchronize()
+    out.update({"newton_ms_f32_refined": round((time.perf_counter() - t0) * 1e3, 2),
+                "status": symx.STATUS[st], "newton_iters": rep.newton_iters,
+                "pcg_iters": rep.pcg_iters,
+                "rel_residual": rep.residual / max(rep.residual0, 1e-300),
+                "paper_cpu_ms_per_newton_iter": PAPER_TET10_MS_PER_ITER,
+                "paper_cpu_us_per_elem": PAPER_TET10_US_PER_ELEM})
+    mesh.close()
+    log(f"quadratic tets: {out}")
+    return out
+
+
 def cpu_baseline(seconds_target=10.0):
     """FP64 numpy oracle: eval + assembly (E, g, BSR) of a 24^3 cube of the same
     workload recipe, repeated until ~seconds_target of CPU work."""
@@ -459,7 +527,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-materials", action="store_true")
-    ap.add_argument("--only", choices=["c3", "c4", "materials"],
+    ap.add_argument("--no-quadratic", action="store_true")
+    ap.add_argument("--only", choices=["c3", "c4", "materials", "quadratic"],
                     help="run only this extra workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run plain 512 MiB device copies first (byte-counter calibration)")
@@ -493,6 +562,9 @@ def main():
         return
     if args.only == "materials":
         print(json.dumps({"materials": materials_bench(symx, torch)}), flush=True)
+        return
+    if args.only == "quadratic":
+        print(json.dumps({"quadratic": quadratic_bench(symx, torch)}), flush=True)
         return
     if args.calib_copy:
         # a plain copy kernel of known size: 512 MiB read + 512 MiB written per launch
@@ -660,6 +732,7 @@ def main():
     if c3:
         log(f"c3: {c3}")
     materials = None if args.no_materials else materials_bench(symx, torch)
+    quadratic = None if args.no_quadratic else quadratic_bench(symx, torch)
 
     serving = None
     if not args.no_serving:
@@ -714,6 +787,7 @@ def main():
         "c4_precision": c4,
         "c3_mixed": c3,
         "materials": materials,
+        "quadratic_tets": quadratic,
         "mesh_setup_s": round(setup_s, 3),
         "kernels_f32_refined_steps": kernels,
         "roofline": roofline,

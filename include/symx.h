@@ -59,8 +59,10 @@ typedef enum {
                             refinement correction in float64 */
 } symx_precision;
 
-/* Element energies (the paper's App. B and Eq. 13).  Tets use E = V psi(F)
- * with F = Ds Dm^-1 and Lame parameters from (young, poisson). */
+/* Element energies (the paper's App. B and Eq. 13).  Linear tets use
+ * E = V psi(F) with F = Ds Dm^-1 and Lame parameters from (young, poisson).
+ * The quadratic tet integrates psi over the element (Eq. 12) with a symmetric
+ * 4-point rule of degree 2: E = sum_q w_q |det J_X(xi_q)| psi(J_x J_X^-1). */
 typedef enum {
   SYMX_SNH_TET4 = 0,   /* Stable Neo-Hookean, linear tet, 4 nodes                */
   SYMX_STVK_TRI3 = 1,  /* St. Venant-Kirchhoff membrane triangle, 3 nodes        */
@@ -68,7 +70,11 @@ typedef enum {
   SYMX_NH_TET4 = 3,    /* classic Neo-Hookean (needs det F > 0)                  */
   SYMX_STVK_TET4 = 4,  /* St. Venant-Kirchhoff tet                               */
   SYMX_FCR_TET4 = 5,   /* fixed co-rotational, rotation R lagged per time step   */
-  SYMX_ARAP_TET4 = 6   /* as-rigid-as-possible + volume term, R lagged           */
+  SYMX_ARAP_TET4 = 6,  /* as-rigid-as-possible + volume term, R lagged           */
+  SYMX_SNH_TET10 = 7   /* Stable Neo-Hookean, quadratic tet, 10 nodes: corners
+                          0-3, then the mid-edge nodes of edges (0,1), (1,2),
+                          (2,0), (0,3), (1,3), (2,3) (App. A).  A mesh holding
+                          such a set holds no other kind; no PSD projection. */
 } symx_energy_kind;
 
 /* Evaluation flags (the three levels of Sec. 5.2, plus options). */
@@ -86,7 +92,8 @@ enum {
 typedef struct {
   int32_t kind;            /* symx_energy_kind                                 */
   int64_t n_elem;          /* number of elements, >= 0                         */
-  const int32_t* conn;     /* host, n_elem x (4 | 3 | 4) node ids in [0, N)     */
+  const int32_t* conn;     /* host, n_elem x k node ids in [0, N): k = 3 for the
+                              triangle, 10 for the quadratic tet, else 4       */
   const double* young;     /* host, per-element Young's modulus, or NULL       */
   double young_const;      /* Young's modulus when young == NULL               */
   double poisson;          /* Poisson ratio (tets, triangles)                  */
@@ -170,8 +177,10 @@ symx_status symx_mesh_get_info(symx_mesh mesh, symx_mesh_info* info);
 symx_status symx_mesh_get_pattern(symx_mesh mesh, int32_t* row_ptr, int32_t* col_idx,
                                   int32_t* scatter_map);
 
-/* Lumped node masses (host, N doubles): rho V / 4 per tet, rho h A / 3 per
- * triangle (the inertia term of Eq. 2). */
+/* Lumped node masses (host, N doubles): rho V / 4 per linear tet, rho h A / 3
+ * per triangle (the inertia term of Eq. 2); a quadratic tet gives rho V / 36
+ * to each corner and 4 rho V / 27 to each edge node (HRZ lumping, V of the
+ * straight-sided element). */
 symx_status symx_mesh_get_masses(symx_mesh mesh, double* mass_host);
 
 /* Per-element evaluation of one energy set (the low-level element interface

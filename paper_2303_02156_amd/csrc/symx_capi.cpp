@@ -204,6 +204,10 @@ symx_status symx_eval_derivatives(symx_mesh mesh, int32_t energy_index, const do
     set_error("SYMX_PROJECT_PSD needs SYMX_EVAL_HESS and a Hessian buffer");
     return SYMX_ERR_INVALID_ARG;
   }
+  if ((flags & SYMX_PROJECT_PSD) && m.sets[energy_index].k == 10) {
+    set_error("per-element PSD projection is not available for quadratic tets");
+    return SYMX_ERR_INVALID_ARG;
+  }
   symx_status st = launch_elem_eval(m, energy_index, x_dev, (int)flags, precision, E, g, H);
   if (st != SYMX_OK) return st;
   if (flags & SYMX_PROJECT_PSD) {

@@ -25,6 +25,8 @@ constexpr int kPrm = 8;             // parameter slots per element (doubles)
 constexpr uint32_t kNoSlot = 0xFFu;
 constexpr int kPcgHistory = 64;    // remembered PCG iteration counts
 constexpr int kIncRec = 32;        // values per incidence record (projected path)
+constexpr int kQuadInc = 64;       // incidences per row batch of a quadratic-tet mesh
+constexpr int kMaxElemBits = 26;   // element ids per set < 2^26
 
 // Parameter layout per element (kPrm doubles):
 //   SNH tet4:  mu, lambda (linear-elasticity Lame pair)
@@ -40,7 +42,50 @@ struct SetDev {
   int prm_stride;        // kPrm, or 0 when every element has the same parameters
   const double* rot64;   // lagged-rotation materials: n_elem x 9 (row-major R), else null
   const float* rot32;
+  const int* conn10;     // quadratic tets: n_elem x 10 node ids (conn is null)
 };
+
+// Quadratic tet node order (App. A): corners 0-3, then the mid-edge nodes of
+// edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3).  The element's energy is
+// unchanged when the corners are relabelled and the edge nodes follow their
+// edges (the quadrature rule is symmetric), so node a's Hessian row comes from
+// the row function of node 0 (a corner: a moved to corner 0) or node 4 (an
+// edge node of edge (i, j): i, j moved to corners 0, 1).  kTet10Perm[a][b] is
+// the original local node at position b of that relabelled order.
+constexpr int kTet10Edge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+struct Tet10Perm {
+  int8_t p[10][10];
+};
+constexpr Tet10Perm make_tet10_perm() {
+  Tet10Perm t{};
+  for (int a = 0; a < 10; ++a) {
+    int sig[4] = {0, 0, 0, 0};
+    int n = 0;
+    if (a < 4) {
+      sig[n++] = a;
+    } else {
+      sig[n++] = kTet10Edge[a - 4][0];
+      sig[n++] = kTet10Edge[a - 4][1];
+    }
+    for (int c = 0; c < 4; ++c) {
+      bool used = false;
+      for (int u = 0; u < n; ++u) used = used || sig[u] == c;
+      if (!used) sig[n++] = c;
+    }
+    for (int c = 0; c < 4; ++c) t.p[a][c] = int8_t(sig[c]);
+    for (int k = 0; k < 6; ++k) {
+      const int u = sig[kTet10Edge[k][0]], v = sig[kTet10Edge[k][1]];
+      for (int m = 0; m < 6; ++m)
+        if ((kTet10Edge[m][0] == u && kTet10Edge[m][1] == v) ||
+            (kTet10Edge[m][0] == v && kTet10Edge[m][1] == u))
+          t.p[a][4 + k] = int8_t(4 + m);
+    }
+  }
+  return t;
+}
+constexpr Tet10Perm kTet10Perm = make_tet10_perm();
+// position of node a in its relabelled order: 0 for corners, 4 for edge nodes
+__host__ __device__ constexpr int tet10_row_pos(int a) { return a < 4 ? 0 : 4; }
 
 // Fixed co-rotational and ARAP tets carry a lagged rotation per element.
 inline bool kind_has_rotation(int kind) {
@@ -52,13 +97,13 @@ struct SetsDev {
   int n;
 };
 
-// Incidence code: element id (bits 0-27), local node a (28-29), set (30-31).
+// Incidence code: element id (bits 0-25), local node a (26-29), set (30-31).
 __host__ __device__ inline uint32_t inc_make(int set, int a, int64_t e) {
-  return (uint32_t(set) << 30) | (uint32_t(a) << 28) | uint32_t(e);
+  return (uint32_t(set) << 30) | (uint32_t(a) << 26) | uint32_t(e);
 }
 __host__ __device__ inline int inc_set(uint32_t c) { return int(c >> 30); }
-__host__ __device__ inline int inc_local(uint32_t c) { return int((c >> 28) & 3u); }
-__host__ __device__ inline int inc_elem(uint32_t c) { return int(c & 0x0FFFFFFFu); }
+__host__ __device__ inline int inc_local(uint32_t c) { return int((c >> 26) & 15u); }
+__host__ __device__ inline int inc_elem(uint32_t c) { return int(c & 0x03FFFFFFu); }
 
 template <typename T>
 struct DevBuf {
@@ -147,7 +192,8 @@ struct TopoSet {
   int k = 0;
   int64_t n_elem = 0;
   std::vector<int32_t> conn;        // n_elem * k
-  int4* d_conn = nullptr;           // n_elem (unused components = -1)
+  int4* d_conn = nullptr;           // n_elem (unused components = -1); k <= 4
+  int* d_conn10 = nullptr;          // n_elem * 10; quadratic tets
 };
 
 struct Topology {
@@ -156,6 +202,9 @@ struct Topology {
   size_t device_bytes = 0;
   int64_t N = 0, n_inc = 0, nnzb = 0;
   int n_batch = 0, max_row_blocks = 0;
+  // quadratic-tet topology: batches of at most kQuadInc incidences, nine
+  // contribution entries per incidence (u16 = incidence << 4 | other node j)
+  bool quad = false;
   std::vector<TopoSet> sets;
   std::vector<int32_t> h_row_ptr;
   uvector<int32_t> h_col_idx;
@@ -168,7 +217,8 @@ struct Topology {
   uint32_t* inc_code = nullptr;     // n_inc
   int* batch_row = nullptr;         // n_batch+1
   uint32_t* blk_info = nullptr;     // nnzb: off-diagonal contribution list (start << 8 | count)
-  uint16_t* centry = nullptr;       // contribution entries (incidence << 2 | node)
+  uint16_t* centry = nullptr;       // contribution entries (incidence << 2 | node b),
+                                    // or incidence << 4 | j for a quadratic topology
   int* batch_entry = nullptr;       // n_batch+1: first entry of each batch
   ~Topology();
   bool matches(const symx_mesh_desc& d) const;  // same N, kinds and connectivity
@@ -202,6 +252,7 @@ struct SetHost {
   bool uniform = true;
   // device
   const int4* d_conn = nullptr;     // the topology's
+  const int* d_conn10 = nullptr;
   double* d_prm64 = nullptr;
   float* d_prm32 = nullptr;
   double* d_rot64 = nullptr;        // lagged rotations (FCR / ARAP sets)
@@ -240,6 +291,7 @@ struct Mesh {
   int64_t n_inc = 0;
   int n_batch = 0;
   int max_row_blocks = 0;
+  bool quad = false;                // quadratic tets (the topology's flag)
   double total_mass = 0.0;
   std::vector<SetHost> sets;
   std::vector<double> h_X, h_mass;

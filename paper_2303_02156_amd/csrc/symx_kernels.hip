@@ -75,6 +75,7 @@ __device__ double sum_partials(const double* __restrict__ partials, int n, doubl
   return block_sum_256(acc, sh);
 }
 
+// [valu-hash-begin row_inputs]
 // ---------------------------------------------------------------------------
 // element gather: node ids in relabelled order (node a first, then the other
 // nodes in ascending local order), positions relative to node a
@@ -231,6 +232,7 @@ __device__ __forceinline__ void with_kind(int kind, F&& f) {
     with_kind<KMASK, KIND + 1>(kind, f);
   }
 }
+// [valu-hash-end row_inputs]
 
 // ---------------------------------------------------------------------------
 // lagged rotations (fixed co-rotational and ARAP tets)
@@ -1078,6 +1080,298 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
 // [valu-hash-end row_assemble]
 
 // ---------------------------------------------------------------------------
+// quadratic tets (Eq. 12): the element energy is a sum over quadrature points
+// of one generated function, called with each point's weight and reference
+// coordinates (Sec. 5.2, fixed value summation)
+// ---------------------------------------------------------------------------
+// Symmetric 4-point rule of degree 2 on the reference tet (Hammer, Marlowe and
+// Stroud 1956): point q has barycentric coordinate a at corner q and b at the
+// others, a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20, weight 1/24; xi =
+// (L1, L2, L3).
+constexpr double kSqrt5 = 2.2360679774997896964;
+constexpr double kQuadA = (5.0 + 3.0 * kSqrt5) / 20.0;
+constexpr double kQuadB = (5.0 - kSqrt5) / 20.0;
+constexpr int kQuadPts = 4;
+
+__constant__ Tet10Perm c_tet10_perm = make_tet10_perm();
+
+template <typename T>
+__device__ __forceinline__ void set_quad_point(int q, T* in) {
+  in[62] = T(1.0 / 24.0);
+  in[63] = T(q == 1 ? kQuadA : kQuadB);
+  in[64] = T(q == 2 ? kQuadA : kQuadB);
+  in[65] = T(q == 3 ? kQuadA : kQuadB);
+}
+
+// Inputs 0..61 of the per-point function for element e with its nodes in the
+// order perm (local indices): positions and rest positions relative to the
+// first node (a corner), then mu and lambda.
+template <typename T>
+__device__ __forceinline__ void fill_tet10(const SetDev& S, int64_t e, const int8_t* perm,
+                                           const double* __restrict__ x,
+                                           const double* __restrict__ X, T* in) {
+  const int* c = S.conn10 + 10 * e;
+  const int n0 = c[perm[0]];
+  const double x0 = x[3 * (int64_t)n0], x1 = x[3 * (int64_t)n0 + 1], x2 = x[3 * (int64_t)n0 + 2];
+  const double X0 = X[3 * (int64_t)n0], X1 = X[3 * (int64_t)n0 + 1], X2 = X[3 * (int64_t)n0 + 2];
+  in[0] = in[1] = in[2] = T(0);
+  in[30] = in[31] = in[32] = T(0);
+#pragma unroll
+  for (int b = 1; b < 10; ++b) {
+    const int64_t n = c[perm[b]];
+    in[3 * b + 0] = T(x[3 * n + 0] - x0);
+    in[3 * b + 1] = T(x[3 * n + 1] - x1);
+    in[3 * b + 2] = T(x[3 * n + 2] - x2);
+    in[30 + 3 * b + 0] = T(X[3 * n + 0] - X0);
+    in[30 + 3 * b + 1] = T(X[3 * n + 1] - X1);
+    in[30 + 3 * b + 2] = T(X[3 * n + 2] - X2);
+  }
+  const T* P = prm_ptr<T>(S);
+  in[60] = ld_prm(P, S.prm_stride, e, 0);
+  in[61] = ld_prm(P, S.prm_stride, e, 1);
+}
+
+__device__ __forceinline__ const int8_t* identity10() {
+  // the relabelling of corner 0 leaves every node in place
+  return c_tet10_perm.p[0];
+}
+
+// Element energies of a quadratic-tet set -> one partial sum per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy_t10(SetDev S, const double* __restrict__ x,
+                                                   const double* __restrict__ X,
+                                                   double* __restrict__ partials,
+                                                   int* __restrict__ nonfinite) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < S.n_elem;
+       e += (int64_t)gridDim.x * 256) {
+    T in[66];
+    fill_tet10<T>(S, e, identity10(), x, X, in);
+    double Ee = 0.0;
+    for (int q = 0; q < kQuadPts; ++q) {
+      T out[1];
+      set_quad_point<T>(q, in);
+      snh_tet10_s_E<T>(in, out);
+      Ee += double(out[0]);
+    }
+    acc += Ee;
+  }
+  double s = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s;
+    if (!isfinite(s)) *nonfinite = 1;
+  }
+}
+
+// Row of local node a of element e summed over the quadrature points: out[0..2]
+// gradient, out[3 + 27 i + 3 j + k] the off-diagonal block entries of the nine
+// other nodes in the row function's order (WANT_H), or the gradient only.
+template <typename T, bool WANT_H>
+__device__ __forceinline__ void tet10_row_point(const SetDev& S, int64_t e, int a, int q,
+                                                const double* x, const double* X, T* out) {
+  T in[66];
+  fill_tet10<T>(S, e, c_tet10_perm.p[a], x, X, in);
+  set_quad_point<T>(q, in);
+  if (WANT_H) {
+    if (a < 4)
+      snh_tet10_row0_gHoff<T>(in, out);
+    else
+      snh_tet10_row4_gHoff<T>(in, out);
+  } else {
+    if (a < 4)
+      snh_tet10_row0_g<T>(in, out);
+    else
+      snh_tet10_row4_g<T>(in, out);
+  }
+}
+
+// Per-element E, gradient (n x 30) and Hessian (n x 30 x 30, row-major) of a
+// quadratic-tet set: one lane per (element, local node a) writes node a's
+// gradient and Hessian rows; the diagonal block is minus the sum of the row's
+// off-diagonal blocks (translation invariance).
+template <typename T>
+__global__ __launch_bounds__(64) void k_elem_eval_t10(SetDev S, const double* __restrict__ x,
+                                                     const double* __restrict__ X,
+                                                     T* __restrict__ Eo, T* __restrict__ go,
+                                                     T* __restrict__ Ho) {
+  const int64_t n = S.n_elem * 10;
+  for (int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 64) {
+    const int64_t e = t / 10;
+    const int a = int(t - 10 * e);
+    const int8_t* perm = c_tet10_perm.p[a];
+    const int r = tet10_row_pos(a);
+    T acc[84];
+#pragma unroll
+    for (int v = 0; v < 84; ++v) acc[v] = T(0);
+    for (int q = 0; q < kQuadPts; ++q) {
+      T out[84];
+      tet10_row_point<T, true>(S, e, a, q, x, X, out);
+#pragma unroll
+      for (int v = 0; v < 84; ++v) acc[v] += out[v];
+    }
+    if (go) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) go[e * 30 + 3 * a + i] = acc[i];
+    }
+    if (Ho) {
+      T* Hr = Ho + e * 900 + (int64_t)(3 * a) * 30;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T d0 = T(0), d1 = T(0), d2 = T(0);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+          const int b = perm[j < r ? j : j + 1];
+          const T h0 = acc[3 + 27 * i + 3 * j], h1 = acc[4 + 27 * i + 3 * j],
+                  h2 = acc[5 + 27 * i + 3 * j];
+          Hr[30 * i + 3 * b + 0] = h0;
+          Hr[30 * i + 3 * b + 1] = h1;
+          Hr[30 * i + 3 * b + 2] = h2;
+          d0 += h0;
+          d1 += h1;
+          d2 += h2;
+        }
+        Hr[30 * i + 3 * a + 0] = -d0;
+        Hr[30 * i + 3 * a + 1] = -d1;
+        Hr[30 * i + 3 * a + 2] = -d2;
+      }
+    }
+    if (Eo && a == 0) {
+      T in[66];
+      fill_tet10<T>(S, e, identity10(), x, X, in);
+      double Ee = 0.0;
+      for (int q = 0; q < kQuadPts; ++q) {
+        T o[1];
+        set_quad_point<T>(q, in);
+        snh_tet10_s_E<T>(in, o);
+        Ee += double(o[0]);
+      }
+      Eo[e] = T(Ee);
+    }
+  }
+}
+
+// Row assembly of a quadratic-tet mesh (the steps of k_row_assemble_fast with
+// the evaluation split over quadrature points).  A batch holds at most
+// kQuadInc incidences; wave w of the workgroup evaluates quadrature point w of
+// every incidence, and the four points are added into LDS in point order.
+// The contribution entries are (incidence << 4) | j, j the other node's index
+// in the row function's order.  WANT_H = false: gradient only.
+template <typename T, bool WANT_G, bool WANT_H>
+__global__ __launch_bounds__(kRowWG) void k_row_assemble_t10(RowArgs<T> A) {
+  constexpr int NV = WANT_H ? 84 : 3;
+  __shared__ T st[NV][kQuadInc];
+  __shared__ T blk[WANT_H ? 9 : 1][kRowWG];
+  __shared__ uint16_t s_blk[kRowWG + 1];
+  __shared__ uint16_t s_inc[kRowWG + 1];
+  const int t = threadIdx.x;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int r0 = A.batch_row[b], r1 = A.batch_row[b + 1];
+  const int nrows = r1 - r0;
+  const int q0 = A.inc_ptr[r0];
+  const int p0 = A.row_ptr[r0];
+  for (int r = t; r <= nrows; r += kRowWG) {
+    s_blk[r] = (uint16_t)(A.row_ptr[r0 + r] - p0);
+    s_inc[r] = (uint16_t)(A.inc_ptr[r0 + r] - q0);
+  }
+  __syncthreads();
+  const int nq = s_inc[nrows];
+  const int np = s_blk[nrows];
+  // step 1: wave w evaluates point w of incidence qi
+  const int w = t >> 6, qi = t & 63;
+  T out[NV];
+  if (qi < nq) {
+    const uint32_t code = A.inc_code[q0 + qi];
+    tet10_row_point<T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), inc_local(code), w,
+                               A.x, A.X, out);
+  }
+  for (int k = 0; k < kQuadPts; ++k) {
+    if (w == k && qi < nq) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) st[v][qi] = k == 0 ? out[v] : st[v][qi] + out[v];
+    }
+    __syncthreads();
+  }
+  int r = 0, col = 0;
+  bool diag = false;
+  T acc[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = T(0);
+  if constexpr (WANT_H) {
+    // step 2: off-diagonal blocks from their contribution lists
+    if (t < np) {
+      while (s_blk[r + 1] <= t) ++r;
+      col = A.col_idx[p0 + t];
+      diag = (col == r0 + r);
+      const uint32_t info = A.blk_info[p0 + t];
+      const uint16_t* ce = A.centry + A.batch_entry[b] + (info >> 8);
+      const int cnt = int(info & 0xFFu);
+      for (int j = 0; j < cnt; ++j) {
+        const uint32_t wv = ce[j];
+        const int q = int(wv >> 4);
+        const int jj = int(wv & 15u);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk)
+            acc[3 * i + kk] += st[3 + 27 * i + 3 * jj + kk][q];
+      }
+      // step 3: publish
+#pragma unroll
+      for (int c = 0; c < 9; ++c) blk[c][t] = acc[c];
+    }
+    __syncthreads();
+  }
+  // step 4: diagonal blocks (minus the sum of the row's off-diagonal blocks,
+  // plus inertia) and the gradient (incidences in order, float64)
+  const int nd = WANT_H ? 9 * nrows : 0;
+  for (int j = t; j < nd + (WANT_G ? 3 * nrows : 0); j += kRowWG) {
+    if (j < nd) {
+      const int rr = j / 9, c = j - 9 * rr;
+      T sum = T(0);
+      for (int sl = s_blk[rr]; sl < s_blk[rr + 1]; ++sl) sum += blk[WANT_H ? c : 0][sl];
+      T dv = -sum;
+      if (A.xt && (c % 4) == 0) dv += T(A.mass[r0 + rr] * A.inv_dt2);
+      blk[WANT_H ? c : 0][A.diag_pos[r0 + rr] - p0] = dv;
+    } else {
+      const int jj = j - nd;
+      const int rr = jj / 3, c = jj - 3 * rr;
+      const int row = r0 + rr;
+      double g = 0.0;
+      for (int q = s_inc[rr]; q < s_inc[rr + 1]; ++q) g += double(st[c][q]);
+      if (A.xt) g += A.mass[row] * A.inv_dt2 * (A.x[3 * row + c] - A.xt[3 * row + c]);
+      if (A.fixed && A.fixed[row]) g = 0.0;
+      if (!isfinite(g)) *A.nonfinite = 1;
+      A.g[3 * row + c] = g;
+    }
+  }
+  if (!WANT_H) return;
+  __syncthreads();
+  // step 5: Dirichlet, write every block once, block-Jacobi inverses
+  if (t < np) {
+    const int row = r0 + r;
+    if (diag) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] = blk[WANT_H ? c : 0][t];
+    }
+    if (A.fixed && (A.fixed[row] | A.fixed[col])) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] = (diag && (c % 4) == 0) ? T(1) : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A.vals[(int64_t)c * A.nnzb + p0 + t] = acc[c];
+    if (diag && A.dinv) {
+      double a9[9], ri[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) a9[c] = double(acc[c]);
+      inverse3(a9, ri);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) A.dinv[9 * (int64_t)row + c] = T(ri[c]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // solver kernels
 // ---------------------------------------------------------------------------
 
@@ -1363,7 +1657,8 @@ __global__ __launch_bounds__(256) void k_check_finite(int64_t n, const double* _
 // host launchers
 // ---------------------------------------------------------------------------
 // Host side of the kind dispatch: f(std::integral_constant<int, KIND>) for a
-// set of kind `kind` (validated at mesh creation).
+// set of kind `kind` (validated at mesh creation); quadratic tets have kernels
+// of their own and are not dispatched here.
 template <typename F>
 static void host_with_kind(int kind, F&& f) {
   switch (kind) {
@@ -1373,7 +1668,8 @@ static void host_with_kind(int kind, F&& f) {
     case SYMX_NH_TET4: f(std::integral_constant<int, SYMX_NH_TET4>{}); break;
     case SYMX_STVK_TET4: f(std::integral_constant<int, SYMX_STVK_TET4>{}); break;
     case SYMX_FCR_TET4: f(std::integral_constant<int, SYMX_FCR_TET4>{}); break;
-    default: f(std::integral_constant<int, SYMX_ARAP_TET4>{}); break;
+    case SYMX_ARAP_TET4: f(std::integral_constant<int, SYMX_ARAP_TET4>{}); break;
+    default: break;
   }
 }
 
@@ -1397,6 +1693,14 @@ symx_status launch_energy(Mesh& m, const double* x, const double* xt, double dt,
   int off = 0;
   for (int s = 0; s < sd.n; ++s) {
     const int G = grid_for(sd.s[s].n_elem, 256, 8192);
+    if (sd.s[s].kind == SYMX_SNH_TET10) {
+      if (precision == SYMX_F32)
+        SYMX_LAUNCH(m, PNAME, k_energy_t10<float>, dim3(G), dim3(256), 0, sd.s[s], x, m.X,
+                    m.partials + off, m.nonfinite);
+      else
+        SYMX_LAUNCH(m, PNAME, k_energy_t10<double>, dim3(G), dim3(256), 0, sd.s[s], x, m.X,
+                    m.partials + off, m.nonfinite);
+    }
     host_with_kind(sd.s[s].kind, [&](auto kc) {
       constexpr int KIND = decltype(kc)::value;
       if (precision == SYMX_F32)
@@ -1429,6 +1733,10 @@ static symx_status elem_eval_t(Mesh& m, int set, const double* x, void* E, void*
   const SetDev& S = sd.s[set];
   const int G = grid_for(S.n_elem, 128, 65535);
   if (S.n_elem == 0) return SYMX_OK;
+  if (S.kind == SYMX_SNH_TET10) {
+    SYMX_LAUNCH(m, PNAME, k_elem_eval_t10<T>, dim3(grid_for(10 * S.n_elem, 64, 65535)), dim3(64),
+                0, S, x, m.X, (T*)E, (T*)g, (T*)H);
+  }
   host_with_kind(S.kind, [&](auto kc) {
     constexpr int KIND = decltype(kc)::value;
     SYMX_LAUNCH(m, PNAME, (k_elem_eval<T, KIND>), dim3(G), dim3(128), 0, S, x, m.X, (T*)E,
@@ -1577,7 +1885,14 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   // reads records and evaluates no element.
   uint32_t kinds = 0;
   for (const SetHost& s : m.sets) kinds |= 1u << s.kind;
-  if (inc_rows && want_H) {
+  if (m.quad) {
+    if (want_H && want_g)
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_t10<T, true, true>), grid, block, 0, A);
+    else if (want_H)
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_t10<T, false, true>), grid, block, 0, A);
+    else
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_t10<T, true, false>), grid, block, 0, A);
+  } else if (inc_rows && want_H) {
     if (want_g)
       SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, true, 0u>), grid, block, 0, A);
     else

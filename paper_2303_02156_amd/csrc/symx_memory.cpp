@@ -211,7 +211,9 @@ Topology::~Topology() {
   for (TopoSet& s : sets) dev_free(pool, s.d_conn);
 }
 
-static int kind_nodes(int kind) { return kind == SYMX_STVK_TRI3 ? 3 : 4; }
+static int kind_nodes(int kind) {
+  return kind == SYMX_STVK_TRI3 ? 3 : kind == SYMX_SNH_TET10 ? 10 : 4;
+}
 
 bool Topology::matches(const symx_mesh_desc& d) const {
   if (d.n_nodes != N || d.n_energies != (int)sets.size()) return false;

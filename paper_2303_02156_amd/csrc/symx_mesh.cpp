@@ -77,6 +77,7 @@ SetsDev Mesh::sets_dev() const {
     d.s[s].prm_stride = h.uniform ? 0 : kPrm;
     d.s[s].rot64 = h.d_rot64;
     d.s[s].rot32 = h.d_rot32;
+    d.s[s].conn10 = h.d_conn10;
   }
   return d;
 }
@@ -114,6 +115,7 @@ static void parallel_chunks(int64_t n, int64_t min_chunk, F f) {
 
 static int kind_nodes(int kind) {
   if (kind == SYMX_STVK_TRI3) return 3;
+  if (kind == SYMX_SNH_TET10) return 10;
   return kind >= SYMX_SNH_TET4 && kind <= SYMX_ARAP_TET4 ? 4 : 0;
 }
 
@@ -126,7 +128,7 @@ static symx_status validate_set(const symx_energy_desc& d, int64_t N, bool check
     set_error("unknown energy kind " + std::to_string(d.kind));
     return SYMX_ERR_INVALID_ARG;
   }
-  if (d.n_elem < 0 || (d.n_elem > 0 && !d.conn) || d.n_elem >= (int64_t(1) << 28)) {
+  if (d.n_elem < 0 || (d.n_elem > 0 && !d.conn) || d.n_elem >= (int64_t(1) << kMaxElemBits)) {
     set_error("invalid element count or connectivity pointer");
     return SYMX_ERR_INVALID_ARG;
   }
@@ -195,7 +197,11 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s,
   }
   // rest measures, element masses, hinge weights
   std::atomic<int64_t> bad{-1};
-  if (s.k == 4 && d.kind != SYMX_HINGE4) {
+  if ((s.k == 4 && d.kind != SYMX_HINGE4) || s.k == 10) {
+    // linear tets: rho V / 4 per node; quadratic tets keep rho V / 36 (the
+    // corner share of HRZ lumping, V of the corner tet), edge nodes get 16/3
+    // of it
+    const double share = s.k == 10 ? 1.0 / 36.0 : 0.25;
     elem_mass.resize(s.n_elem);
     parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
       for (int64_t e = e0; e < e1; ++e) {
@@ -203,7 +209,7 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s,
         V3 d1 = sub(P(e, 1), x0), d2 = sub(P(e, 2), x0), d3 = sub(P(e, 3), x0);
         const double vol = std::fabs(dot(d1, cross(d2, d3))) / 6.0;
         if (!(vol > 0.0)) note_first(bad, e);
-        elem_mass[e] = d.density * vol / 4.0;
+        elem_mass[e] = d.density * vol * share;
       }
     });
     if (bad >= 0) {
@@ -272,10 +278,14 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   for (int si = 0; si < d.n_energies; ++si) {
     TopoSet& ts = t.sets[si];
     ts.kind = d.energies[si].kind;
-    ts.k = ts.kind == SYMX_STVK_TRI3 ? 3 : 4;
+    ts.k = kind_nodes(ts.kind);
     ts.n_elem = d.energies[si].n_elem;
     ts.conn.assign(d.energies[si].conn, d.energies[si].conn + ts.n_elem * ts.k);
+    t.quad = t.quad || ts.k == 10;
   }
+  // incidences per batch, and slot bytes per incidence (see below)
+  const int inc_cap = t.quad ? kQuadInc : kRowWG;
+  const int KS = t.quad ? 10 : 4;
   const int64_t N = t.N;
   // Node -> incidences (set, element, local node), in (set, element) order:
   // a counting sort over the concatenated element list, split into
@@ -312,11 +322,12 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
         c += n;
       }
       cnt[i + 1] = c;
-      if (c > kRowWG) crowded = i;
+      if (c > inc_cap) crowded = i;
     }
   });
   if (crowded >= 0) {
-    set_error("node " + std::to_string(crowded.load()) + " belongs to more than 256 elements");
+    set_error("node " + std::to_string(crowded.load()) + " belongs to more than " +
+              std::to_string(inc_cap) + " elements");
     return SYMX_ERR_INVALID_ARG;
   }
   for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
@@ -339,10 +350,13 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   t.h_inc_ptr = cnt;
   // Rows in parallel chunks: sorted unique neighbour list of each node, and
   // for each incidence the row-local slots of its blocks in the relabelled
-  // node order (a first, then the others ascending).  Each thread marks the
-  // nodes already in the current row (mark[j] == row) and maps node -> slot
-  // (pos[j]), so a row costs O(incidences) plus a sort of its few columns.
-  uvector<uint32_t> slots(t.n_inc);
+  // node order.  Up to four nodes: a first, then the others ascending
+  // (slots[KS q + b], b = 0..3).  Quadratic tets: the nine other nodes in the
+  // order of the row function (kTet10Perm, position tet10_row_pos(a) left
+  // out), slots[KS q + j], j = 0..8.  Each thread marks the nodes already in
+  // the current row (mark[j] == row) and maps node -> slot (pos[j]), so a row
+  // costs O(incidences) plus a sort of its few columns.
+  uvector<uint8_t> slots(t.n_inc * KS);
   std::vector<int32_t> row_len(N);
   const int64_t n_chunks = std::min<int64_t>(64, std::max<int64_t>(1, N / 2048));
   std::vector<std::vector<int32_t>> chunk_cols(n_chunks);
@@ -378,16 +392,18 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
           const TopoSet& s = t.sets[si];
           const int a = inc_local(code[q]);
           const int64_t e = inc_elem(code[q]);
-          int order[4] = {a, -1, -1, -1};
-          for (int b = 0, o = 1; b < s.k; ++b)
-            if (b != a) order[o++] = b;
-          uint32_t w = 0;
-          for (int bp = 0; bp < 4; ++bp) {
-            const uint32_t sl =
-                bp < s.k ? (uint32_t)pos[s.conn[e * s.k + order[bp]]] : kNoSlot;
-            w |= (sl & 0xFFu) << (8 * bp);
+          uint8_t* sq = slots.data() + KS * q;
+          if (s.k == 10) {
+            const int r = tet10_row_pos(a);
+            for (int bp = 0, j = 0; bp < 10; ++bp)
+              if (bp != r) sq[j++] = (uint8_t)pos[s.conn[e * 10 + kTet10Perm.p[a][bp]]];
+          } else {
+            int order[4] = {a, -1, -1, -1};
+            for (int b = 0, o = 1; b < s.k; ++b)
+              if (b != a) order[o++] = b;
+            for (int bp = 0; bp < 4; ++bp)
+              sq[bp] = bp < s.k ? (uint8_t)pos[s.conn[e * s.k + order[bp]]] : (uint8_t)kNoSlot;
           }
-          slots[q] = w;
         }
         cols.insert(cols.end(), nb.begin(), nb.end());
       }
@@ -419,13 +435,14 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
     });
   }
   chunk_cols.clear();
-  // row batches: consecutive rows with <= kRowWG incidences and <= kRowWG blocks
+  // row batches: consecutive rows with <= inc_cap incidences and <= kRowWG
+  // blocks
   std::vector<int32_t> batch{0};
   int64_t bi = 0, bb = 0;
   for (int64_t i = 0; i < N; ++i) {
     const int64_t ni = cnt[i + 1] - cnt[i];
     const int64_t nbk = row_len[i];
-    if (i > batch.back() && (bi + ni > kRowWG || bb + nbk > kRowWG)) {
+    if (i > batch.back() && (bi + ni > inc_cap || bb + nbk > kRowWG)) {
       batch.push_back((int32_t)i);
       bi = bb = 0;
     }
@@ -435,9 +452,11 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   batch.push_back((int32_t)N);
   t.n_batch = (int)batch.size() - 1;
   // Off-diagonal contribution lists.  For every off-diagonal block of a batch,
-  // the (incidence, relabelled node b >= 1) pairs that add to it, in incidence
-  // order; entries are u16 = (incidence index within the batch << 2) | b.
-  // blk_info[p] = (first entry relative to the batch's base << 8) | count.
+  // the (incidence, relabelled node) pairs that add to it, in incidence order;
+  // entries are u16 = (incidence index within the batch << 2) | b with b >= 1
+  // the relabelled position, or (incidence << 4) | j for quadratic tets (j =
+  // 0..8, the row function's order).  blk_info[p] = (first entry relative to
+  // the batch's base << 8) | count.
   std::vector<int32_t> batch_entry(t.n_batch + 1, 0);
   for (int b = 0; b < t.n_batch; ++b) {
     int64_t ne = 0;
@@ -454,11 +473,13 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
       const int64_t q0 = cnt[r0], p0 = t.h_row_ptr[r0];
       const int64_t np = t.h_row_ptr[r1] - p0;
       cnt_blk.assign(np + 1, 0);
+      // the blocks an incidence adds to: slots j0..j0+k-2 of its entry
+      const int j0 = t.quad ? 0 : 1;
       for (int64_t r = r0; r < r1; ++r)
         for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
           const int k = t.sets[inc_set(code[q])].k;
-          for (int bp = 1; bp < k; ++bp)
-            cnt_blk[t.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0 + 1]++;
+          for (int j = j0; j < j0 + k - 1; ++j)
+            cnt_blk[t.h_row_ptr[r] + slots[KS * q + j] - p0 + 1]++;
         }
       for (int64_t i = 0; i < np; ++i) {
         if (cnt_blk[i + 1] > 255) batch_bad[b] = 1;
@@ -471,9 +492,10 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
       for (int64_t r = r0; r < r1; ++r)
         for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
           const int k = t.sets[inc_set(code[q])].k;
-          for (int bp = 1; bp < k; ++bp) {
-            const int64_t pl = t.h_row_ptr[r] + ((slots[q] >> (8 * bp)) & 0xFFu) - p0;
-            base[fillp[pl]++] = (uint16_t)(((q - q0) << 2) | bp);
+          for (int j = j0; j < j0 + k - 1; ++j) {
+            const int64_t pl = t.h_row_ptr[r] + slots[KS * q + j] - p0;
+            base[fillp[pl]++] =
+                (uint16_t)(t.quad ? (((q - q0) << 4) | j) : (((q - q0) << 2) | j));
           }
         }
     }
@@ -503,6 +525,10 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   TRY(upload(pool, stream, &t.centry, centry.data(), centry.size(), &nb));
   TRY(upload(pool, stream, &t.batch_entry, batch_entry.data(), batch_entry.size(), &nb));
   for (TopoSet& ts : t.sets) {
+    if (ts.k == 10) {
+      TRY(upload(pool, stream, &ts.d_conn10, ts.conn.data(), ts.conn.size(), &nb));
+      continue;
+    }
     uvector<int4> c4(std::max<int64_t>(ts.n_elem, 1));
     parallel_chunks(ts.n_elem, 65536, [&](int64_t e0, int64_t e1) {
       for (int64_t e = e0; e < e1; ++e) {
@@ -558,7 +584,9 @@ static void attach_topology(Mesh& m, std::shared_ptr<Topology> tp) {
   for (size_t s = 0; s < m.sets.size(); ++s) {
     m.sets[s].conn = t.sets[s].conn.data();
     m.sets[s].d_conn = t.sets[s].d_conn;
+    m.sets[s].d_conn10 = t.sets[s].d_conn10;
   }
+  m.quad = t.quad;
   m.topo = std::move(tp);
 }
 
@@ -627,6 +655,12 @@ symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool,
   if (d->fixed)
     for (int64_t i = 0; i < m->N; ++i) m->h_fixed[i] = d->fixed[i] ? 1 : 0;
   for (int s = 0; s < d->n_energies; ++s) TRY(validate_set(d->energies[s], m->N, false));
+  int n_quad = 0;
+  for (int s = 0; s < d->n_energies; ++s) n_quad += d->energies[s].kind == SYMX_SNH_TET10;
+  if (n_quad > 0 && n_quad < d->n_energies) {
+    set_error("a mesh with quadratic tets holds no other element kind");
+    return SYMX_ERR_INVALID_ARG;
+  }
   std::shared_ptr<Topology> topo;
   if (cache) topo = cache->find(*d, topology_hash(*d));
   if (!topo) {
@@ -645,8 +679,12 @@ symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool,
     for (int64_t i = i0; i < i1; ++i) {
       double mi = 0.0;
       for (int64_t q = t.h_inc_ptr[i]; q < t.h_inc_ptr[i + 1]; ++q) {
-        const std::vector<double>& em = elem_mass[inc_set(t.h_inc_code[q])];
-        if (!em.empty()) mi += em[inc_elem(t.h_inc_code[q])];
+        const uint32_t c = t.h_inc_code[q];
+        const std::vector<double>& em = elem_mass[inc_set(c)];
+        if (em.empty()) continue;
+        // quadratic tets: edge nodes carry 16/3 of the corner share
+        const bool edge = t.sets[inc_set(c)].k == 10 && inc_local(c) >= 4;
+        mi += edge ? em[inc_elem(c)] * (16.0 / 3.0) : em[inc_elem(c)];
       }
       m->h_mass[i] = mi;
     }

@@ -129,6 +129,10 @@ static symx_status project_into_records(Mesh& m, const double* x, int precision)
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g, bool want_H,
                      bool project, int precision, bool dirichlet, double* g_out,
                      void* dinv = nullptr) {
+  if (project && want_H && m.quad) {
+    set_error("per-element PSD projection is not available for quadratic tets");
+    return SYMX_ERR_INVALID_ARG;
+  }
   if (want_H) TRY(ensure_values(m, precision));
   if (project && want_H) {
     TRY(project_into_records(m, x, precision));

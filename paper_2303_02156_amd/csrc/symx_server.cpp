@@ -71,7 +71,7 @@ size_t estimate_request_bytes(const symx_mesh_desc& d, int precision, bool proje
   const size_t N = (size_t)d.n_nodes;
   size_t pairs = N, inc = 0, elems = 0, rot_elems = 0;
   for (int s = 0; s < d.n_energies; ++s) {
-    const int k = d.energies[s].kind == SYMX_STVK_TRI3 ? 3 : 4;
+    const int k = d.energies[s].kind == SYMX_STVK_TRI3 ? 3 : d.energies[s].kind == SYMX_SNH_TET10 ? 10 : 4;
     pairs += (size_t)d.energies[s].n_elem * k * (k - 1);
     inc += (size_t)d.energies[s].n_elem * k;
     elems += (size_t)d.energies[s].n_elem;
@@ -244,7 +244,7 @@ symx_status server_submit(Server* s, const symx_mesh_desc* d, const double* x, c
   sc.young.resize(d->n_energies);
   for (int e = 0; e < d->n_energies; ++e) {
     const symx_energy_desc& ed = d->energies[e];
-    const int k = ed.kind == SYMX_STVK_TRI3 ? 3 : 4;
+    const int k = ed.kind == SYMX_STVK_TRI3 ? 3 : ed.kind == SYMX_SNH_TET10 ? 10 : 4;
     if (ed.n_elem < 0 || (ed.n_elem > 0 && !ed.conn)) {
       set_error("invalid energy set in request");
       return SYMX_ERR_INVALID_ARG;
