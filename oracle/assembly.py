@@ -23,7 +23,7 @@ import scipy.sparse as sp
 
 from . import elements
 from .projection import project_psd
-from .rest import lumped_mass
+from .rest import lame, lumped_mass, young_array
 
 
 def pattern(scene):
@@ -97,7 +97,10 @@ def assemble(scene, x, x_tilde=None, dt=None, project=False, dirichlet=True,
 
     Returns dict(E, g, row_ptr, col_idx, vals, E_parts).  With x_tilde/dt the
     inertia term of the incremental potential is included.  project=True
-    replaces each element Hessian by its PSD projection before assembly.
+    replaces each element Hessian by its PSD projection before assembly;
+    project="filter" instead filters the density Hessian of Stable
+    Neo-Hookean tets (elements.snh_tet4_filtered) and projects the element
+    Hessians of every other kind.
     x_lag: positions of the lagged rotations (default: rest).
     """
     N = scene.n_nodes
@@ -111,13 +114,17 @@ def assemble(scene, x, x_tilde=None, dt=None, project=False, dirichlet=True,
     parts = []
     for es in scene.energies:
         Ee, ge, He = elements.element_eval(es, x, scene.X, want_hess, x_lag)
+        filtered = want_hess and project == "filter" and es.kind == 0
+        if filtered:
+            mu, lam = lame(young_array(es), es.poisson)
+            _, _, He = elements.snh_tet4_filtered(x[es.conn], scene.X[es.conn], mu, lam)
         parts.append(float(np.sum(Ee)))
         E_total += float(np.sum(Ee))
         c = es.conn
         k = c.shape[1]
         np.add.at(g, c.ravel(), ge.reshape(-1, 3))
         if want_hess:
-            if project:
+            if project and not filtered:
                 He = project_psd(He.reshape(-1, 3 * k, 3 * k)).reshape(He.shape)
             key = id(es)
             if key not in lookup:

@@ -20,6 +20,12 @@ Energies:
   Saint Venant-Kirchhoff, fixed co-rotational and as-rigid-as-possible with a
   volume term, the last two with the rotation R held constant over a time step
   (lagged, Sec. 6.1); R is the rotation closest to F at the lag positions.
+* Stable Neo-Hookean tet4 with the density Hessian filtered to PSD: the
+  element Hessian V B^T d2psi B is rebuilt from the 9x9 density Hessian
+  d2psi/dF2 with its negative eigenvalues set to zero (the eigensystem
+  approach of Smith et al. 2019, an alternative to projecting the 12x12
+  element Hessian; it differs from the nearest-PSD element Hessian unless B
+  is orthogonal up to scale).
 * Stable Neo-Hookean quadratic tet (tet10) -- Eq. 12: E_e = sum over the
   quadrature points xi_q of w_q |det J_X(xi_q)| psi(F(xi_q)), F = J_x J_X^-1,
   with the tet10 interpolation of App. A and a symmetric 4-point rule of
@@ -263,6 +269,22 @@ def _snh_density(F, mu_, lam_):
                 + lam_[:, None, None, None, None] * np.einsum("eij,ekl->eijkl", cof, cof)
                 + s2[:, None, None, None, None] * _hess_J(F))
     return psi, P, d2
+
+
+def snh_tet4_filtered(x, X, mu, lam):
+    """E, g and the filtered Hessian V sum b_aj b_bl [d2psi]+_ijkl of linear
+    SNH tets, [.]+ clamping the eigenvalues of the 9x9 matrix d2psi_(ij),(kl)
+    at zero (eigh)."""
+    mu_, lam_ = snh_reparam(np.asarray(mu, dtype=np.float64), np.asarray(lam, dtype=np.float64))
+    V, F, _, _, b = _tet_kinematics(x, X)
+    psi, P, d2 = _snh_density(F, mu_, lam_)
+    A = d2().reshape(-1, 9, 9)
+    w, Q = np.linalg.eigh(0.5 * (A + np.swapaxes(A, 1, 2)))
+    Ap = np.einsum("eij,ej,ekj->eik", Q, np.maximum(w, 0.0), Q).reshape(-1, 3, 3, 3, 3)
+    E = V * psi
+    g = V[:, None, None] * np.einsum("eij,eaj->eai", P, b)
+    H = V[:, None, None, None, None] * np.einsum("eaj,ebl,eijkl->eaibk", b, b, Ap)
+    return E, g, H
 
 
 def snh_tet10(x, X, mu, lam, want_hess=True, rule=None):

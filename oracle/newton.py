@@ -34,7 +34,7 @@ class StepParams:
     newton_rtol: float = 1e-6
     max_newton: int = 100
     max_pcg: int = 500
-    project: bool = False
+    project: bool | str = False        # True: nearest PSD; "filter": see assembly
     ls_max: int = 30
     armijo_c: float = 1e-4
     max_halvings: int = 8

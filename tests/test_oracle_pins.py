@@ -276,6 +276,72 @@ def test_closest_rotation():
 
 
 # ----------------------------------------------------------------------------
+# Stable Neo-Hookean tet4 with the density Hessian filtered to PSD
+# ----------------------------------------------------------------------------
+def _signed_svd(F):
+    U, s, Vt = np.linalg.svd(F)
+    d = np.sign(np.linalg.det(U) * np.linalg.det(Vt))
+    U[:, :, 2] *= np.where(np.linalg.det(U) < 0, -1.0, 1.0)[:, None]
+    Vt[:, 2, :] *= np.where(np.linalg.det(Vt) < 0, -1.0, 1.0)[:, None]
+    return U, s * np.stack([np.ones_like(d), np.ones_like(d), d], 1), Vt
+
+
+def test_snh_density_hessian_eigensystem():
+    """The eigenvalues of d2psi/dF2 (9x9) are, with the rotation-variant SVD
+    F = U diag(s) V^T (s3 < 0 when inverted): 2 psi_2 + psi_3 s_k (twists) and
+    2 psi_2 - psi_3 s_k (flips) for each pair, and those of the 3x3 scaling
+    block 2 psi_2 I + 4 psi_22 s s^T + psi_3 offdiag(s_k) + psi_33 c c^T with
+    c = (s2 s3, s1 s3, s1 s2) (Smith et al. 2019, for psi(I2, I3))."""
+    x, X = sg.random_tets(40, seed=81, inverted_frac=0.3)
+    mu_, lam_ = rest.snh_reparam(np.full(40, MU), np.full(40, LAM))
+    F = elements._cols(x) @ np.linalg.inv(elements._cols(X))
+    _, _, d2 = elements._snh_density(F, mu_, lam_)
+    ev = np.linalg.eigvalsh(d2().reshape(-1, 9, 9))
+    _, s, _ = _signed_svd(F)
+    I2 = np.sum(s * s, 1)
+    J = np.prod(s, 1)
+    alpha = 1.0 + mu_ / lam_ - mu_ / (4.0 * lam_)
+    p2 = 0.5 * mu_ * (1.0 - 1.0 / (I2 + 1.0))
+    p22 = 0.5 * mu_ / (I2 + 1.0) ** 2
+    p3 = lam_ * (J - alpha)
+    c = np.stack([s[:, 1] * s[:, 2], s[:, 0] * s[:, 2], s[:, 0] * s[:, 1]], 1)
+    A = (2 * p2[:, None, None] * np.eye(3) + 4 * p22[:, None, None] * np.einsum("ei,ej->eij", s, s)
+         + lam_[:, None, None] * np.einsum("ei,ej->eij", c, c))
+    for i, j, k in [(0, 1, 2), (0, 2, 1), (1, 2, 0)]:
+        A[:, i, j] += p3 * s[:, k]
+        A[:, j, i] += p3 * s[:, k]
+    closed = np.concatenate([np.linalg.eigvalsh(A), 2 * p2[:, None] + p3[:, None] * s,
+                             2 * p2[:, None] - p3[:, None] * s], 1)
+    assert np.allclose(np.sort(closed, 1), ev, rtol=1e-10, atol=1e-10 * np.abs(ev).max())
+
+
+def test_snh_filtered_hessian_properties():
+    """The filtered element Hessian is PSD, exceeds the raw one by a PSD
+    matrix (only negative directions are removed from d2psi), keeps the
+    gradient, matches the raw Hessian where d2psi is PSD (the rest state),
+    and rotates with the positions."""
+    x, X = sg.random_tets(60, seed=82, inverted_frac=0.3)
+    n = 60
+    mu, lam = np.full(n, MU), np.full(n, LAM)
+    E, g, H = elements.snh_tet4(x, X, mu, lam)
+    Ef, gf, Hf = elements.snh_tet4_filtered(x, X, mu, lam)
+    assert np.allclose(Ef, E, rtol=1e-13) and _rel(gf, g) < 1e-13
+    Hm, Hfm = H.reshape(n, 12, 12), Hf.reshape(n, 12, 12)
+    scale = np.abs(Hm).max()
+    assert np.linalg.eigvalsh(Hfm).min() > -1e-10 * scale
+    assert np.linalg.eigvalsh(Hfm - Hm).min() > -1e-10 * scale
+    assert np.linalg.eigvalsh(Hm).min() < -1e-3 * scale          # the raw one is indefinite
+    Xr = _tet_rest()
+    _, _, H0 = elements.snh_tet4(Xr, Xr, np.full(8, MU), np.full(8, LAM))
+    _, _, H0f = elements.snh_tet4_filtered(Xr, Xr, np.full(8, MU), np.full(8, LAM))
+    assert _rel(H0f, H0) < 1e-12
+    Q = _rot(83)
+    _, _, Hq = elements.snh_tet4_filtered(x @ Q.T, X, mu, lam)
+    QQ = np.kron(np.eye(4), Q)
+    assert _rel(Hq.reshape(n, 12, 12), QQ @ Hfm @ QQ.T) < 1e-11
+
+
+# ----------------------------------------------------------------------------
 # Quadratic tet (tet10), Eq. 12 with the App. A interpolation
 # ----------------------------------------------------------------------------
 def _tet10_random(n, seed, curved=0.1):
