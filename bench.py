@@ -615,8 +615,11 @@ def main():
         melem[name] = n_elem / (m * 1e-3) / 1e6
         log(f"eval+assembly {name}: {m:.3f} ms -> {melem[name]:.1f} Melem/s")
     if not args.no_projection:
-        for name, prec in (("f32_project", symx.SYMX_F32), ("f64_project", symx.SYMX_F64)):
-            m = time_assembly(prec, flags | symx.SYMX_PROJECT_PSD, 3)
+        for name, prec, fl in (("f32_project", symx.SYMX_F32, symx.SYMX_PROJECT_PSD),
+                               ("f64_project", symx.SYMX_F64, symx.SYMX_PROJECT_PSD),
+                               ("f32_filter", symx.SYMX_F32, symx.SYMX_PROJECT_FILTER),
+                               ("f64_filter", symx.SYMX_F64, symx.SYMX_PROJECT_FILTER)):
+            m = time_assembly(prec, flags | fl, 5)
             asm_ms[name] = m
             melem[name] = n_elem / (m * 1e-3) / 1e6
             log(f"eval+assembly {name}: {m:.3f} ms -> {melem[name]:.2f} Melem/s")

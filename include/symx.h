@@ -83,6 +83,12 @@ enum {
   SYMX_EVAL_GRAD = 2,
   SYMX_EVAL_HESS = 4,
   SYMX_PROJECT_PSD = 8,   /* project each element Hessian onto the PSD cone   */
+  SYMX_PROJECT_FILTER = 32, /* Stable Neo-Hookean tets: rebuild the element
+                             Hessian from the density Hessian d2psi/dF2 with
+                             its negative eigenvalues set to zero (analytic
+                             eigensystem, Smith et al. 2019); every other kind
+                             is projected as with SYMX_PROJECT_PSD.  Takes
+                             precedence over SYMX_PROJECT_PSD.              */
   SYMX_DIRICHLET = 16     /* zero gradient rows and Hessian rows/columns of
                              fixed nodes, identity diagonal block            */
 };
@@ -137,7 +143,8 @@ typedef struct {
   double newton_rtol;        /* stop when |g_free| <= rtol * |g_free(x(t))|     */
   int32_t max_newton;        /* Newton iterations per attempt                   */
   int32_t max_pcg;           /* PCG iterations per linear solve                 */
-  int32_t project;           /* 1: project element Hessians to PSD              */
+  int32_t project;           /* 0: none, 1: project element Hessians to PSD,
+                                2: as SYMX_PROJECT_FILTER                       */
   int32_t precision;         /* symx_precision                                  */
   int32_t max_halvings;      /* dt halvings before giving up                    */
   int32_t regrow_after;      /* successful steps before dt is doubled back      */
@@ -238,9 +245,11 @@ symx_status symx_mesh_update_rotations(symx_mesh mesh, const double* x_dev);
  * kernels enqueued past convergence only check a flag and return; a small
  * min_ms separates them).  kernel_names writes the known names, comma
  * separated, into buf (host, buf_len bytes).  Names: row_assemble_gH,
- * row_assemble_H, row_assemble_g, energy, reduce, elem_eval, project_psd,
- * pcg_init, pcg_spmv, pcg_update, residual64, dot64, x_tilde, lincomb64,
- * velocity, check_finite, accumulate. */
+ * row_assemble_H, row_assemble_g, energy, reduce, elem_eval, elem_filtered,
+ * project_psd, incidence_positions, elem_rows_projected, elem_rows_filtered,
+ * lagged_rotations, pcg_init, pcg_spmv, pcg_update, residual64, dot64,
+ * x_tilde, lincomb64, velocity, check_finite, accumulate (those launched
+ * since profiling was enabled). */
 symx_status symx_mesh_set_profiling(symx_mesh mesh, int32_t enable);
 symx_status symx_mesh_get_kernel_time(symx_mesh mesh, const char* name, double min_ms,
                                       int64_t* launches, double* total_ms);

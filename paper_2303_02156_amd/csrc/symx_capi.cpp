@@ -45,7 +45,7 @@ symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool = 
 void build_scatter(Mesh& m);
 void free_workspace(Mesh& m);
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
-                     bool want_H, bool project, int precision, bool dirichlet, double* g_out,
+                     bool want_H, int project, int precision, bool dirichlet, double* g_out,
                      void* dinv);
 symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E);
 symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P,
@@ -200,17 +200,24 @@ symx_status symx_eval_derivatives(symx_mesh mesh, int32_t energy_index, const do
   void* E = (flags & SYMX_EVAL_E) ? elem_E : nullptr;
   void* g = (flags & SYMX_EVAL_GRAD) ? elem_grad : nullptr;
   void* H = (flags & SYMX_EVAL_HESS) ? elem_hess : nullptr;
-  if ((flags & SYMX_PROJECT_PSD) && !H) {
-    set_error("SYMX_PROJECT_PSD needs SYMX_EVAL_HESS and a Hessian buffer");
+  const bool filter = (flags & SYMX_PROJECT_FILTER) != 0;
+  const bool proj = filter || (flags & SYMX_PROJECT_PSD) != 0;
+  if (proj && !H) {
+    set_error("SYMX_PROJECT_PSD and SYMX_PROJECT_FILTER need SYMX_EVAL_HESS and a Hessian buffer");
     return SYMX_ERR_INVALID_ARG;
   }
-  if ((flags & SYMX_PROJECT_PSD) && m.sets[energy_index].k == 10) {
+  if (proj && m.sets[energy_index].k == 10) {
     set_error("per-element PSD projection is not available for quadratic tets");
     return SYMX_ERR_INVALID_ARG;
   }
+  if (filter && m.sets[energy_index].kind == SYMX_SNH_TET4) {
+    symx_status st = launch_elem_filtered(m, energy_index, x_dev, precision, E, g, H);
+    if (st != SYMX_OK) return st;
+    return hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize");
+  }
   symx_status st = launch_elem_eval(m, energy_index, x_dev, (int)flags, precision, E, g, H);
   if (st != SYMX_OK) return st;
-  if (flags & SYMX_PROJECT_PSD) {
+  if (proj) {
     const SetHost& s = m.sets[energy_index];
     st = launch_project(m, precision, H, s.n_elem, 3 * s.k);
     if (st != SYMX_OK) return st;
@@ -233,8 +240,8 @@ symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double*
   }
   const bool want_g = (flags & SYMX_EVAL_GRAD) != 0;
   const bool want_H = (flags & SYMX_EVAL_HESS) != 0;
-  symx_status st = assemble(m, x_dev, x_tilde_dev, dt, want_g, want_H,
-                            (flags & SYMX_PROJECT_PSD) != 0, precision,
+  const int project = (flags & SYMX_PROJECT_FILTER) ? 2 : (flags & SYMX_PROJECT_PSD) ? 1 : 0;
+  symx_status st = assemble(m, x_dev, x_tilde_dev, dt, want_g, want_H, project, precision,
                             (flags & SYMX_DIRICHLET) != 0, grad_dev, nullptr);
   if (st != SYMX_OK) return st;
   if (flags & SYMX_EVAL_E) {
@@ -259,7 +266,8 @@ symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
   if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
   if (!x_dev || !v_dev || !params || !(params->dt > 0.0) || params->max_newton < 0 ||
       params->max_pcg < 1 || params->precision < SYMX_F64 || params->precision > SYMX_F32_REFINED ||
-      params->max_halvings < 0 || !(params->newton_rtol >= 0.0)) {
+      params->max_halvings < 0 || !(params->newton_rtol >= 0.0) || params->project < 0 ||
+      params->project > 2) {
     set_error("invalid arguments to symx_newton_step");
     return SYMX_ERR_INVALID_ARG;
   }

@@ -354,6 +354,9 @@ symx_status launch_elem_eval(Mesh& m, int set, const double* x, int want, int pr
                              void* E, void* g, void* H);
 // In-place nearest-PSD projection of n element Hessians (dim x dim each).
 symx_status launch_project(Mesh& m, int precision, void* H, int64_t n, int dim);
+// Per-element E, g and filtered H of a Stable Neo-Hookean set.
+symx_status launch_elem_filtered(Mesh& m, int set, const double* x, int precision, void* E,
+                                 void* g, void* H);
 // Row assembly: gradient (FP64, may be null) and/or Hessian (precision).
 // inc_rows: projected path, read each incidence's row from the incidence
 // records (kIncRec values each) instead of evaluating it.
@@ -365,7 +368,9 @@ symx_status launch_row_assemble(Mesh& m, const double* x, const double* x_tilde,
 // Incidence positions (inverse of the incidence codes), n_inc ints.
 symx_status launch_incidence_positions(Mesh& m, int* inc_pos);
 // Projected element rows into the incidence records (n_inc x 32, precision).
-symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precision,
+// mode 1: nearest-PSD element Hessians; 2: Stable Neo-Hookean sets filtered
+// (analytic eigensystem of the density Hessian), other sets as mode 1.
+symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precision, int mode,
                                             const int* inc_pos, void* rows);
 // Lagged rotations of every fixed co-rotational / ARAP set: the rotation
 // closest to each element's deformation gradient at positions x.

@@ -269,14 +269,13 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
   c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-// R = argmax tr(R^T F) over rotations (the rotation factor of the polar
-// decomposition, with the sign of det F put on the smallest singular value).
-// F^T F = V diag(s^2) V^T by cyclic Jacobi, columns sorted by decreasing s;
-// u1 = F v1 / |F v1|, u2 = F v2 made orthogonal to u1 and normalised,
-// u3 = u1 x u2, v3 = v1 x v2, so U and V are proper rotations and R = U V^T.
-// Rank-deficient F (non-unique maximiser) takes any completion; F = 0
-// gives R = I.
-__device__ void closest_rotation3(const double (&F)[3][3], double (&R)[3][3]) {
+// Rotation-variant SVD F = U diag(s) V^T with U, V proper rotations and s3
+// carrying the sign of det F.  F^T F = V diag(s^2) V^T by cyclic Jacobi,
+// columns sorted by decreasing s^2; u1 = F v1 / |F v1|, u2 = F v2 made
+// orthogonal to u1 and normalised, u3 = u1 x u2, v3 = v1 x v2, and s_k =
+// u_k . F v_k.  A rank-deficient F takes any completion; F = 0 gives U = V.
+__device__ void svd3(const double (&F)[3][3], double (&U)[3][3], double (&s)[3],
+                     double (&V)[3][3]) {
   double a[3][3], v[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -293,7 +292,6 @@ __device__ void closest_rotation3(const double (&F)[3][3], double (&R)[3][3]) {
     jacobi3_rotate<0, 2>(a, v);
     jacobi3_rotate<1, 2>(a, v);
   }
-  // the two largest eigenvalues' columns
   int i1 = 0, i2 = 1, i3 = 2;
   auto swap_if = [&](int& p, int& q) {
     const double lp = p == 0 ? a[0][0] : p == 1 ? a[1][1] : a[2][2];
@@ -322,9 +320,12 @@ __device__ void closest_rotation3(const double (&F)[3][3], double (&R)[3][3]) {
   const double n1 = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
   if (!(n1 > 0.0)) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) R[i][j] = i == j ? 1.0 : 0.0;
+    for (int r = 0; r < 3; ++r) {
+      U[r][0] = V[r][0] = v1[r];
+      U[r][1] = V[r][1] = v2[r];
+      U[r][2] = V[r][2] = v3[r];
+      s[r] = 0.0;
+    }
     return;
   }
 #pragma unroll
@@ -344,10 +345,267 @@ __device__ void closest_rotation3(const double (&F)[3][3], double (&R)[3][3]) {
 #pragma unroll
   for (int r = 0; r < 3; ++r) u2[r] /= n2;
   cross3(u1, u2, u3);
+  double fv[3][3];  // F v_k
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    fv[0][r] = n1 * u1[r];
+    fv[1][r] = F[r][0] * v2[0] + F[r][1] * v2[1] + F[r][2] * v2[2];
+    fv[2][r] = F[r][0] * v3[0] + F[r][1] * v3[1] + F[r][2] * v3[2];
+  }
+  s[0] = n1;
+  s[1] = u2[0] * fv[1][0] + u2[1] * fv[1][1] + u2[2] * fv[1][2];
+  s[2] = u3[0] * fv[2][0] + u3[1] * fv[2][1] + u3[2] * fv[2][2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    U[r][0] = u1[r];
+    U[r][1] = u2[r];
+    U[r][2] = u3[r];
+    V[r][0] = v1[r];
+    V[r][1] = v2[r];
+    V[r][2] = v3[r];
+  }
+}
+
+// R = argmax tr(R^T F) over rotations (the rotation factor of the polar
+// decomposition, with the sign of det F put on the smallest singular value):
+// R = U V^T of the rotation-variant SVD, which maximises tr(R^T F) because the
+// sign of det F sits on the smallest singular value.  F = 0 gives R = I.
+__device__ void closest_rotation3(const double (&F)[3][3], double (&R)[3][3]) {
+  double U[3][3], sv[3], V[3][3];
+  svd3(F, U, sv, V);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) R[i][j] = u1[i] * v1[j] + u2[i] * v2[j] + u3[i] * v3[j];
+    for (int j = 0; j < 3; ++j) R[i][j] = U[i][0] * V[j][0] + U[i][1] * V[j][1] + U[i][2] * V[j][2];
+}
+
+// ---------------------------------------------------------------------------
+// Stable Neo-Hookean tets with the density Hessian filtered to PSD through its
+// analytic eigensystem (Smith et al. 2019, for energies of I2 = |F|^2 and
+// I3 = det F): with the rotation-variant SVD F = U diag(s) V^T and
+// perturbations D = U Dh V^T, the nine eigenvectors of d2psi/dF2 are
+//  * for each pair (i, j), k the third index, the twist Dh_ij = -Dh_ji with
+//    eigenvalue 2 psi_2 + psi_3 s_k and the flip Dh_ij = Dh_ji with
+//    2 psi_2 - psi_3 s_k;
+//  * three scaling modes (diagonal Dh), the eigenvectors of the 3x3 block
+//    2 psi_2 I + 4 psi_22 s s^T + psi_33 c c^T + psi_3 s_k off the diagonal,
+//    c = (s2 s3, s1 s3, s1 s2).
+// Negative eigenvalues are set to zero.  With the shape gradients b_a and
+// c_a = V^T b_a, the filtered block of nodes (a, b) is vol U K_ab U^T with
+// K_ab = diag(c_a) A+ diag(c_b) plus, per pair, the twist/flip terms.  All in
+// float64 (on this chip it issues at the float32 rate).
+// ---------------------------------------------------------------------------
+struct SnhFilter {
+  double vol;
+  double U[3][3];
+  double c[4][3];      // V^T b_a
+  double Ap[3][3];     // filtered scaling block
+  double sp[3], dp[3]; // per pair (0,1), (0,2), (1,2): (l_twist + l_flip)/2, (l_flip - l_twist)/2
+  double g[4][3];      // gradient vol P b_a
+};
+
+__device__ void snh_filter(const SetDev& S, int64_t e, const double* __restrict__ x,
+                           const double* __restrict__ X, SnhFilter& f) {
+  const int4 cn = S.conn[e];
+  const int nd[4] = {cn.x, cn.y, cn.z, cn.w};
+  double Ds[3][3], Dm[3][3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      Ds[r][b] = x[3 * (int64_t)nd[b + 1] + r] - x[3 * (int64_t)nd[0] + r];
+      Dm[r][b] = X[3 * (int64_t)nd[b + 1] + r] - X[3 * (int64_t)nd[0] + r];
+    }
+  double Mi[3][3];  // adj(Dm)
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int j1 = (j + 1) % 3, j2 = (j + 2) % 3, i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+      Mi[i][j] = Dm[j1][i1] * Dm[j2][i2] - Dm[j1][i2] * Dm[j2][i1];
+    }
+  const double det = Dm[0][0] * Mi[0][0] + Dm[0][1] * Mi[1][0] + Dm[0][2] * Mi[2][0];
+  f.vol = fabs(det) / 6.0;
+  double B[4][3];  // shape gradients: rows of Dm^-1, b_0 = -their sum
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    B[1][j] = Mi[0][j] / det;
+    B[2][j] = Mi[1][j] / det;
+    B[3][j] = Mi[2][j] / det;
+    B[0][j] = -(B[1][j] + B[2][j] + B[3][j]);
+  }
+  double F[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      F[i][j] = Ds[i][0] * B[1][j] + Ds[i][1] * B[2][j] + Ds[i][2] * B[3][j];
+  const int st = S.prm_stride;
+  const double mu = ld_prm(S.prm64, st, e, 0), lam = ld_prm(S.prm64, st, e, 1);
+  const double mu_ = mu * (4.0 / 3.0), lam_ = lam + mu * (5.0 / 6.0);
+  const double alpha = 1.0 + mu_ / lam_ - mu_ / (4.0 * lam_);
+  double V[3][3], sv[3];
+  svd3(F, f.U, sv, V);
+  const double I2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
+  const double J = sv[0] * sv[1] * sv[2];
+  const double p2 = 0.5 * mu_ * (1.0 - 1.0 / (I2 + 1.0));
+  const double p22 = 0.5 * mu_ / ((I2 + 1.0) * (I2 + 1.0));
+  const double p3 = lam_ * (J - alpha);
+  const double p33 = lam_;
+  // gradient: P = 2 psi_2 F + psi_3 cof F
+  double cof[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+      cof[i][j] = F[i1][j1] * F[i2][j2] - F[i1][j2] * F[i2][j1];
+    }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc += (2.0 * p2 * F[i][j] + p3 * cof[i][j]) * B[a][j];
+      f.g[a][i] = f.vol * acc;
+    }
+  // c_a = V^T b_a
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) f.c[a][m] = V[0][m] * B[a][0] + V[1][m] * B[a][1] + V[2][m] * B[a][2];
+  // scaling block, its eigensystem, the filtered block
+  const double cc[3] = {sv[1] * sv[2], sv[0] * sv[2], sv[0] * sv[1]};
+  double A[3][3], W[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      A[i][j] = 4.0 * p22 * sv[i] * sv[j] + p33 * cc[i] * cc[j] +
+                (i == j ? 2.0 * p2 : p3 * sv[3 - i - j]);
+      W[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (!(off > 1e-34 * dia)) break;
+    jacobi3_rotate<0, 1>(A, W);
+    jacobi3_rotate<0, 2>(A, W);
+    jacobi3_rotate<1, 2>(A, W);
+  }
+  const double l0 = fmax(A[0][0], 0.0), l1 = fmax(A[1][1], 0.0), l2 = fmax(A[2][2], 0.0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      f.Ap[i][j] = l0 * W[i][0] * W[j][0] + l1 * W[i][1] * W[j][1] + l2 * W[i][2] * W[j][2];
+  // twist / flip of the pairs (0,1), (0,2), (1,2); the third index is 2, 1, 0
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const double sk = sv[2 - p];
+    const double lt = fmax(2.0 * p2 + p3 * sk, 0.0), lf = fmax(2.0 * p2 - p3 * sk, 0.0);
+    f.sp[p] = 0.5 * (lt + lf);
+    f.dp[p] = 0.5 * (lf - lt);
+  }
+}
+
+// Filtered Hessian block of nodes (a, b): vol U K_ab U^T.
+__device__ __forceinline__ void snh_filter_block(const SnhFilter& f, int a, int b,
+                                                 double (&H)[3][3]) {
+  double K[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) K[i][j] = f.c[a][i] * f.Ap[i][j] * f.c[b][j];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int i = p == 2 ? 1 : 0, j = p == 0 ? 1 : 2;
+    K[i][i] += f.sp[p] * f.c[a][j] * f.c[b][j];
+    K[j][j] += f.sp[p] * f.c[a][i] * f.c[b][i];
+    K[i][j] += f.dp[p] * f.c[a][j] * f.c[b][i];
+    K[j][i] += f.dp[p] * f.c[a][i] * f.c[b][j];
+  }
+  double KU[3][3];  // K U^T
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      KU[i][k] = K[i][0] * f.U[k][0] + K[i][1] * f.U[k][1] + K[i][2] * f.U[k][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      H[i][k] = f.vol * (f.U[i][0] * KU[0][k] + f.U[i][1] * KU[1][k] + f.U[i][2] * KU[2][k]);
+}
+
+// Filtered rows of every incidence of a Stable Neo-Hookean set into the
+// incidence-ordered records (the layout of k_elem_rows_projected*).
+template <typename T>
+__global__ __launch_bounds__(64) void k_elem_rows_filtered(SetDev S, const double* __restrict__ x,
+                                                          const double* __restrict__ X,
+                                                          const int* __restrict__ inc_pos,
+                                                          T* __restrict__ rows) {
+  for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < S.n_elem;
+       e += (int64_t)gridDim.x * 64) {
+    SnhFilter f;
+    snh_filter(S, e, x, X, f);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      T* rec = rows + (int64_t)inc_pos[e * 4 + a] * kIncRec;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rec[i] = T(f.g[a][i]);
+#pragma unroll
+      for (int bp = 1; bp < 4; ++bp) {
+        const int b = bp <= a ? bp - 1 : bp;
+        double H[3][3];
+        snh_filter_block(f, a, b, H);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) rec[3 + 9 * i + 3 * (bp - 1) + k] = T(H[i][k]);
+      }
+    }
+  }
+}
+
+// Element-major E, gradient (n x 12) and filtered Hessian (n x 12 x 12) of a
+// Stable Neo-Hookean set (the per-element interface).
+template <typename T>
+__global__ __launch_bounds__(64) void k_elem_filtered(SetDev S, const double* __restrict__ x,
+                                                     const double* __restrict__ X,
+                                                     T* __restrict__ Eo, T* __restrict__ go,
+                                                     T* __restrict__ Ho) {
+  for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < S.n_elem;
+       e += (int64_t)gridDim.x * 64) {
+    SnhFilter f;
+    snh_filter(S, e, x, X, f);
+    if (Eo) {
+      T in[kMaxIn], out[1];
+      elem_inputs<T, SYMX_SNH_TET4>(S, e, identity_order(S.conn[e]), x, X, in);
+      gen_s_E<T, SYMX_SNH_TET4>(in, out);
+      Eo[e] = out[0];
+    }
+    if (go) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) go[e * 12 + 3 * a + i] = T(f.g[a][i]);
+    }
+    if (Ho) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          double H[3][3];
+          snh_filter_block(f, a, b, H);
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Ho[e * 144 + (3 * a + i) * 12 + 3 * b + k] = T(H[i][k]);
+        }
+    }
+  }
 }
 
 // One lane per element: F = Ds Dm^-1 at positions x (node order of the
@@ -1780,7 +2038,7 @@ symx_status launch_incidence_positions(Mesh& m, int* inc_pos) {
   return SYMX_OK;
 }
 
-symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precision,
+symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precision, int mode,
                                             const int* inc_pos, void* rows) {
   const char* PNAME = "elem_rows_projected";
   const SetsDev sd = m.sets_dev();
@@ -1791,6 +2049,16 @@ symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precis
     first += S.n_elem * S.k;
     if (S.n_elem == 0) continue;
     const int G = grid_for(S.n_elem, 64, 65535);
+    if (mode == 2 && S.kind == SYMX_SNH_TET4) {
+      if (precision == SYMX_F32)
+        SYMX_LAUNCH(m, "elem_rows_filtered", k_elem_rows_filtered<float>, dim3(G), dim3(64), 0, S,
+                    x, m.X, ip, (float*)rows);
+      else
+        SYMX_LAUNCH(m, "elem_rows_filtered", k_elem_rows_filtered<double>, dim3(G), dim3(64), 0,
+                    S, x, m.X, ip, (double*)rows);
+      LAUNCH_CHECK("k_elem_rows_filtered");
+      continue;
+    }
     host_with_kind(S.kind, [&](auto kc) {
       constexpr int KIND = decltype(kc)::value;
       if (precision == SYMX_F32)
@@ -1802,6 +2070,22 @@ symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precis
     });
     LAUNCH_CHECK("k_elem_rows_projected");
   }
+  return SYMX_OK;
+}
+
+symx_status launch_elem_filtered(Mesh& m, int set, const double* x, int precision, void* E,
+                                 void* g, void* H) {
+  const char* PNAME = "elem_filtered";
+  const SetDev S = m.sets_dev().s[set];
+  if (S.n_elem == 0) return SYMX_OK;
+  const int G = grid_for(S.n_elem, 64, 65535);
+  if (precision == SYMX_F32)
+    SYMX_LAUNCH(m, PNAME, k_elem_filtered<float>, dim3(G), dim3(64), 0, S, x, m.X, (float*)E,
+                (float*)g, (float*)H);
+  else
+    SYMX_LAUNCH(m, PNAME, k_elem_filtered<double>, dim3(G), dim3(64), 0, S, x, m.X, (double*)E,
+                (double*)g, (double*)H);
+  LAUNCH_CHECK("k_elem_filtered");
   return SYMX_OK;
 }
 

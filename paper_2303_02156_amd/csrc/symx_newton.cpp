@@ -108,7 +108,7 @@ static symx_status read_window(Mesh& m, double* win, bool* bad) {
 
 // Projected path: incidence positions and records (allocated on first use),
 // then the fused evaluation + projection of every element into the records.
-static symx_status project_into_records(Mesh& m, const double* x, int precision) {
+static symx_status project_into_records(Mesh& m, const double* x, int precision, int mode) {
   if (!m.inc_pos) {
     TRY(dev_alloc(m.pool, (void**)&m.inc_pos, m.n_inc * sizeof(int)));
     TRY(launch_incidence_positions(m, m.inc_pos));
@@ -121,13 +121,13 @@ static symx_status project_into_records(Mesh& m, const double* x, int precision)
     TRY(dev_alloc(m.pool, &m.inc_rows, need));
     m.inc_rows_bytes = need;
   }
-  return launch_incidence_rows_projected(m, x, precision, m.inc_pos, m.inc_rows);
+  return launch_incidence_rows_projected(m, x, precision, mode, m.inc_pos, m.inc_rows);
 }
 
 // Assemble gradient (float64) and/or Hessian values (precision) at x.  With
 // dinv, the block-Jacobi inverses (N x 9, precision's type) are produced too.
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g, bool want_H,
-                     bool project, int precision, bool dirichlet, double* g_out,
+                     int project, int precision, bool dirichlet, double* g_out,
                      void* dinv = nullptr) {
   if (project && want_H && m.quad) {
     set_error("per-element PSD projection is not available for quadratic tets");
@@ -135,7 +135,7 @@ symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool
   }
   if (want_H) TRY(ensure_values(m, precision));
   if (project && want_H) {
-    TRY(project_into_records(m, x, precision));
+    TRY(project_into_records(m, x, precision, project));
     return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, m.inc_rows, g_out,
                                dinv);
   }
@@ -259,10 +259,10 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
     auto t0 = clk::now();
     // gradient, Hessian and the block-Jacobi inverses (workspace pcg[0])
     if (pe == ph) {
-      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project != 0, ph, true, w->g, w->pcg[0]));
+      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project, ph, true, w->g, w->pcg[0]));
     } else {
       TRY(assemble(m, w->xk, w->xt, dt, true, false, false, pe, true, w->g));
-      TRY(assemble(m, w->xk, w->xt, dt, false, true, P.project != 0, ph, true, nullptr,
+      TRY(assemble(m, w->xk, w->xt, dt, false, true, P.project, ph, true, nullptr,
                    w->pcg[0]));
     }
     TRY(launch_dot64(m, w->g, w->g, n, m.scalars + D_GG));
