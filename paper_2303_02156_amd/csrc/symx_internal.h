@@ -359,12 +359,13 @@ symx_status launch_elem_filtered(Mesh& m, int set, const double* x, int precisio
                                  void* g, void* H);
 // Row assembly: gradient (FP64, may be null) and/or Hessian (precision).
 // inc_rows: projected path, read each incidence's row from the incidence
-// records (kIncRec values each) instead of evaluating it.
+// records (kIncRec values each) instead of evaluating it.  filter: every set
+// is Stable Neo-Hookean; evaluate each row with the filtered density Hessian.
 // dinv (optional): the kernel also writes the inverses of the final diagonal
 // blocks (N x 9, precision's type).
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* x_tilde, double dt,
                                 bool want_g, bool want_H, int precision, bool dirichlet,
-                                const void* inc_rows, double* g_out, void* dinv);
+                                const void* inc_rows, bool filter, double* g_out, void* dinv);
 // Incidence positions (inverse of the incidence codes), n_inc ints.
 symx_status launch_incidence_positions(Mesh& m, int* inc_pos);
 // Projected element rows into the incidence records (n_inc x 32, precision).

@@ -42,6 +42,16 @@ __device__ __forceinline__ int xcd_remap(int i, int n) {
   return x * q + (x < r ? x : r) + j;
 }
 
+// Reciprocal, reciprocal square root and square root of the small rotation
+// solvers: the hardware approximations in float (about 1 ulp), correctly
+// rounded in double.
+__device__ __forceinline__ float rot_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rot_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float rot_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double rot_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ double rot_rsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ double rot_sqrt(double x) { return sqrt(x); }
+
 template <typename T>
 __device__ __forceinline__ T ld_prm(const T* p, int stride, int64_t e, int k) {
   return p[(int64_t)stride * e + k];
@@ -241,32 +251,48 @@ __device__ __forceinline__ void with_kind(int kind, F&& f) {
 // One Jacobi rotation of the symmetric 3x3 matrix a in the (P, Q) plane,
 // accumulated into the columns of v: tan(phi) = t is the root of smaller
 // magnitude of t^2 + 2 t cot(2 phi) - 1 = 0, cot(2 phi) = (a_QQ - a_PP) / 2a_PQ.
-template <int P, int Q>
-__device__ __forceinline__ void jacobi3_rotate(double (&a)[3][3], double (&v)[3][3]) {
+template <int P, int Q, typename R>
+__device__ __forceinline__ void jacobi3_rotate(R (&a)[3][3], R (&v)[3][3]) {
   constexpr int Rr = 3 - P - Q;  // the third index
-  const double apq = a[P][Q];
-  if (apq == 0.0) return;
-  const double d = a[Q][Q] - a[P][P];
-  const double t = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
-  const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+  const R apq = a[P][Q];
+  if (apq == R(0)) return;
+  const R d = a[Q][Q] - a[P][P];
+  const R t = (d >= R(0) ? R(2) : R(-2)) * apq * rot_rcp(fabs(d) + rot_sqrt(d * d + R(4) * apq * apq));
+  const R c = rot_rsq(R(1) + t * t), s = t * c;
   a[P][P] -= t * apq;
   a[Q][Q] += t * apq;
-  a[P][Q] = a[Q][P] = 0.0;
-  const double arp = a[Rr][P], arq = a[Rr][Q];
+  a[P][Q] = a[Q][P] = R(0);
+  const R arp = a[Rr][P], arq = a[Rr][Q];
   a[Rr][P] = a[P][Rr] = c * arp - s * arq;
   a[Rr][Q] = a[Q][Rr] = s * arp + c * arq;
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    const double vp = v[r][P], vq = v[r][Q];
+    const R vp = v[r][P], vq = v[r][Q];
     v[r][P] = c * vp - s * vq;
     v[r][Q] = s * vp + c * vq;
   }
 }
 
-__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
+template <typename R>
+__device__ __forceinline__ void cross3(const R* a, const R* b, R* c) {
   c[0] = a[1] * b[2] - a[2] * b[1];
   c[1] = a[2] * b[0] - a[0] * b[2];
   c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Cyclic Jacobi sweeps on a symmetric 3x3 matrix until the squared
+// off-diagonal falls below tol times the squared diagonal (at most 16 sweeps).
+template <typename R>
+__device__ __forceinline__ void jacobi3(R (&a)[3][3], R (&v)[3][3]) {
+  const R tol = sizeof(R) == 4 ? R(1e-12) : R(1e-34);
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    const R off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const R dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (!(off > tol * dia)) break;
+    jacobi3_rotate<0, 1>(a, v);
+    jacobi3_rotate<0, 2>(a, v);
+    jacobi3_rotate<1, 2>(a, v);
+  }
 }
 
 // Rotation-variant SVD F = U diag(s) V^T with U, V proper rotations and s3
@@ -274,28 +300,21 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
 // columns sorted by decreasing s^2; u1 = F v1 / |F v1|, u2 = F v2 made
 // orthogonal to u1 and normalised, u3 = u1 x u2, v3 = v1 x v2, and s_k =
 // u_k . F v_k.  A rank-deficient F takes any completion; F = 0 gives U = V.
-__device__ void svd3(const double (&F)[3][3], double (&U)[3][3], double (&s)[3],
-                     double (&V)[3][3]) {
-  double a[3][3], v[3][3];
+template <typename R>
+__device__ void svd3(const R (&F)[3][3], R (&U)[3][3], R (&s)[3], R (&V)[3][3]) {
+  R a[3][3], v[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       a[i][j] = F[0][i] * F[0][j] + F[1][i] * F[1][j] + F[2][i] * F[2][j];
-      v[i][j] = i == j ? 1.0 : 0.0;
+      v[i][j] = i == j ? R(1) : R(0);
     }
-  for (int sweep = 0; sweep < 16; ++sweep) {
-    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
-    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
-    if (!(off > 1e-34 * dia)) break;
-    jacobi3_rotate<0, 1>(a, v);
-    jacobi3_rotate<0, 2>(a, v);
-    jacobi3_rotate<1, 2>(a, v);
-  }
+  jacobi3(a, v);
   int i1 = 0, i2 = 1, i3 = 2;
   auto swap_if = [&](int& p, int& q) {
-    const double lp = p == 0 ? a[0][0] : p == 1 ? a[1][1] : a[2][2];
-    const double lq = q == 0 ? a[0][0] : q == 1 ? a[1][1] : a[2][2];
+    const R lp = p == 0 ? a[0][0] : p == 1 ? a[1][1] : a[2][2];
+    const R lq = q == 0 ? a[0][0] : q == 1 ? a[1][1] : a[2][2];
     if (lq > lp) {
       const int t = p;
       p = q;
@@ -305,7 +324,7 @@ __device__ void svd3(const double (&F)[3][3], double (&U)[3][3], double (&s)[3],
   swap_if(i1, i2);
   swap_if(i1, i3);
   swap_if(i2, i3);
-  double v1[3], v2[3], v3[3], u1[3], u2[3], u3[3];
+  R v1[3], v2[3], v3[3], u1[3], u2[3], u3[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     v1[r] = i1 == 0 ? v[r][0] : i1 == 1 ? v[r][1] : v[r][2];
@@ -317,35 +336,36 @@ __device__ void svd3(const double (&F)[3][3], double (&U)[3][3], double (&s)[3],
     u1[r] = F[r][0] * v1[0] + F[r][1] * v1[1] + F[r][2] * v1[2];
     u2[r] = F[r][0] * v2[0] + F[r][1] * v2[1] + F[r][2] * v2[2];
   }
-  const double n1 = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
-  if (!(n1 > 0.0)) {
+  const R n1 = rot_sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+  if (!(n1 > R(0))) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       U[r][0] = V[r][0] = v1[r];
       U[r][1] = V[r][1] = v2[r];
       U[r][2] = V[r][2] = v3[r];
-      s[r] = 0.0;
+      s[r] = R(0);
     }
     return;
   }
+  const R in1 = rot_rcp(n1);
 #pragma unroll
-  for (int r = 0; r < 3; ++r) u1[r] /= n1;
-  const double p = u1[0] * u2[0] + u1[1] * u2[1] + u1[2] * u2[2];
+  for (int r = 0; r < 3; ++r) u1[r] *= in1;
+  const R p = u1[0] * u2[0] + u1[1] * u2[1] + u1[2] * u2[2];
 #pragma unroll
   for (int r = 0; r < 3; ++r) u2[r] -= p * u1[r];
-  double n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
-  if (!(n2 > 1e-300)) {
+  R n2 = rot_sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  if (!(n2 > (sizeof(R) == 4 ? R(1e-30) : R(1e-300)))) {
     // rank one: any unit vector orthogonal to u1
-    const double ax = fabs(u1[0]), ay = fabs(u1[1]), az = fabs(u1[2]);
-    const double e[3] = {ax <= ay && ax <= az ? 1.0 : 0.0, ay < ax && ay <= az ? 1.0 : 0.0,
-                         az < ax && az < ay ? 1.0 : 0.0};
+    const R ax = fabs(u1[0]), ay = fabs(u1[1]), az = fabs(u1[2]);
+    const R e[3] = {R(ax <= ay && ax <= az ? 1 : 0), R(ay < ax && ay <= az ? 1 : 0),
+                    R(az < ax && az < ay ? 1 : 0)};
     cross3(u1, e, u2);
-    n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+    n2 = rot_sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
   }
 #pragma unroll
-  for (int r = 0; r < 3; ++r) u2[r] /= n2;
+  for (int r = 0; r < 3; ++r) u2[r] *= rot_rcp(n2);
   cross3(u1, u2, u3);
-  double fv[3][3];  // F v_k
+  R fv[3][3];  // F v_k
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     fv[0][r] = n1 * u1[r];
@@ -392,20 +412,24 @@ __device__ void closest_rotation3(const double (&F)[3][3], double (&R)[3][3]) {
 //    c = (s2 s3, s1 s3, s1 s2).
 // Negative eigenvalues are set to zero.  With the shape gradients b_a and
 // c_a = V^T b_a, the filtered block of nodes (a, b) is vol U K_ab U^T with
-// K_ab = diag(c_a) A+ diag(c_b) plus, per pair, the twist/flip terms.  All in
-// float64 (on this chip it issues at the float32 rate).
+// K_ab = diag(c_a) A+ diag(c_b) plus, per pair, the twist/flip terms.
 // ---------------------------------------------------------------------------
+template <typename R>
 struct SnhFilter {
-  double vol;
-  double U[3][3];
-  double c[4][3];      // V^T b_a
-  double Ap[3][3];     // filtered scaling block
-  double sp[3], dp[3]; // per pair (0,1), (0,2), (1,2): (l_twist + l_flip)/2, (l_flip - l_twist)/2
-  double g[4][3];      // gradient vol P b_a
+  R vol;
+  R U[3][3];
+  R c[4][3];      // V^T b_a
+  R Ap[3][3];     // filtered scaling block
+  R sp[3], dp[3]; // per pair (0,1), (0,2), (1,2): (l_twist + l_flip)/2, (l_flip - l_twist)/2
+  R g[4][3];      // gradient vol P b_a
 };
 
+// R: the compute type (float in the single-precision kernels, with the
+// hardware reciprocal and square root in the rotations; double otherwise).
+// Edge vectors, Dm^-1 and F are formed in double.
+template <typename R>
 __device__ void snh_filter(const SetDev& S, int64_t e, const double* __restrict__ x,
-                           const double* __restrict__ X, SnhFilter& f) {
+                           const double* __restrict__ X, SnhFilter<R>& f) {
   const int4 cn = S.conn[e];
   const int nd[4] = {cn.x, cn.y, cn.z, cn.w};
   double Ds[3][3], Dm[3][3];
@@ -425,76 +449,73 @@ __device__ void snh_filter(const SetDev& S, int64_t e, const double* __restrict_
       Mi[i][j] = Dm[j1][i1] * Dm[j2][i2] - Dm[j1][i2] * Dm[j2][i1];
     }
   const double det = Dm[0][0] * Mi[0][0] + Dm[0][1] * Mi[1][0] + Dm[0][2] * Mi[2][0];
-  f.vol = fabs(det) / 6.0;
-  double B[4][3];  // shape gradients: rows of Dm^-1, b_0 = -their sum
+  const double idet = 1.0 / det;
+  f.vol = R(fabs(det) / 6.0);
+  R B[4][3];  // shape gradients: rows of Dm^-1, b_0 = -their sum
+  R F[3][3];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    B[1][j] = Mi[0][j] / det;
-    B[2][j] = Mi[1][j] / det;
-    B[3][j] = Mi[2][j] / det;
-    B[0][j] = -(B[1][j] + B[2][j] + B[3][j]);
-  }
-  double F[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 3; ++i) {
+    double Fi[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      F[i][j] = Ds[i][0] * B[1][j] + Ds[i][1] * B[2][j] + Ds[i][2] * B[3][j];
+      Fi[j] = (Ds[i][0] * Mi[0][j] + Ds[i][1] * Mi[1][j] + Ds[i][2] * Mi[2][j]) * idet;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F[i][j] = R(Fi[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double b1 = Mi[0][j] * idet, b2 = Mi[1][j] * idet, b3 = Mi[2][j] * idet;
+    B[1][j] = R(b1);
+    B[2][j] = R(b2);
+    B[3][j] = R(b3);
+    B[0][j] = R(-(b1 + b2 + b3));
+  }
   const int st = S.prm_stride;
   const double mu = ld_prm(S.prm64, st, e, 0), lam = ld_prm(S.prm64, st, e, 1);
-  const double mu_ = mu * (4.0 / 3.0), lam_ = lam + mu * (5.0 / 6.0);
-  const double alpha = 1.0 + mu_ / lam_ - mu_ / (4.0 * lam_);
-  double V[3][3], sv[3];
+  const double mu_d = mu * (4.0 / 3.0), lam_d = lam + mu * (5.0 / 6.0);
+  const R mu_ = R(mu_d), lam_ = R(lam_d);
+  const R alpha = R(1.0 + mu_d / lam_d - mu_d / (4.0 * lam_d));
+  R V[3][3], sv[3];
   svd3(F, f.U, sv, V);
-  const double I2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
-  const double J = sv[0] * sv[1] * sv[2];
-  const double p2 = 0.5 * mu_ * (1.0 - 1.0 / (I2 + 1.0));
-  const double p22 = 0.5 * mu_ / ((I2 + 1.0) * (I2 + 1.0));
-  const double p3 = lam_ * (J - alpha);
-  const double p33 = lam_;
+  const R I2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
+  const R J = sv[0] * sv[1] * sv[2];
+  const R q = rot_rcp(I2 + R(1));
+  const R p2 = R(0.5) * mu_ * (R(1) - q);
+  const R p22 = R(0.5) * mu_ * q * q;
+  const R p3 = lam_ * (J - alpha);
+  const R p33 = lam_;
   // gradient: P = 2 psi_2 F + psi_3 cof F
-  double cof[3][3];
+  R Pm[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-      cof[i][j] = F[i1][j1] * F[i2][j2] - F[i1][j2] * F[i2][j1];
+      Pm[i][j] = R(2) * p2 * F[i][j] + p3 * (F[i1][j1] * F[i2][j2] - F[i1][j2] * F[i2][j1]);
     }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      double acc = 0.0;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) acc += (2.0 * p2 * F[i][j] + p3 * cof[i][j]) * B[a][j];
-      f.g[a][i] = f.vol * acc;
-    }
+    for (int i = 0; i < 3; ++i)
+      f.g[a][i] = f.vol * (Pm[i][0] * B[a][0] + Pm[i][1] * B[a][1] + Pm[i][2] * B[a][2]);
   // c_a = V^T b_a
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int m = 0; m < 3; ++m) f.c[a][m] = V[0][m] * B[a][0] + V[1][m] * B[a][1] + V[2][m] * B[a][2];
   // scaling block, its eigensystem, the filtered block
-  const double cc[3] = {sv[1] * sv[2], sv[0] * sv[2], sv[0] * sv[1]};
-  double A[3][3], W[3][3];
+  const R cc[3] = {sv[1] * sv[2], sv[0] * sv[2], sv[0] * sv[1]};
+  R A[3][3], W[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      A[i][j] = 4.0 * p22 * sv[i] * sv[j] + p33 * cc[i] * cc[j] +
-                (i == j ? 2.0 * p2 : p3 * sv[3 - i - j]);
-      W[i][j] = i == j ? 1.0 : 0.0;
+      A[i][j] = R(4) * p22 * sv[i] * sv[j] + p33 * cc[i] * cc[j] +
+                (i == j ? R(2) * p2 : p3 * sv[3 - i - j]);
+      W[i][j] = i == j ? R(1) : R(0);
     }
-  for (int sweep = 0; sweep < 16; ++sweep) {
-    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
-    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
-    if (!(off > 1e-34 * dia)) break;
-    jacobi3_rotate<0, 1>(A, W);
-    jacobi3_rotate<0, 2>(A, W);
-    jacobi3_rotate<1, 2>(A, W);
-  }
-  const double l0 = fmax(A[0][0], 0.0), l1 = fmax(A[1][1], 0.0), l2 = fmax(A[2][2], 0.0);
+  jacobi3(A, W);
+  const R l0 = fmax(A[0][0], R(0)), l1 = fmax(A[1][1], R(0)), l2 = fmax(A[2][2], R(0));
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -503,17 +524,18 @@ __device__ void snh_filter(const SetDev& S, int64_t e, const double* __restrict_
   // twist / flip of the pairs (0,1), (0,2), (1,2); the third index is 2, 1, 0
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
-    const double sk = sv[2 - p];
-    const double lt = fmax(2.0 * p2 + p3 * sk, 0.0), lf = fmax(2.0 * p2 - p3 * sk, 0.0);
-    f.sp[p] = 0.5 * (lt + lf);
-    f.dp[p] = 0.5 * (lf - lt);
+    const R sk = sv[2 - p];
+    const R lt = fmax(R(2) * p2 + p3 * sk, R(0)), lf = fmax(R(2) * p2 - p3 * sk, R(0));
+    f.sp[p] = R(0.5) * (lt + lf);
+    f.dp[p] = R(0.5) * (lf - lt);
   }
 }
 
 // Filtered Hessian block of nodes (a, b): vol U K_ab U^T.
-__device__ __forceinline__ void snh_filter_block(const SnhFilter& f, int a, int b,
-                                                 double (&H)[3][3]) {
-  double K[3][3];
+template <typename R>
+__device__ __forceinline__ void snh_filter_block(const SnhFilter<R>& f, int a, int b,
+                                                 R (&H)[3][3]) {
+  R K[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -526,7 +548,7 @@ __device__ __forceinline__ void snh_filter_block(const SnhFilter& f, int a, int 
     K[i][j] += f.dp[p] * f.c[a][j] * f.c[b][i];
     K[j][i] += f.dp[p] * f.c[a][i] * f.c[b][j];
   }
-  double KU[3][3];  // K U^T
+  R KU[3][3];  // K U^T
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -548,7 +570,7 @@ __global__ __launch_bounds__(64) void k_elem_rows_filtered(SetDev S, const doubl
                                                           T* __restrict__ rows) {
   for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < S.n_elem;
        e += (int64_t)gridDim.x * 64) {
-    SnhFilter f;
+    SnhFilter<T> f;
     snh_filter(S, e, x, X, f);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -558,7 +580,7 @@ __global__ __launch_bounds__(64) void k_elem_rows_filtered(SetDev S, const doubl
 #pragma unroll
       for (int bp = 1; bp < 4; ++bp) {
         const int b = bp <= a ? bp - 1 : bp;
-        double H[3][3];
+        T H[3][3];
         snh_filter_block(f, a, b, H);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -578,7 +600,7 @@ __global__ __launch_bounds__(64) void k_elem_filtered(SetDev S, const double* __
                                                      T* __restrict__ Ho) {
   for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < S.n_elem;
        e += (int64_t)gridDim.x * 64) {
-    SnhFilter f;
+    SnhFilter<T> f;
     snh_filter(S, e, x, X, f);
     if (Eo) {
       T in[kMaxIn], out[1];
@@ -597,7 +619,7 @@ __global__ __launch_bounds__(64) void k_elem_filtered(SetDev S, const double* __
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          double H[3][3];
+          T H[3][3];
           snh_filter_block(f, a, b, H);
 #pragma unroll
           for (int i = 0; i < 3; ++i)
@@ -762,12 +784,6 @@ __device__ constexpr T helmert(int i, int a) {
 // Reciprocal, reciprocal square root and square root for the rotation
 // parameters: the hardware approximations (about 1 ulp) in single precision,
 // correctly rounded operations in double precision.
-__device__ __forceinline__ float rot_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float rot_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ float rot_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double rot_rcp(double x) { return 1.0 / x; }
-__device__ __forceinline__ double rot_rsq(double x) { return 1.0 / sqrt(x); }
-__device__ __forceinline__ double rot_sqrt(double x) { return sqrt(x); }
 
 // Eigenvector matrix V (R x R, row-major) of one lane: in registers, or in
 // LDS with the lanes of the workgroup interleaved (entry i at i * 64 + lane).
@@ -1203,6 +1219,29 @@ __device__ __forceinline__ void incidence_row_off(const RowArgs<T>& A, uint32_t 
   });
 }
 
+constexpr int kRowEval = 0, kRowRecords = 1, kRowFilter = 2;
+
+// Filtered Stable Neo-Hookean row of one incidence, in the layout of
+// incidence_row_off.
+template <typename T>
+__device__ __forceinline__ void incidence_row_filtered(const RowArgs<T>& A, uint32_t code, T* out) {
+  const int a = inc_local(code);
+  SnhFilter<T> f;
+  snh_filter(A.sets.s[inc_set(code)], inc_elem(code), A.x, A.X, f);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[i] = T(f.g[a][i]);
+#pragma unroll
+  for (int bp = 1; bp < 4; ++bp) {
+    const int b = bp <= a ? bp - 1 : bp;
+    T H[3][3];
+    snh_filter_block(f, a, b, H);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) out[3 + 9 * i + 3 * (bp - 1) + k] = T(H[i][k]);
+  }
+}
+
 // Row assembly for translation-invariant element energies (all three kinds:
 // each element Hessian row sums to zero over the nodes, and so does its
 // nearest-PSD projection, which only removes directions orthogonal to the
@@ -1217,11 +1256,13 @@ __device__ __forceinline__ void incidence_row_off(const RowArgs<T>& A, uint32_t 
 //     the gradient sums the row's incidences (float64, incidence order);
 //  5. Dirichlet is applied and every block is written once, with the inverse
 //     of each diagonal block when requested.
-// FROM_REC: step 1 reads each incidence's row from its record in the
-// incidence-ordered buffer (projected path) instead of evaluating it.
+// SRC: where step 1 takes each incidence's row from -- kRowEval evaluates the
+// generated row function, kRowRecords reads the incidence's record in the
+// incidence-ordered buffer (projected path), kRowFilter evaluates the
+// filtered Stable Neo-Hookean row (all sets of that kind).
 // KMASK: the element kinds compiled in (kKindsSnh for the common single-
 // material mesh keeps the kernel small).
-template <typename T, bool WANT_G, bool FROM_REC, uint32_t KMASK>
+template <typename T, bool WANT_G, int SRC, uint32_t KMASK>
 __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   constexpr int NV = 30;
   __shared__ T st[NV][kRowWG];
@@ -1244,10 +1285,12 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   const int np = s_blk[nrows];
   if (t < nq) {
     T out[NV];
-    if (FROM_REC) {
+    if constexpr (SRC == kRowRecords) {
       const T* rec = A.inc_rows + (int64_t)(q0 + t) * kIncRec;
 #pragma unroll
       for (int v = 0; v < NV; ++v) out[v] = rec[v];
+    } else if constexpr (SRC == kRowFilter) {
+      incidence_row_filtered<T>(A, A.inc_code[q0 + t], out);
     } else {
       incidence_row_off<T, KMASK>(A, A.inc_code[q0 + t], out);
     }
@@ -2121,9 +2164,9 @@ template <typename T, uint32_t KMASK>
 static void row_assemble_launch(Mesh& m, const char* PNAME, dim3 grid, dim3 block,
                                 const RowArgs<T>& A, bool want_g, bool want_H) {
   if (want_H && want_g) {
-    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, false, KMASK>), grid, block, 0, A);
+    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, kRowEval, KMASK>), grid, block, 0, A);
   } else if (want_H) {
-    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, false, KMASK>), grid, block, 0, A);
+    SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, kRowEval, KMASK>), grid, block, 0, A);
   } else {
     SYMX_LAUNCH(m, PNAME, (k_row_gradient<T, KMASK>), grid, block, 0, A);
   }
@@ -2132,7 +2175,7 @@ static void row_assemble_launch(Mesh& m, const char* PNAME, dim3 grid, dim3 bloc
 template <typename T>
 static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, double dt,
                                   bool want_g, bool want_H, bool dirichlet,
-                                  const void* inc_rows, double* g_out, void* dinv) {
+                                  const void* inc_rows, bool filter, double* g_out, void* dinv) {
   RowArgs<T> A;
   A.sets = m.sets_dev();
   A.x = x;
@@ -2176,11 +2219,16 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
       SYMX_LAUNCH(m, PNAME, (k_row_assemble_t10<T, false, true>), grid, block, 0, A);
     else
       SYMX_LAUNCH(m, PNAME, (k_row_assemble_t10<T, true, false>), grid, block, 0, A);
+  } else if (filter && want_H) {
+    if (want_g)
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, kRowFilter, 0u>), grid, block, 0, A);
+    else
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, kRowFilter, 0u>), grid, block, 0, A);
   } else if (inc_rows && want_H) {
     if (want_g)
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, true, 0u>), grid, block, 0, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, kRowRecords, 0u>), grid, block, 0, A);
     else
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, true, 0u>), grid, block, 0, A);
+      SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, false, kRowRecords, 0u>), grid, block, 0, A);
   } else if (kinds == kKindsSnh)
     row_assemble_launch<T, kKindsSnh>(m, PNAME, grid, block, A, want_g, want_H);
   else if ((kinds & ~kKindsShell) == 0)
@@ -2201,10 +2249,12 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
 
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
                                 bool want_H, int precision, bool dirichlet,
-                                const void* inc_rows, double* g_out, void* dinv) {
+                                const void* inc_rows, bool filter, double* g_out, void* dinv) {
   if (precision == SYMX_F32)
-    return row_assemble_t<float>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, g_out, dinv);
-  return row_assemble_t<double>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, g_out, dinv);
+    return row_assemble_t<float>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, filter, g_out,
+                                 dinv);
+  return row_assemble_t<double>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, filter, g_out,
+                                dinv);
 }
 
 symx_status launch_x_tilde(Mesh& m, const double* x, const double* v, double dt, const double g[3],

@@ -135,13 +135,20 @@ symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool
   }
   if (want_H) TRY(ensure_values(m, precision));
   if (project && want_H) {
+    // filter mode on a Stable Neo-Hookean mesh: the row kernel evaluates the
+    // filtered rows itself; otherwise element-wise records, then assembly
+    bool snh_only = true;
+    for (const SetHost& s : m.sets) snh_only = snh_only && s.kind == SYMX_SNH_TET4;
+    if (project == 2 && snh_only)
+      return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, nullptr, true,
+                                 g_out, dinv);
     TRY(project_into_records(m, x, precision, project));
-    return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, m.inc_rows, g_out,
-                               dinv);
+    return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, m.inc_rows, false,
+                               g_out, dinv);
   }
   if (!want_g && !want_H) return SYMX_OK;
-  return launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, g_out,
-                             want_H ? dinv : nullptr);
+  return launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, false,
+                             g_out, want_H ? dinv : nullptr);
 }
 
 symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E) {
