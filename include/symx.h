@@ -237,6 +237,28 @@ symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
  * sets. */
 symx_status symx_mesh_update_rotations(symx_mesh mesh, const double* x_dev);
 
+/* Candidate contacts of a conditional barrier (Sec. 5.2, conditional
+ * evaluations, Eq. 9; the contact potential of Sec. 5.4): tuples_host holds n
+ * x 4 node ids (p, t0, t1, t2), node p against the plane through t0, t1, t2
+ * with normal N = (t1 - t0) x (t2 - t0).  With d the signed distance of p to
+ * that plane, the energy is -k_c (d - d_hat)^2 ln(d / d_hat) while
+ * 0 < d < d_hat, zero for d >= d_hat (inactive: not evaluated, not assembled)
+ * and +inf for d <= 0, so that a line search backs off.  The list replaces
+ * the previous one and n = 0 removes all contacts: as in the paper's dynamic
+ * topology, the caller updates the list (e.g. from a proximity query at each
+ * time step) and the couplings follow.  They form a second block-sparse matrix
+ * beside the mesh's pattern (rebuilt here on the host when the list changes);
+ * assembly, energies, the PCG and the Newton step include it.  With
+ * projection on, contact element Hessians take the nearest-PSD projection.
+ * Node ids in range and distinct within a tuple; k_c, d_hat > 0; not on
+ * meshes of quadratic tets. */
+symx_status symx_mesh_set_contacts(symx_mesh mesh, int64_t n, const int32_t* tuples_host,
+                                   double k_c, double d_hat);
+/* View of the contact matrix of the last assembly (device pointers, the
+ * layout of symx_bsr_view, n_block_rows = N, blocks of inactive candidates
+ * zero), at `precision`.  Without contacts nnzb = 0. */
+symx_status symx_mesh_get_contact_bsr(symx_mesh mesh, int32_t precision, symx_bsr_view* view);
+
 /* Kernel timing for measurement: with profiling on, every kernel launch of
  * the mesh carries start/stop HIP events on the mesh's stream
  * (hipExtLaunchKernelGGL), which time the kernel itself.  set_profiling

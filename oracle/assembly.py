@@ -21,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from . import elements
+from . import contact, elements
 from .projection import project_psd
 from .rest import lame, lumped_mass, young_array
 
@@ -102,6 +102,10 @@ def assemble(scene, x, x_tilde=None, dt=None, project=False, dirichlet=True,
     Neo-Hookean tets (elements.snh_tet4_filtered) and projects the element
     Hessians of every other kind.
     x_lag: positions of the lagged rotations (default: rest).
+    A scene with candidate contacts adds the conditional barrier (inactive
+    candidates contribute nothing); its blocks are returned apart, as
+    "contact_blocks" {(i, j): 3x3} (Dirichlet applied, element Hessians
+    projected to PSD when project is set).
     """
     N = scene.n_nodes
     if row_ptr is None:
@@ -132,6 +136,26 @@ def assemble(scene, x, x_tilde=None, dt=None, project=False, dirichlet=True,
             pos = lookup[key]                                 # (n, k, k)
             blocks = He.transpose(0, 1, 3, 2, 4)             # (n, a, b, i, k)
             np.add.at(vals, pos.ravel(), blocks.reshape(-1, 3, 3))
+    cblocks = {}
+    cl = scene.contacts
+    if cl is not None and cl.tuples.shape[0] > 0:
+        Ec, gc, Hc, act = contact.point_plane_barrier(x[cl.tuples], cl.kc, cl.dhat, want_hess)
+        parts.append(float(np.sum(Ec)))
+        E_total += float(np.sum(Ec))
+        np.add.at(g, cl.tuples.ravel(), gc.reshape(-1, 3))
+        if want_hess:
+            Ha = Hc[act].reshape(-1, 12, 12)
+            if project:
+                Ha = project_psd(Ha)
+            Ha = Ha.reshape(-1, 4, 3, 4, 3)
+            fixed = scene.fixed.astype(bool)
+            for t, He in zip(cl.tuples[act], Ha):
+                for a in range(4):
+                    for b in range(4):
+                        key = (int(t[a]), int(t[b]))
+                        blk = He[a, :, b, :] if not (dirichlet and (fixed[t[a]] or fixed[t[b]])) \
+                            else np.zeros((3, 3))
+                        cblocks[key] = cblocks.get(key, np.zeros((3, 3))) + blk
     if x_tilde is not None:
         m = lumped_mass(scene)
         Ei, gi, w = elements.inertia(x, x_tilde, m, dt)
@@ -150,7 +174,8 @@ def assemble(scene, x, x_tilde=None, dt=None, project=False, dirichlet=True,
             vals[kill] = 0.0
             diag = _diag_index(row_ptr, col_idx)
             vals[diag[fixed]] = np.eye(3)
-    return dict(E=E_total, g=g, row_ptr=row_ptr, col_idx=col_idx, vals=vals, E_parts=parts)
+    return dict(E=E_total, g=g, row_ptr=row_ptr, col_idx=col_idx, vals=vals, E_parts=parts,
+                contact_blocks=cblocks)
 
 
 def _block_index(conn, row_ptr, col_idx):
@@ -181,6 +206,10 @@ def energy(scene, x, x_tilde=None, dt=None, x_lag=None):
     for es in scene.energies:
         Ee, _, _ = elements.element_eval(es, x, scene.X, want_hess=False, x_lag=x_lag)
         E += float(np.sum(Ee))
+    cl = scene.contacts
+    if cl is not None and cl.tuples.shape[0] > 0:
+        Ec, _, _, _ = contact.point_plane_barrier(x[cl.tuples], cl.kc, cl.dhat, want_hess=False)
+        E += float(np.sum(Ec))
     if x_tilde is not None:
         m = lumped_mass(scene)
         Ei, _, _ = elements.inertia(x, x_tilde, m, dt)
@@ -188,6 +217,17 @@ def energy(scene, x, x_tilde=None, dt=None, x_lag=None):
     return E
 
 
-def to_scipy(row_ptr, col_idx, vals):
+def to_scipy(row_ptr, col_idx, vals, contact_blocks=None):
+    """The assembled Hessian as a scipy CSR matrix, contact blocks added."""
     N = row_ptr.shape[0] - 1
-    return sp.bsr_matrix((vals, col_idx, row_ptr), shape=(3 * N, 3 * N)).tocsr()
+    A = sp.bsr_matrix((vals, col_idx, row_ptr), shape=(3 * N, 3 * N)).tocsr()
+    if contact_blocks:
+        rows, cols, data = [], [], []
+        for (i, j), b in contact_blocks.items():
+            for r in range(3):
+                for c in range(3):
+                    rows.append(3 * i + r)
+                    cols.append(3 * j + c)
+                    data.append(b[r, c])
+        A = A + sp.csr_matrix((data, (rows, cols)), shape=(3 * N, 3 * N))
+    return A

@@ -41,12 +41,17 @@ class StepParams:
     regrow_after: int = 3
 
 
-def diag_inverse(row_ptr, col_idx, vals):
-    """Inverses of the 3x3 diagonal blocks (block-Jacobi preconditioner)."""
+def diag_inverse(row_ptr, col_idx, vals, contact_blocks=None):
+    """Inverses of the 3x3 diagonal blocks (block-Jacobi preconditioner),
+    contact diagonal blocks included."""
     N = row_ptr.shape[0] - 1
     rows = np.repeat(np.arange(N), np.diff(row_ptr))
     d = np.nonzero(rows == col_idx)[0]
-    return np.linalg.inv(vals[d])
+    D = vals[d].copy()
+    for (i, j), b in (contact_blocks or {}).items():
+        if i == j:
+            D[i] += b
+    return np.linalg.inv(D)
 
 
 def pcg(A, Dinv, b, rtol, max_iter):
@@ -105,14 +110,14 @@ def newton_solve(scene, x_t, v_t, dt, prm: StepParams, solver="pcg", record=None
             return True, x, rep
         if it == prm.max_newton:
             break
-        A = assembly.to_scipy(rp, ci, asm["vals"])
+        A = assembly.to_scipy(rp, ci, asm["vals"], asm["contact_blocks"])
         b = -g.ravel()
         if solver == "direct":
             dx = spla.spsolve(A.tocsc(), b)
             n_cg = 0
         else:
             eta = min(0.5, np.sqrt(r / r0))
-            Dinv = diag_inverse(rp, ci, asm["vals"])
+            Dinv = diag_inverse(rp, ci, asm["vals"], asm["contact_blocks"])
             dx, n_cg, _ = pcg(A, Dinv, b, eta, prm.max_pcg)
         rep["pcg_iters"] += n_cg
         if record is not None:

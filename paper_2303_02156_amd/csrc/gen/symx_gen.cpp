@@ -214,6 +214,35 @@ S snh_tet10_qp(Graph& g, const std::vector<S>& in) {
   return in[62] * abs(det3(JX)) * snh_density(F, in[60], in[61]);
 }
 
+// Signed distance of node p (inputs 0..2) to the plane through t0, t1, t2
+// (3..11), positive on the side of N = (t1 - t0) x (t2 - t0).
+S point_plane_distance(Graph& g, const std::vector<S>& in) {
+  (void)g;
+  Vec u(3), e1(3), e2(3);
+  for (int i = 0; i < 3; ++i) {
+    u[i] = in[i] - in[3 + i];
+    e1[i] = in[6 + i] - in[3 + i];
+    e2[i] = in[9 + i] - in[3 + i];
+  }
+  Vec N = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+           e1[0] * e2[1] - e1[1] * e2[0]};
+  return dot(u, N) / sqrt(dot(N, N));
+}
+
+// Contact barrier between a point and a plane (Sec. 5.4, the contact
+// potential): -k_c (d - d_hat)^2 ln(d / d_hat), k_c (input 12), d_hat (13).
+// It is evaluated only where its activation is positive (Eq. 9).
+S ipc_point_plane(Graph& g, const std::vector<S>& in) {
+  S d = point_plane_distance(g, in);
+  S kc = in[12], dh = in[13];
+  return -kc * pown(d - dh, 2) * log(d / dh);
+}
+
+// Its activation c_e = d_hat - d (Eq. 9), compiled as a function of its own.
+S ipc_point_plane_act(Graph& g, const std::vector<S>& in) {
+  return in[13] - point_plane_distance(g, in);
+}
+
 // Quadratic bending (Eq. 13, Bergou et al. 2006): E = k_b/2 x^T Q x with the
 // constant Q = c (K K^T) (x) I3; inputs are the per-node weights K_a and the
 // scale c = 3/(A0 + A1), precomputed from the rest hinge.
@@ -339,6 +368,8 @@ int main(int argc, char** argv) {
       {"fcr_tet4", 4, 35, 12, fcr_tet4},
       {"arap_tet4", 4, 35, 12, arap_tet4},
       {"snh_tet10", 10, 66, 30, snh_tet10_qp, {0, 4}},
+      {"ipc_point_plane", 4, 14, -1, ipc_point_plane},
+      {"ipc_point_plane_act", 4, 14, -1, ipc_point_plane_act},
   };
   Generated all;
   all.hip =

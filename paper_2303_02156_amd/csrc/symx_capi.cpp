@@ -56,6 +56,7 @@ void mesh_free(Mesh* m) {
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   else (void)hipDeviceSynchronize();
   free_workspace(*m);
+  contacts_free(*m);
   m->prof.destroy();
   void* dev[] = {m->X,        m->mass,     m->fixed,    m->vals32, m->vals64,
                  m->inc_rows, m->inc_pos, m->partials, m->scalars};
@@ -272,6 +273,33 @@ symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
     return SYMX_ERR_INVALID_ARG;
   }
   return newton_step(*mesh->m, x_dev, v_dev, *params, report);
+  GUARD_END
+}
+
+symx_status symx_mesh_set_contacts(symx_mesh mesh, int64_t n, const int32_t* tuples_host,
+                                   double k_c, double d_hat) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
+  return contacts_set(*mesh->m, n, tuples_host, k_c, d_hat);
+  GUARD_END
+}
+
+symx_status symx_mesh_get_contact_bsr(symx_mesh mesh, int32_t precision, symx_bsr_view* view) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh) || !view || (precision != SYMX_F64 && precision != SYMX_F32)) {
+    set_error("invalid arguments to symx_mesh_get_contact_bsr");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  Mesh& m = *mesh->m;
+  const Contacts* c = m.contacts;
+  view->n_block_rows = m.N;
+  view->nnzb = c ? c->nnzb : 0;
+  view->row_ptr = c ? c->row_ptr : nullptr;
+  view->col_idx = c ? c->col_idx : nullptr;
+  view->values = c ? (precision == SYMX_F64 ? (const void*)c->vals64 : (const void*)c->vals32)
+                   : nullptr;
+  view->precision = precision;
+  return SYMX_OK;
   GUARD_END
 }
 

@@ -261,6 +261,40 @@ struct SetHost {
 
 struct Workspace;  // Newton / PCG buffers (symx_newton.cpp)
 
+// Candidate contacts of the conditional point-plane barrier (node p against
+// the plane of nodes t0, t1, t2) and the block pattern of their couplings: a
+// second block-sparse matrix beside the mesh's own (the dual storage of the
+// assembly: the mesh pattern stays, the contact pattern is rebuilt whenever
+// the candidate list changes).  Blocks of inactive candidates hold zero.
+constexpr int kContactVals = 12 + 144;  // gradient and Hessian of one element
+constexpr int kContactChunk = 2048;     // candidates per workgroup of the compaction scan
+struct Contacts {
+  int64_t n = 0;                   // candidate tuples
+  double kc = 0.0, dhat = 0.0;
+  int* tuples = nullptr;           // n x 4
+  int64_t nnzb = 0;
+  int* row_ptr = nullptr;          // N+1
+  int* col_idx = nullptr;          // nnzb, ascending within each row
+  int* blk_row = nullptr;          // nnzb
+  int* blk_ptr = nullptr;          // nnzb+1 into blk_src
+  int* blk_src = nullptr;          // 16 n: candidate * 16 + 4 a + b, candidate order per block
+  int64_t n_gnode = 0;
+  int* gnode = nullptr;            // nodes of the candidates
+  int* gptr = nullptr;             // n_gnode+1 into gsrc
+  int* gsrc = nullptr;             // 4 n: candidate * 4 + a, candidate order per node
+  int* gdiag = nullptr;            // n_gnode: the node's diagonal block
+  float* vals32 = nullptr;         // 9 x nnzb, component-major
+  double* vals64 = nullptr;
+  // per evaluation: activation and compaction
+  uint8_t* flag = nullptr;         // n
+  int* slot = nullptr;             // n: compacted index, or -1 when inactive
+  int* act = nullptr;              // n: the active candidates in order
+  int* chunk_count = nullptr;      // per scan chunk
+  int* n_active = nullptr;         // device scalar
+  void* eval = nullptr;            // n x kContactVals in the evaluation's precision
+  size_t eval_bytes = 0;
+};
+
 // Optional per-kernel timing: HIP events recorded around every launch on the
 // mesh's stream, resolved lazily.
 struct Profiler {
@@ -324,6 +358,7 @@ struct Mesh {
   double* pinned = nullptr;         // host pinned scalars
   int* nonfinite = nullptr;         // device flag (inside `scalars`)
   Workspace* ws = nullptr;
+  Contacts* contacts = nullptr;     // conditional contact barrier, or null
   // dt control
   double dt_cur = 0.0, dt_nominal = 0.0;
   int successes = 0;
@@ -376,6 +411,19 @@ symx_status launch_incidence_rows_projected(Mesh& m, const double* x, int precis
 // Lagged rotations of every fixed co-rotational / ARAP set: the rotation
 // closest to each element's deformation gradient at positions x.
 symx_status launch_lagged_rotations(Mesh& m, const double* x);
+// Contact barrier at positions x: activation and compaction, then the
+// active elements' derivatives into the contact matrix (want_H, precision's
+// type, element Hessians projected to PSD when `project`, Dirichlet when
+// `dirichlet`), their gradient rows added into g (want_g),
+// and the block-Jacobi inverses of the nodes with contact blocks recomputed
+// from the mesh's and the contact diagonal (dinv).  Run after the mesh's row
+// assembly.
+symx_status launch_contact_assemble(Mesh& m, const double* x, bool want_g, bool want_H,
+                                    bool project, int precision, bool dirichlet, double* g,
+                                    void* dinv);
+// Replace the candidate contacts (host n x 4 node ids) and free them.
+symx_status contacts_set(Mesh& m, int64_t n, const int32_t* tuples, double kc, double dhat);
+void contacts_free(Mesh& m);
 // Total energy (float64 sum of per-element energies in `precision`).
 symx_status launch_energy(Mesh& m, const double* x, const double* x_tilde, double dt,
                           int precision, double* E_dev);

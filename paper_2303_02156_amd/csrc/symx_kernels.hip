@@ -1699,19 +1699,35 @@ __device__ __forceinline__ void spmv_row(int row, int lane, const int* __restric
   }
 }
 
+// The contact matrix beside the mesh's (DYN): a second BSR over the same rows.
+template <typename T>
+struct DynBsr {
+  const int* row_ptr;
+  const int* col;
+  const T* vals;
+  int64_t nnzb;
+};
+
 // r = b - A x  (float64 residual of the Newton system, A promoted)
-template <typename TA>
+template <typename TA, bool DYN>
 __global__ __launch_bounds__(256) void k_residual64(int64_t N, const int* __restrict__ row_ptr,
                                                     const int* __restrict__ col,
                                                     const TA* __restrict__ vals, int64_t nnzb,
                                                     const double* __restrict__ x,
                                                     const double* __restrict__ b,
-                                                    double* __restrict__ r) {
+                                                    double* __restrict__ r, DynBsr<TA> C) {
   const int lane = threadIdx.x & 15;
   for (int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4; row < N;
        row += ((int64_t)gridDim.x * 256) >> 4) {
     double acc[3];
     spmv_row<TA, double, double>((int)row, lane, row_ptr, col, vals, nnzb, x, acc);
+    if (DYN) {
+      double ac[3];
+      spmv_row<TA, double, double>((int)row, lane, C.row_ptr, C.col, C.vals, C.nnzb, x, ac);
+      acc[0] += ac[0];
+      acc[1] += ac[1];
+      acc[2] += ac[2];
+    }
     if (lane == 0) {
       r[3 * row + 0] = b[3 * row + 0] - acc[0];
       r[3 * row + 1] = b[3 * row + 1] - acc[1];
@@ -1794,13 +1810,13 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restric
 // Rows: workgroup b runs on XCD b % 8 and takes, in steps of 16 rows, the
 // rows of the XCD's contiguous eighth of the matrix, so that the gathered
 // entries of z stay in that XCD's L2 (gridDim.x is a multiple of 8).
-template <typename T>
+template <typename T, bool DYN>
 __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* __restrict__ row_ptr,
                                                   const int* __restrict__ col,
                                                   const T* __restrict__ vals, int64_t nnzb,
                                                   const T* __restrict__ z, T* __restrict__ p,
                                                   T* __restrict__ q, double* __restrict__ P,
-                                                  double* __restrict__ S, int gu) {
+                                                  double* __restrict__ S, int gu, DynBsr<T> C) {
   if (S[S_DONE] != 0.0) return;
   __shared__ double sh[4];
   const double rz = sum_partials(P + P_RZ * kPcgP, gu, sh);
@@ -1828,6 +1844,13 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* _
        row += stride) {
     T acc[3];
     spmv_row<T, T, T>((int)row, lane, row_ptr, col, vals, nnzb, z, acc);
+    if (DYN) {
+      T ac[3];
+      spmv_row<T, T, T>((int)row, lane, C.row_ptr, C.col, C.vals, C.nnzb, z, ac);
+      acc[0] += ac[0];
+      acc[1] += ac[1];
+      acc[2] += ac[2];
+    }
     if (lane == 0) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1957,6 +1980,247 @@ __global__ __launch_bounds__(256) void k_check_finite(int64_t n, const double* _
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// conditional contact barrier: node p against the plane of nodes t0, t1, t2
+// (Eq. 9: elements whose activation c_e = d_hat - d is positive are gathered
+// and evaluated, the others add nothing)
+// ---------------------------------------------------------------------------
+// Inputs of the generated functions: positions relative to p, k_c, d_hat.
+template <typename T>
+__device__ __forceinline__ void fill_contact(const int* __restrict__ tup,
+                                             const double* __restrict__ x, double kc, double dhat,
+                                             T* in) {
+  const int64_t p = tup[0];
+  const double x0 = x[3 * p], x1 = x[3 * p + 1], x2 = x[3 * p + 2];
+  in[0] = in[1] = in[2] = T(0);
+#pragma unroll
+  for (int a = 1; a < 4; ++a) {
+    const int64_t n = tup[a];
+    in[3 * a + 0] = T(x[3 * n + 0] - x0);
+    in[3 * a + 1] = T(x[3 * n + 1] - x1);
+    in[3 * a + 2] = T(x[3 * n + 2] - x2);
+  }
+  in[12] = T(kc);
+  in[13] = T(dhat);
+}
+
+// Activation of every candidate (float64), counted per chunk of
+// kContactChunk candidates (one workgroup per chunk).  A degenerate triangle
+// gives a NaN activation: inactive.
+__global__ __launch_bounds__(256) void k_contact_activate(int64_t n, const int* __restrict__ tuples,
+                                                         const double* __restrict__ x, double kc,
+                                                         double dhat, uint8_t* __restrict__ flag,
+                                                         int* __restrict__ chunk_count) {
+  __shared__ int sh[4];
+  const int64_t c0 = (int64_t)blockIdx.x * kContactChunk;
+  const int64_t c1 = c0 + kContactChunk < n ? c0 + kContactChunk : n;
+  int cnt = 0;
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += 256) {
+    double in[14], a[1];
+    fill_contact<double>(tuples + 4 * c, x, kc, dhat, in);
+    ipc_point_plane_act_s_E<double>(in, a);
+    const int f = a[0] > 0.0 ? 1 : 0;
+    flag[c] = (uint8_t)f;
+    cnt += f;
+  }
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) chunk_count[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Exclusive scan of the chunk counts (in place) and the total.
+__global__ void k_contact_scan(int n_chunks, int* __restrict__ chunk_count, int* __restrict__ total) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int acc = 0;
+  for (int i = 0; i < n_chunks; ++i) {
+    const int v = chunk_count[i];
+    chunk_count[i] = acc;
+    acc += v;
+  }
+  *total = acc;
+}
+
+// Compaction in candidate order: act[k] = the k-th active candidate, slot[c]
+// = its k, or -1 for an inactive candidate.
+__global__ __launch_bounds__(256) void k_contact_compact(int64_t n, const uint8_t* __restrict__ flag,
+                                                        const int* __restrict__ chunk_off,
+                                                        int* __restrict__ slot, int* __restrict__ act) {
+  __shared__ int wsum[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * kContactChunk;
+  int base = chunk_off[blockIdx.x];
+  for (int r = 0; r < kContactChunk / 256; ++r) {
+    const int64_t c = c0 + r * 256 + threadIdx.x;
+    const int f = c < n ? flag[c] : 0;
+    const unsigned long long mask = __ballot(f);
+    const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(mask);
+    __syncthreads();
+    int off = base;
+    for (int k = 0; k < w; ++k) off += wsum[k];
+    if (c < n) {
+      if (f) {
+        slot[c] = off + pre;
+        act[off + pre] = (int)c;
+      } else {
+        slot[c] = -1;
+      }
+    }
+    base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+}
+
+// Gradients (eg, n x 12) and Hessians (eH, n x 144) of the active elements,
+// in compacted order.
+template <typename T>
+__global__ __launch_bounds__(128) void k_contact_eval(const int* __restrict__ act,
+                                                     const int* __restrict__ n_active,
+                                                     const int* __restrict__ tuples,
+                                                     const double* __restrict__ x, double kc,
+                                                     double dhat, T* __restrict__ eg,
+                                                     T* __restrict__ eH) {
+  const int na = *n_active;
+  for (int k = blockIdx.x * 128 + threadIdx.x; k < na; k += gridDim.x * 128) {
+    T in[14], o[157];
+    fill_contact<T>(tuples + 4 * (int64_t)act[k], x, kc, dhat, in);
+    ipc_point_plane_s_EgH<T>(in, o);
+#pragma unroll
+    for (int v = 0; v < 12; ++v) eg[(int64_t)k * 12 + v] = o[1 + v];
+#pragma unroll
+    for (int v = 0; v < 144; ++v) eH[(int64_t)k * 144 + v] = o[13 + v];
+  }
+}
+
+// Nearest-PSD projection of the active elements' Hessians (the element
+// projection of the mesh's energies; the count is read on the device).
+__global__ __launch_bounds__(64, 2) void k_contact_project32(float* __restrict__ H,
+                                                            const int* __restrict__ n_active) {
+  project_psd_lane<float, 4, 1>(H, *n_active, 30, 2e-7f, nullptr);
+}
+__global__ __launch_bounds__(64) void k_contact_project64(double* __restrict__ H,
+                                                         const int* __restrict__ n_active) {
+  __shared__ double vs[9 * 9 * 64];
+  project_psd_lane<double, 4, 64>(H, *n_active, 30, 1e-15, vs);
+}
+
+// Contact blocks: each block sums its (candidate, a, b) contributions of the
+// active candidates in candidate order; Dirichlet rows and columns are zero.
+template <typename T>
+__global__ __launch_bounds__(256) void k_contact_blocks(
+    int64_t nnzb, const int* __restrict__ blk_row, const int* __restrict__ col,
+    const int* __restrict__ blk_ptr, const int* __restrict__ blk_src, const int* __restrict__ slot,
+    const T* __restrict__ eH, const uint8_t* __restrict__ fixed, T* __restrict__ vals) {
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nnzb;
+       p += (int64_t)gridDim.x * 256) {
+    T acc[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) acc[v] = T(0);
+    for (int j = blk_ptr[p]; j < blk_ptr[p + 1]; ++j) {
+      const int src = blk_src[j];
+      const int k = slot[src >> 4];
+      if (k < 0) continue;
+      const int a = (src >> 2) & 3, b = src & 3;
+      const T* H = eH + (int64_t)k * 144;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += H[(3 * a + i) * 12 + 3 * b + kk];
+    }
+    if (fixed && (fixed[blk_row[p]] | fixed[col[p]])) {
+#pragma unroll
+      for (int v = 0; v < 9; ++v) acc[v] = T(0);
+    }
+#pragma unroll
+    for (int v = 0; v < 9; ++v) vals[(int64_t)v * nnzb + p] = acc[v];
+  }
+}
+
+// Contact gradient rows added to g (float64, candidate order per node);
+// Dirichlet nodes keep their zero row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_contact_grad(int64_t n_gnode, const int* __restrict__ gnode,
+                                                     const int* __restrict__ gptr,
+                                                     const int* __restrict__ gsrc,
+                                                     const int* __restrict__ slot,
+                                                     const T* __restrict__ eg,
+                                                     const uint8_t* __restrict__ fixed,
+                                                     double* __restrict__ g,
+                                                     int* __restrict__ nonfinite) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_gnode;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t v = gnode[i];
+    if (fixed && fixed[v]) continue;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int j = gptr[i]; j < gptr[i + 1]; ++j) {
+      const int src = gsrc[j];
+      const int k = slot[src >> 2];
+      if (k < 0) continue;
+      const int a = src & 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] += double(eg[(int64_t)k * 12 + 3 * a + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double gv = g[3 * v + c] + acc[c];
+      if (!isfinite(gv)) *nonfinite = 1;
+      g[3 * v + c] = gv;
+    }
+  }
+}
+
+// Block-Jacobi inverses of the nodes with contact blocks, from the sum of the
+// mesh's and the contact diagonal block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_contact_dinv(int64_t n_gnode, const int* __restrict__ gnode,
+                                                     const int* __restrict__ gdiag,
+                                                     const int* __restrict__ diag_pos,
+                                                     const T* __restrict__ vals, int64_t nnzb,
+                                                     const T* __restrict__ cvals, int64_t cnnzb,
+                                                     T* __restrict__ dinv) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_gnode;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t v = gnode[i];
+    const int64_t p = diag_pos[v], q = gdiag[i];
+    double a[9], r[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) a[c] = double(vals[c * nnzb + p]) + double(cvals[c * cnnzb + q]);
+    inverse3(a, r);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dinv[9 * v + c] = T(r[c]);
+  }
+}
+
+// Contact energy of every candidate at x (float64): zero when inactive, +inf
+// when the point is on or behind the plane.
+__global__ __launch_bounds__(256) void k_contact_energy(int64_t n, const int* __restrict__ tuples,
+                                                       const double* __restrict__ x, double kc,
+                                                       double dhat, double* __restrict__ partials,
+                                                       int* __restrict__ nonfinite) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
+    double in[14], a[1];
+    fill_contact<double>(tuples + 4 * c, x, kc, dhat, in);
+    ipc_point_plane_act_s_E<double>(in, a);
+    if (!(a[0] > 0.0)) continue;
+    if (!(a[0] < dhat)) {
+      acc = INFINITY;
+      continue;
+    }
+    double e[1];
+    ipc_point_plane_s_E<double>(in, e);
+    acc += e[0];
+  }
+  const double s = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s;
+    if (!isfinite(s)) *nonfinite = 1;
+  }
+}
+
 // Host side of the kind dispatch: f(std::integral_constant<int, KIND>) for a
 // set of kind `kind` (validated at mesh creation); quadratic tets have kernels
 // of their own and are not dispatched here.
@@ -1987,6 +2251,12 @@ static int grid_for(int64_t work, int per_block, int cap = 16384) {
     if (e_ != hipSuccess) return hip_check(e_, what);              \
   } while (0)
 
+#define TRY(expr)                     \
+  do {                                \
+    symx_status s_ = (expr);          \
+    if (s_ != SYMX_OK) return s_;     \
+  } while (0)
+
 symx_status launch_energy(Mesh& m, const double* x, const double* xt, double dt, int precision,
                           double* E_dev) {
   const char* PNAME = "energy";
@@ -2012,6 +2282,14 @@ symx_status launch_energy(Mesh& m, const double* x, const double* xt, double dt,
                     m.X, m.partials + off, m.nonfinite);
     });
     LAUNCH_CHECK("k_energy_set");
+    off += G;
+  }
+  if (m.contacts) {
+    const Contacts& c = *m.contacts;
+    const int G = grid_for(c.n, 256, 8192);
+    SYMX_LAUNCH(m, "contact_energy", k_contact_energy, dim3(G), dim3(256), 0, c.n, c.tuples, x,
+                c.kc, c.dhat, m.partials + off, m.nonfinite);
+    LAUNCH_CHECK("k_contact_energy");
     off += G;
   }
   if (xt) {
@@ -2325,17 +2603,33 @@ symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const d
 // Enqueue iterations k0 .. k0+n_iter-1 (each: SpMV kernel, update kernel).
 symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0, int n_iter) {
   const int gs = pcg_gs(m.N), gu = pcg_gu(m.N);
+  const Contacts* cs = m.contacts;
+  const DynBsr<double> C64{cs ? cs->row_ptr : nullptr, cs ? cs->col_idx : nullptr,
+                           cs ? cs->vals64 : nullptr, cs ? cs->nnzb : 0};
+  const DynBsr<float> C32{cs ? cs->row_ptr : nullptr, cs ? cs->col_idx : nullptr,
+                          cs ? cs->vals32 : nullptr, cs ? cs->nnzb : 0};
   for (int it = k0; it < k0 + n_iter; ++it) {
     {
       const char* PNAME = "pcg_spmv";
-      if (precision == SYMX_F64)
-        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<double>, dim3(gs), dim3(256), 0, it, m.N,
-                           m.row_ptr, m.col_idx, m.vals64, m.nnzb, (const double*)B.z,
-                           (double*)B.p, (double*)B.q, m.partials, m.scalars, gu);
-      else
-        SYMX_LAUNCH(m, PNAME, k_pcg_spmv<float>, dim3(gs), dim3(256), 0, it, m.N,
-                           m.row_ptr, m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p,
-                           (float*)B.q, m.partials, m.scalars, gu);
+      if (precision == SYMX_F64) {
+        if (cs)
+          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<double, true>), dim3(gs), dim3(256), 0, it, m.N,
+                      m.row_ptr, m.col_idx, m.vals64, m.nnzb, (const double*)B.z, (double*)B.p,
+                      (double*)B.q, m.partials, m.scalars, gu, C64);
+        else
+          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<double, false>), dim3(gs), dim3(256), 0, it, m.N,
+                      m.row_ptr, m.col_idx, m.vals64, m.nnzb, (const double*)B.z, (double*)B.p,
+                      (double*)B.q, m.partials, m.scalars, gu, C64);
+      } else {
+        if (cs)
+          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<float, true>), dim3(gs), dim3(256), 0, it, m.N,
+                      m.row_ptr, m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p,
+                      (float*)B.q, m.partials, m.scalars, gu, C32);
+        else
+          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<float, false>), dim3(gs), dim3(256), 0, it, m.N,
+                      m.row_ptr, m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p,
+                      (float*)B.q, m.partials, m.scalars, gu, C32);
+      }
     }
     {
       const char* PNAME = "pcg_update";
@@ -2366,16 +2660,90 @@ symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs
   return SYMX_OK;
 }
 
+template <typename T>
+static symx_status contact_assemble_t(Mesh& m, const double* x, bool want_g, bool want_H,
+                                      bool project, bool dirichlet, double* g, T* dinv) {
+  Contacts& c = *m.contacts;
+  const int n_chunks = (int)((c.n + kContactChunk - 1) / kContactChunk);
+  SYMX_LAUNCH(m, "contact_activate", k_contact_activate, dim3(n_chunks), dim3(256), 0, c.n,
+              c.tuples, x, c.kc, c.dhat, c.flag, c.chunk_count);
+  SYMX_LAUNCH(m, "contact_scan", k_contact_scan, dim3(1), dim3(64), 0, n_chunks, c.chunk_count,
+              c.n_active);
+  SYMX_LAUNCH(m, "contact_compact", k_contact_compact, dim3(n_chunks), dim3(256), 0, c.n, c.flag,
+              c.chunk_count, c.slot, c.act);
+  const size_t eb = size_t(c.n) * kContactVals * sizeof(T);
+  if (c.eval_bytes < eb) {
+    dev_free(m.pool, c.eval);
+    c.eval = nullptr;
+    c.eval_bytes = 0;
+    TRY(dev_alloc(m.pool, &c.eval, eb));
+    c.eval_bytes = eb;
+  }
+  T* eg = (T*)c.eval;
+  T* eH = eg + 12 * c.n;
+  SYMX_LAUNCH(m, "contact_eval", k_contact_eval<T>, dim3(grid_for(c.n, 128, 8192)), dim3(128), 0,
+              c.act, c.n_active, c.tuples, x, c.kc, c.dhat, eg, eH);
+  if (want_H && project) {
+    const int G = grid_for(c.n, 64, 65535);
+    if (sizeof(T) == 4)
+      SYMX_LAUNCH(m, "contact_project", k_contact_project32, dim3(G), dim3(64), 0, (float*)eH,
+                  c.n_active);
+    else
+      SYMX_LAUNCH(m, "contact_project", k_contact_project64, dim3(G), dim3(64), 0, (double*)eH,
+                  c.n_active);
+  }
+  const uint8_t* fixed = dirichlet ? m.fixed : nullptr;
+  if (want_H) {
+    T*& vals = *(T**)(sizeof(T) == 4 ? (void*)&c.vals32 : (void*)&c.vals64);
+    if (!vals) TRY(dev_alloc(m.pool, (void**)&vals, 9 * c.nnzb * sizeof(T)));
+    SYMX_LAUNCH(m, "contact_blocks", k_contact_blocks<T>, dim3(grid_for(c.nnzb, 256)), dim3(256),
+                0, c.nnzb, c.blk_row, c.col_idx, c.blk_ptr, c.blk_src, c.slot, eH, fixed, vals);
+    if (dinv) {
+      const T* mv = (const T*)(sizeof(T) == 4 ? (void*)m.vals32 : (void*)m.vals64);
+      SYMX_LAUNCH(m, "contact_dinv", k_contact_dinv<T>, dim3(grid_for(c.n_gnode, 256)), dim3(256),
+                  0, c.n_gnode, c.gnode, c.gdiag, m.diag_pos, mv, m.nnzb, vals, c.nnzb, dinv);
+    }
+  }
+  if (want_g)
+    SYMX_LAUNCH(m, "contact_grad", k_contact_grad<T>, dim3(grid_for(c.n_gnode, 256)), dim3(256), 0,
+                c.n_gnode, c.gnode, c.gptr, c.gsrc, c.slot, eg, fixed, g, m.nonfinite);
+  LAUNCH_CHECK("k_contact");
+  return SYMX_OK;
+}
+
+symx_status launch_contact_assemble(Mesh& m, const double* x, bool want_g, bool want_H,
+                                    bool project, int precision, bool dirichlet, double* g,
+                                    void* dinv) {
+  if (!m.contacts || (!want_g && !want_H)) return SYMX_OK;
+  if (precision == SYMX_F32)
+    return contact_assemble_t<float>(m, x, want_g, want_H, project, dirichlet, g, (float*)dinv);
+  return contact_assemble_t<double>(m, x, want_g, want_H, project, dirichlet, g, (double*)dinv);
+}
+
 symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b,
                               double* r) {
   const char* PNAME = "residual64";
   const int G = grid_for(m.N * 16, 256, 16384);
-  if (precision == SYMX_F64)
-    SYMX_LAUNCH(m, PNAME, k_residual64<double>, dim3(G), dim3(256), 0, m.N, m.row_ptr,
-                       m.col_idx, m.vals64, m.nnzb, x, b, r);
-  else
-    SYMX_LAUNCH(m, PNAME, k_residual64<float>, dim3(G), dim3(256), 0, m.N, m.row_ptr,
-                       m.col_idx, m.vals32, m.nnzb, x, b, r);
+  const Contacts* cs = m.contacts;
+  const DynBsr<double> C64{cs ? cs->row_ptr : nullptr, cs ? cs->col_idx : nullptr,
+                           cs ? cs->vals64 : nullptr, cs ? cs->nnzb : 0};
+  const DynBsr<float> C32{cs ? cs->row_ptr : nullptr, cs ? cs->col_idx : nullptr,
+                          cs ? cs->vals32 : nullptr, cs ? cs->nnzb : 0};
+  if (precision == SYMX_F64) {
+    if (cs)
+      SYMX_LAUNCH(m, PNAME, (k_residual64<double, true>), dim3(G), dim3(256), 0, m.N, m.row_ptr,
+                  m.col_idx, m.vals64, m.nnzb, x, b, r, C64);
+    else
+      SYMX_LAUNCH(m, PNAME, (k_residual64<double, false>), dim3(G), dim3(256), 0, m.N, m.row_ptr,
+                  m.col_idx, m.vals64, m.nnzb, x, b, r, C64);
+  } else {
+    if (cs)
+      SYMX_LAUNCH(m, PNAME, (k_residual64<float, true>), dim3(G), dim3(256), 0, m.N, m.row_ptr,
+                  m.col_idx, m.vals32, m.nnzb, x, b, r, C32);
+    else
+      SYMX_LAUNCH(m, PNAME, (k_residual64<float, false>), dim3(G), dim3(256), 0, m.N, m.row_ptr,
+                  m.col_idx, m.vals32, m.nnzb, x, b, r, C32);
+  }
   LAUNCH_CHECK("k_residual64");
   return SYMX_OK;
 }

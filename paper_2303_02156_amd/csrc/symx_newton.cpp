@@ -139,16 +139,22 @@ symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool
     // filtered rows itself; otherwise element-wise records, then assembly
     bool snh_only = true;
     for (const SetHost& s : m.sets) snh_only = snh_only && s.kind == SYMX_SNH_TET4;
-    if (project == 2 && snh_only)
-      return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, nullptr, true,
-                                 g_out, dinv);
-    TRY(project_into_records(m, x, precision, project));
-    return launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, m.inc_rows, false,
-                               g_out, dinv);
+    if (project == 2 && snh_only) {
+      TRY(launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, nullptr, true,
+                              g_out, dinv));
+    } else {
+      TRY(project_into_records(m, x, precision, project));
+      TRY(launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, m.inc_rows, false,
+                              g_out, dinv));
+    }
+    // contact element Hessians take the nearest-PSD projection in both modes
+    return launch_contact_assemble(m, x, want_g, true, true, precision, dirichlet, g_out, dinv);
   }
   if (!want_g && !want_H) return SYMX_OK;
-  return launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, false,
-                             g_out, want_H ? dinv : nullptr);
+  TRY(launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, false,
+                          g_out, want_H ? dinv : nullptr));
+  return launch_contact_assemble(m, x, want_g, want_H, false, precision, dirichlet, g_out,
+                                 want_H ? dinv : nullptr);
 }
 
 symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E) {

@@ -92,6 +92,9 @@ EXPORTS = {
     "symx_newton_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(StepParams),
                                    C.POINTER(StepReport)]),
     "symx_mesh_update_rotations": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "symx_mesh_set_contacts": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_double,
+                                         C.c_double]),
+    "symx_mesh_get_contact_bsr": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(BsrView)]),
     "symx_mesh_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "symx_mesh_get_kernel_time": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double,
                                             C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -185,6 +188,19 @@ def symx_newton_step(h, x_dev, v_dev, params):
 
 def symx_mesh_update_rotations(h, x_dev):
     _check(load().symx_mesh_update_rotations(h, x_dev), "symx_mesh_update_rotations")
+
+
+def symx_mesh_set_contacts(h, tuples_host, kc, dhat):
+    t = np.ascontiguousarray(tuples_host, dtype=np.int32).reshape(-1, 4)
+    _check(load().symx_mesh_set_contacts(h, t.shape[0], t.ctypes.data if t.size else None, kc, dhat),
+           "symx_mesh_set_contacts")
+
+
+def symx_mesh_get_contact_bsr(h, precision):
+    view = BsrView()
+    _check(load().symx_mesh_get_contact_bsr(h, precision, C.byref(view)),
+           "symx_mesh_get_contact_bsr")
+    return view
 
 
 def symx_mesh_set_profiling(h, enable):
@@ -363,6 +379,27 @@ class Mesh:
             vals = t.empty((9, self.info.nnzb), dtype=dtype, device="cuda")
             _device_copy(vals.data_ptr(), view.values, vals.numel() * vals.element_size())
         return E, g, vals
+
+    def set_contacts(self, tuples, kc, dhat):
+        """Candidate contacts (n x 4: point, triangle) of the barrier."""
+        symx_mesh_set_contacts(self.handle, tuples, kc, dhat)
+
+    def contact_bsr(self, precision=SYMX_F64):
+        """Host copies (row_ptr, col_idx, values (nnzb, 3, 3) float64) of the
+        contact matrix of the last assembly."""
+        t = self.torch
+        v = symx_mesh_get_contact_bsr(self.handle, precision)
+        if v.nnzb == 0:
+            return np.zeros(self.N + 1, np.int32), np.zeros(0, np.int32), np.zeros((0, 3, 3))
+        rp = t.empty(self.N + 1, dtype=t.int32, device="cuda")
+        ci = t.empty(v.nnzb, dtype=t.int32, device="cuda")
+        dtype = t.float64 if precision == SYMX_F64 else t.float32
+        vals = t.empty((9, v.nnzb), dtype=dtype, device="cuda")
+        _device_copy(rp.data_ptr(), v.row_ptr, rp.numel() * 4)
+        _device_copy(ci.data_ptr(), v.col_idx, ci.numel() * 4)
+        _device_copy(vals.data_ptr(), v.values, vals.numel() * vals.element_size())
+        return (rp.cpu().numpy(), ci.cpu().numpy(),
+                vals.cpu().numpy().astype(np.float64).T.reshape(-1, 3, 3))
 
     def update_rotations(self, x):
         """Lagged rotations of the co-rotational and ARAP sets taken at x."""

@@ -66,6 +66,15 @@ class EnergySet:
 
 
 @dataclass
+class ContactList:
+    """Candidate contacts of the point-plane barrier: node p against the plane
+    of nodes t0, t1, t2 (rows (p, t0, t1, t2)); barrier stiffness and range."""
+    tuples: np.ndarray                 # (n, 4) int32
+    kc: float = 1e3
+    dhat: float = 1e-3
+
+
+@dataclass
 class Scene:
     name: str
     X: np.ndarray                      # (N,3) float64 rest positions
@@ -76,6 +85,7 @@ class Scene:
     dt: float = 0.01
     gravity: tuple = (0.0, 0.0, -9.81)
     meta: dict = field(default_factory=dict)
+    contacts: ContactList | None = None
 
     @property
     def n_nodes(self) -> int:
@@ -236,6 +246,41 @@ def stretched_box_scene(kind: int, dims: tuple = (40, 40, 60), h: float = 0.01,
     es = EnergySet(kind, tets, young=young, poisson=poisson, density=1000.0)
     return Scene(f"stretched-box-k{kind}", X, [es], fixed, x0, np.zeros_like(X), dt=0.01,
                  meta=dict(dims=dims, h=h, stretch=stretch, seed=seed))
+
+
+def contact_stack_scene(n: int = 4, h: float = 0.01, dhat: float = 1e-3, kc: float = 1e3,
+                        gap: float = 1.0, noise: float = 0.5, vz: float = -0.05,
+                        seed: int = 9) -> Scene:
+    """Two SNH cubes of n^3 6-tet cubes, the upper one resting gap * dhat above
+    the lower one's top face (bottom face of the lower cube fixed).  Upper
+    nodes get a vertical offset U(-noise, noise) * dhat and velocity vz.
+    Candidate contacts: every node of the upper cube's bottom face against the
+    lower top-face triangle (v00, v10, v11) of the cell below it, so about
+    half of them are within d_hat."""
+    X1, t1 = tet_grid(n, n, n, h)
+    X2, t2 = tet_grid(n, n, n, h, origin=(0.0, 0.0, n * h + gap * dhat))
+    N1 = X1.shape[0]
+    X = np.concatenate([X1, X2])
+    tets = np.concatenate([t1, t2 + N1]).astype(np.int32)
+    fixed = np.concatenate([_bottom_fixed(X1), np.zeros(N1, np.uint8)])
+    rng = np.random.default_rng(seed)
+    x0 = X.copy()
+    x0[N1:, 2] += rng.uniform(-noise, noise, N1) * dhat
+    v0 = np.zeros_like(X)
+    v0[N1:, 2] = vz
+
+    def nid(i, j, k):
+        return i + (n + 1) * (j + (n + 1) * k)
+    tuples = []
+    for j in range(n + 1):
+        for i in range(n + 1):
+            ci, cj = min(i, n - 1), min(j, n - 1)
+            tuples.append([N1 + nid(i, j, 0), nid(ci, cj, n), nid(ci + 1, cj, n),
+                           nid(ci + 1, cj + 1, n)])
+    es = EnergySet(SNH_TET4, tets, young=1e5, poisson=0.4, density=1000.0)
+    return Scene(f"contact-stack{n}", X, [es], fixed, x0, v0, dt=0.01,
+                 meta=dict(n=n, h=h, gap=gap, noise=noise, seed=seed),
+                 contacts=ContactList(np.asarray(tuples, dtype=np.int32), kc=kc, dhat=dhat))
 
 
 def config_c1() -> Scene:

@@ -303,3 +303,31 @@ def test_tet10_generated_vs_oracle(lib):
         assert _rel(row[:, 3:].reshape(n, 3, 9, 3), H[:, a][:, :, others, :]) < 1e-9
         rg = _tet10_sum(lib, f"snh_tet10_row{r}_g", xs, Xs, mu, lam, 3)
         assert _rel(rg, g[:, a]) < 1e-9
+
+
+def test_contact_barrier_generated_vs_oracle(lib):
+    """The conditional point-plane barrier and its activation (Eq. 9 and the
+    contact potential) against the oracle's hand derivatives."""
+    from oracle import contact
+    rng = np.random.default_rng(111)
+    n = 30
+    t = rng.normal(size=(n, 3, 3)) * 0.01
+    N = np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    nrm = N / np.linalg.norm(N, axis=1, keepdims=True)
+    d = rng.uniform(0.1, 0.95, n) * 1e-3
+    p = t.mean(axis=1) + rng.normal(size=(n, 3)) * 0.003
+    p = p - np.einsum("ei,ei->e", p - t[:, 0], nrm)[:, None] * nrm + d[:, None] * nrm
+    x = np.concatenate([p[:, None], t], axis=1)
+    kc, dh = 1e3, 1e-3
+    E, g, H, act = contact.point_plane_barrier(x, kc, dh)
+    assert act.all()
+    inp = np.concatenate([x.reshape(n, 12), np.full((n, 1), kc), np.full((n, 1), dh)], axis=1)
+    out = _call(lib, "ipc_point_plane_EgH", inp, 157)
+    assert _rel(out[:, 0], E) < 1e-10
+    assert _rel(out[:, 1:13], g.reshape(n, 12)) < 1e-10
+    assert _rel(out[:, 13:], H.reshape(n, 144)) < 1e-9
+    rel_in = inp.copy()
+    rel_in[:, :12] -= np.tile(x[:, 0], 4)
+    assert _rel(_call(lib, "ipc_point_plane_s_EgH", rel_in, 157), out) < 1e-9
+    a = _call(lib, "ipc_point_plane_act_s_E", rel_in, 1)[:, 0]
+    assert _rel(a, contact.activation(x, dh)) < 1e-10

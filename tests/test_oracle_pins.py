@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import scenegen as sg
-from oracle import assembly, elements, newton, projection, rest
+from oracle import contact, assembly, elements, newton, projection, rest
 
 
 def _rot(seed):
@@ -273,6 +273,68 @@ def test_closest_rotation():
     for s in range(300):                                  # no rotation does better
         T = _rot(s + 100)
         assert np.all(np.einsum("ij,eij->e", T, F) <= best + 1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Conditional contact barrier: point against the plane of a triangle
+# ----------------------------------------------------------------------------
+def _contact_elems(n, seed, d_lo=0.1, d_hi=2.0):
+    """Random triangles and points at signed distance in [d_lo, d_hi] * 1e-3
+    above them (plus an in-plane offset)."""
+    rng = np.random.default_rng(seed)
+    t = rng.normal(size=(n, 3, 3)) * 0.01
+    N = np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    nrm = N / np.linalg.norm(N, axis=1, keepdims=True)
+    d = rng.uniform(d_lo, d_hi, n) * 1e-3
+    p = t.mean(axis=1) + rng.normal(size=(n, 3)) * 0.003
+    p = p - np.einsum("ei,ei->e", p - t[:, 0], nrm)[:, None] * nrm + d[:, None] * nrm
+    return np.concatenate([p[:, None], t], axis=1), d
+
+
+def test_point_plane_distance_closed_form_and_derivatives():
+    x, d_true = _contact_elems(30, 101)
+    d, dd, d2d = contact.point_plane_distance(x)
+    assert np.allclose(d, d_true, rtol=1e-12)
+    # complex-step gradient and Hessian of the distance
+    gc = _cs_grad(lambda xc: contact.point_plane_distance(xc)[0], x).reshape(30, 12)
+    Hc = _cs_jac(lambda xc: contact.point_plane_distance(xc)[1].reshape(-1, 4, 3), x)
+    assert _rel(dd, gc) < 1e-12
+    assert _rel(d2d, Hc.reshape(30, 12, 12)) < 1e-10
+    # translation and rotation invariance; the gradient of p is the unit normal
+    Q = _rot(102)
+    d2, _, _ = contact.point_plane_distance(x @ Q.T + 0.3)
+    assert np.allclose(d2, d, rtol=1e-12)
+    assert np.allclose(np.linalg.norm(dd[:, :3], axis=1), 1.0)
+
+
+def test_contact_barrier_and_activation():
+    """b(d) vanishes with its first two derivatives at d = d_hat (the
+    conditional energy is C2 across the activation boundary); complex-step
+    derivatives of b and of the element energy; inactive elements give zero,
+    a point through the plane gives +inf."""
+    kc, dhat = 1e3, 1e-3
+    dv = np.linspace(0.05, 0.999, 25) * dhat
+    b, b1, b2 = contact.barrier(dv, kc, dhat)
+    h = 1e-30
+    assert np.allclose(b1, np.imag(contact.barrier(dv + 1j * h, kc, dhat)[0]) / h, rtol=1e-12)
+    assert np.allclose(b2, np.imag(contact.barrier(dv + 1j * h, kc, dhat)[1]) / h, rtol=1e-12)
+    bb = contact.barrier(np.array([dhat]), kc, dhat)
+    assert all(abs(v[0]) < 1e-18 for v in bb)
+    x, d = _contact_elems(40, 103, d_lo=0.2, d_hi=1.8)            # about half active
+    E, g, H, act = contact.point_plane_barrier(x, kc, dhat)
+    assert np.array_equal(act, d < dhat) and 5 < act.sum() < 35
+    assert np.all(E[~act] == 0) and np.all(g[~act] == 0) and np.all(H[~act] == 0)
+    assert np.all(E[act] > 0)
+    xa = x[act]
+    gc = _cs_grad(lambda xc: contact.point_plane_barrier(xc, kc, dhat, False)[0], xa)
+    Hc = _cs_jac(lambda xc: contact.point_plane_barrier(xc, kc, dhat, False)[1], xa)
+    assert _rel(g[act], gc) < 1e-11
+    assert _rel(H[act], Hc) < 1e-9
+    xin = x[:1].copy()
+    d0, dd0, _ = contact.point_plane_distance(xin)
+    xin[0, 0] -= (d0[0] + 1e-4) * dd0[0, :3]                      # through the plane
+    E2, _, _, act2 = contact.point_plane_barrier(xin, kc, dhat)
+    assert act2[0] and np.isinf(E2[0])
 
 
 # ----------------------------------------------------------------------------
