@@ -474,6 +474,73 @@ def quadratic_bench(symx, torch, reps=10):
     return out
 
 
+def contact_bench(symx, torch, n=32, reps=10):
+    """Conditional point-plane barrier on two stacked SNH cubes of n^3 6-tet
+    cubes: every node of the upper bottom face against both triangles of the
+    lower top-face cells around it (about 8 candidates per node, half of them
+    within d_hat).  E+g+H assembly with and without contacts (FP32, device
+    events, median of reps), the contact kernels' device times, and one
+    FP32-refined Newton step."""
+    import numpy as np
+    import scenegen as sg
+    scene = sg.contact_stack_scene(n, neighbors=True)
+    cl = scene.contacts
+    mesh = symx.Mesh(scene)
+    dt = scene.dt
+    x0 = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v0 = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    xt = torch.tensor(scene.x0 + dt * scene.v0 + dt * dt * np.asarray(scene.gravity)[None, :],
+                      dtype=torch.float64, device="cuda")
+    g = torch.empty_like(x0)
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+
+    def timed():
+        ms = []
+        for r in range(reps + 3):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            symx.symx_assemble_bsr(mesh.handle, x0.data_ptr(), xt.data_ptr(), dt, flags,
+                                   symx.SYMX_F32, g.data_ptr())
+            b.record()
+            b.synchronize()
+            if r >= 3:
+                ms.append(a.elapsed_time(b))
+        return statistics.median(ms)
+    t_plain = timed()
+    t0 = time.perf_counter()
+    mesh.set_contacts(cl.tuples, cl.kc, cl.dhat)
+    set_ms = (time.perf_counter() - t0) * 1e3
+    t_contact = timed()
+    mesh.profile(True)
+    for _ in range(3):
+        mesh.assemble(x0, xt, dt, flags, symx.SYMX_F32, grad_out=g)
+    kt = {k: round(v[1] / max(v[0], 1), 5) for k, v in mesh.kernel_times().items()
+          if k.startswith("contact")}
+    mesh.profile(False)
+    cview = symx.symx_mesh_get_contact_bsr(mesh.handle, symx.SYMX_F32)
+    x = x0.clone()
+    v = v0.clone()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st, rep = mesh.newton_step(x, v, symx.step_params(dt=dt, precision=symx.SYMX_F32_REFINED,
+                                                      max_pcg=500))
+    torch.cuda.synchronize()
+    out = {"workload": f"two stacked {n}^3-cube SNH blocks ({scene.n_elements()} tets), "
+                       f"{cl.tuples.shape[0]} point-plane candidates (k_c {cl.kc}, d_hat "
+                       f"{cl.dhat}), upper block moving down at 0.05 m/s, dt 0.01",
+           "candidates": int(cl.tuples.shape[0]), "contact_blocks": int(cview.nnzb),
+           "set_contacts_ms_host": round(set_ms, 2),
+           "assembly_ms_f32_without_contacts": round(t_plain, 4),
+           "assembly_ms_f32_with_contacts": round(t_contact, 4),
+           "contact_kernel_avg_ms": kt,
+           "newton_ms_f32_refined": round((time.perf_counter() - t1) * 1e3, 2),
+           "status": symx.STATUS[st], "newton_iters": rep.newton_iters, "pcg_iters": rep.pcg_iters}
+    mesh.close()
+    log(f"contacts: {out}")
+    return out
+
+
 def cpu_baseline(seconds_target=10.0):
     """FP64 numpy oracle: eval + assembly (E, g, BSR) of a 24^3 cube of the same
     workload recipe, repeated until ~seconds_target of CPU work."""
@@ -528,7 +595,8 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-materials", action="store_true")
     ap.add_argument("--no-quadratic", action="store_true")
-    ap.add_argument("--only", choices=["c3", "c4", "materials", "quadratic"],
+    ap.add_argument("--no-contacts", action="store_true")
+    ap.add_argument("--only", choices=["c3", "c4", "materials", "quadratic", "contacts"],
                     help="run only this extra workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run plain 512 MiB device copies first (byte-counter calibration)")
@@ -565,6 +633,9 @@ def main():
         return
     if args.only == "quadratic":
         print(json.dumps({"quadratic": quadratic_bench(symx, torch)}), flush=True)
+        return
+    if args.only == "contacts":
+        print(json.dumps({"contacts": contact_bench(symx, torch)}), flush=True)
         return
     if args.calib_copy:
         # a plain copy kernel of known size: 512 MiB read + 512 MiB written per launch
@@ -736,6 +807,7 @@ def main():
         log(f"c3: {c3}")
     materials = None if args.no_materials else materials_bench(symx, torch)
     quadratic = None if args.no_quadratic else quadratic_bench(symx, torch)
+    contacts = None if args.no_contacts else contact_bench(symx, torch)
 
     serving = None
     if not args.no_serving:
@@ -791,6 +863,7 @@ def main():
         "c3_mixed": c3,
         "materials": materials,
         "quadratic_tets": quadratic,
+        "contacts": contacts,
         "mesh_setup_s": round(setup_s, 3),
         "kernels_f32_refined_steps": kernels,
         "roofline": roofline,

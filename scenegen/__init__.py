@@ -250,13 +250,15 @@ def stretched_box_scene(kind: int, dims: tuple = (40, 40, 60), h: float = 0.01,
 
 def contact_stack_scene(n: int = 4, h: float = 0.01, dhat: float = 1e-3, kc: float = 1e3,
                         gap: float = 1.0, noise: float = 0.5, vz: float = -0.05,
-                        seed: int = 9) -> Scene:
+                        seed: int = 9, neighbors: bool = False) -> Scene:
     """Two SNH cubes of n^3 6-tet cubes, the upper one resting gap * dhat above
     the lower one's top face (bottom face of the lower cube fixed).  Upper
     nodes get a vertical offset U(-noise, noise) * dhat and velocity vz.
     Candidate contacts: every node of the upper cube's bottom face against the
     lower top-face triangle (v00, v10, v11) of the cell below it, so about
-    half of them are within d_hat."""
+    half of them are within d_hat.  neighbors=True lists instead both
+    triangles of every cell touching the node's position (up to 8 per node),
+    the candidate set of a proximity query with a one-cell margin."""
     X1, t1 = tet_grid(n, n, n, h)
     X2, t2 = tet_grid(n, n, n, h, origin=(0.0, 0.0, n * h + gap * dhat))
     N1 = X1.shape[0]
@@ -274,9 +276,18 @@ def contact_stack_scene(n: int = 4, h: float = 0.01, dhat: float = 1e-3, kc: flo
     tuples = []
     for j in range(n + 1):
         for i in range(n + 1):
-            ci, cj = min(i, n - 1), min(j, n - 1)
-            tuples.append([N1 + nid(i, j, 0), nid(ci, cj, n), nid(ci + 1, cj, n),
-                           nid(ci + 1, cj + 1, n)])
+            if not neighbors:
+                ci, cj = min(i, n - 1), min(j, n - 1)
+                tuples.append([N1 + nid(i, j, 0), nid(ci, cj, n), nid(ci + 1, cj, n),
+                               nid(ci + 1, cj + 1, n)])
+                continue
+            for cj in (j - 1, j):
+                for ci in (i - 1, i):
+                    if 0 <= ci < n and 0 <= cj < n:
+                        v00, v10 = nid(ci, cj, n), nid(ci + 1, cj, n)
+                        v01, v11 = nid(ci, cj + 1, n), nid(ci + 1, cj + 1, n)
+                        tuples.append([N1 + nid(i, j, 0), v00, v10, v11])
+                        tuples.append([N1 + nid(i, j, 0), v00, v11, v01])
     es = EnergySet(SNH_TET4, tets, young=1e5, poisson=0.4, density=1000.0)
     return Scene(f"contact-stack{n}", X, [es], fixed, x0, v0, dt=0.01,
                  meta=dict(n=n, h=h, gap=gap, noise=noise, seed=seed),
