@@ -26,6 +26,11 @@ Energies:
   approach of Smith et al. 2019, an alternative to projecting the 12x12
   element Hessian; it differs from the nearest-PSD element Hessian unless B
   is orthogonal up to scale).
+* Stable Neo-Hookean cubic tet (tet20) -- Eq. 12 with the cubic Lagrange
+  interpolation (corners L(3L-1)(3L-2)/2, edge nodes 9/2 L_i L_j (3L_i - 1),
+  face nodes 27 L_i L_j L_k) and Keast's symmetric 11-point rule of degree 4
+  (centroid weight -74/5625; points (11/14, 1/14, 1/14, 1/14) with 343/45000;
+  points (c, c, d, d), c, d = (1 +- sqrt(5/14))/4, with 56/2250).
 * Stable Neo-Hookean quadratic tet (tet10) -- Eq. 12: E_e = sum over the
   quadrature points xi_q of w_q |det J_X(xi_q)| psi(F(xi_q)), F = J_x J_X^-1,
   with the tet10 interpolation of App. A and a symmetric 4-point rule of
@@ -250,6 +255,49 @@ def tet10_shape_derivatives(xi):
     return dN
 
 
+def tet20_shape_derivatives(xi):
+    """dN_a/dxi_k (20, 3) of the cubic interpolation at xi (node order of
+    scenegen's cubic grids)."""
+    L = np.array([1.0 - xi.sum(), xi[0], xi[1], xi[2]])
+    dL = np.array([[-1.0, -1.0, -1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    dN = np.empty((20, 3))
+    for c in range(4):
+        # d/dL [L (3L-1)(3L-2) / 2] = (27 L^2 - 18 L + 2) / 2
+        dN[c] = 0.5 * (27.0 * L[c] ** 2 - 18.0 * L[c] + 2.0) * dL[c]
+    edges = ((0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3))
+    for k, (i, j) in enumerate(edges):
+        for slot, (u, v) in enumerate(((i, j), (j, i))):
+            # N = 9/2 L_u L_v (3 L_u - 1)
+            dN[4 + 2 * k + slot] = 4.5 * ((6.0 * L[u] - 1.0) * L[v] * dL[u]
+                                          + L[u] * (3.0 * L[u] - 1.0) * dL[v])
+    faces = ((1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2))
+    for c, (i, j, k) in enumerate(faces):
+        dN[16 + c] = 27.0 * (L[j] * L[k] * dL[i] + L[i] * L[k] * dL[j] + L[i] * L[j] * dL[k])
+    return dN
+
+
+def _keast11():
+    """Keast's 11-point rule of degree 4 on the reference tet (weights sum to
+    the volume 1/6); symmetric under the vertex permutations."""
+    rule = [(-74.0 / 5625.0, np.array([0.25, 0.25, 0.25]))]
+    a, b = 11.0 / 14.0, 1.0 / 14.0
+    for i in range(4):
+        L = np.full(4, b)
+        L[i] = a
+        rule.append((343.0 / 45000.0, L[1:].copy()))
+    c = (1.0 + np.sqrt(5.0 / 14.0)) / 4.0
+    d = (1.0 - np.sqrt(5.0 / 14.0)) / 4.0
+    for i in range(4):
+        for j in range(i + 1, 4):
+            L = np.full(4, d)
+            L[i] = L[j] = c
+            rule.append((56.0 / 2250.0, L[1:].copy()))
+    return rule
+
+
+TET20_RULE = _keast11()
+
+
 def _snh_density(F, mu_, lam_):
     """psi, dpsi/dF and (lazily) d2psi/dF2 of Stable Neo-Hookean (App. B)."""
     Ic = np.einsum("eij,eij->e", F, F)
@@ -287,18 +335,28 @@ def snh_tet4_filtered(x, X, mu, lam):
     return E, g, H
 
 
+def snh_tet20(x, X, mu, lam, want_hess=True):
+    """Cubic tets: as snh_tet10 with the cubic interpolation and its rule."""
+    return _snh_high_order(x, X, mu, lam, want_hess, TET20_RULE, tet20_shape_derivatives)
+
+
 def snh_tet10(x, X, mu, lam, want_hess=True, rule=None):
     """Energy, gradient (E,10,3) and Hessian (E,10,3,10,3) of a quadratic tet:
     at each quadrature point the shape gradients b_a = J_X^-T dN_a/dxi give
     dF_ij/dx_{a,m} = delta_im b_a[j], and the point adds w |det J_X| times
     psi, P b_a and b_a d2psi b_b to E, g_a and H_ab."""
+    return _snh_high_order(x, X, mu, lam, want_hess, TET10_RULE if rule is None else rule,
+                           tet10_shape_derivatives)
+
+
+def _snh_high_order(x, X, mu, lam, want_hess, rule, shape_derivatives):
     mu_, lam_ = snh_reparam(np.asarray(mu, dtype=np.float64), np.asarray(lam, dtype=np.float64))
-    n = x.shape[0]
+    n, k = x.shape[0], x.shape[1]
     E = np.zeros(n, dtype=x.dtype)
-    g = np.zeros((n, 10, 3), dtype=x.dtype)
-    H = np.zeros((n, 10, 3, 10, 3), dtype=x.dtype) if want_hess else None
-    for w, xi in (TET10_RULE if rule is None else rule):
-        dN = tet10_shape_derivatives(xi)
+    g = np.zeros((n, k, 3), dtype=x.dtype)
+    H = np.zeros((n, k, 3, k, 3), dtype=x.dtype) if want_hess else None
+    for w, xi in rule:
+        dN = shape_derivatives(xi)
         JX = np.einsum("eai,ak->eik", X, dN)
         Jx = np.einsum("eai,ak->eik", x, dN)
         JXinv = np.linalg.inv(JX)
@@ -450,4 +508,6 @@ def element_eval(es, x, X, want_hess=True, x_lag=None):
         return f(xe, Xe, mu, lam, R, want_hess)
     if es.kind == 7:
         return snh_tet10(xe, Xe, mu, lam, want_hess)
+    if es.kind == 8:
+        return snh_tet20(xe, Xe, mu, lam, want_hess)
     raise ValueError(f"unknown energy kind {es.kind}")

@@ -14,7 +14,9 @@
   rho V.  With int L0^p L1^q L2^r L3^s dV = 6V p!q!r!s!/(p+q+r+s+3)! the
   diagonal is V/70 at a corner and 8V/105 at an edge node (sum 18V/35), so a
   corner gets rho V/36 and an edge node 4 rho V/27 (V of the straight-sided
-  element, i.e. of its corner tet).
+  element, i.e. of its corner tet).  Cubic tets likewise: the diagonal is
+  V/280 at a corner, 27V/1120 at an edge node and 27V/280 at a face node
+  (sum 193V/280), so rho V/193, 27 rho V/772 and 27 rho V/193.
 """
 from __future__ import annotations
 
@@ -25,6 +27,7 @@ import numpy as np
 # Saint Venant-Kirchhoff, fixed co-rotational, ARAP (scenegen numbering).
 TET_KINDS = (0, 3, 4, 5, 6)
 TET10_KIND = 7                     # quadratic Stable Neo-Hookean tet
+TET20_KIND = 8                     # cubic Stable Neo-Hookean tet
 
 
 def lame(young, poisson):
@@ -58,9 +61,12 @@ def lumped_mass(scene):
         if es.kind in TET_KINDS:
             V = tet_volume(scene.X[es.conn])
             np.add.at(m, es.conn.ravel(), np.repeat(es.density * V / 4.0, 4))
-        elif es.kind == TET10_KIND:
+        elif es.kind in (TET10_KIND, TET20_KIND):
             V = tet_volume(scene.X[es.conn[:, :4]])
-            share = np.array([1.0 / 36.0] * 4 + [4.0 / 27.0] * 6)
+            if es.kind == TET10_KIND:
+                share = np.array([1.0 / 36.0] * 4 + [4.0 / 27.0] * 6)
+            else:
+                share = np.array([1.0 / 193.0] * 4 + [27.0 / 772.0] * 12 + [27.0 / 193.0] * 4)
             np.add.at(m, es.conn.ravel(), (es.density * V[:, None] * share[None, :]).ravel())
         elif es.kind == 1:
             A = tri_area(scene.X[es.conn])

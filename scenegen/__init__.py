@@ -19,6 +19,10 @@ their meshes are not public, so procedural grids of the same kind stand in
   tet edge (i, j), i < j, gets a mid-edge node at the midpoint of its rest
   endpoints, numbered after the vertices in ascending (i, j) order.  Element
   connectivity is (4 corners, 6 edge nodes) in the App. A order above.
+* Cubic tet grids: vertices keep their ids; every distinct edge (i, j), i < j,
+  gets the nodes at 1/3 and 2/3 from i (numbered in that order, edges in
+  ascending (i, j)), then every distinct face (i < j < k) a node at its
+  centroid (faces in ascending order).
 * Cloth grids: m*m cells on [0,size]^2 at height z0, node id i + (m+1)j, each
   cell split along (i,j)->(i+1,j+1) into two counter-clockwise triangles.
   Hinges are the interior edges shared by two triangles, listed as
@@ -40,13 +44,17 @@ STVK_TET4 = 4
 FCR_TET4 = 5
 ARAP_TET4 = 6
 SNH_TET10 = 7
+SNH_TET20 = 8
 
 NODES_PER_ELEM = {SNH_TET4: 4, STVK_TRI3: 3, HINGE4: 4, NH_TET4: 4, STVK_TET4: 4, FCR_TET4: 4,
-                  ARAP_TET4: 4, SNH_TET10: 10}
+                  ARAP_TET4: 4, SNH_TET10: 10, SNH_TET20: 20}
 
 # Quadratic tet node order (App. A, tet10 interpolation): corners 0-3, then the
 # mid-edge nodes of edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3).
 TET10_EDGES = ((0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3))
+# Cubic tet node order: corners 0-3; for edge k = (i, j) of the list above the
+# nodes 4 + 2k (one third from i) and 5 + 2k (one third from j); the face
+# nodes 16 + c (centroid of the face opposite corner c).
 
 _PERMS = list(itertools.permutations(range(3)))          # lexicographic order
 _PERM_ODD = [False, True, True, False, False, True]      # parity of each entry
@@ -147,6 +155,39 @@ def tet10_grid(nx: int, ny: int, nz: int, h: float, origin=(0.0, 0.0, 0.0)):
     return np.concatenate([X, Xe]), conn.astype(np.int32)
 
 
+def tet20_grid(nx: int, ny: int, nz: int, h: float, origin=(0.0, 0.0, 0.0)):
+    """The tet grid with two nodes on every tet edge and one on every face
+    (cubic tets)."""
+    X, tets = tet_grid(nx, ny, nz, h, origin)
+    nv = X.shape[0]
+    t = tets.astype(np.int64)
+    ends = np.stack([np.stack([t[:, i], t[:, j]], axis=1) for i, j in TET10_EDGES], axis=1)
+    lo, hi = ends.min(axis=2), ends.max(axis=2)
+    ekey = lo * nv + hi
+    uniq, inv = np.unique(ekey.ravel(), return_inverse=True)
+    inv = inv.reshape(-1, 6)
+    ulo, uhi = uniq // nv, uniq % nv
+    Xe = np.empty((2 * uniq.size, 3))
+    Xe[0::2] = (2.0 * X[ulo] + X[uhi]) / 3.0
+    Xe[1::2] = (X[ulo] + 2.0 * X[uhi]) / 3.0
+    # element edge nodes: the one nearer the element's first endpoint first
+    first_is_lo = ends[:, :, 0] == lo
+    near_i = nv + 2 * inv + np.where(first_is_lo, 0, 1)
+    near_j = nv + 2 * inv + np.where(first_is_lo, 1, 0)
+    faces = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]       # opposite corner c
+    fv = np.sort(np.stack([t[:, list(f)] for f in faces], axis=1), axis=2)   # (n, 4, 3)
+    fkey = (fv[:, :, 0] * nv + fv[:, :, 1]) * nv + fv[:, :, 2]
+    funiq, finv = np.unique(fkey.ravel(), return_inverse=True)
+    f0 = funiq // (nv * nv)
+    f1 = (funiq // nv) % nv
+    f2 = funiq % nv
+    Xf = (X[f0] + X[f1] + X[f2]) / 3.0
+    nf0 = nv + 2 * uniq.size
+    conn = np.concatenate([t, np.stack([near_i, near_j], axis=2).reshape(-1, 12),
+                           nf0 + finv.reshape(-1, 4)], axis=1)
+    return np.concatenate([X, Xe, Xf]), conn.astype(np.int32)
+
+
 def cloth_grid(m: int, size: float = 1.0, z0: float = 0.0, origin_xy=(0.0, 0.0)):
     """m*m cells on [0,size]^2 at height z0, two counter-clockwise triangles per cell."""
     jj, ii = np.meshgrid(np.arange(m + 1), np.arange(m + 1), indexing="ij")
@@ -199,6 +240,10 @@ def _bottom_fixed(X: np.ndarray, z_min: float | None = None) -> np.ndarray:
     return (np.abs(z - zmin) <= 1e-12).astype(np.uint8)
 
 
+def _grid_for(kind):
+    return {SNH_TET10: tet10_grid, SNH_TET20: tet20_grid}.get(kind, tet_grid)
+
+
 def tet_cube_scene(n: int, h: float = 0.01, young: float = 1e5, poisson: float = 0.4,
                    density: float = 1000.0, dt: float = 0.01, seed: int = 1,
                    perturb: float = 0.01, vel_std: float = 0.0, name: str | None = None,
@@ -211,7 +256,7 @@ def tet_cube_scene(n: int, h: float = 0.01, young: float = 1e5, poisson: float =
     or SNH_TET10 for quadratic Stable Neo-Hookean tets on the same cubes.
     """
     nx, ny, nz = dims if dims is not None else (n, n, n)
-    X, tets = tet10_grid(nx, ny, nz, h) if kind == SNH_TET10 else tet_grid(nx, ny, nz, h)
+    X, tets = _grid_for(kind)(nx, ny, nz, h)
     fixed = _bottom_fixed(X)
     rng = np.random.default_rng(seed)
     N = X.shape[0]
@@ -234,7 +279,7 @@ def stretched_box_scene(kind: int, dims: tuple = (40, 40, 60), h: float = 0.01,
     interior stretched affinely in z plus +-1% noise (seed).  SNH_TET10
     builds the same box from quadratic tets."""
     nx, ny, nz = dims
-    X, tets = tet10_grid(nx, ny, nz, h) if kind == SNH_TET10 else tet_grid(nx, ny, nz, h)
+    X, tets = _grid_for(kind)(nx, ny, nz, h)
     z = X[:, 2]
     top = z >= z.max() - 1e-12
     fixed = (_bottom_fixed(X).astype(bool) | top).astype(np.uint8)

@@ -535,6 +535,138 @@ def test_tet10_hrz_masses():
     assert np.all(m[e] >= own[e] - 1e-18)
 
 
+# ----------------------------------------------------------------------------
+# Cubic tet (tet20)
+# ----------------------------------------------------------------------------
+_E6 = [(0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3)]
+_F4 = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]
+
+
+def _tet20_nodes(P4):
+    """Straight-sided cubic node positions from corner positions (E,4,3)."""
+    e = []
+    for i, j in _E6:
+        e += [(2 * P4[:, i] + P4[:, j]) / 3, (P4[:, i] + 2 * P4[:, j]) / 3]
+    f = [P4[:, list(fc)].mean(axis=1) for fc in _F4]
+    return np.concatenate([P4, np.stack(e, 1), np.stack(f, 1)], 1)
+
+
+def _tet20_random(n, seed, curved=0.1):
+    x4, X4 = sg.random_tets(n, seed, inverted_frac=0.0)
+    X, x = _tet20_nodes(X4), _tet20_nodes(x4)
+    return x + np.random.default_rng(seed + 1).uniform(-curved, curved, x.shape) * 0.01, X
+
+
+def _tet20_relabel(sigma):
+    """Original node of each position after relabelling the corners by sigma."""
+    perm = list(sigma)
+    for i, j in _E6:
+        a, b = sigma[i], sigma[j]
+        m = next(k for k, e in enumerate(_E6) if set(e) == {a, b})
+        near_a = 4 + 2 * m if _E6[m][0] == a else 5 + 2 * m
+        perm += [near_a, near_a + 1 if near_a == 4 + 2 * m else near_a - 1]
+    perm += [16 + sigma[c] for c in range(4)]
+    return perm
+
+
+def _snh20(x, X, **kw):
+    n = x.shape[0]
+    return elements.snh_tet20(x, X, np.full(n, MU), np.full(n, LAM), **kw)
+
+
+def test_tet20_rule_is_degree_four_and_symmetric():
+    """Every monomial of degree <= 4 integrated exactly (not degree 5), and
+    the point set maps onto itself under every vertex permutation (what the
+    row-wise relabelling of the elements relies on)."""
+    from math import factorial
+    rule = elements.TET20_RULE
+    for p in itertools.product(range(6), repeat=3):
+        q = sum(w * xi[0] ** p[0] * xi[1] ** p[1] * xi[2] ** p[2] for w, xi in rule)
+        exact = factorial(p[0]) * factorial(p[1]) * factorial(p[2]) / factorial(sum(p) + 3)
+        if sum(p) <= 4:
+            assert q == pytest.approx(exact, rel=1e-13)
+        if p == (5, 0, 0):
+            assert abs(q - exact) > 1e-6 * exact
+    bary = [np.concatenate([[1 - xi.sum()], xi]) for _, xi in rule]
+    for sigma in itertools.permutations(range(4)):
+        for (w, _), L in zip(rule, bary):
+            Ls = L[list(sigma)]
+            assert any(abs(w - w2) < 1e-15 and np.allclose(Ls, L2, atol=1e-15)
+                       for (w2, _), L2 in zip(rule, bary))
+
+
+def test_tet20_shape_functions():
+    """Interpolation at the 20 nodes, partition of unity, and derivatives by
+    the complex step of the interpolation written out here."""
+    nodes = _tet20_nodes(np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]]]))[0]
+
+    def N(xi):
+        L = [1 - xi[0] - xi[1] - xi[2], xi[0], xi[1], xi[2]]
+        out = [0.5 * L[c] * (3 * L[c] - 1) * (3 * L[c] - 2) for c in range(4)]
+        for i, j in _E6:
+            out += [4.5 * L[i] * L[j] * (3 * L[i] - 1), 4.5 * L[i] * L[j] * (3 * L[j] - 1)]
+        out += [27 * L[a] * L[b] * L[c] for a, b, c in _F4]
+        return np.array(out)
+    assert np.allclose(np.stack([N(p) for p in nodes]), np.eye(20), atol=1e-14)
+    rng = np.random.default_rng(56)
+    for _ in range(10):
+        xi = rng.dirichlet(np.ones(4))[1:]
+        dN = elements.tet20_shape_derivatives(xi)
+        cs = np.stack([np.imag(N(xi + 1e-30j * np.eye(3)[k])) / 1e-30 for k in range(3)], 1)
+        assert np.allclose(dN, cs, rtol=0, atol=1e-12)
+        assert abs(N(xi).sum() - 1) < 1e-14 and np.allclose(dN.sum(0), 0.0, atol=1e-13)
+
+
+def test_tet20_affine_patch_and_derivatives():
+    _, X = _tet20_random(6, 57)
+    A = np.eye(3)[None] + np.random.default_rng(58).uniform(-0.3, 0.3, (6, 3, 3))
+    xa = np.einsum("eij,eaj->eai", A, X) - 0.2
+    E20, _, _ = _snh20(xa, X, want_hess=False)
+    E4, _, _ = _snh(xa[:, :4], X[:, :4], want_hess=False)
+    assert _rel(E20, E4) < 1e-12
+    x, X = _tet20_random(2, 59)
+    E, g, H = _snh20(x, X)
+    gc = _cs_grad(lambda xc: _snh20(xc, X, want_hess=False)[0], x)
+    Hc = _cs_jac(lambda xc: _snh20(xc, X, want_hess=False)[1], x)
+    assert _rel(g, gc) < 1e-12
+    assert _rel(H, Hc) < 1e-11
+
+
+def test_tet20_relabelling_invariance():
+    x, X = _tet20_random(4, 60)
+    E, g, H = _snh20(x, X)
+    for sigma in [(1, 0, 2, 3), (2, 3, 0, 1), (3, 1, 2, 0), (1, 2, 3, 0)]:
+        perm = _tet20_relabel(sigma)
+        assert sorted(perm) == list(range(20))
+        E2, g2, H2 = _snh20(x[:, perm], X[:, perm])
+        assert np.allclose(E2, E, rtol=1e-12)
+        assert _rel(g2, g[:, perm]) < 1e-11
+        assert _rel(H2, H[:, perm][:, :, :, perm]) < 1e-10
+
+
+def test_tet20_hrz_masses():
+    t, w = np.polynomial.legendre.leggauss(8)
+    t, w = 0.5 * (t + 1.0), 0.5 * w
+    total = np.zeros(20)
+    for u, wu in zip(t, w):
+        for v, wv in zip(t, w):
+            for r, wr in zip(t, w):
+                xi = np.array([u, v * (1 - u), r * (1 - u) * (1 - v)])
+                jac = (1 - u) ** 2 * (1 - v)
+                L = [1 - xi.sum(), *xi]
+                N = [0.5 * L[c] * (3 * L[c] - 1) * (3 * L[c] - 2) for c in range(4)]
+                for i, j in _E6:
+                    N += [4.5 * L[i] * L[j] * (3 * L[i] - 1), 4.5 * L[i] * L[j] * (3 * L[j] - 1)]
+                N += [27 * L[a] * L[b] * L[c] for a, b, c in _F4]
+                total += wu * wv * wr * jac * np.array(N) ** 2
+    frac = total / total.sum()
+    assert np.allclose(frac[:4], 1 / 193, rtol=1e-12)
+    assert np.allclose(frac[4:16], 27 / 772, rtol=1e-12)
+    assert np.allclose(frac[16:], 27 / 193, rtol=1e-12)
+    s = sg.tet_cube_scene(2, h=0.01, kind=sg.SNH_TET20)
+    assert np.sum(rest.lumped_mass(s)) == pytest.approx(1000.0 * 0.02 ** 3, rel=1e-12)
+
+
 def _random_tris(n, seed, stretch=0.2):
     rng = np.random.default_rng(seed)
     base = np.array([[0, 0, 0], [1, 0, 0], [0.2, 0.9, 0]], dtype=np.float64) * 0.01
