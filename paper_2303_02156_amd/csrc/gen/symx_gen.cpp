@@ -24,6 +24,7 @@
 //                                  relabelled into a corner)
 //
 // Usage: symx_gen <output directory>
+#include <algorithm>
 #include <cstdio>
 #include <fstream>
 #include <functional>
@@ -45,6 +46,7 @@ struct EnergySpec {
   int rest_slot;      // first slot of node-0 rest coordinates, or -1
   std::function<S(Graph&, const std::vector<S>&)> energy;
   std::vector<int> row_nodes = {0};  // nodes with row functions (see header)
+  bool full = true;  // emit the full-Hessian variants (too large for the cubic tet)
 };
 
 Mat cols_minus_first(Graph& g, const std::vector<S>& in, int base, int n_nodes) {
@@ -243,6 +245,49 @@ S ipc_point_plane_act(Graph& g, const std::vector<S>& in) {
   return in[13] - point_plane_distance(g, in);
 }
 
+// Jacobian of the cubic tet interpolation (as tet10_jacobian).  Node order:
+// corners 0-3; for edge k = (i, j) of (0,1), (1,2), (2,0), (0,3), (1,3), (2,3)
+// the nodes 4 + 2k (one third from i) and 5 + 2k (one third from j); the
+// centroid of the face opposite corner c is node 16 + c.  Shape functions:
+// L (3L - 1)(3L - 2) / 2 at a corner, 9/2 L_i L_j (3 L_i - 1) at the edge node
+// nearer i, 27 L_i L_j L_k at a face node.
+Mat tet20_jacobian(Graph& g, const std::vector<S>& in, int base, const std::vector<S>& xi) {
+  S L0 = 1.0 - xi[0] - xi[1] - xi[2];
+  std::vector<S> L = {L0, xi[0], xi[1], xi[2]};
+  const int edge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+  std::vector<S> N;
+  for (int c = 0; c < 4; ++c) N.push_back(0.5 * L[c] * (3.0 * L[c] - 1.0) * (3.0 * L[c] - 2.0));
+  for (const auto& e : edge) {
+    N.push_back(4.5 * L[e[0]] * L[e[1]] * (3.0 * L[e[0]] - 1.0));
+    N.push_back(4.5 * L[e[0]] * L[e[1]] * (3.0 * L[e[1]] - 1.0));
+  }
+  for (int c = 0; c < 4; ++c) {
+    S p = 27.0 * L[c == 0 ? 1 : 0];
+    for (int k = (c == 0 ? 2 : 1); k < 4; ++k)
+      if (k != c) p = p * L[k];
+    N.push_back(p);
+  }
+  Mat Jm(3, 3, &g);
+  for (int i = 0; i < 3; ++i) {
+    S p = N[0] * in[base + i];
+    for (int a = 1; a < 20; ++a) p = p + N[a] * in[base + 3 * a + i];
+    for (int k = 0; k < 3; ++k) Jm(i, k) = S(&g, g.diff(p.id, xi[k].id));
+  }
+  return Jm;
+}
+
+// One quadrature point of the cubic Stable Neo-Hookean tet (Eq. 12): inputs
+// x (0..59), X (60..119), mu (120), lambda (121), weight (122), point xi
+// (123..125).
+S snh_tet20_qp(Graph& g, const std::vector<S>& in) {
+  std::vector<S> xi = {in[123], in[124], in[125]};
+  for (const S& v : xi) g.set_dof(v.id);
+  Mat Jx = tet20_jacobian(g, in, 0, xi);
+  Mat JX = tet20_jacobian(g, in, 60, xi);
+  Mat F = matmul(Jx, inv3(JX));
+  return in[122] * abs(det3(JX)) * snh_density(F, in[120], in[121]);
+}
+
 // Quadratic bending (Eq. 13, Bergou et al. 2006): E = k_b/2 x^T Q x with the
 // constant Q = c (K K^T) (x) I3; inputs are the per-node weights K_a and the
 // scale c = 3/(A0 + A1), precomputed from the rest hinge.
@@ -280,9 +325,15 @@ void generate(const EnergySpec& spec, Generated& out) {
   S E = spec.energy(g, in);
   std::vector<int> grad(n_dof);
   for (int k = 0; k < n_dof; ++k) grad[k] = g.diff(E.id, in[k].id);
-  std::vector<int> hess(n_dof * n_dof);
+  // the Hessian rows the variants use: all of them, or those of the row nodes
+  std::vector<int> hess(n_dof * n_dof, -1);
+  std::vector<char> need(n_dof, spec.full ? 1 : 0);
+  for (int r : spec.row_nodes)
+    for (int i = 0; i < 3; ++i) need[3 * r + i] = 1;
   for (int k = 0; k < n_dof; ++k)
-    for (int l = k; l < n_dof; ++l) hess[k * n_dof + l] = hess[l * n_dof + k] = g.diff(grad[k], in[l].id);
+    for (int l = 0; l < n_dof; ++l)
+      if ((need[k] || need[l]) && hess[k * n_dof + l] < 0)
+        hess[k * n_dof + l] = hess[l * n_dof + k] = g.diff(grad[std::min(k, l)], in[std::max(k, l)].id);
 
   std::vector<Function> fns;
   auto add_fn = [&](const std::string& suffix, std::vector<int> outs) {
@@ -295,10 +346,12 @@ void generate(const EnergySpec& spec, Generated& out) {
   std::vector<int> Eg = {E.id};
   Eg.insert(Eg.end(), grad.begin(), grad.end());
   std::vector<int> EgH = Eg;
-  EgH.insert(EgH.end(), hess.begin(), hess.end());
+  if (spec.full) EgH.insert(EgH.end(), hess.begin(), hess.end());
   add_fn("_E", {E.id});
-  add_fn("_Eg", Eg);
-  add_fn("_EgH", EgH);
+  if (spec.full) {
+    add_fn("_Eg", Eg);
+    add_fn("_EgH", EgH);
+  }
 
   // node 0 at the origin
   std::map<int, double> zero;
@@ -307,7 +360,7 @@ void generate(const EnergySpec& spec, Generated& out) {
     if (spec.rest_slot >= 0) zero[spec.rest_slot + i] = 0.0;
   }
   add_fn("_s_E", g.substitute({E.id}, zero));
-  add_fn("_s_EgH", g.substitute(EgH, zero));
+  if (spec.full) add_fn("_s_EgH", g.substitute(EgH, zero));
   for (int r : spec.row_nodes) {
     const std::string R = "_row" + std::to_string(r);
     std::vector<int> row_g(grad.begin() + 3 * r, grad.begin() + 3 * r + 3);
@@ -368,6 +421,7 @@ int main(int argc, char** argv) {
       {"fcr_tet4", 4, 35, 12, fcr_tet4},
       {"arap_tet4", 4, 35, 12, arap_tet4},
       {"snh_tet10", 10, 66, 30, snh_tet10_qp, {0, 4}},
+      {"snh_tet20", 20, 126, 60, snh_tet20_qp, {0, 4, 19}, false},
       {"ipc_point_plane", 4, 14, -1, ipc_point_plane},
       {"ipc_point_plane_act", 4, 14, -1, ipc_point_plane_act},
   };

@@ -331,3 +331,65 @@ def test_contact_barrier_generated_vs_oracle(lib):
     assert _rel(_call(lib, "ipc_point_plane_s_EgH", rel_in, 157), out) < 1e-9
     a = _call(lib, "ipc_point_plane_act_s_E", rel_in, 1)[:, 0]
     assert _rel(a, contact.activation(x, dh)) < 1e-10
+
+
+def _tet20_perm(a):
+    """Node order putting local node a at position 0 (corner), 4 (edge node:
+    its edge's nearer corner first) or 19 (face node: the opposite corner
+    last)."""
+    E6 = [(0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3)]
+    if a < 4:
+        sigma = [a] + [c for c in range(4) if c != a]
+    elif a < 16:
+        i, j = E6[(a - 4) // 2]
+        u, v = (i, j) if (a - 4) % 2 == 0 else (j, i)
+        sigma = [u, v] + [c for c in range(4) if c not in (u, v)]
+    else:
+        c0 = a - 16
+        sigma = [c for c in range(4) if c != c0] + [c0]
+    perm = list(sigma)
+    for i, j in E6:
+        s, t = sigma[i], sigma[j]
+        m = next(k for k, e in enumerate(E6) if set(e) == {s, t})
+        near_s = 4 + 2 * m if E6[m][0] == s else 5 + 2 * m
+        perm += [near_s, near_s + 1 if near_s == 4 + 2 * m else near_s - 1]
+    perm += [16 + sigma[c] for c in range(4)]
+    return perm
+
+
+def test_tet20_generated_vs_oracle(lib):
+    """Cubic tets: the per-point energy summed over the rule, and every node's
+    row from the corner (0), edge (4) or face (19) row function of the
+    relabelled element, against the oracle."""
+    x4, X4 = sg.random_tets(6, 121, inverted_frac=0.0)
+    E6 = [(0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3)]
+    F4 = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]
+
+    def nodes(P):
+        e = []
+        for i, j in E6:
+            e += [(2 * P[:, i] + P[:, j]) / 3, (P[:, i] + 2 * P[:, j]) / 3]
+        return np.concatenate([P, np.stack(e, 1), np.stack([P[:, list(f)].mean(1) for f in F4], 1)], 1)
+    X = nodes(X4)
+    x = nodes(x4) + np.random.default_rng(122).uniform(-1e-3, 1e-3, (6, 20, 3))
+    n = 6
+    mu, lam = np.full(n, MU), np.full(n, LAM)
+    E, g, H = elements.snh_tet20(x, X, mu, lam)
+
+    def inputs(xx, XX, w, xi):
+        return np.concatenate([xx.reshape(n, 60), XX.reshape(n, 60), mu[:, None], lam[:, None],
+                               np.full((n, 1), w), np.broadcast_to(xi, (n, 3))], axis=1)
+
+    def summed(name, xx, XX, n_out):
+        return sum(_call(lib, name, inputs(xx, XX, w, xi), n_out) for w, xi in elements.TET20_RULE)
+    Es = summed("snh_tet20_s_E", x - x[:, :1], X - X[:, :1], 1)[:, 0]
+    assert _rel(Es, E) < 1e-10
+    for a in range(20):
+        perm = _tet20_perm(a)
+        r = 0 if a < 4 else 4 if a < 16 else 19
+        assert perm[r] == a and sorted(perm) == list(range(20))
+        xs, Xs = x[:, perm] - x[:, perm[:1]], X[:, perm] - X[:, perm[:1]]
+        row = summed(f"snh_tet20_row{r}_gHoff", xs, Xs, 174)
+        others = [perm[b] for b in range(20) if b != r]
+        assert _rel(row[:, :3], g[:, a]) < 1e-9
+        assert _rel(row[:, 3:].reshape(n, 3, 19, 3), H[:, a][:, :, others, :]) < 1e-9
