@@ -61,8 +61,12 @@ typedef enum {
 
 /* Element energies (the paper's App. B and Eq. 13).  Linear tets use
  * E = V psi(F) with F = Ds Dm^-1 and Lame parameters from (young, poisson).
- * The quadratic tet integrates psi over the element (Eq. 12) with a symmetric
- * 4-point rule of degree 2: E = sum_q w_q |det J_X(xi_q)| psi(J_x J_X^-1). */
+ * Quadratic and cubic tets integrate psi over the element (Eq. 12),
+ * E = sum_q w_q |det J_X(xi_q)| psi(J_x J_X^-1), with a symmetric rule: 4
+ * points of degree 2 (Hammer, Marlowe and Stroud) for the quadratic tet, 11
+ * points of degree 4 (Keast) for the cubic tet.  Their lumped masses follow
+ * HRZ lumping (diagonal of the consistent mass scaled to the element mass).
+ * Element ids per set are below 2^25. */
 typedef enum {
   SYMX_SNH_TET4 = 0,   /* Stable Neo-Hookean, linear tet, 4 nodes                */
   SYMX_STVK_TRI3 = 1,  /* St. Venant-Kirchhoff membrane triangle, 3 nodes        */
@@ -71,10 +75,16 @@ typedef enum {
   SYMX_STVK_TET4 = 4,  /* St. Venant-Kirchhoff tet                               */
   SYMX_FCR_TET4 = 5,   /* fixed co-rotational, rotation R lagged per time step   */
   SYMX_ARAP_TET4 = 6,  /* as-rigid-as-possible + volume term, R lagged           */
-  SYMX_SNH_TET10 = 7   /* Stable Neo-Hookean, quadratic tet, 10 nodes: corners
+  SYMX_SNH_TET10 = 7,  /* Stable Neo-Hookean, quadratic tet, 10 nodes: corners
                           0-3, then the mid-edge nodes of edges (0,1), (1,2),
-                          (2,0), (0,3), (1,3), (2,3) (App. A).  A mesh holding
-                          such a set holds no other kind; no PSD projection. */
+                          (2,0), (0,3), (1,3), (2,3) (App. A).               */
+  SYMX_SNH_TET20 = 8   /* Stable Neo-Hookean, cubic tet, 20 nodes: corners 0-3;
+                          on edge k = (i, j) of the list above, node 4 + 2k a
+                          third of the way from i and node 5 + 2k a third of
+                          the way from j; node 16 + c at the centroid of the
+                          face opposite corner c (App. A).
+                          A mesh holding a quadratic or cubic set holds no
+                          other set; no PSD projection, no contacts.         */
 } symx_energy_kind;
 
 /* Evaluation flags (the three levels of Sec. 5.2, plus options). */
@@ -99,7 +109,8 @@ typedef struct {
   int32_t kind;            /* symx_energy_kind                                 */
   int64_t n_elem;          /* number of elements, >= 0                         */
   const int32_t* conn;     /* host, n_elem x k node ids in [0, N): k = 3 for the
-                              triangle, 10 for the quadratic tet, else 4       */
+                              triangle, 10 for the quadratic tet, 20 for the
+                              cubic tet, else 4                                */
   const double* young;     /* host, per-element Young's modulus, or NULL       */
   double young_const;      /* Young's modulus when young == NULL               */
   double poisson;          /* Poisson ratio (tets, triangles)                  */
@@ -186,8 +197,9 @@ symx_status symx_mesh_get_pattern(symx_mesh mesh, int32_t* row_ptr, int32_t* col
 
 /* Lumped node masses (host, N doubles): rho V / 4 per linear tet, rho h A / 3
  * per triangle (the inertia term of Eq. 2); a quadratic tet gives rho V / 36
- * to each corner and 4 rho V / 27 to each edge node (HRZ lumping, V of the
- * straight-sided element). */
+ * to each corner and 4 rho V / 27 to each edge node, a cubic tet rho V / 193
+ * to each corner, 27 rho V / 772 to each edge node and 27 rho V / 193 to each
+ * face node (HRZ lumping, V of the straight-sided element). */
 symx_status symx_mesh_get_masses(symx_mesh mesh, double* mass_host);
 
 /* Per-element evaluation of one energy set (the low-level element interface
@@ -251,7 +263,7 @@ symx_status symx_mesh_update_rotations(symx_mesh mesh, const double* x_dev);
  * assembly, energies, the PCG and the Newton step include it.  With
  * projection on, contact element Hessians take the nearest-PSD projection.
  * Node ids in range and distinct within a tuple; k_c, d_hat > 0; not on
- * meshes of quadratic tets. */
+ * meshes of quadratic or cubic tets. */
 symx_status symx_mesh_set_contacts(symx_mesh mesh, int64_t n, const int32_t* tuples_host,
                                    double k_c, double d_hat);
 /* View of the contact matrix of the last assembly (device pointers, the

@@ -207,8 +207,8 @@ symx_status symx_eval_derivatives(symx_mesh mesh, int32_t energy_index, const do
     set_error("SYMX_PROJECT_PSD and SYMX_PROJECT_FILTER need SYMX_EVAL_HESS and a Hessian buffer");
     return SYMX_ERR_INVALID_ARG;
   }
-  if (proj && m.sets[energy_index].k == 10) {
-    set_error("per-element PSD projection is not available for quadratic tets");
+  if (proj && m.sets[energy_index].k >= 10) {
+    set_error("per-element PSD projection is not available for quadratic or cubic tets");
     return SYMX_ERR_INVALID_ARG;
   }
   if (filter && m.sets[energy_index].kind == SYMX_SNH_TET4) {

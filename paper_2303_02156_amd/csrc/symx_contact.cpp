@@ -55,8 +55,8 @@ symx_status contacts_set(Mesh& m, int64_t n, const int32_t* tuples, double kc, d
     set_error("invalid contact list or barrier parameters");
     return SYMX_ERR_INVALID_ARG;
   }
-  if (m.quad) {
-    set_error("contacts are not available on meshes of quadratic tets");
+  if (m.ho) {
+    set_error("contacts are not available on meshes of quadratic or cubic tets");
     return SYMX_ERR_INVALID_ARG;
   }
   for (int64_t c = 0; c < n; ++c)

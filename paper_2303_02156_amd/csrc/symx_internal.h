@@ -26,7 +26,20 @@ constexpr uint32_t kNoSlot = 0xFFu;
 constexpr int kPcgHistory = 64;    // remembered PCG iteration counts
 constexpr int kIncRec = 32;        // values per incidence record (projected path)
 constexpr int kQuadInc = 64;       // incidences per row batch of a quadratic-tet mesh
-constexpr int kMaxElemBits = 26;   // element ids per set < 2^26
+constexpr int kCubicInc = 32;      // incidences per row batch of a cubic-tet mesh
+constexpr int kMaxElemBits = 25;   // element ids per set < 2^25
+
+// Nodes per element of an energy kind.
+__host__ __device__ constexpr int kind_nodes(int kind) {
+  return kind == SYMX_STVK_TRI3  ? 3
+         : kind == SYMX_SNH_TET10 ? 10
+         : kind == SYMX_SNH_TET20 ? 20
+                                  : 4;
+}
+// Higher-order tets (10 or 20 nodes), 0 for any other kind.
+__host__ __device__ constexpr int kind_high_order(int kind) {
+  return kind == SYMX_SNH_TET10 ? 10 : kind == SYMX_SNH_TET20 ? 20 : 0;
+}
 
 // Parameter layout per element (kPrm doubles):
 //   SNH tet4:  mu, lambda (linear-elasticity Lame pair)
@@ -42,50 +55,87 @@ struct SetDev {
   int prm_stride;        // kPrm, or 0 when every element has the same parameters
   const double* rot64;   // lagged-rotation materials: n_elem x 9 (row-major R), else null
   const float* rot32;
-  const int* conn10;     // quadratic tets: n_elem x 10 node ids (conn is null)
+  const int* conn_ho;    // higher-order tets: n_elem x k node ids (conn is null)
 };
 
-// Quadratic tet node order (App. A): corners 0-3, then the mid-edge nodes of
-// edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3).  The element's energy is
-// unchanged when the corners are relabelled and the edge nodes follow their
-// edges (the quadrature rule is symmetric), so node a's Hessian row comes from
-// the row function of node 0 (a corner: a moved to corner 0) or node 4 (an
-// edge node of edge (i, j): i, j moved to corners 0, 1).  kTet10Perm[a][b] is
-// the original local node at position b of that relabelled order.
-constexpr int kTet10Edge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
-struct Tet10Perm {
-  int8_t p[10][10];
+// Higher-order tet node orders (App. A).  Corners 0-3; edges k = (0,1),
+// (1,2), (2,0), (0,3), (1,3), (2,3).  Quadratic tets (10 nodes): node 4 + k
+// at the middle of edge k.  Cubic tets (20 nodes): nodes 4 + 2k and 5 + 2k on
+// edge k = (i, j), a third of the way from i and from j; node 16 + c at the
+// centroid of the face opposite corner c.  The element energy is unchanged
+// when the corners are permuted and the other nodes follow their edges and
+// faces (both quadrature rules are symmetric), so the Hessian row of any node
+// comes from the row function of one node per class: node 0 (a corner, moved
+// to corner 0), node 4 (an edge node: its edge moved to (0, 1) with its own
+// end at 0) or node 19 (a cubic face node: the opposite corner moved to 3).
+// HoPerm<K>::p[a][b] is the original local node at position b of node a's
+// relabelled order.
+constexpr int kTetEdge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+template <int K>
+struct HoPerm {
+  int8_t p[K][K];
 };
-constexpr Tet10Perm make_tet10_perm() {
-  Tet10Perm t{};
-  for (int a = 0; a < 10; ++a) {
-    int sig[4] = {0, 0, 0, 0};
+// position of node a in its relabelled order (the row function it uses)
+__host__ __device__ constexpr int ho_row_pos(int K, int a) {
+  return a < 4 ? 0 : (K == 20 && a >= 16) ? 19 : 4;
+}
+template <int K>
+constexpr HoPerm<K> make_ho_perm() {
+  HoPerm<K> t{};
+  for (int a = 0; a < K; ++a) {
+    int sig[4] = {0, 0, 0, 0};  // new corner c is original corner sig[c]
     int n = 0;
+    const int last = (K == 20 && a >= 16) ? a - 16 : -1;
     if (a < 4) {
       sig[n++] = a;
-    } else {
-      sig[n++] = kTet10Edge[a - 4][0];
-      sig[n++] = kTet10Edge[a - 4][1];
+    } else if (last < 0) {
+      const int k = K == 10 ? a - 4 : (a - 4) / 2;
+      const int own = K == 10 ? 0 : (a - 4) % 2;  // the end the node is nearer
+      sig[n++] = kTetEdge[k][own];
+      sig[n++] = kTetEdge[k][1 - own];
     }
     for (int c = 0; c < 4; ++c) {
-      bool used = false;
+      bool used = c == last;
       for (int u = 0; u < n; ++u) used = used || sig[u] == c;
       if (!used) sig[n++] = c;
     }
+    if (last >= 0) sig[n++] = last;
     for (int c = 0; c < 4; ++c) t.p[a][c] = int8_t(sig[c]);
     for (int k = 0; k < 6; ++k) {
-      const int u = sig[kTet10Edge[k][0]], v = sig[kTet10Edge[k][1]];
-      for (int m = 0; m < 6; ++m)
-        if ((kTet10Edge[m][0] == u && kTet10Edge[m][1] == v) ||
-            (kTet10Edge[m][0] == v && kTet10Edge[m][1] == u))
+      const int u = sig[kTetEdge[k][0]], v = sig[kTetEdge[k][1]];
+      for (int m = 0; m < 6; ++m) {
+        const bool same = kTetEdge[m][0] == u && kTetEdge[m][1] == v;
+        const bool flipped = kTetEdge[m][0] == v && kTetEdge[m][1] == u;
+        if (!same && !flipped) continue;
+        if (K == 10) {
           t.p[a][4 + k] = int8_t(4 + m);
+        } else {
+          t.p[a][4 + 2 * k] = int8_t(same ? 4 + 2 * m : 5 + 2 * m);
+          t.p[a][5 + 2 * k] = int8_t(same ? 5 + 2 * m : 4 + 2 * m);
+        }
+      }
     }
+    if (K == 20)
+      for (int c = 0; c < 4; ++c) t.p[a][16 + c] = int8_t(16 + sig[c]);
   }
   return t;
 }
-constexpr Tet10Perm kTet10Perm = make_tet10_perm();
-// position of node a in its relabelled order: 0 for corners, 4 for edge nodes
-__host__ __device__ constexpr int tet10_row_pos(int a) { return a < 4 ? 0 : 4; }
+template <int K>
+constexpr bool ho_perm_valid(const HoPerm<K>& t) {
+  for (int a = 0; a < K; ++a) {
+    if (t.p[a][ho_row_pos(K, a)] != a) return false;
+    int seen[K] = {};
+    for (int b = 0; b < K; ++b) {
+      if (t.p[a][b] < 0 || t.p[a][b] >= K || seen[t.p[a][b]]) return false;
+      seen[t.p[a][b]] = 1;
+    }
+  }
+  return true;
+}
+constexpr HoPerm<10> kTet10Perm = make_ho_perm<10>();
+constexpr HoPerm<20> kTet20Perm = make_ho_perm<20>();
+static_assert(ho_perm_valid(kTet10Perm) && ho_perm_valid(kTet20Perm),
+              "relabelled node orders must be permutations that put node a at its row position");
 
 // Fixed co-rotational and ARAP tets carry a lagged rotation per element.
 inline bool kind_has_rotation(int kind) {
@@ -97,13 +147,13 @@ struct SetsDev {
   int n;
 };
 
-// Incidence code: element id (bits 0-25), local node a (26-29), set (30-31).
+// Incidence code: element id (bits 0-24), local node a (25-29), set (30-31).
 __host__ __device__ inline uint32_t inc_make(int set, int a, int64_t e) {
-  return (uint32_t(set) << 30) | (uint32_t(a) << 26) | uint32_t(e);
+  return (uint32_t(set) << 30) | (uint32_t(a) << 25) | uint32_t(e);
 }
 __host__ __device__ inline int inc_set(uint32_t c) { return int(c >> 30); }
-__host__ __device__ inline int inc_local(uint32_t c) { return int((c >> 26) & 15u); }
-__host__ __device__ inline int inc_elem(uint32_t c) { return int(c & 0x03FFFFFFu); }
+__host__ __device__ inline int inc_local(uint32_t c) { return int((c >> 25) & 31u); }
+__host__ __device__ inline int inc_elem(uint32_t c) { return int(c & 0x01FFFFFFu); }
 
 template <typename T>
 struct DevBuf {
@@ -193,7 +243,7 @@ struct TopoSet {
   int64_t n_elem = 0;
   std::vector<int32_t> conn;        // n_elem * k
   int4* d_conn = nullptr;           // n_elem (unused components = -1); k <= 4
-  int* d_conn10 = nullptr;          // n_elem * 10; quadratic tets
+  int* d_conn_ho = nullptr;         // n_elem * k; higher-order tets
 };
 
 struct Topology {
@@ -202,9 +252,10 @@ struct Topology {
   size_t device_bytes = 0;
   int64_t N = 0, n_inc = 0, nnzb = 0;
   int n_batch = 0, max_row_blocks = 0;
-  // quadratic-tet topology: batches of at most kQuadInc incidences, nine
-  // contribution entries per incidence (u16 = incidence << 4 | other node j)
-  bool quad = false;
+  // higher-order tets (k = 10 or 20 nodes, else 0): batches of at most
+  // kQuadInc or kCubicInc incidences, k - 1 contribution entries per incidence
+  // (u16 = incidence << 4 | other node j, or incidence << 5 | j when k = 20)
+  int ho = 0;
   std::vector<TopoSet> sets;
   std::vector<int32_t> h_row_ptr;
   uvector<int32_t> h_col_idx;
@@ -218,7 +269,7 @@ struct Topology {
   int* batch_row = nullptr;         // n_batch+1
   uint32_t* blk_info = nullptr;     // nnzb: off-diagonal contribution list (start << 8 | count)
   uint16_t* centry = nullptr;       // contribution entries (incidence << 2 | node b),
-                                    // or incidence << 4 | j for a quadratic topology
+                                    // or incidence << 4 (5) | j for higher-order tets
   int* batch_entry = nullptr;       // n_batch+1: first entry of each batch
   ~Topology();
   bool matches(const symx_mesh_desc& d) const;  // same N, kinds and connectivity
@@ -252,7 +303,7 @@ struct SetHost {
   bool uniform = true;
   // device
   const int4* d_conn = nullptr;     // the topology's
-  const int* d_conn10 = nullptr;
+  const int* d_conn_ho = nullptr;
   double* d_prm64 = nullptr;
   float* d_prm32 = nullptr;
   double* d_rot64 = nullptr;        // lagged rotations (FCR / ARAP sets)
@@ -325,7 +376,7 @@ struct Mesh {
   int64_t n_inc = 0;
   int n_batch = 0;
   int max_row_blocks = 0;
-  bool quad = false;                // quadratic tets (the topology's flag)
+  int ho = 0;                       // higher-order tets: 10 or 20 nodes (the topology's)
   double total_mass = 0.0;
   std::vector<SetHost> sets;
   std::vector<double> h_X, h_mass;

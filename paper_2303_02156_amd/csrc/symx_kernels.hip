@@ -1381,83 +1381,175 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
 // [valu-hash-end row_assemble]
 
 // ---------------------------------------------------------------------------
-// quadratic tets (Eq. 12): the element energy is a sum over quadrature points
-// of one generated function, called with each point's weight and reference
-// coordinates (Sec. 5.2, fixed value summation)
+// higher-order tets (Eq. 12): the element energy is a sum over quadrature
+// points of one generated function, called with each point's weight and
+// reference coordinates (Sec. 5.2, fixed value summation)
 // ---------------------------------------------------------------------------
-// Symmetric 4-point rule of degree 2 on the reference tet (Hammer, Marlowe and
-// Stroud 1956): point q has barycentric coordinate a at corner q and b at the
-// others, a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20, weight 1/24; xi =
-// (L1, L2, L3).
+// Quadratic tets: the symmetric 4-point rule of degree 2 (Hammer, Marlowe and
+// Stroud 1956); point q has barycentric coordinate a at corner q and b at the
+// others, a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20, weight 1/24.
+// Cubic tets: Keast's symmetric 11-point rule of degree 4: the centroid with
+// weight -74/5625; four points with 11/14 at one corner and 1/14 at the
+// others, weight 343/45000; six points with c at two corners and d at the
+// other two, c, d = (1 +- sqrt(5/14))/4, weight 56/2250.  The weights of both
+// rules sum to the reference volume 1/6; xi = (L1, L2, L3).
 constexpr double kSqrt5 = 2.2360679774997896964;
 constexpr double kQuadA = (5.0 + 3.0 * kSqrt5) / 20.0;
 constexpr double kQuadB = (5.0 - kSqrt5) / 20.0;
-constexpr int kQuadPts = 4;
+constexpr double kSqrt5over14 = 0.59761430466719681998;
+constexpr double kKeastC = (1.0 + kSqrt5over14) / 4.0;
+constexpr double kKeastD = (1.0 - kSqrt5over14) / 4.0;
 
-__constant__ Tet10Perm c_tet10_perm = make_tet10_perm();
-
-template <typename T>
-__device__ __forceinline__ void set_quad_point(int q, T* in) {
-  in[62] = T(1.0 / 24.0);
-  in[63] = T(q == 1 ? kQuadA : kQuadB);
-  in[64] = T(q == 2 ? kQuadA : kQuadB);
-  in[65] = T(q == 3 ? kQuadA : kQuadB);
+struct QuadRule {
+  double w[11];
+  double xi[11][3];
+};
+constexpr QuadRule make_rule(int K) {
+  QuadRule r{};
+  auto put = [&r](int q, double w, const double L[4]) {
+    r.w[q] = w;
+    for (int k = 0; k < 3; ++k) r.xi[q][k] = L[k + 1];
+  };
+  if (K == 10) {
+    for (int q = 0; q < 4; ++q) {
+      double L[4] = {kQuadB, kQuadB, kQuadB, kQuadB};
+      L[q] = kQuadA;
+      put(q, 1.0 / 24.0, L);
+    }
+    return r;
+  }
+  const double Lc[4] = {0.25, 0.25, 0.25, 0.25};
+  put(0, -74.0 / 5625.0, Lc);
+  for (int i = 0; i < 4; ++i) {
+    double L[4] = {1.0 / 14.0, 1.0 / 14.0, 1.0 / 14.0, 1.0 / 14.0};
+    L[i] = 11.0 / 14.0;
+    put(1 + i, 343.0 / 45000.0, L);
+  }
+  int q = 5;
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j) {
+      double L[4] = {kKeastD, kKeastD, kKeastD, kKeastD};
+      L[i] = L[j] = kKeastC;
+      put(q++, 56.0 / 2250.0, L);
+    }
+  return r;
 }
 
-// Inputs 0..61 of the per-point function for element e with its nodes in the
-// order perm (local indices): positions and rest positions relative to the
-// first node (a corner), then mu and lambda.
-template <typename T>
-__device__ __forceinline__ void fill_tet10(const SetDev& S, int64_t e, const int8_t* perm,
-                                           const double* __restrict__ x,
-                                           const double* __restrict__ X, T* in) {
-  const int* c = S.conn10 + 10 * e;
+__constant__ HoPerm<10> c_perm10 = make_ho_perm<10>();
+__constant__ HoPerm<20> c_perm20 = make_ho_perm<20>();
+__constant__ QuadRule c_rule10 = make_rule(10);
+__constant__ QuadRule c_rule20 = make_rule(20);
+
+// Per-order data: quadrature points, incidences per row batch, the shift of
+// the incidence in a contribution entry, and the generated functions (one
+// row function per node class: corner, edge node, face node).
+template <int K>
+struct HoTet;
+template <>
+struct HoTet<10> {
+  static constexpr int kPts = 4, kCap = kQuadInc, kShift = 4;
+  __device__ static const int8_t* perm(int a) { return c_perm10.p[a]; }
+  __device__ static const QuadRule& rule() { return c_rule10; }
+  template <typename T>
+  __device__ static void energy(const T* in, T* out) { snh_tet10_s_E<T>(in, out); }
+  template <typename T, bool H>
+  __device__ static void row(int a, const T* in, T* out) {
+    if (H) {
+      if (a < 4) snh_tet10_row0_gHoff<T>(in, out);
+      else snh_tet10_row4_gHoff<T>(in, out);
+    } else {
+      if (a < 4) snh_tet10_row0_g<T>(in, out);
+      else snh_tet10_row4_g<T>(in, out);
+    }
+  }
+};
+template <>
+struct HoTet<20> {
+  static constexpr int kPts = 11, kCap = kCubicInc, kShift = 5;
+  __device__ static const int8_t* perm(int a) { return c_perm20.p[a]; }
+  __device__ static const QuadRule& rule() { return c_rule20; }
+  template <typename T>
+  __device__ static void energy(const T* in, T* out) { snh_tet20_s_E<T>(in, out); }
+  template <typename T, bool H>
+  __device__ static void row(int a, const T* in, T* out) {
+    if (H) {
+      if (a < 4) snh_tet20_row0_gHoff<T>(in, out);
+      else if (a < 16) snh_tet20_row4_gHoff<T>(in, out);
+      else snh_tet20_row19_gHoff<T>(in, out);
+    } else {
+      if (a < 4) snh_tet20_row0_g<T>(in, out);
+      else if (a < 16) snh_tet20_row4_g<T>(in, out);
+      else snh_tet20_row19_g<T>(in, out);
+    }
+  }
+};
+
+// Inputs 0..6K+1 of the per-point function for element e with its nodes in
+// the order perm (local indices): positions and rest positions relative to
+// the first node (a corner), then mu and lambda.
+template <int K, typename T>
+__device__ __forceinline__ void fill_ho(const SetDev& S, int64_t e, const int8_t* perm,
+                                        const double* __restrict__ x,
+                                        const double* __restrict__ X, T* in) {
+  const int* c = S.conn_ho + (int64_t)K * e;
   const int n0 = c[perm[0]];
   const double x0 = x[3 * (int64_t)n0], x1 = x[3 * (int64_t)n0 + 1], x2 = x[3 * (int64_t)n0 + 2];
   const double X0 = X[3 * (int64_t)n0], X1 = X[3 * (int64_t)n0 + 1], X2 = X[3 * (int64_t)n0 + 2];
   in[0] = in[1] = in[2] = T(0);
-  in[30] = in[31] = in[32] = T(0);
+  in[3 * K] = in[3 * K + 1] = in[3 * K + 2] = T(0);
 #pragma unroll
-  for (int b = 1; b < 10; ++b) {
+  for (int b = 1; b < K; ++b) {
     const int64_t n = c[perm[b]];
     in[3 * b + 0] = T(x[3 * n + 0] - x0);
     in[3 * b + 1] = T(x[3 * n + 1] - x1);
     in[3 * b + 2] = T(x[3 * n + 2] - x2);
-    in[30 + 3 * b + 0] = T(X[3 * n + 0] - X0);
-    in[30 + 3 * b + 1] = T(X[3 * n + 1] - X1);
-    in[30 + 3 * b + 2] = T(X[3 * n + 2] - X2);
+    in[3 * K + 3 * b + 0] = T(X[3 * n + 0] - X0);
+    in[3 * K + 3 * b + 1] = T(X[3 * n + 1] - X1);
+    in[3 * K + 3 * b + 2] = T(X[3 * n + 2] - X2);
   }
   const T* P = prm_ptr<T>(S);
-  in[60] = ld_prm(P, S.prm_stride, e, 0);
-  in[61] = ld_prm(P, S.prm_stride, e, 1);
+  in[6 * K] = ld_prm(P, S.prm_stride, e, 0);
+  in[6 * K + 1] = ld_prm(P, S.prm_stride, e, 1);
 }
 
-__device__ __forceinline__ const int8_t* identity10() {
+// Inputs 6K+2..6K+5: weight and reference coordinates of quadrature point q.
+template <int K, typename T>
+__device__ __forceinline__ void set_point(int q, T* in) {
+  const QuadRule& r = HoTet<K>::rule();
+  in[6 * K + 2] = T(r.w[q]);
+  in[6 * K + 3] = T(r.xi[q][0]);
+  in[6 * K + 4] = T(r.xi[q][1]);
+  in[6 * K + 5] = T(r.xi[q][2]);
+}
+
+// Energy of element e: its points summed in order (float64).
+template <int K, typename T>
+__device__ __forceinline__ double ho_energy(const SetDev& S, int64_t e, const double* x,
+                                            const double* X) {
+  T in[6 * K + 6];
   // the relabelling of corner 0 leaves every node in place
-  return c_tet10_perm.p[0];
+  fill_ho<K, T>(S, e, HoTet<K>::perm(0), x, X, in);
+  double Ee = 0.0;
+  for (int q = 0; q < HoTet<K>::kPts; ++q) {
+    T out[1];
+    set_point<K, T>(q, in);
+    HoTet<K>::template energy<T>(in, out);
+    Ee += double(out[0]);
+  }
+  return Ee;
 }
 
-// Element energies of a quadratic-tet set -> one partial sum per workgroup.
-template <typename T>
-__global__ __launch_bounds__(256) void k_energy_t10(SetDev S, const double* __restrict__ x,
-                                                   const double* __restrict__ X,
-                                                   double* __restrict__ partials,
-                                                   int* __restrict__ nonfinite) {
+// Element energies of a higher-order tet set -> one partial sum per workgroup.
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_energy_ho(SetDev S, const double* __restrict__ x,
+                                                  const double* __restrict__ X,
+                                                  double* __restrict__ partials,
+                                                  int* __restrict__ nonfinite) {
   __shared__ double sh[256];
   double acc = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < S.n_elem;
-       e += (int64_t)gridDim.x * 256) {
-    T in[66];
-    fill_tet10<T>(S, e, identity10(), x, X, in);
-    double Ee = 0.0;
-    for (int q = 0; q < kQuadPts; ++q) {
-      T out[1];
-      set_quad_point<T>(q, in);
-      snh_tet10_s_E<T>(in, out);
-      Ee += double(out[0]);
-    }
-    acc += Ee;
-  }
+       e += (int64_t)gridDim.x * 256)
+    acc += ho_energy<K, T>(S, e, x, X);
   double s = block_sum_256(acc, sh);
   if (threadIdx.x == 0) {
     partials[blockIdx.x] = s;
@@ -1465,103 +1557,89 @@ __global__ __launch_bounds__(256) void k_energy_t10(SetDev S, const double* __re
   }
 }
 
-// Row of local node a of element e summed over the quadrature points: out[0..2]
-// gradient, out[3 + 27 i + 3 j + k] the off-diagonal block entries of the nine
+// Row of local node a of element e at quadrature point q: out[0..2] gradient,
+// out[3 + 3(K-1) i + 3 j + k] the off-diagonal block entries of the K - 1
 // other nodes in the row function's order (WANT_H), or the gradient only.
-template <typename T, bool WANT_H>
-__device__ __forceinline__ void tet10_row_point(const SetDev& S, int64_t e, int a, int q,
-                                                const double* x, const double* X, T* out) {
-  T in[66];
-  fill_tet10<T>(S, e, c_tet10_perm.p[a], x, X, in);
-  set_quad_point<T>(q, in);
-  if (WANT_H) {
-    if (a < 4)
-      snh_tet10_row0_gHoff<T>(in, out);
-    else
-      snh_tet10_row4_gHoff<T>(in, out);
-  } else {
-    if (a < 4)
-      snh_tet10_row0_g<T>(in, out);
-    else
-      snh_tet10_row4_g<T>(in, out);
-  }
+template <int K, typename T, bool WANT_H>
+__device__ __forceinline__ void ho_row_point(const SetDev& S, int64_t e, int a, int q,
+                                             const double* x, const double* X, T* out) {
+  T in[6 * K + 6];
+  fill_ho<K, T>(S, e, HoTet<K>::perm(a), x, X, in);
+  set_point<K, T>(q, in);
+  HoTet<K>::template row<T, WANT_H>(a, in, out);
 }
 
-// Per-element E, gradient (n x 30) and Hessian (n x 30 x 30, row-major) of a
-// quadratic-tet set: one lane per (element, local node a) writes node a's
+// Per-element E, gradient (n x 3K) and Hessian (n x 3K x 3K, row-major) of a
+// higher-order tet set: one lane per (local node a, element) writes node a's
 // gradient and Hessian rows; the diagonal block is minus the sum of the row's
-// off-diagonal blocks (translation invariance).
-template <typename T>
-__global__ __launch_bounds__(64) void k_elem_eval_t10(SetDev S, const double* __restrict__ x,
-                                                     const double* __restrict__ X,
-                                                     T* __restrict__ Eo, T* __restrict__ go,
-                                                     T* __restrict__ Ho) {
-  const int64_t n = S.n_elem * 10;
+// off-diagonal blocks (translation invariance).  Lanes run node-major so that
+// the lanes of a wave take the same row function.
+template <int K, typename T>
+__global__ __launch_bounds__(64) void k_elem_eval_ho(SetDev S, const double* __restrict__ x,
+                                                    const double* __restrict__ X,
+                                                    T* __restrict__ Eo, T* __restrict__ go,
+                                                    T* __restrict__ Ho) {
+  constexpr int NO = 3 * (K - 1);
+  constexpr int NV = 3 + 3 * NO;
+  const int64_t n = S.n_elem * K;
   for (int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 64) {
-    const int64_t e = t / 10;
-    const int a = int(t - 10 * e);
-    const int8_t* perm = c_tet10_perm.p[a];
-    const int r = tet10_row_pos(a);
-    T acc[84];
+    const int a = int(t / S.n_elem);
+    const int64_t e = t - a * S.n_elem;
+    const int8_t* perm = HoTet<K>::perm(a);
+    const int r = ho_row_pos(K, a);
+    T acc[NV];
 #pragma unroll
-    for (int v = 0; v < 84; ++v) acc[v] = T(0);
-    for (int q = 0; q < kQuadPts; ++q) {
-      T out[84];
-      tet10_row_point<T, true>(S, e, a, q, x, X, out);
+    for (int v = 0; v < NV; ++v) acc[v] = T(0);
+    for (int q = 0; q < HoTet<K>::kPts; ++q) {
+      T out[NV];
+      ho_row_point<K, T, true>(S, e, a, q, x, X, out);
 #pragma unroll
-      for (int v = 0; v < 84; ++v) acc[v] += out[v];
+      for (int v = 0; v < NV; ++v) acc[v] += out[v];
     }
     if (go) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) go[e * 30 + 3 * a + i] = acc[i];
+      for (int i = 0; i < 3; ++i) go[e * 3 * K + 3 * a + i] = acc[i];
     }
     if (Ho) {
-      T* Hr = Ho + e * 900 + (int64_t)(3 * a) * 30;
+      T* Hr = Ho + e * 9 * K * K + (int64_t)(3 * a) * 3 * K;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         T d0 = T(0), d1 = T(0), d2 = T(0);
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
+        for (int j = 0; j < K - 1; ++j) {
           const int b = perm[j < r ? j : j + 1];
-          const T h0 = acc[3 + 27 * i + 3 * j], h1 = acc[4 + 27 * i + 3 * j],
-                  h2 = acc[5 + 27 * i + 3 * j];
-          Hr[30 * i + 3 * b + 0] = h0;
-          Hr[30 * i + 3 * b + 1] = h1;
-          Hr[30 * i + 3 * b + 2] = h2;
+          const T h0 = acc[3 + NO * i + 3 * j], h1 = acc[4 + NO * i + 3 * j],
+                  h2 = acc[5 + NO * i + 3 * j];
+          Hr[3 * K * i + 3 * b + 0] = h0;
+          Hr[3 * K * i + 3 * b + 1] = h1;
+          Hr[3 * K * i + 3 * b + 2] = h2;
           d0 += h0;
           d1 += h1;
           d2 += h2;
         }
-        Hr[30 * i + 3 * a + 0] = -d0;
-        Hr[30 * i + 3 * a + 1] = -d1;
-        Hr[30 * i + 3 * a + 2] = -d2;
+        Hr[3 * K * i + 3 * a + 0] = -d0;
+        Hr[3 * K * i + 3 * a + 1] = -d1;
+        Hr[3 * K * i + 3 * a + 2] = -d2;
       }
     }
-    if (Eo && a == 0) {
-      T in[66];
-      fill_tet10<T>(S, e, identity10(), x, X, in);
-      double Ee = 0.0;
-      for (int q = 0; q < kQuadPts; ++q) {
-        T o[1];
-        set_quad_point<T>(q, in);
-        snh_tet10_s_E<T>(in, o);
-        Ee += double(o[0]);
-      }
-      Eo[e] = T(Ee);
-    }
+    if (Eo && a == 0) Eo[e] = T(ho_energy<K, T>(S, e, x, X));
   }
 }
 
-// Row assembly of a quadratic-tet mesh (the steps of k_row_assemble_fast with
-// the evaluation split over quadrature points).  A batch holds at most
-// kQuadInc incidences; wave w of the workgroup evaluates quadrature point w of
-// every incidence, and the four points are added into LDS in point order.
-// The contribution entries are (incidence << 4) | j, j the other node's index
-// in the row function's order.  WANT_H = false: gradient only.
-template <typename T, bool WANT_G, bool WANT_H>
-__global__ __launch_bounds__(kRowWG) void k_row_assemble_t10(RowArgs<T> A) {
-  constexpr int NV = WANT_H ? 84 : 3;
-  __shared__ T st[NV][kQuadInc];
+// Row assembly of a higher-order tet mesh (the steps of k_row_assemble_fast
+// with the evaluation split over quadrature points).  A batch holds at most
+// HoTet<K>::kCap incidences.  Step 1 runs the evaluation items (point p,
+// incidence qi) = (item / nq, item % nq) in passes of kRowWG lanes; each pass
+// adds its items into LDS one point at a time, so every incidence sums its
+// points in point order.  Contribution entries are (incidence << kShift) | j,
+// j the other node's index in the row function's order.  WANT_H = false:
+// gradient only.
+template <int K, typename T, bool WANT_G, bool WANT_H>
+__global__ __launch_bounds__(kRowWG) void k_row_assemble_ho(RowArgs<T> A) {
+  using P = HoTet<K>;
+  constexpr int NO = 3 * (K - 1);
+  constexpr int NV = WANT_H ? 3 + 3 * NO : 3;
+  __shared__ T st[NV][P::kCap];
   __shared__ T blk[WANT_H ? 9 : 1][kRowWG];
   __shared__ uint16_t s_blk[kRowWG + 1];
   __shared__ uint16_t s_inc[kRowWG + 1];
@@ -1578,20 +1656,27 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_t10(RowArgs<T> A) {
   __syncthreads();
   const int nq = s_inc[nrows];
   const int np = s_blk[nrows];
-  // step 1: wave w evaluates point w of incidence qi
-  const int w = t >> 6, qi = t & 63;
-  T out[NV];
-  if (qi < nq) {
-    const uint32_t code = A.inc_code[q0 + qi];
-    tet10_row_point<T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), inc_local(code), w,
-                               A.x, A.X, out);
-  }
-  for (int k = 0; k < kQuadPts; ++k) {
-    if (w == k && qi < nq) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) st[v][qi] = k == 0 ? out[v] : st[v][qi] + out[v];
+  // step 1: evaluation passes
+  const int n_items = nq * P::kPts;
+  for (int i0 = 0; i0 < n_items; i0 += kRowWG) {
+    const int item = i0 + t;
+    const bool act = item < n_items;
+    const int p = act ? item / nq : 0;
+    const int qi = act ? item - p * nq : 0;
+    T out[NV];
+    if (act) {
+      const uint32_t code = A.inc_code[q0 + qi];
+      ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), inc_local(code), p,
+                                 A.x, A.X, out);
     }
-    __syncthreads();
+    const int p_lo = i0 / nq, p_hi = (min(n_items, i0 + kRowWG) - 1) / nq;
+    for (int k = p_lo; k <= p_hi; ++k) {
+      if (act && p == k) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) st[v][qi] = k == 0 ? out[v] : st[v][qi] + out[v];
+      }
+      __syncthreads();
+    }
   }
   int r = 0, col = 0;
   bool diag = false;
@@ -1609,13 +1694,13 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_t10(RowArgs<T> A) {
       const int cnt = int(info & 0xFFu);
       for (int j = 0; j < cnt; ++j) {
         const uint32_t wv = ce[j];
-        const int q = int(wv >> 4);
-        const int jj = int(wv & 15u);
+        const int q = int(wv >> P::kShift);
+        const int jj = int(wv & ((1u << P::kShift) - 1u));
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
           for (int kk = 0; kk < 3; ++kk)
-            acc[3 * i + kk] += st[3 + 27 * i + 3 * jj + kk][q];
+            acc[3 * i + kk] += st[3 + NO * i + 3 * jj + kk][q];
       }
       // step 3: publish
 #pragma unroll
@@ -2222,8 +2307,8 @@ __global__ __launch_bounds__(256) void k_contact_energy(int64_t n, const int* __
 }
 
 // Host side of the kind dispatch: f(std::integral_constant<int, KIND>) for a
-// set of kind `kind` (validated at mesh creation); quadratic tets have kernels
-// of their own and are not dispatched here.
+// set of kind `kind` (validated at mesh creation); higher-order tets have
+// kernels of their own (host_with_order) and are not dispatched here.
 template <typename F>
 static void host_with_kind(int kind, F&& f) {
   switch (kind) {
@@ -2236,6 +2321,14 @@ static void host_with_kind(int kind, F&& f) {
     case SYMX_ARAP_TET4: f(std::integral_constant<int, SYMX_ARAP_TET4>{}); break;
     default: break;
   }
+}
+
+// f(std::integral_constant<int, K>) for a set of quadratic (K = 10) or cubic
+// (K = 20) tets; nothing for any other kind.
+template <typename F>
+static void host_with_order(int kind, F&& f) {
+  if (kind == SYMX_SNH_TET10) f(std::integral_constant<int, 10>{});
+  if (kind == SYMX_SNH_TET20) f(std::integral_constant<int, 20>{});
 }
 
 static int grid_for(int64_t work, int per_block, int cap = 16384) {
@@ -2264,14 +2357,15 @@ symx_status launch_energy(Mesh& m, const double* x, const double* xt, double dt,
   int off = 0;
   for (int s = 0; s < sd.n; ++s) {
     const int G = grid_for(sd.s[s].n_elem, 256, 8192);
-    if (sd.s[s].kind == SYMX_SNH_TET10) {
+    host_with_order(sd.s[s].kind, [&](auto kc) {
+      constexpr int K = decltype(kc)::value;
       if (precision == SYMX_F32)
-        SYMX_LAUNCH(m, PNAME, k_energy_t10<float>, dim3(G), dim3(256), 0, sd.s[s], x, m.X,
+        SYMX_LAUNCH(m, PNAME, (k_energy_ho<K, float>), dim3(G), dim3(256), 0, sd.s[s], x, m.X,
                     m.partials + off, m.nonfinite);
       else
-        SYMX_LAUNCH(m, PNAME, k_energy_t10<double>, dim3(G), dim3(256), 0, sd.s[s], x, m.X,
+        SYMX_LAUNCH(m, PNAME, (k_energy_ho<K, double>), dim3(G), dim3(256), 0, sd.s[s], x, m.X,
                     m.partials + off, m.nonfinite);
-    }
+    });
     host_with_kind(sd.s[s].kind, [&](auto kc) {
       constexpr int KIND = decltype(kc)::value;
       if (precision == SYMX_F32)
@@ -2312,10 +2406,11 @@ static symx_status elem_eval_t(Mesh& m, int set, const double* x, void* E, void*
   const SetDev& S = sd.s[set];
   const int G = grid_for(S.n_elem, 128, 65535);
   if (S.n_elem == 0) return SYMX_OK;
-  if (S.kind == SYMX_SNH_TET10) {
-    SYMX_LAUNCH(m, PNAME, k_elem_eval_t10<T>, dim3(grid_for(10 * S.n_elem, 64, 65535)), dim3(64),
-                0, S, x, m.X, (T*)E, (T*)g, (T*)H);
-  }
+  host_with_order(S.kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    SYMX_LAUNCH(m, PNAME, (k_elem_eval_ho<K, T>), dim3(grid_for(K * S.n_elem, 64, 65535)),
+                dim3(64), 0, S, x, m.X, (T*)E, (T*)g, (T*)H);
+  });
   host_with_kind(S.kind, [&](auto kc) {
     constexpr int KIND = decltype(kc)::value;
     SYMX_LAUNCH(m, PNAME, (k_elem_eval<T, KIND>), dim3(G), dim3(128), 0, S, x, m.X, (T*)E,
@@ -2490,13 +2585,16 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   // reads records and evaluates no element.
   uint32_t kinds = 0;
   for (const SetHost& s : m.sets) kinds |= 1u << s.kind;
-  if (m.quad) {
-    if (want_H && want_g)
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble_t10<T, true, true>), grid, block, 0, A);
-    else if (want_H)
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble_t10<T, false, true>), grid, block, 0, A);
-    else
-      SYMX_LAUNCH(m, PNAME, (k_row_assemble_t10<T, true, false>), grid, block, 0, A);
+  if (m.ho) {
+    host_with_order(m.sets[0].kind, [&](auto kc) {
+      constexpr int K = decltype(kc)::value;
+      if (want_H && want_g)
+        SYMX_LAUNCH(m, PNAME, (k_row_assemble_ho<K, T, true, true>), grid, block, 0, A);
+      else if (want_H)
+        SYMX_LAUNCH(m, PNAME, (k_row_assemble_ho<K, T, false, true>), grid, block, 0, A);
+      else
+        SYMX_LAUNCH(m, PNAME, (k_row_assemble_ho<K, T, true, false>), grid, block, 0, A);
+    });
   } else if (filter && want_H) {
     if (want_g)
       SYMX_LAUNCH(m, PNAME, (k_row_assemble_fast<T, true, kRowFilter, 0u>), grid, block, 0, A);

@@ -208,11 +208,10 @@ Topology::~Topology() {
   void* dev[] = {row_ptr, col_idx, diag_pos, inc_ptr, inc_code, batch_row, blk_info, centry,
                  batch_entry};
   for (void* p : dev) dev_free(pool, p);
-  for (TopoSet& s : sets) dev_free(pool, s.d_conn);
-}
-
-static int kind_nodes(int kind) {
-  return kind == SYMX_STVK_TRI3 ? 3 : kind == SYMX_SNH_TET10 ? 10 : 4;
+  for (TopoSet& s : sets) {
+    dev_free(pool, s.d_conn);
+    dev_free(pool, s.d_conn_ho);
+  }
 }
 
 bool Topology::matches(const symx_mesh_desc& d) const {

@@ -77,7 +77,7 @@ SetsDev Mesh::sets_dev() const {
     d.s[s].prm_stride = h.uniform ? 0 : kPrm;
     d.s[s].rot64 = h.d_rot64;
     d.s[s].rot32 = h.d_rot32;
-    d.s[s].conn10 = h.d_conn10;
+    d.s[s].conn_ho = h.d_conn_ho;
   }
   return d;
 }
@@ -113,17 +113,16 @@ static void parallel_chunks(int64_t n, int64_t min_chunk, F f) {
   for (auto& x : th) x.join();
 }
 
-static int kind_nodes(int kind) {
-  if (kind == SYMX_STVK_TRI3) return 3;
-  if (kind == SYMX_SNH_TET10) return 10;
-  return kind >= SYMX_SNH_TET4 && kind <= SYMX_ARAP_TET4 ? 4 : 0;
+// Nodes per element, 0 for an unknown kind.
+static int known_kind_nodes(int kind) {
+  return kind >= SYMX_SNH_TET4 && kind <= SYMX_SNH_TET20 ? kind_nodes(kind) : 0;
 }
 
 // Element kind, count and connectivity of one energy set.  check_nodes: node
 // ids in range and distinct within each element (skipped when the
 // connectivity equals that of a cached, already validated topology).
 static symx_status validate_set(const symx_energy_desc& d, int64_t N, bool check_nodes) {
-  const int k = kind_nodes(d.kind);
+  const int k = known_kind_nodes(d.kind);
   if (k == 0) {
     set_error("unknown energy kind " + std::to_string(d.kind));
     return SYMX_ERR_INVALID_ARG;
@@ -162,9 +161,29 @@ static void note_first(std::atomic<int64_t>& first, int64_t e) {
   }
 }
 
+// HRZ lumping of higher-order tets: node a's share of the element mass is its
+// consistent-mass diagonal, the integral of N_a^2, over the sum of the
+// diagonal.  With the integral of L0^p L1^q L2^r L3^s over a tet of volume V
+// equal to 6V p!q!r!s!/(p+q+r+s+3)!, the diagonal is V/70 at a corner and
+// 8V/105 at an edge node of a quadratic tet; V/280 at a corner, 27V/1120 at an
+// edge node and 27V/280 at a face node of a cubic tet.  Other kinds: 1 (their
+// element mass is per node).
+static double ho_mass_share(int k, int a) {
+  if (k == 10) {
+    const double dc = 1.0 / 70.0, de = 8.0 / 105.0;
+    return (a < 4 ? dc : de) / (4.0 * dc + 6.0 * de);
+  }
+  if (k == 20) {
+    const double dc = 1.0 / 280.0, de = 27.0 / 1120.0, df = 27.0 / 280.0;
+    return (a < 4 ? dc : a < 16 ? de : df) / (4.0 * dc + 12.0 * de + 4.0 * df);
+  }
+  return 1.0;
+}
+
 // Per-mesh data of one energy set: parameters and rest measures.  elem_mass
 // receives each element's lumped mass per node (rho V / 4 per tet, rho h A / 3
-// per triangle; hinges carry none).
+// per triangle; hinges carry none), or for higher-order tets the element mass
+// rho V that ho_mass_share splits over the nodes.
 static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s,
                              std::vector<double>& elem_mass) {
   s.kind = d.kind;
@@ -197,11 +216,10 @@ static symx_status build_set(Mesh& m, const symx_energy_desc& d, SetHost& s,
   }
   // rest measures, element masses, hinge weights
   std::atomic<int64_t> bad{-1};
-  if ((s.k == 4 && d.kind != SYMX_HINGE4) || s.k == 10) {
-    // linear tets: rho V / 4 per node; quadratic tets keep rho V / 36 (the
-    // corner share of HRZ lumping, V of the corner tet), edge nodes get 16/3
-    // of it
-    const double share = s.k == 10 ? 1.0 / 36.0 : 0.25;
+  if ((s.k == 4 && d.kind != SYMX_HINGE4) || s.k >= 10) {
+    // linear tets: rho V / 4 per node; higher-order tets: rho V (V of the
+    // corner tet)
+    const double share = s.k >= 10 ? 1.0 : 0.25;
     elem_mass.resize(s.n_elem);
     parallel_chunks(s.n_elem, 16384, [&](int64_t e0, int64_t e1) {
       for (int64_t e = e0; e < e1; ++e) {
@@ -281,11 +299,11 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
     ts.k = kind_nodes(ts.kind);
     ts.n_elem = d.energies[si].n_elem;
     ts.conn.assign(d.energies[si].conn, d.energies[si].conn + ts.n_elem * ts.k);
-    t.quad = t.quad || ts.k == 10;
+    t.ho = std::max(t.ho, kind_high_order(ts.kind));
   }
   // incidences per batch, and slot bytes per incidence (see below)
-  const int inc_cap = t.quad ? kQuadInc : kRowWG;
-  const int KS = t.quad ? 10 : 4;
+  const int inc_cap = t.ho == 20 ? kCubicInc : t.ho == 10 ? kQuadInc : kRowWG;
+  const int KS = t.ho ? t.ho : 4;
   const int64_t N = t.N;
   // Node -> incidences (set, element, local node), in (set, element) order:
   // a counting sort over the concatenated element list, split into
@@ -351,9 +369,9 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   // Rows in parallel chunks: sorted unique neighbour list of each node, and
   // for each incidence the row-local slots of its blocks in the relabelled
   // node order.  Up to four nodes: a first, then the others ascending
-  // (slots[KS q + b], b = 0..3).  Quadratic tets: the nine other nodes in the
-  // order of the row function (kTet10Perm, position tet10_row_pos(a) left
-  // out), slots[KS q + j], j = 0..8.  Each thread marks the nodes already in
+  // (slots[KS q + b], b = 0..3).  Higher-order tets (k nodes): the k - 1
+  // other nodes in the order of the row function (kTet10Perm or kTet20Perm,
+  // position ho_row_pos(k, a) left out), slots[KS q + j], j = 0..k-2.  Each thread marks the nodes already in
   // the current row (mark[j] == row) and maps node -> slot (pos[j]), so a row
   // costs O(incidences) plus a sort of its few columns.
   uvector<uint8_t> slots(t.n_inc * KS);
@@ -393,10 +411,11 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
           const int a = inc_local(code[q]);
           const int64_t e = inc_elem(code[q]);
           uint8_t* sq = slots.data() + KS * q;
-          if (s.k == 10) {
-            const int r = tet10_row_pos(a);
-            for (int bp = 0, j = 0; bp < 10; ++bp)
-              if (bp != r) sq[j++] = (uint8_t)pos[s.conn[e * 10 + kTet10Perm.p[a][bp]]];
+          if (s.k >= 10) {
+            const int r = ho_row_pos(s.k, a);
+            const int8_t* perm = s.k == 10 ? kTet10Perm.p[a] : kTet20Perm.p[a];
+            for (int bp = 0, j = 0; bp < s.k; ++bp)
+              if (bp != r) sq[j++] = (uint8_t)pos[s.conn[e * s.k + perm[bp]]];
           } else {
             int order[4] = {a, -1, -1, -1};
             for (int b = 0, o = 1; b < s.k; ++b)
@@ -454,8 +473,9 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   // Off-diagonal contribution lists.  For every off-diagonal block of a batch,
   // the (incidence, relabelled node) pairs that add to it, in incidence order;
   // entries are u16 = (incidence index within the batch << 2) | b with b >= 1
-  // the relabelled position, or (incidence << 4) | j for quadratic tets (j =
-  // 0..8, the row function's order).  blk_info[p] = (first entry relative to
+  // the relabelled position, or (incidence << 4) | j for quadratic tets and
+  // (incidence << 5) | j for cubic tets (j = 0..k-2, the row function's
+  // order).  blk_info[p] = (first entry relative to
   // the batch's base << 8) | count.
   std::vector<int32_t> batch_entry(t.n_batch + 1, 0);
   for (int b = 0; b < t.n_batch; ++b) {
@@ -474,7 +494,8 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
       const int64_t np = t.h_row_ptr[r1] - p0;
       cnt_blk.assign(np + 1, 0);
       // the blocks an incidence adds to: slots j0..j0+k-2 of its entry
-      const int j0 = t.quad ? 0 : 1;
+      const int j0 = t.ho ? 0 : 1;
+      const int shift = t.ho == 20 ? 5 : t.ho == 10 ? 4 : 2;
       for (int64_t r = r0; r < r1; ++r)
         for (int64_t q = cnt[r]; q < cnt[r + 1]; ++q) {
           const int k = t.sets[inc_set(code[q])].k;
@@ -494,8 +515,7 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
           const int k = t.sets[inc_set(code[q])].k;
           for (int j = j0; j < j0 + k - 1; ++j) {
             const int64_t pl = t.h_row_ptr[r] + slots[KS * q + j] - p0;
-            base[fillp[pl]++] =
-                (uint16_t)(t.quad ? (((q - q0) << 4) | j) : (((q - q0) << 2) | j));
+            base[fillp[pl]++] = (uint16_t)(((q - q0) << shift) | j);
           }
         }
     }
@@ -525,8 +545,8 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   TRY(upload(pool, stream, &t.centry, centry.data(), centry.size(), &nb));
   TRY(upload(pool, stream, &t.batch_entry, batch_entry.data(), batch_entry.size(), &nb));
   for (TopoSet& ts : t.sets) {
-    if (ts.k == 10) {
-      TRY(upload(pool, stream, &ts.d_conn10, ts.conn.data(), ts.conn.size(), &nb));
+    if (ts.k >= 10) {
+      TRY(upload(pool, stream, &ts.d_conn_ho, ts.conn.data(), ts.conn.size(), &nb));
       continue;
     }
     uvector<int4> c4(std::max<int64_t>(ts.n_elem, 1));
@@ -584,9 +604,9 @@ static void attach_topology(Mesh& m, std::shared_ptr<Topology> tp) {
   for (size_t s = 0; s < m.sets.size(); ++s) {
     m.sets[s].conn = t.sets[s].conn.data();
     m.sets[s].d_conn = t.sets[s].d_conn;
-    m.sets[s].d_conn10 = t.sets[s].d_conn10;
+    m.sets[s].d_conn_ho = t.sets[s].d_conn_ho;
   }
-  m.quad = t.quad;
+  m.ho = t.ho;
   m.topo = std::move(tp);
 }
 
@@ -655,10 +675,12 @@ symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool,
   if (d->fixed)
     for (int64_t i = 0; i < m->N; ++i) m->h_fixed[i] = d->fixed[i] ? 1 : 0;
   for (int s = 0; s < d->n_energies; ++s) TRY(validate_set(d->energies[s], m->N, false));
-  int n_quad = 0;
-  for (int s = 0; s < d->n_energies; ++s) n_quad += d->energies[s].kind == SYMX_SNH_TET10;
-  if (n_quad > 0 && n_quad < d->n_energies) {
-    set_error("a mesh with quadratic tets holds no other element kind");
+  int ho_kind = -1, n_same = 0;
+  for (int s = 0; s < d->n_energies; ++s)
+    if (ho_kind < 0 && kind_high_order(d->energies[s].kind)) ho_kind = d->energies[s].kind;
+  for (int s = 0; s < d->n_energies; ++s) n_same += d->energies[s].kind == ho_kind;
+  if (ho_kind >= 0 && n_same < d->n_energies) {
+    set_error("a mesh with quadratic or cubic tets holds no other set");
     return SYMX_ERR_INVALID_ARG;
   }
   std::shared_ptr<Topology> topo;
@@ -682,9 +704,7 @@ symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool,
         const uint32_t c = t.h_inc_code[q];
         const std::vector<double>& em = elem_mass[inc_set(c)];
         if (em.empty()) continue;
-        // quadratic tets: edge nodes carry 16/3 of the corner share
-        const bool edge = t.sets[inc_set(c)].k == 10 && inc_local(c) >= 4;
-        mi += edge ? em[inc_elem(c)] * (16.0 / 3.0) : em[inc_elem(c)];
+        mi += em[inc_elem(c)] * ho_mass_share(t.sets[inc_set(c)].k, inc_local(c));
       }
       m->h_mass[i] = mi;
     }

@@ -129,8 +129,8 @@ static symx_status project_into_records(Mesh& m, const double* x, int precision,
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g, bool want_H,
                      int project, int precision, bool dirichlet, double* g_out,
                      void* dinv = nullptr) {
-  if (project && want_H && m.quad) {
-    set_error("per-element PSD projection is not available for quadratic tets");
+  if (project && want_H && m.ho) {
+    set_error("per-element PSD projection is not available for quadratic or cubic tets");
     return SYMX_ERR_INVALID_ARG;
   }
   if (want_H) TRY(ensure_values(m, precision));

@@ -69,18 +69,19 @@ struct Request {
 // project: include the incidence-ordered records of per-element projection.
 size_t estimate_request_bytes(const symx_mesh_desc& d, int precision, bool project) {
   const size_t N = (size_t)d.n_nodes;
-  size_t pairs = N, inc = 0, elems = 0, rot_elems = 0;
+  size_t pairs = N, inc = 0, elems = 0, rot_elems = 0, conn = 0;
   for (int s = 0; s < d.n_energies; ++s) {
-    const int k = d.energies[s].kind == SYMX_STVK_TRI3 ? 3 : d.energies[s].kind == SYMX_SNH_TET10 ? 10 : 4;
+    const int k = kind_nodes(d.energies[s].kind);
     pairs += (size_t)d.energies[s].n_elem * k * (k - 1);
     inc += (size_t)d.energies[s].n_elem * k;
     elems += (size_t)d.energies[s].n_elem;
+    conn += (size_t)d.energies[s].n_elem * 4 * (k < 4 ? 4 : k);
     if (kind_has_rotation(d.energies[s].kind)) rot_elems += (size_t)d.energies[s].n_elem;
   }
   const size_t vbytes = precision == SYMX_F64 ? 8 : 4;
   size_t b = 0;
   b += pairs * (9 * vbytes + 4 + 4 + 2 * 3);   // values, col_idx, contribution info/entries
-  b += inc * 4 + elems * (16 + 2 * 8 * kPrm + 4 * 4);  // incidence codes, conn, params
+  b += inc * 4 + conn + elems * (2 * 8 * kPrm + 4 * 4);  // incidence codes, conn, params
   b += rot_elems * 9 * (8 + 4);                // lagged rotations
   if (project) b += inc * (kIncRec * vbytes + 4);  // projected records, their positions
   b += N * (3 * 8 + 8 + 1 + 4 * 4);            // X, mass, fixed, row/inc pointers
@@ -250,7 +251,7 @@ symx_status server_submit(Server* s, const symx_mesh_desc* d, const double* x, c
   sc.young.resize(d->n_energies);
   for (int e = 0; e < d->n_energies; ++e) {
     const symx_energy_desc& ed = d->energies[e];
-    const int k = ed.kind == SYMX_STVK_TRI3 ? 3 : ed.kind == SYMX_SNH_TET10 ? 10 : 4;
+    const int k = kind_nodes(ed.kind);
     if (ed.n_elem < 0 || (ed.n_elem > 0 && !ed.conn)) {
       set_error("invalid energy set in request");
       return SYMX_ERR_INVALID_ARG;

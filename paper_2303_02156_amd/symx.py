@@ -25,7 +25,7 @@ SYMX_SNH_TET4, SYMX_STVK_TRI3, SYMX_HINGE4 = 0, 1, 2
 SYMX_NH_TET4, SYMX_STVK_TET4, SYMX_FCR_TET4, SYMX_ARAP_TET4 = 3, 4, 5, 6
 SYMX_EVAL_E, SYMX_EVAL_GRAD, SYMX_EVAL_HESS, SYMX_PROJECT_PSD, SYMX_DIRICHLET = 1, 2, 4, 8, 16
 SYMX_PROJECT_FILTER = 32
-SYMX_SNH_TET10 = 7
+SYMX_SNH_TET10, SYMX_SNH_TET20 = 7, 8
 
 
 class EnergyDesc(C.Structure):
