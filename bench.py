@@ -406,23 +406,40 @@ def materials_bench(symx, torch, reps=10):
             "materials": out}
 
 
-# Quadratic tets on the stretched box: the paper's per-Newton-iteration
-# evaluation + assembly time of its 137K-DoF stretched cube with quadratic
-# elements (simulation benchmark table, SymX column) and its single-element
-# E+g+H time of a quadratic tet (single element benchmark table), CPU, ms and
-# us; context only, another machine.
+# Higher-order tets on the stretched box: the paper's per-Newton-iteration
+# evaluation + assembly time of its 137K-DoF stretched cube with quadratic and
+# cubic elements (simulation benchmark table, SymX column) and its
+# single-element E+g+H time of such a tet (single element benchmark table),
+# CPU, ms and us; context only, another machine.
 PAPER_TET10_MS_PER_ITER = 24.3
 PAPER_TET10_US_PER_ELEM = 5.91
+PAPER_TET20_MS_PER_ITER = 52.9
+PAPER_TET20_US_PER_ELEM = 64.13
+
+# order -> (kind, box dims in cubes, points of the rule, row functions with
+# the number of local nodes that use each, paper numbers)
+HIGH_ORDER = {
+    "quadratic": dict(kind=7, k=10, dims=(17, 17, 18), pts=4, rule="4-point rule",
+                      rows=(("snh_tet10_row0_gHoff", 4), ("snh_tet10_row4_gHoff", 6)),
+                      paper=(PAPER_TET10_MS_PER_ITER, PAPER_TET10_US_PER_ELEM)),
+    "cubic": dict(kind=8, k=20, dims=(11, 11, 13), pts=11, rule="Keast 11-point rule",
+                  rows=(("snh_tet20_row0_gHoff", 4), ("snh_tet20_row4_gHoff", 12),
+                        ("snh_tet20_row19_gHoff", 4)),
+                  paper=(PAPER_TET20_MS_PER_ITER, PAPER_TET20_US_PER_ELEM)),
+}
 
 
-def quadratic_bench(symx, torch, reps=10):
-    """Quadratic SNH tets (Eq. 12, 4-point rule) on a stretched box of
-    17 x 17 x 18 cubes (31,212 tets, 45,325 nodes = 135,975 DoF): one E+g+H
-    assembly in FP32 and FP64 (device events, median of reps) and one
-    FP32-refined Newton step."""
+def high_order_bench(symx, torch, order, reps=10):
+    """Quadratic or cubic SNH tets (Eq. 12) on a stretched box of about 137K
+    DoF (quadratic: 17 x 17 x 18 cubes, 31,212 tets, 135,975 DoF; cubic:
+    11 x 11 x 13 cubes, 9,438 tets, 138,720 DoF): one E+g+H assembly in FP32
+    and FP64 (device events, median of reps) and one FP32-refined Newton step.
+    row_ops_per_elem counts the generated operations of the row functions the
+    assembly evaluates (every node of every element at every point)."""
     import numpy as np
     import scenegen as sg
-    scene = sg.stretched_box_scene(sg.SNH_TET10, dims=(17, 17, 18))
+    cfg = HIGH_ORDER[order]
+    scene = sg.stretched_box_scene(cfg["kind"], dims=cfg["dims"])
     mesh = symx.Mesh(scene)
     n_elem = scene.n_elements()
     dt = scene.dt
@@ -432,9 +449,11 @@ def quadratic_bench(symx, torch, reps=10):
                       dtype=torch.float64, device="cuda")
     g = torch.empty_like(x0)
     flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
-    out = {"workload": "stretched box of quadratic SNH tets: 17x17x18 cubes x 6 tet10 "
-                       f"({n_elem} elements, {3 * scene.n_nodes} DoF), E=1e4 nu=0.3, top face "
-                       "held at 1.2x height, +-1% noise (seed 6), dt=0.01, 4-point rule",
+    nx, ny, nz = cfg["dims"]
+    out = {"workload": f"stretched box of {order} SNH tets: {nx}x{ny}x{nz} cubes x 6 "
+                       f"tet{cfg['k']} ({n_elem} elements, {3 * scene.n_nodes} DoF), E=1e4 "
+                       "nu=0.3, top face held at 1.2x height, +-1% noise (seed 6), dt=0.01, "
+                       + cfg["rule"],
            "elements": n_elem, "dof": 3 * scene.n_nodes, "nnzb": int(mesh.info.nnzb)}
     for pname, prec in (("f32", symx.SYMX_F32), ("f64", symx.SYMX_F64)):
         ms = []
@@ -451,11 +470,13 @@ def quadratic_bench(symx, torch, reps=10):
         m = statistics.median(ms)
         out[f"assembly_ms_{pname}"] = round(m, 4)
         out[f"ns_per_elem_{pname}"] = round(m * 1e6 / n_elem, 2)
-    ops = census_ops("snh_tet10_EgH")
-    if ops:
-        out["algorithmic_ops_per_elem"] = 4 * ops
-        out["achieved_tflops_f32"] = round(4 * ops * n_elem / (out["assembly_ms_f32"] * 1e-3) / 1e12,
-                                           2)
+    row_ops = [census_ops(name) for name, _ in cfg["rows"]]
+    if all(row_ops):
+        ops = cfg["pts"] * sum(o * n for o, (_, n) in zip(row_ops, cfg["rows"]))
+        out["row_ops_per_elem"] = ops
+        for pname in ("f32", "f64"):
+            out[f"achieved_tflops_{pname}"] = round(
+                ops * n_elem / (out[f"assembly_ms_{pname}"] * 1e-3) / 1e12, 2)
     x = x0.clone()
     v = v0.clone()
     torch.cuda.synchronize()
@@ -467,10 +488,10 @@ def quadratic_bench(symx, torch, reps=10):
                 "status": symx.STATUS[st], "newton_iters": rep.newton_iters,
                 "pcg_iters": rep.pcg_iters,
                 "rel_residual": rep.residual / max(rep.residual0, 1e-300),
-                "paper_cpu_ms_per_newton_iter": PAPER_TET10_MS_PER_ITER,
-                "paper_cpu_us_per_elem": PAPER_TET10_US_PER_ELEM})
+                "paper_cpu_ms_per_newton_iter": cfg["paper"][0],
+                "paper_cpu_us_per_elem": cfg["paper"][1]})
     mesh.close()
-    log(f"quadratic tets: {out}")
+    log(f"{order} tets: {out}")
     return out
 
 
@@ -595,8 +616,9 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-materials", action="store_true")
     ap.add_argument("--no-quadratic", action="store_true")
+    ap.add_argument("--no-cubic", action="store_true")
     ap.add_argument("--no-contacts", action="store_true")
-    ap.add_argument("--only", choices=["c3", "c4", "materials", "quadratic", "contacts"],
+    ap.add_argument("--only", choices=["c3", "c4", "materials", "quadratic", "cubic", "contacts"],
                     help="run only this extra workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run plain 512 MiB device copies first (byte-counter calibration)")
@@ -631,8 +653,8 @@ def main():
     if args.only == "materials":
         print(json.dumps({"materials": materials_bench(symx, torch)}), flush=True)
         return
-    if args.only == "quadratic":
-        print(json.dumps({"quadratic": quadratic_bench(symx, torch)}), flush=True)
+    if args.only in HIGH_ORDER:
+        print(json.dumps({args.only: high_order_bench(symx, torch, args.only)}), flush=True)
         return
     if args.only == "contacts":
         print(json.dumps({"contacts": contact_bench(symx, torch)}), flush=True)
@@ -806,7 +828,8 @@ def main():
     if c3:
         log(f"c3: {c3}")
     materials = None if args.no_materials else materials_bench(symx, torch)
-    quadratic = None if args.no_quadratic else quadratic_bench(symx, torch)
+    quadratic = None if args.no_quadratic else high_order_bench(symx, torch, "quadratic")
+    cubic = None if args.no_cubic else high_order_bench(symx, torch, "cubic")
     contacts = None if args.no_contacts else contact_bench(symx, torch)
 
     serving = None
@@ -863,6 +886,7 @@ def main():
         "c3_mixed": c3,
         "materials": materials,
         "quadratic_tets": quadratic,
+        "cubic_tets": cubic,
         "contacts": contacts,
         "mesh_setup_s": round(setup_s, 3),
         "kernels_f32_refined_steps": kernels,

@@ -1484,38 +1484,45 @@ struct HoTet<20> {
   }
 };
 
-// Inputs 0..6K+1 of the per-point function for element e with its nodes in
-// the order perm (local indices): positions and rest positions relative to
-// the first node (a corner), then mu and lambda.
+// Inputs 0..6K+1 of the per-point function for element e, whose node ids
+// are c[0..K), with its nodes in the order perm (local indices): positions
+// and rest positions relative to the first node (a corner), then mu and
+// lambda.  All positions are loaded before they are used, so the loads are
+// in flight together.
 template <int K, typename T>
-__device__ __forceinline__ void fill_ho(const SetDev& S, int64_t e, const int8_t* perm,
-                                        const double* __restrict__ x,
+__device__ __forceinline__ void fill_ho(const SetDev& S, int64_t e, const int* c,
+                                        const int8_t* perm, const double* __restrict__ x,
                                         const double* __restrict__ X, T* in) {
-  const int* c = S.conn_ho + (int64_t)K * e;
-  const int n0 = c[perm[0]];
-  const double x0 = x[3 * (int64_t)n0], x1 = x[3 * (int64_t)n0 + 1], x2 = x[3 * (int64_t)n0 + 2];
-  const double X0 = X[3 * (int64_t)n0], X1 = X[3 * (int64_t)n0 + 1], X2 = X[3 * (int64_t)n0 + 2];
-  in[0] = in[1] = in[2] = T(0);
-  in[3 * K] = in[3 * K + 1] = in[3 * K + 2] = T(0);
+  double px[3 * K], pX[3 * K];
 #pragma unroll
-  for (int b = 1; b < K; ++b) {
+  for (int b = 0; b < K; ++b) {
     const int64_t n = c[perm[b]];
-    in[3 * b + 0] = T(x[3 * n + 0] - x0);
-    in[3 * b + 1] = T(x[3 * n + 1] - x1);
-    in[3 * b + 2] = T(x[3 * n + 2] - x2);
-    in[3 * K + 3 * b + 0] = T(X[3 * n + 0] - X0);
-    in[3 * K + 3 * b + 1] = T(X[3 * n + 1] - X1);
-    in[3 * K + 3 * b + 2] = T(X[3 * n + 2] - X2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      px[3 * b + i] = x[3 * n + i];
+      pX[3 * b + i] = X[3 * n + i];
+    }
   }
+  // a compiler barrier: every position load above is issued before the first
+  // use below (otherwise the loads are interleaved with their uses and each
+  // node costs a memory round trip)
+  __asm__ volatile("" ::: "memory");
+#pragma unroll
+  for (int b = 0; b < K; ++b)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      in[3 * b + i] = T(px[3 * b + i] - px[i]);
+      in[3 * K + 3 * b + i] = T(pX[3 * b + i] - pX[i]);
+    }
   const T* P = prm_ptr<T>(S);
   in[6 * K] = ld_prm(P, S.prm_stride, e, 0);
   in[6 * K + 1] = ld_prm(P, S.prm_stride, e, 1);
 }
 
-// Inputs 6K+2..6K+5: weight and reference coordinates of quadrature point q.
+// Inputs 6K+2..6K+5: weight and reference coordinates of quadrature point q
+// of rule r.
 template <int K, typename T>
-__device__ __forceinline__ void set_point(int q, T* in) {
-  const QuadRule& r = HoTet<K>::rule();
+__device__ __forceinline__ void set_point(const QuadRule& r, int q, T* in) {
   in[6 * K + 2] = T(r.w[q]);
   in[6 * K + 3] = T(r.xi[q][0]);
   in[6 * K + 4] = T(r.xi[q][1]);
@@ -1528,11 +1535,11 @@ __device__ __forceinline__ double ho_energy(const SetDev& S, int64_t e, const do
                                             const double* X) {
   T in[6 * K + 6];
   // the relabelling of corner 0 leaves every node in place
-  fill_ho<K, T>(S, e, HoTet<K>::perm(0), x, X, in);
+  fill_ho<K, T>(S, e, S.conn_ho + (int64_t)K * e, HoTet<K>::perm(0), x, X, in);
   double Ee = 0.0;
   for (int q = 0; q < HoTet<K>::kPts; ++q) {
     T out[1];
-    set_point<K, T>(q, in);
+    set_point<K, T>(HoTet<K>::rule(), q, in);
     HoTet<K>::template energy<T>(in, out);
     Ee += double(out[0]);
   }
@@ -1557,15 +1564,17 @@ __global__ __launch_bounds__(256) void k_energy_ho(SetDev S, const double* __res
   }
 }
 
-// Row of local node a of element e at quadrature point q: out[0..2] gradient,
-// out[3 + 3(K-1) i + 3 j + k] the off-diagonal block entries of the K - 1
-// other nodes in the row function's order (WANT_H), or the gradient only.
+// Row of local node a of element e (node ids c, relabelling perm of node a)
+// at point q of rule r: out[0..2] gradient, out[3 + 3(K-1) i + 3 j + k] the
+// off-diagonal block entries of the K - 1 other nodes in the row function's
+// order (WANT_H), or the gradient only.
 template <int K, typename T, bool WANT_H>
-__device__ __forceinline__ void ho_row_point(const SetDev& S, int64_t e, int a, int q,
+__device__ __forceinline__ void ho_row_point(const SetDev& S, int64_t e, const int* c,
+                                             const int8_t* perm, int a, const QuadRule& r, int q,
                                              const double* x, const double* X, T* out) {
   T in[6 * K + 6];
-  fill_ho<K, T>(S, e, HoTet<K>::perm(a), x, X, in);
-  set_point<K, T>(q, in);
+  fill_ho<K, T>(S, e, c, perm, x, X, in);
+  set_point<K, T>(r, q, in);
   HoTet<K>::template row<T, WANT_H>(a, in, out);
 }
 
@@ -1592,7 +1601,8 @@ __global__ __launch_bounds__(64) void k_elem_eval_ho(SetDev S, const double* __r
     for (int v = 0; v < NV; ++v) acc[v] = T(0);
     for (int q = 0; q < HoTet<K>::kPts; ++q) {
       T out[NV];
-      ho_row_point<K, T, true>(S, e, a, q, x, X, out);
+      ho_row_point<K, T, true>(S, e, S.conn_ho + (int64_t)K * e, perm, a, HoTet<K>::rule(), q,
+                               x, X, out);
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] += out[v];
     }
@@ -1631,16 +1641,30 @@ __global__ __launch_bounds__(64) void k_elem_eval_ho(SetDev S, const double* __r
 // HoTet<K>::kCap incidences.  Step 1 runs the evaluation items (point p,
 // incidence qi) = (item / nq, item % nq) in passes of kRowWG lanes; each pass
 // adds its items into LDS one point at a time, so every incidence sums its
-// points in point order.  Contribution entries are (incidence << kShift) | j,
-// j the other node's index in the row function's order.  WANT_H = false:
-// gradient only.
+// points in point order.  The batch's incidence codes and element node ids,
+// the relabelling tables and the rule are staged in LDS first (in the space
+// the block sums use later), so an item's position loads depend on LDS reads
+// only.  Contribution entries are (incidence << kShift) | j, j the other
+// node's index in the row function's order.  WANT_H = false: gradient only.
+template <int K>
+struct HoStage {
+  uint32_t code[HoTet<K>::kCap];
+  int conn[HoTet<K>::kCap][K];
+  HoPerm<K> perm;
+  QuadRule rule;
+};
+
 template <int K, typename T, bool WANT_G, bool WANT_H>
 __global__ __launch_bounds__(kRowWG) void k_row_assemble_ho(RowArgs<T> A) {
   using P = HoTet<K>;
   constexpr int NO = 3 * (K - 1);
   constexpr int NV = WANT_H ? 3 + 3 * NO : 3;
   __shared__ T st[NV][P::kCap];
-  __shared__ T blk[WANT_H ? 9 : 1][kRowWG];
+  __shared__ union {
+    T blk[WANT_H ? 9 : 1][kRowWG];
+    HoStage<K> stg;
+  } sh;
+  auto& blk = sh.blk;
   __shared__ uint16_t s_blk[kRowWG + 1];
   __shared__ uint16_t s_inc[kRowWG + 1];
   const int t = threadIdx.x;
@@ -1656,6 +1680,21 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_ho(RowArgs<T> A) {
   __syncthreads();
   const int nq = s_inc[nrows];
   const int np = s_blk[nrows];
+  // step 0: staging
+  for (int j = t; j < nq; j += kRowWG) sh.stg.code[j] = A.inc_code[q0 + j];
+  for (int j = t; j < K * K; j += kRowWG) sh.stg.perm.p[j / K][j % K] = P::perm(j / K)[j % K];
+  for (int j = t; j < 4 * P::kPts; j += kRowWG) {
+    const int q = j >> 2, c = j & 3;
+    if (c == 0) sh.stg.rule.w[q] = P::rule().w[q];
+    else sh.stg.rule.xi[q][c - 1] = P::rule().xi[q][c - 1];
+  }
+  __syncthreads();
+  for (int j = t; j < nq * K; j += kRowWG) {
+    const int qi = j / K, bb = j - qi * K;
+    const uint32_t code = sh.stg.code[qi];
+    sh.stg.conn[qi][bb] = A.sets.s[inc_set(code)].conn_ho[(int64_t)K * inc_elem(code) + bb];
+  }
+  __syncthreads();
   // step 1: evaluation passes
   const int n_items = nq * P::kPts;
   for (int i0 = 0; i0 < n_items; i0 += kRowWG) {
@@ -1665,9 +1704,10 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_ho(RowArgs<T> A) {
     const int qi = act ? item - p * nq : 0;
     T out[NV];
     if (act) {
-      const uint32_t code = A.inc_code[q0 + qi];
-      ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), inc_local(code), p,
-                                 A.x, A.X, out);
+      const uint32_t code = sh.stg.code[qi];
+      const int a = inc_local(code);
+      ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), sh.stg.conn[qi],
+                                 sh.stg.perm.p[a], a, sh.stg.rule, p, A.x, A.X, out);
     }
     const int p_lo = i0 / nq, p_hi = (min(n_items, i0 + kRowWG) - 1) / nq;
     for (int k = p_lo; k <= p_hi; ++k) {
