@@ -166,6 +166,13 @@ int Graph::diff(int f, int s) {
 
 std::vector<int> Graph::substitute(const std::vector<int>& roots,
                                    const std::map<int, double>& slot_values) {
+  std::map<int, int> slot_nodes;
+  for (const auto& sv : slot_values) slot_nodes[sv.first] = cst(sv.second);
+  return substitute_nodes(roots, slot_nodes);
+}
+
+std::vector<int> Graph::substitute_nodes(const std::vector<int>& roots,
+                                         const std::map<int, int>& slot_nodes) {
   std::unordered_map<int, int> memo;
   std::function<int(int)> go = [&](int id) -> int {
     auto it = memo.find(id);
@@ -174,8 +181,8 @@ std::vector<int> Graph::substitute(const std::vector<int>& roots,
     int r;
     switch (nd.op) {
       case Op::Sym: {
-        auto sv = slot_values.find(nd.n);
-        r = (sv != slot_values.end()) ? cst(sv->second) : id;
+        auto sv = slot_nodes.find(nd.n);
+        r = (sv != slot_nodes.end()) ? sv->second : id;
         break;
       }
       case Op::Const: r = id; break;

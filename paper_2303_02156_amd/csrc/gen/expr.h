@@ -54,6 +54,10 @@ class Graph {
   // folding rules apply again, so e.g. x0 = 0 removes whole subtrees.
   std::vector<int> substitute(const std::vector<int>& roots,
                               const std::map<int, double>& slot_values);
+  // The same with input slots replaced by existing nodes (e.g. placeholder
+  // symbols by the expressions they stand for).
+  std::vector<int> substitute_nodes(const std::vector<int>& roots,
+                                    const std::map<int, int>& slot_nodes);
 
   const Node& node(int id) const { return nodes_[id]; }
   int size() const { return (int)nodes_.size(); }

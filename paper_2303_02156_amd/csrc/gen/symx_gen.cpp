@@ -45,8 +45,6 @@ struct EnergySpec {
   int n_in;           // total inputs
   int rest_slot;      // first slot of node-0 rest coordinates, or -1
   std::function<S(Graph&, const std::vector<S>&)> energy;
-  std::vector<int> row_nodes = {0};  // nodes with row functions (see header)
-  bool full = true;  // emit the full-Hessian variants (too large for the cubic tet)
 };
 
 Mat cols_minus_first(Graph& g, const std::vector<S>& in, int base, int n_nodes) {
@@ -182,40 +180,6 @@ S snh_density(const Mat& F, S mu, S lam) {
   return 0.5 * mu_ * (Ic - 3.0) + 0.5 * lam_ * pown(J - alpha, 2) - 0.5 * mu_ * log(Ic + 1.0);
 }
 
-// Jacobian d p / d xi of the quadratic tet interpolation p(xi) = sum_a N_a(xi)
-// p_a (App. A: the interpolation is written out and differentiated
-// symbolically with respect to the reference coordinates xi).  Node order:
-// corners 0-3, then edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3).
-Mat tet10_jacobian(Graph& g, const std::vector<S>& in, int base, const std::vector<S>& xi) {
-  S L0 = 1.0 - xi[0] - xi[1] - xi[2];
-  std::vector<S> L = {L0, xi[0], xi[1], xi[2]};
-  const int edge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
-  std::vector<S> N;
-  for (int c = 0; c < 4; ++c) N.push_back(L[c] * (2.0 * L[c] - 1.0));
-  for (const auto& e : edge) N.push_back(4.0 * L[e[0]] * L[e[1]]);
-  Mat Jm(3, 3, &g);
-  for (int i = 0; i < 3; ++i) {
-    S p = N[0] * in[base + i];
-    for (int a = 1; a < 10; ++a) p = p + N[a] * in[base + 3 * a + i];
-    for (int k = 0; k < 3; ++k) Jm(i, k) = S(&g, g.diff(p.id, xi[k].id));
-  }
-  return Jm;
-}
-
-// One quadrature point of the quadratic Stable Neo-Hookean tet (Eq. 12):
-// w |det J_X| psi(F), F = J_x J_X^-1.  Inputs: x (0..29), X (30..59), mu (60),
-// lambda (61), weight w (62), point xi (63..65).  The element energy is the
-// sum over the rule's points of this one function (Sec. 5.2, fixed value
-// summation), so only it is differentiated and compiled.
-S snh_tet10_qp(Graph& g, const std::vector<S>& in) {
-  std::vector<S> xi = {in[63], in[64], in[65]};
-  for (const S& v : xi) g.set_dof(v.id);  // differentiation symbols for the Jacobians
-  Mat Jx = tet10_jacobian(g, in, 0, xi);
-  Mat JX = tet10_jacobian(g, in, 30, xi);
-  Mat F = matmul(Jx, inv3(JX));
-  return in[62] * abs(det3(JX)) * snh_density(F, in[60], in[61]);
-}
-
 // Signed distance of node p (inputs 0..2) to the plane through t0, t1, t2
 // (3..11), positive on the side of N = (t1 - t0) x (t2 - t0).
 S point_plane_distance(Graph& g, const std::vector<S>& in) {
@@ -245,49 +209,6 @@ S ipc_point_plane_act(Graph& g, const std::vector<S>& in) {
   return in[13] - point_plane_distance(g, in);
 }
 
-// Jacobian of the cubic tet interpolation (as tet10_jacobian).  Node order:
-// corners 0-3; for edge k = (i, j) of (0,1), (1,2), (2,0), (0,3), (1,3), (2,3)
-// the nodes 4 + 2k (one third from i) and 5 + 2k (one third from j); the
-// centroid of the face opposite corner c is node 16 + c.  Shape functions:
-// L (3L - 1)(3L - 2) / 2 at a corner, 9/2 L_i L_j (3 L_i - 1) at the edge node
-// nearer i, 27 L_i L_j L_k at a face node.
-Mat tet20_jacobian(Graph& g, const std::vector<S>& in, int base, const std::vector<S>& xi) {
-  S L0 = 1.0 - xi[0] - xi[1] - xi[2];
-  std::vector<S> L = {L0, xi[0], xi[1], xi[2]};
-  const int edge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
-  std::vector<S> N;
-  for (int c = 0; c < 4; ++c) N.push_back(0.5 * L[c] * (3.0 * L[c] - 1.0) * (3.0 * L[c] - 2.0));
-  for (const auto& e : edge) {
-    N.push_back(4.5 * L[e[0]] * L[e[1]] * (3.0 * L[e[0]] - 1.0));
-    N.push_back(4.5 * L[e[0]] * L[e[1]] * (3.0 * L[e[1]] - 1.0));
-  }
-  for (int c = 0; c < 4; ++c) {
-    S p = 27.0 * L[c == 0 ? 1 : 0];
-    for (int k = (c == 0 ? 2 : 1); k < 4; ++k)
-      if (k != c) p = p * L[k];
-    N.push_back(p);
-  }
-  Mat Jm(3, 3, &g);
-  for (int i = 0; i < 3; ++i) {
-    S p = N[0] * in[base + i];
-    for (int a = 1; a < 20; ++a) p = p + N[a] * in[base + 3 * a + i];
-    for (int k = 0; k < 3; ++k) Jm(i, k) = S(&g, g.diff(p.id, xi[k].id));
-  }
-  return Jm;
-}
-
-// One quadrature point of the cubic Stable Neo-Hookean tet (Eq. 12): inputs
-// x (0..59), X (60..119), mu (120), lambda (121), weight (122), point xi
-// (123..125).
-S snh_tet20_qp(Graph& g, const std::vector<S>& in) {
-  std::vector<S> xi = {in[123], in[124], in[125]};
-  for (const S& v : xi) g.set_dof(v.id);
-  Mat Jx = tet20_jacobian(g, in, 0, xi);
-  Mat JX = tet20_jacobian(g, in, 60, xi);
-  Mat F = matmul(Jx, inv3(JX));
-  return in[122] * abs(det3(JX)) * snh_density(F, in[120], in[121]);
-}
-
 // Quadratic bending (Eq. 13, Bergou et al. 2006): E = k_b/2 x^T Q x with the
 // constant Q = c (K K^T) (x) I3; inputs are the per-node weights K_a and the
 // scale c = 3/(A0 + A1), precomputed from the rest hinge.
@@ -312,9 +233,69 @@ S inertia(Graph& g, const std::vector<S>& in) {
   return m / (2.0 * (dt * dt)) * dot(d, d);
 }
 
+// ---------------------------------------------------------------------------
+// Higher-order tets (App. A, Eq. 12).  Node order: corners 0-3; the edges are
+// k = (0,1), (1,2), (2,0), (0,3), (1,3), (2,3).  Quadratic: node 4 + k at the
+// middle of edge k, N = L_c (2 L_c - 1) at a corner and 4 L_i L_j on an edge.
+// Cubic: on edge k = (i, j) node 4 + 2k a third of the way from i and 5 + 2k a
+// third from j, N = 9/2 L_i L_j (3 L_i - 1) (resp. 3 L_j - 1); node 16 + c at
+// the centroid of the face opposite corner c, N = 27 L_i L_j L_k; corners
+// N = L (3L - 1)(3L - 2) / 2.  L = (1 - xi0 - xi1 - xi2, xi0, xi1, xi2).
+// ---------------------------------------------------------------------------
+std::vector<S> tet10_shape(const std::vector<S>& L) {
+  const int edge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+  std::vector<S> N;
+  for (int c = 0; c < 4; ++c) N.push_back(L[c] * (2.0 * L[c] - 1.0));
+  for (const auto& e : edge) N.push_back(4.0 * L[e[0]] * L[e[1]]);
+  return N;
+}
+
+std::vector<S> tet20_shape(const std::vector<S>& L) {
+  const int edge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+  std::vector<S> N;
+  for (int c = 0; c < 4; ++c) N.push_back(0.5 * L[c] * (3.0 * L[c] - 1.0) * (3.0 * L[c] - 2.0));
+  for (const auto& e : edge) {
+    N.push_back(4.5 * L[e[0]] * L[e[1]] * (3.0 * L[e[0]] - 1.0));
+    N.push_back(4.5 * L[e[0]] * L[e[1]] * (3.0 * L[e[1]] - 1.0));
+  }
+  for (int c = 0; c < 4; ++c) {
+    S p = 27.0 * L[c == 0 ? 1 : 0];
+    for (int k = (c == 0 ? 2 : 1); k < 4; ++k)
+      if (k != c) p = p * L[k];
+    N.push_back(p);
+  }
+  return N;
+}
+
+// One quadrature point of a higher-order Stable Neo-Hookean tet (Eq. 12):
+// E = c psi(F) with c = w |det J_X(xi)| and F = J_x J_X^-1 = sum_b x_b g_b^T,
+// g_b = J_X^-T dN_b/dxi (the shape functions differentiated symbolically with
+// respect to xi, as in App. A).  Inputs for K nodes: x (0..3K-1), X
+// (3K..6K-1), mu, lambda, weight w, point xi (6K..6K+5).  The element energy
+// is the sum over the rule's points of this one function (Sec. 5.2, fixed
+// value summation).
+//
+// F is linear in the positions, so the density is differentiated with respect
+// to the nine entries of F (placeholder symbols, replaced by F's expressions
+// afterwards) and the chain rule gives the element derivatives:
+//   dE/dx_{a,i} = c sum_j P_ij g_a[j],
+//   d2E/dx_{a,i} dx_{b,m} = sum_l M_a[i][m][l] g_b[l],
+//   M_a[i][m][l] = c sum_j D_{ij,ml} g_a[j],
+// with P = dpsi/dF and D = d2psi/dF2; M_a is formed once per row and shared
+// by the row's blocks.
+struct HighOrderSpec {
+  std::string name;
+  int n_nodes;
+  std::function<std::vector<S>(const std::vector<S>&)> shape;
+  std::vector<int> row_nodes;  // nodes with row functions (one per node class)
+  bool full;                   // also the full element E, g, H (quadratic only)
+};
+
 struct Generated {
   std::string hip, c, meta;
 };
+
+void emit_all(Graph& g, const std::vector<Function>& fns, Generated& out);
 
 void generate(const EnergySpec& spec, Generated& out) {
   Graph g;
@@ -325,15 +306,9 @@ void generate(const EnergySpec& spec, Generated& out) {
   S E = spec.energy(g, in);
   std::vector<int> grad(n_dof);
   for (int k = 0; k < n_dof; ++k) grad[k] = g.diff(E.id, in[k].id);
-  // the Hessian rows the variants use: all of them, or those of the row nodes
-  std::vector<int> hess(n_dof * n_dof, -1);
-  std::vector<char> need(n_dof, spec.full ? 1 : 0);
-  for (int r : spec.row_nodes)
-    for (int i = 0; i < 3; ++i) need[3 * r + i] = 1;
+  std::vector<int> hess(n_dof * n_dof);
   for (int k = 0; k < n_dof; ++k)
-    for (int l = 0; l < n_dof; ++l)
-      if ((need[k] || need[l]) && hess[k * n_dof + l] < 0)
-        hess[k * n_dof + l] = hess[l * n_dof + k] = g.diff(grad[std::min(k, l)], in[std::max(k, l)].id);
+    for (int l = k; l < n_dof; ++l) hess[k * n_dof + l] = hess[l * n_dof + k] = g.diff(grad[k], in[l].id);
 
   std::vector<Function> fns;
   auto add_fn = [&](const std::string& suffix, std::vector<int> outs) {
@@ -346,12 +321,10 @@ void generate(const EnergySpec& spec, Generated& out) {
   std::vector<int> Eg = {E.id};
   Eg.insert(Eg.end(), grad.begin(), grad.end());
   std::vector<int> EgH = Eg;
-  if (spec.full) EgH.insert(EgH.end(), hess.begin(), hess.end());
+  EgH.insert(EgH.end(), hess.begin(), hess.end());
   add_fn("_E", {E.id});
-  if (spec.full) {
-    add_fn("_Eg", Eg);
-    add_fn("_EgH", EgH);
-  }
+  add_fn("_Eg", Eg);
+  add_fn("_EgH", EgH);
 
   // node 0 at the origin
   std::map<int, double> zero;
@@ -360,28 +333,26 @@ void generate(const EnergySpec& spec, Generated& out) {
     if (spec.rest_slot >= 0) zero[spec.rest_slot + i] = 0.0;
   }
   add_fn("_s_E", g.substitute({E.id}, zero));
-  if (spec.full) add_fn("_s_EgH", g.substitute(EgH, zero));
-  for (int r : spec.row_nodes) {
-    const std::string R = "_row" + std::to_string(r);
-    std::vector<int> row_g(grad.begin() + 3 * r, grad.begin() + 3 * r + 3);
-    add_fn(R + "_g", g.substitute(row_g, zero));
-    if (r == 0) {
-      std::vector<int> row_gH = row_g;
-      for (int i = 0; i < 3; ++i)
-        for (int l = 0; l < n_dof; ++l) row_gH.push_back(hess[i * n_dof + l]);
-      add_fn(R + "_gH", g.substitute(row_gH, zero));
+  add_fn("_s_EgH", g.substitute(EgH, zero));
+  // row of node 0: gradient and Hessian row; gradient only; gradient and the
+  // off-diagonal blocks (the other nodes in ascending order), the diagonal
+  // block following from translation invariance (each Hessian row sums to
+  // zero over the nodes), so the kernel forms it as minus their sum
+  std::vector<int> row_g(grad.begin(), grad.begin() + 3);
+  add_fn("_row0_g", g.substitute(row_g, zero));
+  std::vector<int> row_gH = row_g, row_gHoff = row_g;
+  for (int i = 0; i < 3; ++i)
+    for (int l = 0; l < n_dof; ++l) {
+      row_gH.push_back(hess[i * n_dof + l]);
+      if (l >= 3) row_gHoff.push_back(hess[i * n_dof + l]);
     }
-    // gradient of node r and the off-diagonal blocks of its Hessian row (the
-    // other nodes in ascending order); the diagonal block follows from
-    // translation invariance (each Hessian row sums to zero over the nodes),
-    // so the kernel forms it as minus their sum
-    std::vector<int> row_gHoff = row_g;
-    for (int i = 0; i < 3; ++i)
-      for (int l = 0; l < n_dof; ++l)
-        if (l / 3 != r) row_gHoff.push_back(hess[(3 * r + i) * n_dof + l]);
-    add_fn(R + "_gHoff", g.substitute(row_gHoff, zero));
-  }
+  add_fn("_row0_gH", g.substitute(row_gH, zero));
+  add_fn("_row0_gHoff", g.substitute(row_gHoff, zero));
 
+  emit_all(g, fns, out);
+}
+
+void emit_all(Graph& g, const std::vector<Function>& fns, Generated& out) {
   for (const Function& f : fns) {
     Census ch, cc;
     out.hip += emit_hip(g, f, &ch);
@@ -394,6 +365,117 @@ void generate(const EnergySpec& spec, Generated& out) {
     std::printf("  %-24s in %3d out %4zu ops %6d\n", f.name.c_str(), f.n_in, f.outputs.size(),
                 ch.total());
   }
+}
+
+void generate_high_order(const HighOrderSpec& spec, Generated& out) {
+  Graph g;
+  const int K = spec.n_nodes, n_in = 6 * K + 6;
+  std::vector<S> in;
+  for (int k = 0; k < n_in; ++k) in.push_back(S(&g, g.sym(k)));
+  std::vector<S> xi = {in[6 * K + 3], in[6 * K + 4], in[6 * K + 5]};
+  for (const S& v : xi) g.set_dof(v.id);
+  const std::vector<S> N = spec.shape({1.0 - xi[0] - xi[1] - xi[2], xi[0], xi[1], xi[2]});
+  std::vector<std::vector<S>> dN(K, std::vector<S>(3));
+  for (int a = 0; a < K; ++a)
+    for (int k = 0; k < 3; ++k) dN[a][k] = S(&g, g.diff(N[a].id, xi[k].id));
+  Mat JX(3, 3, &g);
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      S p = in[3 * K + i] * dN[0][k];
+      for (int a = 1; a < K; ++a) p = p + in[3 * K + 3 * a + i] * dN[a][k];
+      JX(i, k) = p;
+    }
+  const Mat JXi = inv3(JX);
+  std::vector<std::vector<S>> G(K, std::vector<S>(3));
+  for (int a = 0; a < K; ++a)
+    for (int j = 0; j < 3; ++j)
+      G[a][j] = JXi(0, j) * dN[a][0] + JXi(1, j) * dN[a][1] + JXi(2, j) * dN[a][2];
+  Mat Jx(3, 3, &g);
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      S p = in[i] * dN[0][k];
+      for (int a = 1; a < K; ++a) p = p + in[3 * a + i] * dN[a][k];
+      Jx(i, k) = p;
+    }
+  const Mat F = matmul(Jx, JXi);
+  std::map<int, int> to_F;  // placeholder slot -> entry of F
+  Mat Fh(3, 3, &g);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      Fh(i, j) = S(&g, g.sym(n_in + 3 * i + j));
+      g.set_dof(Fh(i, j).id);
+      to_F[n_in + 3 * i + j] = F(i, j).id;
+    }
+  const S c = in[6 * K + 2] * abs(det3(JX));
+  const S psi = snh_density(Fh, in[6 * K], in[6 * K + 1]);
+  std::vector<int> dens = {psi.id};  // psi, P (9), D (81, symmetric)
+  for (int k = 0; k < 9; ++k) dens.push_back(g.diff(psi.id, Fh.v[k].id));
+  for (int k = 0; k < 9; ++k)
+    for (int l = 0; l < 9; ++l) dens.push_back(g.diff(dens[1 + std::min(k, l)], Fh.v[std::max(k, l)].id));
+  dens = g.substitute_nodes(dens, to_F);
+  auto P = [&](int i, int j) { return S(&g, dens[1 + 3 * i + j]); };
+  auto D = [&](int i, int j, int m, int l) { return S(&g, dens[10 + 9 * (3 * i + j) + 3 * m + l]); };
+  const S E = c * S(&g, dens[0]);
+  auto grad = [&](int a, int i) { return c * (P(i, 0) * G[a][0] + P(i, 1) * G[a][1] + P(i, 2) * G[a][2]); };
+  // Hessian row of node a: the 3 x 3 blocks (a, b), b in order
+  auto row_blocks = [&](int a, bool with_diag) {
+    std::vector<S> M(27);
+    for (int i = 0; i < 3; ++i)
+      for (int m = 0; m < 3; ++m)
+        for (int l = 0; l < 3; ++l)
+          M[9 * i + 3 * m + l] = c * (D(i, 0, m, l) * G[a][0] + D(i, 1, m, l) * G[a][1] +
+                                      D(i, 2, m, l) * G[a][2]);
+    std::vector<int> ids;
+    for (int i = 0; i < 3; ++i)
+      for (int b = 0; b < K; ++b) {
+        if (b == a && !with_diag) continue;
+        for (int m = 0; m < 3; ++m)
+          ids.push_back((M[9 * i + 3 * m] * G[b][0] + M[9 * i + 3 * m + 1] * G[b][1] +
+                         M[9 * i + 3 * m + 2] * G[b][2]).id);
+      }
+    return ids;
+  };
+
+  std::vector<Function> fns;
+  auto add_fn = [&](const std::string& suffix, std::vector<int> outs) {
+    Function f;
+    f.name = spec.name + suffix;
+    f.n_in = n_in;
+    f.outputs = std::move(outs);
+    fns.push_back(f);
+  };
+  // node 0 at the origin
+  std::map<int, double> zero;
+  for (int i = 0; i < 3; ++i) zero[i] = zero[3 * K + i] = 0.0;
+  add_fn("_E", {E.id});
+  add_fn("_s_E", g.substitute({E.id}, zero));
+  if (spec.full) {
+    std::vector<int> EgH = {E.id};
+    for (int a = 0; a < K; ++a)
+      for (int i = 0; i < 3; ++i) EgH.push_back(grad(a, i).id);
+    // full Hessian, row-major (a, i) x (b, m)
+    std::vector<std::vector<int>> rows(K);
+    for (int a = 0; a < K; ++a) rows[a] = row_blocks(a, true);
+    for (int a = 0; a < K; ++a)
+      for (int i = 0; i < 3; ++i)
+        EgH.insert(EgH.end(), rows[a].begin() + 3 * K * i, rows[a].begin() + 3 * K * (i + 1));
+    add_fn("_EgH", EgH);
+    add_fn("_s_EgH", g.substitute(EgH, zero));
+  }
+  for (int r : spec.row_nodes) {
+    const std::string R = "_row" + std::to_string(r);
+    std::vector<int> row_g;
+    for (int i = 0; i < 3; ++i) row_g.push_back(grad(r, i).id);
+    add_fn(R + "_g", g.substitute(row_g, zero));
+    // gradient of node r and the off-diagonal blocks of its Hessian row (the
+    // other nodes in ascending order); the kernels form the diagonal block as
+    // minus their sum (translation invariance)
+    std::vector<int> row_gHoff = row_g;
+    const std::vector<int> blocks = row_blocks(r, false);
+    row_gHoff.insert(row_gHoff.end(), blocks.begin(), blocks.end());
+    add_fn(R + "_gHoff", g.substitute(row_gHoff, zero));
+  }
+  emit_all(g, fns, out);
 }
 
 bool write_file(const std::string& path, const std::string& text) {
@@ -420,8 +502,6 @@ int main(int argc, char** argv) {
       {"stvk_tet4", 4, 26, 12, stvk_tet4},
       {"fcr_tet4", 4, 35, 12, fcr_tet4},
       {"arap_tet4", 4, 35, 12, arap_tet4},
-      {"snh_tet10", 10, 66, 30, snh_tet10_qp, {0, 4}},
-      {"snh_tet20", 20, 126, 60, snh_tet20_qp, {0, 4, 19}, false},
       {"ipc_point_plane", 4, 14, -1, ipc_point_plane},
       {"ipc_point_plane_act", 4, 14, -1, ipc_point_plane_act},
   };
@@ -438,6 +518,14 @@ int main(int argc, char** argv) {
   for (const auto& s : specs) {
     std::printf("%s\n", s.name.c_str());
     generate(s, all);
+  }
+  const std::vector<HighOrderSpec> high_order = {
+      {"snh_tet10", 10, tet10_shape, {0, 4}, true},
+      {"snh_tet20", 20, tet20_shape, {0, 4, 19}, false},
+  };
+  for (const auto& s : high_order) {
+    std::printf("%s\n", s.name.c_str());
+    generate_high_order(s, all);
   }
   if (!write_file(dir + "/symx_generated.h", all.hip) ||
       !write_file(dir + "/symx_generated_cpu.c", all.c) ||
