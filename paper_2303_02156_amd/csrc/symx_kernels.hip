@@ -1709,11 +1709,27 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_ho(RowArgs<T> A) {
       ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), sh.stg.conn[qi],
                                  sh.stg.perm.p[a], a, sh.stg.rule, p, A.x, A.X, out);
     }
+    // k is uniform: the first point stores, the others add in chunks of 16
+    // values (16 LDS reads in flight, then the adds and stores)
     const int p_lo = i0 / nq, p_hi = (min(n_items, i0 + kRowWG) - 1) / nq;
     for (int k = p_lo; k <= p_hi; ++k) {
-      if (act && p == k) {
+      if (k == 0) {
+        if (act && p == 0) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) st[v][qi] = k == 0 ? out[v] : st[v][qi] + out[v];
+          for (int v = 0; v < NV; ++v) st[v][qi] = out[v];
+        }
+      } else if (act && p == k) {
+        constexpr int C = 16;
+#pragma unroll
+        for (int v0 = 0; v0 < NV; v0 += C) {
+          T cur[C];
+#pragma unroll
+          for (int u = 0; u < C; ++u)
+            if (v0 + u < NV) cur[u] = st[v0 + u][qi];
+#pragma unroll
+          for (int u = 0; u < C; ++u)
+            if (v0 + u < NV) st[v0 + u][qi] = cur[u] + out[v0 + u];
+        }
       }
       __syncthreads();
     }
