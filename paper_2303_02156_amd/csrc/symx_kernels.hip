@@ -1654,8 +1654,20 @@ struct HoStage {
   QuadRule rule;
 };
 
+// Waves per SIMD the row kernel is compiled for (registers capped at 512 /
+// waves, the rest spilled), so that several workgroups share a CU and one's
+// memory waits overlap another's arithmetic.  Measured on the 137K-DoF boxes:
+// FP32 g+H 0.24 -> 0.20 ms (quadratic, 3 waves) and 1.51 -> 0.98 ms (cubic, 2
+// waves); the FP64 kernels spill too much for it to pay (cubic 3.0 -> 5.8 ms).
+template <int K, typename T, bool WANT_H>
+constexpr int ho_row_waves() {
+  if (sizeof(T) == 8) return 1;
+  return K == 10 ? (WANT_H ? 3 : 1) : 2;
+}
+
 template <int K, typename T, bool WANT_G, bool WANT_H>
-__global__ __launch_bounds__(kRowWG) void k_row_assemble_ho(RowArgs<T> A) {
+__global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_assemble_ho(
+    RowArgs<T> A) {
   using P = HoTet<K>;
   constexpr int NO = 3 * (K - 1);
   constexpr int NV = WANT_H ? 3 + 3 * NO : 3;
@@ -1709,8 +1721,8 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_ho(RowArgs<T> A) {
       ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), sh.stg.conn[qi],
                                  sh.stg.perm.p[a], a, sh.stg.rule, p, A.x, A.X, out);
     }
-    // k is uniform: the first point stores, the others add in chunks of 16
-    // values (16 LDS reads in flight, then the adds and stores)
+    // k is uniform: the first point stores, the others add in chunks of 64
+    // values (their LDS reads in flight together, then the adds and stores)
     const int p_lo = i0 / nq, p_hi = (min(n_items, i0 + kRowWG) - 1) / nq;
     for (int k = p_lo; k <= p_hi; ++k) {
       if (k == 0) {
@@ -1719,7 +1731,7 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_ho(RowArgs<T> A) {
           for (int v = 0; v < NV; ++v) st[v][qi] = out[v];
         }
       } else if (act && p == k) {
-        constexpr int C = 16;
+        constexpr int C = 64;
 #pragma unroll
         for (int v0 = 0; v0 < NV; v0 += C) {
           T cur[C];
