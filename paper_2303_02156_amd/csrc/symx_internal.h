@@ -266,6 +266,8 @@ struct Topology {
   int* diag_pos = nullptr;          // N: index of block (i,i)
   int* inc_ptr = nullptr;           // N+1
   uint32_t* inc_code = nullptr;     // n_inc
+  int* inc_nodes = nullptr;         // higher-order tets: n_inc x k node ids of the
+                                    // incidence's element in its node's relabelled order
   int* batch_row = nullptr;         // n_batch+1
   uint32_t* blk_info = nullptr;     // nnzb: off-diagonal contribution list (start << 8 | count)
   uint16_t* centry = nullptr;       // contribution entries (incidence << 2 | node b),
@@ -393,6 +395,7 @@ struct Mesh {
   const int* diag_pos = nullptr;
   const int* inc_ptr = nullptr;
   const uint32_t* inc_code = nullptr;
+  const int* inc_nodes = nullptr;
   const int* batch_row = nullptr;
   const uint32_t* blk_info = nullptr;
   const uint16_t* centry = nullptr;

@@ -1098,6 +1098,7 @@ struct RowArgs {
   double* g;             // N x 3
   const T* inc_rows;     // projected path: incidence records (kIncRec per incidence)
   int* nonfinite;
+  const int* inc_nodes;  // higher-order tets: relabelled element node ids per incidence
 };
 
 // Gradient row of one incidence (element e seen from its local node a).
@@ -1484,19 +1485,18 @@ struct HoTet<20> {
   }
 };
 
-// Inputs 0..6K+1 of the per-point function for element e, whose node ids
-// are c[0..K), with its nodes in the order perm (local indices): positions
-// and rest positions relative to the first node (a corner), then mu and
-// lambda.  All positions are loaded before they are used, so the loads are
-// in flight together.
+// Inputs 0..6K+1 of the per-point function for element e whose node ids, in
+// the evaluation order, are ids[0..K): positions and rest positions relative
+// to the first node (a corner), then mu and lambda.  All positions are loaded
+// before they are used, so the loads are in flight together.
 template <int K, typename T>
-__device__ __forceinline__ void fill_ho(const SetDev& S, int64_t e, const int* c,
-                                        const int8_t* perm, const double* __restrict__ x,
-                                        const double* __restrict__ X, T* in) {
+__device__ __forceinline__ void fill_ho_ids(const SetDev& S, int64_t e, const int* ids,
+                                            const double* __restrict__ x,
+                                            const double* __restrict__ X, T* in) {
   double px[3 * K], pX[3 * K];
 #pragma unroll
   for (int b = 0; b < K; ++b) {
-    const int64_t n = c[perm[b]];
+    const int64_t n = ids[b];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       px[3 * b + i] = x[3 * n + i];
@@ -1517,6 +1517,17 @@ __device__ __forceinline__ void fill_ho(const SetDev& S, int64_t e, const int* c
   const T* P = prm_ptr<T>(S);
   in[6 * K] = ld_prm(P, S.prm_stride, e, 0);
   in[6 * K + 1] = ld_prm(P, S.prm_stride, e, 1);
+}
+
+// The same for the element's node ids c[0..K) taken in the order perm.
+template <int K, typename T>
+__device__ __forceinline__ void fill_ho(const SetDev& S, int64_t e, const int* c,
+                                        const int8_t* perm, const double* __restrict__ x,
+                                        const double* __restrict__ X, T* in) {
+  int ids[K];
+#pragma unroll
+  for (int b = 0; b < K; ++b) ids[b] = c[perm[b]];
+  fill_ho_ids<K, T>(S, e, ids, x, X, in);
 }
 
 // Inputs 6K+2..6K+5: weight and reference coordinates of quadrature point q
@@ -1564,16 +1575,16 @@ __global__ __launch_bounds__(256) void k_energy_ho(SetDev S, const double* __res
   }
 }
 
-// Row of local node a of element e (node ids c, relabelling perm of node a)
-// at point q of rule r: out[0..2] gradient, out[3 + 3(K-1) i + 3 j + k] the
+// Row of local node a of element e (node ids in a's relabelled order) at
+// point q of rule r: out[0..2] gradient, out[3 + 3(K-1) i + 3 j + k] the
 // off-diagonal block entries of the K - 1 other nodes in the row function's
 // order (WANT_H), or the gradient only.
 template <int K, typename T, bool WANT_H>
-__device__ __forceinline__ void ho_row_point(const SetDev& S, int64_t e, const int* c,
-                                             const int8_t* perm, int a, const QuadRule& r, int q,
-                                             const double* x, const double* X, T* out) {
+__device__ __forceinline__ void ho_row_point(const SetDev& S, int64_t e, const int* ids, int a,
+                                             const QuadRule& r, int q, const double* x,
+                                             const double* X, T* out) {
   T in[6 * K + 6];
-  fill_ho<K, T>(S, e, c, perm, x, X, in);
+  fill_ho_ids<K, T>(S, e, ids, x, X, in);
   set_point<K, T>(r, q, in);
   HoTet<K>::template row<T, WANT_H>(a, in, out);
 }
@@ -1599,10 +1610,12 @@ __global__ __launch_bounds__(64) void k_elem_eval_ho(SetDev S, const double* __r
     T acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = T(0);
+    int ids[K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) ids[b] = S.conn_ho[(int64_t)K * e + perm[b]];
     for (int q = 0; q < HoTet<K>::kPts; ++q) {
       T out[NV];
-      ho_row_point<K, T, true>(S, e, S.conn_ho + (int64_t)K * e, perm, a, HoTet<K>::rule(), q,
-                               x, X, out);
+      ho_row_point<K, T, true>(S, e, ids, a, HoTet<K>::rule(), q, x, X, out);
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] += out[v];
     }
@@ -1641,16 +1654,17 @@ __global__ __launch_bounds__(64) void k_elem_eval_ho(SetDev S, const double* __r
 // HoTet<K>::kCap incidences.  Step 1 runs the evaluation items (point p,
 // incidence qi) = (item / nq, item % nq) in passes of kRowWG lanes; each pass
 // adds its items into LDS one point at a time, so every incidence sums its
-// points in point order.  The batch's incidence codes and element node ids,
-// the relabelling tables and the rule are staged in LDS first (in the space
-// the block sums use later), so an item's position loads depend on LDS reads
-// only.  Contribution entries are (incidence << kShift) | j, j the other
-// node's index in the row function's order.  WANT_H = false: gradient only.
+// points in point order.  The batch's incidence codes, the incidences'
+// relabelled element node ids (contiguous per batch) and the rule are staged
+// in LDS first (in the space the block sums use later), so an item's position
+// loads depend on LDS reads only; the contribution entries are staged too,
+// and the block metadata of steps 2 and 5 is loaded before the evaluation.
+// Contribution entries are (incidence << kShift) | j, j the other node's
+// index in the row function's order.  WANT_H = false: gradient only.
 template <int K>
 struct HoStage {
   uint32_t code[HoTet<K>::kCap];
-  int conn[HoTet<K>::kCap][K];
-  HoPerm<K> perm;
+  int ids[HoTet<K>::kCap][K];
   QuadRule rule;
 };
 
@@ -1677,6 +1691,7 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
     HoStage<K> stg;
   } sh;
   auto& blk = sh.blk;
+  __shared__ uint16_t s_ce[WANT_H ? P::kCap * (K - 1) : 1];
   __shared__ uint16_t s_blk[kRowWG + 1];
   __shared__ uint16_t s_inc[kRowWG + 1];
   const int t = threadIdx.x;
@@ -1692,21 +1707,30 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
   __syncthreads();
   const int nq = s_inc[nrows];
   const int np = s_blk[nrows];
+  // block metadata for steps 2 and 5, in flight during the evaluation
+  int r = 0, col = 0;
+  uint32_t info = 0;
+  if (WANT_H && t < np) {
+    while (s_blk[r + 1] <= t) ++r;
+    col = A.col_idx[p0 + t];
+    info = A.blk_info[p0 + t];
+  }
   // step 0: staging
   for (int j = t; j < nq; j += kRowWG) sh.stg.code[j] = A.inc_code[q0 + j];
-  for (int j = t; j < K * K; j += kRowWG) sh.stg.perm.p[j / K][j % K] = P::perm(j / K)[j % K];
+  for (int j = t; j < nq * K; j += kRowWG)
+    sh.stg.ids[j / K][j % K] = A.inc_nodes[(int64_t)q0 * K + j];
   for (int j = t; j < 4 * P::kPts; j += kRowWG) {
     const int q = j >> 2, c = j & 3;
     if (c == 0) sh.stg.rule.w[q] = P::rule().w[q];
     else sh.stg.rule.xi[q][c - 1] = P::rule().xi[q][c - 1];
   }
-  __syncthreads();
-  for (int j = t; j < nq * K; j += kRowWG) {
-    const int qi = j / K, bb = j - qi * K;
-    const uint32_t code = sh.stg.code[qi];
-    sh.stg.conn[qi][bb] = A.sets.s[inc_set(code)].conn_ho[(int64_t)K * inc_elem(code) + bb];
+  if (WANT_H) {
+    const int e0 = A.batch_entry[b];
+    for (int j = t; j < (K - 1) * nq; j += kRowWG) s_ce[j] = A.centry[e0 + j];
   }
   __syncthreads();
+  uint8_t fixed_rc = 0;  // Dirichlet flags of the block's row and column
+  if (WANT_H && t < np && A.fixed) fixed_rc = A.fixed[r0 + r] | A.fixed[col];
   // step 1: evaluation passes
   const int n_items = nq * P::kPts;
   for (int i0 = 0; i0 < n_items; i0 += kRowWG) {
@@ -1717,9 +1741,8 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
     T out[NV];
     if (act) {
       const uint32_t code = sh.stg.code[qi];
-      const int a = inc_local(code);
-      ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), sh.stg.conn[qi],
-                                 sh.stg.perm.p[a], a, sh.stg.rule, p, A.x, A.X, out);
+      ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), sh.stg.ids[qi],
+                                 inc_local(code), sh.stg.rule, p, A.x, A.X, out);
     }
     // k is uniform: the first point stores, the others add in chunks of 64
     // values (their LDS reads in flight together, then the adds and stores)
@@ -1746,19 +1769,14 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
       __syncthreads();
     }
   }
-  int r = 0, col = 0;
-  bool diag = false;
+  const bool diag = WANT_H && t < np && col == r0 + r;
   T acc[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = T(0);
   if constexpr (WANT_H) {
     // step 2: off-diagonal blocks from their contribution lists
     if (t < np) {
-      while (s_blk[r + 1] <= t) ++r;
-      col = A.col_idx[p0 + t];
-      diag = (col == r0 + r);
-      const uint32_t info = A.blk_info[p0 + t];
-      const uint16_t* ce = A.centry + A.batch_entry[b] + (info >> 8);
+      const uint16_t* ce = s_ce + (info >> 8);
       const int cnt = int(info & 0xFFu);
       for (int j = 0; j < cnt; ++j) {
         const uint32_t wv = ce[j];
@@ -1808,7 +1826,7 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] = blk[WANT_H ? c : 0][t];
     }
-    if (A.fixed && (A.fixed[row] | A.fixed[col])) {
+    if (fixed_rc) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] = (diag && (c % 4) == 0) ? T(1) : T(0);
     }
@@ -2641,6 +2659,7 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   A.dinv = (T*)dinv;
   A.nonfinite = m.nonfinite;
   A.inc_rows = (const T*)inc_rows;
+  A.inc_nodes = m.inc_nodes;
   if ((want_g && !g_out) || (!want_g && !want_H)) {
     set_error("row assembly without an output");
     return SYMX_ERR_INVALID_ARG;

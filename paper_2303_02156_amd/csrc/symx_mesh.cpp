@@ -539,6 +539,22 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
   TRY(upload(pool, stream, &t.diag_pos, diag.data(), N, &nb));
   TRY(upload(pool, stream, &t.inc_ptr, inc_ptr32.data(), N + 1, &nb));
   TRY(upload(pool, stream, &t.inc_code, code.data(), t.n_inc, &nb));
+  if (t.ho) {
+    // each incidence's element node ids in the relabelled order of its node,
+    // so that the row kernel reads them contiguously per batch
+    const int K = t.ho;
+    uvector<int32_t> nodes(t.n_inc * K);
+    parallel_chunks(t.n_inc, 65536, [&](int64_t q0, int64_t q1) {
+      for (int64_t q = q0; q < q1; ++q) {
+        const TopoSet& s = t.sets[inc_set(code[q])];
+        const int a = inc_local(code[q]);
+        const int8_t* perm = K == 10 ? kTet10Perm.p[a] : kTet20Perm.p[a];
+        const int32_t* c = s.conn.data() + (int64_t)K * inc_elem(code[q]);
+        for (int b = 0; b < K; ++b) nodes[q * K + b] = c[perm[b]];
+      }
+    });
+    TRY(upload(pool, stream, &t.inc_nodes, nodes.data(), nodes.size(), &nb));
+  }
   t.h_inc_code = std::move(code);
   TRY(upload(pool, stream, &t.batch_row, batch.data(), batch.size(), &nb));
   TRY(upload(pool, stream, &t.blk_info, blk_info.data(), blk_info.size(), &nb));
@@ -597,6 +613,7 @@ static void attach_topology(Mesh& m, std::shared_ptr<Topology> tp) {
   m.diag_pos = t.diag_pos;
   m.inc_ptr = t.inc_ptr;
   m.inc_code = t.inc_code;
+  m.inc_nodes = t.inc_nodes;
   m.batch_row = t.batch_row;
   m.blk_info = t.blk_info;
   m.centry = t.centry;

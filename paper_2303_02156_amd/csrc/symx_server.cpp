@@ -76,6 +76,7 @@ size_t estimate_request_bytes(const symx_mesh_desc& d, int precision, bool proje
     inc += (size_t)d.energies[s].n_elem * k;
     elems += (size_t)d.energies[s].n_elem;
     conn += (size_t)d.energies[s].n_elem * 4 * (k < 4 ? 4 : k);
+    if (k >= 10) conn += (size_t)d.energies[s].n_elem * k * k * 4;  // relabelled incidence nodes
     if (kind_has_rotation(d.energies[s].kind)) rot_elems += (size_t)d.energies[s].n_elem;
   }
   const size_t vbytes = precision == SYMX_F64 ? 8 : 4;
