@@ -1442,13 +1442,15 @@ __constant__ QuadRule c_rule10 = make_rule(10);
 __constant__ QuadRule c_rule20 = make_rule(20);
 
 // Per-order data: quadrature points, incidences per row batch, the shift of
-// the incidence in a contribution entry, and the generated functions (one
-// row function per node class: corner, edge node, face node).
+// the incidence in a contribution entry, the number of LDS accumulators the
+// row kernel sums the points into (two for the 11-point rule: half the
+// rounds), and the generated functions (one row function per node class:
+// corner, edge node, face node).
 template <int K>
 struct HoTet;
 template <>
 struct HoTet<10> {
-  static constexpr int kPts = 4, kCap = kQuadInc, kShift = 4;
+  static constexpr int kPts = 4, kCap = kQuadInc, kShift = 4, kAcc = 1;
   __device__ static const int8_t* perm(int a) { return c_perm10.p[a]; }
   __device__ static const QuadRule& rule() { return c_rule10; }
   template <typename T>
@@ -1466,7 +1468,7 @@ struct HoTet<10> {
 };
 template <>
 struct HoTet<20> {
-  static constexpr int kPts = 11, kCap = kCubicInc, kShift = 5;
+  static constexpr int kPts = 11, kCap = kCubicInc, kShift = 5, kAcc = 2;
   __device__ static const int8_t* perm(int a) { return c_perm20.p[a]; }
   __device__ static const QuadRule& rule() { return c_rule20; }
   template <typename T>
@@ -1653,8 +1655,9 @@ __global__ __launch_bounds__(64) void k_elem_eval_ho(SetDev S, const double* __r
 // with the evaluation split over quadrature points).  A batch holds at most
 // HoTet<K>::kCap incidences.  Step 1 runs the evaluation items (point p,
 // incidence qi) = (item / nq, item % nq) in passes of kRowWG lanes; each pass
-// adds its items into LDS one point at a time, so every incidence sums its
-// points in point order.  The batch's incidence codes, the incidences'
+// adds its items into LDS one point at a time, or for the cubic rule two at a
+// time (even points into one accumulator, odd points into another), so every
+// incidence sums its points (its even and its odd points) in point order.  The batch's incidence codes, the incidences'
 // relabelled element node ids (contiguous per batch) and the rule are staged
 // in LDS first (in the space the block sums use later), so an item's position
 // loads depend on LDS reads only; the contribution entries are staged too,
@@ -1686,6 +1689,7 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
   constexpr int NO = 3 * (K - 1);
   constexpr int NV = WANT_H ? 3 + 3 * NO : 3;
   __shared__ T st[NV][P::kCap];
+  __shared__ T st2[P::kAcc == 2 ? NV : 1][P::kAcc == 2 ? P::kCap : 1];  // odd points
   __shared__ union {
     T blk[WANT_H ? 9 : 1][kRowWG];
     HoStage<K> stg;
@@ -1744,30 +1748,42 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
       ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), sh.stg.ids[qi],
                                  inc_local(code), sh.stg.rule, p, A.x, A.X, out);
     }
-    // k is uniform: the first point stores, the others add in chunks of 64
-    // values (their LDS reads in flight together, then the adds and stores)
-    const int p_lo = i0 / nq, p_hi = (min(n_items, i0 + kRowWG) - 1) / nq;
-    for (int k = p_lo; k <= p_hi; ++k) {
-      if (k == 0) {
-        if (act && p == 0) {
+    // With two accumulators, even points accumulate in st and odd points in
+    // st2, a pair of points per round.  Round k is uniform: the first round
+    // stores, the others add in chunks of 64 values (their LDS reads in
+    // flight together, then the adds and stores).
+    const int k_lo = (i0 / nq) / P::kAcc, k_hi = ((min(n_items, i0 + kRowWG) - 1) / nq) / P::kAcc;
+    T(*acc_st)[P::kCap] = st;
+    if constexpr (P::kAcc == 2) acc_st = (p & 1) ? st2 : st;
+    for (int k = k_lo; k <= k_hi; ++k) {
+      if (act && p / P::kAcc == k) {
+        if (k == 0) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) st[v][qi] = out[v];
-        }
-      } else if (act && p == k) {
-        constexpr int C = 64;
+          for (int v = 0; v < NV; ++v) acc_st[v][qi] = out[v];
+        } else {
+          constexpr int C = 64;
 #pragma unroll
-        for (int v0 = 0; v0 < NV; v0 += C) {
-          T cur[C];
+          for (int v0 = 0; v0 < NV; v0 += C) {
+            T cur[C];
 #pragma unroll
-          for (int u = 0; u < C; ++u)
-            if (v0 + u < NV) cur[u] = st[v0 + u][qi];
+            for (int u = 0; u < C; ++u)
+              if (v0 + u < NV) cur[u] = acc_st[v0 + u][qi];
 #pragma unroll
-          for (int u = 0; u < C; ++u)
-            if (v0 + u < NV) st[v0 + u][qi] = cur[u] + out[v0 + u];
+            for (int u = 0; u < C; ++u)
+              if (v0 + u < NV) acc_st[v0 + u][qi] = cur[u] + out[v0 + u];
+          }
         }
       }
       __syncthreads();
     }
+  }
+  if constexpr (P::kAcc == 2) {
+    // sum of the even and the odd points
+    for (int j = t; j < NV * nq; j += kRowWG) {
+      const int v = j / nq, qi = j - v * nq;
+      st[v][qi] += st2[v][qi];
+    }
+    __syncthreads();
   }
   const bool diag = WANT_H && t < np && col == r0 + r;
   T acc[9];
