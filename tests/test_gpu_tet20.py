@@ -184,3 +184,18 @@ def test_tet20_rejections(symx):
                          np.zeros((N + other.n_nodes, 3)))
         with pytest.raises(symx.SymxError, match="INVALID_ARG"):
             symx.Mesh(mixed)
+
+
+def test_tet20_crowded_node_rejected(symx):
+    """A row batch holds at most 32 cubic incidences: a node shared by 33
+    elements is an argument error that names the limit."""
+    n = 33
+    _, X4 = sg.random_tets(n, 86, inverted_frac=0.0)
+    X4 = X4 - X4[:, :1]                                  # corner 0 of every element at 0
+    X = _cubic_nodes(X4).reshape(-1, 3)
+    conn = np.arange(20 * n, dtype=np.int32).reshape(n, 20)
+    conn[:, 0] = 0                                       # corner 0 shared by all
+    es = sg.EnergySet(sg.SNH_TET20, conn, young=1e5, poisson=0.4)
+    scene = sg.Scene("fan20", X, [es], np.zeros(X.shape[0], np.uint8), X.copy(), np.zeros_like(X))
+    with pytest.raises(symx.SymxError, match="INVALID_ARG.*more than 32 elements"):
+        symx.Mesh(scene)
