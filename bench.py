@@ -529,9 +529,14 @@ def contact_bench(symx, torch, n=32, reps=10):
                 ms.append(a.elapsed_time(b))
         return statistics.median(ms)
     t_plain = timed()
-    t0 = time.perf_counter()
-    mesh.set_contacts(cl.tuples, cl.kc, cl.dhat)
-    set_ms = (time.perf_counter() - t0) * 1e3
+    # the candidate list is handed over again at every time step (dynamic
+    # topology): time repeated calls after two warm-up calls
+    set_ms_all = []
+    for r in range(7):
+        t0 = time.perf_counter()
+        mesh.set_contacts(cl.tuples, cl.kc, cl.dhat)
+        set_ms_all.append((time.perf_counter() - t0) * 1e3)
+    set_ms = statistics.median(set_ms_all[2:])
     t_contact = timed()
     mesh.profile(True)
     for _ in range(3):
@@ -551,7 +556,8 @@ def contact_bench(symx, torch, n=32, reps=10):
                        f"{cl.tuples.shape[0]} point-plane candidates (k_c {cl.kc}, d_hat "
                        f"{cl.dhat}), upper block moving down at 0.05 m/s, dt 0.01",
            "candidates": int(cl.tuples.shape[0]), "contact_blocks": int(cview.nnzb),
-           "set_contacts_ms_host": round(set_ms, 2),
+           "set_contacts_ms": round(set_ms, 3),
+           "set_contacts_first_call_ms": round(set_ms_all[0], 2),
            "assembly_ms_f32_without_contacts": round(t_plain, 4),
            "assembly_ms_f32_with_contacts": round(t_contact, 4),
            "contact_kernel_avg_ms": kt,

@@ -259,7 +259,8 @@ symx_status symx_mesh_update_rotations(symx_mesh mesh, const double* x_dev);
  * the previous one and n = 0 removes all contacts: as in the paper's dynamic
  * topology, the caller updates the list (e.g. from a proximity query at each
  * time step) and the couplings follow.  They form a second block-sparse matrix
- * beside the mesh's pattern (rebuilt here on the host when the list changes);
+ * beside the mesh's pattern (rebuilt on the device when the list changes;
+ * a list no longer than the one its buffers were sized for reuses them);
  * assembly, energies, the PCG and the Newton step include it.  With
  * projection on, contact element Hessians take the nearest-PSD projection.
  * Node ids in range and distinct within a tuple; k_c, d_hat > 0; not on

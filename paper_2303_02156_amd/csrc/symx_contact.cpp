@@ -1,6 +1,6 @@
-// Candidate contacts of the conditional point-plane barrier: the host build of
-// the contact block pattern and of the contribution lists that the device
-// assembly sums in candidate order.
+// Candidate contacts of the conditional point-plane barrier: validation of the
+// candidate list and the device arrays of the contact pattern (built on the
+// device, symx_contact_pattern.hip) and of the per-evaluation compaction.
 //
 // The mesh's own pattern is static; contacts appear and disappear with the
 // candidate list (the dynamic topology of Sec. 5.2).  Following the dual
@@ -21,9 +21,12 @@ namespace symxi {
 void contacts_free(Mesh& m) {
   Contacts* c = m.contacts;
   if (!c) return;
-  void* dev[] = {c->tuples, c->row_ptr, c->col_idx, c->blk_row, c->blk_ptr, c->blk_src,
-                 c->gnode,  c->gptr,    c->gsrc,    c->gdiag,   c->vals32,  c->vals64,
-                 c->flag,   c->slot,    c->act,     c->chunk_count, c->n_active, c->eval};
+  void* dev[] = {c->tuples,    c->row_ptr,   c->col_idx, c->blk_row, c->blk_ptr,
+                 c->blk_src,   c->gnode,     c->gptr,    c->gsrc,    c->gdiag,
+                 c->vals32,    c->vals64,    c->flag,    c->slot,    c->act,
+                 c->chunk_count, c->n_active, c->eval,   c->bkey_in, c->bkey,
+                 c->bval_in,   c->gkey_in,   c->gkey,    c->gval_in, c->head,
+                 c->idx,       c->row_count, c->counts,  c->sort_temp};
   for (void* p : dev) dev_free(m.pool, p);
   delete c;
   m.contacts = nullptr;
@@ -76,72 +79,40 @@ symx_status contacts_set(Mesh& m, int64_t n, const int32_t* tuples, double kc, d
     (void)hipStreamSynchronize(m.stream);
   else
     (void)hipDeviceSynchronize();
-  contacts_free(m);
-  if (n == 0) return SYMX_OK;
-  auto* c = new Contacts();
-  m.contacts = c;
+  if (n == 0) {
+    contacts_free(m);
+    return SYMX_OK;
+  }
+  // a list that fits the buffers of the previous one reuses them
+  const bool reuse = m.contacts && m.contacts->cap >= n;
+  if (!reuse) {
+    contacts_free(m);
+    m.contacts = new Contacts();
+  }
+  Contacts* c = m.contacts;
   c->n = n;
   c->kc = kc;
   c->dhat = dhat;
-  // blocks: (row, col, candidate * 16 + 4 a + b) sorted by (row, col, source)
-  struct Ent {
-    int32_t row, col, src;
+  auto build = [&]() -> symx_status {
+    if (!reuse) {
+      TRY_STATUS(put<int>(m, &c->tuples, nullptr, 4 * n));
+      TRY_STATUS(put<uint8_t>(m, &c->flag, nullptr, n));
+      TRY_STATUS(put<int>(m, &c->slot, nullptr, n));
+      TRY_STATUS(put<int>(m, &c->act, nullptr, n));
+      TRY_STATUS(
+          put<int>(m, &c->chunk_count, nullptr, (n + kContactChunk - 1) / kContactChunk + 1));
+      TRY_STATUS(put<int>(m, &c->n_active, nullptr, 1));
+      TRY_STATUS(contacts_reserve_pattern(m, *c, n));
+      c->cap = n;
+    }
+    TRY_STATUS(hip_check(hipMemcpyAsync(c->tuples, tuples, 4 * n * sizeof(int32_t),
+                                        hipMemcpyHostToDevice, m.stream),
+                         "hipMemcpyAsync"));
+    return contacts_build_pattern(m, *c);  // ends with a stream synchronisation
   };
-  std::vector<Ent> ent(16 * n);
-  for (int64_t q = 0; q < n; ++q)
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b)
-        ent[16 * q + 4 * a + b] = {tuples[4 * q + a], tuples[4 * q + b], int32_t(16 * q + 4 * a + b)};
-  std::sort(ent.begin(), ent.end(), [](const Ent& x, const Ent& y) {
-    return x.row != y.row ? x.row < y.row : x.col != y.col ? x.col < y.col : x.src < y.src;
-  });
-  std::vector<int32_t> row_ptr(m.N + 1, 0), col, brow, bptr{0}, bsrc(16 * n);
-  for (size_t i = 0; i < ent.size(); ++i) {
-    if (i == 0 || ent[i].row != ent[i - 1].row || ent[i].col != ent[i - 1].col) {
-      if (i > 0) bptr.push_back((int32_t)i);
-      col.push_back(ent[i].col);
-      brow.push_back(ent[i].row);
-      row_ptr[ent[i].row + 1]++;
-    }
-    bsrc[i] = ent[i].src;
-  }
-  bptr.push_back((int32_t)ent.size());
-  for (int64_t i = 0; i < m.N; ++i) row_ptr[i + 1] += row_ptr[i];
-  c->nnzb = (int64_t)col.size();
-  // gradient rows: (node, candidate * 4 + a) sorted by (node, source)
-  std::vector<std::pair<int32_t, int32_t>> gent(4 * n);
-  for (int64_t q = 0; q < n; ++q)
-    for (int a = 0; a < 4; ++a) gent[4 * q + a] = {tuples[4 * q + a], int32_t(4 * q + a)};
-  std::sort(gent.begin(), gent.end());
-  std::vector<int32_t> gnode, gptr{0}, gsrc(4 * n), gdiag;
-  for (size_t i = 0; i < gent.size(); ++i) {
-    if (i == 0 || gent[i].first != gent[i - 1].first) {
-      if (i > 0) gptr.push_back((int32_t)i);
-      const int32_t v = gent[i].first;
-      gnode.push_back(v);
-      const auto b0 = col.begin() + row_ptr[v], b1 = col.begin() + row_ptr[v + 1];
-      gdiag.push_back(row_ptr[v] + (int32_t)(std::lower_bound(b0, b1, v) - b0));
-    }
-    gsrc[i] = gent[i].second;
-  }
-  gptr.push_back((int32_t)gent.size());
-  c->n_gnode = (int64_t)gnode.size();
-  TRY_STATUS(put(m, &c->tuples, tuples, 4 * n));
-  TRY_STATUS(put(m, &c->row_ptr, row_ptr.data(), row_ptr.size()));
-  TRY_STATUS(put(m, &c->col_idx, col.data(), col.size()));
-  TRY_STATUS(put(m, &c->blk_row, brow.data(), brow.size()));
-  TRY_STATUS(put(m, &c->blk_ptr, bptr.data(), bptr.size()));
-  TRY_STATUS(put(m, &c->blk_src, bsrc.data(), bsrc.size()));
-  TRY_STATUS(put(m, &c->gnode, gnode.data(), gnode.size()));
-  TRY_STATUS(put(m, &c->gptr, gptr.data(), gptr.size()));
-  TRY_STATUS(put(m, &c->gsrc, gsrc.data(), gsrc.size()));
-  TRY_STATUS(put(m, &c->gdiag, gdiag.data(), gdiag.size()));
-  TRY_STATUS(put<uint8_t>(m, &c->flag, nullptr, n));
-  TRY_STATUS(put<int>(m, &c->slot, nullptr, n));
-  TRY_STATUS(put<int>(m, &c->act, nullptr, n));
-  TRY_STATUS(put<int>(m, &c->chunk_count, nullptr, (n + kContactChunk - 1) / kContactChunk + 1));
-  TRY_STATUS(put<int>(m, &c->n_active, nullptr, 1));
-  return SYMX_OK;
+  const symx_status st = build();
+  if (st != SYMX_OK) contacts_free(m);  // no half-built contact list stays attached
+  return st;
 }
 
 }  // namespace symxi

@@ -346,6 +346,24 @@ struct Contacts {
   int* n_active = nullptr;         // device scalar
   void* eval = nullptr;            // n x kContactVals in the evaluation's precision
   size_t eval_bytes = 0;
+  // capacities: the buffers above hold `cap` candidates (the pattern arrays
+  // 16 cap blocks), vals32 / vals64 the given numbers of blocks; a new list
+  // of at most cap candidates reuses them
+  int64_t cap = 0;
+  int64_t vals_cap32 = 0, vals_cap64 = 0;
+  // scratch of the device pattern build
+  uint64_t* bkey_in = nullptr;
+  uint64_t* bkey = nullptr;
+  int* bval_in = nullptr;
+  uint32_t* gkey_in = nullptr;
+  uint32_t* gkey = nullptr;
+  int* gval_in = nullptr;
+  int* head = nullptr;
+  int* idx = nullptr;
+  int* row_count = nullptr;        // N+1
+  int* counts = nullptr;           // nnzb, n_gnode
+  void* sort_temp = nullptr;
+  size_t sort_temp_bytes = 0;
 };
 
 // Optional per-kernel timing: HIP events recorded around every launch on the
@@ -478,6 +496,11 @@ symx_status launch_contact_assemble(Mesh& m, const double* x, bool want_g, bool 
 // Replace the candidate contacts (host n x 4 node ids) and free them.
 symx_status contacts_set(Mesh& m, int64_t n, const int32_t* tuples, double kc, double dhat);
 void contacts_free(Mesh& m);
+// Device buffers of the contact pattern and of its build for cap candidates.
+symx_status contacts_reserve_pattern(Mesh& m, Contacts& c, int64_t cap);
+// Contact block pattern and contribution lists of the c.n candidates in
+// c.tuples (on the device; the buffers reserved for at least c.n).
+symx_status contacts_build_pattern(Mesh& m, Contacts& c);
 // Total energy (float64 sum of per-element energies in `precision`).
 symx_status launch_energy(Mesh& m, const double* x, const double* x_tilde, double dt,
                           int precision, double* E_dev);

@@ -2896,7 +2896,14 @@ static symx_status contact_assemble_t(Mesh& m, const double* x, bool want_g, boo
   const uint8_t* fixed = dirichlet ? m.fixed : nullptr;
   if (want_H) {
     T*& vals = *(T**)(sizeof(T) == 4 ? (void*)&c.vals32 : (void*)&c.vals64);
-    if (!vals) TRY(dev_alloc(m.pool, (void**)&vals, 9 * c.nnzb * sizeof(T)));
+    int64_t& vcap = sizeof(T) == 4 ? c.vals_cap32 : c.vals_cap64;
+    if (vcap < c.nnzb) {  // a new candidate list may have more blocks
+      dev_free(m.pool, vals);
+      vals = nullptr;
+      vcap = 0;
+      TRY(dev_alloc(m.pool, (void**)&vals, 9 * c.nnzb * sizeof(T)));
+      vcap = c.nnzb;
+    }
     SYMX_LAUNCH(m, "contact_blocks", k_contact_blocks<T>, dim3(grid_for(c.nnzb, 256)), dim3(256),
                 0, c.nnzb, c.blk_row, c.col_idx, c.blk_ptr, c.blk_src, c.slot, eH, fixed, vals);
     if (dinv) {

@@ -58,6 +58,19 @@ def _all_triangles(scene, n):
     return np.array([[p, *t] for p in pts for t in tris], dtype=np.int32)
 
 
+def _expected_pattern(tuples, n_nodes):
+    """Row pointers and sorted columns of every node pair of every candidate
+    (diagonal included): the contact pattern, written out with numpy."""
+    t = np.asarray(tuples, dtype=np.int64)
+    rows = np.repeat(t, 4, axis=1).ravel()
+    cols = np.tile(t, (1, 4)).ravel()
+    key = np.unique(rows * n_nodes + cols)
+    r, c = key // n_nodes, key % n_nodes
+    rp = np.zeros(n_nodes + 1, dtype=np.int64)
+    np.add.at(rp, r + 1, 1)
+    return np.cumsum(rp), c
+
+
 def _check_contact_blocks(mesh, ref, precision, tol):
     rp, ci, vals = mesh.contact_bsr(precision)
     scale = max(np.abs(b).max() for b in ref["contact_blocks"].values())
@@ -134,6 +147,7 @@ def test_contact_list_changes(symx):
     mesh = symx.Mesh(scene)
     xt = elements.x_tilde(scene.x0, scene.v0, scene.dt, scene.gravity)
     full = scene.contacts.tuples
+    # sizes: n, n/3 (buffers reused), a longer list (buffers grown), empty
     for tuples in (full, full[::3], _all_triangles(scene, 4)[5::7], full[:0]):
         scene.contacts = sg.ContactList(tuples, kc=1e3, dhat=1e-3) if len(tuples) else None
         mesh.set_contacts(tuples, 1e3, 1e-3)
@@ -144,6 +158,9 @@ def test_contact_list_changes(symx):
         assert rel(_bsr(vals), ref["vals"]) < F64_TOL
         if len(tuples):
             _check_contact_blocks(mesh, ref, symx.SYMX_F64, F64_TOL)
+            rp, ci, _ = mesh.contact_bsr(symx.SYMX_F64)
+            rp_o, ci_o = _expected_pattern(tuples, scene.n_nodes)
+            assert np.array_equal(rp, rp_o) and np.array_equal(ci, ci_o)   # bit-exact pattern
         else:
             assert mesh.contact_bsr()[1].size == 0
     mesh.close()
