@@ -151,3 +151,22 @@ def test_idle_patterns_are_evicted_under_a_tight_budget(symx):
     assert [r[0] for r in res] == [0] * len(scenes)
     assert stats.peak_bytes <= stats.budget_bytes
     assert stats.pattern_cache_bytes <= stats.budget_bytes
+
+
+def test_quadratic_and_cubic_requests_served_like_direct_steps(symx):
+    """Quadratic and cubic tet scenes in a mix with a linear one: each served
+    step equals the same step taken directly on a mesh, bit for bit."""
+    scenes = [(None, sg.tet_cube_scene(2, kind=sg.SNH_TET10, seed=21, perturb=0.05, vel_std=0.05)),
+              (None, sg.tet_cube_scene(2, kind=sg.SNH_TET20, seed=22, perturb=0.05, vel_std=0.05)),
+              _requests()[0]]
+    res, stats = _run(symx, scenes, 3)
+    assert stats.completed == 3
+    for (_, sc), (st, rep, x, v, _) in zip(scenes, res):
+        assert st == 0, rep
+        mesh = symx.Mesh(sc)
+        xd = torch.tensor(sc.x0, dtype=torch.float64, device="cuda")
+        vd = torch.tensor(sc.v0, dtype=torch.float64, device="cuda")
+        st2, _ = mesh.newton_step(xd, vd, symx.step_params(dt=0.01))
+        mesh.close()
+        assert st2 == 0
+        assert np.array_equal(xd.cpu().numpy(), x) and np.array_equal(vd.cpu().numpy(), v)
