@@ -148,7 +148,9 @@ def test_contact_list_changes(symx):
     xt = elements.x_tilde(scene.x0, scene.v0, scene.dt, scene.gravity)
     full = scene.contacts.tuples
     # sizes: n, n/3 (buffers reused), a longer list (buffers grown), empty
-    for tuples in (full, full[::3], _all_triangles(scene, 4)[5::7], full[:0]):
+    # (buffers freed), one candidate repeated (two contributions per block), n
+    rep = np.repeat(full[:1], 2, axis=0)
+    for tuples in (full, full[::3], _all_triangles(scene, 4)[5::7], full[:0], rep, full):
         scene.contacts = sg.ContactList(tuples, kc=1e3, dhat=1e-3) if len(tuples) else None
         mesh.set_contacts(tuples, 1e3, 1e-3)
         E, g, vals = mesh.assemble(scene.x0, xt, scene.dt, FLAGS, symx.SYMX_F64)
