@@ -80,8 +80,19 @@ __device__ double block_sum_256(double v, double* sh) {
 // workgroup that calls it gets the same value.  Visibility comes from the
 // kernel boundary, so no fences or atomics are needed.
 __device__ double sum_partials(const double* __restrict__ partials, int n, double* sh) {
+  // A thread's loads are independent: eight are issued together, then added
+  // in index order (the same order as one at a time, without a memory round
+  // trip per partial).
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += partials[i];
+  int i = threadIdx.x;
+  for (; i + 7 * 256 < n; i += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = partials[i + k * 256];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += v[k];
+  }
+  for (; i < n; i += 256) acc += partials[i];
   return block_sum_256(acc, sh);
 }
 
