@@ -84,15 +84,13 @@ __device__ double sum_partials(const double* __restrict__ partials, int n, doubl
   // in index order (the same order as one at a time, without a memory round
   // trip per partial).
   double acc = 0.0;
-  int i = threadIdx.x;
-  for (; i + 7 * 256 < n; i += 8 * 256) {
+  for (int i = threadIdx.x; i < n; i += 8 * 256) {
     double v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = partials[i + k * 256];
+    for (int k = 0; k < 8; ++k) v[k] = i + k * 256 < n ? partials[i + k * 256] : 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc += v[k];
   }
-  for (; i < n; i += 256) acc += partials[i];
   return block_sum_256(acc, sh);
 }
 
