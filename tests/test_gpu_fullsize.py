@@ -1,5 +1,6 @@
-"""Parity at the full 64^3-cube size (1,572,864 tets), in the launch
-configuration that bench.py times.
+"""Parity at the full 64^3-cube size (1,572,864 tets) and on the quadratic
+and cubic benchmark boxes (about 137K DoF), in the launch configurations
+that bench.py times.
 
 The oracle cannot assemble the whole Hessian at this size in a test, so it
 checks sampled block rows: for each sampled node, the oracle's element
@@ -56,8 +57,9 @@ def _oracle_rows(scene, x, xt, dt, nodes):
                        young_per_elem=None if es.young_per_elem is None else es.young_per_elem[sel],
                        poisson=es.poisson, density=es.density)
     _, ge, He = elements.element_eval(sub, x, scene.X)
-    ge = ge.reshape(-1, 4, 3)
-    He = He.reshape(-1, 4, 3, 4, 3)
+    k = conn.shape[1]
+    ge = ge.reshape(-1, k, 3)
+    He = He.reshape(-1, k, 3, k, 3)
     mass = rest.lumped_mass(scene)
     w = mass / dt ** 2
     fixed = scene.fixed.astype(bool)
@@ -68,7 +70,7 @@ def _oracle_rows(scene, x, xt, dt, nodes):
         blocks = {}
         for k, a in np.argwhere(csel == i):          # ascending element id
             g += ge[k, a]
-            for b in range(4):
+            for b in range(csel.shape[1]):
                 j = int(csel[k, b])
                 blocks[j] = blocks.get(j, np.zeros((3, 3))) + He[k, a, :, b, :]
         g += w[i] * (x[i] - xt[i])
@@ -82,9 +84,7 @@ def _oracle_rows(scene, x, xt, dt, nodes):
     return rows
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_c2_sampled_rows_match_oracle(symx, c2, precision):
-    scene = c2
+def _check_sampled_rows(symx, scene, precision, n_nodes, seed):
     mesh = symx.Mesh(scene)
     dt = scene.dt
     xt = elements.x_tilde(scene.x0, scene.v0, dt, scene.gravity)
@@ -95,7 +95,7 @@ def test_c2_sampled_rows_match_oracle(symx, c2, precision):
     rp, ci, _ = mesh.pattern()
     V = vals.cpu().numpy().astype(np.float64).T.reshape(-1, 3, 3)
     gd = g.cpu().numpy()
-    nodes = _sample_nodes(scene, 200, seed=41)
+    nodes = _sample_nodes(scene, n_nodes, seed=seed)
     ref = _oracle_rows(scene, scene.x0, xt, dt, nodes)
     gerr = gmax = herr = hmax = 0.0
     for i, (go, blocks) in ref.items():
@@ -111,6 +111,46 @@ def test_c2_sampled_rows_match_oracle(symx, c2, precision):
     E_ref = assembly.energy(scene, scene.x0, xt, dt)
     assert abs(E - E_ref) <= tol * abs(E_ref)
     mesh.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_c2_sampled_rows_match_oracle(symx, c2, precision):
+    _check_sampled_rows(symx, c2, precision, 200, 41)
+
+
+# The quadratic and cubic stretched boxes of the benchmark (about 137K DoF).
+HIGH_ORDER_BOXES = {"quadratic": (sg.SNH_TET10, (17, 17, 18)),
+                    "cubic": (sg.SNH_TET20, (11, 11, 13))}
+
+
+@pytest.mark.parametrize("order", ["quadratic", "cubic"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_high_order_box_sampled_rows_match_oracle(symx, order, precision):
+    kind, dims = HIGH_ORDER_BOXES[order]
+    _check_sampled_rows(symx, sg.stretched_box_scene(kind, dims=dims), precision, 120, 43)
+
+
+@pytest.mark.parametrize("order", ["quadratic", "cubic"])
+def test_high_order_box_newton_step_f32_refined(symx, order):
+    """One FP32-refined step on the benchmark box: the oracle's float64
+    gradient at the result meets the Newton tolerance, the energy is the
+    oracle's."""
+    kind, dims = HIGH_ORDER_BOXES[order]
+    scene = sg.stretched_box_scene(kind, dims=dims)
+    mesh = symx.Mesh(scene)
+    x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+    st, rep = mesh.newton_step(x, v, symx.step_params(dt=scene.dt,
+                                                      precision=symx.SYMX_F32_REFINED))
+    mesh.close()
+    assert st == 0, (symx.STATUS[st], rep.as_dict())
+    xh = x.cpu().numpy()
+    xt = elements.x_tilde(scene.x0, scene.v0, scene.dt, scene.gravity)
+    r0 = np.linalg.norm(assembly.assemble(scene, scene.x0, xt, scene.dt, want_hess=False)["g"])
+    assert rep.residual0 == pytest.approx(r0, rel=1e-10)
+    r = np.linalg.norm(assembly.assemble(scene, xh, xt, scene.dt, want_hess=False)["g"])
+    assert r <= 1.01e-6 * r0
+    assert rep.energy == pytest.approx(assembly.energy(scene, xh, xt, scene.dt), rel=1e-10)
 
 
 def test_c2_newton_step_f32_refined(symx, c2):
