@@ -173,3 +173,11 @@ def test_c2_newton_step_f32_refined(symx, c2):
     E_ref = assembly.energy(scene, xh, xt, scene.dt)
     assert rep.energy == pytest.approx(E_ref, rel=1e-10)
     assert np.allclose(v.cpu().numpy(), (xh - scene.x0) / scene.dt)
+
+
+@pytest.mark.parametrize("kind", [sg.NH_TET4, sg.STVK_TET4, sg.FCR_TET4, sg.ARAP_TET4])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_material_box_sampled_rows_match_oracle(symx, kind, precision):
+    """The other App. B materials on their benchmark box (40 x 40 x 60 cubes,
+    576,000 tets; lagged rotations at the rest shape)."""
+    _check_sampled_rows(symx, sg.stretched_box_scene(kind), precision, 80, 47)
