@@ -181,3 +181,48 @@ def test_material_box_sampled_rows_match_oracle(symx, kind, precision):
     """The other App. B materials on their benchmark box (40 x 40 x 60 cubes,
     576,000 tets; lagged rotations at the rest shape)."""
     _check_sampled_rows(symx, sg.stretched_box_scene(kind), precision, 80, 47)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_contact_scene_at_benchmark_size(symx, precision):
+    """The contact benchmark (two stacked 32^3-cube blocks, 393,216 tets, 8,192
+    candidates): energy and full gradient against the oracle, and every block
+    of the contact matrix against the oracle's active contact blocks."""
+    from oracle import contact
+    scene = sg.contact_stack_scene(32, neighbors=True)
+    cl = scene.contacts
+    mesh = symx.Mesh(scene)
+    mesh.set_contacts(cl.tuples, cl.kc, cl.dhat)
+    dt = scene.dt
+    xt = elements.x_tilde(scene.x0, scene.v0, dt, scene.gravity)
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32
+    tol = F64_TOL if precision == "f64" else F32_TOL
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    E, g, _ = mesh.assemble(scene.x0, xt, dt, flags, p)
+    ref = assembly.assemble(scene, scene.x0, xt, dt, want_hess=False)
+    assert abs(E - ref["E"]) <= tol * abs(ref["E"])
+    gd = g.cpu().numpy()
+    assert np.abs(gd - ref["g"]).max() <= tol * np.abs(ref["g"]).max()
+    # contact blocks: candidate element Hessians of the active candidates,
+    # summed per node pair, Dirichlet applied
+    _, _, Hc, act = contact.point_plane_barrier(scene.x0[cl.tuples], cl.kc, cl.dhat)
+    assert 0 < act.sum() < act.size
+    fixed = scene.fixed.astype(bool)
+    want = {}
+    for t, He in zip(cl.tuples[act], Hc[act]):
+        for a in range(4):
+            for b in range(4):
+                key = (int(t[a]), int(t[b]))
+                blk = np.zeros((3, 3)) if fixed[t[a]] or fixed[t[b]] else He[a, :, b, :]
+                want[key] = want.get(key, np.zeros((3, 3))) + blk
+    rp, ci, vals = mesh.contact_bsr(p)
+    scale = max(np.abs(b).max() for b in want.values())
+    err, seen = 0.0, set()
+    for i in range(len(rp) - 1):
+        for q in range(rp[i], rp[i + 1]):
+            key = (i, int(ci[q]))
+            seen.add(key)
+            err = max(err, np.abs(vals[q] - want.get(key, np.zeros((3, 3)))).max())
+    assert set(want) <= seen
+    assert err <= tol * scale
+    mesh.close()
