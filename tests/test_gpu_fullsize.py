@@ -47,9 +47,11 @@ def _sample_nodes(scene, n, seed):
                                      [0, scene.n_nodes - 1]]))
 
 
-def _oracle_rows(scene, x, xt, dt, nodes):
+def _oracle_rows(scene, x, xt, dt, nodes, project=False):
     """Gradient rows and Hessian block rows {(i, j): 3x3} of the sampled nodes,
-    from the oracle's element functions on the incident elements."""
+    from the oracle's element functions on the incident elements (element
+    Hessians projected to PSD, or SNH density Hessians filtered, as the
+    assembly does with project=True / "filter")."""
     es = scene.energies[0]
     conn = es.conn
     sel = np.nonzero(np.isin(conn, nodes).any(axis=1))[0]        # ascending element ids
@@ -58,6 +60,11 @@ def _oracle_rows(scene, x, xt, dt, nodes):
                        poisson=es.poisson, density=es.density)
     _, ge, He = elements.element_eval(sub, x, scene.X)
     k = conn.shape[1]
+    if project == "filter":
+        mu, lam = rest.lame(rest.young_array(sub), sub.poisson)
+        _, _, He = elements.snh_tet4_filtered(x[sub.conn], scene.X[sub.conn], mu, lam)
+    elif project:
+        He = assembly.project_psd(He.reshape(-1, 3 * k, 3 * k))
     ge = ge.reshape(-1, k, 3)
     He = He.reshape(-1, k, 3, k, 3)
     mass = rest.lumped_mass(scene)
@@ -84,19 +91,21 @@ def _oracle_rows(scene, x, xt, dt, nodes):
     return rows
 
 
-def _check_sampled_rows(symx, scene, precision, n_nodes, seed):
+def _check_sampled_rows(symx, scene, precision, n_nodes, seed, project=False):
     mesh = symx.Mesh(scene)
     dt = scene.dt
     xt = elements.x_tilde(scene.x0, scene.v0, dt, scene.gravity)
     p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32
     tol = F64_TOL if precision == "f64" else F32_TOL
     flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    if project:
+        flags |= symx.SYMX_PROJECT_FILTER if project == "filter" else symx.SYMX_PROJECT_PSD
     E, g, vals = mesh.assemble(scene.x0, xt, dt, flags, p)
     rp, ci, _ = mesh.pattern()
     V = vals.cpu().numpy().astype(np.float64).T.reshape(-1, 3, 3)
     gd = g.cpu().numpy()
     nodes = _sample_nodes(scene, n_nodes, seed=seed)
-    ref = _oracle_rows(scene, scene.x0, xt, dt, nodes)
+    ref = _oracle_rows(scene, scene.x0, xt, dt, nodes, project)
     gerr = gmax = herr = hmax = 0.0
     for i, (go, blocks) in ref.items():
         cols = ci[rp[i]:rp[i + 1]]
@@ -116,6 +125,13 @@ def _check_sampled_rows(symx, scene, precision, n_nodes, seed):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_c2_sampled_rows_match_oracle(symx, c2, precision):
     _check_sampled_rows(symx, c2, precision, 200, 41)
+
+
+@pytest.mark.parametrize("project", [True, "filter"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_c2_projected_sampled_rows_match_oracle(symx, c2, precision, project):
+    """Per-element PSD projection and the filtered SNH Hessian at full size."""
+    _check_sampled_rows(symx, c2, precision, 120, 45, project)
 
 
 # The quadratic and cubic stretched boxes of the benchmark (about 137K DoF).
