@@ -49,45 +49,52 @@ def _sample_nodes(scene, n, seed):
 
 def _oracle_rows(scene, x, xt, dt, nodes, project=False):
     """Gradient rows and Hessian block rows {(i, j): 3x3} of the sampled nodes,
-    from the oracle's element functions on the incident elements (element
-    Hessians projected to PSD, or SNH density Hessians filtered, as the
-    assembly does with project=True / "filter")."""
-    es = scene.energies[0]
-    conn = es.conn
-    sel = np.nonzero(np.isin(conn, nodes).any(axis=1))[0]        # ascending element ids
-    sub = sg.EnergySet(es.kind, conn[sel], young=es.young,
-                       young_per_elem=None if es.young_per_elem is None else es.young_per_elem[sel],
-                       poisson=es.poisson, density=es.density)
-    _, ge, He = elements.element_eval(sub, x, scene.X)
-    k = conn.shape[1]
-    if project == "filter":
-        mu, lam = rest.lame(rest.young_array(sub), sub.poisson)
-        _, _, He = elements.snh_tet4_filtered(x[sub.conn], scene.X[sub.conn], mu, lam)
-    elif project:
-        He = assembly.project_psd(He.reshape(-1, 3 * k, 3 * k))
-    ge = ge.reshape(-1, k, 3)
-    He = He.reshape(-1, k, 3, k, 3)
+    from the oracle's element functions on the incident elements of every
+    energy set, summed in (set, element) order (element Hessians projected to
+    PSD, or SNH density Hessians filtered, as the assembly does with
+    project=True / "filter")."""
+    import dataclasses
     mass = rest.lumped_mass(scene)
     w = mass / dt ** 2
     fixed = scene.fixed.astype(bool)
-    csel = conn[sel]
+    g = {int(i): np.zeros(3) for i in nodes}
+    blocks = {int(i): {} for i in nodes}
+    for es in scene.energies:
+        conn = es.conn
+        sel = np.nonzero(np.isin(conn, nodes).any(axis=1))[0]    # ascending element ids
+        if sel.size == 0:
+            continue
+        sub = dataclasses.replace(es, conn=conn[sel], young_per_elem=None if es.young_per_elem
+                                  is None else es.young_per_elem[sel])
+        _, ge, He = elements.element_eval(sub, x, scene.X)
+        k = conn.shape[1]
+        if project == "filter" and es.kind == sg.SNH_TET4:
+            mu, lam = rest.lame(rest.young_array(sub), sub.poisson)
+            _, _, He = elements.snh_tet4_filtered(x[sub.conn], scene.X[sub.conn], mu, lam)
+        elif project:
+            He = assembly.project_psd(He.reshape(-1, 3 * k, 3 * k))
+        ge = ge.reshape(-1, k, 3)
+        He = He.reshape(-1, k, 3, k, 3)
+        csel = conn[sel]
+        for i in nodes:
+            bi = blocks[int(i)]
+            for e, a in np.argwhere(csel == i):                    # ascending element id
+                g[int(i)] += ge[e, a]
+                for b in range(k):
+                    j = int(csel[e, b])
+                    bi[j] = bi.get(j, np.zeros((3, 3))) + He[e, a, :, b, :]
     rows = {}
     for i in nodes:
-        g = np.zeros(3)
-        blocks = {}
-        for k, a in np.argwhere(csel == i):          # ascending element id
-            g += ge[k, a]
-            for b in range(csel.shape[1]):
-                j = int(csel[k, b])
-                blocks[j] = blocks.get(j, np.zeros((3, 3))) + He[k, a, :, b, :]
-        g += w[i] * (x[i] - xt[i])
-        blocks[int(i)] = blocks.get(int(i), np.zeros((3, 3))) + w[i] * np.eye(3)
+        i = int(i)
+        gi, bi = g[i], blocks[i]
+        gi += w[i] * (x[i] - xt[i])
+        bi[i] = bi.get(i, np.zeros((3, 3))) + w[i] * np.eye(3)
         if fixed[i]:
-            g[:] = 0.0
-        for j in blocks:
+            gi[:] = 0.0
+        for j in bi:
             if fixed[i] or fixed[j]:
-                blocks[j] = np.eye(3) if j == i else np.zeros((3, 3))
-        rows[int(i)] = (g, blocks)
+                bi[j] = np.eye(3) if j == i else np.zeros((3, 3))
+        rows[i] = (gi, bi)
     return rows
 
 
@@ -242,3 +249,11 @@ def test_contact_scene_at_benchmark_size(symx, precision):
     assert set(want) <= seen
     assert err <= tol * scale
     mesh.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_c3_sampled_rows_match_oracle(symx, precision):
+    """C3 (512^2 cloth with membranes and hinges, and a 32^3-cube tet block):
+    rows of cloth and block nodes, several element kinds per row."""
+    _check_sampled_rows(symx, sg.config_c3(), precision, 120, 49)
+
