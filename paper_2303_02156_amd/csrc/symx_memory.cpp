@@ -45,11 +45,22 @@ bool DevicePool::add_chunk(size_t min_bytes) {
   size_t size = std::max(kChunk, align_up(min_bytes, size_t(2) << 20));
   if (capacity_ && held_ + size > capacity_ && held_ + min_bytes <= capacity_)
     size = align_up(capacity_ - held_, kAlign);  // last chunk: what the capacity leaves
-  void* p = nullptr;
-  if (hipMalloc(&p, size) != hipSuccess) {
+  // Allocate on the pool's device whatever device the calling thread has
+  // current, and leave the caller's current device as it was.
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) {
     (void)hipGetLastError();
     return false;
   }
+  if (prev != device_ && hipSetDevice(device_) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  void* p = nullptr;
+  const bool ok = hipMalloc(&p, size) == hipSuccess;
+  if (!ok) (void)hipGetLastError();
+  if (prev != device_) (void)hipSetDevice(prev);
+  if (!ok) return false;
   auto c = std::make_unique<Chunk>();
   c->base = static_cast<char*>(p);
   c->size = size;
