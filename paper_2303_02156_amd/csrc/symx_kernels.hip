@@ -1882,10 +1882,14 @@ __device__ __forceinline__ void spmv_row(int row, int lane, const int* __restric
   const int pe = row_ptr[row + 1];
   for (int p = row_ptr[row] + lane; p < pe; p += 16) {
     const int j = col[p];
+    // the nine value loads are issued together, ahead of the gather of x
+    TY v[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[c] = TY(vals[c * nnzb + p]);
     const TY x0 = TY(x[3 * j]), x1 = TY(x[3 * j + 1]), x2 = TY(x[3 * j + 2]);
-    acc[0] += TY(vals[p]) * x0 + TY(vals[nnzb + p]) * x1 + TY(vals[2 * nnzb + p]) * x2;
-    acc[1] += TY(vals[3 * nnzb + p]) * x0 + TY(vals[4 * nnzb + p]) * x1 + TY(vals[5 * nnzb + p]) * x2;
-    acc[2] += TY(vals[6 * nnzb + p]) * x0 + TY(vals[7 * nnzb + p]) * x1 + TY(vals[8 * nnzb + p]) * x2;
+    acc[0] += v[0] * x0 + v[1] * x1 + v[2] * x2;
+    acc[1] += v[3] * x0 + v[4] * x1 + v[5] * x2;
+    acc[2] += v[6] * x0 + v[7] * x1 + v[8] * x2;
   }
 #pragma unroll
   for (int m = 8; m > 0; m >>= 1) {
@@ -1938,11 +1942,13 @@ __global__ __launch_bounds__(256) void k_residual64(int64_t N, const int* __rest
 // iteration k is kept in slot S_RZ + (k & 1) so that readers of the previous
 // value never race with the writer of the new one.
 // Grid sizes: the SpMV kernel streams the matrix and runs best with up to
-// 2048 workgroups; the node-wise kernels use up to 1024.  Small meshes get
+// 2048 workgroups; the node-wise kernels use up to 256 (every SpMV workgroup
+// first sums their partials, so fewer of them make that preamble cheaper at
+// no cost to the node-wise kernels themselves).  Small meshes get
 // grids sized to their rows (gs a multiple of 8), so that no launch is made
 // of workgroups with nothing to do.  Each partial array holds up to kPcgP
 // entries.
-constexpr int kPcgGs = 2048, kPcgGu = 1024, kPcgP = 4096;
+constexpr int kPcgGs = 2048, kPcgGu = 256, kPcgP = 4096;
 static int pcg_gs(int64_t N) {
   const int64_t g = (N * 16 + 255) / 256;
   return (int)std::min<int64_t>(kPcgGs, std::max<int64_t>(8, (g + 7) / 8 * 8));
@@ -2003,8 +2009,8 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restric
 // Iteration k: reduce rz, rr of the previous update; stop on convergence or
 // at the iteration limit; beta = rz_k / rz_(k-1); w = A z; p = z + beta p;
 // q = w + beta q; partials of p.q.
-// Rows: workgroup b runs on XCD b % 8 and takes, in steps of 16 rows, the
-// rows of the XCD's contiguous eighth of the matrix, so that the gathered
+// Rows (FP32): workgroup b runs on XCD b % 8 and takes, in steps of 16 rows,
+// the rows of the XCD's contiguous eighth of the matrix, so that the gathered
 // entries of z stay in that XCD's L2 (gridDim.x is a multiple of 8).
 template <typename T, bool DYN>
 __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* __restrict__ row_ptr,
@@ -2032,12 +2038,15 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* _
     if (k == 0) S[S_BB] = bb;
   }
   const int lane = threadIdx.x & 15;
+  // FP32: the XCD-aware row ranges below; FP64 streams twice the bytes per
+  // block and runs faster on a plain grid-stride over all rows (measured).
+  constexpr bool kXcd = sizeof(T) == 4;
   const int xcd = blockIdx.x & 7;
-  const int64_t lo = N * xcd / 8, hi = N * (xcd + 1) / 8;
-  const int64_t stride = (int64_t)(gridDim.x >> 3) * 16;
+  const int64_t lo = kXcd ? N * xcd / 8 : 0, hi = kXcd ? N * (xcd + 1) / 8 : N;
+  const int64_t stride = kXcd ? (int64_t)(gridDim.x >> 3) * 16 : (int64_t)gridDim.x * 16;
+  const int64_t first_row = kXcd ? (int64_t)(blockIdx.x >> 3) * 16 : (int64_t)blockIdx.x * 16;
   double pq = 0.0;
-  for (int64_t row = lo + (int64_t)(blockIdx.x >> 3) * 16 + (threadIdx.x >> 4); row < hi;
-       row += stride) {
+  for (int64_t row = lo + first_row + (threadIdx.x >> 4); row < hi; row += stride) {
     T acc[3];
     spmv_row<T, T, T>((int)row, lane, row_ptr, col, vals, nnzb, z, acc);
     if (DYN) {
@@ -2047,15 +2056,13 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* _
       acc[1] += ac[1];
       acc[2] += ac[2];
     }
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T pn = z[3 * row + c] + beta * p[3 * row + c];
-        const T qn = acc[c] + beta * q[3 * row + c];
-        p[3 * row + c] = pn;
-        q[3 * row + c] = qn;
-        pq += double(pn) * double(qn);
-      }
+    if (lane < 3) {  // lane c writes component c of the row
+      const T a = lane == 0 ? acc[0] : lane == 1 ? acc[1] : acc[2];
+      const T pn = z[3 * row + lane] + beta * p[3 * row + lane];
+      const T qn = a + beta * q[3 * row + lane];
+      p[3 * row + lane] = pn;
+      q[3 * row + lane] = qn;
+      pq += double(pn) * double(qn);
     }
   }
   const double s = block_sum_256(pq, sh);
