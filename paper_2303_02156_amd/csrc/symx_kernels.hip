@@ -1321,14 +1321,23 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
     const uint32_t info = A.blk_info[p0 + t];
     const uint16_t* ce = A.centry + A.batch_entry[b] + (info >> 8);
     const int cnt = int(info & 0xFFu);
-    for (int j = 0; j < cnt; ++j) {
-      const uint32_t w = ce[j];
-      const int q = int(w >> 2);
-      const int bb = int(w & 3u) - 1;
+    // up to eight list entries are loaded together, then summed in list
+    // order (one global round trip per eight entries instead of per entry)
+    for (int j0 = 0; j0 < cnt; j0 += 8) {
+      uint32_t w[8];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 8; ++k) w[k] = j0 + k < cnt ? uint32_t(ce[j0 + k]) : 0u;
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += st[3 + 9 * i + 3 * bb + kk][q];
+      for (int k = 0; k < 8; ++k) {
+        if (j0 + k < cnt) {
+          const int q = int(w[k] >> 2);
+          const int bb = int(w[k] & 3u) - 1;
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += st[3 + 9 * i + 3 * bb + kk][q];
+        }
+      }
     }
   }
   __syncthreads();
@@ -1346,8 +1355,17 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   for (int j = t; j < (WANT_G ? 12 : 9) * nrows; j += kRowWG) {
     if (j < 9 * nrows) {
       const int rr = j / 9, c = j - 9 * rr;
+      // LDS reads in groups of eight, added in slot order
       T sum = T(0);
-      for (int sl = s_blk[rr]; sl < s_blk[rr + 1]; ++sl) sum += st[3 + c][sl];
+      const int sl1 = s_blk[rr + 1];
+      for (int sl = s_blk[rr]; sl < sl1; sl += 8) {
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = sl + k < sl1 ? st[3 + c][sl + k] : T(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (sl + k < sl1) sum += v[k];
+      }
       T dv = -sum;
       if (A.xt && (c % 4) == 0) dv += T(A.mass[r0 + rr] * A.inv_dt2);
       st[3 + c][A.diag_pos[r0 + rr] - p0] = dv;
@@ -1356,7 +1374,15 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
       const int rr = jj / 3, c = jj - 3 * rr;
       const int row = r0 + rr;
       double g = 0.0;
-      for (int q = s_inc[rr]; q < s_inc[rr + 1]; ++q) g += double(st[c][q]);
+      const int q1 = s_inc[rr + 1];
+      for (int q = s_inc[rr]; q < q1; q += 8) {  // as above, incidence order
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = q + k < q1 ? st[c][q + k] : T(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (q + k < q1) g += double(v[k]);
+      }
       if (A.xt) g += A.mass[row] * A.inv_dt2 * (A.x[3 * row + c] - A.xt[3 * row + c]);
       if (A.fixed && A.fixed[row]) g = 0.0;
       if (!isfinite(g)) *A.nonfinite = 1;
