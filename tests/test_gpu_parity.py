@@ -345,6 +345,35 @@ def test_newton_rigid_translation_exact(symx):
     assert np.max(np.abs(x - (s.X + s.dt * s.v0))) <= bound
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32r"])
+def test_newton_free_fall_closed_form(symx, precision):
+    """A free body under gravity (Eq. 2-3): every implicit-Euler step moves all
+    nodes as one particle, v_{k+1} = v_k + dt g, x_{k+1} = x_k + dt v_{k+1};
+    after K steps x_K = x_0 + K dt v_0 + dt^2 g K (K + 1) / 2 (a closed form,
+    not the oracle)."""
+    s = sg.tet_cube_scene(3, seed=2, perturb=0.0)
+    s.fixed[:] = 0
+    grav = np.array([0.7, -0.4, -9.81])
+    v0 = np.array([0.05, 0.02, -0.1])
+    dt, K = 0.01, 5
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32_REFINED
+    mesh = symx.Mesh(s)
+    x = torch.tensor(s.X, dtype=torch.float64, device="cuda")
+    v = torch.tensor(np.tile(v0, (s.n_nodes, 1)), dtype=torch.float64, device="cuda")
+    bound = 0.0
+    m_min = rest.lumped_mass(s).min()
+    for _ in range(K):
+        st, rep = mesh.newton_step(x, v, symx.step_params(dt=dt, precision=p,
+                                                          gravity=tuple(grav)))
+        assert st == 0 and rep.dt_halvings == 0, (symx.STATUS[st], rep.as_dict())
+        # Newton stops at |g| <= 1e-6 r0 and H >= M / dt^2 for a translation
+        bound += dt * dt / m_min * 1.01e-6 * rep.residual0
+    x_ref = s.X + K * dt * v0 + dt * dt * grav * K * (K + 1) / 2
+    assert np.max(np.abs(x.cpu().numpy() - x_ref)) <= bound + 1e-13
+    assert np.max(np.abs(v.cpu().numpy() - (v0 + K * dt * grav))) <= bound / dt * 2 + 1e-11
+    mesh.close()
+
+
 def test_nonfinite_input_is_reported(symx):
     scene = sg.tet_cube_scene(2, seed=1)
     mesh = symx.Mesh(scene)

@@ -1026,6 +1026,69 @@ def test_newton_rigid_translation_is_exact():
     assert np.allclose(v1, v, atol=1e-9)
 
 
+def test_x_tilde_free_fall_closed_form():
+    # Eq. 2-3 for a body in free fall: a uniform translation leaves every
+    # elastic energy at its rest value, so each implicit-Euler step moves all
+    # nodes as one particle, v_{k+1} = v_k + dt g and x_{k+1} = x_k + dt v_{k+1}.
+    # Summed over K steps: v_K = v_0 + K dt g, x_K = x_0 + K dt v_0 +
+    # dt^2 g K (K + 1) / 2 (explicit Euler would give K (K - 1) / 2, the exact
+    # flow K^2 / 2).  A slip in the prediction x_tilde (dt g for dt^2 g, a
+    # half, a sign, a component) moves x_K off this closed form.
+    s = sg.tet_cube_scene(2, seed=3, perturb=0.0)
+    s.fixed[:] = 0
+    grav = np.array([0.7, -0.4, -9.81])
+    v0 = np.array([0.05, 0.02, -0.1])
+    dt, K = 0.01, 5
+    prm = newton.StepParams(dt=dt, gravity=tuple(grav))
+    st = newton.Stepper(s, prm, solver="direct")
+    x, v = s.X.copy(), np.tile(v0, (s.n_nodes, 1))
+    for _ in range(K):
+        x, v, rep = st.step(x, v)
+        assert rep["status"] == "ok" and rep["dt_halvings"] == 0
+    x_ref = s.X + K * dt * v0 + dt * dt * grav * K * (K + 1) / 2
+    v_ref = v0 + K * dt * grav
+    assert np.max(np.abs(x - x_ref)) <= 1e-12
+    assert np.max(np.abs(v - v_ref[None, :])) <= 1e-9
+
+
+def test_block_jacobi_is_exact_on_block_diagonal_systems():
+    # With every off-diagonal block removed the matrix is its own block-Jacobi
+    # preconditioner, so preconditioned CG reaches the exact solution in one
+    # iteration.  The diagonal blocks (inertia + elastic, fully populated 3x3)
+    # are split between the mesh matrix and the contact blocks, whose diagonal
+    # blocks the preconditioner must add in; a wrong block, a missing contact
+    # part or a wrong inverse needs more iterations.
+    s = sg.config_c1()
+    xt = elements.x_tilde(s.x0, s.v0, 0.01, s.gravity)
+    a = assembly.assemble(s, s.x0, xt, 0.01)
+    rp, ci = a["row_ptr"], a["col_idx"]
+    N = rp.size - 1
+    rows = np.repeat(np.arange(N), np.diff(rp))
+    diag = rows == ci
+    # free nodes' diagonal blocks couple their components (fixed ones are I)
+    assert np.mean(np.abs(a["vals"][diag][:, 0, 1]) > 0) > 0.8
+    vals = np.where(diag[:, None, None], a["vals"], 0.0)
+    # contact part: a random symmetric matrix per node (not a multiple of the
+    # block, since CG does not see a uniform scaling of the preconditioner)
+    R = np.random.default_rng(4).normal(size=(N, 3, 3))
+    R = 0.3 * (R + np.transpose(R, (0, 2, 1))) * np.abs(vals[diag]).max(axis=(1, 2))[:, None, None]
+    cb = {(i, i): R[i] for i in range(N)}
+    part = vals.copy()
+    part[diag] -= R
+    A = assembly.to_scipy(rp, ci, part, cb)
+    D = newton.diag_inverse(rp, ci, part, cb)
+    b = np.random.default_rng(5).normal(size=3 * N)
+    x, it, ok = newton.pcg(A, D, b, 1e-13, 50)
+    assert ok and it == 1
+    ref = np.concatenate([np.linalg.solve(vals[d], b[3 * i:3 * i + 3])
+                          for i, d in zip(rows[diag], np.nonzero(diag)[0])])
+    assert _rel(x, ref) < 1e-12
+    # and the full matrix needs many iterations with the same preconditioner
+    Af = assembly.to_scipy(rp, ci, a["vals"])
+    _, it_full, _ = newton.pcg(Af, newton.diag_inverse(rp, ci, a["vals"]), b, 1e-13, 2000)
+    assert it_full > 10
+
+
 def test_newton_quadratic_energy_one_iteration():
     # inertia + bending only: E_BE is quadratic, so one exact Newton step solves it
     c = sg.cloth_scene(3, perturb=0.2)
