@@ -9,15 +9,20 @@ residual, block-Jacobi PCG at most 500 iterations.  All inputs are synthetic
 and resident on the GPU before timing starts.
 
 One step = one implicit-Euler time step through the whole path (assembly of
-energy, gradient and BSR Hessian; PCG; float64 refinement; line search;
-update) in the FP32-with-refinement mode.  The JSON line reports
-  value        element evaluation + assembly throughput (Melem/s, FP32, no
+energy, gradient and BSR Hessian; PCG; line search; update) in float64, the
+paper's precision.  The JSON line reports
+  value        element evaluation + assembly throughput (Melem/s, FP64, no
                projection): device time of one full E + gradient + BSR Hessian
                evaluation, median over repetitions
-  ms_per_step  FP32-refined Newton time step (K timed steps)
-and, beside them, FP64 figures, projection-on figures, the roofline of the
-dominant kernel (live HIP-event timing inside the timed steps) and the FP64
-CPU oracle timed on a bounded sample.
+  ms_per_step  FP64 Newton time step (K timed steps)
+  roofline     the FP64 PCG SpMV, the dominant kernel of the step (live
+               HIP-event timing in a replay of the timed steps)
+and, beside them, FP32 and FP32-with-refinement figures, projection-on
+figures, the FP32 SpMV (Infinity-Cache resident, labelled "mall"), the
+assembly's ALU roofline, and the FP64 CPU oracle timed on all host cores of
+the GPU's CPU share and on one core.  The other workloads (C3, C4, beam,
+materials, higher-order tets, contacts, serving) are logged to stderr and,
+with --details, written to a JSON file.
 """
 import argparse
 import json
@@ -58,11 +63,13 @@ def algorithmic_bytes(kernel, N, nnzb, n_elem, t_bytes):
     return None
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    when the kernel source changed since the counters were taken."""
+def measured_traffic(kernel, label):
+    """HBM bytes per launch of kernel<label> (label "float" or "double") from
+    the committed rocprofv3 counter runs, or None when the kernel source
+    changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_traffic.json")
+    tag = {"float": "f32", "double": "f64"}[label]
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{tag}_c2_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -568,42 +575,218 @@ def contact_bench(symx, torch, n=32, reps=10):
     return out
 
 
+_CPU = {}
+
+
+def _cpu_init(n):
+    """Worker set-up of the all-core oracle baseline: the scene, its pattern and
+    the prediction x_tilde (setup, not timed)."""
+    import scenegen as sg
+    from oracle import assembly, elements
+    s = sg.tet_cube_scene(n, h=0.01, seed=2, perturb=0.0, vel_std=0.1)
+    rp, ci = assembly.pattern_fast(s)
+    _CPU.update(scene=s, rp=rp, ci=ci, xt=elements.x_tilde(s.x0, s.v0, 0.01, s.gravity))
+
+
+def _cpu_chunk(rng):
+    """One worker's share: the oracle's assembly of elements [lo, hi) (no inertia,
+    no Dirichlet) at the predicted positions; returns the touched slice of the
+    gradient rows and of the block values."""
+    import copy
+
+    import numpy as np
+
+    from oracle import assembly
+    lo, hi = rng
+    s, rp, ci, xt = _CPU["scene"], _CPU["rp"], _CPU["ci"], _CPU["xt"]
+    sub = copy.copy(s)
+    es = copy.copy(s.energies[0])
+    es.conn = es.conn[lo:hi]
+    sub.energies = [es]
+    a = assembly.assemble(sub, xt, None, None, dirichlet=False, row_ptr=rp, col_idx=ci)
+    n0, n1 = int(es.conn.min()), int(es.conn.max()) + 1
+    b0, b1 = int(rp[n0]), int(rp[n1])
+    return a["E"], n0, a["g"][n0:n1], b0, a["vals"][b0:b1]
+
+
 def cpu_baseline(seconds_target=10.0):
-    """FP64 numpy oracle: eval + assembly (E, g, BSR) of a 24^3 cube of the same
-    workload recipe, repeated until ~seconds_target of CPU work."""
+    """The FP64 numpy oracle timed on the host, before the GPU is touched:
+    - one core: the oracle's E + g + BSR assembly of a 24^3-cube grid (82,944
+      tets) of the workload recipe, repeated for about seconds_target;
+    - all cores: a 32^3-cube grid (196,608 tets) split into one contiguous
+      element range per worker process (the CPU share of one GPU, at most 16
+      workers); each runs the same oracle assembly on its range and the parent
+      adds the touched row and block slices, then the inertia term and the
+      Dirichlet rows (the rest of the oracle's assembly).  Wall time per pass,
+      median of several passes after one warm-up."""
+    import multiprocessing as mp
+
     import numpy as np
 
     import scenegen as sg
     from oracle import assembly, elements
-    n = 24
-    s = sg.tet_cube_scene(n, h=0.01, seed=2, perturb=0.0, vel_std=0.1)
+    from oracle.rest import lumped_mass
+
+    def host_model():
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+        except OSError:
+            pass
+        return platform.processor()
+
+    # one core
+    n1 = 24
+    s = sg.tet_cube_scene(n1, h=0.01, seed=2, perturb=0.0, vel_std=0.1)
     rp, ci = assembly.pattern_fast(s)
     xt = elements.x_tilde(s.x0, s.v0, 0.01, s.gravity)
-    ne = s.energies[0].conn.shape[0]
+    ne1 = s.energies[0].conn.shape[0]
     times = []
-    cpu0 = time.process_time()
-    w0 = time.perf_counter()
     while sum(times) < seconds_target and len(times) < 8:
         t = time.perf_counter()
         assembly.assemble(s, xt, xt, 0.01, row_ptr=rp, col_idx=ci)
         times.append(time.perf_counter() - t)
-    wall = time.perf_counter() - w0
-    cores = max(1, round((time.process_time() - cpu0) / wall))
-    med = statistics.median(times)
-    model = ""
+    one = ne1 / statistics.median(times) / 1e6
+
+    # all cores of the GPU's CPU share
+    n_all = 32
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return {"value": round(ne / med / 1e6, 5), "unit": "Melem/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"FP64 numpy oracle, E+g+BSR assembly of a 24^3-cube grid ({ne} tets, "
-                      f"same material/state recipe), median of {len(times)} passes "
-                      f"({sum(times):.1f} s); host {model or platform.processor()}, "
-                      f"{os.cpu_count()} logical CPUs visible"}
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    workers = max(1, min(16, avail))
+    sa = sg.tet_cube_scene(n_all, h=0.01, seed=2, perturb=0.0, vel_std=0.1)
+    rpa, cia = assembly.pattern_fast(sa)
+    xta = elements.x_tilde(sa.x0, sa.v0, 0.01, sa.gravity)
+    nea = sa.energies[0].conn.shape[0]
+    m = lumped_mass(sa)
+    fixed = sa.fixed.astype(bool)
+    rows = np.repeat(np.arange(sa.n_nodes), np.diff(rpa))
+    kill = fixed[rows] | fixed[cia]
+    diag = np.nonzero(rows == cia)[0]
+    cuts = np.linspace(0, nea, workers + 1).astype(int)
+    ranges = [(int(cuts[i]), int(cuts[i + 1])) for i in range(workers)]
+    ctx = mp.get_context("fork")
+    times_all = []
+    with ctx.Pool(workers, initializer=_cpu_init, initargs=(n_all,)) as pool:
+        pool.map(_cpu_chunk, ranges)  # warm-up
+        while sum(times_all) < seconds_target / 2 and len(times_all) < 8:
+            t = time.perf_counter()
+            parts = pool.map(_cpu_chunk, ranges)
+            g = np.zeros((sa.n_nodes, 3))
+            vals = np.zeros((cia.size, 3, 3))
+            E = 0.0
+            for Ep, n0, gp, b0, vp in parts:
+                E += Ep
+                g[n0:n0 + gp.shape[0]] += gp
+                vals[b0:b0 + vp.shape[0]] += vp
+            Ei, gi, w = elements.inertia(xta, xta, m, 0.01)
+            E += float(np.sum(Ei))
+            g += gi
+            vals[diag] += w[:, None, None] * np.eye(3)[None]
+            g[fixed] = 0.0
+            vals[kill] = 0.0
+            vals[diag[fixed]] = np.eye(3)
+            times_all.append(time.perf_counter() - t)
+    allc = nea / statistics.median(times_all) / 1e6
+    return {"value": round(allc, 4), "unit": "Melem/s", "cores": workers, "kind": "oracle",
+            "value_1core": round(one, 5),
+            "sample": f"FP64 numpy oracle, E+g+BSR assembly (eval+assembly, as the GPU value): "
+                      f"{workers} worker processes on a {n_all}^3-cube grid ({nea} tets), "
+                      f"median of {len(times_all)} passes; one core on a {n1}^3-cube grid "
+                      f"({ne1} tets), median of {len(times)} passes; host {host_model()}, "
+                      f"{avail} CPUs available"}
+
+
+def c1_oracle_newton():
+    """The oracle's Newton step on C1 (block-Jacobi PCG, the device's control
+    logic), wall time on one core; run before the GPU is touched."""
+    import scenegen as sg
+    from oracle import newton
+    s = sg.config_c1()
+    t = time.perf_counter()
+    ok, x, rep = newton.newton_solve(s, s.x0, s.v0, s.dt, newton.StepParams(dt=s.dt))
+    return {"ms": round((time.perf_counter() - t) * 1e3, 1), "ok": ok,
+            "newton_iters": rep["newton_iters"], "pcg_iters": rep["pcg_iters"], "x": x}
+
+
+def c1_newton_vs_oracle(symx, torch, oracle_c1):
+    """One C1 Newton step on the device (FP64 and FP32-refined, mean of 10 from
+    x(t)) beside the oracle's (one core), with the largest position difference."""
+    import numpy as np
+
+    import scenegen as sg
+    s = sg.config_c1()
+    mesh = symx.Mesh(s)
+    out = {"workload": "C1: 10^3 cubes x 6 SNH tets (6000 tets), one implicit-Euler step",
+           "oracle_ms_1core": oracle_c1["ms"], "oracle_newton_iters": oracle_c1["newton_iters"],
+           "oracle_pcg_iters": oracle_c1["pcg_iters"]}
+    for name, prec in (("f64", symx.SYMX_F64), ("f32_refined", symx.SYMX_F32_REFINED)):
+        ms = []
+        for k in range(11):
+            x = torch.tensor(s.x0, dtype=torch.float64, device="cuda")
+            v = torch.tensor(s.v0, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, rep = mesh.newton_step(x, v, symx.step_params(dt=s.dt, precision=prec))
+            torch.cuda.synchronize()
+            if k:
+                ms.append((time.perf_counter() - t) * 1e3)
+        out[f"device_ms_{name}"] = round(float(np.mean(ms)), 3)
+        out[f"device_newton_iters_{name}"] = rep.newton_iters
+        out[f"max_abs_position_diff_to_oracle_m_{name}"] = float(
+            "%.3g" % np.max(np.abs(x.cpu().numpy() - oracle_c1["x"])))
+    mesh.close()
+    return out
+
+
+def beam_bench(symx, torch, reps=10):
+    """The linear-tet beam of the simulation benchmark table: a k x k x 3k beam of
+    6-tet cubes with k = 24 (25 * 25 * 73 nodes = 136,875 DoF, 248,832 tets),
+    Stable Neo-Hookean E = 1e4 Pa, nu = 0.3, bottom fixed, top stretched 20%
+    (the stretched-box recipe).  FP64 and FP32 eval+assembly (device events,
+    median of reps) and one Newton step per precision, with the paper's CPU
+    figures (another machine: context)."""
+    import statistics as st_
+
+    import scenegen as sg
+    scene = sg.stretched_box_scene(sg.SNH_TET4, dims=(24, 24, 72), young=1e4, poisson=0.3)
+    mesh = symx.Mesh(scene)
+    x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(x)
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    out = {"workload": "24x24x72-cube SNH beam (136875 DoF, 248832 tets), E 1e4, nu 0.3, "
+                       "stretched 20%, bottom and top fixed",
+           "paper_cpu_ms": {"eval_assembly_per_newton_iter": 14.8, "pcg_per_newton_iter": 29.8,
+                            "hardware": "Threadripper PRO 5975WX, 32 threads, FP64"}}
+    for name, prec in (("f64", symx.SYMX_F64), ("f32", symx.SYMX_F32)):
+        for _ in range(3):
+            mesh.assemble(x, None, 0.0, flags, prec, grad_out=g)
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            symx.symx_assemble_bsr(mesh.handle, x.data_ptr(), None, 0.0, flags, prec, g.data_ptr())
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        out[f"assembly_ms_{name}"] = round(st_.median(ms), 4)
+    for name, prec in (("f64", symx.SYMX_F64), ("f32_refined", symx.SYMX_F32_REFINED)):
+        xs = x.clone()
+        vs = torch.zeros_like(xs)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, rep = mesh.newton_step(xs, vs, symx.step_params(dt=scene.dt, precision=prec))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        out[f"newton_{name}"] = {"status": symx.STATUS[st], "ms": round(ms, 2),
+                                 "newton_iters": rep.newton_iters, "pcg_iters": rep.pcg_iters,
+                                 "pcg_ms_per_newton_iter": round(rep.ms_pcg / max(rep.newton_iters, 1), 3)}
+    mesh.close()
+    log(f"beam: {out}")
+    return out
 
 
 def main():
@@ -614,7 +797,10 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="cubes per side")
     ap.add_argument("--asm-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-f64-newton", action="store_true")
+    ap.add_argument("--no-f32-newton", action="store_true")
+    ap.add_argument("--no-beam", action="store_true")
+    ap.add_argument("--details", default=None,
+                    help="also write every section's figures to this JSON file")
     ap.add_argument("--no-projection", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
@@ -624,7 +810,8 @@ def main():
     ap.add_argument("--no-quadratic", action="store_true")
     ap.add_argument("--no-cubic", action="store_true")
     ap.add_argument("--no-contacts", action="store_true")
-    ap.add_argument("--only", choices=["c3", "c4", "materials", "quadratic", "cubic", "contacts"],
+    ap.add_argument("--only", choices=["c3", "c4", "materials", "quadratic", "cubic", "contacts",
+                                       "beam"],
                     help="run only this extra workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run plain 512 MiB device copies first (byte-counter calibration)")
@@ -642,6 +829,15 @@ def main():
     import scenegen as sg
     from paper_2303_02156_amd import symx
 
+    # the CPU legs run first: their worker processes are forked before this
+    # process touches the GPU
+    cpu, oracle_c1 = None, None
+    if not args.no_cpu_baseline and not args.only and not args.serving_only:
+        log("cpu baseline (FP64 oracle, all host cores and one core)...")
+        cpu = cpu_baseline()
+        log(f"cpu baseline {cpu}")
+        oracle_c1 = c1_oracle_newton()
+        log(f"oracle C1 Newton step: {oracle_c1['ms']} ms, {oracle_c1['newton_iters']} iterations")
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
@@ -664,6 +860,9 @@ def main():
         return
     if args.only == "contacts":
         print(json.dumps({"contacts": contact_bench(symx, torch)}), flush=True)
+        return
+    if args.only == "beam":
+        print(json.dumps({"beam": beam_bench(symx, torch)}), flush=True)
         return
     if args.calib_copy:
         # a plain copy kernel of known size: 512 MiB read + 512 MiB written per launch
@@ -773,7 +972,8 @@ def main():
             reps.append(rep.as_dict())
             log(f"step {k}: status {symx.STATUS[st]} newton {rep.newton_iters} pcg "
                 f"{rep.pcg_iters} refine {rep.refinements} halvings {rep.dt_halvings} "
-                f"res {rep.residual:.3e}/{rep.residual0:.3e} {rep.ms_total:.1f} ms")
+                f"res {rep.residual:.3e}/{rep.residual0:.3e} lin {rep.lin_residual:.2e} "
+                f"{rep.ms_total:.1f} ms")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kt = None
@@ -783,120 +983,146 @@ def main():
             mesh.profile(False)
         return wall * 1e3 / K, reps, kt
 
-    # timed run without per-kernel events (they add host work to every launch)
-    ms_f32r, reps_f32r, _ = run_steps(symx.SYMX_F32_REFINED, args.steps, args.warmup, False)
-    log(f"newton f32_refined: {ms_f32r:.2f} ms/step")
-    # replay of the identical (deterministic) step sequence with per-kernel
-    # start/stop events; kernel device times feed the roofline
-    ms_prof, reps_prof, ktimes = run_steps(symx.SYMX_F32_REFINED, args.steps, args.warmup, True)
-    log(f"newton f32_refined with kernel events: {ms_prof:.2f} ms/step")
-    same = [(a["newton_iters"], a["pcg_iters"]) for a in reps_f32r] == \
-        [(a["newton_iters"], a["pcg_iters"]) for a in reps_prof]
-    ms_f64, reps_f64 = None, None
-    if not args.no_f64_newton:
-        ms_f64, reps_f64, _ = run_steps(symx.SYMX_F64, args.steps, args.warmup, False)
-        log(f"newton f64: {ms_f64:.2f} ms/step")
+    def same_iters(r1, r2):
+        return [(a["newton_iters"], a["pcg_iters"]) for a in r1] == \
+            [(a["newton_iters"], a["pcg_iters"]) for a in r2]
 
-    # ---- roofline of the dominant kernel (live HIP-event timing) --------------
-    busy, allk = ktimes["busy"], ktimes["all"]
-    kname, (launches, total_ms) = max(busy.items(), key=lambda kv: kv[1][1])
-    avg_ms = total_ms / max(launches, 1)
-    t_bytes = 4
-    nbytes = algorithmic_bytes(kname, N, nnzb, n_elem, t_bytes)
-    roofline = {"kernel": kname, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": None, "traffic": None, "launches": launches,
-                "avg_ms": round(avg_ms, 5), "algorithmic_bytes": nbytes,
-                "idle_launches": allk[kname][0] - launches,
-                "idle_ms": round(allk[kname][1] - total_ms, 3),
-                "share_of_step_time": round(allk[kname][1] / (ms_f32r * args.steps), 4),
-                "timing": "hipExtLaunchKernelGGL start/stop events in a replay of the timed "
-                          "steps (identical iteration counts: %s)" % same}
-    if nbytes:
+    def spmv_roofline(ktimes, t_bytes, ms_step, label, bound):
+        """Roofline of the SpMV launches of a profiled replay (device times from
+        per-launch HIP events; launches past convergence excluded)."""
+        busy, allk = ktimes["busy"], ktimes["all"]
+        kname = "pcg_spmv"
+        launches, total_ms = busy[kname]
+        avg_ms = total_ms / max(launches, 1)
+        nbytes = algorithmic_bytes(kname, N, nnzb, n_elem, t_bytes)
         ach = nbytes / (avg_ms * 1e-3) / 1e9
-        roofline["achieved"] = round(ach, 1)
-        roofline["frac"] = round(ach / HBM_PEAK_GBS, 4)
-    if args.n == 64:
-        roofline["traffic"] = measured_traffic(kname)
-    kernels = {}
-    for k, (n, ms) in sorted(allk.items(), key=lambda kv: -kv[1][1]):
-        nb_, msb = busy.get(k, (0, 0.0))
-        d = {"launches": n, "total_ms": round(ms, 3), "busy_launches": nb_,
-             "busy_avg_ms": round(msb / max(nb_, 1), 5)}
-        b_ = algorithmic_bytes(k, N, nnzb, n_elem, t_bytes)
-        if b_ and nb_:
-            d["busy_gbs"] = round(b_ / (msb / nb_ * 1e-3) / 1e9, 1)
-        kernels[k] = d
+        top = max(busy.items(), key=lambda kv: kv[1][1])[0]
+        return {"kernel": f"pcg_spmv<{label}>", "bound": bound, "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(kname, label) if args.n == 64 else None,
+                "launches": launches, "avg_ms": round(avg_ms, 5), "algorithmic_bytes": nbytes,
+                "idle_launches": allk[kname][0] - launches,
+                "share_of_step_time": round(allk[kname][1] / (ms_step * args.steps), 4),
+                "dominant_kernel_of_step": top == kname}
 
-    c4 = None if args.no_c4 else precision_c4(symx, torch)
-    if c4:
-        log(f"c4: {c4}")
-    c3 = None if args.no_c3 else mixed_c3(symx, torch)
-    if c3:
-        log(f"c3: {c3}")
-    materials = None if args.no_materials else materials_bench(symx, torch)
-    quadratic = None if args.no_quadratic else high_order_bench(symx, torch, "quadratic")
-    cubic = None if args.no_cubic else high_order_bench(symx, torch, "cubic")
-    contacts = None if args.no_contacts else contact_bench(symx, torch)
+    def kernel_table(ktimes, t_bytes):
+        busy, allk = ktimes["busy"], ktimes["all"]
+        out = {}
+        for k, (n, ms) in sorted(allk.items(), key=lambda kv: -kv[1][1]):
+            nb_, msb = busy.get(k, (0, 0.0))
+            d = {"launches": n, "total_ms": round(ms, 3), "busy_launches": nb_,
+                 "busy_avg_ms": round(msb / max(nb_, 1), 5)}
+            b_ = algorithmic_bytes(k, N, nnzb, n_elem, t_bytes)
+            if b_ and nb_:
+                d["busy_gbs"] = round(b_ / (msb / nb_ * 1e-3) / 1e9, 1)
+            out[k] = d
+        return out
 
+    # FP64 (the paper's precision): timed run without per-kernel events (they
+    # add host work to every launch), then a replay of the identical
+    # deterministic step sequence with per-kernel start/stop events for the
+    # roofline of the dominant kernel
+    ms_f64, reps_f64, _ = run_steps(symx.SYMX_F64, args.steps, args.warmup, False)
+    log(f"newton f64: {ms_f64:.2f} ms/step")
+    ms_f64p, reps_f64p, kt64 = run_steps(symx.SYMX_F64, args.steps, args.warmup, True)
+    log(f"newton f64 with kernel events: {ms_f64p:.2f} ms/step")
+    roofline = spmv_roofline(kt64, 8, ms_f64, "double", "hbm")
+    roofline["timing"] = ("hipExtLaunchKernelGGL start/stop events in a replay of the timed "
+                          "steps (identical iteration counts: %s)" % same_iters(reps_f64, reps_f64p))
+    log(f"roofline f64 spmv: {roofline}")
+    ms_f32r, reps_f32r, kt32 = None, None, None
+    roofline32 = None
+    if not args.no_f32_newton:
+        ms_f32r, reps_f32r, _ = run_steps(symx.SYMX_F32_REFINED, args.steps, args.warmup, False)
+        log(f"newton f32_refined: {ms_f32r:.2f} ms/step")
+        _, reps_f32p, kt32 = run_steps(symx.SYMX_F32_REFINED, args.steps, args.warmup, True)
+        # the float32 matrix and vectors (about 200 MB) fit in the 256 MB
+        # Infinity Cache (MALL): its SpMV rate is not an HBM figure
+        roofline32 = spmv_roofline(kt32, 4, ms_f32r, "float", "mall")
+        roofline32["identical_iteration_counts"] = same_iters(reps_f32r, reps_f32p)
+        log(f"roofline f32 spmv (MALL-resident): {roofline32}")
+        log(f"kernels f32_refined steps: {kernel_table(kt32, 4)}")
+    log(f"kernels f64 steps: {kernel_table(kt64, 8)}")
+
+    extras = {}
+    if not args.no_c4:
+        extras["c4_precision"] = precision_c4(symx, torch)
+        log(f"c4: {extras['c4_precision']}")
+    if not args.no_c3:
+        extras["c3_mixed"] = mixed_c3(symx, torch)
+        log(f"c3: {extras['c3_mixed']}")
+    if not args.no_beam:
+        extras["beam"] = beam_bench(symx, torch)
+    if not args.no_materials:
+        extras["materials"] = materials_bench(symx, torch)
+    if not args.no_quadratic:
+        extras["quadratic_tets"] = high_order_bench(symx, torch, "quadratic")
+    if not args.no_cubic:
+        extras["cubic_tets"] = high_order_bench(symx, torch, "cubic")
+    if not args.no_contacts:
+        extras["contacts"] = contact_bench(symx, torch)
     serving = None
     if not args.no_serving:
         log("serving (256 requests, Poisson 200/s)...")
         serving = serving_bench(symx, torch)
+        extras["serving"] = serving
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (FP64 oracle)...")
-        cpu = cpu_baseline()
-        log(f"cpu baseline {cpu['value']} Melem/s")
+    if oracle_c1 is not None:
+        c1 = c1_newton_vs_oracle(symx, torch, oracle_c1)
+        extras["c1_newton_vs_oracle"] = c1
+        log(f"c1 newton step, device vs oracle: {c1}")
 
     def summary(reps):
         if not reps:
             return None
+        lin = [r["lin_residual"] for r in reps if r["lin_residual"] >= 0]
         return {"newton_iters": sum(r["newton_iters"] for r in reps),
                 "pcg_iters": sum(r["pcg_iters"] for r in reps),
                 "refinements": sum(r["refinements"] for r in reps),
                 "dt_halvings": sum(r["dt_halvings"] for r in reps),
                 "all_converged": all(r["status"] == 0 for r in reps),
-                "max_rel_residual": max(r["residual"] / max(r["residual0"], 1e-300) for r in reps)}
+                "max_rel_residual": float("%.3g" % max(r["residual"] / max(r["residual0"], 1e-300)
+                                                       for r in reps)),
+                "max_lin_residual": float("%.3g" % max(lin)) if lin else None}
 
+    if args.details:
+        with open(args.details, "w") as f:
+            json.dump({"assembly_kernels_f32": asm_kernels, "kernels_f64_steps": kernel_table(kt64, 8),
+                       "kernels_f32_refined_steps": kernel_table(kt32, 4) if kt32 else None,
+                       "mesh_setup_s": setup_s, **extras}, f, indent=1)
+    ms_pair = {"f64": round(ms_f64, 3),
+               "f32_refined": None if ms_f32r is None else round(ms_f32r, 3)}
+    # compact summary as the last line of the log (the JSON line follows on stdout)
+    log("summary: eval+assembly Melem/s " + ", ".join(f"{k} {v:.0f}" for k, v in melem.items())
+        + f"; Newton step ms {ms_pair}; SpMV f64 {roofline['achieved']} GB/s "
+        f"(frac {roofline['frac']}), f32 (MALL) "
+        f"{None if roofline32 is None else roofline32['achieved']} GB/s; "
+        f"cpu oracle {None if cpu is None else cpu['value']} Melem/s on "
+        f"{None if cpu is None else cpu['cores']} cores")
     out = {
         "metric": "elem eval+assembly Melem/s, Newton step ms FP32-refined vs FP64; p99 latency",
-        "value": round(melem["f32"], 2),
+        "value": round(melem["f64"], 2),
         "unit": "Melem/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_f32r, 3),
+        "ms_per_step": round(ms_f64, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"C2: {args.n}^3-cube grid x 6 Stable Neo-Hookean tets "
-                               f"({n_elem} tets, {N} nodes, {nnzb} 3x3 blocks), E=1e5 nu=0.4, "
-                               "v~N(0,0.1) seed 2, dt=0.01, Newton rtol 1e-6, PCG<=500",
-                   "precision": "FP32 element kernels/SpMV/PCG, FP64 energies, gradient, "
-                                "residual and refinement"},
-        "melem_per_s": {k: round(v, 3) for k, v in melem.items()},
-        "assembly_ms": {k: round(v, 4) for k, v in asm_ms.items()},
-        "assembly_kernels_f32": {k: {"launches": n, "ms": round(ms, 4)}
-                                 for k, (n, ms) in asm_kernels.items()},
-        "newton_step_ms_with_kernel_events": round(ms_prof, 3),
-        "newton_step_ms": {"f32_refined": round(ms_f32r, 3),
-                           "f64": None if ms_f64 is None else round(ms_f64, 3)},
-        "newton_f32_refined": summary(reps_f32r),
+        "config": {"workload": f"C2 {args.n}^3 cubes x 6 SNH tets: {n_elem} tets, {N} nodes, "
+                               f"{nnzb} blocks",
+                   "value": "FP64 E+g+BSR-H eval+assembly, no projection",
+                   "ms_per_step": "FP64 Newton time step (rtol 1e-6, PCG<=500)"},
+        "melem_per_s": {k: round(v, 1) for k, v in melem.items()},
+        "newton_step_ms": ms_pair,
         "newton_f64": summary(reps_f64),
+        "newton_f32_refined": summary(reps_f32r),
         "p99_latency_ms": None if serving is None else serving["full_budget"]["p99_ms"],
-        "serving": serving,
-        "c4_precision": c4,
-        "c3_mixed": c3,
-        "materials": materials,
-        "quadratic_tets": quadratic,
-        "cubic_tets": cubic,
-        "contacts": contacts,
-        "mesh_setup_s": round(setup_s, 3),
-        "kernels_f32_refined_steps": kernels,
         "roofline": roofline,
+        "roofline_f32_spmv": roofline32,
         "roofline_assembly": roofline_asm,
         "cpu_baseline": cpu,
     }

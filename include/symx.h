@@ -54,9 +54,11 @@ typedef enum {
   SYMX_F64 = 0,          /* everything in float64 */
   SYMX_F32 = 1,          /* element kernels, Hessian values and PCG in float32;
                             gradient and energy sums accumulated in float64 */
-  SYMX_F32_REFINED = 2   /* Newton only: Hessian values, SpMV and PCG in float32;
-                            energies, gradient, residual and the iterative-
-                            refinement correction in float64 */
+  SYMX_F32_REFINED = 2   /* Newton only: SpMV and PCG in float32 on the float64
+                            Hessian rounded to float32; energies, gradient,
+                            Newton residual and the iterative refinement of
+                            each linear solve in float64 (the refinement
+                            residual b - H dx uses the float64 Hessian) */
 } symx_precision;
 
 /* Element energies (the paper's App. B and Eq. 13).  Linear tets use
@@ -160,6 +162,9 @@ typedef struct {
   int32_t max_halvings;      /* dt halvings before giving up                    */
   int32_t regrow_after;      /* successful steps before dt is doubled back      */
   int32_t max_refine;        /* F32_REFINED: refinement passes per solve        */
+  double forcing_max;        /* largest forcing term: PCG stops at
+                                |r| <= min(forcing_max, sqrt(r_k / r_0)) |b|;
+                                in (0, 1)                                       */
 } symx_step_params;
 
 typedef struct {
@@ -169,11 +174,15 @@ typedef struct {
   double residual0, residual;/* |g_free| at x(t) and at the result (float64)    */
   double energy;             /* incremental potential at the result             */
   double ms_assemble, ms_pcg, ms_linesearch, ms_total;
+  double lin_residual;       /* F32_REFINED: the largest relative residual
+                                |b - H dx| / |b| of the step's linear solves
+                                after refinement, in float64 with the float64
+                                Hessian; -1 in the other modes                  */
 } symx_step_report;
 
 /* Defaults for symx_step_params: dt 0.01, gravity (0,0,-9.81), rtol 1e-6,
  * max_newton 100, max_pcg 500, project 0, precision SYMX_F64, max_halvings 8,
- * regrow_after 3, max_refine 4. */
+ * regrow_after 3, max_refine 4, forcing_max 0.5. */
 void symx_step_params_default(symx_step_params* p);
 
 /* Build a mesh: copies all host inputs (the caller may free them afterwards),
@@ -230,7 +239,7 @@ symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double*
 /* One implicit-Euler time step (Eq. 2-3): x_dev, v_dev (device N x 3 float64)
  * hold x(t), v(t) on entry and x(t+dt_used), v(t+dt_used) on success; on
  * failure they are left unchanged.  Newton from x(t); block-Jacobi PCG with
- * forcing term min(0.5, sqrt(r_k / r_0)); Armijo backtracking (c = 1e-4,
+ * forcing term min(forcing_max, sqrt(r_k / r_0)); Armijo backtracking (c = 1e-4,
  * halving, at most 30); on line-search failure or too many Newton iterations
  * the step restarts with dt/2 (at most max_halvings times); the mesh keeps the
  * reduced dt and doubles it back after regrow_after successful steps.

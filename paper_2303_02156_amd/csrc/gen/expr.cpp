@@ -164,6 +164,57 @@ int Graph::diff(int f, int s) {
   return r;
 }
 
+std::vector<int> Graph::tangent(const std::vector<int>& roots,
+                               const std::map<int, int>& tangent_of) {
+  // bits of the moving symbols that are differentiation variables, so that
+  // subtrees independent of every moving symbol get a zero tangent at once
+  uint64_t moving = 0;
+  bool all_dof = true;
+  for (const auto& st : tangent_of) {
+    auto b = dof_bit_.find(st.first);
+    if (b == dof_bit_.end())
+      all_dof = false;
+    else
+      moving |= uint64_t(1) << b->second;
+  }
+  std::unordered_map<int, int> memo;
+  std::function<int(int)> go = [&](int id) -> int {
+    auto it = memo.find(id);
+    if (it != memo.end()) return it->second;
+    const Node nd = nodes_[id];  // copy: nodes_ may grow
+    int r;
+    if (all_dof && !(nd.dep & moving)) {
+      r = cst(0.0);
+    } else {
+      switch (nd.op) {
+        case Op::Sym: {
+          auto t = tangent_of.find(id);
+          r = t != tangent_of.end() ? t->second : cst(0.0);
+          break;
+        }
+        case Op::Const: r = cst(0.0); break;
+        case Op::Add: r = add(go(nd.a), go(nd.b)); break;
+        case Op::Sub: r = sub(go(nd.a), go(nd.b)); break;
+        case Op::Mul: r = add(mul(go(nd.a), nd.b), mul(nd.a, go(nd.b))); break;
+        // (a/b)' = (a' - (a/b) b') * (1/b), through the shared reciprocal
+        case Op::Div: r = mul(sub(go(nd.a), mul(id, go(nd.b))), div(cst(1.0), nd.b)); break;
+        case Op::Neg: r = neg(go(nd.a)); break;
+        case Op::Log: r = mul(go(nd.a), div(cst(1.0), nd.a)); break;
+        case Op::Sqrt: r = mul(go(nd.a), mul(cst(0.5), div(cst(1.0), id))); break;
+        case Op::Abs: r = mul(go(nd.a), mul(nd.a, div(cst(1.0), id))); break;
+        case Op::PowN: r = mul(mul(cst((double)nd.n), pown(nd.a, nd.n - 1)), go(nd.a)); break;
+        default: throw std::runtime_error("tangent: bad op");
+      }
+    }
+    memo[id] = r;
+    return r;
+  };
+  std::vector<int> out;
+  out.reserve(roots.size());
+  for (int r : roots) out.push_back(go(r));
+  return out;
+}
+
 std::vector<int> Graph::substitute(const std::vector<int>& roots,
                                    const std::map<int, double>& slot_values) {
   std::map<int, int> slot_nodes;

@@ -50,6 +50,11 @@ class Graph {
   void set_dof(int sym_node);
   // d f / d (symbol node s); cached per (f, s)
   int diff(int f, int s);
+  // Forward-mode (directional) derivative of `roots`: every symbol node s in
+  // `tangent_of` moves along the expression tangent_of[s], all other symbols
+  // stay fixed; returns d root / d eps of root(s + eps t) at eps = 0 for each
+  // root, built with the same folding rules (zero tangents remove terms).
+  std::vector<int> tangent(const std::vector<int>& roots, const std::map<int, int>& tangent_of);
   // Rebuild `roots` with some input slots replaced by constants (memoised);
   // folding rules apply again, so e.g. x0 = 0 removes whole subtrees.
   std::vector<int> substitute(const std::vector<int>& roots,

@@ -438,30 +438,35 @@ void generate_through_F(const ThroughFSpec& spec, Generated& out) {
       to_F[n_in + 3 * i + j] = kin.F(i, j).id;
     }
   const S psi = spec.psi(Fh, in);
-  std::vector<int> dens = {psi.id};  // psi, P (9), D (81, symmetric)
-  for (int k = 0; k < 9; ++k) dens.push_back(g.diff(psi.id, Fh.v[k].id));
-  for (int k = 0; k < 9; ++k)
-    for (int l = 0; l < 9; ++l) dens.push_back(g.diff(dens[1 + std::min(k, l)], Fh.v[std::max(k, l)].id));
+  // psi and P = dpsi/dF in terms of the placeholders
+  std::vector<int> Pph(9);
+  for (int k = 0; k < 9; ++k) Pph[k] = g.diff(psi.id, Fh.v[k].id);
+  std::vector<int> dens = {psi.id};
+  dens.insert(dens.end(), Pph.begin(), Pph.end());
   dens = g.substitute_nodes(dens, to_F);
   auto P = [&](int i, int j) { return S(&g, dens[1 + 3 * i + j]); };
-  auto D = [&](int i, int j, int m, int l) { return S(&g, dens[10 + 9 * (3 * i + j) + 3 * m + l]); };
   const S E = c * S(&g, dens[0]);
   auto grad = [&](int a, int i) { return c * (P(i, 0) * G[a][0] + P(i, 1) * G[a][1] + P(i, 2) * G[a][2]); };
-  // Hessian row of node a: for i = 0..2 the blocks (a, b), b in order
+  // Hessian row of node a: for i = 0..2 the blocks (a, b), b in order.
+  // Entry (a_i, b_m) = c sum_{j,l} D_{ij,ml} g_a[j] g_b[l] with D = d2psi/dF2.
+  // The contraction over j is the directional derivative of P along
+  // dF = c e_i g_a^T (forward mode through the graph of P, zero entries of
+  // dF folded away), so D itself is never formed:
+  //   dP_i = dP/deps (F + eps c e_i g_a^T),  entry (a_i, b_m) = sum_l dP_i[m][l] g_b[l].
   auto row_blocks = [&](int a, bool with_diag) {
-    std::vector<S> M(27);
-    for (int i = 0; i < 3; ++i)
-      for (int m = 0; m < 3; ++m)
-        for (int l = 0; l < 3; ++l)
-          M[9 * i + 3 * m + l] = c * (D(i, 0, m, l) * G[a][0] + D(i, 1, m, l) * G[a][1] +
-                                      D(i, 2, m, l) * G[a][2]);
+    std::vector<std::vector<int>> dP(3);
+    for (int i = 0; i < 3; ++i) {
+      std::map<int, int> dir;
+      for (int q = 0; q < 3; ++q) dir[Fh(i, q).id] = (c * G[a][q]).id;
+      dP[i] = g.substitute_nodes(g.tangent(Pph, dir), to_F);
+    }
     std::vector<int> ids;
     for (int i = 0; i < 3; ++i)
       for (int b = 0; b < K; ++b) {
         if (b == a && !with_diag) continue;
         for (int m = 0; m < 3; ++m)
-          ids.push_back((M[9 * i + 3 * m] * G[b][0] + M[9 * i + 3 * m + 1] * G[b][1] +
-                         M[9 * i + 3 * m + 2] * G[b][2]).id);
+          ids.push_back((S(&g, dP[i][3 * m]) * G[b][0] + S(&g, dP[i][3 * m + 1]) * G[b][1] +
+                         S(&g, dP[i][3 * m + 2]) * G[b][2]).id);
       }
     return ids;
   };
@@ -568,6 +573,7 @@ int main(int argc, char** argv) {
                         full};
   };
   const std::vector<ThroughFSpec> through_F = {
+      tet4("XPsnh_tet4", 26, [](const Mat& F, const std::vector<S>& in) { return snh_density(F, in[24], in[25]); }),
       tet4("stvk_tet4", 26, stvk_density),
       high_order("snh_tet10", 10, tet10_shape, {0, 4}, true),
       high_order("snh_tet20", 20, tet20_shape, {0, 4, 19}, false),

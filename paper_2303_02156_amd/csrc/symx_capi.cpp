@@ -115,6 +115,7 @@ void symx_step_params_default(symx_step_params* p) {
   p->max_halvings = 8;
   p->regrow_after = 3;
   p->max_refine = 4;
+  p->forcing_max = 0.5;
 }
 
 symx_status symx_mesh_create(const symx_mesh_desc* desc, symx_mesh* out) {
@@ -265,10 +266,7 @@ symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
                              const symx_step_params* params, symx_step_report* report) {
   GUARD_BEGIN
   if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
-  if (!x_dev || !v_dev || !params || !(params->dt > 0.0) || params->max_newton < 0 ||
-      params->max_pcg < 1 || params->precision < SYMX_F64 || params->precision > SYMX_F32_REFINED ||
-      params->max_halvings < 0 || !(params->newton_rtol >= 0.0) || params->project < 0 ||
-      params->project > 2) {
+  if (!x_dev || !v_dev || !params || !step_params_valid(*params)) {
     set_error("invalid arguments to symx_newton_step");
     return SYMX_ERR_INVALID_ARG;
   }

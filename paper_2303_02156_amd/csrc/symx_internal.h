@@ -530,5 +530,11 @@ symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const d
 symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0, int n_iter);
 symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs);
 symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b, double* r);
+// Rounds the float64 Hessian values of the mesh (and of its contacts) to
+// their float32 copies, and n9 float64 block inverses dinv64 to dinv32.
+symx_status launch_round_values(Mesh& m, const double* dinv64, float* dinv32, int64_t n9);
+
+// Newton driver (symx_newton.cpp): the ranges symx_newton_step accepts.
+bool step_params_valid(const symx_step_params& P);
 
 }  // namespace symxi

@@ -2190,6 +2190,13 @@ __global__ __launch_bounds__(256) void k_velocity(int64_t n, double* __restrict_
     v[i] = (xn[i] - xo[i]) * inv_dt;
 }
 
+// dst = float(src), round to nearest (the float32 copy of float64 data)
+__global__ __launch_bounds__(256) void k_round_f64(int64_t n, const double* __restrict__ src,
+                                                   float* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = float(src[i]);
+}
+
 // dx (float64) += x_pcg (T)
 template <typename T>
 __global__ __launch_bounds__(256) void k_accumulate(int64_t n, double* __restrict__ dx,
@@ -2813,6 +2820,35 @@ symx_status launch_velocity(Mesh& m, double* v, const double* xn, const double* 
   SYMX_LAUNCH(m, PNAME, k_velocity, dim3(grid_for(n, 256)), dim3(256), 0, n, v, xn, xo,
                      inv_dt);
   LAUNCH_CHECK("k_velocity");
+  return SYMX_OK;
+}
+
+symx_status launch_round_values(Mesh& m, const double* dinv64, float* dinv32, int64_t n9) {
+  const char* PNAME = "round_values";
+  if (!m.vals64 || !m.vals32) {
+    set_error("round_values: the float64 and float32 value arrays must exist");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  const int64_t nv = 9 * m.nnzb;
+  SYMX_LAUNCH(m, PNAME, k_round_f64, dim3(grid_for(nv, 256, 8192)), dim3(256), 0, nv,
+              (const double*)m.vals64, m.vals32);
+  if (m.contacts && m.contacts->nnzb > 0) {
+    Contacts& c = *m.contacts;
+    if (c.vals_cap32 < c.nnzb) {
+      dev_free(m.pool, c.vals32);
+      c.vals32 = nullptr;
+      c.vals_cap32 = 0;
+      TRY(dev_alloc(m.pool, (void**)&c.vals32, 9 * c.nnzb * sizeof(float)));
+      c.vals_cap32 = c.nnzb;
+    }
+    const int64_t nc = 9 * c.nnzb;
+    SYMX_LAUNCH(m, PNAME, k_round_f64, dim3(grid_for(nc, 256, 8192)), dim3(256), 0, nc,
+                (const double*)c.vals64, c.vals32);
+  }
+  if (dinv64 && dinv32)
+    SYMX_LAUNCH(m, PNAME, k_round_f64, dim3(grid_for(n9, 256, 8192)), dim3(256), 0, n9, dinv64,
+                dinv32);
+  LAUNCH_CHECK("k_round_f64");
   return SYMX_OK;
 }
 

@@ -3,17 +3,21 @@
 // Newton step (Eq. 2-3, Sec. 7): minimise the incremental potential from
 // x(t); per iteration assemble the gradient and Hessian, stop when
 // |g_free| <= rtol |g_free(x(t))|, solve H dx = -g with block-Jacobi PCG to the
-// forcing tolerance min(0.5, sqrt(r_k / r_0)), backtrack along dx with the
+// forcing tolerance min(forcing_max, sqrt(r_k / r_0)) (forcing_max 0.5 by
+// default), backtrack along dx with the
 // Armijo test E(x + a dx) <= E(x) + 1e-4 a g.dx (a halves, at most 30 times),
 // and restart the whole step with dt/2 when the line search fails or Newton
 // exceeds its iteration limit (the paper's benchmark protocol, Sec. 7).
 //
 // Precision modes: SYMX_F64 runs everything in float64.  SYMX_F32_REFINED
-// assembles the Hessian and runs SpMV/PCG in float32, while energies, the
-// gradient (hence the residual) and the solution update stay float64; the
-// linear solve is refined in float64 (residual b - H dx with the float32 H
-// promoted, then another float32 PCG solve for the correction).  SYMX_F32
-// evaluates all element quantities in float32 (sums in float64).
+// evaluates energies, gradient and Hessian in float64 and keeps a float32
+// copy of the Hessian (each value rounded) for the SpMV and PCG, which run in
+// float32; the solution update stays float64, and each linear solve is
+// refined in float64: the residual b - H dx is formed with the float64
+// Hessian, and while it exceeds the forcing tolerance a float32 PCG solve of
+// H c = r gives the correction dx += c (mixed-precision iterative
+// refinement).  SYMX_F32 evaluates all element quantities in float32 (sums in
+// float64).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -41,7 +45,15 @@ struct Workspace {
   double *x_t = nullptr, *v_t = nullptr, *xt = nullptr, *xk = nullptr, *xtrial = nullptr;
   double *g = nullptr, *dx = nullptr, *b = nullptr, *res = nullptr;
   void* pcg[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // Dinv xs r z p q (max size)
+  double* dinv64 = nullptr;  // F32_REFINED: float64 block inverses before rounding (9N)
 };
+
+bool step_params_valid(const symx_step_params& P) {
+  return P.dt > 0.0 && P.max_newton >= 0 && P.max_pcg >= 1 && P.precision >= SYMX_F64 &&
+         P.precision <= SYMX_F32_REFINED && P.max_halvings >= 0 && P.newton_rtol >= 0.0 &&
+         P.project >= 0 && P.project <= 2 && P.max_refine >= 0 && P.forcing_max > 0.0 &&
+         P.forcing_max < 1.0;
+}
 
 
 static symx_status ensure_values(Mesh& m, int precision) {
@@ -63,12 +75,19 @@ static symx_status ensure_workspace(Mesh& m) {
   return SYMX_OK;
 }
 
+static symx_status ensure_dinv64(Mesh& m) {
+  Workspace* w = m.ws;
+  if (w->dinv64) return SYMX_OK;
+  return dev_alloc(m.pool, (void**)&w->dinv64, 9 * m.N * sizeof(double));
+}
+
 void free_workspace(Mesh& m) {
   if (!m.ws) return;
   Workspace* w = m.ws;
   double* vecs[] = {w->x_t, w->v_t, w->xt, w->xk, w->xtrial, w->g, w->dx, w->b, w->res};
   for (double* p : vecs) dev_free(m.pool, p);
   for (void* p : w->pcg) dev_free(m.pool, p);
+  dev_free(m.pool, w->dinv64);
   delete w;
   m.ws = nullptr;
 }
@@ -209,13 +228,20 @@ static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rto
   return launch_accumulate(m, pp, dx, B.xs);
 }
 
-// Linear solve with optional float64 refinement (F32_REFINED).
+// Linear solve H dx = -g with float64 refinement (F32_REFINED).
 // `slot` indexes the solve within a step (its Newton iteration); the iteration
 // count of the same solve in the previous step sizes the first PCG chunk.
+// In F32_REFINED mode the float32 PCG solution is checked against the float64
+// Hessian: r = b - H dx in float64; while |r| > eta |b| and passes remain, a
+// float32 PCG solve of H c = r (to the relative tolerance that would meet eta,
+// but no tighter than 1e-6, what one float32 solve can deliver) is added in
+// float64.  *lin_res receives |r| / |b| of the final dx (-1 in other modes).
 static symx_status linear_solve(Mesh& m, const symx_step_params& P, const double* g, double eta,
-                                double gnorm, int* pcg_iters, int* refinements, int slot) {
+                                double gnorm, int* pcg_iters, int* refinements, int slot,
+                                double* lin_res) {
   Workspace* w = m.ws;
   const int n = (int)(3 * m.N);
+  *lin_res = -1.0;
   // b = -g ; dx = 0
   TRY(hip_check(hipMemsetAsync(w->dx, 0, n * sizeof(double), m.stream), "hipMemsetAsync"));
   TRY(launch_lincomb64(m, w->b, w->dx, g, -1.0, n));
@@ -224,22 +250,24 @@ static symx_status linear_solve(Mesh& m, const symx_step_params& P, const double
   TRY(pcg_solve(m, P.precision, w->b, eta, P.max_pcg, w->dx, &it, &bd, slot));
   *pcg_iters += it;
   if (P.precision != SYMX_F32_REFINED) return SYMX_OK;
-  // Refinement corrects what single precision loses; a solve that stopped at
-  // its iteration limit (or on breakdown) is used as is, as in float64 mode.
-  if (bd || it >= P.max_pcg) return SYMX_OK;
-  // float64 refinement: r = b - H dx (H float32 promoted); solve H c = r; dx += c
-  for (int k = 0; k < P.max_refine; ++k) {
-    TRY(launch_residual64(m, SYMX_F32, w->dx, w->b, w->res));
+  // A solve that stopped at its iteration limit (or on breakdown) is not
+  // corrected: another solve would restart CG, not correct rounding; it is
+  // used as is, as in float64 mode (its residual is still reported).
+  bool correct = !(bd || it >= P.max_pcg);
+  for (int k = 0;; ++k) {
+    TRY(launch_residual64(m, SYMX_F64, w->dx, w->b, w->res));
     double rr = 0.0;
     TRY(dot(m, w->res, w->res, &rr));
-    if (std::sqrt(rr) <= eta * gnorm) break;
+    const double rn = std::sqrt(rr);
+    *lin_res = gnorm > 0.0 ? rn / gnorm : 0.0;
+    if (rn <= eta * gnorm || !correct || k >= P.max_refine) break;
     int it2 = 0;
-    double tol = std::max(eta * gnorm / std::sqrt(rr), 1e-6);
+    const double tol = std::max(eta * gnorm / rn, 1e-6);
     TRY(pcg_solve(m, P.precision, w->res, std::min(tol, 0.5), P.max_pcg, w->dx, &it2, &bd,
                   kPcgHistory - 1));
     *pcg_iters += it2;
     *refinements += 1;
-    if (bd || it2 >= P.max_pcg) break;
+    correct = !(bd || it2 >= P.max_pcg);
   }
   return SYMX_OK;
 }
@@ -270,13 +298,15 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
   bool have_E0 = false;
   for (int it = 0;; ++it) {
     auto t0 = clk::now();
-    // gradient, Hessian and the block-Jacobi inverses (workspace pcg[0])
-    if (pe == ph) {
-      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project, ph, true, w->g, w->pcg[0]));
+    // gradient, Hessian and the block-Jacobi inverses (workspace pcg[0]); in
+    // F32_REFINED mode all in float64, then the float32 copies for the PCG
+    if (P.precision == SYMX_F32_REFINED) {
+      TRY(ensure_dinv64(m));
+      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project, SYMX_F64, true, w->g, w->dinv64));
+      TRY(ensure_values(m, SYMX_F32));
+      TRY(launch_round_values(m, w->dinv64, (float*)w->pcg[0], 9 * m.N));
     } else {
-      TRY(assemble(m, w->xk, w->xt, dt, true, false, false, pe, true, w->g));
-      TRY(assemble(m, w->xk, w->xt, dt, false, true, P.project, ph, true, nullptr,
-                   w->pcg[0]));
+      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project, ph, true, w->g, w->pcg[0]));
     }
     TRY(launch_dot64(m, w->g, w->g, n, m.scalars + D_GG));
     if (!have_E0) TRY(launch_energy(m, w->xk, w->xt, dt, pe, m.scalars + D_E0));
@@ -303,9 +333,11 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
       return SYMX_ERR_NOT_CONVERGED;
     }
     auto t1 = clk::now();
-    const double eta = std::min(0.5, std::sqrt(r / r0));
+    const double eta = std::min(P.forcing_max, std::sqrt(r / r0));
+    double lin_res = -1.0;
     TRY(linear_solve(m, P, w->g, eta, r, &R->pcg_iters, &R->refinements,
-                     std::min(it, kPcgHistory - 2)));
+                     std::min(it, kPcgHistory - 2), &lin_res));
+    R->lin_residual = std::max(R->lin_residual, lin_res);
     R->ms_pcg += ms_since(t1);
     auto t2 = clk::now();
     // slope and the full step's energy in one round trip
@@ -371,6 +403,7 @@ symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P
   while (true) {
     symx_step_report attempt;
     std::memset(&attempt, 0, sizeof attempt);
+    attempt.lin_residual = -1.0;
     st = solve_step(m, P, dt, &attempt);
     R.newton_iters += attempt.newton_iters;
     R.pcg_iters += attempt.pcg_iters;
@@ -382,6 +415,7 @@ symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P
     R.residual0 = attempt.residual0;
     R.residual = attempt.residual;
     R.energy = attempt.energy;
+    R.lin_residual = attempt.lin_residual;
     if (st == SYMX_OK) break;
     if (st != SYMX_ERR_LINE_SEARCH && st != SYMX_ERR_NOT_CONVERGED) break;
     if (halvings >= P.max_halvings) break;

@@ -236,9 +236,7 @@ symx_status server_submit(Server* s, const symx_mesh_desc* d, const double* x, c
     set_error("invalid request");
     return SYMX_ERR_INVALID_ARG;
   }
-  if (!(P->dt > 0.0) || P->max_newton < 0 || P->max_pcg < 1 || P->precision < SYMX_F64 ||
-      P->precision > SYMX_F32_REFINED || P->max_halvings < 0 || !(P->newton_rtol >= 0.0) ||
-      P->project < 0 || P->project > 2) {
+  if (!step_params_valid(*P)) {
     set_error("invalid step parameters in request");
     return SYMX_ERR_INVALID_ARG;
   }

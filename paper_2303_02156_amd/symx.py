@@ -55,7 +55,8 @@ class StepParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("gravity", C.c_double * 3), ("newton_rtol", C.c_double),
                 ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("project", C.c_int32),
                 ("precision", C.c_int32), ("max_halvings", C.c_int32),
-                ("regrow_after", C.c_int32), ("max_refine", C.c_int32)]
+                ("regrow_after", C.c_int32), ("max_refine", C.c_int32),
+                ("forcing_max", C.c_double)]
 
 
 class StepReport(C.Structure):
@@ -63,7 +64,8 @@ class StepReport(C.Structure):
                 ("ls_backtracks", C.c_int32), ("dt_halvings", C.c_int32),
                 ("refinements", C.c_int32), ("dt_used", C.c_double), ("residual0", C.c_double),
                 ("residual", C.c_double), ("energy", C.c_double), ("ms_assemble", C.c_double),
-                ("ms_pcg", C.c_double), ("ms_linesearch", C.c_double), ("ms_total", C.c_double)]
+                ("ms_pcg", C.c_double), ("ms_linesearch", C.c_double), ("ms_total", C.c_double),
+                ("lin_residual", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -53,16 +53,34 @@ def test_status_strings(lib):
     assert lib.symx_status_string(99) == b"unknown status"
 
 
-def test_struct_sizes_match_c_layout():
+def test_struct_sizes_match_c_layout(tmp_path):
+    """The ctypes structures have the sizes and field offsets the C compiler
+    gives the structs of include/symx.h."""
     import ctypes as C
+    import subprocess
     from paper_2303_02156_amd import symx
-    # sizes implied by include/symx.h on x86-64 (natural alignment)
-    assert C.sizeof(symx.EnergyDesc) == 4 + 4 + 8 * 8
-    assert C.sizeof(symx.MeshDesc) == 8 + 8 + 8 + 8 + 8 + 8
-    assert C.sizeof(symx.BsrView) == 8 * 5 + 8
-    assert C.sizeof(symx.StepParams) == 8 * 5 + 4 * 7 + 4
-    assert C.sizeof(symx.StepReport) == 4 * 6 + 8 * 8
-    assert C.sizeof(symx.ServerStats) == 8 * 8 + 4 * 3 + 4
+    pairs = {"symx_energy_desc": symx.EnergyDesc, "symx_mesh_desc": symx.MeshDesc,
+             "symx_bsr_view": symx.BsrView, "symx_step_params": symx.StepParams,
+             "symx_step_report": symx.StepReport, "symx_server_stats": symx.ServerStats,
+             "symx_mesh_info": symx.MeshInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "symx.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(line.rsplit(" ", 1) for line in
+               subprocess.run([str(exe)], capture_output=True, text=True,
+                              check=True).stdout.split("\n") if line)
+    for cname, py in pairs.items():
+        assert C.sizeof(py) == int(out[cname]), cname
+        for f, _ in py._fields_:
+            assert getattr(py, f).offset == int(out[f"{cname}.{f}"]), (cname, f)
 
 
 def test_null_arguments_rejected_without_gpu(lib):

@@ -98,7 +98,20 @@ def _oracle_rows(scene, x, xt, dt, nodes, project=False):
     return rows
 
 
-def _check_sampled_rows(symx, scene, precision, n_nodes, seed, project=False):
+def _strained(scene, amp, seed):
+    """x(t) plus U(-amp, amp)^3 on the free nodes (seeded): a strained state at
+    which the elastic gradient is far from zero and element Hessians are
+    indefinite, so projection and filtering change them."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-amp, amp, size=scene.x0.shape)
+    return scene.x0 + np.where(scene.fixed[:, None] == 1, 0.0, d)
+
+
+def _check_sampled_rows(symx, scene, precision, n_nodes, seed, project=False, x=None):
+    """Sampled gradient and Hessian block rows at x (default x(t)) against the
+    oracle.  With projection, also checks that the oracle's projected rows
+    differ from its raw rows (the projection acts at x)."""
+    x = scene.x0 if x is None else x
     mesh = symx.Mesh(scene)
     dt = scene.dt
     xt = elements.x_tilde(scene.x0, scene.v0, dt, scene.gravity)
@@ -107,12 +120,17 @@ def _check_sampled_rows(symx, scene, precision, n_nodes, seed, project=False):
     flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
     if project:
         flags |= symx.SYMX_PROJECT_FILTER if project == "filter" else symx.SYMX_PROJECT_PSD
-    E, g, vals = mesh.assemble(scene.x0, xt, dt, flags, p)
+    E, g, vals = mesh.assemble(x, xt, dt, flags, p)
     rp, ci, _ = mesh.pattern()
     V = vals.cpu().numpy().astype(np.float64).T.reshape(-1, 3, 3)
     gd = g.cpu().numpy()
     nodes = _sample_nodes(scene, n_nodes, seed=seed)
-    ref = _oracle_rows(scene, scene.x0, xt, dt, nodes, project)
+    ref = _oracle_rows(scene, x, xt, dt, nodes, project)
+    if project:
+        raw = _oracle_rows(scene, x, xt, dt, nodes, False)
+        diff = max(np.abs(ref[i][1][j] - raw[i][1][j]).max() for i in ref for j in ref[i][1])
+        scale = max(np.abs(raw[i][1][j]).max() for i in raw for j in raw[i][1])
+        assert diff > 1e-3 * scale, (diff, scale)
     gerr = gmax = herr = hmax = 0.0
     for i, (go, blocks) in ref.items():
         cols = ci[rp[i]:rp[i + 1]]
@@ -124,21 +142,34 @@ def _check_sampled_rows(symx, scene, precision, n_nodes, seed, project=False):
             hmax = max(hmax, np.abs(blocks[int(j)]).max())
     assert herr <= tol * hmax
     assert gerr <= tol * max(gmax, 1e-300)
-    E_ref = assembly.energy(scene, scene.x0, xt, dt)
+    E_ref = assembly.energy(scene, x, xt, dt)
     assert abs(E - E_ref) <= tol * abs(E_ref)
     mesh.close()
 
 
+@pytest.fixture(scope="module")
+def c2_strained(c2):
+    """C2 positions plus U(+-20% of the cube edge) on the free nodes."""
+    return _strained(c2, 0.2 * 0.01, 51)
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_c2_sampled_rows_match_oracle(symx, c2, precision):
-    _check_sampled_rows(symx, c2, precision, 200, 41)
+def test_c2_sampled_rows_match_oracle(symx, c2, c2_strained, precision):
+    _check_sampled_rows(symx, c2, precision, 200, 41, x=c2_strained)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_c2_rest_sampled_rows_match_oracle(symx, c2, precision):
+    """At x(t) = X: zero elastic gradient, the rest stiffness."""
+    _check_sampled_rows(symx, c2, precision, 60, 42)
 
 
 @pytest.mark.parametrize("project", [True, "filter"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_c2_projected_sampled_rows_match_oracle(symx, c2, precision, project):
-    """Per-element PSD projection and the filtered SNH Hessian at full size."""
-    _check_sampled_rows(symx, c2, precision, 120, 45, project)
+def test_c2_projected_sampled_rows_match_oracle(symx, c2, c2_strained, precision, project):
+    """Per-element PSD projection and the filtered SNH Hessian at full size, at
+    a strained state where both change the element Hessians."""
+    _check_sampled_rows(symx, c2, precision, 120, 45, project, x=c2_strained)
 
 
 # The quadratic and cubic stretched boxes of the benchmark (about 137K DoF).
@@ -251,9 +282,19 @@ def test_contact_scene_at_benchmark_size(symx, precision):
     mesh.close()
 
 
+@pytest.fixture(scope="module")
+def c3():
+    return sg.config_c3()
+
+
+@pytest.mark.parametrize("project", [False, True, "filter"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_c3_sampled_rows_match_oracle(symx, precision):
+def test_c3_sampled_rows_match_oracle(symx, c3, precision, project):
     """C3 (512^2 cloth with membranes and hinges, and a 32^3-cube tet block):
-    rows of cloth and block nodes, several element kinds per row."""
-    _check_sampled_rows(symx, sg.config_c3(), precision, 120, 49)
+    rows of cloth and block nodes, several element kinds per row, at a strained
+    state (U(+-20% of the cloth spacing) on the free nodes); plain, with
+    per-element PSD projection, and with the filtered SNH Hessian (membranes
+    and hinges projected)."""
+    x = _strained(c3, 0.2 / 512, 53)
+    _check_sampled_rows(symx, c3, precision, 120, 49, project, x=x)
 

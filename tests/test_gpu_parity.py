@@ -324,6 +324,42 @@ def test_newton_step_projected_c1(symx, precision):
     assert rep.energy == pytest.approx(repo["energy"], rel=1e-9)
 
 
+def test_f32_refinement_reaches_float64_accuracy(symx):
+    """Mixed-precision iterative refinement (F32_REFINED).  With the forcing
+    term capped at 1e-9, far below what a float32 PCG on the rounded Hessian
+    reaches (about 1e-6 relative to the float64 Hessian), each linear solve is
+    refined until |b - H dx| <= 1e-9 |b| with H the float64 Hessian; with no
+    refinement passes the same solves stop at the float32 floor."""
+    scene = sg.config_c1()
+    out = {}
+    for mr in (0, 4):
+        st, rep, x, _ = _newton(symx, scene, symx.SYMX_F32_REFINED, forcing_max=1e-9,
+                                max_refine=mr)
+        assert st == 0, (symx.STATUS[st], rep.as_dict())
+        out[mr] = (rep, x)
+    rep0, _ = out[0]
+    rep4, x4 = out[4]
+    assert rep0.refinements == 0 and rep0.lin_residual > 1e-8, rep0.as_dict()
+    assert rep4.refinements >= rep4.newton_iters >= 1, rep4.as_dict()
+    assert 0.0 <= rep4.lin_residual <= 1e-9, rep4.as_dict()
+    # the refined solves behave as exact ones: the oracle's Newton step with
+    # direct sparse solves reaches the same minimiser in as many iterations
+    dt = scene.dt
+    ok, xo, repo = newton.newton_solve(scene, scene.x0, scene.v0, dt, newton.StepParams(dt=dt),
+                                       solver="direct")
+    assert ok
+    assert abs(rep4.newton_iters - repo["newton_iters"]) <= 1
+    m_min = rest.lumped_mass(scene).min()
+    assert np.max(np.abs(x4 - xo)) <= 2.0e-6 * rep4.residual0 * dt * dt / m_min
+    # float64 mode reports no refinement residual
+    st, rep64, _, _ = _newton(symx, scene, symx.SYMX_F64)
+    assert st == 0 and rep64.lin_residual == -1.0 and rep64.refinements == 0
+    # forcing terms outside (0, 1) and negative pass counts are rejected
+    for kw in (dict(forcing_max=0.0), dict(forcing_max=1.0), dict(max_refine=-1)):
+        st, _, _, _ = _newton(symx, scene, symx.SYMX_F32_REFINED, **kw)
+        assert symx.STATUS[st] == "INVALID_ARG", kw
+
+
 def test_newton_step_mixed_f32_refined(symx):
     scene = mixed_scene()
     st, rep, x, _ = _newton(symx, scene, symx.SYMX_F32_REFINED)
