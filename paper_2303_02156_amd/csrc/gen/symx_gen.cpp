@@ -45,6 +45,10 @@ struct EnergySpec {
   int n_in;           // total inputs
   int rest_slot;      // first slot of node-0 rest coordinates, or -1
   std::function<S(Graph&, const std::vector<S>&)> energy;
+  // linear tets: the density psi(F, inputs) of energy = V psi(F); when set,
+  // the Hessian row functions are generated through F (fewer operations
+  // than differentiating the energy with respect to the positions)
+  std::function<S(const symx::Mat&, const std::vector<S>&)> density = nullptr;
 };
 
 Mat cols_minus_first(Graph& g, const std::vector<S>& in, int base, int n_nodes) {
@@ -94,40 +98,48 @@ Mat lagged_rotation(Graph& g, const std::vector<S>& in) {
   return R;
 }
 
-// Classic Neo-Hookean tet4 (App. B, Neo-Hookean branch; Eq. 6 with the sign
-// of the log term that makes the rest state stress free):
+// Classic Neo-Hookean (App. B, Neo-Hookean branch; Eq. 6 with the sign of
+// the log term that makes the rest state stress free):
 // psi = mu/2 (Ic - 3) - mu log J + lambda/2 log^2 J.
+S nh_density(const Mat& F, const std::vector<S>& in) {
+  S mu = in[24], lam = in[25];
+  S logJ = log(det3(F));
+  return 0.5 * mu * (frob2(F) - 3.0) - mu * logJ + 0.5 * lam * pown(logJ, 2);
+}
 S nh_tet4(Graph& g, const std::vector<S>& in) {
   TetKinematics k = tet_kinematics(g, in);
-  S mu = in[24], lam = in[25];
-  S logJ = log(det3(k.F));
-  S psi = 0.5 * mu * (frob2(k.F) - 3.0) - mu * logJ + 0.5 * lam * pown(logJ, 2);
-  return k.V * psi;
+  return k.V * nh_density(k.F, in);
 }
 
-// Fixed co-rotational tet4 (App. B, fixed co-rotational branch) with the
-// rotation R held constant over a time step (lagged):
+// Fixed co-rotational (App. B, fixed co-rotational branch) with the rotation
+// R held constant over a time step (lagged):
 // psi = mu |F - R|^2 + lambda/2 (J - 1)^2.
-S fcr_tet4(Graph& g, const std::vector<S>& in) {
-  TetKinematics k = tet_kinematics(g, in);
+S fcr_density(const Mat& F, const std::vector<S>& in) {
+  Graph& g = *F.v[0].g;
   Mat R = lagged_rotation(g, in);
   S mu = in[24], lam = in[25];
   Mat D(3, 3, &g);
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) D(i, j) = k.F(i, j) - R(i, j);
-  S psi = mu * frob2(D) + 0.5 * lam * pown(det3(k.F) - 1.0, 2);
-  return k.V * psi;
+    for (int j = 0; j < 3; ++j) D(i, j) = F(i, j) - R(i, j);
+  return mu * frob2(D) + 0.5 * lam * pown(det3(F) - 1.0, 2);
+}
+S fcr_tet4(Graph& g, const std::vector<S>& in) {
+  TetKinematics k = tet_kinematics(g, in);
+  return k.V * fcr_density(k.F, in);
 }
 
-// As-rigid-as-possible tet4 with a volume term (App. B, ARAP branch), R
-// lagged: psi = mu/2 (Ic - 2 tr(F^T R) + 3) + lambda/2 (J - 1)^2.
-S arap_tet4(Graph& g, const std::vector<S>& in) {
-  TetKinematics k = tet_kinematics(g, in);
+// As-rigid-as-possible with a volume term (App. B, ARAP branch), R lagged:
+// psi = mu/2 (Ic - 2 tr(F^T R) + 3) + lambda/2 (J - 1)^2.
+S arap_density(const Mat& F, const std::vector<S>& in) {
+  Graph& g = *F.v[0].g;
   Mat R = lagged_rotation(g, in);
   S mu = in[24], lam = in[25];
-  S trFR = trace(matmul(transpose(k.F), R));
-  S psi = 0.5 * mu * (frob2(k.F) - 2.0 * trFR + 3.0) + 0.5 * lam * pown(det3(k.F) - 1.0, 2);
-  return k.V * psi;
+  S trFR = trace(matmul(transpose(F), R));
+  return 0.5 * mu * (frob2(F) - 2.0 * trFR + 3.0) + 0.5 * lam * pown(det3(F) - 1.0, 2);
+}
+S arap_tet4(Graph& g, const std::vector<S>& in) {
+  TetKinematics k = tet_kinematics(g, in);
+  return k.V * arap_density(k.F, in);
 }
 
 // StVK membrane triangle (App. B, Saint Venant-Kirchhoff branch, on the 3x2
@@ -263,14 +275,8 @@ std::vector<S> tet20_shape(const std::vector<S>& L) {
 //   with respect to xi, as in App. A), c = w |det J_X(xi)|; the element
 //   energy is the sum over the rule's points of this one function (Sec. 5.2,
 //   fixed value summation).
-// The density is differentiated with respect to the nine entries of F
-// (placeholder symbols, replaced by F's expressions afterwards) and the chain
-// rule gives the element derivatives:
-//   dE/dx_{a,i} = c sum_j P_ij g_a[j],
-//   d2E/dx_{a,i} dx_{b,m} = sum_l M_a[i][m][l] g_b[l],
-//   M_a[i][m][l] = c sum_j D_{ij,ml} g_a[j],
-// with P = dpsi/dF and D = d2psi/dF2; M_a is formed once per row and shared
-// by the row's blocks.
+// The density is differentiated with respect to the nine entries of F and
+// the chain rule gives the element derivatives (struct ThroughF below).
 struct Kinematics {
   Mat F;
   S c;
@@ -345,6 +351,69 @@ S stvk_density(const Mat& F, const std::vector<S>& in) {
   return mu_of(in) * frob2(E) + 0.5 * lam_of(in) * pown(trace(E), 2);
 }
 
+// Derivatives of c psi(F) through F (see above), built in graph g for the
+// inputs `in` of a function with n_in inputs: nine placeholder symbols stand
+// for F while psi is differentiated, then are replaced by F's expressions.
+//   dE/dx_{a,i} = c sum_j P_ij g_a[j],  P = dpsi/dF;
+//   d2E/dx_{a,i} dx_{b,m} = c sum_{j,l} D_{ij,ml} g_a[j] g_b[l],  D = d2psi/dF2.
+// The contraction over j is the directional derivative of P along
+// dF = c e_i g_a^T (forward mode through the graph of P, the zero entries of
+// dF folded away), so D itself is never formed:
+//   dP_i = d/deps P(F + eps c e_i g_a^T) at eps = 0,
+//   entry (a_i, b_m) = sum_l dP_i[m][l] g_b[l].
+struct ThroughF {
+  Graph& g;
+  const Kinematics& kin;
+  Mat Fh;
+  std::map<int, int> to_F;  // placeholder slot -> entry of F
+  std::vector<int> Pph;     // P in terms of the placeholders
+  std::vector<int> P;       // P in terms of the inputs
+  S E;
+  ThroughF(Graph& gr, const std::vector<S>& in, const Kinematics& k,
+           const std::function<S(const Mat&, const std::vector<S>&)>& psi_of, int n_in)
+      : g(gr), kin(k), Fh(3, 3, &gr), Pph(9) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        Fh(i, j) = S(&g, g.sym(n_in + 3 * i + j));
+        g.set_dof(Fh(i, j).id);
+        to_F[n_in + 3 * i + j] = kin.F(i, j).id;
+      }
+    const S psi = psi_of(Fh, in);
+    for (int k2 = 0; k2 < 9; ++k2) Pph[k2] = g.diff(psi.id, Fh.v[k2].id);
+    std::vector<int> dens = {psi.id};
+    dens.insert(dens.end(), Pph.begin(), Pph.end());
+    dens = g.substitute_nodes(dens, to_F);
+    E = kin.c * S(&g, dens[0]);
+    P.assign(dens.begin() + 1, dens.end());
+  }
+  S grad(int a, int i) const {
+    const auto& G = kin.G;
+    return kin.c * (S(&g, P[3 * i]) * G[a][0] + S(&g, P[3 * i + 1]) * G[a][1] +
+                    S(&g, P[3 * i + 2]) * G[a][2]);
+  }
+  // Hessian row of node a: for i = 0..2 the blocks (a, b), b in order (the
+  // diagonal block left out unless with_diag)
+  std::vector<int> row_blocks(int a, bool with_diag) {
+    const auto& G = kin.G;
+    const int K = (int)G.size();
+    std::vector<std::vector<int>> dP(3);
+    for (int i = 0; i < 3; ++i) {
+      std::map<int, int> dir;
+      for (int q = 0; q < 3; ++q) dir[Fh(i, q).id] = (kin.c * G[a][q]).id;
+      dP[i] = g.substitute_nodes(g.tangent(Pph, dir), to_F);
+    }
+    std::vector<int> ids;
+    for (int i = 0; i < 3; ++i)
+      for (int b = 0; b < K; ++b) {
+        if (b == a && !with_diag) continue;
+        for (int m = 0; m < 3; ++m)
+          ids.push_back((S(&g, dP[i][3 * m]) * G[b][0] + S(&g, dP[i][3 * m + 1]) * G[b][1] +
+                         S(&g, dP[i][3 * m + 2]) * G[b][2]).id);
+      }
+    return ids;
+  }
+};
+
 struct Generated {
   std::string hip, c, meta;
 };
@@ -395,11 +464,21 @@ void generate(const EnergySpec& spec, Generated& out) {
   std::vector<int> row_g(grad.begin(), grad.begin() + 3);
   add_fn("_row0_g", g.substitute(row_g, zero));
   std::vector<int> row_gH = row_g, row_gHoff = row_g;
-  for (int i = 0; i < 3; ++i)
-    for (int l = 0; l < n_dof; ++l) {
-      row_gH.push_back(hess[i * n_dof + l]);
-      if (l >= 3) row_gHoff.push_back(hess[i * n_dof + l]);
-    }
+  if (spec.density) {
+    // linear tets: the Hessian rows (and the gradient row they carry) through F
+    const Kinematics kin = tet4_kin(g, in);
+    ThroughF tf(g, in, kin, spec.density, spec.n_in);
+    for (int i = 0; i < 3; ++i) row_gH[i] = row_gHoff[i] = tf.grad(0, i).id;
+    const std::vector<int> full = tf.row_blocks(0, true), off = tf.row_blocks(0, false);
+    row_gH.insert(row_gH.end(), full.begin(), full.end());
+    row_gHoff.insert(row_gHoff.end(), off.begin(), off.end());
+  } else {
+    for (int i = 0; i < 3; ++i)
+      for (int l = 0; l < n_dof; ++l) {
+        row_gH.push_back(hess[i * n_dof + l]);
+        if (l >= 3) row_gHoff.push_back(hess[i * n_dof + l]);
+      }
+  }
   add_fn("_row0_gH", g.substitute(row_gH, zero));
   add_fn("_row0_gHoff", g.substitute(row_gHoff, zero));
 
@@ -427,49 +506,10 @@ void generate_through_F(const ThroughFSpec& spec, Generated& out) {
   std::vector<S> in;
   for (int k = 0; k < n_in; ++k) in.push_back(S(&g, g.sym(k)));
   const Kinematics kin = spec.kin(g, in);
-  const auto& G = kin.G;
-  const S c = kin.c;
-  std::map<int, int> to_F;  // placeholder slot -> entry of F
-  Mat Fh(3, 3, &g);
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      Fh(i, j) = S(&g, g.sym(n_in + 3 * i + j));
-      g.set_dof(Fh(i, j).id);
-      to_F[n_in + 3 * i + j] = kin.F(i, j).id;
-    }
-  const S psi = spec.psi(Fh, in);
-  // psi and P = dpsi/dF in terms of the placeholders
-  std::vector<int> Pph(9);
-  for (int k = 0; k < 9; ++k) Pph[k] = g.diff(psi.id, Fh.v[k].id);
-  std::vector<int> dens = {psi.id};
-  dens.insert(dens.end(), Pph.begin(), Pph.end());
-  dens = g.substitute_nodes(dens, to_F);
-  auto P = [&](int i, int j) { return S(&g, dens[1 + 3 * i + j]); };
-  const S E = c * S(&g, dens[0]);
-  auto grad = [&](int a, int i) { return c * (P(i, 0) * G[a][0] + P(i, 1) * G[a][1] + P(i, 2) * G[a][2]); };
-  // Hessian row of node a: for i = 0..2 the blocks (a, b), b in order.
-  // Entry (a_i, b_m) = c sum_{j,l} D_{ij,ml} g_a[j] g_b[l] with D = d2psi/dF2.
-  // The contraction over j is the directional derivative of P along
-  // dF = c e_i g_a^T (forward mode through the graph of P, zero entries of
-  // dF folded away), so D itself is never formed:
-  //   dP_i = dP/deps (F + eps c e_i g_a^T),  entry (a_i, b_m) = sum_l dP_i[m][l] g_b[l].
-  auto row_blocks = [&](int a, bool with_diag) {
-    std::vector<std::vector<int>> dP(3);
-    for (int i = 0; i < 3; ++i) {
-      std::map<int, int> dir;
-      for (int q = 0; q < 3; ++q) dir[Fh(i, q).id] = (c * G[a][q]).id;
-      dP[i] = g.substitute_nodes(g.tangent(Pph, dir), to_F);
-    }
-    std::vector<int> ids;
-    for (int i = 0; i < 3; ++i)
-      for (int b = 0; b < K; ++b) {
-        if (b == a && !with_diag) continue;
-        for (int m = 0; m < 3; ++m)
-          ids.push_back((S(&g, dP[i][3 * m]) * G[b][0] + S(&g, dP[i][3 * m + 1]) * G[b][1] +
-                         S(&g, dP[i][3 * m + 2]) * G[b][2]).id);
-      }
-    return ids;
-  };
+  ThroughF tf(g, in, kin, spec.psi, n_in);
+  const S E = tf.E;
+  auto grad = [&](int a, int i) { return tf.grad(a, i); };
+  auto row_blocks = [&](int a, bool with_diag) { return tf.row_blocks(a, with_diag); };
 
   std::vector<Function> fns;
   auto add_fn = [&](const std::string& suffix, std::vector<int> outs) {
@@ -537,21 +577,27 @@ int main(int argc, char** argv) {
     return 2;
   }
   std::string dir = argv[1];
+  // The linear-tet materials carry their density: their Hessian rows are
+  // generated through F (SNH 680 operations per row against 795 by
+  // differentiating the energy directly, NH 663 / 739, fixed co-rotational
+  // 502 / 584, ARAP 512 / 597); energies, gradients and full element
+  // Hessians are differentiated directly (fewer operations that way).
+  auto snh_psi = [](const Mat& F, const std::vector<S>& in) { return snh_density(F, in[24], in[25]); };
   std::vector<EnergySpec> specs = {
-      {"snh_tet4", 4, 26, 12, snh_tet4},
+      {"snh_tet4", 4, 26, 12, snh_tet4, snh_psi},
       {"stvk_tri3", 3, 21, 9, stvk_tri3},
       {"hinge4", 4, 18, -1, hinge4},
       {"inertia", 1, 8, -1, inertia},
-      {"nh_tet4", 4, 26, 12, nh_tet4},
-      {"fcr_tet4", 4, 35, 12, fcr_tet4},
-      {"arap_tet4", 4, 35, 12, arap_tet4},
+      {"nh_tet4", 4, 26, 12, nh_tet4, nh_density},
+      {"fcr_tet4", 4, 35, 12, fcr_tet4, fcr_density},
+      {"arap_tet4", 4, 35, 12, arap_tet4, arap_density},
       {"ipc_point_plane", 4, 14, -1, ipc_point_plane},
       {"ipc_point_plane_act", 4, 14, -1, ipc_point_plane_act},
   };
-  // Energies differentiated through F: StVK on linear tets (its rows take
-  // 1,069 operations this way against 1,330 by direct differentiation; the
-  // other linear-tet materials are cheaper directly) and one quadrature point
-  // of the higher-order tets (2,376 against 4,661 for the cubic rows).
+  // Energies differentiated through F throughout: StVK on linear tets (its
+  // rows take 979 operations this way against 1,330 by direct
+  // differentiation) and one quadrature point of the higher-order tets (2,214
+  // against 4,661 for the cubic rows).
   auto tet4 = [](const std::string& name, int n_in,
                  std::function<S(const Mat&, const std::vector<S>&)> psi) {
     return ThroughFSpec{name, 4, n_in, 12, tet4_kin, std::move(psi), {0}, true};
@@ -573,7 +619,6 @@ int main(int argc, char** argv) {
                         full};
   };
   const std::vector<ThroughFSpec> through_F = {
-      tet4("XPsnh_tet4", 26, [](const Mat& F, const std::vector<S>& in) { return snh_density(F, in[24], in[25]); }),
       tet4("stvk_tet4", 26, stvk_density),
       high_order("snh_tet10", 10, tet10_shape, {0, 4}, true),
       high_order("snh_tet20", 20, tet20_shape, {0, 4, 19}, false),

@@ -46,7 +46,7 @@ void build_scatter(Mesh& m);
 void free_workspace(Mesh& m);
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
                      bool want_H, int project, int precision, bool dirichlet, double* g_out,
-                     void* dinv);
+                     void* dinv, float* dinv_lo);
 symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E);
 symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P,
                         symx_step_report* out);
@@ -244,7 +244,7 @@ symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double*
   const bool want_H = (flags & SYMX_EVAL_HESS) != 0;
   const int project = (flags & SYMX_PROJECT_FILTER) ? 2 : (flags & SYMX_PROJECT_PSD) ? 1 : 0;
   symx_status st = assemble(m, x_dev, x_tilde_dev, dt, want_g, want_H, project, precision,
-                            (flags & SYMX_DIRICHLET) != 0, grad_dev, nullptr);
+                            (flags & SYMX_DIRICHLET) != 0, grad_dev, nullptr, nullptr);
   if (st != SYMX_OK) return st;
   if (flags & SYMX_EVAL_E) {
     st = energy(m, x_dev, x_tilde_dev, dt, precision, energy_host);

@@ -469,10 +469,13 @@ symx_status launch_elem_filtered(Mesh& m, int set, const double* x, int precisio
 // records (kIncRec values each) instead of evaluating it.  filter: every set
 // is Stable Neo-Hookean; evaluate each row with the filtered density Hessian.
 // dinv (optional): the kernel also writes the inverses of the final diagonal
-// blocks (N x 9, precision's type).
+// blocks (N x 9, precision's type).  dinv_lo (float64 only, optional): the
+// linear-tet kernels also write m.vals32 and dinv_lo, the values and
+// inverses rounded to float32 (the higher-order kernels do not).
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* x_tilde, double dt,
                                 bool want_g, bool want_H, int precision, bool dirichlet,
-                                const void* inc_rows, bool filter, double* g_out, void* dinv);
+                                const void* inc_rows, bool filter, double* g_out, void* dinv,
+                                float* dinv_lo = nullptr);
 // Incidence positions (inverse of the incidence codes), n_inc ints.
 symx_status launch_incidence_positions(Mesh& m, int* inc_pos);
 // Projected element rows into the incidence records (n_inc x 32, precision).
@@ -530,9 +533,11 @@ symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const d
 symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0, int n_iter);
 symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs);
 symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b, double* r);
-// Rounds the float64 Hessian values of the mesh (and of its contacts) to
-// their float32 copies, and n9 float64 block inverses dinv64 to dinv32.
-symx_status launch_round_values(Mesh& m, const double* dinv64, float* dinv32, int64_t n9);
+// Rounds the float64 Hessian values of the mesh (if mesh_vals) and of its
+// contacts to their float32 copies, and n9 float64 block inverses dinv64 to
+// dinv32 (if given).
+symx_status launch_round_values(Mesh& m, bool mesh_vals, const double* dinv64, float* dinv32,
+                                int64_t n9);
 
 // Newton driver (symx_newton.cpp): the ranges symx_newton_step accepts.
 bool step_params_valid(const symx_step_params& P);

@@ -1104,6 +1104,8 @@ struct RowArgs {
   int64_t nnzb;
   T* vals;               // component-major 9 x nnzb
   T* dinv;               // N x 9 inverses of the diagonal blocks, or null
+  float* vals_lo;        // null, or the values rounded to float32 (as vals)
+  float* dinv_lo;        // null, or the inverses rounded to float32 (as dinv)
   double* g;             // N x 3
   const T* inc_rows;     // projected path: incidence records (kIncRec per incidence)
   int* nonfinite;
@@ -1257,15 +1259,20 @@ __device__ __forceinline__ void incidence_row_filtered(const RowArgs<T>& A, uint
 // nearest-PSD projection, which only removes directions orthogonal to the
 // translations).
 //  1. one lane per incidence evaluates the gradient and the off-diagonal
-//     blocks of its Hessian row into LDS;
-//  2. one lane per off-diagonal block sums its precomputed contribution list
-//     in incidence order;
-//  3. the off-diagonal blocks are published to LDS;
+//     blocks of its Hessian row (in registers; the gradient to LDS);
+//  2. in three rounds, one per component row i of the blocks: the incidence
+//     lanes put row i of their off-diagonal blocks in LDS, and one lane per
+//     off-diagonal block sums its precomputed contribution list in incidence
+//     order (the rounds keep a third of the values in LDS at a time, which
+//     lets more waves share a CU);
+//  3. the summed off-diagonal blocks are published to LDS;
 //  4. one lane per (row, component): the elastic diagonal block is minus the
 //     sum of the row's off-diagonal blocks (slot order), plus inertia; and
 //     the gradient sums the row's incidences (float64, incidence order);
 //  5. Dirichlet is applied and every block is written once, with the inverse
-//     of each diagonal block when requested.
+//     of each diagonal block when requested; with vals_lo, the block values
+//     and inverses are also written rounded to float32 (the copy a float32
+//     solve iterates on).
 // SRC: where step 1 takes each incidence's row from -- kRowEval evaluates the
 // generated row function, kRowRecords reads the incidence's record in the
 // incidence-ordered buffer (projected path), kRowFilter evaluates the
@@ -1275,9 +1282,9 @@ __device__ __forceinline__ void incidence_row_filtered(const RowArgs<T>& A, uint
 template <typename T, bool WANT_G, int SRC, uint32_t KMASK>
 __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   constexpr int NV = 30;
-  __shared__ T st[NV][kRowWG];
-  // batch-relative offsets (at most kRowWG) in 16 bits keep the workgroup's
-  // LDS within 32 KiB: five workgroups (20 waves) per CU in single precision
+  __shared__ T st[9][kRowWG];  // one component row of the incidences' blocks; then the sums
+  __shared__ T sg[3][kRowWG];  // the incidences' gradient rows
+  // batch-relative offsets (at most kRowWG) in 16 bits
   __shared__ uint16_t s_blk[kRowWG + 1];
   __shared__ uint16_t s_inc[kRowWG + 1];
   const int t = threadIdx.x;
@@ -1293,8 +1300,8 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   __syncthreads();
   const int nq = s_inc[nrows];
   const int np = s_blk[nrows];
+  T out[NV];
   if (t < nq) {
-    T out[NV];
     if constexpr (SRC == kRowRecords) {
       const T* rec = A.inc_rows + (int64_t)(q0 + t) * kIncRec;
 #pragma unroll
@@ -1305,12 +1312,13 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
       incidence_row_off<T, KMASK>(A, A.inc_code[q0 + t], out);
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) st[v][t] = out[v];
+    for (int v = 0; v < 3; ++v) sg[v][t] = out[v];
   }
-  __syncthreads();
-  // phase 2: off-diagonal blocks from their contribution lists
-  int r = 0, col = 0;
+  // block lanes: row, column and the first eight contribution-list entries
+  int r = 0, col = 0, cnt = 0;
   bool diag = false;
+  const uint16_t* ce = nullptr;
+  uint32_t w0[8];
   T acc[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = T(0);
@@ -1319,33 +1327,44 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
     col = A.col_idx[p0 + t];
     diag = (col == r0 + r);
     const uint32_t info = A.blk_info[p0 + t];
-    const uint16_t* ce = A.centry + A.batch_entry[b] + (info >> 8);
-    const int cnt = int(info & 0xFFu);
-    // up to eight list entries are loaded together, then summed in list
-    // order (one global round trip per eight entries instead of per entry)
-    for (int j0 = 0; j0 < cnt; j0 += 8) {
-      uint32_t w[8];
+    ce = A.centry + A.batch_entry[b] + (info >> 8);
+    cnt = int(info & 0xFFu);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) w[k] = j0 + k < cnt ? uint32_t(ce[j0 + k]) : 0u;
+    for (int k = 0; k < 8; ++k) w0[k] = k < cnt ? uint32_t(ce[k]) : 0u;
+  }
+  // phase 2, one component row of the blocks per round
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        if (j0 + k < cnt) {
-          const int q = int(w[k] >> 2);
-          const int bb = int(w[k] & 3u) - 1;
+  for (int i = 0; i < 3; ++i) {
+    if (t < nq) {
 #pragma unroll
-          for (int i = 0; i < 3; ++i)
+      for (int v = 0; v < 9; ++v) st[v][t] = out[3 + 9 * i + v];
+    }
+    __syncthreads();
+    if (t < np) {
+      // up to eight list entries are summed from registers, later ones are
+      // loaded eight at a time; all in list order
+      for (int j0 = 0; j0 < cnt; j0 += 8) {
+        uint32_t w[8];
 #pragma unroll
-            for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += st[3 + 9 * i + 3 * bb + kk][q];
+        for (int k = 0; k < 8; ++k)
+          w[k] = j0 == 0 ? w0[k] : (j0 + k < cnt ? uint32_t(ce[j0 + k]) : 0u);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (j0 + k < cnt) {
+            const int q = int(w[k] >> 2);
+            const int bb = int(w[k] & 3u) - 1;
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += st[3 * bb + kk][q];
+          }
         }
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
-  // phase 3: publish the off-diagonal blocks (over the off-diagonal rows of
-  // the incidence table; the gradients in st[0..2] stay)
+  // phase 3: publish the off-diagonal blocks
   if (t < np) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) st[3 + c][t] = acc[c];
+    for (int c = 0; c < 9; ++c) st[c][t] = acc[c];
   }
   __syncthreads();
   // phase 4: one lane per (row, component) of the elastic diagonal blocks
@@ -1361,14 +1380,14 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
       for (int sl = s_blk[rr]; sl < sl1; sl += 8) {
         T v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = sl + k < sl1 ? st[3 + c][sl + k] : T(0);
+        for (int k = 0; k < 8; ++k) v[k] = sl + k < sl1 ? st[c][sl + k] : T(0);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
           if (sl + k < sl1) sum += v[k];
       }
       T dv = -sum;
       if (A.xt && (c % 4) == 0) dv += T(A.mass[r0 + rr] * A.inv_dt2);
-      st[3 + c][A.diag_pos[r0 + rr] - p0] = dv;
+      st[c][A.diag_pos[r0 + rr] - p0] = dv;
     } else {
       const int jj = j - 9 * nrows;
       const int rr = jj / 3, c = jj - 3 * rr;
@@ -1378,7 +1397,7 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
       for (int q = s_inc[rr]; q < q1; q += 8) {  // as above, incidence order
         T v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = q + k < q1 ? st[c][q + k] : T(0);
+        for (int k = 0; k < 8; ++k) v[k] = q + k < q1 ? sg[c][q + k] : T(0);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
           if (q + k < q1) g += double(v[k]);
@@ -1395,7 +1414,7 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
     const int row = r0 + r;
     if (diag) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc[c] = st[3 + c][t];
+      for (int c = 0; c < 9; ++c) acc[c] = st[c][t];
     }
     if (A.fixed && (A.fixed[row] | A.fixed[col])) {
 #pragma unroll
@@ -1403,6 +1422,10 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) A.vals[(int64_t)c * A.nnzb + p0 + t] = acc[c];
+    if (A.vals_lo) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) A.vals_lo[(int64_t)c * A.nnzb + p0 + t] = float(acc[c]);
+    }
     if (diag && A.dinv) {
       double a[9], ri[9];
 #pragma unroll
@@ -1410,6 +1433,10 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
       inverse3(a, ri);
 #pragma unroll
       for (int c = 0; c < 9; ++c) A.dinv[9 * (int64_t)row + c] = T(ri[c]);
+      if (A.dinv_lo) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) A.dinv_lo[9 * (int64_t)row + c] = float(ri[c]);
+      }
     }
   }
 }
@@ -2699,7 +2726,8 @@ static void row_assemble_launch(Mesh& m, const char* PNAME, dim3 grid, dim3 bloc
 template <typename T>
 static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, double dt,
                                   bool want_g, bool want_H, bool dirichlet,
-                                  const void* inc_rows, bool filter, double* g_out, void* dinv) {
+                                  const void* inc_rows, bool filter, double* g_out, void* dinv,
+                                  float* dinv_lo) {
   RowArgs<T> A;
   A.sets = m.sets_dev();
   A.x = x;
@@ -2722,6 +2750,10 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   if (want_H) A.vals = (T*)(sizeof(T) == 4 ? (void*)m.vals32 : (void*)m.vals64);
   A.g = g_out;
   A.dinv = (T*)dinv;
+  // float32 copies written by the float64 kernel itself (not by the
+  // higher-order kernels, whose copies are rounded afterwards)
+  A.vals_lo = want_H && dinv_lo && !m.ho ? m.vals32 : nullptr;
+  A.dinv_lo = want_H && !m.ho ? dinv_lo : nullptr;
   A.nonfinite = m.nonfinite;
   A.inc_rows = (const T*)inc_rows;
   A.inc_nodes = m.inc_nodes;
@@ -2777,12 +2809,17 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
 
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
                                 bool want_H, int precision, bool dirichlet,
-                                const void* inc_rows, bool filter, double* g_out, void* dinv) {
+                                const void* inc_rows, bool filter, double* g_out, void* dinv,
+                                float* dinv_lo) {
   if (precision == SYMX_F32)
     return row_assemble_t<float>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, filter, g_out,
-                                 dinv);
+                                 dinv, nullptr);
+  if (dinv_lo && (!m.vals32 || !dinv)) {
+    set_error("row assembly: float32 copies need the float32 values and the inverses");
+    return SYMX_ERR_INVALID_ARG;
+  }
   return row_assemble_t<double>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, filter, g_out,
-                                dinv);
+                                dinv, dinv_lo);
 }
 
 symx_status launch_x_tilde(Mesh& m, const double* x, const double* v, double dt, const double g[3],
@@ -2823,15 +2860,17 @@ symx_status launch_velocity(Mesh& m, double* v, const double* xn, const double* 
   return SYMX_OK;
 }
 
-symx_status launch_round_values(Mesh& m, const double* dinv64, float* dinv32, int64_t n9) {
+symx_status launch_round_values(Mesh& m, bool mesh_vals, const double* dinv64, float* dinv32,
+                                int64_t n9) {
   const char* PNAME = "round_values";
   if (!m.vals64 || !m.vals32) {
     set_error("round_values: the float64 and float32 value arrays must exist");
     return SYMX_ERR_INVALID_ARG;
   }
   const int64_t nv = 9 * m.nnzb;
-  SYMX_LAUNCH(m, PNAME, k_round_f64, dim3(grid_for(nv, 256, 8192)), dim3(256), 0, nv,
-              (const double*)m.vals64, m.vals32);
+  if (mesh_vals)
+    SYMX_LAUNCH(m, PNAME, k_round_f64, dim3(grid_for(nv, 256, 8192)), dim3(256), 0, nv,
+                (const double*)m.vals64, m.vals32);
   if (m.contacts && m.contacts->nnzb > 0) {
     Contacts& c = *m.contacts;
     if (c.vals_cap32 < c.nnzb) {

@@ -143,11 +143,36 @@ static symx_status project_into_records(Mesh& m, const double* x, int precision,
   return launch_incidence_rows_projected(m, x, precision, mode, m.inc_pos, m.inc_rows);
 }
 
+static symx_status assemble_main(Mesh& m, const double* x, const double* xt, double dt,
+                                 bool want_g, bool want_H, int project, int precision,
+                                 bool dirichlet, double* g_out, void* dinv, float* dinv_lo);
+
 // Assemble gradient (float64) and/or Hessian values (precision) at x.  With
-// dinv, the block-Jacobi inverses (N x 9, precision's type) are produced too.
+// dinv, the block-Jacobi inverses (N x 9, precision's type) are produced too;
+// with dinv_lo (float64 Hessian and dinv only), also the float32 copies of
+// the values (m.vals32) and of the inverses (dinv_lo).
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g, bool want_H,
                      int project, int precision, bool dirichlet, double* g_out,
-                     void* dinv = nullptr) {
+                     void* dinv = nullptr, float* dinv_lo = nullptr) {
+  if (dinv_lo) {
+    if (precision != SYMX_F64 || !want_H || !dinv) {
+      set_error("float32 copies need a float64 Hessian with its inverses");
+      return SYMX_ERR_INVALID_ARG;
+    }
+    TRY(ensure_values(m, SYMX_F32));
+  }
+  TRY(assemble_main(m, x, xt, dt, want_g, want_H, project, precision, dirichlet, g_out, dinv,
+                    dinv_lo));
+  // copies the row kernel does not write: higher-order meshes (all values),
+  // contacts (their values, and the inverses of the nodes they touch)
+  if (dinv_lo && (m.ho || m.contacts))
+    TRY(launch_round_values(m, m.ho != 0, (const double*)dinv, dinv_lo, 9 * m.N));
+  return SYMX_OK;
+}
+
+static symx_status assemble_main(Mesh& m, const double* x, const double* xt, double dt,
+                                 bool want_g, bool want_H, int project, int precision,
+                                 bool dirichlet, double* g_out, void* dinv, float* dinv_lo) {
   if (project && want_H && m.ho) {
     set_error("per-element PSD projection is not available for quadratic or cubic tets");
     return SYMX_ERR_INVALID_ARG;
@@ -160,18 +185,18 @@ symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool
     for (const SetHost& s : m.sets) snh_only = snh_only && s.kind == SYMX_SNH_TET4;
     if (project == 2 && snh_only) {
       TRY(launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, nullptr, true,
-                              g_out, dinv));
+                              g_out, dinv, dinv_lo));
     } else {
       TRY(project_into_records(m, x, precision, project));
       TRY(launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, m.inc_rows, false,
-                              g_out, dinv));
+                              g_out, dinv, dinv_lo));
     }
     // contact element Hessians take the nearest-PSD projection in both modes
     return launch_contact_assemble(m, x, want_g, true, true, precision, dirichlet, g_out, dinv);
   }
   if (!want_g && !want_H) return SYMX_OK;
   TRY(launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, false,
-                          g_out, want_H ? dinv : nullptr));
+                          g_out, want_H ? dinv : nullptr, want_H ? dinv_lo : nullptr));
   return launch_contact_assemble(m, x, want_g, want_H, false, precision, dirichlet, g_out,
                                  want_H ? dinv : nullptr);
 }
@@ -302,9 +327,8 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
     // F32_REFINED mode all in float64, then the float32 copies for the PCG
     if (P.precision == SYMX_F32_REFINED) {
       TRY(ensure_dinv64(m));
-      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project, SYMX_F64, true, w->g, w->dinv64));
-      TRY(ensure_values(m, SYMX_F32));
-      TRY(launch_round_values(m, w->dinv64, (float*)w->pcg[0], 9 * m.N));
+      TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project, SYMX_F64, true, w->g, w->dinv64,
+                   (float*)w->pcg[0]));
     } else {
       TRY(assemble(m, w->xk, w->xt, dt, true, true, P.project, ph, true, w->g, w->pcg[0]));
     }

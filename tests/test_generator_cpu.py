@@ -127,13 +127,13 @@ def test_other_materials_generated_vs_oracle(lib, name):
     assert _rel(out[:, 1:13], g.reshape(n, 12)) < 1e-10
     assert _rel(out[:, 13:], H.reshape(n, 144)) < 1e-10
     out_s = _call(lib, name + "_s_EgH", inputs(x - x[:, :1], X - X[:, :1]), 157)
-    assert _rel(out_s, out) < 1e-9
+    assert _rel(out_s, out) < 1e-10
     for a in range(4):
         perm = [a] + [b for b in range(4) if b != a]
         r = _call(lib, name + "_row0_gHoff",
                   inputs(x[:, perm] - x[:, a:a + 1], X[:, perm] - X[:, a:a + 1]), 30)
-        assert _rel(r[:, :3], g[:, a]) < 1e-9
-        assert _rel(r[:, 3:].reshape(n, 3, 9), H[:, a][:, :, perm[1:], :].reshape(n, 3, 9)) < 1e-9
+        assert _rel(r[:, :3], g[:, a]) < 1e-10
+        assert _rel(r[:, 3:].reshape(n, 3, 9), H[:, a][:, :, perm[1:], :].reshape(n, 3, 9)) < 1e-10
 
 
 def _random_tris(n, seed):
@@ -291,7 +291,7 @@ def test_tet10_generated_vs_oracle(lib):
     assert _rel(out[:, 1:31], g.reshape(n, 30)) < 1e-10
     assert _rel(out[:, 31:], H.reshape(n, 900)) < 1e-10
     out_s = _tet10_sum(lib, "snh_tet10_s_EgH", x - x[:, :1], X - X[:, :1], mu, lam, 931)
-    assert _rel(out_s, out) < 1e-9
+    assert _rel(out_s, out) < 1e-10
     for a in range(10):
         perm = tet10_relabel(a)
         r = 0 if a < 4 else 4
@@ -299,10 +299,10 @@ def test_tet10_generated_vs_oracle(lib):
         xs, Xs = x[:, perm] - x[:, perm[:1]], X[:, perm] - X[:, perm[:1]]
         row = _tet10_sum(lib, f"snh_tet10_row{r}_gHoff", xs, Xs, mu, lam, 84)
         others = [perm[b] for b in range(10) if b != r]
-        assert _rel(row[:, :3], g[:, a]) < 1e-9
-        assert _rel(row[:, 3:].reshape(n, 3, 9, 3), H[:, a][:, :, others, :]) < 1e-9
+        assert _rel(row[:, :3], g[:, a]) < 1e-10
+        assert _rel(row[:, 3:].reshape(n, 3, 9, 3), H[:, a][:, :, others, :]) < 1e-10
         rg = _tet10_sum(lib, f"snh_tet10_row{r}_g", xs, Xs, mu, lam, 3)
-        assert _rel(rg, g[:, a]) < 1e-9
+        assert _rel(rg, g[:, a]) < 1e-10
 
 
 def test_contact_barrier_generated_vs_oracle(lib):
@@ -325,10 +325,10 @@ def test_contact_barrier_generated_vs_oracle(lib):
     out = _call(lib, "ipc_point_plane_EgH", inp, 157)
     assert _rel(out[:, 0], E) < 1e-10
     assert _rel(out[:, 1:13], g.reshape(n, 12)) < 1e-10
-    assert _rel(out[:, 13:], H.reshape(n, 144)) < 1e-9
+    assert _rel(out[:, 13:], H.reshape(n, 144)) < 1e-10
     rel_in = inp.copy()
     rel_in[:, :12] -= np.tile(x[:, 0], 4)
-    assert _rel(_call(lib, "ipc_point_plane_s_EgH", rel_in, 157), out) < 1e-9
+    assert _rel(_call(lib, "ipc_point_plane_s_EgH", rel_in, 157), out) < 1e-10
     a = _call(lib, "ipc_point_plane_act_s_E", rel_in, 1)[:, 0]
     assert _rel(a, contact.activation(x, dh)) < 1e-10
 
@@ -391,5 +391,5 @@ def test_tet20_generated_vs_oracle(lib):
         xs, Xs = x[:, perm] - x[:, perm[:1]], X[:, perm] - X[:, perm[:1]]
         row = summed(f"snh_tet20_row{r}_gHoff", xs, Xs, 174)
         others = [perm[b] for b in range(20) if b != r]
-        assert _rel(row[:, :3], g[:, a]) < 1e-9
-        assert _rel(row[:, 3:].reshape(n, 3, 19, 3), H[:, a][:, :, others, :]) < 1e-9
+        assert _rel(row[:, :3], g[:, a]) < 1e-10
+        assert _rel(row[:, 3:].reshape(n, 3, 19, 3), H[:, a][:, :, others, :]) < 1e-10
