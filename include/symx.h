@@ -236,6 +236,33 @@ symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double*
                               double dt, uint32_t flags, int32_t precision, double* energy_host,
                               double* grad_dev, symx_bsr_view* H_out);
 
+/* symx_assemble_bsr for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same evaluation and assembly, allocating nothing.
+ *   values_dev: device, 9 * nnzb values of the precision's type (float for
+ *     SYMX_F32, double for SYMX_F64), component-major as in symx_bsr_view
+ *     (entry (i, j) of block b at values_dev[(3 i + j) nnzb + b]), over the
+ *     pattern of symx_mesh_get_pattern; caller-owned; required with
+ *     SYMX_EVAL_HESS, otherwise unused (may be NULL).
+ *   other arguments as symx_assemble_bsr; results are bitwise those of
+ *   symx_assemble_bsr.
+ * Scratch: the energy reduction (one partial sum per workgroup of the energy
+ * kernels), the total and the non-finite flag live in a static device array
+ * of the library, 40,992 doubles (320.25 KiB) per GPU, held until the process
+ * ends; its address is taken once per device on the first call.  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (any mesh,
+ * any stream) race.  The call synchronises the mesh's stream.
+ * Errors: INVALID_ARG for the cases of symx_assemble_bsr, a NULL values_dev
+ * with SYMX_EVAL_HESS, meshes with contacts, and SYMX_PROJECT_PSD (and
+ * SYMX_PROJECT_FILTER on meshes that are not all Stable Neo-Hookean tets),
+ * whose element records need a workspace; BUDGET if the energy needs more
+ * partial sums than the array holds (not reached by meshes of at most four
+ * sets); NONFINITE as symx_assemble_bsr. */
+symx_status symx_assemble_bsr_noalloc(symx_mesh mesh, const double* x_dev,
+                                      const double* x_tilde_dev, double dt, uint32_t flags,
+                                      int32_t precision, double* energy_host, double* grad_dev,
+                                      void* values_dev);
+
 /* One implicit-Euler time step (Eq. 2-3): x_dev, v_dev (device N x 3 float64)
  * hold x(t), v(t) on entry and x(t+dt_used), v(t+dt_used) on success; on
  * failure they are left unchanged.  Newton from x(t); block-Jacobi PCG with

@@ -48,6 +48,9 @@ symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool
                      bool want_H, int project, int precision, bool dirichlet, double* g_out,
                      void* dinv, float* dinv_lo);
 symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E);
+symx_status assemble_noalloc(Mesh& m, const double* x, const double* xt, double dt, uint32_t flags,
+                             int precision, double* energy_host, double* grad_dev,
+                             void* values_dev);
 symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P,
                         symx_step_report* out);
 
@@ -259,6 +262,23 @@ symx_status symx_assemble_bsr(symx_mesh mesh, const double* x_dev, const double*
     H_out->precision = precision;
   }
   return hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize");
+  GUARD_END
+}
+
+symx_status symx_assemble_bsr_noalloc(symx_mesh mesh, const double* x_dev,
+                                      const double* x_tilde_dev, double dt, uint32_t flags,
+                                      int32_t precision, double* energy_host, double* grad_dev,
+                                      void* values_dev) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
+  if (!x_dev || (precision != SYMX_F64 && precision != SYMX_F32) ||
+      (x_tilde_dev && !(dt > 0.0)) || ((flags & SYMX_EVAL_E) && !energy_host) ||
+      ((flags & SYMX_EVAL_GRAD) && !grad_dev) || ((flags & SYMX_EVAL_HESS) && !values_dev)) {
+    set_error("invalid arguments to symx_assemble_bsr_noalloc");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  return assemble_noalloc(*mesh->m, x_dev, x_tilde_dev, dt, flags, precision, energy_host,
+                          grad_dev, values_dev);
   GUARD_END
 }
 

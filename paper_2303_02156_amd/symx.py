@@ -91,6 +91,9 @@ EXPORTS = {
     "symx_assemble_bsr": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_uint32,
                                     C.c_int32, C.POINTER(C.c_double), C.c_void_p,
                                     C.POINTER(BsrView)]),
+    "symx_assemble_bsr_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                            C.c_uint32, C.c_int32, C.POINTER(C.c_double),
+                                            C.c_void_p, C.c_void_p]),
     "symx_newton_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(StepParams),
                                    C.POINTER(StepReport)]),
     "symx_mesh_update_rotations": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -180,6 +183,14 @@ def symx_assemble_bsr(h, x_dev, xt_dev, dt, flags, precision, grad_dev):
     _check(load().symx_assemble_bsr(h, x_dev, xt_dev, dt, flags, precision, C.byref(E), grad_dev,
                                     C.byref(view)), "symx_assemble_bsr")
     return E.value, view
+
+
+def symx_assemble_bsr_noalloc(h, x_dev, xt_dev, dt, flags, precision, grad_dev, values_dev):
+    """Returns (status, energy): the allocation-free assembly into values_dev."""
+    E = C.c_double(0.0)
+    st = load().symx_assemble_bsr_noalloc(h, x_dev, xt_dev, dt, flags, precision, C.byref(E),
+                                          grad_dev, values_dev)
+    return st, E.value
 
 
 def symx_newton_step(h, x_dev, v_dev, params):
