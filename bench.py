@@ -185,6 +185,8 @@ def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
                 "melem_steps_per_s": round(float(n_tets / span_s / 1e6), 3),
                 "peak_active": stats.peak_active, "peak_gb": round(stats.peak_bytes / 1e9, 3),
                 "pattern_cache": {"hits": stats.pattern_hits, "misses": stats.pattern_misses},
+                "pcg_batches": stats.pcg_batches, "pcg_chunks": stats.pcg_chunks,
+                "chunks_per_batch": round(stats.pcg_chunks / max(stats.pcg_batches, 1), 2),
                 "mean_phase_ms": dict(zip(("queued", "setup", "step", "teardown"),
                                           [round(float(v), 2) for v in np.mean(phases, axis=0)]))}
 
@@ -195,6 +197,10 @@ def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
     binding = sum(sorted(est)[-3:])
     out["binding_budget"] = run(binding, slots, True)
     log(f"serving binding budget: {out['binding_budget']}")
+    # saturated: every request queued at t = 0, so the slots stay full and
+    # the run measures the capacity of the batched server
+    out["saturated"] = run(int(0.8 * free), slots, False)
+    log(f"serving saturated: {out['saturated']}")
     out["sequential"] = run(int(0.8 * free), 1, False)
     log(f"serving sequential: {out['sequential']}")
     return out
@@ -1121,6 +1127,13 @@ def main():
         "newton_f64": summary(reps_f64),
         "newton_f32_refined": summary(reps_f32r),
         "p99_latency_ms": None if serving is None else serving["full_budget"]["p99_ms"],
+        "serving": None if serving is None else {
+            "p50_ms": serving["full_budget"]["p50_ms"], "p99_ms": serving["full_budget"]["p99_ms"],
+            "requests_per_s": {k: serving[k]["requests_per_s"]
+                               for k in ("full_budget", "saturated", "sequential")},
+            "melem_steps_per_s": {k: serving[k]["melem_steps_per_s"]
+                                  for k in ("full_budget", "saturated", "sequential")},
+            "chunks_per_batch_saturated": serving["saturated"]["chunks_per_batch"]},
         "roofline": roofline,
         "roofline_f32_spmv": roofline32,
         "roofline_assembly": roofline_asm,

@@ -269,7 +269,10 @@ symx_status symx_assemble_bsr_noalloc(symx_mesh mesh, const double* x_dev,
  * forcing term min(forcing_max, sqrt(r_k / r_0)); Armijo backtracking (c = 1e-4,
  * halving, at most 30); on line-search failure or too many Newton iterations
  * the step restarts with dt/2 (at most max_halvings times); the mesh keeps the
- * reduced dt and doubles it back after regrow_after successful steps.
+ * reduced dt and doubles it back after regrow_after successful steps.  With
+ * max_halvings == 0 there is no step control: the step is taken at exactly
+ * params->dt and the mesh's reduced dt and success count are neither used nor
+ * changed (so a given dt sequence can be replayed).
  * report may be NULL. */
 symx_status symx_newton_step(symx_mesh mesh, double* x_dev, double* v_dev,
                              const symx_step_params* params, symx_step_report* report);
@@ -303,6 +306,20 @@ symx_status symx_mesh_update_rotations(symx_mesh mesh, const double* x_dev);
  * meshes of quadratic or cubic tets. */
 symx_status symx_mesh_set_contacts(symx_mesh mesh, int64_t n, const int32_t* tuples_host,
                                    double k_c, double d_hat);
+/* How the contact barrier's activation (Eq. 9) is evaluated.
+ *   SYMX_CONTACT_COMPACT (default): an activation pass flags the candidates
+ *     with d < d_hat, a scan compacts them, and only they are evaluated.
+ *   SYMX_CONTACT_BRANCH: the activation is a branch inside the generated
+ *     element function (Sec. 5.2, branching): every candidate is evaluated,
+ *     and an inactive one takes the zero arm with an if/else, so it costs the
+ *     distance and nothing more; no compaction.
+ * Both give the same energy, gradient and contact matrix (up to rounding
+ * order of the barrier's arithmetic). */
+typedef enum { SYMX_CONTACT_COMPACT = 0, SYMX_CONTACT_BRANCH = 1 } symx_contact_mode;
+/* Select the mode for the mesh's contacts (kept across symx_mesh_set_contacts
+ * calls; INVALID_ARG for another value). */
+symx_status symx_mesh_set_contact_mode(symx_mesh mesh, int32_t mode);
+
 /* View of the contact matrix of the last assembly (device pointers, the
  * layout of symx_bsr_view, n_block_rows = N, blocks of inactive candidates
  * zero), at `precision`.  Without contacts nnzb = 0. */
@@ -330,9 +347,14 @@ symx_status symx_mesh_kernel_names(symx_mesh mesh, char* buf, int64_t buf_len);
  * Requests wait in a FIFO queue and are admitted when one of max_slots slots
  * is free and the request's estimated device footprint fits in what is left
  * of hbm_budget_bytes.  Each slot has its own worker thread and HIP stream;
- * admitted requests run concurrently (their kernels overlap on the device).
+ * admitted requests run concurrently (their kernels overlap on the device),
+ * and the PCG iterations of the requests that are solving at the same time
+ * are batched: one SpMV and one update launch per iteration cover all their
+ * meshes (each with its own grid and arrays), so kernel boundaries are the
+ * only synchronisation and one host synchronisation serves the whole batch.
  * A request is one implicit-Euler time step (as symx_newton_step) of its own
- * scene; the result does not depend on the other requests in flight.
+ * scene; the result does not depend on the other requests in flight (it is
+ * bitwise the result of symx_newton_step on that scene alone).
  * Device memory comes from a pool owned by the server, and the block pattern
  * of a scene stays on the device after its request: a later request with the
  * same node count, energy kinds and connectivity reuses it (only positions,
@@ -344,6 +366,8 @@ typedef struct {
   uint64_t pattern_cache_bytes;      /* idle cached patterns                    */
   int64_t queued, completed;
   int64_t pattern_hits, pattern_misses;
+  int64_t pcg_batches;               /* batched PCG launch sequences            */
+  int64_t pcg_chunks;                /* request chunks they carried             */
   int32_t active, peak_active, max_slots;
 } symx_server_stats;
 

@@ -148,7 +148,11 @@ def newton_solve(scene, x_t, v_t, dt, prm: StepParams, solver="pcg", record=None
 
 
 class Stepper:
-    """Time stepping with dt halving on failure and regrowth after successes."""
+    """Time stepping with dt halving on failure and regrowth after successes.
+
+    With max_halvings == 0 there is no step control: every step is taken at
+    exactly prm.dt and the reduced step and success count are left alone, so a
+    given dt sequence can be replayed."""
 
     def __init__(self, scene, prm: StepParams, solver="pcg"):
         self.scene = scene
@@ -158,7 +162,8 @@ class Stepper:
         self.successes = 0
 
     def step(self, x_t, v_t):
-        dt = self.dt_cur
+        control = self.prm.max_halvings > 0
+        dt = self.dt_cur if control else self.prm.dt
         halvings = 0
         while True:
             ok, x, rep = newton_solve(self.scene, x_t, v_t, dt, self.prm, self.solver)
@@ -171,7 +176,9 @@ class Stepper:
             dt *= 0.5
             halvings += 1
         v = (x - x_t) / dt
-        if halvings:
+        if not control:
+            pass
+        elif halvings:
             self.dt_cur = dt
             self.successes = 0
         else:

@@ -24,7 +24,7 @@ CPU_TESTLIB = os.path.join(BUILD, "libsymx_gen_cpu.so")
 
 HIP_SOURCES = ["symx_mesh.cpp", "symx_kernels.hip", "symx_newton.cpp", "symx_capi.cpp",
                "symx_profile.cpp", "symx_server.cpp", "symx_memory.cpp", "symx_contact.cpp",
-               "symx_contact_pattern.hip", "symx_noalloc.hip"]
+               "symx_contact_pattern.hip", "symx_noalloc.hip", "symx_batch.cpp"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are disabled for all device code

@@ -3,7 +3,12 @@
 
 #include <cmath>
 #include <cstdio>
+#include <climits>
 #include <functional>
+#include <map>
+#include <set>
+#include <tuple>
+#include <unordered_map>
 #include <sstream>
 #include <stdexcept>
 
@@ -11,9 +16,9 @@ namespace symx {
 
 Graph::Graph() { nodes_.reserve(1 << 16); }
 
-int Graph::make(Op op, int a, int b, int n, double c) {
-  char key[96];
-  std::snprintf(key, sizeof key, "%d|%d|%d|%d|%a", (int)op, a, b, n, c);
+int Graph::make(Op op, int a, int b, int n, double c, int e) {
+  char key[112];
+  std::snprintf(key, sizeof key, "%d|%d|%d|%d|%a|%d", (int)op, a, b, n, c, e);
   auto it = cse_.find(key);
   if (it != cse_.end()) return it->second;
   Node nd;
@@ -22,9 +27,11 @@ int Graph::make(Op op, int a, int b, int n, double c) {
   nd.b = b;
   nd.n = n;
   nd.c = c;
+  nd.e = e;
   nd.dep = 0;
   if (a >= 0) nd.dep |= nodes_[a].dep;
   if (b >= 0) nd.dep |= nodes_[b].dep;
+  if (e >= 0) nd.dep |= nodes_[e].dep;
   nodes_.push_back(nd);
   int id = (int)nodes_.size() - 1;
   cse_.emplace(key, id);
@@ -132,6 +139,13 @@ int Graph::pown(int a, int n) {
   return make(Op::PowN, a, -1, n, 0.0);
 }
 
+int Graph::branch(int cond, int t, int e) {
+  const Node& C = nodes_[cond];
+  if (isc(C)) return C.c > 0.0 ? t : e;
+  if (t == e) return t;
+  return make(Op::Branch, cond, t, 0, 0.0, e);
+}
+
 int Graph::diff(int f, int s) {
   auto bit_it = dof_bit_.find(s);
   if (bit_it == dof_bit_.end()) throw std::runtime_error("diff w.r.t. a non-dof symbol");
@@ -158,6 +172,7 @@ int Graph::diff(int f, int s) {
     case Op::Sqrt: r = mul(diff(nd.a, s), mul(cst(0.5), div(cst(1.0), f))); break;
     case Op::Abs: r = mul(diff(nd.a, s), mul(nd.a, div(cst(1.0), f))); break;
     case Op::PowN: r = mul(mul(cst((double)nd.n), pown(nd.a, nd.n - 1)), diff(nd.a, s)); break;
+    case Op::Branch: r = branch(nd.a, diff(nd.b, s), diff(nd.e, s)); break;
     default: throw std::runtime_error("diff: bad op");
   }
   dcache_[key] = r;
@@ -203,6 +218,7 @@ std::vector<int> Graph::tangent(const std::vector<int>& roots,
         case Op::Sqrt: r = mul(go(nd.a), mul(cst(0.5), div(cst(1.0), id))); break;
         case Op::Abs: r = mul(go(nd.a), mul(nd.a, div(cst(1.0), id))); break;
         case Op::PowN: r = mul(mul(cst((double)nd.n), pown(nd.a, nd.n - 1)), go(nd.a)); break;
+        case Op::Branch: r = branch(nd.a, go(nd.b), go(nd.e)); break;
         default: throw std::runtime_error("tangent: bad op");
       }
     }
@@ -246,6 +262,7 @@ std::vector<int> Graph::substitute_nodes(const std::vector<int>& roots,
       case Op::Sqrt: r = sqrt(go(nd.a)); break;
       case Op::Abs: r = abs(go(nd.a)); break;
       case Op::PowN: r = pown(go(nd.a), nd.n); break;
+      case Op::Branch: r = branch(go(nd.a), go(nd.b), go(nd.e)); break;
       default: throw std::runtime_error("substitute: bad op");
     }
     memo[id] = r;
@@ -277,6 +294,10 @@ S log(S a) { return S(a.g, a.g->log(a.id)); }
 S sqrt(S a) { return S(a.g, a.g->sqrt(a.id)); }
 S abs(S a) { return S(a.g, a.g->abs(a.id)); }
 S pown(S a, int n) { return S(a.g, a.g->pown(a.id, n)); }
+S branch(S cond, S t, S e) {
+  Graph* g = cond.g ? cond.g : (t.g ? t.g : e.g);
+  return S(g, g->branch(cond.id, t.id, e.id));
+}
 
 Mat::Mat(int rr, int cc, Graph* g) : r(rr), c(cc), v(rr * cc, S(g, g->cst(0.0))) {}
 
@@ -357,25 +378,28 @@ S dot(const Vec& a, const Vec& b) {
 static std::vector<int> topo_order(const Graph& g, const std::vector<int>& roots) {
   std::vector<int> order;
   std::vector<char> state(g.size(), 0);
-  std::vector<std::pair<int, int>> stack;
+  std::vector<std::pair<int, int>> stack;  // (node, next child slot 0..3)
   for (int r : roots) {
     if (state[r]) continue;
+    state[r] = 1;
     stack.push_back({r, 0});
     while (!stack.empty()) {
       auto& top = stack.back();
-      int id = top.first;
-      const Node& nd = g.node(id);
-      if (top.second == 0) {
-        state[id] = 1;
-        top.second = 1;
-        if (nd.a >= 0 && !state[nd.a]) { stack.push_back({nd.a, 0}); continue; }
+      const Node& nd = g.node(top.first);
+      const int kids[3] = {nd.a, nd.b, nd.e};
+      bool pushed = false;
+      while (top.second < 3) {
+        const int c = kids[top.second++];
+        if (c >= 0 && !state[c]) {
+          state[c] = 1;
+          stack.push_back({c, 0});
+          pushed = true;
+          break;
+        }
       }
-      if (top.second == 1) {
-        top.second = 2;
-        if (nd.b >= 0 && !state[nd.b]) { stack.push_back({nd.b, 0}); continue; }
-      }
+      if (pushed) continue;
+      order.push_back(top.first);
       stack.pop_back();
-      order.push_back(id);
     }
   }
   return order;
@@ -389,6 +413,42 @@ static std::string literal(double c, bool hip) {
   return hip ? "T(" + s + ")" : s;
 }
 
+// Regions of the generated code: the top level, and per region one pair of
+// arms for each branch condition used there.  A node is emitted in the
+// innermost region that contains all of its uses (so operations that only
+// one arm needs run only when that arm is taken).  All branch nodes of one
+// region with the same condition share one if/else:
+//   T vB1, vB2, ...; if (cond > 0) { <then arm> vB1 = t1; ... } else { ... }
+// placed, like any other item of the region, after everything it reads.
+struct Regions {
+  std::vector<int> parent;  // region -> enclosing region (-1 for the top level)
+  std::vector<int> depth;
+  std::map<std::tuple<int, int, int>, int> arm;  // (condition, arm 0/1, enclosing) -> region
+  int of_arm(int cond, int which, int enclosing) {
+    auto key = std::make_tuple(cond, which, enclosing);
+    auto it = arm.find(key);
+    if (it != arm.end()) return it->second;
+    const int r = (int)parent.size();
+    parent.push_back(enclosing);
+    depth.push_back(depth[enclosing] + 1);
+    arm[key] = r;
+    return r;
+  }
+  int lca(int x, int y) const {
+    while (depth[x] > depth[y]) x = parent[x];
+    while (depth[y] > depth[x]) y = parent[y];
+    while (x != y) {
+      x = parent[x];
+      y = parent[y];
+    }
+    return x;
+  }
+  bool inside(int x, int outer) const {  // x is outer or nested in it
+    while (x >= 0 && depth[x] > depth[outer]) x = parent[x];
+    return x == outer;
+  }
+};
+
 static std::string emit_body(const Graph& g, const Function& f, Census* cen, bool hip) {
   Census local;
   Census& C = cen ? *cen : local;
@@ -400,35 +460,161 @@ static std::string emit_body(const Graph& g, const Function& f, Census* cen, boo
     return "v" + std::to_string(id);
   };
   const char* ty = hip ? "const T" : "const double";
-  std::ostringstream os;
-  for (int id : topo_order(g, f.outputs)) {
+  const std::vector<int> order = topo_order(g, f.outputs);
+  std::unordered_map<int, int> pos;  // node -> index in `order`
+  for (size_t i = 0; i < order.size(); ++i) pos[order[i]] = (int)i;
+  // regions: users come after their children in `order`, so a reverse pass
+  // sees every use of a node before the node itself
+  Regions R;
+  R.parent.push_back(-1);
+  R.depth.push_back(0);
+  std::unordered_map<int, int> region;
+  for (int r : f.outputs) region[r] = 0;
+  for (auto it = order.rbegin(); it != order.rend(); ++it) {
+    const int id = *it;
     const Node& nd = g.node(id);
-    if (nd.op == Op::Sym || nd.op == Op::Const) continue;
-    os << "  " << ty << " v" << id << " = ";
-    switch (nd.op) {
-      case Op::Add: os << name(nd.a) << " + " << name(nd.b); C.add++; break;
-      case Op::Sub: os << name(nd.a) << " - " << name(nd.b); C.sub++; break;
-      case Op::Mul: os << name(nd.a) << " * " << name(nd.b); C.mul++; break;
-      case Op::Div: os << name(nd.a) << " / " << name(nd.b); C.div++; break;
-      case Op::Neg: os << "-" << name(nd.a); C.neg++; break;
-      case Op::Log: os << (hip ? "sx_log(" : "log(") << name(nd.a) << ")"; C.log++; break;
-      case Op::Sqrt: os << (hip ? "sx_sqrt(" : "sqrt(") << name(nd.a) << ")"; C.sqrt++; break;
-      case Op::Abs: os << (hip ? "sx_abs(" : "fabs(") << name(nd.a) << ")"; C.abs++; break;
-      case Op::PowN: {
-        C.pown++;
-        if (nd.n >= 2 && nd.n <= 4) {
-          std::string a = name(nd.a);
-          for (int k = 0; k < nd.n; ++k) os << (k ? " * " : "") << a;
-        } else {
-          os << (hip ? "sx_pown<" : "symx_pown(") << (hip ? std::to_string(nd.n) + ">(" : "")
-             << name(nd.a) << (hip ? ")" : ", " + std::to_string(nd.n) + ")");
-        }
-        break;
-      }
-      default: throw std::runtime_error("emit: bad op");
+    const int here = region.count(id) ? region[id] : 0;
+    auto use = [&](int child, int reg) {
+      if (child < 0) return;
+      auto c = region.find(child);
+      region[child] = c == region.end() ? reg : R.lca(c->second, reg);
+    };
+    if (nd.op == Op::Branch) {
+      use(nd.a, here);
+      use(nd.b, R.of_arm(nd.a, 0, here));
+      use(nd.e, R.of_arm(nd.a, 1, here));
+    } else {
+      use(nd.a, here);
+      use(nd.b, here);
     }
-    os << ";\n";
   }
+  auto emitted = [&](int id) {
+    const Op op = g.node(id).op;
+    return op != Op::Sym && op != Op::Const;
+  };
+  std::ostringstream os;
+  std::function<void(int, int)> emit_region = [&](int reg, int indent) {
+    const std::string pad(2 * indent, ' ');
+    // items of the region: its plain nodes, and one if/else per condition
+    // (key: -1 - condition node) holding the branch nodes with that condition
+    std::vector<int> items;
+    std::map<int, std::vector<int>> groups;  // condition -> branch nodes, in order
+    for (int id : order) {
+      if (!emitted(id) || region[id] != reg) continue;
+      const Node& nd = g.node(id);
+      if (nd.op == Op::Branch) {
+        if (!groups.count(nd.a)) items.push_back(-1 - nd.a);
+        groups[nd.a].push_back(id);
+      } else {
+        items.push_back(id);
+      }
+    }
+    // what each item reads from outside itself: a plain node its children; an
+    // if/else the condition and every child, in or below its arms, that lies
+    // outside them
+    auto item_of = [&](int node) -> int {  // the item of this region holding node, or INT_MIN
+      if (!emitted(node)) return INT_MIN;
+      const int rg = region[node];
+      if (rg == reg) {
+        const Node& nd = g.node(node);
+        return nd.op == Op::Branch ? -1 - nd.a : node;
+      }
+      for (const auto& gr : groups) {
+        for (int w = 0; w < 2; ++w) {
+          auto a = R.arm.find(std::make_tuple(gr.first, w, reg));
+          if (a != R.arm.end() && R.inside(rg, a->second)) return -1 - gr.first;
+        }
+      }
+      return INT_MIN;  // an enclosing region's node: already emitted
+    };
+    std::map<int, std::vector<int>> deps;  // item -> items it waits for
+    for (int it : items) {
+      std::vector<int> reads;
+      if (it >= 0) {
+        reads = {g.node(it).a, g.node(it).b};
+      } else {
+        const int cond = -1 - it;
+        reads.push_back(cond);
+        for (int id : order) {
+          if (!emitted(id)) continue;
+          const Node& nd = g.node(id);
+          const int rg = region[id];
+          bool in_group = false;
+          if (rg == reg && nd.op == Op::Branch && nd.a == cond) in_group = true;
+          for (int w = 0; w < 2 && !in_group; ++w) {
+            auto a = R.arm.find(std::make_tuple(cond, w, reg));
+            if (a != R.arm.end() && R.inside(rg, a->second)) in_group = true;
+          }
+          if (!in_group) continue;
+          for (int c : {nd.a, nd.b, nd.e}) reads.push_back(c);
+        }
+      }
+      for (int c : reads) {
+        if (c < 0) continue;
+        const int dep = item_of(c);
+        if (dep != INT_MIN && dep != it) deps[it].push_back(dep);
+      }
+    }
+    // emit in an order that respects the reads (first ready item in the
+    // original order each time)
+    std::vector<int> done_items;
+    std::set<int> done;
+    std::vector<int> pending = items;
+    while (!pending.empty()) {
+      size_t k = 0;
+      for (; k < pending.size(); ++k) {
+        bool ready = true;
+        for (int d : deps[pending[k]]) ready = ready && done.count(d);
+        if (ready) break;
+      }
+      if (k == pending.size()) throw std::runtime_error("emit: cyclic branch grouping");
+      const int it = pending[k];
+      pending.erase(pending.begin() + k);
+      done.insert(it);
+      if (it < 0) {
+        const int cond = -1 - it;
+        const std::vector<int>& br = groups[cond];
+        C.branch++;
+        for (int id : br) os << pad << (hip ? "T" : "double") << " v" << id << ";\n";
+        os << pad << "if (" << name(cond) << " > " << literal(0.0, hip) << ") {\n";
+        for (int w = 0; w < 2; ++w) {
+          auto a = R.arm.find(std::make_tuple(cond, w, reg));
+          if (a != R.arm.end()) emit_region(a->second, indent + 1);
+          for (int id : br)
+            os << pad << "  v" << id << " = " << name(w == 0 ? g.node(id).b : g.node(id).e)
+               << ";\n";
+          os << pad << (w == 0 ? "} else {\n" : "}\n");
+        }
+        continue;
+      }
+      const Node& nd = g.node(it);
+      os << pad << ty << " v" << it << " = ";
+      switch (nd.op) {
+        case Op::Add: os << name(nd.a) << " + " << name(nd.b); C.add++; break;
+        case Op::Sub: os << name(nd.a) << " - " << name(nd.b); C.sub++; break;
+        case Op::Mul: os << name(nd.a) << " * " << name(nd.b); C.mul++; break;
+        case Op::Div: os << name(nd.a) << " / " << name(nd.b); C.div++; break;
+        case Op::Neg: os << "-" << name(nd.a); C.neg++; break;
+        case Op::Log: os << (hip ? "sx_log(" : "log(") << name(nd.a) << ")"; C.log++; break;
+        case Op::Sqrt: os << (hip ? "sx_sqrt(" : "sqrt(") << name(nd.a) << ")"; C.sqrt++; break;
+        case Op::Abs: os << (hip ? "sx_abs(" : "fabs(") << name(nd.a) << ")"; C.abs++; break;
+        case Op::PowN: {
+          C.pown++;
+          if (nd.n >= 2 && nd.n <= 4) {
+            std::string a = name(nd.a);
+            for (int k2 = 0; k2 < nd.n; ++k2) os << (k2 ? " * " : "") << a;
+          } else {
+            os << (hip ? "sx_pown<" : "symx_pown(") << (hip ? std::to_string(nd.n) + ">(" : "")
+               << name(nd.a) << (hip ? ")" : ", " + std::to_string(nd.n) + ")");
+          }
+          break;
+        }
+        default: throw std::runtime_error("emit: bad op");
+      }
+      os << ";\n";
+    }
+  };
+  emit_region(0, 1);
   for (size_t k = 0; k < f.outputs.size(); ++k)
     os << "  out[" << k << "] = " << name(f.outputs[k]) << ";\n";
   return os.str();

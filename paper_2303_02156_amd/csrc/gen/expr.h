@@ -20,11 +20,16 @@
 
 namespace symx {
 
-enum class Op : uint8_t { Sym, Const, Add, Sub, Mul, Div, Neg, Log, Sqrt, Abs, PowN };
+// Branch: the conditional expression of Sec. 5.2 (branching), a > 0 ? b : e,
+// evaluated with a real if/else in the generated code (only the taken arm's
+// exclusive operations run).  Its derivative is the branch of the arms'
+// derivatives (the condition is not differentiated: piecewise definition).
+enum class Op : uint8_t { Sym, Const, Add, Sub, Mul, Div, Neg, Log, Sqrt, Abs, PowN, Branch };
 
 struct Node {
   Op op;
-  int a = -1, b = -1;  // children
+  int a = -1, b = -1;  // children (Branch: condition a, then-arm b)
+  int e = -1;          // Branch: else-arm
   int n = 0;           // symbol index (Sym) or integer exponent (PowN)
   double c = 0.0;      // value (Const)
   uint64_t dep = 0;    // bit k set: depends on differentiation symbol k
@@ -44,6 +49,7 @@ class Graph {
   int sqrt(int a);
   int abs(int a);
   int pown(int a, int n);
+  int branch(int cond, int then_v, int else_v);  // cond > 0 ? then_v : else_v
 
   // Mark the symbol node of an input slot as a differentiation variable; its
   // bit index is the order of the calls (at most 64 variables).
@@ -71,7 +77,7 @@ class Graph {
   }
 
  private:
-  int make(Op op, int a, int b, int n, double c);
+  int make(Op op, int a, int b, int n, double c, int e = -1);
   std::vector<Node> nodes_;
   std::unordered_map<std::string, int> cse_;
   std::unordered_map<uint64_t, int> dcache_;
@@ -102,6 +108,7 @@ S log(S a);
 S sqrt(S a);
 S abs(S a);
 S pown(S a, int n);
+S branch(S cond, S then_v, S else_v);  // cond > 0 ? then_v : else_v
 
 // Small dense helpers (the paper's `Vector` / `Matrix` are arrays of scalars).
 using Vec = std::vector<S>;
@@ -132,6 +139,7 @@ struct Function {
 
 struct Census {
   int add = 0, sub = 0, mul = 0, div = 0, neg = 0, log = 0, sqrt = 0, abs = 0, pown = 0;
+  int branch = 0;  // if/else points (not counted as operations)
   int total() const { return add + sub + mul + div + neg + log + sqrt + abs + pown; }
 };
 

@@ -203,6 +203,17 @@ S ipc_point_plane(Graph& g, const std::vector<S>& in) {
   return -kc * pown(d - dh, 2) * log(d / dh);
 }
 
+// The same barrier with its activation inside the expression: a branch on
+// c_e = d_hat - d (Eq. 9; Sec. 5.2, branching) selects the barrier where the
+// candidate is active and zero elsewhere.  Differentiation keeps the branch,
+// and the generated code takes it with an if/else, so an inactive candidate
+// costs the distance and nothing more.
+S ipc_point_plane_cond(Graph& g, const std::vector<S>& in) {
+  S d = point_plane_distance(g, in);
+  S kc = in[12], dh = in[13];
+  return branch(dh - d, -kc * pown(d - dh, 2) * log(d / dh), S(&g, g.cst(0.0)));
+}
+
 // Its activation c_e = d_hat - d (Eq. 9), compiled as a function of its own.
 S ipc_point_plane_act(Graph& g, const std::vector<S>& in) {
   return in[13] - point_plane_distance(g, in);
@@ -593,6 +604,7 @@ int main(int argc, char** argv) {
       {"arap_tet4", 4, 35, 12, arap_tet4, arap_density},
       {"ipc_point_plane", 4, 14, -1, ipc_point_plane},
       {"ipc_point_plane_act", 4, 14, -1, ipc_point_plane_act},
+      {"ipc_point_plane_cond", 4, 14, -1, ipc_point_plane_cond},
   };
   // Energies differentiated through F throughout: StVK on linear tets (its
   // rows take 979 operations this way against 1,330 by direct

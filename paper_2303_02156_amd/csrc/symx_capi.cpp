@@ -302,6 +302,18 @@ symx_status symx_mesh_set_contacts(symx_mesh mesh, int64_t n, const int32_t* tup
   GUARD_END
 }
 
+symx_status symx_mesh_set_contact_mode(symx_mesh mesh, int32_t mode) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
+  if (mode != SYMX_CONTACT_COMPACT && mode != SYMX_CONTACT_BRANCH) {
+    set_error("invalid contact mode");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  mesh->m->contact_mode = mode;
+  return SYMX_OK;
+  GUARD_END
+}
+
 symx_status symx_mesh_get_contact_bsr(symx_mesh mesh, int32_t precision, symx_bsr_view* view) {
   GUARD_BEGIN
   if (!valid_mesh(mesh) || !view || (precision != SYMX_F64 && precision != SYMX_F32)) {

@@ -4,12 +4,16 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <condition_variable>
 #include <cstdint>
+#include <deque>
+#include <functional>
 #include <list>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -312,7 +316,8 @@ struct SetHost {
   float* d_rot32 = nullptr;
 };
 
-struct Workspace;  // Newton / PCG buffers (symx_newton.cpp)
+struct Workspace;   // Newton / PCG buffers (symx_newton.cpp)
+class PcgBatcher;   // batched PCG of the serving loop (symx_batch.cpp)
 
 // Candidate contacts of the conditional point-plane barrier (node p against
 // the plane of nodes t0, t1, t2) and the block pattern of their couplings: a
@@ -431,6 +436,8 @@ struct Mesh {
   int* nonfinite = nullptr;         // device flag (inside `scalars`)
   Workspace* ws = nullptr;
   Contacts* contacts = nullptr;     // conditional contact barrier, or null
+  int contact_mode = SYMX_CONTACT_COMPACT;  // symx_contact_mode
+  PcgBatcher* batcher = nullptr;    // serving: PCG chunks go through the server's batcher
   // dt control
   double dt_cur = 0.0, dt_nominal = 0.0;
   int successes = 0;
@@ -532,6 +539,63 @@ symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const d
                             double tol2, int max_iter);
 symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0, int n_iter);
 symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs);
+
+// One mesh's share of a batched PCG chunk (serving): iterations k0 .. k0+n-1
+// of the solve in B, in the mesh's own arrays and grids.
+struct PcgBatchItem {
+  Mesh* m;
+  int precision;  // SYMX_F32 or SYMX_F64 (the solve's type)
+  PcgBuffers B;
+  int k0, n;
+};
+// Device table storage of the batched launches and its pinned host staging,
+// for up to `cap` meshes per (precision, contacts) group.
+struct PcgBatchTables {
+  void* dev = nullptr;
+  void* host = nullptr;
+  int cap = 0;
+};
+symx_status pcg_batch_tables_alloc(PcgBatchTables& t, int cap);
+void pcg_batch_tables_free(PcgBatchTables& t);
+// Enqueue on `stream` the items' iterations: per iteration one SpMV and one
+// update launch per (precision, contacts) group, each covering all its meshes.
+symx_status launch_pcg_batch(hipStream_t stream, PcgBatchTables& t, const PcgBatchItem* items,
+                             int n_items);
+
+// Gathers the PCG chunks of concurrently solving meshes and runs them as
+// batched launches on its own stream (symx_batch.cpp).  run() is called by a
+// mesh's Newton loop in place of its own chunk launches and returns the
+// solve's stop flag and iteration count (scalars S_DONE, S_ITERS).  `active`
+// reports how many requests are in flight (the batch waits for up to that
+// many chunks, at most kGatherUs after the first).
+class PcgBatcher {
+ public:
+  PcgBatcher(int device, int max_meshes, std::function<int()> active);
+  ~PcgBatcher();
+  PcgBatcher(const PcgBatcher&) = delete;
+  PcgBatcher& operator=(const PcgBatcher&) = delete;
+  symx_status run(Mesh& m, int precision, const PcgBuffers& B, int k0, int n, double S_out[2]);
+  int64_t batches();  // batched launches sequences so far
+  int64_t chunks();   // mesh chunks they carried
+
+ private:
+  struct Job;
+  void loop();
+  static constexpr int kGatherUs = 100;
+  int device_ = 0;
+  int cap_ = 0;
+  std::function<int()> active_;
+  symx_status init_status_ = SYMX_OK;
+  hipStream_t stream_ = nullptr;
+  PcgBatchTables tables_;
+  double* s_host_ = nullptr;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  std::deque<Job*> pending_;
+  bool stop_ = false;
+  std::thread thread_;
+  int64_t batches_ = 0, chunks_ = 0;
+};
 symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b, double* r);
 // Rounds the float64 Hessian values of the mesh (if mesh_vals) and of its
 // contacts to their float32 copies, and n9 float64 block inverses dinv64 to

@@ -2065,19 +2065,24 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restric
 // Rows (FP32): workgroup b runs on XCD b % 8 and takes, in steps of 16 rows,
 // the rows of the XCD's contiguous eighth of the matrix, so that the gathered
 // entries of z stay in that XCD's L2 (gridDim.x is a multiple of 8).
+// The body takes the workgroup index and count as arguments: a launch of one
+// mesh passes blockIdx.x and gridDim.x, a launch over several meshes each
+// mesh's own index and count (so each mesh computes exactly what it would
+// alone).
 template <typename T, bool DYN>
-__global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* __restrict__ row_ptr,
-                                                  const int* __restrict__ col,
-                                                  const T* __restrict__ vals, int64_t nnzb,
-                                                  const T* __restrict__ z, T* __restrict__ p,
-                                                  T* __restrict__ q, double* __restrict__ P,
-                                                  double* __restrict__ S, int gu, DynBsr<T> C) {
+__device__ __forceinline__ void pcg_spmv_body(int bid, int nblk, int k, int64_t N,
+                                              const int* __restrict__ row_ptr,
+                                              const int* __restrict__ col,
+                                              const T* __restrict__ vals, int64_t nnzb,
+                                              const T* __restrict__ z, T* __restrict__ p,
+                                              T* __restrict__ q, double* __restrict__ P,
+                                              double* __restrict__ S, int gu, DynBsr<T> C) {
   if (S[S_DONE] != 0.0) return;
   __shared__ double sh[4];
   const double rz = sum_partials(P + P_RZ * kPcgP, gu, sh);
   const double rr = sum_partials(P + P_RR * kPcgP, gu, sh);
   const double bb = k == 0 ? sum_partials(P + P_BB * kPcgP, gu, sh) : S[S_BB];
-  const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool first = bid == 0 && threadIdx.x == 0;
   if (bb == 0.0 || rr <= S[S_TOL2] * bb || k >= int(S[S_MAXIT]) || !isfinite(rr)) {
     if (first) {
       S[S_DONE] = isfinite(rr) ? 1.0 : 3.0;
@@ -2093,11 +2098,13 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* _
   const int lane = threadIdx.x & 15;
   // FP32: the XCD-aware row ranges below; FP64 streams twice the bytes per
   // block and runs faster on a plain grid-stride over all rows (measured).
+  // (Over several meshes, each mesh's first workgroup is a multiple of 8, so
+  // bid & 7 is still the workgroup's XCD.)
   constexpr bool kXcd = sizeof(T) == 4;
-  const int xcd = blockIdx.x & 7;
+  const int xcd = bid & 7;
   const int64_t lo = kXcd ? N * xcd / 8 : 0, hi = kXcd ? N * (xcd + 1) / 8 : N;
-  const int64_t stride = kXcd ? (int64_t)(gridDim.x >> 3) * 16 : (int64_t)gridDim.x * 16;
-  const int64_t first_row = kXcd ? (int64_t)(blockIdx.x >> 3) * 16 : (int64_t)blockIdx.x * 16;
+  const int64_t stride = kXcd ? (int64_t)(nblk >> 3) * 16 : (int64_t)nblk * 16;
+  const int64_t first_row = kXcd ? (int64_t)(bid >> 3) * 16 : (int64_t)bid * 16;
   double pq = 0.0;
   for (int64_t row = lo + first_row + (threadIdx.x >> 4); row < hi; row += stride) {
     T acc[3];
@@ -2119,7 +2126,18 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* _
     }
   }
   const double s = block_sum_256(pq, sh);
-  if (threadIdx.x == 0) P[P_PQ * kPcgP + blockIdx.x] = s;
+  if (threadIdx.x == 0) P[P_PQ * kPcgP + bid] = s;
+}
+
+template <typename T, bool DYN>
+__global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* __restrict__ row_ptr,
+                                                  const int* __restrict__ col,
+                                                  const T* __restrict__ vals, int64_t nnzb,
+                                                  const T* __restrict__ z, T* __restrict__ p,
+                                                  T* __restrict__ q, double* __restrict__ P,
+                                                  double* __restrict__ S, int gu, DynBsr<T> C) {
+  pcg_spmv_body<T, DYN>(blockIdx.x, gridDim.x, k, N, row_ptr, col, vals, nnzb, z, p, q, P, S, gu,
+                        C);
 }
 
 // [traffic-hash-end pcg_spmv]
@@ -2127,17 +2145,17 @@ __global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* _
 // Iteration k: alpha = rz_k / p.q; x += alpha p; r -= alpha q; z = M^-1 r;
 // partials of rz, rr.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pcg_update(int k, int64_t N, const T* __restrict__ Dinv,
-                                                    T* __restrict__ xs, T* __restrict__ r,
-                                                    T* __restrict__ z, const T* __restrict__ p,
-                                                    const T* __restrict__ q,
-                                                    double* __restrict__ P,
-                                                    double* __restrict__ S, int gs) {
+__device__ __forceinline__ void pcg_update_body(int bid, int nblk, int k, int64_t N,
+                                                const T* __restrict__ Dinv, T* __restrict__ xs,
+                                                T* __restrict__ r, T* __restrict__ z,
+                                                const T* __restrict__ p, const T* __restrict__ q,
+                                                double* __restrict__ P, double* __restrict__ S,
+                                                int gs) {
   if (S[S_DONE] != 0.0) return;
   __shared__ double sh[4];
   const double pq = sum_partials(P + P_PQ * kPcgP, gs, sh);
   if (!(pq > 0.0)) {  // direction of non-positive curvature: stop
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
       S[S_DONE] = 2.0;
       S[S_ITERS] = double(k);
     }
@@ -2145,7 +2163,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(int k, int64_t N, const T* _
   }
   const T alpha = T(S[S_RZ + (k & 1)] / pq);
   double rz = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+  for (int64_t i = (int64_t)bid * 256 + threadIdx.x; i < N; i += (int64_t)nblk * 256) {
     T rv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -2165,9 +2183,66 @@ __global__ __launch_bounds__(256) void k_pcg_update(int k, int64_t N, const T* _
   const double s0 = block_sum_256(rz, sh);
   const double s1 = block_sum_256(rr, sh);
   if (threadIdx.x == 0) {
-    P[P_RZ * kPcgP + blockIdx.x] = s0;
-    P[P_RR * kPcgP + blockIdx.x] = s1;
+    P[P_RZ * kPcgP + bid] = s0;
+    P[P_RR * kPcgP + bid] = s1;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_update(int k, int64_t N, const T* __restrict__ Dinv,
+                                                    T* __restrict__ xs, T* __restrict__ r,
+                                                    T* __restrict__ z, const T* __restrict__ p,
+                                                    const T* __restrict__ q,
+                                                    double* __restrict__ P,
+                                                    double* __restrict__ S, int gs) {
+  pcg_update_body<T>(blockIdx.x, gridDim.x, k, N, Dinv, xs, r, z, p, q, P, S, gs);
+}
+
+// PCG iterations of several meshes in one launch (the serving loop's batch):
+// workgroups [blk, blk + g) of the launch run mesh s's iteration k0 + j with
+// that mesh's own grid g, so every mesh computes what it would alone.
+template <typename T>
+struct PcgScene {
+  int64_t N, nnzb;
+  const int* row_ptr;
+  const int* col;
+  const T* vals;
+  DynBsr<T> C;
+  const T* Dinv;
+  T *xs, *r, *z, *p, *q;
+  double* P;
+  double* S;
+  int gs, gu;        // the mesh's SpMV and update grids
+  int k0, n;         // first iteration of this chunk, iterations wanted
+  int blk_s, blk_u;  // first workgroup in the SpMV launch (a multiple of 8) and the update launch
+};
+
+template <typename T>
+__device__ __forceinline__ int pcg_scene_of(const PcgScene<T>* __restrict__ tab, int ns,
+                                            bool spmv) {
+  int s = 0;
+  while (s + 1 < ns && (spmv ? tab[s + 1].blk_s : tab[s + 1].blk_u) <= (int)blockIdx.x) ++s;
+  return s;
+}
+
+template <typename T, bool DYN>
+__global__ __launch_bounds__(256) void k_pcg_spmv_multi(int j, const PcgScene<T>* __restrict__ tab,
+                                                        int ns) {
+  const PcgScene<T>& sc = tab[pcg_scene_of(tab, ns, true)];
+  const int bid = (int)blockIdx.x - sc.blk_s;
+  if (j >= sc.n || bid >= sc.gs) return;
+  pcg_spmv_body<T, DYN>(bid, sc.gs, sc.k0 + j, sc.N, sc.row_ptr, sc.col, sc.vals, sc.nnzb, sc.z,
+                        sc.p, sc.q, sc.P, sc.S, sc.gu, sc.C);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_update_multi(int j, const PcgScene<T>* __restrict__ tab,
+                                                          int ns) {
+  const PcgScene<T>& sc = tab[pcg_scene_of(tab, ns, false)];
+  const int bid = (int)blockIdx.x - sc.blk_u;
+  if (j >= sc.n || bid >= sc.gu) return;
+  pcg_update_body<T>(bid, sc.gu, sc.k0 + j, sc.N, sc.Dinv, sc.xs, sc.r, sc.z, sc.p, sc.q, sc.P,
+                     sc.S, sc.gs);
 }
 
 __global__ __launch_bounds__(256) void k_dot64(int64_t n, const double* __restrict__ a,
@@ -2357,6 +2432,30 @@ __global__ __launch_bounds__(128) void k_contact_eval(const int* __restrict__ ac
   }
 }
 
+// Branch mode: every candidate through the barrier whose activation is a
+// branch of its expression (inactive candidates take the zero arm, which
+// skips the barrier's operations); the element arrays are indexed by
+// candidate, slot[c] = c, and the "active" count is n.
+template <typename T>
+__global__ __launch_bounds__(128) void k_contact_eval_branch(int64_t n, const int* __restrict__ tuples,
+                                                            const double* __restrict__ x, double kc,
+                                                            double dhat, T* __restrict__ eg,
+                                                            T* __restrict__ eH,
+                                                            int* __restrict__ slot,
+                                                            int* __restrict__ n_active) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_active = (int)n;
+  for (int64_t k = (int64_t)blockIdx.x * 128 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 128) {
+    T in[14], o[157];
+    fill_contact<T>(tuples + 4 * k, x, kc, dhat, in);
+    ipc_point_plane_cond_s_EgH<T>(in, o);
+#pragma unroll
+    for (int v = 0; v < 12; ++v) eg[k * 12 + v] = o[1 + v];
+#pragma unroll
+    for (int v = 0; v < 144; ++v) eH[k * 144 + v] = o[13 + v];
+    slot[k] = (int)k;
+  }
+}
+
 // Nearest-PSD projection of the active elements' Hessians (the element
 // projection of the mesh's energies; the count is read on the device).
 __global__ __launch_bounds__(64, 2) void k_contact_project32(float* __restrict__ H,
@@ -2458,6 +2557,10 @@ __global__ __launch_bounds__(256) void k_contact_dinv(int64_t n_gnode, const int
 
 // Contact energy of every candidate at x (float64): zero when inactive, +inf
 // when the point is on or behind the plane.
+// BRANCH: the energy comes from the branched barrier for every candidate
+// (zero arm when inactive) instead of the activation test and the plain
+// barrier; the domain end (d <= 0) is +inf in both.
+template <bool BRANCH>
 __global__ __launch_bounds__(256) void k_contact_energy(int64_t n, const int* __restrict__ tuples,
                                                        const double* __restrict__ x, double kc,
                                                        double dhat, double* __restrict__ partials,
@@ -2468,13 +2571,16 @@ __global__ __launch_bounds__(256) void k_contact_energy(int64_t n, const int* __
     double in[14], a[1];
     fill_contact<double>(tuples + 4 * c, x, kc, dhat, in);
     ipc_point_plane_act_s_E<double>(in, a);
-    if (!(a[0] > 0.0)) continue;
+    if (!BRANCH && !(a[0] > 0.0)) continue;
     if (!(a[0] < dhat)) {
       acc = INFINITY;
       continue;
     }
     double e[1];
-    ipc_point_plane_s_E<double>(in, e);
+    if (BRANCH)
+      ipc_point_plane_cond_s_E<double>(in, e);
+    else
+      ipc_point_plane_s_E<double>(in, e);
     acc += e[0];
   }
   const double s = block_sum_256(acc, sh);
@@ -2559,8 +2665,12 @@ symx_status launch_energy(Mesh& m, const double* x, const double* xt, double dt,
   if (m.contacts) {
     const Contacts& c = *m.contacts;
     const int G = grid_for(c.n, 256, 8192);
-    SYMX_LAUNCH(m, "contact_energy", k_contact_energy, dim3(G), dim3(256), 0, c.n, c.tuples, x,
-                c.kc, c.dhat, m.partials + off, m.nonfinite);
+    if (m.contact_mode == SYMX_CONTACT_BRANCH)
+      SYMX_LAUNCH(m, "contact_energy", k_contact_energy<true>, dim3(G), dim3(256), 0, c.n,
+                  c.tuples, x, c.kc, c.dhat, m.partials + off, m.nonfinite);
+    else
+      SYMX_LAUNCH(m, "contact_energy", k_contact_energy<false>, dim3(G), dim3(256), 0, c.n,
+                  c.tuples, x, c.kc, c.dhat, m.partials + off, m.nonfinite);
     LAUNCH_CHECK("k_contact_energy");
     off += G;
   }
@@ -2965,6 +3075,113 @@ symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0
   return SYMX_OK;
 }
 
+// Batched PCG chunks of several meshes (the serving loop): the items are
+// grouped by precision and by whether the mesh has contacts; per iteration,
+// one SpMV and one update launch per group.  Each item's workgroups keep the
+// mesh's own grids (SpMV ranges start at multiples of 8).
+constexpr int kBatchGroups = 4;  // (float, double) x (no contacts, contacts)
+symx_status pcg_batch_tables_alloc(PcgBatchTables& t, int cap) {
+  const size_t bytes = size_t(kBatchGroups) * cap * sizeof(PcgScene<double>);
+  TRY(hip_check(hipMalloc(&t.dev, bytes), "hipMalloc(batch tables)"));
+  TRY(hip_check(hipHostMalloc(&t.host, bytes), "hipHostMalloc(batch tables)"));
+  t.cap = cap;
+  return SYMX_OK;
+}
+
+void pcg_batch_tables_free(PcgBatchTables& t) {
+  if (t.dev) (void)hipFree(t.dev);
+  if (t.host) (void)hipHostFree(t.host);
+  t = PcgBatchTables();
+}
+
+template <typename T>
+static PcgScene<T> pcg_scene(const PcgBatchItem& it) {
+  const Mesh& m = *it.m;
+  const Contacts* cs = m.contacts;
+  PcgScene<T> sc;
+  sc.N = m.N;
+  sc.nnzb = m.nnzb;
+  sc.row_ptr = m.row_ptr;
+  sc.col = m.col_idx;
+  sc.vals = (const T*)(sizeof(T) == 4 ? (const void*)m.vals32 : (const void*)m.vals64);
+  sc.C = DynBsr<T>{cs ? cs->row_ptr : nullptr, cs ? cs->col_idx : nullptr,
+                   cs ? (const T*)(sizeof(T) == 4 ? (const void*)cs->vals32 : (const void*)cs->vals64)
+                      : nullptr,
+                   cs ? cs->nnzb : 0};
+  sc.Dinv = (const T*)it.B.Dinv;
+  sc.xs = (T*)it.B.xs;
+  sc.r = (T*)it.B.r;
+  sc.z = (T*)it.B.z;
+  sc.p = (T*)it.B.p;
+  sc.q = (T*)it.B.q;
+  sc.P = m.partials;
+  sc.S = m.scalars;
+  sc.gs = pcg_gs(m.N);
+  sc.gu = pcg_gu(m.N);
+  sc.k0 = it.k0;
+  sc.n = it.n;
+  sc.blk_s = sc.blk_u = 0;
+  return sc;
+}
+
+template <typename T, bool DYN>
+static symx_status pcg_batch_group(hipStream_t stream, PcgBatchTables& t, int group,
+                                   const std::vector<const PcgBatchItem*>& items, int* n_max,
+                                   const PcgScene<T>** dev_tab, int* gs_total, int* gu_total) {
+  PcgScene<T>* host = (PcgScene<T>*)((char*)t.host + size_t(group) * t.cap * sizeof(PcgScene<double>));
+  PcgScene<T>* dev = (PcgScene<T>*)((char*)t.dev + size_t(group) * t.cap * sizeof(PcgScene<double>));
+  int bs = 0, bu = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    host[i] = pcg_scene<T>(*items[i]);
+    host[i].blk_s = bs;
+    host[i].blk_u = bu;
+    bs += host[i].gs;  // pcg_gs is a multiple of 8
+    bu += host[i].gu;
+    *n_max = std::max(*n_max, host[i].n);
+  }
+  TRY(hip_check(hipMemcpyAsync(dev, host, items.size() * sizeof(PcgScene<T>),
+                               hipMemcpyHostToDevice, stream),
+                "hipMemcpyAsync(batch table)"));
+  *dev_tab = dev;
+  *gs_total = bs;
+  *gu_total = bu;
+  return SYMX_OK;
+}
+
+symx_status launch_pcg_batch(hipStream_t stream, PcgBatchTables& t, const PcgBatchItem* items,
+                             int n_items) {
+  if (n_items > t.cap) {
+    set_error("batched PCG: more meshes than the batch tables hold");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  std::vector<const PcgBatchItem*> grp[kBatchGroups];
+  for (int i = 0; i < n_items; ++i) {
+    const bool f64 = items[i].precision == SYMX_F64;
+    const bool dyn = items[i].m->contacts != nullptr;
+    grp[(f64 ? 2 : 0) + (dyn ? 1 : 0)].push_back(&items[i]);
+  }
+  int n_max = 0;
+  const PcgScene<float>* tf[2] = {nullptr, nullptr};
+  const PcgScene<double>* td[2] = {nullptr, nullptr};
+  int gs[kBatchGroups] = {}, gu[kBatchGroups] = {};
+  if (!grp[0].empty()) TRY((pcg_batch_group<float, false>(stream, t, 0, grp[0], &n_max, &tf[0], &gs[0], &gu[0])));
+  if (!grp[1].empty()) TRY((pcg_batch_group<float, true>(stream, t, 1, grp[1], &n_max, &tf[1], &gs[1], &gu[1])));
+  if (!grp[2].empty()) TRY((pcg_batch_group<double, false>(stream, t, 2, grp[2], &n_max, &td[0], &gs[2], &gu[2])));
+  if (!grp[3].empty()) TRY((pcg_batch_group<double, true>(stream, t, 3, grp[3], &n_max, &td[1], &gs[3], &gu[3])));
+  for (int j = 0; j < n_max; ++j) {
+    if (tf[0]) hipLaunchKernelGGL((k_pcg_spmv_multi<float, false>), dim3(gs[0]), dim3(256), 0, stream, j, tf[0], (int)grp[0].size());
+    if (tf[1]) hipLaunchKernelGGL((k_pcg_spmv_multi<float, true>), dim3(gs[1]), dim3(256), 0, stream, j, tf[1], (int)grp[1].size());
+    if (td[0]) hipLaunchKernelGGL((k_pcg_spmv_multi<double, false>), dim3(gs[2]), dim3(256), 0, stream, j, td[0], (int)grp[2].size());
+    if (td[1]) hipLaunchKernelGGL((k_pcg_spmv_multi<double, true>), dim3(gs[3]), dim3(256), 0, stream, j, td[1], (int)grp[3].size());
+    if (tf[0]) hipLaunchKernelGGL((k_pcg_update_multi<float>), dim3(gu[0]), dim3(256), 0, stream, j, tf[0], (int)grp[0].size());
+    if (tf[1]) hipLaunchKernelGGL((k_pcg_update_multi<float>), dim3(gu[1]), dim3(256), 0, stream, j, tf[1], (int)grp[1].size());
+    if (td[0]) hipLaunchKernelGGL((k_pcg_update_multi<double>), dim3(gu[2]), dim3(256), 0, stream, j, td[0], (int)grp[2].size());
+    if (td[1]) hipLaunchKernelGGL((k_pcg_update_multi<double>), dim3(gu[3]), dim3(256), 0, stream, j, td[1], (int)grp[3].size());
+  }
+  LAUNCH_CHECK("k_pcg_multi");
+  return SYMX_OK;
+}
+
 symx_status launch_accumulate(Mesh& m, int precision, double* dx, const void* xs) {
   const char* PNAME = "accumulate";
   const int64_t n = 3 * m.N;
@@ -2982,13 +3199,16 @@ template <typename T>
 static symx_status contact_assemble_t(Mesh& m, const double* x, bool want_g, bool want_H,
                                       bool project, bool dirichlet, double* g, T* dinv) {
   Contacts& c = *m.contacts;
-  const int n_chunks = (int)((c.n + kContactChunk - 1) / kContactChunk);
-  SYMX_LAUNCH(m, "contact_activate", k_contact_activate, dim3(n_chunks), dim3(256), 0, c.n,
-              c.tuples, x, c.kc, c.dhat, c.flag, c.chunk_count);
-  SYMX_LAUNCH(m, "contact_scan", k_contact_scan, dim3(1), dim3(64), 0, n_chunks, c.chunk_count,
-              c.n_active);
-  SYMX_LAUNCH(m, "contact_compact", k_contact_compact, dim3(n_chunks), dim3(256), 0, c.n, c.flag,
-              c.chunk_count, c.slot, c.act);
+  const bool branch = m.contact_mode == SYMX_CONTACT_BRANCH;
+  if (!branch) {
+    const int n_chunks = (int)((c.n + kContactChunk - 1) / kContactChunk);
+    SYMX_LAUNCH(m, "contact_activate", k_contact_activate, dim3(n_chunks), dim3(256), 0, c.n,
+                c.tuples, x, c.kc, c.dhat, c.flag, c.chunk_count);
+    SYMX_LAUNCH(m, "contact_scan", k_contact_scan, dim3(1), dim3(64), 0, n_chunks, c.chunk_count,
+                c.n_active);
+    SYMX_LAUNCH(m, "contact_compact", k_contact_compact, dim3(n_chunks), dim3(256), 0, c.n,
+                c.flag, c.chunk_count, c.slot, c.act);
+  }
   const size_t eb = size_t(c.n) * kContactVals * sizeof(T);
   if (c.eval_bytes < eb) {
     dev_free(m.pool, c.eval);
@@ -2999,8 +3219,12 @@ static symx_status contact_assemble_t(Mesh& m, const double* x, bool want_g, boo
   }
   T* eg = (T*)c.eval;
   T* eH = eg + 12 * c.n;
-  SYMX_LAUNCH(m, "contact_eval", k_contact_eval<T>, dim3(grid_for(c.n, 128, 8192)), dim3(128), 0,
-              c.act, c.n_active, c.tuples, x, c.kc, c.dhat, eg, eH);
+  if (branch)
+    SYMX_LAUNCH(m, "contact_eval", k_contact_eval_branch<T>, dim3(grid_for(c.n, 128, 8192)),
+                dim3(128), 0, c.n, c.tuples, x, c.kc, c.dhat, eg, eH, c.slot, c.n_active);
+  else
+    SYMX_LAUNCH(m, "contact_eval", k_contact_eval<T>, dim3(grid_for(c.n, 128, 8192)), dim3(128),
+                0, c.act, c.n_active, c.tuples, x, c.kc, c.dhat, eg, eH);
   if (want_H && project) {
     const int G = grid_for(c.n, 64, 65535);
     if (sizeof(T) == 4)

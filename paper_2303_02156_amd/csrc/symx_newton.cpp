@@ -231,9 +231,14 @@ static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rto
   while (true) {
     // the SpMV kernel of iteration max_iter only records the stop
     const int n = std::min(chunk, max_iter + 1 - k);
-    TRY(launch_pcg_iters(m, pp, B, k, n));
+    if (m.batcher) {
+      // serving: the chunk runs in a batched launch with other meshes' chunks
+      TRY(m.batcher->run(m, pp, B, k, n, S));
+    } else {
+      TRY(launch_pcg_iters(m, pp, B, k, n));
+      TRY(sync_read(m, m.scalars, 2, S));
+    }
     k += n;
-    TRY(sync_read(m, m.scalars, 2, S));
     if (S[S_DONE] != 0.0) {
       done_iters = (int)S[S_ITERS];
       *breakdown = S[S_DONE] == 2.0;
@@ -416,12 +421,18 @@ symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P
                 "hipMemcpyAsync"));
   TRY(hip_check(hipMemcpyAsync(w->v_t, v, n * sizeof(double), hipMemcpyDeviceToDevice, m.stream),
                 "hipMemcpyAsync"));
-  if (m.dt_nominal != P.dt) {
+  // Step control: with max_halvings > 0 the mesh carries a reduced dt from
+  // step to step (and doubles it back after regrow_after successes); with
+  // max_halvings == 0 the step is taken at exactly P.dt and the mesh's step
+  // control state is neither used nor changed (e.g. replaying a given dt
+  // sequence).
+  const bool control = P.max_halvings > 0;
+  if (control && m.dt_nominal != P.dt) {
     m.dt_nominal = P.dt;
     m.dt_cur = P.dt;
     m.successes = 0;
   }
-  double dt = m.dt_cur;
+  double dt = control ? m.dt_cur : P.dt;
   int halvings = 0;
   symx_status st;
   while (true) {
@@ -454,7 +465,9 @@ symx_status newton_step(Mesh& m, double* x, double* v, const symx_step_params& P
     TRY(hip_check(hipMemcpyAsync(x, w->xk, n * sizeof(double), hipMemcpyDeviceToDevice, m.stream),
                   "hipMemcpyAsync"));
     TRY(hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize"));
-    if (halvings) {
+    if (!control) {
+      // no step control: the mesh's state stays as it was
+    } else if (halvings) {
       m.dt_cur = dt;
       m.successes = 0;
     } else if (++m.successes >= P.regrow_after && m.dt_cur < m.dt_nominal) {

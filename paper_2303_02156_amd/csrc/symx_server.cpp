@@ -110,6 +110,8 @@ struct Server {
   std::vector<hipStream_t> streams;
   std::unique_ptr<DevicePool> pool;
   std::unique_ptr<TopologyCache> cache;
+  std::atomic<int> solving{0};               // requests between setup and teardown
+  std::unique_ptr<PcgBatcher> batcher;       // batched PCG of the solving requests
 
   void worker(int slot);
   bool fits(size_t bytes);  // with mu held
@@ -158,7 +160,12 @@ void Server::worker(int slot) {
       st = hip_check(hipMemcpyAsync(dv, r->v.data(), nb, hipMemcpyHostToDevice, stream), "copy");
     if (st == SYMX_OK) st = hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
     r->t_setup = clk::now();
-    if (st == SYMX_OK) st = newton_step(*m, dx, dv, r->params, &r->report);
+    if (st == SYMX_OK) {
+      m->batcher = batcher.get();
+      ++solving;
+      st = newton_step(*m, dx, dv, r->params, &r->report);
+      --solving;
+    }
     if (st == SYMX_OK) {
       symx_status s2 = hip_check(hipMemcpyAsync(r->x.data(), dx, nb, hipMemcpyDeviceToHost, stream), "copy");
       if (s2 == SYMX_OK)
@@ -200,6 +207,8 @@ symx_status server_create(uint64_t budget, int32_t max_slots, Server** out) {
   }
   s->pool = std::make_unique<DevicePool>(s->device, budget);
   s->cache = std::make_unique<TopologyCache>(256);
+  s->batcher = std::make_unique<PcgBatcher>(s->device, max_slots,
+                                            [s] { return s->solving.load(); });
   for (int i = 0; i < max_slots; ++i) {
     hipStream_t h = nullptr;
     st = hip_check(hipStreamCreateWithFlags(&h, hipStreamNonBlocking), "hipStreamCreate");
@@ -223,6 +232,7 @@ void server_destroy(Server* s) {
   }
   s->cv_work.notify_all();
   for (std::thread& t : s->workers) t.join();
+  s->batcher.reset();
   for (hipStream_t h : s->streams) (void)hipStreamDestroy(h);
   s->cache.reset();  // cached patterns go back to the pool first
   s->pool.reset();
@@ -324,6 +334,8 @@ void server_stats(Server* s, symx_server_stats* out) {
   out->peak_active = s->peak_active;
   out->completed = s->completed;
   out->max_slots = s->max_slots;
+  out->pcg_batches = s->batcher ? s->batcher->batches() : 0;
+  out->pcg_chunks = s->batcher ? s->batcher->chunks() : 0;
 }
 
 }  // namespace symxi

@@ -21,6 +21,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NONFIN
           5: "NOT_CONVERGED", 6: "LINE_SEARCH", 7: "BUDGET", 8: "PENDING"}
 SYMX_PENDING = 8
 SYMX_F64, SYMX_F32, SYMX_F32_REFINED = 0, 1, 2
+SYMX_CONTACT_COMPACT, SYMX_CONTACT_BRANCH = 0, 1
 SYMX_SNH_TET4, SYMX_STVK_TRI3, SYMX_HINGE4 = 0, 1, 2
 SYMX_NH_TET4, SYMX_STVK_TET4, SYMX_FCR_TET4, SYMX_ARAP_TET4 = 3, 4, 5, 6
 SYMX_EVAL_E, SYMX_EVAL_GRAD, SYMX_EVAL_HESS, SYMX_PROJECT_PSD, SYMX_DIRICHLET = 1, 2, 4, 8, 16
@@ -75,7 +76,8 @@ class ServerStats(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("in_use_bytes", C.c_uint64),
                 ("peak_bytes", C.c_uint64), ("pattern_cache_bytes", C.c_uint64),
                 ("queued", C.c_int64), ("completed", C.c_int64), ("pattern_hits", C.c_int64),
-                ("pattern_misses", C.c_int64), ("active", C.c_int32), ("peak_active", C.c_int32),
+                ("pattern_misses", C.c_int64), ("pcg_batches", C.c_int64),
+                ("pcg_chunks", C.c_int64), ("active", C.c_int32), ("peak_active", C.c_int32),
                 ("max_slots", C.c_int32)]
 
 
@@ -100,6 +102,7 @@ EXPORTS = {
     "symx_mesh_set_contacts": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_double,
                                          C.c_double]),
     "symx_mesh_get_contact_bsr": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(BsrView)]),
+    "symx_mesh_set_contact_mode": (C.c_int, [C.c_void_p, C.c_int32]),
     "symx_mesh_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "symx_mesh_get_kernel_time": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double,
                                             C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -396,6 +399,9 @@ class Mesh:
     def set_contacts(self, tuples, kc, dhat):
         """Candidate contacts (n x 4: point, triangle) of the barrier."""
         symx_mesh_set_contacts(self.handle, tuples, kc, dhat)
+
+    def set_contact_mode(self, mode):
+        _check(load().symx_mesh_set_contact_mode(self.handle, mode), "symx_mesh_set_contact_mode")
 
     def contact_bsr(self, precision=SYMX_F64):
         """Host copies (row_ptr, col_idx, values (nnzb, 3, 3) float64) of the

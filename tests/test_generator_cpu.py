@@ -333,6 +333,50 @@ def test_contact_barrier_generated_vs_oracle(lib):
     assert _rel(a, contact.activation(x, dh)) < 1e-10
 
 
+def test_branched_contact_barrier_generated_vs_oracle(lib):
+    """The barrier with its activation as a branch (Sec. 5.2, branching): on
+    active candidates it equals the oracle's barrier, on inactive ones (the
+    other arm) energy, gradient and Hessian are exactly zero; both arms are
+    taken within one batch of candidates."""
+    from oracle import contact
+    rng = np.random.default_rng(112)
+    n = 40
+    t = rng.normal(size=(n, 3, 3)) * 0.01
+    N = np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    nrm = N / np.linalg.norm(N, axis=1, keepdims=True)
+    # half inside the barrier range (0, d_hat), half beyond it
+    d = np.where(np.arange(n) % 2 == 0, rng.uniform(0.1, 0.95, n), rng.uniform(1.05, 3.0, n)) * 1e-3
+    p = t.mean(axis=1) + rng.normal(size=(n, 3)) * 0.003
+    p = p - np.einsum("ei,ei->e", p - t[:, 0], nrm)[:, None] * nrm + d[:, None] * nrm
+    x = np.concatenate([p[:, None], t], axis=1)
+    kc, dh = 1e3, 1e-3
+    E, g, H, act = contact.point_plane_barrier(x, kc, dh)
+    assert act.sum() == n // 2 and (~act).sum() == n // 2
+    inp = np.concatenate([x.reshape(n, 12), np.full((n, 1), kc), np.full((n, 1), dh)], axis=1)
+    out = _call(lib, "ipc_point_plane_cond_EgH", inp, 157)
+    assert _rel(out[:, 0], E) < 1e-10
+    assert _rel(out[:, 1:13], g.reshape(n, 12)) < 1e-10
+    assert _rel(out[:, 13:], H.reshape(n, 144)) < 1e-10
+    assert np.all(out[~act] == 0.0)
+    rel_in = inp.copy()
+    rel_in[:, :12] -= np.tile(x[:, 0], 4)
+    assert _rel(_call(lib, "ipc_point_plane_cond_s_EgH", rel_in, 157), out) < 1e-10
+    assert _rel(_call(lib, "ipc_point_plane_cond_s_E", rel_in, 1)[:, 0], E) < 1e-10
+
+
+def test_branch_emits_one_if_per_condition(lib):
+    """The generated branched functions evaluate the barrier's operations only
+    in the taken arm: one if/else per function, holding the log."""
+    import re
+    text = open(os.path.join(os.path.dirname(META), "symx_generated_cpu.c")).read()
+    for fn in ("ipc_point_plane_cond_EgH", "ipc_point_plane_cond_s_EgH", "ipc_point_plane_cond_E"):
+        body = text[text.index(f"void {fn}("):]
+        body = body[:body.index("\n}\n")]
+        assert len(re.findall(r"\bif \(", body)) == 1, fn
+        arm = body[body.index("if ("):body.index("} else {")]
+        assert "log(" in arm and "log(" not in body[:body.index("if (")], fn
+
+
 def _tet20_perm(a):
     """Node order putting local node a at position 0 (corner), 4 (edge node:
     its edge's nearer corner first) or 19 (face node: the opposite corner

@@ -86,11 +86,23 @@ def _check_contact_blocks(mesh, ref, precision, tol):
     assert err <= tol * scale
 
 
+MODES = ["compact", "branch"]
+
+
+def _mode(symx, name):
+    return symx.SYMX_CONTACT_BRANCH if name == "branch" else symx.SYMX_CONTACT_COMPACT
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_contact_assembly(symx, precision):
+def test_contact_assembly(symx, precision, mode):
+    """Both activation modes: compaction of the active candidates, and the
+    activation as a branch of the generated element function (every candidate
+    evaluated, inactive ones through the zero arm)."""
     scene = sg.contact_stack_scene(4)
     mesh = symx.Mesh(scene)
     cl = scene.contacts
+    mesh.set_contact_mode(_mode(symx, mode))
     mesh.set_contacts(cl.tuples, cl.kc, cl.dhat)
     dt = scene.dt
     xt = elements.x_tilde(scene.x0, scene.v0, dt, scene.gravity)
@@ -107,12 +119,14 @@ def test_contact_assembly(symx, precision):
     mesh.close()
 
 
-def test_contact_compaction_many_candidates(symx):
+@pytest.mark.parametrize("mode", MODES)
+def test_contact_compaction_many_candidates(symx, mode):
     """3,528 candidates (two compaction chunks), activity by distance."""
     scene = sg.contact_stack_scene(6, seed=10)
     tuples = _all_triangles(scene, 6)
     scene.contacts = sg.ContactList(tuples, kc=1e3, dhat=1e-3)
     mesh = symx.Mesh(scene)
+    mesh.set_contact_mode(_mode(symx, mode))
     mesh.set_contacts(tuples, 1e3, 1e-3)
     xt = elements.x_tilde(scene.x0, scene.v0, scene.dt, scene.gravity)
     E, g, vals = mesh.assemble(scene.x0, xt, scene.dt, FLAGS, symx.SYMX_F64)
@@ -123,10 +137,12 @@ def test_contact_compaction_many_candidates(symx):
     mesh.close()
 
 
-def test_contact_projected(symx):
+@pytest.mark.parametrize("mode", MODES)
+def test_contact_projected(symx, mode):
     scene = sg.contact_stack_scene(4, seed=11)
     cl = scene.contacts
     mesh = symx.Mesh(scene)
+    mesh.set_contact_mode(_mode(symx, mode))
     mesh.set_contacts(cl.tuples, cl.kc, cl.dhat)
     xt = elements.x_tilde(scene.x0, scene.v0, scene.dt, scene.gravity)
     ref = assembly.assemble(scene, scene.x0, xt, scene.dt, project=True)
@@ -168,14 +184,16 @@ def test_contact_list_changes(symx):
     mesh.close()
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("precision", ["f64", "f32r"])
-def test_contact_newton_step(symx, precision):
+def test_contact_newton_step(symx, precision, mode):
     """The upper cube moves down onto the barrier: one implicit-Euler step
     reaches the oracle's minimiser, every active point stays above its plane."""
     scene = sg.contact_stack_scene(4, seed=13)
     cl = scene.contacts
     p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32_REFINED
     mesh = symx.Mesh(scene)
+    mesh.set_contact_mode(_mode(symx, mode))
     mesh.set_contacts(cl.tuples, cl.kc, cl.dhat)
     x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
     v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
@@ -217,4 +235,11 @@ def test_contact_penetration_and_invalid(symx):
         mesh.set_contacts(bad, cl.kc, cl.dhat)
     with pytest.raises(symx.SymxError, match="INVALID_ARG"):
         mesh.set_contacts(cl.tuples, -1.0, cl.dhat)
+    with pytest.raises(symx.SymxError, match="INVALID_ARG"):
+        mesh.set_contact_mode(2)
+    # the branch mode reports the penetration as the compaction mode does
+    mesh.set_contact_mode(symx.SYMX_CONTACT_BRANCH)
+    mesh.set_contacts(cl.tuples, cl.kc, cl.dhat)
+    with pytest.raises(symx.SymxError, match="NONFINITE"):
+        mesh.assemble(x, None, 0.0, 1, symx.SYMX_F64)
     mesh.close()

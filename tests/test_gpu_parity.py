@@ -433,6 +433,33 @@ def test_forced_failures_halve_dt(symx):
     assert np.array_equal(x, scene.x0)  # unchanged on failure
 
 
+def test_uncontrolled_step_takes_the_given_dt(symx):
+    """After a step that succeeded only at a halved dt, the mesh keeps the
+    reduced dt for its next controlled step; a step with max_halvings = 0 is
+    taken at exactly the given dt and leaves that state alone."""
+    scene = sg.config_c4(6)
+    # the smallest Newton iteration limit with which the first step succeeds
+    # (smaller steps need fewer iterations, so it succeeds after halvings)
+    reduced = None
+    for max_newton in range(2, 40):
+        mesh = symx.Mesh(scene)
+        x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+        v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+        st, rep = mesh.newton_step(x, v, symx.step_params(dt=0.01, max_newton=max_newton,
+                                                          max_halvings=6))
+        if st == 0:
+            reduced = rep.dt_used if rep.dt_halvings > 0 else None
+            break
+        mesh.close()
+    assert reduced is not None and reduced < 0.01
+    x1, v1 = x.clone(), v.clone()
+    st, rep = mesh.newton_step(x1, v1, symx.step_params(dt=0.01, max_halvings=0))
+    assert st == 0 and rep.dt_used == 0.01 and rep.dt_halvings == 0
+    st, rep = mesh.newton_step(x, v, symx.step_params(dt=0.01, max_newton=100, max_halvings=6))
+    assert st == 0 and rep.dt_used == reduced
+    mesh.close()
+
+
 def test_invalid_mesh_rejected(symx):
     s = sg.tet_cube_scene(1, seed=1)
     s.energies[0].conn = s.energies[0].conn.copy()
@@ -540,7 +567,7 @@ def test_f32_refined_tracks_f64_trajectory(symx):
     for dt in dts:
         st, rep = mesh.newton_step(x, v, symx.step_params(dt=dt, precision=symx.SYMX_F32_REFINED,
                                                           max_halvings=0))
-        assert st == 0
+        assert st == 0 and rep.dt_used == dt
     x32 = x.cpu().numpy()
     mesh.close()
     disp = np.max(np.linalg.norm(x64 - scene.x0, axis=1))

@@ -117,6 +117,17 @@ def test_many_concurrent_requests_all_succeed(symx):
     res, stats = _run(symx, [(None, sc) for sc in scenes], 8, precision=2)
     assert [r[0] for r in res] == [0] * len(scenes)
     assert stats.completed == len(scenes) and stats.peak_active >= 2
+    # the PCG chunks of concurrently solving requests shared launches
+    assert stats.pcg_batches > 0 and stats.pcg_chunks > stats.pcg_batches
+    # and each result is the direct step's, bit for bit
+    prm = symx.step_params(dt=0.01, precision=2)
+    for (st, rep, x, v, _), sc in list(zip(res, scenes))[:6]:
+        mesh = symx.Mesh(sc)
+        xd = torch.tensor(sc.x0, dtype=torch.float64, device="cuda")
+        vd = torch.tensor(sc.v0, dtype=torch.float64, device="cuda")
+        st2, rep2 = mesh.newton_step(xd, vd, prm)
+        mesh.close()
+        assert st2 == 0 and np.array_equal(xd.cpu().numpy(), x) and np.array_equal(vd.cpu().numpy(), v)
 
 
 def test_resident_patterns_are_reused_and_give_identical_results(symx):

@@ -1123,3 +1123,8 @@ def test_dt_halving_control():
     for k in range(3):
         st2.step(s.x0, s.v0)
     assert st2.dt_cur == 0.005
+    # no step control (max_halvings 0): exactly prm.dt, state untouched
+    st3 = newton.Stepper(s, newton.StepParams(dt=0.01, max_halvings=0))
+    st3.dt_cur = 0.0025
+    _, _, rep = st3.step(s.x0, s.v0)
+    assert rep["dt_used"] == 0.01 and st3.dt_cur == 0.0025 and st3.successes == 0
