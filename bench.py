@@ -282,6 +282,56 @@ def precision_c4(symx, torch, n=64, steps=10):
             continue
         local_pos.append(float(np.max(np.linalg.norm(x32 - states[k + 1][0], axis=1))))
         local_E.append((rep.energy - E64[k]) / abs(E64[k]))
+    # steps where the two runs landed apart: the incremental potential has
+    # several local minima there and the Newton path picks one (the forcing
+    # term decides it in float64 alone); with the forcing term capped at 0.1
+    # both precisions take the same path, which gives the error on one branch
+    same_branch = []
+    for k, dpos in enumerate(local_pos):
+        if not (dpos > 1e-4):
+            continue
+        pair = []
+        for prec in (symx.SYMX_F64, symx.SYMX_F32_REFINED):
+            xd = torch.tensor(states[k][0], dtype=torch.float64, device="cuda")
+            vd = torch.tensor(states[k][1], dtype=torch.float64, device="cuda")
+            st, rep = mesh.newton_step(xd, vd, symx.step_params(dt=dts[k], precision=prec,
+                                                                max_pcg=500, max_halvings=0,
+                                                                forcing_max=0.1))
+            pair.append((st, rep.energy, xd.cpu().numpy()))
+        same_branch.append({
+            "step": k, "default_forcing_abs_position_diff_m": float("%.4g" % dpos),
+            "default_forcing_energies_f64_f32r": [E64[k], E64[k] + local_E[k] * abs(E64[k])]
+            if k < len(local_E) else None,
+            "forcing_0.1_status": [symx.STATUS[pair[0][0]], symx.STATUS[pair[1][0]]],
+            "forcing_0.1_energies_f64_f32r": [pair[0][1], pair[1][1]],
+            "forcing_0.1_abs_position_diff_m": float(
+                "%.4g" % np.max(np.linalg.norm(pair[0][2] - pair[1][2], axis=1)))})
+    # trajectories on one branch: both precisions with the forcing term
+    # capped at 0.1 (the FP64 run chooses the time steps, FP32-refined replays
+    # them)
+    def traj(prec, dts_in):
+        xd = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+        vd = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+        used, E = [], None
+        for k in range(steps):
+            kw = dict(max_halvings=8) if dts_in is None else dict(max_halvings=0)
+            st, rep = mesh.newton_step(xd, vd, symx.step_params(
+                dt=scene.dt if dts_in is None else dts_in[k], precision=prec, max_pcg=500,
+                forcing_max=0.1, **kw))
+            if st != 0:
+                return None, used, None
+            used.append(rep.dt_used)
+            E = rep.energy
+        return xd.cpu().numpy(), used, E
+    x64b, dts_b, E64b = traj(symx.SYMX_F64, None)
+    x32b, _, E32b = traj(symx.SYMX_F32_REFINED, dts_b) if x64b is not None else (None, None, None)
+    traj_b = None
+    if x64b is not None and x32b is not None:
+        disp_b = np.max(np.linalg.norm(x64b - scene.x0, axis=1))
+        traj_b = {"dt_sequence": dts_b,
+                  "max_rel_position_error": float(np.max(np.linalg.norm(x32b - x64b, axis=1)) / disp_b),
+                  "max_abs_position_error_m": float(np.max(np.linalg.norm(x32b - x64b, axis=1))),
+                  "rel_energy_error": float(abs(E32b - E64b) / abs(E64b))}
     xs, vs = states[0]
     traj_ok, fail_at = True, None
     for k in range(steps):
@@ -302,6 +352,8 @@ def precision_c4(symx, torch, n=64, steps=10):
            "per_step_signed_rel_energy_diff_f32r_minus_f64": [float("%.3g" % e) for e in local_E],
            "per_step_note": "steps whose energies differ reached different local minima of the "
                             "non-convex incremental potential (both meet the 1e-6 residual test)",
+           "same_branch": same_branch,
+           "trajectory_forcing_0.1": traj_b,
            "trajectory_converged": traj_ok, "trajectory_failed_at_step": fail_at}
     if traj_ok:
         xT = states[-1][0]

@@ -306,6 +306,23 @@ symx_status symx_mesh_update_rotations(symx_mesh mesh, const double* x_dev);
  * meshes of quadratic or cubic tets. */
 symx_status symx_mesh_set_contacts(symx_mesh mesh, int64_t n, const int32_t* tuples_host,
                                    double k_c, double d_hat);
+/* Dynamic topology (Sec. 5.2, dynamic topology; Alg. 1, the rebuild of the
+ * sparsity when it changes): a set of elements that replaces the previous
+ * dynamic set between steps (set->n_elem = 0 removes it).  Kinds: SYMX_SNH_TET4,
+ * SYMX_NH_TET4, SYMX_STVK_TET4 (parameters as for a static set; their lumped
+ * masses rho V / 4 are added to the static sets' node masses) or SYMX_HINGE4
+ * (no mass).  All host inputs are copied.  The elements' couplings form the
+ * mesh's second block matrix, built on the device as for contacts (a list
+ * that fits the previous buffers reuses them), and assembly, energies, the
+ * PCG and the Newton step include them, summed after the static sets in
+ * element order; with projection on, their element Hessians take the
+ * nearest-PSD projection.  symx_mesh_get_contact_bsr returns that matrix and
+ * symx_mesh_get_masses the combined masses.  A mesh holds either contacts or
+ * a dynamic set (INVALID_ARG for the other); INVALID_ARG also for another
+ * kind, node ids out of range or repeated within an element, degenerate rest
+ * elements, and meshes of quadratic or cubic tets. */
+symx_status symx_mesh_set_dynamic_elements(symx_mesh mesh, const symx_energy_desc* set);
+
 /* How the contact barrier's activation (Eq. 9) is evaluated.
  *   SYMX_CONTACT_COMPACT (default): an activation pass flags the candidates
  *     with d < d_hat, a scan compacts them, and only they are evaluated.
@@ -320,9 +337,10 @@ typedef enum { SYMX_CONTACT_COMPACT = 0, SYMX_CONTACT_BRANCH = 1 } symx_contact_
  * calls; INVALID_ARG for another value). */
 symx_status symx_mesh_set_contact_mode(symx_mesh mesh, int32_t mode);
 
-/* View of the contact matrix of the last assembly (device pointers, the
- * layout of symx_bsr_view, n_block_rows = N, blocks of inactive candidates
- * zero), at `precision`.  Without contacts nnzb = 0. */
+/* View of the contact matrix (or of the dynamic elements' matrix) of the
+ * last assembly (device pointers, the layout of symx_bsr_view,
+ * n_block_rows = N, blocks of inactive candidates zero), at `precision`.
+ * Without contacts or dynamic elements nnzb = 0. */
 symx_status symx_mesh_get_contact_bsr(symx_mesh mesh, int32_t precision, symx_bsr_view* view);
 
 /* Kernel timing for measurement: with profiling on, every kernel launch of

@@ -26,6 +26,7 @@ struct PcgBatcher::Job {
   PcgBatchItem item;
   hipEvent_t ready = nullptr;  // recorded on the mesh's stream before the chunk
   double S[2] = {0.0, 0.0};
+  int ran = 0;  // iterations the batch ran
   symx_status status = SYMX_OK;
   bool done = false;
 };
@@ -59,7 +60,7 @@ PcgBatcher::~PcgBatcher() {
 }
 
 symx_status PcgBatcher::run(Mesh& m, int precision, const PcgBuffers& B, int k0, int n,
-                            double S_out[2]) {
+                            double S_out[2], int* ran) {
   if (init_status_ != SYMX_OK) return init_status_;
   Job job;
   job.item = PcgBatchItem{&m, precision, B, k0, n};
@@ -78,6 +79,7 @@ symx_status PcgBatcher::run(Mesh& m, int precision, const PcgBuffers& B, int k0,
   if (st == SYMX_OK) {
     S_out[0] = job.S[0];
     S_out[1] = job.S[1];
+    *ran = job.ran;
   }
   return st;
 }
@@ -101,10 +103,15 @@ void PcgBatcher::loop() {
       pending_.pop_front();
     }
     lk.unlock();
+    // the batch runs the smallest chunk asked for: no request waits on
+    // iterations of a larger one (those ask again)
+    int n_run = jobs[0]->item.n;
+    for (Job* j : jobs) n_run = std::min(n_run, j->item.n);
     symx_status st = SYMX_OK;
     std::vector<PcgBatchItem> items;
     for (Job* j : jobs) {
       items.push_back(j->item);
+      items.back().n = n_run;
       if (st == SYMX_OK) st = hip_check(hipStreamWaitEvent(stream_, j->ready, 0), "hipStreamWaitEvent");
     }
     if (st == SYMX_OK) st = launch_pcg_batch(stream_, tables_, items.data(), (int)items.size());
@@ -120,6 +127,7 @@ void PcgBatcher::loop() {
       jobs[i]->status = st;
       jobs[i]->S[0] = s_host_[2 * i];
       jobs[i]->S[1] = s_host_[2 * i + 1];
+      jobs[i]->ran = n_run;
       jobs[i]->done = true;
     }
     done_cv_.notify_all();

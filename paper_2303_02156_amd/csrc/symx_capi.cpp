@@ -60,6 +60,8 @@ void mesh_free(Mesh* m) {
   else (void)hipDeviceSynchronize();
   free_workspace(*m);
   contacts_free(*m);
+  dev_free(m->pool, m->dyn.d_prm64);
+  dev_free(m->pool, m->dyn.d_prm32);
   m->prof.destroy();
   void* dev[] = {m->X,        m->mass,     m->fixed,    m->vals32, m->vals64,
                  m->inc_rows, m->inc_pos, m->partials, m->scalars};
@@ -299,6 +301,13 @@ symx_status symx_mesh_set_contacts(symx_mesh mesh, int64_t n, const int32_t* tup
   GUARD_BEGIN
   if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
   return contacts_set(*mesh->m, n, tuples_host, k_c, d_hat);
+  GUARD_END
+}
+
+symx_status symx_mesh_set_dynamic_elements(symx_mesh mesh, const symx_energy_desc* set) {
+  GUARD_BEGIN
+  if (!valid_mesh(mesh)) return SYMX_ERR_INVALID_ARG;
+  return dynamic_set(*mesh->m, set);
   GUARD_END
 }
 

@@ -53,25 +53,39 @@ symx_status put(Mesh& m, T** dst, const T* src, size_t n) {
 }  // namespace
 
 symx_status contacts_set(Mesh& m, int64_t n, const int32_t* tuples, double kc, double dhat) {
-  if (n < 0 || (n > 0 && !tuples) || n >= (int64_t(1) << 26) || !(kc > 0.0) || !(dhat > 0.0) ||
-      !std::isfinite(kc) || !std::isfinite(dhat)) {
+  if (!(kc > 0.0) || !(dhat > 0.0) || !std::isfinite(kc) || !std::isfinite(dhat)) {
     set_error("invalid contact list or barrier parameters");
     return SYMX_ERR_INVALID_ARG;
   }
+  if (m.contacts && m.contacts->kind >= 0) {
+    set_error("the mesh has a dynamic element set: contacts and dynamic elements share the "
+              "second block matrix, remove the dynamic set first");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  return dual_set(m, n, tuples, kc, dhat, -1);
+}
+
+symx_status dual_set(Mesh& m, int64_t n, const int32_t* tuples, double kc, double dhat, int kind) {
+  if (n < 0 || (n > 0 && !tuples) || n >= (int64_t(1) << 26)) {
+    set_error("invalid tuple list");
+    return SYMX_ERR_INVALID_ARG;
+  }
   if (m.ho) {
-    set_error("contacts are not available on meshes of quadratic or cubic tets");
+    set_error("contacts and dynamic elements are not available on meshes of quadratic or cubic "
+              "tets");
     return SYMX_ERR_INVALID_ARG;
   }
   for (int64_t c = 0; c < n; ++c)
     for (int a = 0; a < 4; ++a) {
       const int32_t v = tuples[4 * c + a];
+      const char* what = kind < 0 ? " in contact " : " in dynamic element ";
       if (v < 0 || v >= m.N) {
-        set_error("node id out of range in contact " + std::to_string(c));
+        set_error(std::string("node id out of range") + what + std::to_string(c));
         return SYMX_ERR_INVALID_ARG;
       }
       for (int b = 0; b < a; ++b)
         if (tuples[4 * c + b] == v) {
-          set_error("repeated node in contact " + std::to_string(c));
+          set_error(std::string("repeated node") + what + std::to_string(c));
           return SYMX_ERR_INVALID_ARG;
         }
     }
@@ -90,6 +104,7 @@ symx_status contacts_set(Mesh& m, int64_t n, const int32_t* tuples, double kc, d
     m.contacts = new Contacts();
   }
   Contacts* c = m.contacts;
+  c->kind = kind;
   c->n = n;
   c->kc = kc;
   c->dhat = dhat;

@@ -327,6 +327,9 @@ class PcgBatcher;   // batched PCG of the serving loop (symx_batch.cpp)
 constexpr int kContactVals = 12 + 144;  // gradient and Hessian of one element
 constexpr int kContactChunk = 2048;     // candidates per workgroup of the compaction scan
 struct Contacts {
+  int kind = -1;                   // -1: contact candidates of the point-plane barrier;
+                                   // else the element kind of the mesh's dynamic
+                                   // element set, whose elements are the tuples
   int64_t n = 0;                   // candidate tuples
   double kc = 0.0, dhat = 0.0;
   int* tuples = nullptr;           // n x 4
@@ -435,7 +438,9 @@ struct Mesh {
   double* pinned = nullptr;         // host pinned scalars
   int* nonfinite = nullptr;         // device flag (inside `scalars`)
   Workspace* ws = nullptr;
-  Contacts* contacts = nullptr;     // conditional contact barrier, or null
+  Contacts* contacts = nullptr;     // conditional contact barrier or dynamic elements, or null
+  SetHost dyn;                      // the dynamic element set (when contacts->kind >= 0)
+  std::vector<double> h_mass_static;  // masses of the static sets (dynamic ones added on top)
   int contact_mode = SYMX_CONTACT_COMPACT;  // symx_contact_mode
   PcgBatcher* batcher = nullptr;    // serving: PCG chunks go through the server's batcher
   // dt control
@@ -445,6 +450,7 @@ struct Mesh {
   Profiler prof;
 
   SetsDev sets_dev() const;
+  SetDev dyn_dev() const;           // the dynamic set's device view (conn = the tuples)
 };
 
 constexpr int kMaxPartials = 1 << 16;
@@ -506,6 +512,11 @@ symx_status launch_contact_assemble(Mesh& m, const double* x, bool want_g, bool 
 // Replace the candidate contacts (host n x 4 node ids) and free them.
 symx_status contacts_set(Mesh& m, int64_t n, const int32_t* tuples, double kc, double dhat);
 void contacts_free(Mesh& m);
+// The second block matrix of n 4-node tuples (contacts: kind -1; dynamic
+// elements: their kind), validated and built on the device.
+symx_status dual_set(Mesh& m, int64_t n, const int32_t* tuples, double kc, double dhat, int kind);
+// Replace the mesh's dynamic element set (symx_mesh_set_dynamic_elements).
+symx_status dynamic_set(Mesh& m, const symx_energy_desc* d);
 // Device buffers of the contact pattern and of its build for cap candidates.
 symx_status contacts_reserve_pattern(Mesh& m, Contacts& c, int64_t cap);
 // Contact block pattern and contribution lists of the c.n candidates in
@@ -565,23 +576,25 @@ symx_status launch_pcg_batch(hipStream_t stream, PcgBatchTables& t, const PcgBat
 // Gathers the PCG chunks of concurrently solving meshes and runs them as
 // batched launches on its own stream (symx_batch.cpp).  run() is called by a
 // mesh's Newton loop in place of its own chunk launches and returns the
-// solve's stop flag and iteration count (scalars S_DONE, S_ITERS).  `active`
-// reports how many requests are in flight (the batch waits for up to that
-// many chunks, at most kGatherUs after the first).
+// solve's stop flag and iteration count (scalars S_DONE, S_ITERS) and how many
+// of the n iterations asked for the batch ran (the smallest chunk of the
+// batch).  `active` reports how many requests are in flight (the batch waits
+// for up to that many chunks, at most kGatherUs after the first).
 class PcgBatcher {
  public:
   PcgBatcher(int device, int max_meshes, std::function<int()> active);
   ~PcgBatcher();
   PcgBatcher(const PcgBatcher&) = delete;
   PcgBatcher& operator=(const PcgBatcher&) = delete;
-  symx_status run(Mesh& m, int precision, const PcgBuffers& B, int k0, int n, double S_out[2]);
+  symx_status run(Mesh& m, int precision, const PcgBuffers& B, int k0, int n, double S_out[2],
+                  int* ran);
   int64_t batches();  // batched launches sequences so far
   int64_t chunks();   // mesh chunks they carried
 
  private:
   struct Job;
   void loop();
-  static constexpr int kGatherUs = 100;
+  static constexpr int kGatherUs = 50;
   int device_ = 0;
   int cap_ = 0;
   std::function<int()> active_;

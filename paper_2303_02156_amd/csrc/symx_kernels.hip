@@ -2456,6 +2456,30 @@ __global__ __launch_bounds__(128) void k_contact_eval_branch(int64_t n, const in
   }
 }
 
+// Dynamic element set: every element's gradient and Hessian (generated
+// s_EgH of its kind) in element order, slot[e] = e and the "active" count n;
+// the contact block, gradient and inverse kernels then assemble them.
+template <typename T, int KIND>
+__global__ __launch_bounds__(128) void k_dyn_eval(SetDev S, const double* __restrict__ x,
+                                                  const double* __restrict__ X,
+                                                  T* __restrict__ eg, T* __restrict__ eH,
+                                                  int* __restrict__ slot, int* __restrict__ n_active) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_active = (int)S.n_elem;
+  for (int64_t e = (int64_t)blockIdx.x * 128 + threadIdx.x; e < S.n_elem;
+       e += (int64_t)gridDim.x * 128) {
+    const Relabel R = identity_order(S.conn[e]);
+    T in[kMaxIn];
+    T out[157];
+    elem_inputs<T, KIND>(S, e, R, x, X, in);
+    gen_s_EgH<T, KIND>(in, out);
+#pragma unroll
+    for (int v = 0; v < 12; ++v) eg[e * 12 + v] = out[1 + v];
+#pragma unroll
+    for (int v = 0; v < 144; ++v) eH[e * 144 + v] = out[13 + v];
+    slot[e] = (int)e;
+  }
+}
+
 // Nearest-PSD projection of the active elements' Hessians (the element
 // projection of the mesh's energies; the count is read on the device).
 __global__ __launch_bounds__(64, 2) void k_contact_project32(float* __restrict__ H,
@@ -2662,7 +2686,22 @@ symx_status launch_energy(Mesh& m, const double* x, const double* xt, double dt,
     LAUNCH_CHECK("k_energy_set");
     off += G;
   }
-  if (m.contacts) {
+  if (m.contacts && m.contacts->kind >= 0) {
+    // the dynamic element set, after the static sets
+    const SetDev S = m.dyn_dev();
+    const int G = grid_for(S.n_elem, 256, 8192);
+    host_with_kind(S.kind, [&](auto kc) {
+      constexpr int KIND = decltype(kc)::value;
+      if (precision == SYMX_F32)
+        SYMX_LAUNCH(m, PNAME, (k_energy_set<float, KIND>), dim3(G), dim3(256), 0, S, x, m.X,
+                    m.partials + off, m.nonfinite);
+      else
+        SYMX_LAUNCH(m, PNAME, (k_energy_set<double, KIND>), dim3(G), dim3(256), 0, S, x, m.X,
+                    m.partials + off, m.nonfinite);
+    });
+    LAUNCH_CHECK("k_energy_set");
+    off += G;
+  } else if (m.contacts) {
     const Contacts& c = *m.contacts;
     const int G = grid_for(c.n, 256, 8192);
     if (m.contact_mode == SYMX_CONTACT_BRANCH)
@@ -3200,7 +3239,7 @@ static symx_status contact_assemble_t(Mesh& m, const double* x, bool want_g, boo
                                       bool project, bool dirichlet, double* g, T* dinv) {
   Contacts& c = *m.contacts;
   const bool branch = m.contact_mode == SYMX_CONTACT_BRANCH;
-  if (!branch) {
+  if (!branch && c.kind < 0) {
     const int n_chunks = (int)((c.n + kContactChunk - 1) / kContactChunk);
     SYMX_LAUNCH(m, "contact_activate", k_contact_activate, dim3(n_chunks), dim3(256), 0, c.n,
                 c.tuples, x, c.kc, c.dhat, c.flag, c.chunk_count);
@@ -3219,7 +3258,16 @@ static symx_status contact_assemble_t(Mesh& m, const double* x, bool want_g, boo
   }
   T* eg = (T*)c.eval;
   T* eH = eg + 12 * c.n;
-  if (branch)
+  if (c.kind >= 0) {
+    const SetDev S = m.dyn_dev();
+    host_with_kind(c.kind, [&](auto kc) {
+      constexpr int KIND = decltype(kc)::value;
+      if constexpr (KIND == SYMX_SNH_TET4 || KIND == SYMX_NH_TET4 || KIND == SYMX_STVK_TET4 ||
+                    KIND == SYMX_HINGE4)
+        SYMX_LAUNCH(m, "dyn_eval", (k_dyn_eval<T, KIND>), dim3(grid_for(c.n, 128, 8192)),
+                    dim3(128), 0, S, x, m.X, eg, eH, c.slot, c.n_active);
+    });
+  } else if (branch)
     SYMX_LAUNCH(m, "contact_eval", k_contact_eval_branch<T>, dim3(grid_for(c.n, 128, 8192)),
                 dim3(128), 0, c.n, c.tuples, x, c.kc, c.dhat, eg, eH, c.slot, c.n_active);
   else

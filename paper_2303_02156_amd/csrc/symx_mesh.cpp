@@ -82,6 +82,21 @@ SetsDev Mesh::sets_dev() const {
   return d;
 }
 
+SetDev Mesh::dyn_dev() const {
+  SetDev d{};
+  d.kind = dyn.kind;
+  d.k = 4;
+  d.n_elem = contacts && contacts->kind >= 0 ? contacts->n : 0;
+  d.conn = d.n_elem ? reinterpret_cast<const int4*>(contacts->tuples) : nullptr;
+  d.prm64 = dyn.d_prm64;
+  d.prm32 = dyn.d_prm32;
+  d.prm_stride = dyn.uniform ? 0 : kPrm;
+  d.rot64 = nullptr;
+  d.rot32 = nullptr;
+  d.conn_ho = nullptr;
+  return d;
+}
+
 static int host_threads() {
   return (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
 }
@@ -731,6 +746,71 @@ symx_status mesh_create(const symx_mesh_desc* d, Mesh** out, DevicePool* pool,
   attach_topology(*m, std::move(topo));
   TRY(upload_instance(*m));
   return SYMX_OK;
+}
+
+// Dynamic topology (Sec. 5.2, Alg. 1's rebuild step): a set of 4-node
+// elements replaced between steps.  Its couplings form the mesh's second
+// block matrix (built on the device, as for contacts); its parameters and
+// rest data are computed like a static set's; its lumped masses are added to
+// the static sets' (static sets first, then the dynamic elements in order,
+// the summation order of a mesh that held the set from the start).
+symx_status dynamic_set(Mesh& m, const symx_energy_desc* d) {
+  if (!d) {
+    set_error("null dynamic element set");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  if (m.ho) {
+    set_error("dynamic elements are not available on meshes of quadratic or cubic tets");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  if (m.contacts && m.contacts->kind < 0) {
+    set_error("the mesh has contacts: contacts and dynamic elements share the second block "
+              "matrix, remove the contacts first");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  if (d->kind != SYMX_SNH_TET4 && d->kind != SYMX_NH_TET4 && d->kind != SYMX_STVK_TET4 &&
+      d->kind != SYMX_HINGE4) {
+    set_error("dynamic elements: Stable Neo-Hookean, Neo-Hookean or StVK tets, or hinges");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  const int64_t n = d->n_elem;
+  if (n < 0 || (n > 0 && !d->conn) || n >= (int64_t(1) << 26)) {
+    set_error("invalid dynamic element list");
+    return SYMX_ERR_INVALID_ARG;
+  }
+  for (int64_t i = 0; i < 4 * n; ++i)
+    if (d->conn[i] < 0 || d->conn[i] >= m.N) {
+      set_error("node id out of range in dynamic element " + std::to_string(i / 4));
+      return SYMX_ERR_INVALID_ARG;
+    }
+  if (m.h_mass_static.empty()) m.h_mass_static = m.h_mass;
+  SetHost s;
+  std::vector<double> em;
+  if (n > 0) TRY(build_set(m, *d, s, em));
+  TRY(dual_set(m, n, d->conn, 1.0, 1.0, d->kind));  // n = 0 frees the set
+  dev_free(m.pool, m.dyn.d_prm64);
+  dev_free(m.pool, m.dyn.d_prm32);
+  m.dyn = SetHost();
+  if (n > 0) {
+    m.dyn.kind = s.kind;
+    m.dyn.k = 4;
+    m.dyn.n_elem = n;
+    m.dyn.uniform = s.uniform;
+    m.dyn.prm = std::move(s.prm);
+    std::vector<float> p32(m.dyn.prm.begin(), m.dyn.prm.end());
+    TRY(upload(m.pool, m.stream, &m.dyn.d_prm64, m.dyn.prm.data(), m.dyn.prm.size()));
+    TRY(upload(m.pool, m.stream, &m.dyn.d_prm32, p32.data(), p32.size()));
+  }
+  m.h_mass = m.h_mass_static;
+  if (!em.empty())
+    for (int64_t e = 0; e < n; ++e)
+      for (int a = 0; a < 4; ++a) m.h_mass[d->conn[4 * e + a]] += em[e];
+  m.total_mass = 0.0;
+  for (double v : m.h_mass) m.total_mass += v;
+  TRY(hip_check(hipMemcpyAsync(m.mass, m.h_mass.data(), m.N * sizeof(double),
+                               hipMemcpyHostToDevice, m.stream),
+                "hipMemcpyAsync"));
+  return hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize");
 }
 
 void mesh_free(Mesh* m);

@@ -225,20 +225,23 @@ static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rto
   int done_iters = 0;
   // first chunk sized from the previous solve, so that few launches run past
   // convergence and few host synchronisations are needed
-  int chunk = std::max(8, (7 * m.last_pcg_iters[slot]) / 8);
+  const int target = std::max(8, (7 * m.last_pcg_iters[slot]) / 8);
+  int chunk = target;
   int k = 0;
   *breakdown = false;
   while (true) {
     // the SpMV kernel of iteration max_iter only records the stop
     const int n = std::min(chunk, max_iter + 1 - k);
+    int ran = n;
     if (m.batcher) {
-      // serving: the chunk runs in a batched launch with other meshes' chunks
-      TRY(m.batcher->run(m, pp, B, k, n, S));
+      // serving: the chunk runs in a batched launch with other meshes'
+      // chunks, which may run fewer iterations than asked (`ran`)
+      TRY(m.batcher->run(m, pp, B, k, n, S, &ran));
     } else {
       TRY(launch_pcg_iters(m, pp, B, k, n));
       TRY(sync_read(m, m.scalars, 2, S));
     }
-    k += n;
+    k += ran;
     if (S[S_DONE] != 0.0) {
       done_iters = (int)S[S_ITERS];
       *breakdown = S[S_DONE] == 2.0;
@@ -248,10 +251,11 @@ static symx_status pcg_solve(Mesh& m, int precision, const double* b, double rto
       set_error("PCG did not stop");
       return SYMX_ERR_DEVICE;
     }
-    // past the prediction: short chunks; with no prediction (a fresh mesh),
-    // chunks that double, so both the launches that run past convergence and
-    // the host synchronisations stay few
-    chunk = m.last_pcg_iters[slot] > 0 ? 8 : std::min(64, std::max(8, k));
+    // the rest of the predicted chunk, then short chunks past the prediction;
+    // with no prediction (a fresh mesh), chunks that double, so both the
+    // launches that run past convergence and the host synchronisations stay few
+    chunk = k < target ? target - k
+                       : (m.last_pcg_iters[slot] > 0 ? 8 : std::min(64, std::max(8, k)));
   }
   m.last_pcg_iters[slot] = done_iters;
   *iters = done_iters;

@@ -103,6 +103,7 @@ EXPORTS = {
                                          C.c_double]),
     "symx_mesh_get_contact_bsr": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(BsrView)]),
     "symx_mesh_set_contact_mode": (C.c_int, [C.c_void_p, C.c_int32]),
+    "symx_mesh_set_dynamic_elements": (C.c_int, [C.c_void_p, C.POINTER(EnergyDesc)]),
     "symx_mesh_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "symx_mesh_get_kernel_time": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double,
                                             C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -399,6 +400,23 @@ class Mesh:
     def set_contacts(self, tuples, kc, dhat):
         """Candidate contacts (n x 4: point, triangle) of the barrier."""
         symx_mesh_set_contacts(self.handle, tuples, kc, dhat)
+
+    def set_dynamic_elements(self, es):
+        """Replace the dynamic element set by the scenegen.EnergySet `es` (None
+        or an empty set removes it)."""
+        n = 0 if es is None else int(es.conn.shape[0])
+        conn = np.ascontiguousarray(np.zeros((0, 4)) if es is None else es.conn, dtype=np.int32)
+        young = None
+        if es is not None and es.young_per_elem is not None:
+            young = np.ascontiguousarray(es.young_per_elem, dtype=np.float64)
+        d = EnergyDesc(0 if es is None else es.kind, n, _ptr(conn), _ptr(young),
+                       0.0 if es is None else float(es.young),
+                       0.0 if es is None else float(es.poisson),
+                       0.0 if es is None else float(es.thickness),
+                       0.0 if es is None else float(es.bend_kb),
+                       0.0 if es is None else float(es.density))
+        _check(load().symx_mesh_set_dynamic_elements(self.handle, C.byref(d)),
+               "symx_mesh_set_dynamic_elements")
 
     def set_contact_mode(self, mode):
         _check(load().symx_mesh_set_contact_mode(self.handle, mode), "symx_mesh_set_contact_mode")

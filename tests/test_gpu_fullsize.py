@@ -298,3 +298,86 @@ def test_c3_sampled_rows_match_oracle(symx, c3, precision, project):
     x = _strained(c3, 0.2 / 512, 53)
     _check_sampled_rows(symx, c3, precision, 120, 49, project, x=x)
 
+
+
+def _lanczos_smallest(matvec, v0, iters):
+    """Smallest Ritz value of a symmetric operator (Lanczos with full
+    reorthogonalisation, on the device) and the residual norm of its Ritz
+    vector: an eigenvalue lies within that distance of the Ritz value."""
+    n = v0.numel()
+    Q = torch.zeros((iters + 1, n), dtype=torch.float64, device="cuda")
+    Q[0] = v0 / torch.linalg.norm(v0)
+    alpha, beta = [], []
+    for k in range(iters):
+        w = matvec(Q[k])
+        a = torch.dot(w, Q[k])
+        for _ in range(2):
+            w = w - Q[:k + 1].T @ (Q[:k + 1] @ w)
+        b = torch.linalg.norm(w)
+        alpha.append(float(a))
+        beta.append(float(b))
+        Q[k + 1] = w / b
+    T = np.diag(alpha) + np.diag(beta[:-1], 1) + np.diag(beta[:-1], -1)
+    ev, V = np.linalg.eigh(T)
+    return float(ev[0]), abs(beta[-1] * V[-1, 0])
+
+
+def test_c4_step_endpoints_are_distinct_stationary_minima(symx):
+    """C4 at 64^3 cubes, step 1 (dt 0.005) from the float64 state after step 0:
+    float64 Newton with the forcing term capped at 0.5 and at 0.1 lands on
+    two endpoints centimetres apart.  Both are stationary (the oracle's float64
+    gradient meets the Newton tolerance) and minima (the smallest eigenvalue
+    of the float64 Hessian on the free DoFs is positive), so the incremental
+    potential of this violently compressed, stiffness-contrasted block has
+    several local minima and the linear solver's path picks one; FP32-refined
+    with the same forcing lands on the float64 endpoint."""
+    scene = sg.config_c4(64)
+    mesh = symx.Mesh(scene)
+
+    def step(xs, vs, dt, **kw):
+        x = torch.tensor(xs, dtype=torch.float64, device="cuda")
+        v = torch.tensor(vs, dtype=torch.float64, device="cuda")
+        st, rep = mesh.newton_step(x, v, symx.step_params(dt=dt, max_pcg=500, **kw))
+        assert st == 0, (symx.STATUS[st], rep.as_dict())
+        return x.cpu().numpy(), v.cpu().numpy(), rep
+
+    x0, v0, rep0 = step(scene.x0, scene.v0, 0.01, precision=symx.SYMX_F64)
+    dt = 0.005
+    xa, _, ra = step(x0, v0, dt, precision=symx.SYMX_F64, max_halvings=0)
+    xf, _, rf = step(x0, v0, dt, precision=symx.SYMX_F64, max_halvings=0, forcing_max=0.1)
+    xq, _, rq = step(x0, v0, dt, precision=symx.SYMX_F32_REFINED, max_halvings=0,
+                     forcing_max=0.1)
+    assert np.max(np.linalg.norm(xa - xf, axis=1)) > 1e-2
+    assert abs(ra.energy - rf.energy) > 1e-7 * abs(rf.energy)
+    assert np.max(np.linalg.norm(xq - xf, axis=1)) < 1e-6
+    xt = elements.x_tilde(x0, v0, dt, scene.gravity)
+    rp, ci = assembly.pattern_fast(scene)
+    r0 = np.linalg.norm(assembly.assemble(scene, x0, xt, dt, want_hess=False, row_ptr=rp,
+                                          col_idx=ci)["g"])
+    N = scene.n_nodes
+    br = torch.tensor(np.repeat(np.arange(N), np.diff(rp)), dtype=torch.int64, device="cuda")
+    cc = torch.tensor(ci, dtype=torch.int64, device="cuda")
+    free = torch.tensor(np.repeat(scene.fixed == 0, 3), device="cuda")
+    xtd = torch.tensor(xt, dtype=torch.float64, device="cuda")
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+    for x in (xa, xf):
+        g = assembly.assemble(scene, x, xt, dt, want_hess=False, row_ptr=rp, col_idx=ci)["g"]
+        assert np.linalg.norm(g) <= 1.01e-6 * r0
+        _, _, vals = mesh.assemble(x, xtd, dt, flags, symx.SYMX_F64)
+        rows = torch.cat([3 * br + r for r in range(3) for c in range(3)])
+        cols = torch.cat([3 * cc + c for r in range(3) for c in range(3)])
+        H = torch.sparse_coo_tensor(torch.stack([rows, cols]), vals.reshape(-1),
+                                    (3 * N, 3 * N)).coalesce().to_sparse_csr()
+        # Lanczos on S H S with S = diag(H)^(-1/2): the same inertia as H
+        # (Sylvester's law) and a far smaller condition number
+        dmask = br == cc
+        d = torch.ones(3 * N, dtype=torch.float64, device="cuda")
+        for r in range(3):
+            d[3 * br[dmask] + r] = vals[4 * r][dmask]
+        assert bool(torch.all(d > 0))
+        sc = 1.0 / torch.sqrt(d)
+        v = torch.randn(3 * N, dtype=torch.float64, device="cuda") * free
+        lam, res = _lanczos_smallest(lambda q: sc * (H @ (sc * q)), v, 900)
+        assert lam > 0.0 and res < 0.5 * lam, (lam, res)
+        del H
+    mesh.close()
