@@ -47,8 +47,10 @@ def algorithmic_bytes(kernel, N, nnzb, n_elem, t_bytes):
     """Bytes the method itself must move per launch of a kernel (no staging,
     no index metadata beyond the matrix structure, gathers counted once)."""
     if kernel == "pcg_spmv":
-        # values + column index + row pointer; z read; p, q read and written
-        return (9 * t_bytes + 4) * nnzb + 4 * (N + 1) + 5 * 3 * t_bytes * N
+        # the symmetric matrix's half (blocks (i, j), j <= i: values and
+        # column index) + row pointer; z read; p, q read and written
+        nnzl = (nnzb + N) // 2
+        return (9 * t_bytes + 4) * nnzl + 4 * (N + 1) + 5 * 3 * t_bytes * N
     if kernel == "pcg_update":
         # Dinv (9), x rw, r rw, z w, p r, q r (3 each)
         return (9 + 6 + 6 + 3 + 3 + 3) * t_bytes * N

@@ -267,7 +267,8 @@ symx_status symx_assemble_bsr_noalloc(symx_mesh mesh, const double* x_dev,
  * hold x(t), v(t) on entry and x(t+dt_used), v(t+dt_used) on success; on
  * failure they are left unchanged.  Newton from x(t); block-Jacobi PCG with
  * forcing term min(forcing_max, sqrt(r_k / r_0)); Armijo backtracking (c = 1e-4,
- * halving, at most 30); on line-search failure or too many Newton iterations
+ * halving, at most 30; energies compared up to 1e-12 |E(x)|, the rounding of
+ * their float64 sum); on line-search failure or too many Newton iterations
  * the step restarts with dt/2 (at most max_halvings times); the mesh keeps the
  * reduced dt and doubles it back after regrow_after successful steps.  With
  * max_halvings == 0 there is no step control: the step is taken at exactly

@@ -13,8 +13,11 @@ TEST INFRASTRUCTURE ONLY.  Follows:
   step grows back after a few successes (read here as 3).
 
 Line search: backtracking from alpha = 1, halving while
-E(x + alpha dx) > E(x) + 1e-4 alpha g.dx, at most 30 times.  Convergence:
-||g_free||_2 <= rtol * ||g_free(x(t))||_2.
+E(x + alpha dx) > E(x) + 1e-4 alpha g.dx + 1e-12 |E(x)|, at most 30 times
+(the paper names no line-search rule; this reading adds to Armijo's test the
+rounding of the float64 energy sum, so that close to the minimiser, where the
+energy no longer resolves the decrease, the full Newton step is taken).
+Convergence: ||g_free||_2 <= rtol * ||g_free(x(t))||_2.
 """
 from __future__ import annotations
 
@@ -37,6 +40,7 @@ class StepParams:
     project: bool | str = False        # True: nearest PSD; "filter": see assembly
     ls_max: int = 30
     armijo_c: float = 1e-4
+    energy_round: float = 1e-12       # relative rounding allowance of E comparisons
     max_halvings: int = 8
     regrow_after: int = 3
 
@@ -133,7 +137,7 @@ def newton_solve(scene, x_t, v_t, dt, prm: StepParams, solver="pcg", record=None
         ok = False
         for _ in range(prm.ls_max + 1):
             Et = assembly.energy(scene, x + alpha * dx, xt, dt, x_lag=x_t)
-            if Et <= E0 + prm.armijo_c * alpha * gd:
+            if Et <= E0 + prm.armijo_c * alpha * gd + prm.energy_round * abs(E0):
                 ok = True
                 break
             alpha *= 0.5

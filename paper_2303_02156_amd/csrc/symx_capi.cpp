@@ -63,8 +63,8 @@ void mesh_free(Mesh* m) {
   dev_free(m->pool, m->dyn.d_prm64);
   dev_free(m->pool, m->dyn.d_prm32);
   m->prof.destroy();
-  void* dev[] = {m->X,        m->mass,     m->fixed,    m->vals32, m->vals64,
-                 m->inc_rows, m->inc_pos, m->partials, m->scalars};
+  void* dev[] = {m->X,       m->mass,    m->fixed,    m->vals32,   m->vals64, m->lvals32,
+                 m->lvals64, m->inc_rows, m->inc_pos, m->partials, m->scalars};
   for (void* p : dev) dev_free(m->pool, p);
   for (SetHost& s : m->sets) {
     dev_free(m->pool, s.d_prm64);

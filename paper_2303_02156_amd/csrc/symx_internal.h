@@ -268,6 +268,13 @@ struct Topology {
   int* row_ptr = nullptr;           // N+1
   int* col_idx = nullptr;           // nnzb
   int* diag_pos = nullptr;          // N: index of block (i,i)
+  // the solver's half storage (blocks (i, j) with j <= i, row by row): first
+  // half block of each row (N+1), and for every pattern slot (i, j) the pair
+  // (j, half position of block (i, j)), or (j, ~half position of its
+  // transpose (j, i)) when j > i
+  int64_t nnzl = 0;
+  int* lrow_ptr = nullptr;
+  int2* cv = nullptr;
   int* inc_ptr = nullptr;           // N+1
   uint32_t* inc_code = nullptr;     // n_inc
   int* inc_nodes = nullptr;         // higher-order tets: n_inc x k node ids of the
@@ -419,6 +426,9 @@ struct Mesh {
   const int* row_ptr = nullptr;
   const int* col_idx = nullptr;
   const int* diag_pos = nullptr;
+  int64_t nnzl = 0;                 // half storage of the solver (the topology's)
+  const int* lrow_ptr = nullptr;
+  const int2* cv = nullptr;
   const int* inc_ptr = nullptr;
   const uint32_t* inc_code = nullptr;
   const int* inc_nodes = nullptr;
@@ -428,6 +438,9 @@ struct Mesh {
   const int* batch_entry = nullptr;
   float* vals32 = nullptr;          // 9*nnzb, component-major
   double* vals64 = nullptr;
+  // the Newton solve's matrix: half storage, nine values per block (row-major)
+  float* lvals32 = nullptr;         // 9*nnzl
+  double* lvals64 = nullptr;
   // projected path: incidence positions (n_inc) and records (n_inc x 32)
   int* inc_pos = nullptr;
   void* inc_rows = nullptr;
@@ -482,13 +495,15 @@ symx_status launch_elem_filtered(Mesh& m, int set, const double* x, int precisio
 // records (kIncRec values each) instead of evaluating it.  filter: every set
 // is Stable Neo-Hookean; evaluate each row with the filtered density Hessian.
 // dinv (optional): the kernel also writes the inverses of the final diagonal
-// blocks (N x 9, precision's type).  dinv_lo (float64 only, optional): the
-// linear-tet kernels also write m.vals32 and dinv_lo, the values and
-// inverses rounded to float32 (the higher-order kernels do not).
+// blocks (N x 9, precision's type).  half: the Hessian goes to the solver's
+// half storage (m.lvals64 / m.lvals32) instead of the block arrays
+// (m.vals64 / m.vals32).  dinv_lo (float64 only, optional): the linear-tet
+// kernels also write the values and inverses rounded to float32 (into
+// m.lvals32 or m.vals32, and dinv_lo; the higher-order kernels do not).
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* x_tilde, double dt,
                                 bool want_g, bool want_H, int precision, bool dirichlet,
                                 const void* inc_rows, bool filter, double* g_out, void* dinv,
-                                float* dinv_lo = nullptr);
+                                float* dinv_lo = nullptr, bool half = false);
 // Incidence positions (inverse of the incidence codes), n_inc ints.
 symx_status launch_incidence_positions(Mesh& m, int* inc_pos);
 // Projected element rows into the incidence records (n_inc x 32, precision).
@@ -609,10 +624,12 @@ class PcgBatcher {
   std::thread thread_;
   int64_t batches_ = 0, chunks_ = 0;
 };
+// r = b - A x in float64, A the solver's matrix (half storage of the mesh's
+// blocks in `precision`, plus the contact matrix).
 symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b, double* r);
-// Rounds the float64 Hessian values of the mesh (if mesh_vals) and of its
-// contacts to their float32 copies, and n9 float64 block inverses dinv64 to
-// dinv32 (if given).
+// Rounds the float64 Hessian values of the mesh (half storage, if mesh_vals)
+// and of its contacts to their float32 copies, and n9 float64 block inverses
+// dinv64 to dinv32 (if given).
 symx_status launch_round_values(Mesh& m, bool mesh_vals, const double* dinv64, float* dinv32,
                                 int64_t n9);
 

@@ -1102,10 +1102,16 @@ struct RowArgs {
   const uint16_t* centry;
   const int* batch_entry;
   int64_t nnzb;
-  T* vals;               // component-major 9 x nnzb
+  T* vals;               // component-major 9 x nnzb, or null
   T* dinv;               // N x 9 inverses of the diagonal blocks, or null
   float* vals_lo;        // null, or the values rounded to float32 (as vals)
   float* dinv_lo;        // null, or the inverses rounded to float32 (as dinv)
+  // the solver's half storage (blocks (i, j) with j <= i, nine values each,
+  // row-major), or null; lvals_lo its float32 copy, or null
+  const int* lrow_ptr;
+  int64_t nnzl;
+  T* lvals;
+  float* lvals_lo;
   double* g;             // N x 3
   const T* inc_rows;     // projected path: incidence records (kIncRec per incidence)
   int* nonfinite;
@@ -1251,6 +1257,41 @@ __device__ __forceinline__ void incidence_row_filtered(const RowArgs<T>& A, uint
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int k = 0; k < 3; ++k) out[3 + 9 * i + 3 * (bp - 1) + k] = T(H[i][k]);
+  }
+}
+
+// Layout of the solver's half storage: value c of half block l.  Component-
+// major (nine arrays of nnzl values) when kHalfSoA, else nine consecutive
+// values per block.
+constexpr bool kHalfSoA = false;
+__host__ __device__ __forceinline__ int64_t half_at(int64_t l, int c, int64_t nnzl) {
+  return kHalfSoA ? (int64_t)c * nnzl + l : 9 * l + c;
+}
+
+// Store the final block of row `row`, column `col` at slot `slot` of the row
+// (pattern position row_ptr[row] + slot): into the component-major block
+// arrays and their float32 copy, and into the solver's half storage (when
+// col <= row) and its float32 copy, each when present.
+template <typename T>
+__device__ __forceinline__ void store_block(const RowArgs<T>& A, int row, int col, int slot,
+                                            const T (&acc)[9]) {
+  const int64_t p = (int64_t)A.row_ptr[row] + slot;
+  if (A.vals) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A.vals[(int64_t)c * A.nnzb + p] = acc[c];
+  }
+  if (A.vals_lo) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A.vals_lo[(int64_t)c * A.nnzb + p] = float(acc[c]);
+  }
+  if (A.lvals && col <= row) {
+    const int64_t l = (int64_t)A.lrow_ptr[row] + slot;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A.lvals[half_at(l, c, A.nnzl)] = acc[c];
+    if (A.lvals_lo) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) A.lvals_lo[half_at(l, c, A.nnzl)] = float(acc[c]);
+    }
   }
 }
 
@@ -1420,12 +1461,7 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] = (diag && (c % 4) == 0) ? T(1) : T(0);
     }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) A.vals[(int64_t)c * A.nnzb + p0 + t] = acc[c];
-    if (A.vals_lo) {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) A.vals_lo[(int64_t)c * A.nnzb + p0 + t] = float(acc[c]);
-    }
+    store_block(A, row, col, t - s_blk[r], acc);
     if (diag && A.dinv) {
       double a[9], ri[9];
 #pragma unroll
@@ -1908,8 +1944,7 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] = (diag && (c % 4) == 0) ? T(1) : T(0);
     }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) A.vals[(int64_t)c * A.nnzb + p0 + t] = acc[c];
+    store_block(A, row, col, t - s_blk[r], acc);
     if (diag && A.dinv) {
       double a9[9], ri[9];
 #pragma unroll
@@ -1926,14 +1961,28 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
 // ---------------------------------------------------------------------------
 
 // [traffic-hash-begin pcg_spmv]
-// y = A x (BSR, 16 lanes per block row, lane l takes blocks l, l+16, ...)
+// Lanes per block row of the solver's SpMV kernels (a row of a tet mesh has
+// about 15 blocks).
+constexpr int kSpmvLanes = 16;
+constexpr int kSpmvRows = 256 / kSpmvLanes;  // block rows per 256-lane workgroup pass
+
+// Sum of v over the kSpmvLanes lanes of a row group (same order on every row).
+template <typename TY>
+__device__ __forceinline__ TY row_lane_sum(TY v) {
+#pragma unroll
+  for (int m = kSpmvLanes / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kSpmvLanes);
+  return v;
+}
+
+// y = A x (BSR, component-major values; kSpmvLanes lanes per block row,
+// lane l takes blocks l, l + kSpmvLanes, ...)
 template <typename TA, typename TX, typename TY>
 __device__ __forceinline__ void spmv_row(int row, int lane, const int* __restrict__ row_ptr,
                                          const int* __restrict__ col, const TA* __restrict__ vals,
                                          int64_t nnzb, const TX* __restrict__ x, TY* acc) {
   acc[0] = acc[1] = acc[2] = TY(0);
   const int pe = row_ptr[row + 1];
-  for (int p = row_ptr[row] + lane; p < pe; p += 16) {
+  for (int p = row_ptr[row] + lane; p < pe; p += kSpmvLanes) {
     const int j = col[p];
     // the nine value loads are issued together, ahead of the gather of x
     TY v[9];
@@ -1945,11 +1994,47 @@ __device__ __forceinline__ void spmv_row(int row, int lane, const int* __restric
     acc[2] += v[6] * x0 + v[7] * x1 + v[8] * x2;
   }
 #pragma unroll
-  for (int m = 8; m > 0; m >>= 1) {
-    acc[0] += __shfl_xor(acc[0], m, 16);
-    acc[1] += __shfl_xor(acc[1], m, 16);
-    acc[2] += __shfl_xor(acc[2], m, 16);
+  for (int c = 0; c < 3; ++c) acc[c] = row_lane_sum(acc[c]);
+}
+
+// The solver's matrix in half storage: row i holds its blocks (i, j), j <= i,
+// at half positions lrow_ptr[i] ... (values at half_at); cv[p] pairs pattern
+// slot p's column with the half position to read (bitwise complement: the
+// stored block is the transpose (j, i) of slot (i, j)).
+template <typename T>
+struct HalfBsr {
+  const int* row_ptr;
+  const int2* cv;
+  const T* vals;
+  int64_t nnzl;
+};
+
+// y = A x for one block row of a half-stored symmetric matrix (kSpmvLanes
+// lanes per block row, lane l takes pattern slots l, l + kSpmvLanes, ...;
+// same lane order and reduction as spmv_row).
+template <typename TA, typename TX, typename TY>
+__device__ __forceinline__ void spmv_row_half(int row, int lane, const HalfBsr<TA>& H,
+                                              const TX* __restrict__ x, TY* acc) {
+  acc[0] = acc[1] = acc[2] = TY(0);
+  const int pe = H.row_ptr[row + 1];
+  for (int p = H.row_ptr[row] + lane; p < pe; p += kSpmvLanes) {
+    const int2 e = H.cv[p];
+    const bool tr = e.y < 0;  // the stored block is read by columns
+    const int64_t l = tr ? ~e.y : e.y;
+    TY v[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[c] = TY(H.vals[half_at(l, c, H.nnzl)]);
+    const TY x0 = TY(x[3 * (int64_t)e.x]), x1 = TY(x[3 * (int64_t)e.x + 1]),
+             x2 = TY(x[3 * (int64_t)e.x + 2]);
+    const TY a01 = tr ? v[3] : v[1], a02 = tr ? v[6] : v[2];
+    const TY a10 = tr ? v[1] : v[3], a12 = tr ? v[7] : v[5];
+    const TY a20 = tr ? v[2] : v[6], a21 = tr ? v[5] : v[7];
+    acc[0] += v[0] * x0 + a01 * x1 + a02 * x2;
+    acc[1] += a10 * x0 + v[4] * x1 + a12 * x2;
+    acc[2] += a20 * x0 + a21 * x1 + v[8] * x2;
   }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = row_lane_sum(acc[c]);
 }
 
 // The contact matrix beside the mesh's (DYN): a second BSR over the same rows.
@@ -1963,17 +2048,15 @@ struct DynBsr {
 
 // r = b - A x  (float64 residual of the Newton system, A promoted)
 template <typename TA, bool DYN>
-__global__ __launch_bounds__(256) void k_residual64(int64_t N, const int* __restrict__ row_ptr,
-                                                    const int* __restrict__ col,
-                                                    const TA* __restrict__ vals, int64_t nnzb,
+__global__ __launch_bounds__(256) void k_residual64(int64_t N, HalfBsr<TA> H,
                                                     const double* __restrict__ x,
                                                     const double* __restrict__ b,
                                                     double* __restrict__ r, DynBsr<TA> C) {
-  const int lane = threadIdx.x & 15;
-  for (int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4; row < N;
-       row += ((int64_t)gridDim.x * 256) >> 4) {
+  const int lane = threadIdx.x % kSpmvLanes;
+  for (int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kSpmvLanes; row < N;
+       row += (int64_t)gridDim.x * kSpmvRows) {
     double acc[3];
-    spmv_row<TA, double, double>((int)row, lane, row_ptr, col, vals, nnzb, x, acc);
+    spmv_row_half<TA, double, double>((int)row, lane, H, x, acc);
     if (DYN) {
       double ac[3];
       spmv_row<TA, double, double>((int)row, lane, C.row_ptr, C.col, C.vals, C.nnzb, x, ac);
@@ -2003,7 +2086,7 @@ __global__ __launch_bounds__(256) void k_residual64(int64_t N, const int* __rest
 // entries.
 constexpr int kPcgGs = 2048, kPcgGu = 256, kPcgP = 4096;
 static int pcg_gs(int64_t N) {
-  const int64_t g = (N * 16 + 255) / 256;
+  const int64_t g = (N + kSpmvRows - 1) / kSpmvRows;
   return (int)std::min<int64_t>(kPcgGs, std::max<int64_t>(8, (g + 7) / 8 * 8));
 }
 static int pcg_gu(int64_t N) {
@@ -2062,18 +2145,16 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restric
 // Iteration k: reduce rz, rr of the previous update; stop on convergence or
 // at the iteration limit; beta = rz_k / rz_(k-1); w = A z; p = z + beta p;
 // q = w + beta q; partials of p.q.
-// Rows (FP32): workgroup b runs on XCD b % 8 and takes, in steps of 16 rows,
-// the rows of the XCD's contiguous eighth of the matrix, so that the gathered
-// entries of z stay in that XCD's L2 (gridDim.x is a multiple of 8).
+// Rows: workgroup b runs on XCD b % 8 and takes, in steps of kSpmvRows rows,
+// the rows of the XCD's contiguous eighth of the matrix (gridDim.x is a
+// multiple of 8).
 // The body takes the workgroup index and count as arguments: a launch of one
 // mesh passes blockIdx.x and gridDim.x, a launch over several meshes each
 // mesh's own index and count (so each mesh computes exactly what it would
 // alone).
 template <typename T, bool DYN>
 __device__ __forceinline__ void pcg_spmv_body(int bid, int nblk, int k, int64_t N,
-                                              const int* __restrict__ row_ptr,
-                                              const int* __restrict__ col,
-                                              const T* __restrict__ vals, int64_t nnzb,
+                                              const HalfBsr<T>& H,
                                               const T* __restrict__ z, T* __restrict__ p,
                                               T* __restrict__ q, double* __restrict__ P,
                                               double* __restrict__ S, int gu, DynBsr<T> C) {
@@ -2095,20 +2176,20 @@ __device__ __forceinline__ void pcg_spmv_body(int bid, int nblk, int k, int64_t 
     S[S_RZ + (k & 1)] = rz;
     if (k == 0) S[S_BB] = bb;
   }
-  const int lane = threadIdx.x & 15;
-  // FP32: the XCD-aware row ranges below; FP64 streams twice the bytes per
-  // block and runs faster on a plain grid-stride over all rows (measured).
-  // (Over several meshes, each mesh's first workgroup is a multiple of 8, so
-  // bid & 7 is still the workgroup's XCD.)
-  constexpr bool kXcd = sizeof(T) == 4;
+  const int lane = threadIdx.x % kSpmvLanes;
+  // XCD-aware row ranges: XCD x takes the x-th contiguous eighth of the rows,
+  // so that the gathered entries of z and the transposed blocks (read from
+  // rows a few thousand rows away) are met again in that XCD's L2.  (Over
+  // several meshes, each mesh's first workgroup is a multiple of 8, so bid & 7
+  // is still the workgroup's XCD.)
   const int xcd = bid & 7;
-  const int64_t lo = kXcd ? N * xcd / 8 : 0, hi = kXcd ? N * (xcd + 1) / 8 : N;
-  const int64_t stride = kXcd ? (int64_t)(nblk >> 3) * 16 : (int64_t)nblk * 16;
-  const int64_t first_row = kXcd ? (int64_t)(bid >> 3) * 16 : (int64_t)bid * 16;
+  const int64_t lo = N * xcd / 8, hi = N * (xcd + 1) / 8;
+  const int64_t stride = (int64_t)(nblk >> 3) * kSpmvRows;
+  const int64_t first_row = (int64_t)(bid >> 3) * kSpmvRows;
   double pq = 0.0;
-  for (int64_t row = lo + first_row + (threadIdx.x >> 4); row < hi; row += stride) {
+  for (int64_t row = lo + first_row + threadIdx.x / kSpmvLanes; row < hi; row += stride) {
     T acc[3];
-    spmv_row<T, T, T>((int)row, lane, row_ptr, col, vals, nnzb, z, acc);
+    spmv_row_half<T, T, T>((int)row, lane, H, z, acc);
     if (DYN) {
       T ac[3];
       spmv_row<T, T, T>((int)row, lane, C.row_ptr, C.col, C.vals, C.nnzb, z, ac);
@@ -2130,14 +2211,11 @@ __device__ __forceinline__ void pcg_spmv_body(int bid, int nblk, int k, int64_t 
 }
 
 template <typename T, bool DYN>
-__global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, const int* __restrict__ row_ptr,
-                                                  const int* __restrict__ col,
-                                                  const T* __restrict__ vals, int64_t nnzb,
+__global__ __launch_bounds__(256) void k_pcg_spmv(int k, int64_t N, HalfBsr<T> H,
                                                   const T* __restrict__ z, T* __restrict__ p,
                                                   T* __restrict__ q, double* __restrict__ P,
                                                   double* __restrict__ S, int gu, DynBsr<T> C) {
-  pcg_spmv_body<T, DYN>(blockIdx.x, gridDim.x, k, N, row_ptr, col, vals, nnzb, z, p, q, P, S, gu,
-                        C);
+  pcg_spmv_body<T, DYN>(blockIdx.x, gridDim.x, k, N, H, z, p, q, P, S, gu, C);
 }
 
 // [traffic-hash-end pcg_spmv]
@@ -2203,10 +2281,8 @@ __global__ __launch_bounds__(256) void k_pcg_update(int k, int64_t N, const T* _
 // that mesh's own grid g, so every mesh computes what it would alone.
 template <typename T>
 struct PcgScene {
-  int64_t N, nnzb;
-  const int* row_ptr;
-  const int* col;
-  const T* vals;
+  int64_t N;
+  HalfBsr<T> H;
   DynBsr<T> C;
   const T* Dinv;
   T *xs, *r, *z, *p, *q;
@@ -2231,8 +2307,8 @@ __global__ __launch_bounds__(256) void k_pcg_spmv_multi(int j, const PcgScene<T>
   const PcgScene<T>& sc = tab[pcg_scene_of(tab, ns, true)];
   const int bid = (int)blockIdx.x - sc.blk_s;
   if (j >= sc.n || bid >= sc.gs) return;
-  pcg_spmv_body<T, DYN>(bid, sc.gs, sc.k0 + j, sc.N, sc.row_ptr, sc.col, sc.vals, sc.nnzb, sc.z,
-                        sc.p, sc.q, sc.P, sc.S, sc.gu, sc.C);
+  pcg_spmv_body<T, DYN>(bid, sc.gs, sc.k0 + j, sc.N, sc.H, sc.z, sc.p, sc.q, sc.P, sc.S, sc.gu,
+                        sc.C);
 }
 
 template <typename T>
@@ -2562,17 +2638,22 @@ __global__ __launch_bounds__(256) void k_contact_grad(int64_t n_gnode, const int
 template <typename T>
 __global__ __launch_bounds__(256) void k_contact_dinv(int64_t n_gnode, const int* __restrict__ gnode,
                                                      const int* __restrict__ gdiag,
+                                                     const int* __restrict__ row_ptr,
                                                      const int* __restrict__ diag_pos,
-                                                     const T* __restrict__ vals, int64_t nnzb,
+                                                     const int* __restrict__ lrow_ptr,
+                                                     const T* __restrict__ lvals, int64_t nnzl,
                                                      const T* __restrict__ cvals, int64_t cnnzb,
                                                      T* __restrict__ dinv) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_gnode;
        i += (int64_t)gridDim.x * 256) {
     const int64_t v = gnode[i];
-    const int64_t p = diag_pos[v], q = gdiag[i];
+    // the mesh's diagonal block: the last block of row v's half
+    const int64_t l = (int64_t)lrow_ptr[v] + diag_pos[v] - row_ptr[v];
+    const int64_t q = gdiag[i];
     double a[9], r[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) a[c] = double(vals[c * nnzb + p]) + double(cvals[c * cnnzb + q]);
+    for (int c = 0; c < 9; ++c)
+      a[c] = double(lvals[half_at(l, c, nnzl)]) + double(cvals[c * cnnzb + q]);
     inverse3(a, r);
 #pragma unroll
     for (int c = 0; c < 9; ++c) dinv[9 * v + c] = T(r[c]);
@@ -2876,7 +2957,7 @@ template <typename T>
 static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, double dt,
                                   bool want_g, bool want_H, bool dirichlet,
                                   const void* inc_rows, bool filter, double* g_out, void* dinv,
-                                  float* dinv_lo) {
+                                  float* dinv_lo, bool half) {
   RowArgs<T> A;
   A.sets = m.sets_dev();
   A.x = x;
@@ -2895,18 +2976,25 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
   A.centry = m.centry;
   A.batch_entry = m.batch_entry;
   A.nnzb = m.nnzb;
-  A.vals = nullptr;
-  if (want_H) A.vals = (T*)(sizeof(T) == 4 ? (void*)m.vals32 : (void*)m.vals64);
-  A.g = g_out;
-  A.dinv = (T*)dinv;
+  T* const v = (T*)(sizeof(T) == 4 ? (half ? (void*)m.lvals32 : (void*)m.vals32)
+                                    : (half ? (void*)m.lvals64 : (void*)m.vals64));
   // float32 copies written by the float64 kernel itself (not by the
   // higher-order kernels, whose copies are rounded afterwards)
-  A.vals_lo = want_H && dinv_lo && !m.ho ? m.vals32 : nullptr;
+  float* const v_lo = want_H && dinv_lo && !m.ho ? (half ? m.lvals32 : m.vals32) : nullptr;
+  A.vals = want_H && !half ? v : nullptr;
+  A.vals_lo = half ? nullptr : v_lo;
+  A.lrow_ptr = m.lrow_ptr;
+  A.nnzl = m.nnzl;
+  A.lvals = want_H && half ? v : nullptr;
+  A.lvals_lo = half ? v_lo : nullptr;
+  A.g = g_out;
+  A.dinv = (T*)dinv;
   A.dinv_lo = want_H && !m.ho ? dinv_lo : nullptr;
   A.nonfinite = m.nonfinite;
   A.inc_rows = (const T*)inc_rows;
   A.inc_nodes = m.inc_nodes;
-  if ((want_g && !g_out) || (!want_g && !want_H)) {
+  if ((want_g && !g_out) || (!want_g && !want_H) || (want_H && !v) ||
+      (want_H && dinv_lo && !m.ho && !v_lo)) {
     set_error("row assembly without an output");
     return SYMX_ERR_INVALID_ARG;
   }
@@ -2959,16 +3047,16 @@ static symx_status row_assemble_t(Mesh& m, const double* x, const double* xt, do
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g,
                                 bool want_H, int precision, bool dirichlet,
                                 const void* inc_rows, bool filter, double* g_out, void* dinv,
-                                float* dinv_lo) {
+                                float* dinv_lo, bool half) {
   if (precision == SYMX_F32)
     return row_assemble_t<float>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, filter, g_out,
-                                 dinv, nullptr);
-  if (dinv_lo && (!m.vals32 || !dinv)) {
-    set_error("row assembly: float32 copies need the float32 values and the inverses");
+                                 dinv, nullptr, half);
+  if (dinv_lo && !dinv) {
+    set_error("row assembly: float32 copies need the inverses");
     return SYMX_ERR_INVALID_ARG;
   }
   return row_assemble_t<double>(m, x, xt, dt, want_g, want_H, dirichlet, inc_rows, filter, g_out,
-                                dinv, dinv_lo);
+                                dinv, dinv_lo, half);
 }
 
 symx_status launch_x_tilde(Mesh& m, const double* x, const double* v, double dt, const double g[3],
@@ -3012,14 +3100,14 @@ symx_status launch_velocity(Mesh& m, double* v, const double* xn, const double* 
 symx_status launch_round_values(Mesh& m, bool mesh_vals, const double* dinv64, float* dinv32,
                                 int64_t n9) {
   const char* PNAME = "round_values";
-  if (!m.vals64 || !m.vals32) {
+  if (mesh_vals && (!m.lvals64 || !m.lvals32)) {
     set_error("round_values: the float64 and float32 value arrays must exist");
     return SYMX_ERR_INVALID_ARG;
   }
-  const int64_t nv = 9 * m.nnzb;
+  const int64_t nv = 9 * m.nnzl;
   if (mesh_vals)
     SYMX_LAUNCH(m, PNAME, k_round_f64, dim3(grid_for(nv, 256, 8192)), dim3(256), 0, nv,
-                (const double*)m.vals64, m.vals32);
+                (const double*)m.lvals64, m.lvals32);
   if (m.contacts && m.contacts->nnzb > 0) {
     Contacts& c = *m.contacts;
     if (c.vals_cap32 < c.nnzb) {
@@ -3067,6 +3155,14 @@ symx_status launch_pcg_init(Mesh& m, int precision, const PcgBuffers& B, const d
   return SYMX_OK;
 }
 
+// The mesh's half-stored solver matrix in precision T.
+template <typename T>
+static HalfBsr<T> half_bsr(const Mesh& m) {
+  return HalfBsr<T>{m.row_ptr, m.cv,
+                    (const T*)(sizeof(T) == 4 ? (const void*)m.lvals32 : (const void*)m.lvals64),
+                    m.nnzl};
+}
+
 // Enqueue iterations k0 .. k0+n_iter-1 (each: SpMV kernel, update kernel).
 symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0, int n_iter) {
   const int gs = pcg_gs(m.N), gu = pcg_gu(m.N);
@@ -3075,27 +3171,27 @@ symx_status launch_pcg_iters(Mesh& m, int precision, const PcgBuffers& B, int k0
                            cs ? cs->vals64 : nullptr, cs ? cs->nnzb : 0};
   const DynBsr<float> C32{cs ? cs->row_ptr : nullptr, cs ? cs->col_idx : nullptr,
                           cs ? cs->vals32 : nullptr, cs ? cs->nnzb : 0};
+  const HalfBsr<double> H64 = half_bsr<double>(m);
+  const HalfBsr<float> H32 = half_bsr<float>(m);
   for (int it = k0; it < k0 + n_iter; ++it) {
     {
       const char* PNAME = "pcg_spmv";
       if (precision == SYMX_F64) {
         if (cs)
-          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<double, true>), dim3(gs), dim3(256), 0, it, m.N,
-                      m.row_ptr, m.col_idx, m.vals64, m.nnzb, (const double*)B.z, (double*)B.p,
-                      (double*)B.q, m.partials, m.scalars, gu, C64);
+          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<double, true>), dim3(gs), dim3(256), 0, it, m.N, H64,
+                      (const double*)B.z, (double*)B.p, (double*)B.q, m.partials, m.scalars, gu,
+                      C64);
         else
-          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<double, false>), dim3(gs), dim3(256), 0, it, m.N,
-                      m.row_ptr, m.col_idx, m.vals64, m.nnzb, (const double*)B.z, (double*)B.p,
-                      (double*)B.q, m.partials, m.scalars, gu, C64);
+          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<double, false>), dim3(gs), dim3(256), 0, it, m.N, H64,
+                      (const double*)B.z, (double*)B.p, (double*)B.q, m.partials, m.scalars, gu,
+                      C64);
       } else {
         if (cs)
-          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<float, true>), dim3(gs), dim3(256), 0, it, m.N,
-                      m.row_ptr, m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p,
-                      (float*)B.q, m.partials, m.scalars, gu, C32);
+          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<float, true>), dim3(gs), dim3(256), 0, it, m.N, H32,
+                      (const float*)B.z, (float*)B.p, (float*)B.q, m.partials, m.scalars, gu, C32);
         else
-          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<float, false>), dim3(gs), dim3(256), 0, it, m.N,
-                      m.row_ptr, m.col_idx, m.vals32, m.nnzb, (const float*)B.z, (float*)B.p,
-                      (float*)B.q, m.partials, m.scalars, gu, C32);
+          SYMX_LAUNCH(m, PNAME, (k_pcg_spmv<float, false>), dim3(gs), dim3(256), 0, it, m.N, H32,
+                      (const float*)B.z, (float*)B.p, (float*)B.q, m.partials, m.scalars, gu, C32);
       }
     }
     {
@@ -3139,10 +3235,7 @@ static PcgScene<T> pcg_scene(const PcgBatchItem& it) {
   const Contacts* cs = m.contacts;
   PcgScene<T> sc;
   sc.N = m.N;
-  sc.nnzb = m.nnzb;
-  sc.row_ptr = m.row_ptr;
-  sc.col = m.col_idx;
-  sc.vals = (const T*)(sizeof(T) == 4 ? (const void*)m.vals32 : (const void*)m.vals64);
+  sc.H = half_bsr<T>(m);
   sc.C = DynBsr<T>{cs ? cs->row_ptr : nullptr, cs ? cs->col_idx : nullptr,
                    cs ? (const T*)(sizeof(T) == 4 ? (const void*)cs->vals32 : (const void*)cs->vals64)
                       : nullptr,
@@ -3296,9 +3389,11 @@ static symx_status contact_assemble_t(Mesh& m, const double* x, bool want_g, boo
     SYMX_LAUNCH(m, "contact_blocks", k_contact_blocks<T>, dim3(grid_for(c.nnzb, 256)), dim3(256),
                 0, c.nnzb, c.blk_row, c.col_idx, c.blk_ptr, c.blk_src, c.slot, eH, fixed, vals);
     if (dinv) {
-      const T* mv = (const T*)(sizeof(T) == 4 ? (void*)m.vals32 : (void*)m.vals64);
+      // with the inverses, the mesh's blocks are in the solver's half storage
+      const T* mv = (const T*)(sizeof(T) == 4 ? (void*)m.lvals32 : (void*)m.lvals64);
       SYMX_LAUNCH(m, "contact_dinv", k_contact_dinv<T>, dim3(grid_for(c.n_gnode, 256)), dim3(256),
-                  0, c.n_gnode, c.gnode, c.gdiag, m.diag_pos, mv, m.nnzb, vals, c.nnzb, dinv);
+                  0, c.n_gnode, c.gnode, c.gdiag, m.row_ptr, m.diag_pos, m.lrow_ptr, mv, m.nnzl,
+                  vals, c.nnzb, dinv);
     }
   }
   if (want_g)
@@ -3320,7 +3415,7 @@ symx_status launch_contact_assemble(Mesh& m, const double* x, bool want_g, bool 
 symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b,
                               double* r) {
   const char* PNAME = "residual64";
-  const int G = grid_for(m.N * 16, 256, 16384);
+  const int G = grid_for(m.N * kSpmvLanes, 256, 16384);
   const Contacts* cs = m.contacts;
   const DynBsr<double> C64{cs ? cs->row_ptr : nullptr, cs ? cs->col_idx : nullptr,
                            cs ? cs->vals64 : nullptr, cs ? cs->nnzb : 0};
@@ -3328,18 +3423,18 @@ symx_status launch_residual64(Mesh& m, int precision, const double* x, const dou
                           cs ? cs->vals32 : nullptr, cs ? cs->nnzb : 0};
   if (precision == SYMX_F64) {
     if (cs)
-      SYMX_LAUNCH(m, PNAME, (k_residual64<double, true>), dim3(G), dim3(256), 0, m.N, m.row_ptr,
-                  m.col_idx, m.vals64, m.nnzb, x, b, r, C64);
+      SYMX_LAUNCH(m, PNAME, (k_residual64<double, true>), dim3(G), dim3(256), 0, m.N,
+                  half_bsr<double>(m), x, b, r, C64);
     else
-      SYMX_LAUNCH(m, PNAME, (k_residual64<double, false>), dim3(G), dim3(256), 0, m.N, m.row_ptr,
-                  m.col_idx, m.vals64, m.nnzb, x, b, r, C64);
+      SYMX_LAUNCH(m, PNAME, (k_residual64<double, false>), dim3(G), dim3(256), 0, m.N,
+                  half_bsr<double>(m), x, b, r, C64);
   } else {
     if (cs)
-      SYMX_LAUNCH(m, PNAME, (k_residual64<float, true>), dim3(G), dim3(256), 0, m.N, m.row_ptr,
-                  m.col_idx, m.vals32, m.nnzb, x, b, r, C32);
+      SYMX_LAUNCH(m, PNAME, (k_residual64<float, true>), dim3(G), dim3(256), 0, m.N,
+                  half_bsr<float>(m), x, b, r, C32);
     else
-      SYMX_LAUNCH(m, PNAME, (k_residual64<float, false>), dim3(G), dim3(256), 0, m.N, m.row_ptr,
-                  m.col_idx, m.vals32, m.nnzb, x, b, r, C32);
+      SYMX_LAUNCH(m, PNAME, (k_residual64<float, false>), dim3(G), dim3(256), 0, m.N,
+                  half_bsr<float>(m), x, b, r, C32);
   }
   LAUNCH_CHECK("k_residual64");
   return SYMX_OK;

@@ -216,8 +216,8 @@ void pinned_free(DevicePool* pool, void* p) {
 // ---------------------------------------------------------------------------
 
 Topology::~Topology() {
-  void* dev[] = {row_ptr, col_idx, diag_pos, inc_ptr, inc_code, inc_nodes, batch_row, blk_info,
-                 centry,  batch_entry};
+  void* dev[] = {row_ptr,  col_idx,   diag_pos, lrow_ptr, cv,         inc_ptr,
+                 inc_code, inc_nodes, batch_row, blk_info, centry, batch_entry};
   for (void* p : dev) dev_free(pool, p);
   for (TopoSet& s : sets) {
     dev_free(pool, s.d_conn);

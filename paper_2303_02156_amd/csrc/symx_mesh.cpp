@@ -548,10 +548,40 @@ static symx_status build_topology(const symx_mesh_desc& d, DevicePool* pool, hip
     const int32_t* b = t.h_col_idx.data() + t.h_row_ptr[i];
     diag[i] = t.h_row_ptr[i] + (int32_t)(std::lower_bound(b, b + row_len[i], (int32_t)i) - b);
   }
+  // The solver's half storage: row i keeps its blocks (i, j) with j <= i
+  // (the pattern is symmetric); an upper block (i, j), j > i, is read as the
+  // transpose of block (j, i).  cv[p] pairs each pattern slot's column with
+  // the half position it reads (bitwise complement for a transpose), so that
+  // one load per block gives the solver both.
+  std::vector<int32_t> lrow(N + 1, 0);
+  for (int64_t i = 0; i < N; ++i) lrow[i + 1] = lrow[i] + (diag[i] - t.h_row_ptr[i] + 1);
+  t.nnzl = lrow[N];
+  uvector<int2> cv(t.nnzb);
+  std::atomic<int> asym{0};
+  parallel_chunks(N, 4096, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      for (int32_t p = t.h_row_ptr[i]; p <= diag[i]; ++p)
+        cv[p] = make_int2(t.h_col_idx[p], lrow[i] + (p - t.h_row_ptr[i]));
+      for (int32_t p = diag[i] + 1; p < t.h_row_ptr[i + 1]; ++p) {
+        const int32_t j = t.h_col_idx[p];
+        const int32_t* b = t.h_col_idx.data() + t.h_row_ptr[j];
+        const int32_t* e = t.h_col_idx.data() + diag[j];
+        const int32_t* f = std::lower_bound(b, e, (int32_t)i);
+        if (f == e || *f != (int32_t)i) asym = 1;
+        cv[p] = make_int2(j, ~(lrow[j] + (int32_t)(f - b)));
+      }
+    }
+  });
+  if (asym) {
+    set_error("block pattern is not symmetric");
+    return SYMX_ERR_INVALID_ARG;
+  }
   size_t& nb = t.device_bytes;
   TRY(upload(pool, stream, &t.row_ptr, t.h_row_ptr.data(), N + 1, &nb));
   TRY(upload(pool, stream, &t.col_idx, t.h_col_idx.data(), t.nnzb, &nb));
   TRY(upload(pool, stream, &t.diag_pos, diag.data(), N, &nb));
+  TRY(upload(pool, stream, &t.lrow_ptr, lrow.data(), N + 1, &nb));
+  TRY(upload(pool, stream, &t.cv, cv.data(), cv.size(), &nb));
   TRY(upload(pool, stream, &t.inc_ptr, inc_ptr32.data(), N + 1, &nb));
   TRY(upload(pool, stream, &t.inc_code, code.data(), t.n_inc, &nb));
   if (t.ho) {
@@ -626,6 +656,9 @@ static void attach_topology(Mesh& m, std::shared_ptr<Topology> tp) {
   m.row_ptr = t.row_ptr;
   m.col_idx = t.col_idx;
   m.diag_pos = t.diag_pos;
+  m.nnzl = t.nnzl;
+  m.lrow_ptr = t.lrow_ptr;
+  m.cv = t.cv;
   m.inc_ptr = t.inc_ptr;
   m.inc_code = t.inc_code;
   m.inc_nodes = t.inc_nodes;

@@ -5,9 +5,12 @@
 // |g_free| <= rtol |g_free(x(t))|, solve H dx = -g with block-Jacobi PCG to the
 // forcing tolerance min(forcing_max, sqrt(r_k / r_0)) (forcing_max 0.5 by
 // default), backtrack along dx with the
-// Armijo test E(x + a dx) <= E(x) + 1e-4 a g.dx (a halves, at most 30 times),
-// and restart the whole step with dt/2 when the line search fails or Newton
-// exceeds its iteration limit (the paper's benchmark protocol, Sec. 7).
+// Armijo test E(x + a dx) <= E(x) + 1e-4 a g.dx + 1e-12 |E(x)| (a halves, at
+// most 30 times; the last term is the rounding of the float64 energy sum, so
+// that a step whose decrease the energy can no longer resolve, close to the
+// minimiser, is taken whole), and restart the whole step with dt/2 when the
+// line search fails or Newton exceeds its iteration limit (the paper's
+// benchmark protocol, Sec. 7).
 //
 // Precision modes: SYMX_F64 runs everything in float64.  SYMX_F32_REFINED
 // evaluates energies, gradient and Hessian in float64 and keeps a float32
@@ -56,7 +59,16 @@ bool step_params_valid(const symx_step_params& P) {
 }
 
 
-static symx_status ensure_values(Mesh& m, int precision) {
+// Value arrays of the Hessian in `precision`: the block arrays of the public
+// assembly, or (half) the half storage of the Newton solve.
+static symx_status ensure_values(Mesh& m, int precision, bool half) {
+  if (half) {
+    if (precision == SYMX_F64 && !m.lvals64)
+      return dev_alloc(m.pool, (void**)&m.lvals64, 9 * m.nnzl * sizeof(double));
+    if (precision != SYMX_F64 && !m.lvals32)
+      return dev_alloc(m.pool, (void**)&m.lvals32, 9 * m.nnzl * sizeof(float));
+    return SYMX_OK;
+  }
   if (precision == SYMX_F64 && !m.vals64) return dev_alloc(m.pool, (void**)&m.vals64, 9 * m.nnzb * sizeof(double));
   if (precision != SYMX_F64 && !m.vals32) return dev_alloc(m.pool, (void**)&m.vals32, 9 * m.nnzb * sizeof(float));
   return SYMX_OK;
@@ -148,9 +160,11 @@ static symx_status assemble_main(Mesh& m, const double* x, const double* xt, dou
                                  bool dirichlet, double* g_out, void* dinv, float* dinv_lo);
 
 // Assemble gradient (float64) and/or Hessian values (precision) at x.  With
-// dinv, the block-Jacobi inverses (N x 9, precision's type) are produced too;
-// with dinv_lo (float64 Hessian and dinv only), also the float32 copies of
-// the values (m.vals32) and of the inverses (dinv_lo).
+// dinv (the Newton solve), the block-Jacobi inverses (N x 9, precision's
+// type) are produced too and the Hessian goes to the solver's half storage
+// (m.lvals64 / m.lvals32); without, to the block arrays (m.vals64 /
+// m.vals32).  With dinv_lo (float64 Hessian and dinv only), also the float32
+// copies of the values (m.lvals32) and of the inverses (dinv_lo).
 symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool want_g, bool want_H,
                      int project, int precision, bool dirichlet, double* g_out,
                      void* dinv = nullptr, float* dinv_lo = nullptr) {
@@ -159,7 +173,7 @@ symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool
       set_error("float32 copies need a float64 Hessian with its inverses");
       return SYMX_ERR_INVALID_ARG;
     }
-    TRY(ensure_values(m, SYMX_F32));
+    TRY(ensure_values(m, SYMX_F32, true));
   }
   TRY(assemble_main(m, x, xt, dt, want_g, want_H, project, precision, dirichlet, g_out, dinv,
                     dinv_lo));
@@ -177,7 +191,8 @@ static symx_status assemble_main(Mesh& m, const double* x, const double* xt, dou
     set_error("per-element PSD projection is not available for quadratic or cubic tets");
     return SYMX_ERR_INVALID_ARG;
   }
-  if (want_H) TRY(ensure_values(m, precision));
+  const bool half = dinv != nullptr;
+  if (want_H) TRY(ensure_values(m, precision, half));
   if (project && want_H) {
     // filter mode on a Stable Neo-Hookean mesh: the row kernel evaluates the
     // filtered rows itself; otherwise element-wise records, then assembly
@@ -185,18 +200,18 @@ static symx_status assemble_main(Mesh& m, const double* x, const double* xt, dou
     for (const SetHost& s : m.sets) snh_only = snh_only && s.kind == SYMX_SNH_TET4;
     if (project == 2 && snh_only) {
       TRY(launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, nullptr, true,
-                              g_out, dinv, dinv_lo));
+                              g_out, dinv, dinv_lo, half));
     } else {
       TRY(project_into_records(m, x, precision, project));
       TRY(launch_row_assemble(m, x, xt, dt, want_g, true, precision, dirichlet, m.inc_rows, false,
-                              g_out, dinv, dinv_lo));
+                              g_out, dinv, dinv_lo, half));
     }
     // contact element Hessians take the nearest-PSD projection in both modes
     return launch_contact_assemble(m, x, want_g, true, true, precision, dirichlet, g_out, dinv);
   }
   if (!want_g && !want_H) return SYMX_OK;
   TRY(launch_row_assemble(m, x, xt, dt, want_g, want_H, precision, dirichlet, nullptr, false,
-                          g_out, want_H ? dinv : nullptr, want_H ? dinv_lo : nullptr));
+                          g_out, want_H ? dinv : nullptr, want_H ? dinv_lo : nullptr, half));
   return launch_contact_assemble(m, x, want_g, want_H, false, precision, dirichlet, g_out,
                                  want_H ? dinv : nullptr);
 }
@@ -306,6 +321,10 @@ static symx_status linear_solve(Mesh& m, const symx_step_params& P, const double
   return SYMX_OK;
 }
 
+// Relative rounding allowance of the line search's energy comparison (the
+// float64 sum of the element energies is exact to about 1e-14 relative).
+constexpr double kEnergyRound = 1e-12;
+
 using clk = std::chrono::steady_clock;
 static double ms_since(clk::time_point t0) {
   return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
@@ -387,7 +406,7 @@ static symx_status solve_step(Mesh& m, const symx_step_params& P, double dt, sym
     bool ok = false;
     double Et = at(D_ET);
     for (int ls = 0;; ++ls) {
-      if (!bad && Et <= E0 + 1e-4 * alpha * gd) {
+      if (!bad && Et <= E0 + 1e-4 * alpha * gd + kEnergyRound * std::fabs(E0)) {
         ok = true;
         break;
       }

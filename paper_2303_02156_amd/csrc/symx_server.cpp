@@ -79,14 +79,17 @@ size_t estimate_request_bytes(const symx_mesh_desc& d, int precision, bool proje
     if (k >= 10) conn += (size_t)d.energies[s].n_elem * k * k * 4;  // relabelled incidence nodes
     if (kind_has_rotation(d.energies[s].kind)) rot_elems += (size_t)d.energies[s].n_elem;
   }
-  const size_t vbytes = precision == SYMX_F64 ? 8 : 4;
+  // the solve's values (half storage; refined solves keep float64 and float32)
+  const size_t vbytes = precision == SYMX_F64 ? 8 : precision == SYMX_F32 ? 4 : 12;
+  const size_t half = (pairs + N) / 2;
   size_t b = 0;
-  b += pairs * (9 * vbytes + 4 + 4 + 2 * 3);   // values, col_idx, contribution info/entries
+  b += half * 9 * vbytes + (pairs / 2 + N) * 4;  // half values, transposed positions, rows
+  b += pairs * (4 + 4 + 2 * 3);                 // col_idx, contribution info/entries
   b += inc * 4 + conn + elems * (2 * 8 * kPrm + 4 * 4);  // incidence codes, conn, params
   b += rot_elems * 9 * (8 + 4);                // lagged rotations
   if (project) b += inc * (kIncRec * vbytes + 4);  // projected records, their positions
   b += N * (3 * 8 + 8 + 1 + 4 * 4);            // X, mass, fixed, row/inc pointers
-  b += N * 3 * 8 * 9 + N * 9 * 8;              // Newton workspace, Dinv
+  b += N * 3 * 8 * 9 + N * 9 * 8 * 2;          // Newton workspace, Dinv (and its float64 copy)
   b += N * 3 * 8 * 5;                          // PCG vectors (double worst case)
   b += (size_t)kMaxPartials * 8 + (1 << 16);   // reductions and slack
   return b;

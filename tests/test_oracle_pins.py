@@ -1128,3 +1128,32 @@ def test_dt_halving_control():
     st3.dt_cur = 0.0025
     _, _, rep = st3.step(s.x0, s.v0)
     assert rep["dt_used"] == 0.01 and st3.dt_cur == 0.0025 and st3.successes == 0
+
+
+def test_line_search_takes_full_steps_within_energy_rounding(monkeypatch):
+    # Newton's line search compares float64 energy sums, whose rounding grows
+    # with the number of elements (1e-14 relative and more); close to the
+    # minimiser the decrease of a full Newton step falls below it.  Planted
+    # here: every trial energy comes back 1e-13 relative too high, and the
+    # step is solved to 1e-8.  With the rounding allowance of the Armijo test
+    # it converges on full Newton steps to the same point as without the
+    # noise; with no allowance the line search fails on the same noise.
+    s = sg.tet_cube_scene(3, seed=4, perturb=0.05)
+    dt = s.dt
+    base = newton.StepParams(dt=dt, newton_rtol=1e-8)
+    ok0, x0, rep0 = newton.newton_solve(s, s.x0, s.v0, dt, base, solver="direct")
+    assert ok0 and rep0["ls_backtracks"] == 0
+    true_energy = newton.assembly.energy
+
+    def noisy(*a, **k):
+        e = true_energy(*a, **k)
+        return e + 1e-13 * abs(e)
+
+    monkeypatch.setattr(newton.assembly, "energy", noisy)
+    ok1, x1, rep1 = newton.newton_solve(s, s.x0, s.v0, dt, base, solver="direct")
+    assert ok1 and rep1["ls_backtracks"] == 0
+    assert rep1["newton_iters"] == rep0["newton_iters"]
+    assert np.max(np.abs(x1 - x0)) == 0.0
+    strict = newton.StepParams(dt=dt, newton_rtol=1e-8, energy_round=0.0)
+    ok2, _, rep2 = newton.newton_solve(s, s.x0, s.v0, dt, strict, solver="direct")
+    assert not ok2 and rep2["status"] == "line_search"
