@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <utility>
 
 #include "symx_generated.h"
 #include "symx_internal.h"
@@ -48,8 +49,17 @@ __device__ __forceinline__ int xcd_remap(int i, int n) {
 __device__ __forceinline__ float rot_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float rot_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float rot_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double rot_rcp(double x) { return 1.0 / x; }
-__device__ __forceinline__ double rot_rsq(double x) { return 1.0 / sqrt(x); }
+// float64: the hardware approximation refined by one Newton step (a few ulp;
+// the rotations only need c^2 + s^2 = 1 to rounding, not correctly rounded
+// parameters).
+__device__ __forceinline__ double rot_rcp(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rot_rsq(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
 __device__ __forceinline__ double rot_sqrt(double x) { return sqrt(x); }
 
 template <typename T>
@@ -805,44 +815,101 @@ struct LaneMat {
 // One Jacobi rotation zeroing a(p,q) (Golub & Van Loan, Alg. 8.4.1): the
 // smaller root t of t^2 + 2 tau t - 1 = 0 with tau = (a_qq - a_pp) / (2 a_pq),
 // written as t = sign(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp
-// (no division by a_pq, no overflow of tau^2); c = 1 / sqrt(1 + t^2), s = t c;
-// A <- J^T A J, V <- V J.
-template <typename T, int R, int P, int Q, typename VM>
-__device__ __forceinline__ void jacobi_rotate(T* a, VM v) {
+// (no division by a_pq, no overflow of tau^2); c = 1 / sqrt(1 + t^2), s = t c.
+template <typename T>
+struct JacobiRot {
+  T t, c, s, apq;
+};
+template <typename T, int R, int P, int Q>
+__device__ __forceinline__ JacobiRot<T> jacobi_params(const T* a) {
   const T apq = a[up_idx<R>(P, Q)];
   const T app = a[up_idx<R>(P, P)], aqq = a[up_idx<R>(Q, Q)];
   const T d = aqq - app;
-  const T den = fabs(d) + rot_sqrt(d * d + T(4) * apq * apq);
+  // float64 takes the root as disc rsq(disc): a zero discriminant gives NaN,
+  // which only arises for a_pq = 0, where t = 0 is taken
+  const T disc = d * d + T(4) * apq * apq;
+  const T den = fabs(d) + (sizeof(T) == 8 ? disc * rot_rsq(disc) : rot_sqrt(disc));
   const T num = d < T(0) ? T(-2) * apq : T(2) * apq;
   const T t = (apq != T(0) && den > T(0)) ? num * rot_rcp(den) : T(0);
   const T c = rot_rsq(T(1) + t * t);
-  const T sn = t * c;
-  a[up_idx<R>(P, P)] = app - t * apq;
-  a[up_idx<R>(Q, Q)] = aqq + t * apq;
+  return JacobiRot<T>{t, c, t * c, apq};
+}
+// A <- J^T A J, V <- V J for the rotation r of the (P, Q) plane.
+template <typename T, int R, int P, int Q, typename VM>
+__device__ __forceinline__ void jacobi_apply(T* a, VM v, const JacobiRot<T>& r) {
+  a[up_idx<R>(P, P)] -= r.t * r.apq;
+  a[up_idx<R>(Q, Q)] += r.t * r.apq;
   a[up_idx<R>(P, Q)] = T(0);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     if (k == P || k == Q) continue;
     const T akp = a[up_idx<R>(k, P)], akq = a[up_idx<R>(k, Q)];
-    a[up_idx<R>(k, P)] = c * akp - sn * akq;
-    a[up_idx<R>(k, Q)] = sn * akp + c * akq;
+    a[up_idx<R>(k, P)] = r.c * akp - r.s * akq;
+    a[up_idx<R>(k, Q)] = r.s * akp + r.c * akq;
   }
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const T vkp = v[k * R + P], vkq = v[k * R + Q];
-    v[k * R + P] = c * vkp - sn * vkq;
-    v[k * R + Q] = sn * vkp + c * vkq;
+    v[k * R + P] = r.c * vkp - r.s * vkq;
+    v[k * R + Q] = r.s * vkp + r.c * vkq;
   }
 }
 
+// Parallel (round-robin) order of the R(R-1)/2 planes: rounds of disjoint
+// planes.  R odd: round r holds the pairs i < j with i + j = r (mod R), one
+// index idle; R even: index R-1 meets r, the others pair as for R-1 with
+// i + j = 2r (mod R-1).  Every plane appears once per sweep.
+template <int R>
+struct JacobiRounds {
+  static constexpr int kRounds = R % 2 ? R : R - 1;
+  static constexpr int kPairs = R / 2;
+  int p[kRounds][kPairs], q[kRounds][kPairs];
+  constexpr JacobiRounds() : p(), q() {
+    const int m = R % 2 ? R : R - 1;
+    for (int r = 0; r < kRounds; ++r) {
+      int n = 0;
+      if (R % 2 == 0) {
+        p[r][n] = r;
+        q[r][n] = R - 1;
+        ++n;
+      }
+      const int target = R % 2 ? r : (2 * r) % m;
+      for (int i = 0; i < m; ++i)
+        for (int j = i + 1; j < m; ++j)
+          if ((i + j) % m == target) {
+            p[r][n] = i;
+            q[r][n] = j;
+            ++n;
+          }
+    }
+  }
+};
+
+// One round: the rotations of its disjoint planes are computed from the same
+// A (a rotation of one plane leaves the other planes' 2 x 2 blocks alone, so
+// their parameters are independent: instruction-level parallelism) and then
+// applied one after another (disjoint rotations commute).
+template <typename T, int R, int RI, typename VM, int... K>
+__device__ __forceinline__ void jacobi_round(T* a, VM v, std::integer_sequence<int, K...>) {
+  constexpr JacobiRounds<R> tab{};
+  const JacobiRot<T> rot[] = {jacobi_params<T, R, tab.p[RI][K], tab.q[RI][K]>(a)...};
+  (jacobi_apply<T, R, tab.p[RI][K], tab.q[RI][K]>(a, v, rot[K]), ...);
+}
+
+template <typename T, int R, typename VM, int... RI>
+__device__ __forceinline__ void jacobi_sweep(T* a, VM v, std::integer_sequence<int, RI...>) {
+  (jacobi_round<T, R, RI>(a, v, std::make_integer_sequence<int, JacobiRounds<R>::kPairs>{}), ...);
+}
+
+// Cyclic (row-order) sweep: one plane after another.
 template <typename T, int R, int P, int Q, typename VM>
-__device__ __forceinline__ void jacobi_sweep_from(T* a, VM v) {
+__device__ __forceinline__ void jacobi_sweep_cyclic(T* a, VM v) {
   if constexpr (P < R - 1) {
-    jacobi_rotate<T, R, P, Q>(a, v);
+    jacobi_apply<T, R, P, Q>(a, v, jacobi_params<T, R, P, Q>(a));
     if constexpr (Q + 1 < R)
-      jacobi_sweep_from<T, R, P, Q + 1>(a, v);
+      jacobi_sweep_cyclic<T, R, P, Q + 1>(a, v);
     else
-      jacobi_sweep_from<T, R, P + 1, P + 2>(a, v);
+      jacobi_sweep_cyclic<T, R, P + 1, P + 2>(a, v);
   }
 }
 
@@ -876,7 +943,7 @@ __device__ __forceinline__ void reduce_hessian(HF h, T* a) {
     }
 }
 
-// Cyclic Jacobi on the packed upper triangle a (R x R) with V accumulated;
+// Jacobi sweeps on the packed upper triangle a (R x R) with V accumulated;
 // stops when the off-diagonal norm is below tol times the matrix norm.
 // Returns whether an eigenvalue (diagonal of a) is negative.
 template <typename T, int R, typename VM>
@@ -892,7 +959,12 @@ __device__ __forceinline__ bool jacobi_eigen(T* a, VM v, int max_sweeps, T tol) 
       for (int j = i + 1; j < R; ++j) off += a[up_idx<R>(i, j)] * a[up_idx<R>(i, j)];
     }
     if (off <= tol * tol * (dia + T(2) * off)) break;
-    jacobi_sweep_from<T, R, 0, 1>(a, v);
+    // float64 (latency-bound at one wave per SIMD): the parallel order; float32
+    // (issue-bound) keeps the cyclic order and its lower register count
+    if constexpr (sizeof(T) == 8)
+      jacobi_sweep<T, R>(a, v, std::make_integer_sequence<int, JacobiRounds<R>::kRounds>{});
+    else
+      jacobi_sweep_cyclic<T, R, 0, 1>(a, v);
   }
   bool neg = false;
 #pragma unroll
@@ -1035,11 +1107,12 @@ __global__ __launch_bounds__(64) void k_elem_rows_projected64(SetDev S, const do
                                                               const double* X,
                                                               const int* inc_pos, double* rows,
                                                               int max_sweeps, double tol) {
-  if constexpr (KIND == SYMX_STVK_TRI3) {
-    elem_rows_projected<double, KIND, 1>(S, x, X, inc_pos, rows, max_sweeps, tol, nullptr);
-  } else {
+  if constexpr (KIND == SYMX_STVK_TET4) {
+    // the StVK Hessian's evaluation leaves too few registers: V in LDS
     __shared__ double vs[9 * 9 * 64];
     elem_rows_projected<double, KIND, 64>(S, x, X, inc_pos, rows, max_sweeps, tol, vs);
+  } else {
+    elem_rows_projected<double, KIND, 1>(S, x, X, inc_pos, rows, max_sweeps, tol, nullptr);
   }
 }
 
@@ -1061,14 +1134,16 @@ __global__ __launch_bounds__(256) void k_incidence_positions(int64_t n_inc,
 }
 
 // Single precision fits A and V in 256 registers: two waves per SIMD.  Double
-// precision needs more and runs one wave per SIMD.
+// precision keeps them in registers too (VGPRs and AGPRs, no scratch) and runs
+// one wave per SIMD; V in LDS (41 KiB per 64-lane workgroup) allows only
+// three waves per CU and measured slower on the assembly path.
 template <int K>
 __global__ __launch_bounds__(64, 2) void k_project_psd32(float* __restrict__ H, int64_t n,
                                                          int max_sweeps, float tol) {
   project_psd_lane<float, K, 1>(H, n, max_sweeps, tol, nullptr);
 }
-// Double precision: the 9 x 9 V of four-node elements lives in LDS (41 KiB per
-// 64-lane workgroup); registers alone would spill to scratch.
+// The element-major projection (per-element interface) updates H in memory
+// and would spill with V in registers: V in LDS for four-node elements.
 template <int K>
 __global__ __launch_bounds__(64) void k_project_psd64(double* __restrict__ H, int64_t n,
                                                       int max_sweeps, double tol) {
