@@ -550,22 +550,22 @@ __device__ void snh_filter(const SetDev& S, int64_t e, const double* __restrict_
   }
 }
 
-// Filtered Hessian block of nodes (a, b): vol U K_ab U^T.
+// Filtered Hessian block of nodes (a, b): vol U K_ab U^T, ca = c_a, cb = c_b.
 template <typename R>
-__device__ __forceinline__ void snh_filter_block(const SnhFilter<R>& f, int a, int b,
-                                                 R (&H)[3][3]) {
+__device__ __forceinline__ void snh_filter_block(const SnhFilter<R>& f, const R (&ca)[3],
+                                                 const R (&cb)[3], R (&H)[3][3]) {
   R K[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) K[i][j] = f.c[a][i] * f.Ap[i][j] * f.c[b][j];
+    for (int j = 0; j < 3; ++j) K[i][j] = ca[i] * f.Ap[i][j] * cb[j];
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     const int i = p == 2 ? 1 : 0, j = p == 0 ? 1 : 2;
-    K[i][i] += f.sp[p] * f.c[a][j] * f.c[b][j];
-    K[j][j] += f.sp[p] * f.c[a][i] * f.c[b][i];
-    K[i][j] += f.dp[p] * f.c[a][j] * f.c[b][i];
-    K[j][i] += f.dp[p] * f.c[a][i] * f.c[b][j];
+    K[i][i] += f.sp[p] * ca[j] * cb[j];
+    K[j][j] += f.sp[p] * ca[i] * cb[i];
+    K[i][j] += f.dp[p] * ca[j] * cb[i];
+    K[j][i] += f.dp[p] * ca[i] * cb[j];
   }
   R KU[3][3];  // K U^T
 #pragma unroll
@@ -600,7 +600,7 @@ __global__ __launch_bounds__(64) void k_elem_rows_filtered(SetDev S, const doubl
       for (int bp = 1; bp < 4; ++bp) {
         const int b = bp <= a ? bp - 1 : bp;
         T H[3][3];
-        snh_filter_block(f, a, b, H);
+        snh_filter_block(f, f.c[a], f.c[b], H);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -639,7 +639,7 @@ __global__ __launch_bounds__(64) void k_elem_filtered(SetDev S, const double* __
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           T H[3][3];
-          snh_filter_block(f, a, b, H);
+          snh_filter_block(f, f.c[a], f.c[b], H);
 #pragma unroll
           for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -1321,13 +1321,22 @@ __device__ __forceinline__ void incidence_row_filtered(const RowArgs<T>& A, uint
   const int a = inc_local(code);
   SnhFilter<T> f;
   snh_filter(A.sets.s[inc_set(code)], inc_elem(code), A.x, A.X, f);
+  // the lane's node first, then the others in ascending order: selected with
+  // constant indices (indexing f's arrays by a would place them in scratch)
+  T cr[4][3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) out[i] = T(f.g[a][i]);
+  for (int m = 0; m < 3; ++m) {
+    const T c0 = f.c[0][m], c1 = f.c[1][m], c2 = f.c[2][m], c3 = f.c[3][m];
+    cr[0][m] = a == 0 ? c0 : a == 1 ? c1 : a == 2 ? c2 : c3;
+    cr[1][m] = a == 0 ? c1 : c0;
+    cr[2][m] = a <= 1 ? c2 : c1;
+    cr[3][m] = a <= 2 ? c3 : c2;
+    out[m] = a == 0 ? f.g[0][m] : a == 1 ? f.g[1][m] : a == 2 ? f.g[2][m] : f.g[3][m];
+  }
 #pragma unroll
   for (int bp = 1; bp < 4; ++bp) {
-    const int b = bp <= a ? bp - 1 : bp;
     T H[3][3];
-    snh_filter_block(f, a, b, H);
+    snh_filter_block(f, cr[0], cr[bp], H);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -1398,8 +1407,12 @@ __device__ __forceinline__ void store_block(const RowArgs<T>& A, int row, int co
 template <typename T, bool WANT_G, int SRC, uint32_t KMASK>
 __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   constexpr int NV = 30;
-  __shared__ T st[9][kRowWG];  // one component row of the incidences' blocks; then the sums
-  __shared__ T sg[3][kRowWG];  // the incidences' gradient rows
+  // One component row of the incidences' blocks, then the sums; and the
+  // incidences' gradient rows.  Rows are padded by one value so that lanes
+  // reading several components of one incidence (or one slot) hit distinct
+  // LDS banks.
+  __shared__ T st[9][kRowWG + 1];
+  __shared__ T sg[3][kRowWG + 1];
   // batch-relative offsets (at most kRowWG) in 16 bits
   __shared__ uint16_t s_blk[kRowWG + 1];
   __shared__ uint16_t s_inc[kRowWG + 1];
@@ -1861,10 +1874,12 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
   using P = HoTet<K>;
   constexpr int NO = 3 * (K - 1);
   constexpr int NV = WANT_H ? 3 + 3 * NO : 3;
-  __shared__ T st[NV][P::kCap];
-  __shared__ T st2[P::kAcc == 2 ? NV : 1][P::kAcc == 2 ? P::kCap : 1];  // odd points
+  // rows padded by one value: lanes reading several components of one
+  // incidence (or one slot) hit distinct LDS banks
+  __shared__ T st[NV][P::kCap + 1];
+  __shared__ T st2[P::kAcc == 2 ? NV : 1][P::kAcc == 2 ? P::kCap + 1 : 1];  // odd points
   __shared__ union {
-    T blk[WANT_H ? 9 : 1][kRowWG];
+    T blk[WANT_H ? 9 : 1][kRowWG + 1];
     HoStage<K> stg;
   } sh;
   auto& blk = sh.blk;
@@ -1926,7 +1941,7 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
     // stores, the others add in chunks of 64 values (their LDS reads in
     // flight together, then the adds and stores).
     const int k_lo = (i0 / nq) / P::kAcc, k_hi = ((min(n_items, i0 + kRowWG) - 1) / nq) / P::kAcc;
-    T(*acc_st)[P::kCap] = st;
+    T(*acc_st)[P::kCap + 1] = st;
     if constexpr (P::kAcc == 2) acc_st = (p & 1) ? st2 : st;
     for (int k = k_lo; k <= k_hi; ++k) {
       if (act && p / P::kAcc == k) {
