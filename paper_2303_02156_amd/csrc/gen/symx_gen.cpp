@@ -303,6 +303,10 @@ struct ThroughFSpec {
   std::function<S(const Mat& F, const std::vector<S>& in)> psi;
   std::vector<int> row_nodes;  // nodes with row functions (one per node class)
   bool full;                   // also the full element E, g, H
+  // also each row in parts: part k holds (gradient, for k = 0, and) the
+  // off-diagonal blocks of the other nodes j in [part_lo[k], part_lo[k+1])
+  // of the row's order, so that a kernel never holds the whole row
+  std::vector<int> part_lo = {};
 };
 
 // Linear tet: inputs x (0..11), X (12..23).
@@ -403,8 +407,9 @@ struct ThroughF {
                     S(&g, P[3 * i + 2]) * G[a][2]);
   }
   // Hessian row of node a: for i = 0..2 the blocks (a, b), b in order (the
-  // diagonal block left out unless with_diag)
-  std::vector<int> row_blocks(int a, bool with_diag) {
+  // diagonal block left out unless with_diag); only the blocks whose
+  // position j in that order is in [j_lo, j_hi)
+  std::vector<int> row_blocks(int a, bool with_diag, int j_lo = 0, int j_hi = 1 << 30) {
     const auto& G = kin.G;
     const int K = (int)G.size();
     std::vector<std::vector<int>> dP(3);
@@ -415,11 +420,14 @@ struct ThroughF {
     }
     std::vector<int> ids;
     for (int i = 0; i < 3; ++i)
-      for (int b = 0; b < K; ++b) {
+      for (int b = 0, j = 0; b < K; ++b) {
         if (b == a && !with_diag) continue;
-        for (int m = 0; m < 3; ++m)
-          ids.push_back((S(&g, dP[i][3 * m]) * G[b][0] + S(&g, dP[i][3 * m + 1]) * G[b][1] +
-                         S(&g, dP[i][3 * m + 2]) * G[b][2]).id);
+        if (j >= j_lo && j < j_hi) {
+          for (int m = 0; m < 3; ++m)
+            ids.push_back((S(&g, dP[i][3 * m]) * G[b][0] + S(&g, dP[i][3 * m + 1]) * G[b][1] +
+                           S(&g, dP[i][3 * m + 2]) * G[b][2]).id);
+        }
+        ++j;
       }
     return ids;
   }
@@ -569,6 +577,12 @@ void generate_through_F(const ThroughFSpec& spec, Generated& out) {
     const std::vector<int> blocks = row_blocks(r, false);
     row_gHoff.insert(row_gHoff.end(), blocks.begin(), blocks.end());
     add_fn(R + "_gHoff", g.substitute(row_gHoff, zero));
+    for (size_t k = 0; k + 1 < spec.part_lo.size(); ++k) {
+      std::vector<int> part = k == 0 ? row_g : std::vector<int>();
+      const std::vector<int> pb = tf.row_blocks(r, false, spec.part_lo[k], spec.part_lo[k + 1]);
+      part.insert(part.end(), pb.begin(), pb.end());
+      add_fn(R + "_gHoff_p" + std::to_string(k), g.substitute(part, zero));
+    }
   }
   emit_all(g, fns, out);
 }
@@ -616,7 +630,7 @@ int main(int argc, char** argv) {
   };
   auto high_order = [](const std::string& name, int K,
                        std::function<std::vector<S>(const std::vector<S>&)> shape,
-                       std::vector<int> rows, bool full) {
+                       std::vector<int> rows, bool full, std::vector<int> part_lo = {}) {
     return ThroughFSpec{name,
                         K,
                         6 * K + 6,
@@ -628,12 +642,14 @@ int main(int argc, char** argv) {
                           return snh_density(F, in[6 * K], in[6 * K + 1]);
                         },
                         std::move(rows),
-                        full};
+                        full,
+                        std::move(part_lo)};
   };
   const std::vector<ThroughFSpec> through_F = {
       tet4("stvk_tet4", 26, stvk_density),
       high_order("snh_tet10", 10, tet10_shape, {0, 4}, true),
-      high_order("snh_tet20", 20, tet20_shape, {0, 4, 19}, false),
+      // the cubic rows also in three parts (7, 6 and 6 of the 19 other nodes)
+      high_order("snh_tet20", 20, tet20_shape, {0, 4, 19}, false, {0, 7, 13, 19}),
   };
   Generated all;
   all.hip =

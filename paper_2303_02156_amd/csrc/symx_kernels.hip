@@ -1651,6 +1651,12 @@ struct HoTet<10> {
       else snh_tet10_row4_g<T>(in, out);
     }
   }
+  // the row in one part
+  template <typename T>
+  static constexpr int parts() { return 1; }
+  static constexpr int part_lo(int k) { return k == 0 ? 0 : 9; }
+  template <typename T, int PART>
+  __device__ static void row_part(int a, const T* in, T* out) { row<T, true>(a, in, out); }
 };
 template <>
 struct HoTet<20> {
@@ -1669,6 +1675,30 @@ struct HoTet<20> {
       if (a < 4) snh_tet20_row0_g<T>(in, out);
       else if (a < 16) snh_tet20_row4_g<T>(in, out);
       else snh_tet20_row19_g<T>(in, out);
+    }
+  }
+  // float64: the row in three parts (gradient and the blocks of the other
+  // nodes 0-6; 7-12; 13-18), each generated on its own, so that no lane
+  // holds the 174 values of a whole row (which spilled 740 B per lane to
+  // scratch: 2.40 -> 2.13 ms on the cubic box).  Float32 keeps the whole row
+  // (the parts repeat the row's common part three times: 0.86 -> 1.12 ms).
+  template <typename T>
+  static constexpr int parts() { return sizeof(T) == 8 ? 3 : 1; }
+  static constexpr int part_lo(int k) { return k == 0 ? 0 : k == 1 ? 7 : k == 2 ? 13 : 19; }
+  template <typename T, int PART>
+  __device__ static void row_part(int a, const T* in, T* out) {
+    if constexpr (PART == 0) {
+      if (a < 4) snh_tet20_row0_gHoff_p0<T>(in, out);
+      else if (a < 16) snh_tet20_row4_gHoff_p0<T>(in, out);
+      else snh_tet20_row19_gHoff_p0<T>(in, out);
+    } else if constexpr (PART == 1) {
+      if (a < 4) snh_tet20_row0_gHoff_p1<T>(in, out);
+      else if (a < 16) snh_tet20_row4_gHoff_p1<T>(in, out);
+      else snh_tet20_row19_gHoff_p1<T>(in, out);
+    } else {
+      if (a < 4) snh_tet20_row0_gHoff_p2<T>(in, out);
+      else if (a < 16) snh_tet20_row4_gHoff_p2<T>(in, out);
+      else snh_tet20_row19_gHoff_p2<T>(in, out);
     }
   }
 };
@@ -1775,6 +1805,17 @@ __device__ __forceinline__ void ho_row_point(const SetDev& S, int64_t e, const i
   fill_ho_ids<K, T>(S, e, ids, x, X, in);
   set_point<K, T>(r, q, in);
   HoTet<K>::template row<T, WANT_H>(a, in, out);
+}
+
+// Part PART of the Hessian row (as HoTet<K>::row_part).
+template <int K, typename T, int PART>
+__device__ __forceinline__ void ho_row_point_part(const SetDev& S, int64_t e, const int* ids,
+                                                  int a, const QuadRule& r, int q,
+                                                  const double* x, const double* X, T* out) {
+  T in[6 * K + 6];
+  fill_ho_ids<K, T>(S, e, ids, x, X, in);
+  set_point<K, T>(r, q, in);
+  HoTet<K>::template row_part<T, PART>(a, in, out);
 }
 
 // Per-element E, gradient (n x 3K) and Hessian (n x 3K x 3K, row-major) of a
@@ -1923,48 +1964,70 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
   __syncthreads();
   uint8_t fixed_rc = 0;  // Dirichlet flags of the block's row and column
   if (WANT_H && t < np && A.fixed) fixed_rc = A.fixed[r0 + r] | A.fixed[col];
-  // step 1: evaluation passes
+  // step 1: evaluation passes (with the Hessian, once per part of the row:
+  // part k accumulates its values v = part_v(k, u) only)
   const int n_items = nq * P::kPts;
-  for (int i0 = 0; i0 < n_items; i0 += kRowWG) {
-    const int item = i0 + t;
-    const bool act = item < n_items;
-    const int p = act ? item / nq : 0;
-    const int qi = act ? item - p * nq : 0;
-    T out[NV];
-    if (act) {
-      const uint32_t code = sh.stg.code[qi];
-      ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), sh.stg.ids[qi],
-                                 inc_local(code), sh.stg.rule, p, A.x, A.X, out);
-    }
-    // With two accumulators, even points accumulate in st and odd points in
-    // st2, a pair of points per round.  Round k is uniform: the first round
-    // stores, the others add in chunks of 64 values (their LDS reads in
-    // flight together, then the adds and stores).
-    const int k_lo = (i0 / nq) / P::kAcc, k_hi = ((min(n_items, i0 + kRowWG) - 1) / nq) / P::kAcc;
-    T(*acc_st)[P::kCap + 1] = st;
-    if constexpr (P::kAcc == 2) acc_st = (p & 1) ? st2 : st;
-    for (int k = k_lo; k <= k_hi; ++k) {
-      if (act && p / P::kAcc == k) {
-        if (k == 0) {
+  auto eval_part = [&](auto part_c) {
+    constexpr int PART = decltype(part_c)::value;
+    constexpr int NP = WANT_H ? P::template parts<T>() : 1;
+    constexpr int J0 = WANT_H ? P::part_lo(PART) : 0, J1 = WANT_H ? P::part_lo(PART + 1) : 0;
+    constexpr int NG = PART == 0 ? 3 : 0;                   // gradient values in this part
+    constexpr int NVP = NP == 1 ? NV : NG + 9 * (J1 - J0);  // values of this part
+    // value u of the part -> its row entry v (NP == 1: the identity)
+    auto part_v = [](int u) {
+      if (NP == 1 || u < NG) return u;
+      const int w = u - NG, per_i = 3 * (J1 - J0);
+      const int i = w / per_i, jm = w - i * per_i;
+      return 3 + NO * i + 3 * J0 + jm;
+    };
+    for (int i0 = 0; i0 < n_items; i0 += kRowWG) {
+      const int item = i0 + t;
+      const bool act = item < n_items;
+      const int p = act ? item / nq : 0;
+      const int qi = act ? item - p * nq : 0;
+      T out[NVP];
+      if (act) {
+        const uint32_t code = sh.stg.code[qi];
+        if constexpr (NP == 1)
+          ho_row_point<K, T, WANT_H>(A.sets.s[inc_set(code)], inc_elem(code), sh.stg.ids[qi],
+                                     inc_local(code), sh.stg.rule, p, A.x, A.X, out);
+        else
+          ho_row_point_part<K, T, PART>(A.sets.s[inc_set(code)], inc_elem(code), sh.stg.ids[qi],
+                                        inc_local(code), sh.stg.rule, p, A.x, A.X, out);
+      }
+      // With two accumulators, even points accumulate in st and odd points in
+      // st2, a pair of points per round.  Round k is uniform: the first round
+      // stores, the others add in chunks of 64 values (their LDS reads in
+      // flight together, then the adds and stores).
+      const int k_lo = (i0 / nq) / P::kAcc, k_hi = ((min(n_items, i0 + kRowWG) - 1) / nq) / P::kAcc;
+      T(*acc_st)[P::kCap + 1] = st;
+      if constexpr (P::kAcc == 2) acc_st = (p & 1) ? st2 : st;
+      for (int k = k_lo; k <= k_hi; ++k) {
+        if (act && p / P::kAcc == k) {
+          if (k == 0) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) acc_st[v][qi] = out[v];
-        } else {
-          constexpr int C = 64;
+            for (int u = 0; u < NVP; ++u) acc_st[part_v(u)][qi] = out[u];
+          } else {
+            constexpr int C = 64;
 #pragma unroll
-          for (int v0 = 0; v0 < NV; v0 += C) {
-            T cur[C];
+            for (int u0 = 0; u0 < NVP; u0 += C) {
+              T cur[C];
 #pragma unroll
-            for (int u = 0; u < C; ++u)
-              if (v0 + u < NV) cur[u] = acc_st[v0 + u][qi];
+              for (int u = 0; u < C; ++u)
+                if (u0 + u < NVP) cur[u] = acc_st[part_v(u0 + u)][qi];
 #pragma unroll
-            for (int u = 0; u < C; ++u)
-              if (v0 + u < NV) acc_st[v0 + u][qi] = cur[u] + out[v0 + u];
+              for (int u = 0; u < C; ++u)
+                if (u0 + u < NVP) acc_st[part_v(u0 + u)][qi] = cur[u] + out[u0 + u];
+            }
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
-  }
+  };
+  eval_part(std::integral_constant<int, 0>{});
+  if constexpr (WANT_H && P::template parts<T>() > 1) eval_part(std::integral_constant<int, 1>{});
+  if constexpr (WANT_H && P::template parts<T>() > 2) eval_part(std::integral_constant<int, 2>{});
   if constexpr (P::kAcc == 2) {
     // sum of the even and the odd points
     for (int j = t; j < NV * nq; j += kRowWG) {

@@ -437,3 +437,16 @@ def test_tet20_generated_vs_oracle(lib):
         others = [perm[b] for b in range(20) if b != r]
         assert _rel(row[:, :3], g[:, a]) < 1e-10
         assert _rel(row[:, 3:].reshape(n, 3, 19, 3), H[:, a][:, :, others, :]) < 1e-10
+        # the row in three parts (gradient and the blocks of the other nodes
+        # 0-6; 7-12; 13-18), point by point, against the whole row
+        for w, xi in elements.TET20_RULE[:2]:
+            inp = inputs(xs, Xs, w, xi)
+            whole = _call(lib, f"snh_tet20_row{r}_gHoff", inp, 174)
+            blocks = whole[:, 3:].reshape(n, 3, 19, 3)
+            parts = [_call(lib, f"snh_tet20_row{r}_gHoff_p{k}", inp, n_out)
+                     for k, n_out in enumerate((66, 54, 54))]
+            assert _rel(parts[0][:, :3], whole[:, :3]) < 1e-12
+            lo = (0, 7, 13, 19)
+            for k in range(3):
+                pb = parts[k][:, 3 if k == 0 else 0:].reshape(n, 3, lo[k + 1] - lo[k], 3)
+                assert _rel(pb, blocks[:, :, lo[k]:lo[k + 1], :]) < 1e-12
