@@ -208,8 +208,10 @@ def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
     return out
 
 
-def trajectory(symx, torch, scene, precision, steps, dt):
-    """Run `steps` implicit-Euler steps; returns (x, v, reports, ms per step)."""
+def trajectory(symx, torch, scene, precision, steps, dt, profile_steps=0):
+    """Run `steps` implicit-Euler steps; returns (x, v, reports, ms per step),
+    and with profile_steps > 0 also {kernel: (launches, device ms)} of that
+    many more steps run with per-launch events (after the timed ones)."""
     mesh = symx.Mesh(scene)
     x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
     v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
@@ -225,6 +227,15 @@ def trajectory(symx, torch, scene, precision, steps, dt):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     out = (x.cpu().numpy(), v.cpu().numpy(), reps, ms)
+    if profile_steps:
+        mesh.profile(True)
+        preps = []
+        for k in range(profile_steps):
+            st, rep = mesh.newton_step(x.clone(), v.clone(), prm)
+            preps.append(rep.as_dict())
+        kt = mesh.kernel_times()
+        mesh.profile(False)
+        out = out + ((kt, preps),)
     mesh.close()
     return out
 
@@ -395,17 +406,34 @@ def mixed_c3(symx, torch, steps=20):
     asm_ms = statistics.median(ms)
     mesh.close()
     n_elem = scene.n_elements()
-    _, _, reps, ms_step = trajectory(symx, torch, scene, symx.SYMX_F32_REFINED, steps, dt)
+    _, _, reps, ms_step, (kt, preps) = trajectory(symx, torch, scene, symx.SYMX_F32_REFINED,
+                                                  steps, dt, profile_steps=2)
+    # where a step's device time goes (2 more steps with per-launch events):
+    # the solve (SpMV, update, refinement residual) against the assembly,
+    # energies and the rest
+    solve = ("pcg_spmv", "pcg_update", "pcg_init", "residual64", "accumulate")
+    assembly_k = ("row_assemble_gH", "row_assemble_H", "row_assemble_g", "round_values")
+    tot = sum(t for _, t in kt.values())
+    t_solve = sum(kt[k][1] for k in solve if k in kt)
+    t_asm = sum(kt[k][1] for k in assembly_k if k in kt)
+    newton = sum(r["newton_iters"] for r in reps)
+    pcg = sum(r["pcg_iters"] for r in reps)
     return {"workload": "C3: 512^2 cloth (524,288 StVK triangles, 785,408 hinges, pinned edge) "
                         "+ 32^3-cube SNH block (196,608 tets), dt 1/60",
             "elements": n_elem, "nnzb": int(info.nnzb),
             "assembly_ms_f32": round(asm_ms, 4),
             "melem_per_s_f32": round(n_elem / (asm_ms * 1e-3) / 1e6, 2),
             "steps": steps, "ms_per_step_f32_refined": round(ms_step, 3),
-            "newton_iters": sum(r["newton_iters"] for r in reps),
-            "pcg_iters": sum(r["pcg_iters"] for r in reps),
+            "newton_iters": newton, "pcg_iters": pcg,
+            "pcg_iters_per_solve": round(pcg / max(newton, 1), 1),
+            "pcg_cap": 500,
             "all_converged": all(r["status"] == 0 for r in reps),
-            "dt_halvings": sum(r["dt_halvings"] for r in reps)}
+            "dt_halvings": sum(r["dt_halvings"] for r in reps),
+            "device_ms_split_2_steps": {
+                "solve": round(t_solve, 2), "assembly": round(t_asm, 2),
+                "other": round(tot - t_solve - t_asm, 2),
+                "newton_iters": sum(r["newton_iters"] for r in preps),
+                "pcg_iters": sum(r["pcg_iters"] for r in preps)}}
 
 
 # Evaluation + assembly per Newton iteration on the material-comparison box
