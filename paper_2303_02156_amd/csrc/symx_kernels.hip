@@ -1385,11 +1385,11 @@ __device__ __forceinline__ void store_block(const RowArgs<T>& A, int row, int co
 // translations).
 //  1. one lane per incidence evaluates the gradient and the off-diagonal
 //     blocks of its Hessian row (in registers; the gradient to LDS);
-//  2. in three rounds, one per component row i of the blocks: the incidence
-//     lanes put row i of their off-diagonal blocks in LDS, and one lane per
-//     off-diagonal block sums its precomputed contribution list in incidence
-//     order (the rounds keep a third of the values in LDS at a time, which
-//     lets more waves share a CU);
+//  2. in two rounds (component rows 0 and 1 of the blocks, then row 2): the
+//     incidence lanes put those rows of their off-diagonal blocks in LDS, and
+//     one lane per off-diagonal block sums its precomputed contribution list
+//     in incidence order (the rounds keep at most two thirds of the values in
+//     LDS at a time, which lets more waves share a CU);
 //  3. the summed off-diagonal blocks are published to LDS;
 //  4. one lane per (row, component): the elastic diagonal block is minus the
 //     sum of the row's off-diagonal blocks (slot order), plus inertia; and
@@ -1411,11 +1411,12 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
   // incidences' gradient rows.  Rows are padded by one value so that lanes
   // reading several components of one incidence (or one slot) hit distinct
   // LDS banks.
-  __shared__ T st[9][kRowWG + 1];
+  __shared__ T st[18][kRowWG + 1];
   __shared__ T sg[3][kRowWG + 1];
   // batch-relative offsets (at most kRowWG) in 16 bits
   __shared__ uint16_t s_blk[kRowWG + 1];
   __shared__ uint16_t s_inc[kRowWG + 1];
+  __shared__ uint16_t s_dslot[kRowWG];  // each row's diagonal block slot in the batch
   const int t = threadIdx.x;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int r0 = A.batch_row[b], r1 = A.batch_row[b + 1];
@@ -1461,12 +1462,39 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) w0[k] = k < cnt ? uint32_t(ce[k]) : 0u;
   }
-  // phase 2, one component row of the blocks per round
+  // The loads of phases 4 and 5 (masses, positions, x_tilde and Dirichlet
+  // flags for the lane's first phase-4 item; the Dirichlet flags of the
+  // lane's block) are issued now, so that they arrive during phase 2 instead
+  // of after the barriers that precede their use.
+  const int n4 = (WANT_G ? 12 : 9) * nrows;
+  double pf_m = 0.0, pf_x = 0.0, pf_xt = 0.0;
+  bool pf_fixed = false;
+  if (t < n4) {
+    if (t < 9 * nrows) {
+      const int rr = t / 9, c = t - 9 * rr;
+      if (A.xt && (c % 4) == 0) pf_m = A.mass[r0 + rr];
+    } else {
+      const int jj = t - 9 * nrows;
+      const int rr = jj / 3, c = jj - 3 * rr;
+      const int row = r0 + rr;
+      if (A.xt) {
+        pf_m = A.mass[row];
+        pf_x = A.x[3 * row + c];
+        pf_xt = A.xt[3 * row + c];
+      }
+      pf_fixed = A.fixed && A.fixed[row];
+    }
+  }
+  const bool blk_fixed = t < np && A.fixed && (A.fixed[r0 + r] | A.fixed[col]);
+  // phase 2 in two rounds: component rows i = 0, 1 of the blocks, then i = 2
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int round = 0; round < 2; ++round) {
+    const int i0 = round == 0 ? 0 : 2, i1 = round == 0 ? 2 : 3;
     if (t < nq) {
 #pragma unroll
-      for (int v = 0; v < 9; ++v) st[v][t] = out[3 + 9 * i + v];
+      for (int i = i0; i < i1; ++i)
+#pragma unroll
+        for (int v = 0; v < 9; ++v) st[9 * (i - i0) + v][t] = out[3 + 9 * i + v];
     }
     __syncthreads();
     if (t < np) {
@@ -1483,24 +1511,29 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
             const int q = int(w[k] >> 2);
             const int bb = int(w[k] & 3u) - 1;
 #pragma unroll
-            for (int kk = 0; kk < 3; ++kk) acc[3 * i + kk] += st[3 * bb + kk][q];
+            for (int i = i0; i < i1; ++i)
+#pragma unroll
+              for (int kk = 0; kk < 3; ++kk)
+                acc[3 * i + kk] += st[9 * (i - i0) + 3 * bb + kk][q];
           }
         }
       }
     }
     __syncthreads();
   }
-  // phase 3: publish the off-diagonal blocks
+  // phase 3: publish the off-diagonal blocks (and each row's diagonal slot)
   if (t < np) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) st[c][t] = acc[c];
+    if (diag) s_dslot[r] = (uint16_t)t;
   }
   __syncthreads();
   // phase 4: one lane per (row, component) of the elastic diagonal blocks
   // (minus the sum of the row's off-diagonal blocks, in slot order; the
   // diagonal slot still holds zero) and per (row, component) of the
   // gradient (incidences in order, float64)
-  for (int j = t; j < (WANT_G ? 12 : 9) * nrows; j += kRowWG) {
+  for (int j = t; j < n4; j += kRowWG) {
+    const bool first = j == t;  // the item whose loads were issued before phase 2
     if (j < 9 * nrows) {
       const int rr = j / 9, c = j - 9 * rr;
       // LDS reads in groups of eight, added in slot order
@@ -1515,8 +1548,8 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
           if (sl + k < sl1) sum += v[k];
       }
       T dv = -sum;
-      if (A.xt && (c % 4) == 0) dv += T(A.mass[r0 + rr] * A.inv_dt2);
-      st[c][A.diag_pos[r0 + rr] - p0] = dv;
+      if (A.xt && (c % 4) == 0) dv += T((first ? pf_m : A.mass[r0 + rr]) * A.inv_dt2);
+      st[c][s_dslot[rr]] = dv;
     } else {
       const int jj = j - 9 * nrows;
       const int rr = jj / 3, c = jj - 3 * rr;
@@ -1531,8 +1564,13 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
         for (int k = 0; k < 8; ++k)
           if (q + k < q1) g += double(v[k]);
       }
-      if (A.xt) g += A.mass[row] * A.inv_dt2 * (A.x[3 * row + c] - A.xt[3 * row + c]);
-      if (A.fixed && A.fixed[row]) g = 0.0;
+      if (A.xt) {
+        if (first)
+          g += pf_m * A.inv_dt2 * (pf_x - pf_xt);
+        else
+          g += A.mass[row] * A.inv_dt2 * (A.x[3 * row + c] - A.xt[3 * row + c]);
+      }
+      if (first ? pf_fixed : (A.fixed && A.fixed[row])) g = 0.0;
       if (!isfinite(g)) *A.nonfinite = 1;
       A.g[3 * row + c] = g;
     }
@@ -1545,7 +1583,7 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] = st[c][t];
     }
-    if (A.fixed && (A.fixed[row] | A.fixed[col])) {
+    if (blk_fixed) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] = (diag && (c % 4) == 0) ? T(1) : T(0);
     }
