@@ -1385,11 +1385,11 @@ __device__ __forceinline__ void store_block(const RowArgs<T>& A, int row, int co
 // translations).
 //  1. one lane per incidence evaluates the gradient and the off-diagonal
 //     blocks of its Hessian row (in registers; the gradient to LDS);
-//  2. in two rounds (component rows 0 and 1 of the blocks, then row 2): the
-//     incidence lanes put those rows of their off-diagonal blocks in LDS, and
-//     one lane per off-diagonal block sums its precomputed contribution list
-//     in incidence order (the rounds keep at most two thirds of the values in
-//     LDS at a time, which lets more waves share a CU);
+//  2. in rounds of one or two component rows of the blocks: the incidence
+//     lanes put those rows of their off-diagonal blocks in LDS, and one lane
+//     per off-diagonal block sums its precomputed contribution list in
+//     incidence order (the rounds keep a part of the values in LDS at a time,
+//     which lets more waves share a CU);
 //  3. the summed off-diagonal blocks are published to LDS;
 //  4. one lane per (row, component): the elastic diagonal block is minus the
 //     sum of the row's off-diagonal blocks (slot order), plus inertia; and
@@ -1404,14 +1404,23 @@ __device__ __forceinline__ void store_block(const RowArgs<T>& A, int row, int co
 // filtered Stable Neo-Hookean row (all sets of that kind).
 // KMASK: the element kinds compiled in (kKindsSnh for the common single-
 // material mesh keeps the kernel small).
+// Occupancy: the float32 kernels are held to six waves per SIMD (at most 80
+// VGPRs; a few values of the Stable Neo-Hookean row spill, which costs less
+// than the wave lost at 83); the float64 ones are bound to three by LDS.
 template <typename T, bool WANT_G, int SRC, uint32_t KMASK>
-__global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
+__global__ __launch_bounds__(kRowWG, sizeof(T) == 8 ? 3 : 6) void k_row_assemble_fast(RowArgs<T> A) {
   constexpr int NV = 30;
-  // One component row of the incidences' blocks, then the sums; and the
+  // Phase 2 stages two component rows of the blocks per round (two rounds)
+  // where registers already hold occupancy down to what the larger LDS array
+  // allows, and one row per round (three rounds) when the rows come from the
+  // records, whose kernel needs far fewer registers.
+  constexpr int ROWS = SRC == kRowRecords ? 1 : 2;
+  constexpr int ROUNDS = ROWS == 1 ? 3 : 2;
+  // Component rows of the incidences' blocks, then the sums; and the
   // incidences' gradient rows.  Rows are padded by one value so that lanes
   // reading several components of one incidence (or one slot) hit distinct
   // LDS banks.
-  __shared__ T st[18][kRowWG + 1];
+  __shared__ T st[9 * ROWS][kRowWG + 1];
   __shared__ T sg[3][kRowWG + 1];
   // batch-relative offsets (at most kRowWG) in 16 bits
   __shared__ uint16_t s_blk[kRowWG + 1];
@@ -1486,10 +1495,10 @@ __global__ __launch_bounds__(kRowWG) void k_row_assemble_fast(RowArgs<T> A) {
     }
   }
   const bool blk_fixed = t < np && A.fixed && (A.fixed[r0 + r] | A.fixed[col]);
-  // phase 2 in two rounds: component rows i = 0, 1 of the blocks, then i = 2
+  // phase 2: component rows [i0, i1) of the blocks per round
 #pragma unroll
-  for (int round = 0; round < 2; ++round) {
-    const int i0 = round == 0 ? 0 : 2, i1 = round == 0 ? 2 : 3;
+  for (int round = 0; round < ROUNDS; ++round) {
+    const int i0 = ROWS * round, i1 = i0 + ROWS < 3 ? i0 + ROWS : 3;
     if (t < nq) {
 #pragma unroll
       for (int i = i0; i < i1; ++i)
