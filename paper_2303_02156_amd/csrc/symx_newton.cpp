@@ -114,9 +114,10 @@ static symx_status sync_read(Mesh& m, const double* dev, int n, double* host) {
 
 static symx_status check_nonfinite(Mesh& m) {
   int flag = 0;
-  TRY(hip_check(hipMemcpyAsync(&flag, m.nonfinite, sizeof(int), hipMemcpyDeviceToHost, m.stream),
+  TRY(hip_check(hipMemcpyAsync(m.pinned, m.nonfinite, sizeof(int), hipMemcpyDeviceToHost, m.stream),
                 "hipMemcpyAsync"));
   TRY(hip_check(hipStreamSynchronize(m.stream), "hipStreamSynchronize"));
+  std::memcpy(&flag, m.pinned, sizeof(int));
   if (flag) {
     TRY(hip_check(hipMemsetAsync(m.nonfinite, 0, sizeof(int), m.stream), "hipMemsetAsync"));
     set_error("non-finite value in positions, energy or gradient");
@@ -218,8 +219,15 @@ static symx_status assemble_main(Mesh& m, const double* x, const double* xt, dou
 
 symx_status energy(Mesh& m, const double* x, const double* xt, double dt, int precision, double* E) {
   TRY(launch_energy(m, x, xt, dt, precision, m.scalars + D_ENERGY));
-  TRY(sync_read(m, m.scalars + D_ENERGY, 1, E));
-  TRY(check_nonfinite(m));
+  // one synchronisation: the energy and the non-finite flag come back together
+  double win[D_FLAG - D_ENERGY + 1];
+  bool bad = false;
+  TRY(read_window(m, win, &bad));
+  if (bad) {
+    set_error("non-finite value in positions, energy or gradient");
+    return SYMX_ERR_NONFINITE;
+  }
+  *E = win[0];
   return SYMX_OK;
 }
 
