@@ -425,6 +425,27 @@ def test_nonfinite_input_is_reported(symx):
     mesh.close()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_assembly_reports_nonfinite_and_recovers(symx, precision):
+    """A NaN position makes the assembly call report NONFINITE (the energy and
+    the flag come back together); the flag is cleared, so the next call with
+    finite positions succeeds and matches the oracle's energy."""
+    scene = sg.tet_cube_scene(2, seed=3, perturb=0.05)
+    mesh = symx.Mesh(scene)
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32
+    flags = symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS
+    x = scene.x0.copy()
+    x[5, 0] = np.nan
+    with pytest.raises(symx.SymxError, match="NONFINITE"):
+        mesh.assemble(x, None, 0.0, flags, p)
+    E, g, _ = mesh.assemble(scene.x0, None, 0.0, flags, p)
+    ref = assembly.assemble(scene, scene.x0, None, 0.0, want_hess=False)
+    tol = 1e-10 if precision == "f64" else 1e-4
+    assert abs(E - ref["E"]) <= tol * abs(ref["E"])
+    assert np.all(np.isfinite(g.cpu().numpy()))
+    mesh.close()
+
+
 def test_forced_failures_halve_dt(symx):
     scene = sg.tet_cube_scene(2, seed=1)
     st, rep, x, _ = _newton(symx, scene, symx.SYMX_F64, max_newton=0, max_halvings=3)
