@@ -388,6 +388,9 @@ typedef struct {
   int64_t pcg_batches;               /* batched PCG launch sequences            */
   int64_t pcg_chunks;                /* request chunks they carried             */
   int32_t active, peak_active, max_slots;
+  uint64_t peak_device_bytes;        /* most device memory the server's pool
+                                        handed out at once (admission charges
+                                        estimates; this is what was used)   */
 } symx_server_stats;
 
 /* Create a server on the current HIP device; max_slots in 1..64. */

@@ -188,6 +188,7 @@ class DevicePool {
   void release_pinned(void* p);
   size_t chunk_bytes();       // device bytes held
   size_t live_bytes();        // device bytes handed out
+  size_t peak_live_bytes();   // most device bytes handed out at once
  private:
   struct Chunk {
     char* base = nullptr;
@@ -204,7 +205,7 @@ class DevicePool {
   std::vector<std::unique_ptr<Chunk>> chunks_;
   std::multimap<size_t, FreeKey> free_by_len_;                   // length -> (chunk, offset)
   std::unordered_map<void*, std::pair<Chunk*, size_t>> live_;  // block -> (chunk, length)
-  size_t held_ = 0, live_bytes_ = 0;
+  size_t held_ = 0, live_bytes_ = 0, peak_live_ = 0;
   std::multimap<size_t, void*> pinned_free_;
   std::unordered_map<void*, size_t> pinned_live_;
 };

@@ -86,6 +86,7 @@ void* DevicePool::alloc(size_t bytes) {
   void* p = c->base + off;
   live_[p] = {c, n};
   live_bytes_ += n;
+  peak_live_ = std::max(peak_live_, live_bytes_);
   return p;
 }
 
@@ -157,6 +158,11 @@ size_t DevicePool::chunk_bytes() {
 size_t DevicePool::live_bytes() {
   std::lock_guard<std::mutex> lk(mu_);
   return live_bytes_;
+}
+
+size_t DevicePool::peak_live_bytes() {
+  std::lock_guard<std::mutex> lk(mu_);
+  return peak_live_;
 }
 
 DevicePool::~DevicePool() {

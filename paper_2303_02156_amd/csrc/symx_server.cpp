@@ -337,6 +337,7 @@ void server_stats(Server* s, symx_server_stats* out) {
   out->peak_active = s->peak_active;
   out->completed = s->completed;
   out->max_slots = s->max_slots;
+  out->peak_device_bytes = s->pool->peak_live_bytes();
   out->pcg_batches = s->batcher ? s->batcher->batches() : 0;
   out->pcg_chunks = s->batcher ? s->batcher->chunks() : 0;
 }

@@ -78,7 +78,7 @@ class ServerStats(C.Structure):
                 ("queued", C.c_int64), ("completed", C.c_int64), ("pattern_hits", C.c_int64),
                 ("pattern_misses", C.c_int64), ("pcg_batches", C.c_int64),
                 ("pcg_chunks", C.c_int64), ("active", C.c_int32), ("peak_active", C.c_int32),
-                ("max_slots", C.c_int32)]
+                ("max_slots", C.c_int32), ("peak_device_bytes", C.c_uint64)]
 
 
 EXPORTS = {

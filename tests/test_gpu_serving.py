@@ -181,3 +181,43 @@ def test_quadratic_and_cubic_requests_served_like_direct_steps(symx):
         mesh.close()
         assert st2 == 0
         assert np.array_equal(xd.cpu().numpy(), x) and np.array_equal(vd.cpu().numpy(), v)
+
+
+def _served_peak(symx, scene, precision, project):
+    """Device bytes the pool of a fresh one-slot server handed out at most
+    while it served one step of `scene`."""
+    srv = symx.symx_server_create(1 << 36, 1)
+    desc, keep = symx.scene_desc(scene)
+    prm = symx.step_params(dt=0.01, precision=precision, project=project)
+    t = symx.symx_server_submit(srv, desc, np.ascontiguousarray(scene.x0),
+                                np.ascontiguousarray(scene.v0), prm)
+    x = np.zeros_like(scene.x0)
+    v = np.zeros_like(scene.v0)
+    st, rep, times = symx.symx_server_poll(srv, t, 1, x, v)
+    stats = symx.symx_server_get_stats(srv)
+    symx.symx_server_destroy(srv)
+    return st, stats.peak_device_bytes
+
+
+@pytest.mark.parametrize("name", ["snh", "cloth", "fcr", "tet10", "tet20"])
+def test_estimate_bounds_the_device_memory_used(symx, name):
+    """The footprint admission charges is an upper bound of the device memory
+    a request really takes (mesh, pattern, Newton workspace, projection
+    records), in every precision and projection mode."""
+    scenes = {
+        "snh": lambda: sg.tet_cube_scene(6, seed=21, perturb=0.1),
+        "cloth": lambda: sg.cloth_scene(10, perturb=0.1),
+        "fcr": lambda: sg.stretched_box_scene(sg.FCR_TET4, dims=(4, 4, 6)),
+        "tet10": lambda: sg.tet_cube_scene(3, kind=sg.SNH_TET10, seed=22, perturb=0.05),
+        "tet20": lambda: sg.tet_cube_scene(2, kind=sg.SNH_TET20, seed=23, perturb=0.05),
+    }
+    scene = scenes[name]()
+    modes = [0] if name.startswith("tet1") or name.startswith("tet2") else [0, 1]
+    if name == "snh":
+        modes.append(2)
+    for precision in (symx.SYMX_F64, symx.SYMX_F32, symx.SYMX_F32_REFINED):
+        bound = _estimate(symx, scene, precision)
+        for project in modes:
+            st, peak = _served_peak(symx, scene, precision, project)
+            assert st == 0, (name, precision, project, symx.STATUS[st])
+            assert 0 < peak <= bound, (name, precision, project, peak, bound)
