@@ -52,8 +52,9 @@ def algorithmic_bytes(kernel, N, nnzb, n_elem, t_bytes):
         nnzl = (nnzb + N) // 2
         return (9 * t_bytes + 4) * nnzl + 4 * (N + 1) + 5 * 3 * t_bytes * N
     if kernel == "pcg_update":
-        # Dinv (9), x rw, r rw, z w, p r, q r (3 each)
-        return (9 + 6 + 6 + 3 + 3 + 3) * t_bytes * N
+        # Dinv (6: the upper triangle of each symmetric block inverse),
+        # x rw, r rw, z w, p r, q r (3 each)
+        return (6 + 6 + 6 + 3 + 3 + 3) * t_bytes * N
     if kernel in ("row_assemble_gH", "row_assemble_H"):
         out = 9 * t_bytes * nnzb + (24 * N if kernel == "row_assemble_gH" else 0)
         # connectivity, positions and rest positions (float64), masses, x_tilde, flags

@@ -28,6 +28,8 @@ constexpr int kRedWG = 256;         // reduction workgroup size
 constexpr int kPrm = 8;             // parameter slots per element (doubles)
 constexpr uint32_t kNoSlot = 0xFFu;
 constexpr int kPcgHistory = 64;    // remembered PCG iteration counts
+constexpr int kDinv = 6;           // values per block-Jacobi inverse: the upper triangle
+                                    // (d00, d01, d02, d11, d12, d22) of the symmetric 3x3
 constexpr int kIncRec = 32;        // values per incidence record (projected path)
 constexpr int kQuadInc = 64;       // incidences per row batch of a quadratic-tet mesh
 constexpr int kCubicInc = 32;      // incidences per row batch of a cubic-tet mesh
@@ -629,10 +631,10 @@ class PcgBatcher {
 // blocks in `precision`, plus the contact matrix).
 symx_status launch_residual64(Mesh& m, int precision, const double* x, const double* b, double* r);
 // Rounds the float64 Hessian values of the mesh (half storage, if mesh_vals)
-// and of its contacts to their float32 copies, and n9 float64 block inverses
-// dinv64 to dinv32 (if given).
+// and of its contacts to their float32 copies, and the n_inv float64 values of
+// the block inverses dinv64 to dinv32 (if given).
 symx_status launch_round_values(Mesh& m, bool mesh_vals, const double* dinv64, float* dinv32,
-                                int64_t n9);
+                                int64_t n_inv);
 
 // Newton driver (symx_newton.cpp): the ranges symx_newton_step accepts.
 bool step_params_valid(const symx_step_params& P);

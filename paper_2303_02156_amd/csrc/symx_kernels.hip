@@ -1178,7 +1178,7 @@ struct RowArgs {
   const int* batch_entry;
   int64_t nnzb;
   T* vals;               // component-major 9 x nnzb, or null
-  T* dinv;               // N x 9 inverses of the diagonal blocks, or null
+  T* dinv;               // N x kDinv inverses of the diagonal blocks, or null
   float* vals_lo;        // null, or the values rounded to float32 (as vals)
   float* dinv_lo;        // null, or the inverses rounded to float32 (as dinv)
   // the solver's half storage (blocks (i, j) with j <= i, nine values each,
@@ -1276,6 +1276,19 @@ __device__ __forceinline__ void inverse3(const double a[9], double r[9]) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) r[c] = (c % 4 == 0) ? 1.0 : 0.0;
   }
+}
+
+// The block-Jacobi inverse of a node's diagonal block is symmetric (so is the
+// block); it is stored as its upper triangle, kDinv values, each off-diagonal
+// entry the mean of the computed inverse's two (equal up to rounding).
+template <typename T>
+__device__ __forceinline__ void store_dinv(T* d, const double r[9]) {
+  d[0] = T(r[0]);
+  d[1] = T(0.5 * (r[1] + r[3]));
+  d[2] = T(0.5 * (r[2] + r[6]));
+  d[3] = T(r[4]);
+  d[4] = T(0.5 * (r[5] + r[7]));
+  d[5] = T(r[8]);
 }
 
 // Off-diagonal part of one incidence's Hessian block row (recompute path):
@@ -1602,12 +1615,8 @@ __global__ __launch_bounds__(kRowWG, sizeof(T) == 8 ? 3 : 6) void k_row_assemble
 #pragma unroll
       for (int c = 0; c < 9; ++c) a[c] = double(acc[c]);
       inverse3(a, ri);
-#pragma unroll
-      for (int c = 0; c < 9; ++c) A.dinv[9 * (int64_t)row + c] = T(ri[c]);
-      if (A.dinv_lo) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) A.dinv_lo[9 * (int64_t)row + c] = float(ri[c]);
-      }
+      store_dinv(A.dinv + kDinv * (int64_t)row, ri);
+      if (A.dinv_lo) store_dinv(A.dinv_lo + kDinv * (int64_t)row, ri);
     }
   }
 }
@@ -2150,8 +2159,7 @@ __global__ __launch_bounds__(kRowWG, (ho_row_waves<K, T, WANT_H>())) void k_row_
 #pragma unroll
       for (int c = 0; c < 9; ++c) a9[c] = double(acc[c]);
       inverse3(a9, ri);
-#pragma unroll
-      for (int c = 0; c < 9; ++c) A.dinv[9 * (int64_t)row + c] = T(ri[c]);
+      store_dinv(A.dinv + kDinv * (int64_t)row, ri);
     }
   }
 }
@@ -2318,12 +2326,14 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t N, const TB* __restric
       bb += bc * bc;
       rr += double(rv[c]) * double(rv[c]);
     }
+    const T* d = Dinv + kDinv * i;  // upper triangle of the symmetric inverse
+    const T d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4], d5 = d[5];
+    const T zv[3] = {d0 * rv[0] + d1 * rv[1] + d2 * rv[2], d1 * rv[0] + d3 * rv[1] + d4 * rv[2],
+                     d2 * rv[0] + d4 * rv[1] + d5 * rv[2]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T zc = Dinv[9 * i + 3 * c] * rv[0] + Dinv[9 * i + 3 * c + 1] * rv[1] +
-                   Dinv[9 * i + 3 * c + 2] * rv[2];
-      z[3 * i + c] = zc;
-      rz += double(rv[c]) * double(zc);
+      z[3 * i + c] = zv[c];
+      rz += double(rv[c]) * double(zv[c]);
     }
   }
   const double s0 = block_sum_256(rz, sh);
@@ -2450,12 +2460,14 @@ __device__ __forceinline__ void pcg_update_body(int bid, int nblk, int k, int64_
       r[3 * i + c] = rv[c];
       rr += double(rv[c]) * double(rv[c]);
     }
+    const T* d = Dinv + kDinv * i;  // upper triangle of the symmetric inverse
+    const T d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4], d5 = d[5];
+    const T zv[3] = {d0 * rv[0] + d1 * rv[1] + d2 * rv[2], d1 * rv[0] + d3 * rv[1] + d4 * rv[2],
+                     d2 * rv[0] + d4 * rv[1] + d5 * rv[2]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T zc = Dinv[9 * i + 3 * c] * rv[0] + Dinv[9 * i + 3 * c + 1] * rv[1] +
-                   Dinv[9 * i + 3 * c + 2] * rv[2];
-      z[3 * i + c] = zc;
-      rz += double(rv[c]) * double(zc);
+      z[3 * i + c] = zv[c];
+      rz += double(rv[c]) * double(zv[c]);
     }
   }
   const double s0 = block_sum_256(rz, sh);
@@ -2855,8 +2867,7 @@ __global__ __launch_bounds__(256) void k_contact_dinv(int64_t n_gnode, const int
     for (int c = 0; c < 9; ++c)
       a[c] = double(lvals[half_at(l, c, nnzl)]) + double(cvals[c * cnnzb + q]);
     inverse3(a, r);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) dinv[9 * v + c] = T(r[c]);
+    store_dinv(dinv + kDinv * v, r);
   }
 }
 
@@ -3298,7 +3309,7 @@ symx_status launch_velocity(Mesh& m, double* v, const double* xn, const double* 
 }
 
 symx_status launch_round_values(Mesh& m, bool mesh_vals, const double* dinv64, float* dinv32,
-                                int64_t n9) {
+                                int64_t n_inv) {
   const char* PNAME = "round_values";
   if (mesh_vals && (!m.lvals64 || !m.lvals32)) {
     set_error("round_values: the float64 and float32 value arrays must exist");
@@ -3322,8 +3333,8 @@ symx_status launch_round_values(Mesh& m, bool mesh_vals, const double* dinv64, f
                 (const double*)c.vals64, c.vals32);
   }
   if (dinv64 && dinv32)
-    SYMX_LAUNCH(m, PNAME, k_round_f64, dim3(grid_for(n9, 256, 8192)), dim3(256), 0, n9, dinv64,
-                dinv32);
+    SYMX_LAUNCH(m, PNAME, k_round_f64, dim3(grid_for(n_inv, 256, 8192)), dim3(256), 0, n_inv,
+                dinv64, dinv32);
   LAUNCH_CHECK("k_round_f64");
   return SYMX_OK;
 }

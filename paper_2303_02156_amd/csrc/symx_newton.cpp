@@ -48,7 +48,7 @@ struct Workspace {
   double *x_t = nullptr, *v_t = nullptr, *xt = nullptr, *xk = nullptr, *xtrial = nullptr;
   double *g = nullptr, *dx = nullptr, *b = nullptr, *res = nullptr;
   void* pcg[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // Dinv xs r z p q (max size)
-  double* dinv64 = nullptr;  // F32_REFINED: float64 block inverses before rounding (9N)
+  double* dinv64 = nullptr;  // F32_REFINED: float64 block inverses before rounding (kDinv N)
 };
 
 bool step_params_valid(const symx_step_params& P) {
@@ -82,7 +82,7 @@ static symx_status ensure_workspace(Mesh& m) {
   const size_t v64 = 3 * m.N * sizeof(double);
   double** vecs[] = {&w->x_t, &w->v_t, &w->xt, &w->xk, &w->xtrial, &w->g, &w->dx, &w->b, &w->res};
   for (double** p : vecs) TRY(dev_alloc(m.pool, (void**)p, v64));
-  TRY(dev_alloc(m.pool, &w->pcg[0], 9 * m.N * sizeof(double)));
+  TRY(dev_alloc(m.pool, &w->pcg[0], kDinv * m.N * sizeof(double)));
   for (int i = 1; i < 6; ++i) TRY(dev_alloc(m.pool, &w->pcg[i], v64));
   return SYMX_OK;
 }
@@ -90,7 +90,7 @@ static symx_status ensure_workspace(Mesh& m) {
 static symx_status ensure_dinv64(Mesh& m) {
   Workspace* w = m.ws;
   if (w->dinv64) return SYMX_OK;
-  return dev_alloc(m.pool, (void**)&w->dinv64, 9 * m.N * sizeof(double));
+  return dev_alloc(m.pool, (void**)&w->dinv64, kDinv * m.N * sizeof(double));
 }
 
 void free_workspace(Mesh& m) {
@@ -161,7 +161,7 @@ static symx_status assemble_main(Mesh& m, const double* x, const double* xt, dou
                                  bool dirichlet, double* g_out, void* dinv, float* dinv_lo);
 
 // Assemble gradient (float64) and/or Hessian values (precision) at x.  With
-// dinv (the Newton solve), the block-Jacobi inverses (N x 9, precision's
+// dinv (the Newton solve), the block-Jacobi inverses (N x kDinv, precision's
 // type) are produced too and the Hessian goes to the solver's half storage
 // (m.lvals64 / m.lvals32); without, to the block arrays (m.vals64 /
 // m.vals32).  With dinv_lo (float64 Hessian and dinv only), also the float32
@@ -181,7 +181,7 @@ symx_status assemble(Mesh& m, const double* x, const double* xt, double dt, bool
   // copies the row kernel does not write: higher-order meshes (all values),
   // contacts (their values, and the inverses of the nodes they touch)
   if (dinv_lo && (m.ho || m.contacts))
-    TRY(launch_round_values(m, m.ho != 0, (const double*)dinv, dinv_lo, 9 * m.N));
+    TRY(launch_round_values(m, m.ho != 0, (const double*)dinv, dinv_lo, kDinv * m.N));
   return SYMX_OK;
 }
 

@@ -325,12 +325,14 @@ def _lanczos_smallest(matvec, v0, iters):
 def test_c4_step_endpoints_are_distinct_stationary_minima(symx):
     """C4 at 64^3 cubes, step 1 (dt 0.005) from the float64 state after step 0:
     float64 Newton with the forcing term capped at 0.5 and at 0.1 lands on
-    two endpoints centimetres apart.  Both are stationary (the oracle's float64
-    gradient meets the Newton tolerance) and minima (the smallest eigenvalue
-    of the float64 Hessian on the free DoFs is positive), so the incremental
-    potential of this violently compressed, stiffness-contrasted block has
-    several local minima and the linear solver's path picks one; FP32-refined
-    with the same forcing lands on the float64 endpoint."""
+    two endpoints a centimetre or more apart.  Both are stationary (the
+    oracle's float64 gradient meets the Newton tolerance) and minima (the
+    smallest eigenvalue of the float64 Hessian on the free DoFs is positive),
+    and the oracle's energy halfway between them lies above both (they sit in
+    different basins), so the incremental potential of this violently
+    compressed, stiffness-contrasted block has several local minima and the
+    linear solver's path picks one; FP32-refined with the same forcing lands
+    on the float64 endpoint."""
     scene = sg.config_c4(64)
     mesh = symx.Mesh(scene)
 
@@ -348,10 +350,15 @@ def test_c4_step_endpoints_are_distinct_stationary_minima(symx):
     xq, _, rq = step(x0, v0, dt, precision=symx.SYMX_F32_REFINED, max_halvings=0,
                      forcing_max=0.1)
     assert np.max(np.linalg.norm(xa - xf, axis=1)) > 1e-2
-    assert abs(ra.energy - rf.energy) > 1e-7 * abs(rf.energy)
     assert np.max(np.linalg.norm(xq - xf, axis=1)) < 1e-6
     xt = elements.x_tilde(x0, v0, dt, scene.gravity)
     rp, ci = assembly.pattern_fast(scene)
+    # an energy barrier between the endpoints: different basins
+    E_end = [assembly.assemble(scene, x, xt, dt, want_hess=False, row_ptr=rp, col_idx=ci)["E"]
+             for x in (xa, xf)]
+    E_mid = assembly.assemble(scene, 0.5 * (xa + xf), xt, dt, want_hess=False, row_ptr=rp,
+                              col_idx=ci)["E"]
+    assert E_mid > max(E_end) + 1e-9 * abs(E_mid), (E_end, E_mid)
     r0 = np.linalg.norm(assembly.assemble(scene, x0, xt, dt, want_hess=False, row_ptr=rp,
                                           col_idx=ci)["g"])
     N = scene.n_nodes

