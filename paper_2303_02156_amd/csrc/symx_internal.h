@@ -498,11 +498,11 @@ symx_status launch_elem_filtered(Mesh& m, int set, const double* x, int precisio
 // records (kIncRec values each) instead of evaluating it.  filter: every set
 // is Stable Neo-Hookean; evaluate each row with the filtered density Hessian.
 // dinv (optional): the kernel also writes the inverses of the final diagonal
-// blocks (N x 9, precision's type).  half: the Hessian goes to the solver's
-// half storage (m.lvals64 / m.lvals32) instead of the block arrays
-// (m.vals64 / m.vals32).  dinv_lo (float64 only, optional): the linear-tet
-// kernels also write the values and inverses rounded to float32 (into
-// m.lvals32 or m.vals32, and dinv_lo; the higher-order kernels do not).
+// blocks (N x kDinv upper triangles, precision's type).  half: the Hessian
+// goes to the solver's half storage (m.lvals64 / m.lvals32) instead of the
+// block arrays (m.vals64 / m.vals32).  dinv_lo (float64 only, optional): the
+// linear-tet kernels also write the values and inverses rounded to float32
+// (into m.lvals32 or m.vals32, and dinv_lo; the higher-order kernels do not).
 symx_status launch_row_assemble(Mesh& m, const double* x, const double* x_tilde, double dt,
                                 bool want_g, bool want_H, int precision, bool dirichlet,
                                 const void* inc_rows, bool filter, double* g_out, void* dinv,
@@ -554,7 +554,7 @@ symx_status launch_velocity(Mesh& m, double* v, const double* x_new, const doubl
                             double inv_dt, int64_t n);
 symx_status launch_check_finite(Mesh& m, const double* a, int64_t n);
 
-// PCG buffers (device): block-Jacobi inverse (9N) and the vectors of the
+// PCG buffers (device): block-Jacobi inverses (kDinv N) and the vectors of the
 // iteration (3N each), float or double per the solve precision.
 struct PcgBuffers {
   void* Dinv;
