@@ -1419,15 +1419,18 @@ __device__ __forceinline__ void store_block(const RowArgs<T>& A, int row, int co
 // material mesh keeps the kernel small).
 // Occupancy: the float32 kernels are held to six waves per SIMD (at most 80
 // VGPRs; a few values of the Stable Neo-Hookean row spill, which costs less
-// than the wave lost at 83); the float64 ones are bound to three by LDS.
+// than the wave lost at 83); the float64 ones run three, except the float64
+// filtered kernel, held to four (128 VGPRs, a few values spilled, and the
+// three-round LDS footprint), which is faster than three at 137 VGPRs.
 template <typename T, bool WANT_G, int SRC, uint32_t KMASK>
-__global__ __launch_bounds__(kRowWG, sizeof(T) == 8 ? 3 : 6) void k_row_assemble_fast(RowArgs<T> A) {
+__global__ __launch_bounds__(kRowWG, sizeof(T) == 8 ? (SRC == kRowFilter ? 4 : 3) : 6) void
+k_row_assemble_fast(RowArgs<T> A) {
   constexpr int NV = 30;
   // Phase 2 stages two component rows of the blocks per round (two rounds)
   // where registers already hold occupancy down to what the larger LDS array
-  // allows, and one row per round (three rounds) when the rows come from the
-  // records, whose kernel needs far fewer registers.
-  constexpr int ROWS = SRC == kRowRecords ? 1 : 2;
+  // allows, and one row per round (three rounds) where more waves fit: the
+  // records kernel (far fewer registers) and the float64 filtered one.
+  constexpr int ROWS = SRC == kRowRecords || (SRC == kRowFilter && sizeof(T) == 8) ? 1 : 2;
   constexpr int ROUNDS = ROWS == 1 ? 3 : 2;
   // Component rows of the incidences' blocks, then the sums; and the
   // incidences' gradient rows.  Rows are padded by one value so that lanes
