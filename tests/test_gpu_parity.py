@@ -245,6 +245,46 @@ def test_assembly_bitwise_reproducible(symx):
     mesh.close()
 
 
+@pytest.mark.parametrize("mode", ["psd", "filter"])
+def test_projected_assembly_bitwise_reproducible(symx, mode):
+    """Projected (records path) and filtered assembly at a strained state give
+    the same bits on every call: fixed reduction orders, no atomics."""
+    scene = sg.tet_cube_scene(5, seed=41, perturb=0.2)
+    mesh = symx.Mesh(scene)
+    xt = elements.x_tilde(scene.x0, scene.v0, 0.01, scene.gravity)
+    proj = symx.SYMX_PROJECT_PSD if mode == "psd" else symx.SYMX_PROJECT_FILTER
+    flags = (symx.SYMX_EVAL_E | symx.SYMX_EVAL_GRAD | symx.SYMX_EVAL_HESS | symx.SYMX_DIRICHLET
+             | proj)
+    for p in (symx.SYMX_F64, symx.SYMX_F32):
+        outs = [mesh.assemble(scene.x0, xt, 0.01, flags, p) for _ in range(3)]
+        for E, g, v in outs[1:]:
+            assert E == outs[0][0]
+            assert torch.equal(g, outs[0][1])
+            assert torch.equal(v, outs[0][2])
+    mesh.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32r"])
+def test_newton_step_bitwise_reproducible(symx, precision):
+    """The same implicit-Euler step from the same state, twice: identical
+    positions, velocities and iteration counts."""
+    scene = sg.tet_cube_scene(6, seed=42, perturb=0.1, vel_std=0.1)
+    mesh = symx.Mesh(scene)
+    p = symx.SYMX_F64 if precision == "f64" else symx.SYMX_F32_REFINED
+    runs = []
+    for _ in range(2):
+        x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
+        v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
+        st, rep = mesh.newton_step(x, v, symx.step_params(dt=0.01, precision=p))
+        assert st == 0
+        runs.append((x, v, rep.as_dict()))
+    (xa, va, ra), (xb, vb, rb) = runs
+    assert torch.equal(xa, xb) and torch.equal(va, vb)
+    assert ra["newton_iters"] == rb["newton_iters"] and ra["pcg_iters"] == rb["pcg_iters"]
+    assert ra["energy"] == rb["energy"]
+    mesh.close()
+
+
 def test_bsr_symmetry_and_matvec(symx):
     scene = sg.config_c1()
     mesh = symx.Mesh(scene)
