@@ -53,7 +53,12 @@ typedef enum {
 typedef enum {
   SYMX_F64 = 0,          /* everything in float64 */
   SYMX_F32 = 1,          /* element kernels, Hessian values and PCG in float32;
-                            gradient and energy sums accumulated in float64 */
+                            gradient and energy sums accumulated in float64
+                            (a Newton step in this mode is limited by the
+                            float32 element gradients: on stiff or strongly
+                            stretched meshes it can stall above a tight
+                            residual tolerance and halve dt; the refined mode
+                            below does not) */
   SYMX_F32_REFINED = 2   /* Newton only: SpMV and PCG in float32 on the float64
                             Hessian rounded to float32; energies, gradient,
                             Newton residual and the iterative refinement of
