@@ -209,14 +209,14 @@ def serving_bench(symx, torch, n_requests=256, rate=200.0, slots=8):
     return out
 
 
-def trajectory(symx, torch, scene, precision, steps, dt, profile_steps=0):
+def trajectory(symx, torch, scene, precision, steps, dt, profile_steps=0, max_pcg=500):
     """Run `steps` implicit-Euler steps; returns (x, v, reports, ms per step),
     and with profile_steps > 0 also {kernel: (launches, device ms)} of that
     many more steps run with per-launch events (after the timed ones)."""
     mesh = symx.Mesh(scene)
     x = torch.tensor(scene.x0, dtype=torch.float64, device="cuda")
     v = torch.tensor(scene.v0, dtype=torch.float64, device="cuda")
-    prm = symx.step_params(dt=dt, precision=precision, max_pcg=500)
+    prm = symx.step_params(dt=dt, precision=precision, max_pcg=max_pcg)
     reps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -419,6 +419,12 @@ def mixed_c3(symx, torch, steps=20):
     t_asm = sum(kt[k][1] for k in assembly_k if k in kt)
     newton = sum(r["newton_iters"] for r in reps)
     pcg = sum(r["pcg_iters"] for r in reps)
+    # the same steps with the PCG cap at 2000: the capped solves (cap 500)
+    # return inexact directions, and Newton then needs many more iterations
+    _, _, reps2k, ms_step2k = trajectory(symx, torch, scene, symx.SYMX_F32_REFINED, steps, dt,
+                                         max_pcg=2000)
+    newton2k = sum(r["newton_iters"] for r in reps2k)
+    pcg2k = sum(r["pcg_iters"] for r in reps2k)
     return {"workload": "C3: 512^2 cloth (524,288 StVK triangles, 785,408 hinges, pinned edge) "
                         "+ 32^3-cube SNH block (196,608 tets), dt 1/60",
             "elements": n_elem, "nnzb": int(info.nnzb),
@@ -434,7 +440,12 @@ def mixed_c3(symx, torch, steps=20):
                 "solve": round(t_solve, 2), "assembly": round(t_asm, 2),
                 "other": round(tot - t_solve - t_asm, 2),
                 "newton_iters": sum(r["newton_iters"] for r in preps),
-                "pcg_iters": sum(r["pcg_iters"] for r in preps)}}
+                "pcg_iters": sum(r["pcg_iters"] for r in preps)},
+            "pcg_cap_2000": {"ms_per_step_f32_refined": round(ms_step2k, 3),
+                             "newton_iters": newton2k, "pcg_iters": pcg2k,
+                             "pcg_iters_per_solve": round(pcg2k / max(newton2k, 1), 1),
+                             "all_converged": all(r["status"] == 0 for r in reps2k),
+                             "dt_halvings": sum(r["dt_halvings"] for r in reps2k)}}
 
 
 # Evaluation + assembly per Newton iteration on the material-comparison box
